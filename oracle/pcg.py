@@ -1,0 +1,57 @@
+"""Jacobi-preconditioned CG on a principal submatrix (oracle; test infrastructure).
+
+Sec. 4.2: the linear systems of each sweep are solved only on the active
+index set I_k, i.e. with the principal submatrix H[I_k, I_k] (homogeneous
+Dirichlet values on the complement, Sec. 4.1), by CG with a Jacobi
+preconditioner because it needs no setup when the submatrix changes.
+
+Stopping rule (a reading; the paper stops at an estimated energy-error
+reduction of 1e-3): ||r||_2 <= rtol * ||b||_2 over the active rows, x0 = 0.
+A zero right-hand side or an empty index set returns x = 0 after 0
+iterations.  ``fixed_iters`` replays a given iteration count instead.
+"""
+import numpy as np
+
+
+class CGNotConverged(RuntimeError):
+    pass
+
+
+def jacobi_pcg(H, b, idx, rtol, maxit=1000, fixed_iters=None):
+    """Solve H[idx, idx] x = b[idx]; return (x full-length, zero off idx; iterations)."""
+    n = H.shape[0]
+    x_full = np.zeros(n)
+    idx = np.asarray(idx, dtype=np.int64)
+    if idx.size == 0:
+        return x_full, 0
+    Hs = H[idx][:, idx]
+    bs = np.asarray(b, dtype=np.float64)[idx]
+    bnorm = np.sqrt(bs @ bs)
+    if bnorm == 0.0:
+        return x_full, 0
+    dinv = 1.0 / Hs.diagonal()
+    x = np.zeros_like(bs)
+    r = bs.copy()
+    z = dinv * r
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    limit = maxit if fixed_iters is None else fixed_iters
+    while it < limit:
+        q = Hs @ p
+        alpha = rz / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        if fixed_iters is None and np.sqrt(r @ r) <= rtol * bnorm:
+            break
+        z = dinv * r
+        rz_new = r @ z
+        beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+    else:
+        if fixed_iters is None:
+            raise CGNotConverged(f"PCG: no convergence in {maxit} iterations")
+    x_full[idx] = x
+    return x_full, it

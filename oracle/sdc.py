@@ -1,0 +1,200 @@
+"""Adaptive IMEX SDC step for the monodomain system (oracle; test infrastructure).
+
+Problem (Sec. 2.2, eq. abstract monodomain, with beta*C_m = 1 and nodal
+quadrature of the reaction):
+
+    ML v' = -A v - ML * I(v, w),      w' = R(v, w).
+
+Time stepping (Sec. 3, eq. final-sdc).  We follow the implicit-explicit
+reading: diffusion implicit through the lower-triangular QI (LU trick),
+reaction and gating explicit through QE (forward Euler between nodes); the
+paper's lumped reaction Jacobian on the diagonal of the system matrix is not
+used, so every solve has the matrix H_m = ML + dt*QI[m,m]*A.  In Q form, one
+sweep over nodes m = 0..M-1 reads
+
+    Phi_m  = ML (v0 - v_m) + dt sum_j Q[m,j] (-A v_j - ML I_j)
+    Gam_m  = w0 - w_m + dt sum_j Q[m,j] R_j
+    dw_m   = Gam_m + dt sum_{j<m} QE[m,j] dR_j
+    H_m dv_m = Phi_m - dt sum_{j<m} QE[m,j] ML dI_j - A (dt sum_{j<m} QI[m,j] dv_j)
+    v_m += dv_m,  w_m += dw_m,  (I_m, R_m) <- AP(v_m, w_m),
+    dI_m, dR_m = change of I_m, R_m in this sweep.
+
+Algebraic adaptivity (Sec. 4.2): sweep k only touches the rows of the index
+set I_k; its solves use the principal submatrix H_m[I_k, I_k] (zero
+correction on the complement); rows outside I_k keep the values they have.
+The next set keeps the rows whose correction reached the drop tolerance,
+
+    I_{k+1} = { i in I_k : max_m |dv_m,i| >= theta },
+
+so the sets are nested.  Readings: the maximum over collocation nodes is
+taken (the bound of Thm. 1 is in L-infinity over the step); the gating
+correction does not enter the rule; theta <= 0 keeps every row (the
+non-adaptive method); every step starts with all rows active and with the
+collocation values spread from the step's initial state.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from . import ionic
+from .collocation import Collocation
+from .pcg import jacobi_pcg
+
+
+class Monodomain:
+    """ML, A and per-node ionic parameters of a (possibly multi-instance) mesh.
+
+    ``ionic_params`` has shape [N, 6]: one Aliev-Panfilov parameter set per
+    node, so that several instances with different parameters can share one
+    vector layout.
+    """
+
+    def __init__(self, ML, A, ionic_params):
+        self.ML = np.asarray(ML, dtype=np.float64)
+        self.A = A.tocsr()
+        self.N = self.ML.size
+        p = np.asarray(ionic_params, dtype=np.float64)
+        if p.ndim == 1:
+            p = np.broadcast_to(p, (self.N, 6))
+        self.p = p.T.copy()          # [6, N] so ionic.current(v, w, p) broadcasts
+
+    def reaction(self, v, w, rows):
+        p = self.p[:, rows]
+        return ionic.current(v, w, p), ionic.rate(v, w, p)
+
+
+class SDC:
+    """IMEX SDC on Radau-IIA nodes with nested active index sets."""
+
+    def __init__(self, model, M, dt, theta, cg_rtol=1e-12, cg_maxit=1000):
+        self.model = model
+        self.col = Collocation(M)
+        self.M = M
+        self.dt = float(dt)
+        self.theta = float(theta)
+        self.cg_rtol = cg_rtol
+        self.cg_maxit = cg_maxit
+        ML, A = model.ML, model.A
+        self.H = [(sp.diags(ML) + self.dt * self.col.QI[m, m] * A).tocsr() for m in range(M)]
+
+    # -- one step -------------------------------------------------------
+    def spread(self, v0, w0):
+        """Initial guess: every collocation value equals the step's start value."""
+        M, N = self.M, self.model.N
+        st = {
+            "v0": v0.copy(), "w0": w0.copy(),
+            "v": np.tile(v0, (M, 1)), "w": np.tile(w0, (M, 1)),
+        }
+        I0, R0 = self.model.reaction(v0, w0, np.arange(N))
+        st["I"] = np.tile(I0, (M, 1))
+        st["R"] = np.tile(R0, (M, 1))
+        return st
+
+    def sweep(self, st, idx, cg_iters=None):
+        """One sweep on rows idx (ascending int array); returns (next idx, info)."""
+        M, dt = self.M, self.dt
+        Q, QI, QE = self.col.Q, self.col.QI, self.col.QE
+        ML, A = self.model.ML, self.model.A
+        N = self.model.N
+        v, w, I, R = st["v"], st["w"], st["I"], st["R"]
+        v0, w0 = st["v0"], st["w0"]
+
+        # sweep-start residuals on the active rows (full rows of A)
+        F = np.zeros((M, N))
+        for j in range(M):
+            F[j, idx] = -(A @ v[j])[idx] - ML[idx] * I[j, idx]
+        Phi = np.zeros((M, N))
+        Gam = np.zeros((M, N))
+        for m in range(M):
+            Phi[m, idx] = ML[idx] * (v0[idx] - v[m, idx]) + dt * (Q[m, :] @ F[:, idx])
+            Gam[m, idx] = w0[idx] - w[m, idx] + dt * (Q[m, :] @ R[:, idx])
+
+        dv = np.zeros((M, N))
+        dI = np.zeros((M, N))
+        dR = np.zeros((M, N))
+        amax = np.zeros(N)
+        iters = []
+        for m in range(M):
+            dw = Gam[m, idx].copy()
+            rhs = Phi[m, idx].copy()
+            y = np.zeros(N)
+            for j in range(m):
+                dw += dt * QE[m, j] * dR[j, idx]
+                rhs -= dt * QE[m, j] * ML[idx] * dI[j, idx]
+                y += dt * QI[m, j] * dv[j]
+            rhs -= (A @ y)[idx]
+            b = np.zeros(N)
+            b[idx] = rhs
+            fixed = None if cg_iters is None else cg_iters[m]
+            x, it = jacobi_pcg(self.H[m], b, idx, self.cg_rtol, self.cg_maxit, fixed)
+            iters.append(it)
+            dv[m] = x
+            v[m, idx] += x[idx]
+            w[m, idx] += dw
+            In, Rn = self.model.reaction(v[m, idx], w[m, idx], idx)
+            dI[m, idx] = In - I[m, idx]
+            dR[m, idx] = Rn - R[m, idx]
+            I[m, idx] = In
+            R[m, idx] = Rn
+            amax[idx] = np.maximum(amax[idx], np.abs(x[idx]))
+        nxt = select(idx, amax, self.theta)
+        return nxt, {"idx": idx, "n_active": int(idx.size), "cg_iters": iters, "amax": amax, "dv": dv}
+
+    def step(self, v0, w0, K, idx_replay=None, cg_replay=None, keep=False):
+        """K sweeps from the spread state; returns (v_end, w_end, infos).
+
+        idx_replay[k], when given, replaces the computed index set of sweep k
+        (the first sweep always uses all rows unless replayed);
+        cg_replay[k][m] replays CG iteration counts.
+        """
+        st = self.spread(v0, w0)
+        idx = np.arange(self.model.N)
+        infos = []
+        for k in range(K):
+            if idx_replay is not None and idx_replay[k] is not None:
+                idx = np.asarray(idx_replay[k], dtype=np.int64)
+            nxt, info = self.sweep(st, idx, None if cg_replay is None else cg_replay[k])
+            if not keep:
+                info.pop("dv")
+                info.pop("amax")
+            infos.append(info)
+            idx = nxt
+        return st["v"][-1].copy(), st["w"][-1].copy(), infos
+
+
+def select(idx, amax, theta):
+    """I_{k+1} = [i in idx : amax_i >= theta]; theta <= 0 keeps all rows."""
+    if theta <= 0.0:
+        return idx.copy()
+    return idx[amax[idx] >= theta]
+
+
+def apply_stimuli(v, t, dt, stimuli):
+    """Set v = value on the listed nodes when t_on lies in [t, t + dt)."""
+    for t_on, nodes, value in stimuli:
+        if t - 1e-9 * dt <= t_on < t + dt - 1e-9 * dt:
+            v[np.asarray(nodes, dtype=np.int64)] = value
+    return v
+
+
+def run(sdc, v, w, n_steps, K, stimuli=(), t0=0.0, idx_replay=None, cg_replay=None):
+    """Advance n_steps; returns (v, w, per-step infos)."""
+    v = np.array(v, dtype=np.float64)
+    w = np.array(w, dtype=np.float64)
+    log = []
+    for n in range(n_steps):
+        t = t0 + n * sdc.dt
+        apply_stimuli(v, t, sdc.dt, stimuli)
+        v, w, infos = sdc.step(v, w, K,
+                               None if idx_replay is None else idx_replay[n],
+                               None if cg_replay is None else cg_replay[n])
+        log.append(infos)
+    return v, w, log
+
+
+def build(problem):
+    """Assemble the oracle model and SDC integrator for a workload Problem."""
+    from .assembly import lumped_mass, stiffness
+    ML = lumped_mass(problem.coords, problem.elems, problem.N)
+    A = stiffness(problem.coords, problem.elems, problem.elem_tensor, problem.node_sigma, problem.N)
+    model = Monodomain(ML, A, problem.node_ionic())
+    return SDC(model, problem.M, problem.dt, problem.theta, problem.cg_rtol, problem.cg_maxit)
