@@ -261,3 +261,45 @@ def test_rest_state_stays_exactly_at_rest():
     assert np.all(v == 0) and np.all(w == 0)
     assert infos[0]["n_active"] == 32 and infos[1]["n_active"] == 0
     assert all(i == 0 for i in infos[0]["cg_iters"])
+
+
+def test_jacobi_preconditioner_properties():
+    # a diagonal system is solved in one iteration; Jacobi PCG is invariant
+    # under symmetric diagonal scaling (same iterates up to rounding)
+    rng = np.random.default_rng(11)
+    n = 30
+    Hd = sp.diags(rng.uniform(0.5, 3.0, n)).tocsr()
+    b = rng.standard_normal(n)
+    x, it = jacobi_pcg(Hd, b, np.arange(n), 1e-14)
+    assert it == 1 and np.allclose(x, b / Hd.diagonal(), rtol=1e-15)
+    coords, elems = meshes.square_tri_mesh(8, 8, 1.0, 1.0)
+    N, E = coords.shape[0], elems.shape[0]
+    A = stiffness(coords, elems, np.broadcast_to(np.eye(2), (E, 2, 2)), np.ones(N), N)
+    H = (sp.diags(lumped_mass(coords, elems, N)) + 0.5 * A).tocsr()
+    Dg = sp.diags(rng.uniform(0.1, 10.0, N))
+    b = rng.standard_normal(N)
+    idx = np.arange(5, N - 3)
+    x1, it1 = jacobi_pcg(H, b, idx, 1e-10)
+    x2, it2 = jacobi_pcg((Dg @ H @ Dg).tocsr(), Dg @ b, idx, 1e-10)
+    assert abs(it1 - it2) <= 1
+
+
+def test_selection_uses_max_correction_over_nodes():
+    import copy
+    P = config0(n=64, theta=1e-4, n_steps=1)
+    s = build(P)
+    v0 = np.where(np.arange(64) < 20, 1.0, 0.0)
+    idx = np.arange(64)
+    st1 = s.spread(v0, np.zeros(64))
+    s.sweep(st1, idx)                      # the second sweep's corrections are not monotone in m
+    _, info = s.sweep(copy.deepcopy(st1), idx)
+    dv = info["dv"]
+    big = np.abs(dv).max(axis=0)
+    last = np.abs(dv[-1])
+    # pick a threshold that separates "max over nodes" from "last node only"
+    i = int(np.argmax(big / np.maximum(last, 1e-300)))
+    assert big[i] > 2 * last[i]
+    s.theta = 0.5 * (big[i] + last[i])
+    nxt, _ = s.sweep(copy.deepcopy(st1), idx)
+    brute = np.array([r for r in idx if max(abs(dv[m, r]) for m in range(s.M)) >= s.theta])
+    assert np.array_equal(nxt, brute) and i in nxt
