@@ -1,0 +1,185 @@
+"""Benchmark: adaptive SDC steps on the 2D monodomain workload on one MI355X.
+
+Workload: 512 x 512 P1 triangle mesh (262,144 dofs) on [0,2]^2 cm,
+anisotropic fibre conductivity, Aliev-Panfilov reaction, SDC on M = 4
+Radau-IIA nodes, K = 4 sweeps per step, dt = 0.2 ms, drop tolerance 1e-7,
+Jacobi-PCG to rtol 1e-12 (synthetic seeded inputs).  A "step" is one SDC
+time step: K sweeps, each with M restricted solves, the reaction and the
+active-set selection.  `--warmup` steps run first (the front leaves the
+stimulus strip), then exactly `--steps` steps are timed with the device
+synchronised on both sides.
+
+Reported value: active dof-sweeps per second = sum over timed steps and
+sweeps of the active rows, divided by the timed wall time.  The roofline
+entry is for the dominant kernel (the CG SpMV pass), timed with HIP events
+on the library's stream; its bytes are the algorithmic minimum per launch.
+The CPU baseline is the FP64 oracle on one host core, run on a bounded
+sample of the same workload (a few steps from the same state).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ROCPROF_TRAFFIC = None   # filled from profiles/ when counters exist for this kernel version
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=512, help="grid side (workload uses 512)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    return ap.parse_args()
+
+
+def sweep_bytes(st, M, ident):
+    """Algorithmic bytes of one sweep from its statistics (FP64 = 8 B, int32 = 4 B).
+
+    Per active row (n_a rows, z_a stored entries of A in them; idx read only
+    when not every row is active):
+      sweep start   12 z_a + 4 + idx + 8 (6M + 4)
+      rhs + CG init 12 z_a [m > 0] + 4 + idx + 8 (2m + 5)
+      CG SpMV pass  12 z + 4 + idx + 40  per iteration (z = entries of the
+                    rows still iterating)
+      CG update     idx + 56             per iteration
+      post-solve    idx + 8 (m + 14)
+      selection     2 idx + 24
+    """
+    na, za = st["n_active"], st["nnz_active"]
+    idxb = 0 if ident else 4
+    b = 12 * za + na * (4 + idxb + 8 * (6 * M + 4))
+    for m in range(M):
+        rows, nnz = st["cg_row_iters"][m], st["cg_nnz_iters"][m]
+        b += 12 * nnz + (44 + idxb) * rows
+        b += (56 + idxb) * rows
+        b += (12 * za if m > 0 else 0) + na * (4 + idxb + 8 * (2 * m + 5))
+        b += na * (idxb + 8 * (m + 14))
+    b += na * (2 * idxb + 24)
+    return b
+
+
+def step_bytes(N, M):
+    """Per step outside the sweeps: spread (read v0, w0; write v, w, I, R at M nodes) and copy-out."""
+    return N * (16 + 32 * M) + N * 32
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    from workloads import config1
+
+    P = config1(n=args.n, theta=1e-7)
+    dev = torch.device("cuda", 0)
+    s = Solver.from_problem(P)
+    v = torch.tensor(P.v_init, device=dev)
+    w = torch.tensor(P.w_init, device=dev)
+    t = 0.0
+    for n in range(args.warmup):
+        s.step(v, w, t)
+        t += P.dt
+    torch.cuda.synchronize()
+    v_start, w_start, t_start = v.cpu().numpy().copy(), w.cpu().numpy().copy(), t
+
+    def timed(profile):
+        vv, ww = torch.tensor(v_start, device=dev), torch.tensor(w_start, device=dev)
+        tt = t_start
+        logs = []
+        if profile:
+            s.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(args.steps):
+            logs.append(s.step(vv, ww, tt, stats=True))
+            tt += P.dt
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = s.profile_read() if profile else None
+        if profile:
+            s.profile(False)
+        return el, logs, prof
+
+    elapsed, logs, _ = timed(False)
+    prof = None
+    if not args.no_profile:
+        _, _, prof = timed(True)
+    sweeps = [st for lg in logs for st in lg]
+    dof_sweeps = sum(st["n_active"] for st in sweeps)
+    nbytes = sum(sweep_bytes(st, P.M, k == 0) for lg in logs for k, st in enumerate(lg))
+    nbytes += args.steps * step_bytes(P.N, P.M)
+    per_sweep_active = [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)]
+    cg_iters = [float(np.mean([lg[k]["cg_iters_max"][m] for lg in logs for k in range(P.K)])) for m in range(P.M)]
+
+    out = {
+        "metric": "active dof-sweeps/sec + HBM GB/s (% peak); adjoint/forward time ratio",
+        "value": dof_sweeps / elapsed,
+        "unit": "active dof-sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2D monodomain {args.n}x{args.n} P1 ({P.N} dofs), Aliev-Panfilov, SDC M={P.M} K={P.K} "
+                        f"dt={P.dt} ms, theta={P.theta}, Jacobi-PCG rtol {P.cg_rtol}; timed steps "
+                        f"t={t_start:.1f}..{t_start + args.steps * P.dt:.1f} ms",
+            "dofs": P.N, "nnz": s.nnz, "M": P.M, "K": P.K,
+        },
+        "algorithmic_GBps": nbytes / elapsed / 1e9,
+        "algorithmic_frac_hbm": nbytes / elapsed / 1e9 / HBM_PEAK_GBS,
+        "mean_active_per_sweep": per_sweep_active,
+        "mean_cg_iters_per_node": cg_iters,
+    }
+    if prof and prof["spmv_launches"]:
+        ach = prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9
+        out["roofline"] = {
+            "kernel": "k_cg_spmv", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": ROCPROF_TRAFFIC,
+            "avg_launch_us": 1e3 * prof["spmv_ms"] / prof["spmv_launches"],
+            "bytes_per_launch": prof["spmv_bytes"] / prof["spmv_launches"],
+            "launches": prof["spmv_launches"],
+        }
+        out["update_kernel"] = {
+            "kernel": "k_cg_update",
+            "achieved_GBps": prof["update_bytes"] / (prof["update_ms"] * 1e-3) / 1e9,
+            "avg_launch_us": 1e3 * prof["update_ms"] / prof["update_launches"],
+        }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(P, v0, w0, t0, nsteps):
+    """The oracle on one core, a few steps from the timed region's start state."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+    from oracle.sdc import build, run
+    orc = build(P)
+    t = time.perf_counter()
+    _, _, log = run(orc, v0, w0, nsteps, P.K, P.stimuli, t0=t0)
+    el = time.perf_counter() - t
+    dof_sweeps = sum(info["n_active"] for step in log for info in step)
+    return {"value": dof_sweeps / el, "unit": "active dof-sweeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} oracle steps of the same workload from t={t0:.1f} ms ({el:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

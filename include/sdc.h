@@ -1,0 +1,200 @@
+/*
+ * sdc.h -- C ABI of the MI355X (gfx950) adaptive spectral-deferred-correction
+ * library for monodomain reaction-diffusion systems.
+ *
+ * Problem (paper Sec. 2.2, eq. "abstract monodomain"; abstract form B z' = F(z),
+ * Sec. 3):  P1 finite elements on simplices give
+ *
+ *     ML v' = -A v - ML * I(v, w),        w' = R(v, w),
+ *
+ * with ML the row-sum lumped mass, A the stiffness matrix and (I, R) the
+ * Aliev-Panfilov current and gating rate (Sec. 5.1).  One step of length dt
+ * is taken by SDC on M Radau-IIA nodes (Sec. 3.1) with the LU-trick
+ * lower-triangular QI for the implicit diffusion and forward Euler between
+ * nodes (QE) for the explicit reaction (operator splitting as basic scheme,
+ * Sec. 3.2, eq. final-sdc, read as implicit-explicit).  Each node's linear
+ * system (ML + dt*QI[m][m]*A) dv = b is solved by Jacobi-preconditioned CG
+ * (Sec. 4.2).  Sweep k works only on the nested active index set I_k
+ * (Sec. 4.2): the next set keeps the rows whose correction max_m |dv_m,i|
+ * reached the drop tolerance theta (eq. "subset"); theta <= 0 gives the
+ * non-adaptive method.  Every step starts with all rows active.
+ *
+ * Several independent instances ("batch") can share one context: they are
+ * numbered consecutively (node_off), never share an element, and each runs
+ * its own CG with its own scalars and stopping test.
+ *
+ * Conventions
+ *  - All calls return int: SDC_OK (0) or a negative SDC_ERR_* code; nothing
+ *    throws across the ABI.  The message of the last error of a context is
+ *    returned by sdc_last_error.  After SDC_ERR_HIP the context should be
+ *    destroyed.
+ *  - "device" pointers are HIP device memory of the context's device, FP64
+ *    unless stated, contiguous, owned by the caller; the library never frees
+ *    them.  "host" arrays are read during the call and copied.
+ *  - Work is enqueued on the stream given to sdc_create.  Calls that return
+ *    host statistics synchronise that stream.
+ *  - Node indices are int32 (0 .. N-1, N < 2^31); index lists are ascending.
+ */
+#ifndef SDC_H
+#define SDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SDC_OK = 0,
+  SDC_ERR_ARG = -1,        /* invalid argument (null pointer, size, order)   */
+  SDC_ERR_HIP = -2,        /* a HIP runtime call failed                      */
+  SDC_ERR_CG_MAXIT = -3,   /* a CG solve did not converge within cg_maxit    */
+  SDC_ERR_STATE = -4,      /* call out of order (e.g. sweep before a step)   */
+  SDC_ERR_OOM = -5,        /* device allocation failed                       */
+  SDC_ERR_NONFINITE = -6   /* NaN/Inf or a non-positive CG curvature p.Hp    */
+};
+
+#define SDC_MAX_NODES 6    /* collocation nodes M supported: 1..6            */
+#define SDC_MAX_SWEEPS 16  /* sweeps per step K supported: 1..16             */
+
+typedef struct sdc_ctx sdc_ctx;
+
+/* Solver settings, copied by sdc_setup_mesh. */
+typedef struct {
+  int32_t M;          /* Radau-IIA collocation nodes, 1..SDC_MAX_NODES         */
+  int32_t K;          /* SDC sweeps per step, 1..SDC_MAX_SWEEPS                */
+  double dt;          /* step length                                           */
+  double theta;       /* drop tolerance TOL_drop; <= 0: all rows stay active   */
+  double cg_rtol;     /* stop when ||r||_2 <= cg_rtol * ||b||_2 (active rows)  */
+  int32_t cg_maxit;   /* CG iteration limit per solve (SDC_ERR_CG_MAXIT)       */
+  int32_t reserved;   /* must be 0                                             */
+} sdc_params;
+
+/* Per-sweep statistics (sums over instances unless stated). */
+typedef struct {
+  int64_t n_active;                    /* rows of I_k                           */
+  int64_t nnz_active;                  /* stored entries of A in those rows     */
+  int64_t n_next;                      /* rows of I_{k+1} (selected)            */
+  int32_t cg_iters_max[SDC_MAX_NODES]; /* max CG iterations over instances      */
+  int64_t cg_row_iters[SDC_MAX_NODES]; /* sum_inst iters * active rows          */
+  int64_t cg_nnz_iters[SDC_MAX_NODES]; /* sum_inst iters * active entries       */
+} sdc_sweep_stats;
+
+typedef struct {
+  int32_t n_sweeps;
+  sdc_sweep_stats sweep[SDC_MAX_SWEEPS];
+} sdc_step_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`; `stream` is a hipStream_t (NULL =
+ * the null stream).  *out receives the context or NULL on error. */
+int sdc_create(sdc_ctx** out, int32_t device, void* stream);
+void sdc_destroy(sdc_ctx* ctx);
+/* Message of the last failed call (owned by ctx; valid until the next call). */
+const char* sdc_last_error(const sdc_ctx* ctx);
+/* Replace the stream later work is enqueued on. */
+int sdc_set_stream(sdc_ctx* ctx, void* stream);
+
+/* ---- setup (paper Sec. 2.2: P1 discretisation) ------------------------ */
+
+/* Assemble ML and A on the host and upload everything the sweeps need.
+ *  dim          1, 2 or 3 (simplices with dim+1 vertices)
+ *  n_inst       number of independent instances (>= 1)
+ *  node_off     host int64[n_inst+1]: instance i owns nodes [node_off[i], node_off[i+1])
+ *  coords       host double[N][dim]
+ *  elem_off     host int64[n_inst+1]: instance i owns elements [elem_off[i], elem_off[i+1])
+ *  elems        host int32[E][dim+1], global node ids inside the owning instance
+ *  elem_tensor  host double[E][dim][dim]: unit conductivity tensor D_T
+ *  node_sigma   host double[N]: conductivity multiplier; element value is the
+ *               mean over its vertices, A = sum_T sigma_T |T| G_T D_T G_T^T
+ *  ionic        host double[n_inst][6]: Aliev-Panfilov (k, a, eps0, mu1, mu2, s)
+ * May be called once per context. */
+int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* params, int32_t dim, int32_t n_inst,
+                   const int64_t* node_off, const double* coords, const int64_t* elem_off,
+                   const int32_t* elems, const double* elem_tensor, const double* node_sigma,
+                   const double* ionic);
+
+/* Stimulus: at the start of the step whose interval [t, t+dt) contains t_on,
+ * set v = value on the listed nodes (host int32[n]) before spreading. */
+int sdc_add_stimulus(sdc_ctx* ctx, double t_on, const int32_t* nodes, int64_t n, double value);
+
+/* Sizes of the assembled system: N, nnz of A, Nw (= N for monodomain). */
+int sdc_get_sizes(const sdc_ctx* ctx, int64_t* n, int64_t* nnz, int64_t* nw);
+
+/* Copy the assembled CSR of A and the lumped mass to host arrays
+ * rowptr int32[N+1], col int32[nnz], val double[nnz], ml double[N]. */
+int sdc_get_system(sdc_ctx* ctx, int32_t* rowptr, int32_t* col, double* val, double* ml);
+
+/* ---- time stepping (paper Sec. 3, eq. final-sdc; Sec. 4.2) ------------- */
+
+/* One SDC step: (v, w) at time t -> (v, w) at t + dt, in place.  v, w are
+ * device double[N].  stats (host, may be NULL) receives per-sweep counts. */
+int sdc_step(sdc_ctx* ctx, double* v, double* w, double t, sdc_step_stats* stats);
+
+/* The same step in parts: begin (stimulus, spread, all rows active), then
+ * sdc_sweep up to K times, then end (copy the last node out). */
+int sdc_begin_step(sdc_ctx* ctx, const double* v, const double* w, double t);
+int sdc_sweep(sdc_ctx* ctx, sdc_sweep_stats* stats);
+int sdc_end_step(sdc_ctx* ctx, double* v, double* w);
+
+/* Copy collocation node m's current values (device double[N] each). */
+int sdc_get_node(sdc_ctx* ctx, int32_t m, double* v_m, double* w_m);
+
+/* Current active set (the set the next sweep will use): idx device int32
+ * with room for N entries (may be NULL to query only), *n receives its length. */
+int sdc_get_active(sdc_ctx* ctx, int32_t* idx, int64_t* n);
+
+/* Pin the active set of sweep `sweep` (1..K-1; sweep 0 always uses all rows)
+ * for all following steps, replacing the selection rule there: idx is a
+ * device int32[n] ascending list (copied).  sweep < 0 clears every pin. */
+int sdc_set_active(sdc_ctx* ctx, int32_t sweep, const int32_t* idx, int64_t n);
+
+/* ---- components (for kernel-level parity tests) ----------------------- */
+
+/* Restricted Jacobi-PCG (paper Sec. 4.2) on H_m = ML + dt*QI[m][m]*A:
+ * solve H_m[idx, idx] x = b[idx] with x = 0 off idx.  idx device int32[n]
+ * ascending, each instance's rows contiguous; b, x device double[N] (x is
+ * fully overwritten).  iters host int32[n_inst] (may be NULL). */
+int sdc_solve(sdc_ctx* ctx, int32_t m, const int32_t* idx, int64_t n, const double* b,
+              double* x, int32_t* iters);
+
+/* Active-set compaction (paper eq. "subset", Sec. 4.2): idx_out = the
+ * entries i of idx_in (device int32[n_in], ascending) with amax[i] >= theta,
+ * in order; theta <= 0 keeps all.  amax device double[N]; idx_out device
+ * int32[n_in]; *n_out host. */
+int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t n_in,
+               double theta, int32_t* idx_out, int64_t* n_out);
+
+/* ---- measurement ------------------------------------------------------ */
+
+/* Kernel timing of the two CG kernels (SpMV pass and update pass), taken
+ * with HIP events on the context's stream around every launch that does
+ * work for at least one instance.  Bytes are the algorithmic minimum per
+ * launch over the instances still iterating:
+ *   SpMV pass:   12 nnz_a + (4 rowptr + 4 idx + 3*8 gathers + 2*8 writes) n_a
+ *   update pass: (4 idx + 5*8 reads + 2*8 writes) n_a
+ * (the 4-byte idx read is absent when every row is active). */
+typedef struct {
+  int64_t spmv_launches;
+  double spmv_ms;
+  double spmv_bytes;
+  int64_t update_launches;
+  double update_ms;
+  double update_bytes;
+} sdc_profile_stats;
+
+/* enable != 0 starts timing (and clears the totals); 0 stops it. */
+int sdc_profile(sdc_ctx* ctx, int32_t enable);
+int sdc_profile_read(sdc_ctx* ctx, sdc_profile_stats* out);
+
+/* Collocation data used by the library (paper Sec. 3.1): host outputs
+ * tau[M], Q[M][M] (zero-to-node integrals of the Lagrange basis),
+ * QI[M][M] (U^T of Q^T = L U), QE[M][M] (forward Euler between nodes). */
+int sdc_collocation(int32_t M, double* tau, double* Q, double* QI, double* QE);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDC_H */

@@ -1,0 +1,96 @@
+"""ctypes declarations of the C ABI in include/sdc.h.
+
+Loading fails loudly when the HIP library has not been built: there is no
+fallback implementation.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdc.so")
+
+MAX_NODES = 6
+MAX_SWEEPS = 16
+
+SDC_OK = 0
+ERRORS = {
+    -1: "SDC_ERR_ARG", -2: "SDC_ERR_HIP", -3: "SDC_ERR_CG_MAXIT", -4: "SDC_ERR_STATE",
+    -5: "SDC_ERR_OOM", -6: "SDC_ERR_NONFINITE",
+}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("M", c_int32), ("K", c_int32), ("dt", c_double), ("theta", c_double),
+                ("cg_rtol", c_double), ("cg_maxit", c_int32), ("reserved", c_int32)]
+
+
+class SweepStats(ctypes.Structure):
+    _fields_ = [("n_active", c_int64), ("nnz_active", c_int64), ("n_next", c_int64),
+                ("cg_iters_max", c_int32 * MAX_NODES), ("cg_row_iters", c_int64 * MAX_NODES),
+                ("cg_nnz_iters", c_int64 * MAX_NODES)]
+
+    def as_dict(self, M):
+        return {
+            "n_active": self.n_active, "nnz_active": self.nnz_active, "n_next": self.n_next,
+            "cg_iters_max": list(self.cg_iters_max[:M]),
+            "cg_row_iters": list(self.cg_row_iters[:M]),
+            "cg_nnz_iters": list(self.cg_nnz_iters[:M]),
+        }
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("n_sweeps", c_int32), ("sweep", SweepStats * MAX_SWEEPS)]
+
+
+class ProfileStats(ctypes.Structure):
+    _fields_ = [("spmv_launches", c_int64), ("spmv_ms", c_double), ("spmv_bytes", c_double),
+                ("update_launches", c_int64), ("update_ms", c_double), ("update_bytes", c_double)]
+
+
+PTR = c_void_p
+P_I64 = POINTER(c_int64)
+P_I32 = POINTER(c_int32)
+
+SIGNATURES = {
+    "sdc_create": (c_int32, [POINTER(c_void_p), c_int32, c_void_p]),
+    "sdc_destroy": (None, [c_void_p]),
+    "sdc_last_error": (c_char_p, [c_void_p]),
+    "sdc_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "sdc_setup_mesh": (c_int32, [c_void_p, POINTER(Params), c_int32, c_int32, PTR, PTR, PTR, PTR,
+                                 PTR, PTR, PTR]),
+    "sdc_add_stimulus": (c_int32, [c_void_p, c_double, PTR, c_int64, c_double]),
+    "sdc_get_sizes": (c_int32, [c_void_p, P_I64, P_I64, P_I64]),
+    "sdc_get_system": (c_int32, [c_void_p, PTR, PTR, PTR, PTR]),
+    "sdc_step": (c_int32, [c_void_p, PTR, PTR, c_double, POINTER(StepStats)]),
+    "sdc_begin_step": (c_int32, [c_void_p, PTR, PTR, c_double]),
+    "sdc_sweep": (c_int32, [c_void_p, POINTER(SweepStats)]),
+    "sdc_end_step": (c_int32, [c_void_p, PTR, PTR]),
+    "sdc_get_node": (c_int32, [c_void_p, c_int32, PTR, PTR]),
+    "sdc_get_active": (c_int32, [c_void_p, PTR, P_I64]),
+    "sdc_set_active": (c_int32, [c_void_p, c_int32, PTR, c_int64]),
+    "sdc_solve": (c_int32, [c_void_p, c_int32, PTR, c_int64, PTR, PTR, P_I32]),
+    "sdc_select": (c_int32, [c_void_p, PTR, PTR, c_int64, c_double, PTR, P_I64]),
+    "sdc_collocation": (c_int32, [c_int32, PTR, PTR, PTR, PTR]),
+    "sdc_profile": (c_int32, [c_void_p, c_int32]),
+    "sdc_profile_read": (c_int32, [c_void_p, POINTER(ProfileStats)]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libsdc.so (once) and declare every ABI function."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(or python paper_2311_07206_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

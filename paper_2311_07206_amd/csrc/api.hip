@@ -1,0 +1,718 @@
+// C ABI and host orchestration of the adaptive SDC step (see include/sdc.h).
+//
+// One context owns: the assembled system (CSR of A, lumped mass ML, the M
+// node matrices H_m = ML + dt*QI[m][m]*A with their inverse diagonals), the
+// collocation state [M][N] (v, w, I, R, Phi, Gam, dv, dI, dR), the CG work
+// vectors, and the work maps of the active sets.  All device work goes to
+// the context's stream; the host synchronises once per CG budget (to learn
+// which instances converged) and once per selection (to size the next
+// sweep's grids).
+#include "sdc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace sdc;
+
+namespace {
+
+struct MapBuf {
+  int4* blk = nullptr;
+  int32_t* inst_blk0 = nullptr;
+  int32_t* inst_nblk = nullptr;
+  int32_t* inst_cnt = nullptr;
+  int64_t* inst_nnz = nullptr;
+  int32_t* aoff = nullptr;
+  int32_t* totals = nullptr;
+  const int32_t* idx = nullptr;       // list the map indexes (null: all rows)
+  // host mirror, valid after the map is built
+  int32_t nblk = 0;
+  int64_t rows = 0;
+  std::vector<int32_t> cnt;
+  std::vector<int64_t> nnz;
+
+  Map dev() const { return Map{blk, inst_blk0, inst_nblk, idx, nblk}; }
+  NextMap next() const { return NextMap{blk, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals}; }
+};
+
+struct Stimulus {
+  double t_on;
+  int32_t* nodes;
+  int64_t n;
+  double value;
+};
+
+}  // namespace
+
+struct sdc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<void*> allocs;
+
+  bool ready = false;
+  sdc_params prm{};
+  Collocation col{};
+  CollArgs cargs{};
+  int dim = 0;
+  int64_t N = 0, nnz = 0;
+  int n_inst = 0;
+  std::vector<int64_t> node_off_h;
+  HostSystem host;   // kept for sdc_get_system
+
+  int32_t *rowptr = nullptr, *colidx = nullptr, *diagpos = nullptr;
+  double *Aval = nullptr, *Hval = nullptr, *ml = nullptr, *dinv = nullptr;
+  int64_t* node_off_d = nullptr;
+  double* ionic_d = nullptr;
+
+  double *v0 = nullptr, *w0 = nullptr, *v = nullptr, *w = nullptr, *I = nullptr, *R = nullptr;
+  double *Phi = nullptr, *Gam = nullptr, *dv = nullptr, *dI = nullptr, *dR = nullptr;
+  double *amax = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+
+  double* cg_scal = nullptr;
+  int32_t *cg_done = nullptr, *cg_iters = nullptr;
+  uint32_t* cg_counter = nullptr;
+  double* part = nullptr;
+  int32_t *sel_cnt = nullptr, *sel_nnz = nullptr;
+
+  MapBuf all;
+  MapBuf dyn[2];
+  int32_t* list[2] = {nullptr, nullptr};
+  int cur = -1;   // -1: all rows; 0/1: dyn slot
+
+  int32_t* h_i32 = nullptr;   // pinned staging
+  int64_t* h_i64 = nullptr;
+
+  std::vector<Stimulus> stims;
+  std::vector<int32_t*> pin;
+  std::vector<int64_t> pin_n;
+
+  bool in_step = false;
+  int k = 0;
+
+  // kernel timing (bench only)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;   // 3 per iteration: before SpMV, between, after update
+  sdc_profile_stats pst{};
+  std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
+
+  const MapBuf& curmap() const { return cur < 0 ? all : dyn[cur]; }
+  CgState cg() const { return CgState{cg_scal, cg_done, cg_iters, cg_counter, part}; }
+  Csr A() const { return Csr{rowptr, colidx, Aval}; }
+  Csr H(int m) const { return Csr{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz}; }
+  ZeroVecs zv() const { return ZeroVecs{r, p[0], p[1], dv, prm.M, N}; }
+};
+
+namespace {
+
+int fail(sdc_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  c->err = buf;
+  return code;
+}
+
+#define HIPC(call)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, SDC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+  } while (0)
+
+template <class T>
+int dalloc(sdc_ctx* ctx, T** out, size_t count) {
+  void* ptr = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) return fail(ctx, SDC_ERR_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  e = hipMemsetAsync(ptr, 0, bytes, ctx->stream);
+  if (e != hipSuccess) return fail(ctx, SDC_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+  ctx->allocs.push_back(ptr);
+  *out = static_cast<T*>(ptr);
+  return SDC_OK;
+}
+
+#define TRY(x)              \
+  do {                      \
+    int rc_ = (x);          \
+    if (rc_ != SDC_OK) return rc_; \
+  } while (0)
+
+int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap) {
+  const int ni = ctx->n_inst;
+  TRY(dalloc(ctx, &mb->blk, nblk_cap));
+  TRY(dalloc(ctx, &mb->inst_blk0, ni + 1));
+  TRY(dalloc(ctx, &mb->inst_nblk, ni + 1));
+  TRY(dalloc(ctx, &mb->inst_cnt, ni + 1));
+  TRY(dalloc(ctx, &mb->inst_nnz, ni + 1));
+  TRY(dalloc(ctx, &mb->aoff, ni + 1));
+  TRY(dalloc(ctx, &mb->totals, 4));
+  mb->cnt.assign(ni, 0);
+  mb->nnz.assign(ni, 0);
+  return SDC_OK;
+}
+
+// Read a freshly built map's sizes back to the host (synchronises).
+int fetch_map(sdc_ctx* ctx, MapBuf* mb) {
+  const int ni = ctx->n_inst;
+  HIPC(hipMemcpyAsync(ctx->h_i32, mb->totals, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->h_i32 + 4, mb->inst_cnt, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->h_i64, mb->inst_nnz, ni * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));
+  mb->nblk = ctx->h_i32[0];
+  mb->rows = ctx->h_i32[1];
+  if (ctx->h_i32[2] != 0) return fail(ctx, SDC_ERR_ARG, "index list not strictly ascending or out of range");
+  for (int i = 0; i < ni; ++i) {
+    mb->cnt[i] = ctx->h_i32[4 + i];
+    mb->nnz[i] = ctx->h_i64[i];
+  }
+  return SDC_OK;
+}
+
+// Add the event timings of iterations [it0, it0 + budget) to the profile;
+// an iteration counts for the instances whose CG had not stopped before it.
+int account_timing(sdc_ctx* ctx, const MapBuf& mb, int it0, int budget, const int32_t* iters) {
+  const bool ident = mb.idx == nullptr;
+  for (int b = 0; b < budget; ++b) {
+    const int it = it0 + b;
+    double sp_bytes = 0.0, up_bytes = 0.0;
+    for (int i = 0; i < ctx->n_inst; ++i) {
+      if (it >= iters[i] || mb.cnt[i] == 0) continue;
+      const double na = mb.cnt[i], za = static_cast<double>(mb.nnz[i]);
+      sp_bytes += 12.0 * za + (ident ? 44.0 : 48.0) * na;
+      up_bytes += (ident ? 56.0 : 60.0) * na;
+    }
+    if (sp_bytes == 0.0) continue;
+    float t1 = 0.f, t2 = 0.f;
+    HIPC(hipEventElapsedTime(&t1, ctx->ev[3 * b], ctx->ev[3 * b + 1]));
+    HIPC(hipEventElapsedTime(&t2, ctx->ev[3 * b + 1], ctx->ev[3 * b + 2]));
+    ctx->pst.spmv_launches++;
+    ctx->pst.spmv_ms += t1;
+    ctx->pst.spmv_bytes += sp_bytes;
+    ctx->pst.update_launches++;
+    ctx->pst.update_ms += t2;
+    ctx->pst.update_bytes += up_bytes;
+  }
+  return SDC_OK;
+}
+
+// Restricted Jacobi-PCG on H_m over the current map, starting from the state
+// prepared by an init kernel (r = b, x = 0, scalars).  Iterations are
+// launched in budgets; after each budget the host reads the per-instance
+// done flags.  Kernels of converged instances return immediately.
+int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std::vector<int>* iters) {
+  const int ni = ctx->n_inst;
+  const Map map = mb.dev();
+  const Csr H = ctx->H(m);
+  const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
+  const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
+  int budget = pred_slot >= 0 ? std::max(1, ctx->pred[pred_slot]) : 8;
+  int it = 0;
+  iters->assign(ni, 0);
+  if (mb.nblk > 0) {
+    for (;;) {
+      const int it0 = it;
+      const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 3 * budget;
+      for (int b = 0; b < budget; ++b, ++it) {
+        double* pold = ctx->p[it & 1];
+        double* pnew = ctx->p[(it + 1) & 1];
+        if (timed) HIPC(hipEventRecord(ctx->ev[3 * b], ctx->stream));
+        launch_cg_spmv(ctx->stream, map, H, dinv, ctx->r, pold, pnew, ctx->q, it == 0, ctx->cg());
+        if (timed) HIPC(hipEventRecord(ctx->ev[3 * b + 1], ctx->stream));
+        launch_cg_update(ctx->stream, map, dinv, pnew, ctx->q, x, ctx->r, rtol2, ctx->prm.cg_maxit, ctx->cg());
+        if (timed) HIPC(hipEventRecord(ctx->ev[3 * b + 2], ctx->stream));
+      }
+      HIPC(hipGetLastError());
+      HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+      HIPC(hipMemcpyAsync(ctx->h_i32 + ni, ctx->cg_iters, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+      HIPC(hipStreamSynchronize(ctx->stream));
+      if (timed) TRY(account_timing(ctx, mb, it0, budget, ctx->h_i32 + ni));
+      bool running = false;
+      for (int i = 0; i < ni; ++i) {
+        const int d = ctx->h_i32[i];
+        if (d == 2)
+          return fail(ctx, SDC_ERR_CG_MAXIT, "CG: instance %d, node %d, sweep %d: no convergence in %d iterations",
+                      i, m, ctx->k, ctx->prm.cg_maxit);
+        if (d == 3)
+          return fail(ctx, SDC_ERR_NONFINITE, "CG: instance %d, node %d, sweep %d: non-finite or non-positive curvature",
+                      i, m, ctx->k);
+        if (d == 0) running = true;
+      }
+      if (!running) break;
+      if (it >= ctx->prm.cg_maxit + 1)
+        return fail(ctx, SDC_ERR_CG_MAXIT, "CG: iteration limit reached (node %d, sweep %d)", m, ctx->k);
+      budget = std::max(2, budget / 2);
+    }
+    for (int i = 0; i < ni; ++i) (*iters)[i] = ctx->h_i32[ni + i];
+  }
+  if (pred_slot >= 0) {
+    int mx = 0;
+    for (int v : *iters) mx = std::max(mx, v);
+    ctx->pred[pred_slot] = mx + 1;
+  }
+  return SDC_OK;
+}
+
+// Build the work map of a device list into dyn slot `slot` and fetch its sizes.
+int map_list(sdc_ctx* ctx, int slot, const int32_t* idx, int64_t n) {
+  MapBuf& mb = ctx->dyn[slot];
+  launch_map_from_list(ctx->stream, idx, n, ctx->N, ctx->node_off_d, ctx->n_inst, ctx->rowptr, mb.next());
+  HIPC(hipGetLastError());
+  TRY(fetch_map(ctx, &mb));
+  mb.idx = idx;
+  return SDC_OK;
+}
+
+// One sweep over the current active set; afterwards the current set is the
+// one the next sweep uses (pinned, selected, or unchanged).
+int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next) {
+  const int M = ctx->prm.M;
+  const int64_t N = ctx->N;
+  const MapBuf& mb = ctx->curmap();
+  const Map map = mb.dev();
+  if (st) {
+    std::memset(st, 0, sizeof *st);
+    st->n_active = mb.rows;
+    for (int i = 0; i < ctx->n_inst; ++i) st->nnz_active += mb.nnz[i];
+  }
+  launch_sweep_start(ctx->stream, M, map, N, ctx->A(), ctx->ml, ctx->v0, ctx->w0, ctx->v, ctx->w,
+                     ctx->I, ctx->R, ctx->Phi, ctx->Gam, ctx->amax, ctx->cargs);
+  std::vector<int> iters;
+  for (int m = 0; m < M; ++m) {
+    double* x = ctx->dv + m * N;
+    launch_rhs_init(ctx->stream, M, m, map, ctx->n_inst, N, ctx->A(), ctx->ml, ctx->dinv + m * N,
+                    ctx->Phi + m * N, ctx->dI, ctx->dv, ctx->r, x, ctx->cg(), ctx->cargs);
+    HIPC(hipGetLastError());
+    const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
+    TRY(run_cg(ctx, m, mb, x, slot, &iters));
+    launch_post(ctx->stream, M, m, map, N, ctx->ionic_d, x, ctx->v + m * N, ctx->w + m * N,
+                ctx->I + m * N, ctx->R + m * N, ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N,
+                ctx->dR, ctx->amax, ctx->cargs);
+    HIPC(hipGetLastError());
+    if (st) {
+      for (int i = 0; i < ctx->n_inst; ++i) {
+        st->cg_iters_max[m] = std::max(st->cg_iters_max[m], iters[i]);
+        st->cg_row_iters[m] += static_cast<int64_t>(iters[i]) * mb.cnt[i];
+        st->cg_nnz_iters[m] += static_cast<int64_t>(iters[i]) * mb.nnz[i];
+      }
+    }
+  }
+  const int next = ctx->k + 1;
+  if (next < static_cast<int>(ctx->pin.size()) && ctx->pin[next]) {
+    launch_zero_rows(ctx->stream, map, ctx->zv());
+    const int slot = ctx->cur == 0 ? 1 : 0;
+    TRY(map_list(ctx, slot, ctx->pin[next], ctx->pin_n[next]));
+    ctx->cur = slot;
+  } else if (ctx->prm.theta > 0.0 && select_next) {
+    const int slot = ctx->cur == 0 ? 1 : 0;
+    MapBuf& nm = ctx->dyn[slot];
+    launch_select(ctx->stream, map, ctx->n_inst, ctx->rowptr, ctx->amax, ctx->prm.theta, ctx->sel_cnt,
+                  ctx->sel_nnz, ctx->list[slot], nm.next(), ctx->zv());
+    HIPC(hipGetLastError());
+    TRY(fetch_map(ctx, &nm));
+    nm.idx = ctx->list[slot];
+    ctx->cur = slot;
+  }
+  if (st) st->n_next = ctx->curmap().rows;
+  ctx->k = next;
+  return SDC_OK;
+}
+
+int check_ready(sdc_ctx* ctx) {
+  if (!ctx) return SDC_ERR_ARG;
+  if (!ctx->ready) return fail(ctx, SDC_ERR_STATE, "sdc_setup_mesh has not been called");
+  HIPC(hipSetDevice(ctx->device));
+  return SDC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- ABI
+
+extern "C" {
+
+int sdc_create(sdc_ctx** out, int32_t device, void* stream) {
+  if (!out) return SDC_ERR_ARG;
+  *out = nullptr;
+  sdc_ctx* ctx = new (std::nothrow) sdc_ctx();
+  if (!ctx) return SDC_ERR_OOM;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    delete ctx;
+    return SDC_ERR_HIP;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return SDC_ERR_HIP;
+  }
+  *out = ctx;
+  return SDC_OK;
+}
+
+void sdc_destroy(sdc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  for (auto& s : ctx->stims) (void)hipFree(s.nodes);
+  for (auto* p : ctx->pin) if (p) (void)hipFree(p);
+  for (auto e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->h_i32) (void)hipHostFree(ctx->h_i32);
+  if (ctx->h_i64) (void)hipHostFree(ctx->h_i64);
+  delete ctx;
+}
+
+const char* sdc_last_error(const sdc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sdc_set_stream(sdc_ctx* ctx, void* stream) {
+  if (!ctx) return SDC_ERR_ARG;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return SDC_OK;
+}
+
+int sdc_collocation(int32_t M, double* tau, double* Q, double* QI, double* QE) {
+  Collocation c;
+  if (M < 1 || M > SDC_MAX_NODES || collocation(M, &c) != 0) return SDC_ERR_ARG;
+  for (int m = 0; m < M; ++m) {
+    if (tau) tau[m] = c.tau[m];
+    for (int j = 0; j < M; ++j) {
+      if (Q) Q[m * M + j] = c.Q[m][j];
+      if (QI) QI[m * M + j] = c.QI[m][j];
+      if (QE) QE[m * M + j] = c.QE[m][j];
+    }
+  }
+  return SDC_OK;
+}
+
+int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_inst,
+                   const int64_t* node_off, const double* coords, const int64_t* elem_off,
+                   const int32_t* elems, const double* elem_tensor, const double* node_sigma,
+                   const double* ionic) {
+  if (!ctx) return SDC_ERR_ARG;
+  if (ctx->ready) return fail(ctx, SDC_ERR_STATE, "sdc_setup_mesh may be called once per context");
+  if (!prm || !node_off || !coords || !elem_off || !elems || !elem_tensor || !node_sigma || !ionic)
+    return fail(ctx, SDC_ERR_ARG, "null argument");
+  if (prm->M < 1 || prm->M > SDC_MAX_NODES) return fail(ctx, SDC_ERR_ARG, "M must be in 1..%d", SDC_MAX_NODES);
+  if (prm->K < 1 || prm->K > SDC_MAX_SWEEPS) return fail(ctx, SDC_ERR_ARG, "K must be in 1..%d", SDC_MAX_SWEEPS);
+  if (!(prm->dt > 0.0) || !(prm->cg_rtol > 0.0) || prm->cg_maxit < 1 || prm->reserved != 0)
+    return fail(ctx, SDC_ERR_ARG, "dt, cg_rtol must be > 0, cg_maxit >= 1, reserved = 0");
+  if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
+  if (node_off[0] != 0 || elem_off[0] != 0) return fail(ctx, SDC_ERR_ARG, "offsets must start at 0");
+  for (int i = 0; i < n_inst; ++i)
+    if (node_off[i + 1] <= node_off[i] || elem_off[i + 1] < elem_off[i])
+      return fail(ctx, SDC_ERR_ARG, "instance %d: empty or decreasing offsets", i);
+  const int64_t N = node_off[n_inst], E = elem_off[n_inst];
+  if (N >= (int64_t(1) << 31) - kBlock) return fail(ctx, SDC_ERR_ARG, "too many nodes");
+  const int nv = dim + 1;
+  for (int i = 0; i < n_inst; ++i)
+    for (int64_t e = elem_off[i]; e < elem_off[i + 1]; ++e)
+      for (int a = 0; a < nv; ++a) {
+        const int64_t g = elems[e * nv + a];
+        if (g < node_off[i] || g >= node_off[i + 1])
+          return fail(ctx, SDC_ERR_ARG, "element %lld of instance %d uses node %lld outside it",
+                      static_cast<long long>(e), i, static_cast<long long>(g));
+      }
+  HIPC(hipSetDevice(ctx->device));
+  ctx->prm = *prm;
+  if (collocation(prm->M, &ctx->col) != 0) return fail(ctx, SDC_ERR_ARG, "collocation setup failed");
+  std::memset(&ctx->cargs, 0, sizeof ctx->cargs);
+  for (int m = 0; m < prm->M; ++m)
+    for (int j = 0; j < prm->M; ++j) {
+      ctx->cargs.Q[m][j] = ctx->col.Q[m][j];
+      ctx->cargs.QI[m][j] = ctx->col.QI[m][j];
+      ctx->cargs.QE[m][j] = ctx->col.QE[m][j];
+    }
+  ctx->cargs.dt = prm->dt;
+  ctx->dim = dim;
+  ctx->n_inst = n_inst;
+  ctx->N = N;
+  ctx->node_off_h.assign(node_off, node_off + n_inst + 1);
+
+  std::string e = assemble_p1(dim, N, coords, E, elems, elem_tensor, node_sigma, &ctx->host);
+  if (!e.empty()) return fail(ctx, SDC_ERR_ARG, "assembly: %s", e.c_str());
+  ctx->nnz = ctx->host.rowptr[N];
+  const int64_t nnz = ctx->nnz;
+  const int M = prm->M;
+
+  TRY(dalloc(ctx, &ctx->rowptr, N + 1));
+  TRY(dalloc(ctx, &ctx->colidx, nnz));
+  TRY(dalloc(ctx, &ctx->diagpos, N));
+  TRY(dalloc(ctx, &ctx->Aval, nnz));
+  TRY(dalloc(ctx, &ctx->Hval, nnz * M));
+  TRY(dalloc(ctx, &ctx->ml, N));
+  TRY(dalloc(ctx, &ctx->dinv, N * M));
+  TRY(dalloc(ctx, &ctx->node_off_d, n_inst + 1));
+  TRY(dalloc(ctx, &ctx->ionic_d, 6 * n_inst));
+  HIPC(hipMemcpyAsync(ctx->rowptr, ctx->host.rowptr.data(), (N + 1) * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->colidx, ctx->host.col.data(), nnz * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->diagpos, ctx->host.diag.data(), N * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->Aval, ctx->host.val.data(), nnz * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->ml, ctx->host.ml.data(), N * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->node_off_d, node_off, (n_inst + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->ionic_d, ionic, 6 * n_inst * 8, hipMemcpyHostToDevice, ctx->stream));
+  for (int m = 0; m < M; ++m)
+    launch_build_h(ctx->stream, N, ctx->rowptr, ctx->diagpos, ctx->Aval, ctx->ml,
+                   prm->dt * ctx->col.QI[m][m], ctx->Hval + m * nnz, ctx->dinv + m * N);
+  HIPC(hipGetLastError());
+
+  const size_t MN = static_cast<size_t>(M) * N;
+  TRY(dalloc(ctx, &ctx->v0, N));
+  TRY(dalloc(ctx, &ctx->w0, N));
+  for (double** b : {&ctx->v, &ctx->w, &ctx->I, &ctx->R, &ctx->Phi, &ctx->Gam, &ctx->dv, &ctx->dI, &ctx->dR})
+    TRY(dalloc(ctx, b, MN));
+  TRY(dalloc(ctx, &ctx->amax, N));
+  TRY(dalloc(ctx, &ctx->r, N));
+  TRY(dalloc(ctx, &ctx->p[0], N));
+  TRY(dalloc(ctx, &ctx->p[1], N));
+  TRY(dalloc(ctx, &ctx->q, N));
+
+  // all-rows work map (host-built)
+  std::vector<int4> blk;
+  std::vector<int32_t> blk0(n_inst + 1), nblk(n_inst + 1), cnt(n_inst + 1), aoff(n_inst + 1);
+  std::vector<int64_t> innz(n_inst + 1, 0);
+  for (int i = 0; i < n_inst; ++i) {
+    const int32_t lo = static_cast<int32_t>(node_off[i]), hi = static_cast<int32_t>(node_off[i + 1]);
+    blk0[i] = static_cast<int32_t>(blk.size());
+    cnt[i] = hi - lo;
+    aoff[i] = lo;
+    innz[i] = ctx->host.rowptr[hi] - ctx->host.rowptr[lo];
+    int bi = 0;
+    for (int32_t b = lo; b < hi; b += kBlock, ++bi) blk.push_back(make_int4(i, b, std::min(b + kBlock, hi), bi));
+    nblk[i] = bi;
+  }
+  aoff[n_inst] = static_cast<int32_t>(N);
+  const int32_t nblk_all = static_cast<int32_t>(blk.size());
+  TRY(alloc_map(ctx, &ctx->all, nblk_all));
+  TRY(alloc_map(ctx, &ctx->dyn[0], nblk_all));
+  TRY(alloc_map(ctx, &ctx->dyn[1], nblk_all));
+  HIPC(hipMemcpyAsync(ctx->all.blk, blk.data(), blk.size() * sizeof(int4), hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->all.inst_blk0, blk0.data(), n_inst * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->all.inst_nblk, nblk.data(), n_inst * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->all.inst_cnt, cnt.data(), n_inst * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->all.inst_nnz, innz.data(), n_inst * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->all.aoff, aoff.data(), (n_inst + 1) * 4, hipMemcpyHostToDevice, ctx->stream));
+  ctx->all.nblk = nblk_all;
+  ctx->all.rows = N;
+  ctx->all.idx = nullptr;
+  for (int i = 0; i < n_inst; ++i) {
+    ctx->all.cnt[i] = cnt[i];
+    ctx->all.nnz[i] = innz[i];
+  }
+  TRY(dalloc(ctx, &ctx->list[0], N));
+  TRY(dalloc(ctx, &ctx->list[1], N));
+  TRY(dalloc(ctx, &ctx->cg_scal, static_cast<size_t>(kScal) * n_inst));
+  TRY(dalloc(ctx, &ctx->cg_done, n_inst));
+  TRY(dalloc(ctx, &ctx->cg_iters, n_inst));
+  TRY(dalloc(ctx, &ctx->cg_counter, n_inst));
+  TRY(dalloc(ctx, &ctx->part, 4 * static_cast<size_t>(nblk_all)));
+  TRY(dalloc(ctx, &ctx->sel_cnt, nblk_all));
+  TRY(dalloc(ctx, &ctx->sel_nnz, nblk_all));
+  HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i32), (8 + 2 * n_inst) * sizeof(int32_t)));
+  HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i64), (8 + n_inst) * sizeof(int64_t)));
+  HIPC(hipStreamSynchronize(ctx->stream));
+  ctx->pred.assign(static_cast<size_t>(SDC_MAX_SWEEPS) * M, 8);
+  ctx->pin.assign(SDC_MAX_SWEEPS, nullptr);
+  ctx->pin_n.assign(SDC_MAX_SWEEPS, 0);
+  ctx->ready = true;
+  return SDC_OK;
+}
+
+int sdc_add_stimulus(sdc_ctx* ctx, double t_on, const int32_t* nodes, int64_t n, double value) {
+  TRY(check_ready(ctx));
+  if (n < 0 || (n > 0 && !nodes)) return fail(ctx, SDC_ERR_ARG, "bad stimulus node list");
+  for (int64_t q = 0; q < n; ++q)
+    if (nodes[q] < 0 || nodes[q] >= ctx->N) return fail(ctx, SDC_ERR_ARG, "stimulus node out of range");
+  Stimulus s{t_on, nullptr, n, value};
+  HIPC(hipMalloc(reinterpret_cast<void**>(&s.nodes), std::max<int64_t>(n, 1) * sizeof(int32_t)));
+  ctx->stims.push_back(s);
+  HIPC(hipMemcpy(s.nodes, nodes, n * sizeof(int32_t), hipMemcpyHostToDevice));
+  return SDC_OK;
+}
+
+int sdc_get_sizes(const sdc_ctx* ctx, int64_t* n, int64_t* nnz, int64_t* nw) {
+  if (!ctx || !ctx->ready) return SDC_ERR_STATE;
+  if (n) *n = ctx->N;
+  if (nnz) *nnz = ctx->nnz;
+  if (nw) *nw = ctx->N;
+  return SDC_OK;
+}
+
+int sdc_get_system(sdc_ctx* ctx, int32_t* rowptr, int32_t* col, double* val, double* ml) {
+  TRY(check_ready(ctx));
+  if (rowptr) std::memcpy(rowptr, ctx->host.rowptr.data(), (ctx->N + 1) * 4);
+  if (col) std::memcpy(col, ctx->host.col.data(), ctx->nnz * 4);
+  if (val) std::memcpy(val, ctx->host.val.data(), ctx->nnz * 8);
+  if (ml) std::memcpy(ml, ctx->host.ml.data(), ctx->N * 8);
+  return SDC_OK;
+}
+
+int sdc_begin_step(sdc_ctx* ctx, const double* v, const double* w, double t) {
+  TRY(check_ready(ctx));
+  if (!v || !w) return fail(ctx, SDC_ERR_ARG, "null state");
+  const int64_t N = ctx->N;
+  HIPC(hipMemcpyAsync(ctx->v0, v, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->w0, w, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  const double dt = ctx->prm.dt;
+  for (const auto& s : ctx->stims)
+    if (t - 1e-9 * dt <= s.t_on && s.t_on < t + dt - 1e-9 * dt)
+      launch_set_values(ctx->stream, s.nodes, s.n, s.value, ctx->v0);
+  launch_spread(ctx->stream, ctx->prm.M, ctx->all.dev(), N, ctx->ionic_d, ctx->v0, ctx->w0, ctx->v,
+                ctx->w, ctx->I, ctx->R);
+  HIPC(hipGetLastError());
+  ctx->cur = -1;
+  ctx->k = 0;
+  ctx->in_step = true;
+  return SDC_OK;
+}
+
+int sdc_sweep(sdc_ctx* ctx, sdc_sweep_stats* stats) {
+  TRY(check_ready(ctx));
+  if (!ctx->in_step) return fail(ctx, SDC_ERR_STATE, "sdc_sweep outside a step");
+  if (ctx->k >= SDC_MAX_SWEEPS) return fail(ctx, SDC_ERR_STATE, "too many sweeps in one step");
+  int rc = do_sweep(ctx, stats, true);
+  if (rc != SDC_OK) ctx->in_step = false;
+  return rc;
+}
+
+int sdc_end_step(sdc_ctx* ctx, double* v, double* w) {
+  TRY(check_ready(ctx));
+  if (!ctx->in_step) return fail(ctx, SDC_ERR_STATE, "sdc_end_step outside a step");
+  if (!v || !w) return fail(ctx, SDC_ERR_ARG, "null state");
+  const int64_t N = ctx->N, last = static_cast<int64_t>(ctx->prm.M - 1) * N;
+  HIPC(hipMemcpyAsync(v, ctx->v + last, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(w, ctx->w + last, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->in_step = false;
+  return SDC_OK;
+}
+
+int sdc_step(sdc_ctx* ctx, double* v, double* w, double t, sdc_step_stats* stats) {
+  TRY(sdc_begin_step(ctx, v, w, t));
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  for (int k = 0; k < ctx->prm.K; ++k) {
+    int rc = do_sweep(ctx, stats ? &stats->sweep[k] : nullptr, k + 1 < ctx->prm.K);
+    if (rc != SDC_OK) {
+      ctx->in_step = false;
+      return rc;
+    }
+    if (stats) stats->n_sweeps = k + 1;
+  }
+  return sdc_end_step(ctx, v, w);
+}
+
+int sdc_get_node(sdc_ctx* ctx, int32_t m, double* v_m, double* w_m) {
+  TRY(check_ready(ctx));
+  if (m < 0 || m >= ctx->prm.M) return fail(ctx, SDC_ERR_ARG, "node out of range");
+  const int64_t N = ctx->N;
+  if (v_m) HIPC(hipMemcpyAsync(v_m, ctx->v + m * N, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  if (w_m) HIPC(hipMemcpyAsync(w_m, ctx->w + m * N, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return SDC_OK;
+}
+
+int sdc_get_active(sdc_ctx* ctx, int32_t* idx, int64_t* n) {
+  TRY(check_ready(ctx));
+  const MapBuf& mb = ctx->curmap();
+  if (n) *n = mb.rows;
+  if (idx) {
+    if (mb.idx)
+      HIPC(hipMemcpyAsync(idx, mb.idx, mb.rows * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    else
+      launch_iota(ctx->stream, idx, ctx->N);
+    HIPC(hipGetLastError());
+  }
+  return SDC_OK;
+}
+
+int sdc_set_active(sdc_ctx* ctx, int32_t sweep, const int32_t* idx, int64_t n) {
+  TRY(check_ready(ctx));
+  if (sweep < 0) {
+    HIPC(hipStreamSynchronize(ctx->stream));
+    for (auto& p : ctx->pin) {
+      if (p) (void)hipFree(p);
+      p = nullptr;
+    }
+    return SDC_OK;
+  }
+  if (sweep == 0 || sweep >= SDC_MAX_SWEEPS || n < 0 || n > ctx->N || (n > 0 && !idx))
+    return fail(ctx, SDC_ERR_ARG, "bad pinned set (sweep must be 1..%d)", SDC_MAX_SWEEPS - 1);
+  if (!ctx->pin[sweep]) HIPC(hipMalloc(reinterpret_cast<void**>(&ctx->pin[sweep]), std::max<int64_t>(ctx->N, 1) * 4));
+  if (n > 0) HIPC(hipMemcpyAsync(ctx->pin[sweep], idx, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->pin_n[sweep] = n;
+  return SDC_OK;
+}
+
+int sdc_solve(sdc_ctx* ctx, int32_t m, const int32_t* idx, int64_t n, const double* b, double* x,
+              int32_t* iters) {
+  TRY(check_ready(ctx));
+  if (m < 0 || m >= ctx->prm.M || n < 0 || n > ctx->N || !b || !x || (n > 0 && !idx))
+    return fail(ctx, SDC_ERR_ARG, "bad solve arguments");
+  ctx->in_step = false;   // the step's work vectors are reused
+  const int64_t N = ctx->N;
+  HIPC(hipMemsetAsync(x, 0, N * 8, ctx->stream));
+  HIPC(hipMemsetAsync(ctx->r, 0, N * 8, ctx->stream));
+  HIPC(hipMemsetAsync(ctx->p[0], 0, N * 8, ctx->stream));
+  HIPC(hipMemsetAsync(ctx->p[1], 0, N * 8, ctx->stream));
+  TRY(map_list(ctx, 0, idx, n));
+  const MapBuf& mb = ctx->dyn[0];
+  launch_cg_init_from_b(ctx->stream, mb.dev(), ctx->n_inst, b, ctx->dinv + m * N, ctx->r, x, ctx->cg());
+  HIPC(hipGetLastError());
+  std::vector<int> it;
+  TRY(run_cg(ctx, m, mb, x, -1, &it));
+  if (iters)
+    for (int i = 0; i < ctx->n_inst; ++i) iters[i] = it[i];
+  HIPC(hipStreamSynchronize(ctx->stream));
+  return SDC_OK;
+}
+
+int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t n_in, double theta,
+               int32_t* idx_out, int64_t* n_out) {
+  TRY(check_ready(ctx));
+  if (!amax || !idx_out || !n_out || n_in < 0 || n_in > ctx->N || (n_in > 0 && !idx_in))
+    return fail(ctx, SDC_ERR_ARG, "bad select arguments");
+  ctx->in_step = false;
+  TRY(map_list(ctx, 0, idx_in, n_in));
+  MapBuf& nm = ctx->dyn[1];
+  ZeroVecs none{nullptr, nullptr, nullptr, nullptr, 0, 0};
+  launch_select(ctx->stream, ctx->dyn[0].dev(), ctx->n_inst, ctx->rowptr, amax, theta, ctx->sel_cnt,
+                ctx->sel_nnz, idx_out, nm.next(), none);
+  HIPC(hipGetLastError());
+  TRY(fetch_map(ctx, &nm));
+  *n_out = nm.rows;
+  return SDC_OK;
+}
+
+int sdc_profile(sdc_ctx* ctx, int32_t enable) {
+  TRY(check_ready(ctx));
+  if (enable && ctx->ev.empty()) {
+    const int n = 3 * 4096;
+    ctx->ev.resize(n);
+    for (int i = 0; i < n; ++i) HIPC(hipEventCreate(&ctx->ev[i]));
+  }
+  ctx->prof = enable != 0;
+  if (enable) ctx->pst = sdc_profile_stats{};
+  return SDC_OK;
+}
+
+int sdc_profile_read(sdc_ctx* ctx, sdc_profile_stats* out) {
+  TRY(check_ready(ctx));
+  if (!out) return fail(ctx, SDC_ERR_ARG, "null output");
+  *out = ctx->pst;
+  return SDC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Internal declarations shared by the host parts of the library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sdc {
+
+constexpr int kMaxNodes = 6;
+
+struct Collocation {
+  int M;
+  double tau[kMaxNodes];
+  double Q[kMaxNodes][kMaxNodes];
+  double QI[kMaxNodes][kMaxNodes];
+  double QE[kMaxNodes][kMaxNodes];
+};
+
+// Radau-IIA collocation data; returns 0 on success.
+int collocation(int M, Collocation* c);
+
+// Host P1 assembly result (CSR with sorted column indices per row).
+struct HostSystem {
+  int64_t n = 0;
+  std::vector<int32_t> rowptr;  // n+1
+  std::vector<int32_t> col;     // nnz
+  std::vector<double> val;      // nnz, A
+  std::vector<double> ml;       // n, lumped mass
+  std::vector<int32_t> diag;    // n, position of the diagonal entry in its row
+};
+
+// Assemble ML and A from simplices; returns an empty string or an error message.
+std::string assemble_p1(int dim, int64_t n_nodes, const double* coords, int64_t n_elems,
+                        const int32_t* elems, const double* elem_tensor,
+                        const double* node_sigma, HostSystem* out);
+
+}  // namespace sdc

@@ -1,0 +1,718 @@
+// Device kernels of the adaptive SDC sweep (gfx950, wave64, FP64).
+//
+// Every active-row kernel is launched on a work map: block b owns up to
+// kBlock consecutive positions of the active list of one instance, one row
+// per thread.  Per-instance scalars (CG alpha/beta, norms) are reduced
+// deterministically: each block writes one partial per quantity, and the last
+// block of the instance to finish (a device-scope counter) sums the partials
+// of its instance in block order and writes the scalars.  No floating-point
+// atomics are used, so repeated runs are bitwise identical.
+#include "kernels.hpp"
+
+#include <type_traits>
+
+namespace sdc {
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Sum NV values over the block; the totals end up in thread 0's v[].
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* sh /* [4 * NV] */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wid * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = (sh[k] + sh[NV + k]) + (sh[2 * NV + k] + sh[3 * NV + k]);
+  }
+}
+
+// Block-sum v, publish this block's partial, and report whether this block is
+// the last of its instance; if so thread 0's v[] holds the instance totals
+// (summed over the instance's blocks in block order).
+template <int NV>
+__device__ bool instance_reduce(double (&v)[NV], const Map& map, int inst, double* part,
+                                uint32_t* counter) {
+  __shared__ double sh[4 * NV];
+  __shared__ int is_last;
+  block_sum<NV>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[blockIdx.x * 4 + k] = v[k];
+    __threadfence();
+    const uint32_t prev = atomicAdd(&counter[inst], 1u);
+    is_last = (prev == static_cast<uint32_t>(map.inst_nblk[inst]) - 1u);
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  const int b0 = map.inst_blk0[inst], nb = map.inst_nblk[inst];
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] += __builtin_nontemporal_load(&part[(b0 + b) * 4 + k]);
+  }
+  block_sum<NV>(acc, sh);
+  if (threadIdx.x == 0) {
+    counter[inst] = 0u;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = acc[k];
+  }
+  return true;
+}
+
+struct Row {
+  int inst;
+  int row;
+  bool valid;
+};
+
+__device__ inline Row map_row(const Map& map) {
+  const int4 bm = map.blk[blockIdx.x];
+  const int pos = bm.y + static_cast<int>(threadIdx.x);
+  Row r;
+  r.inst = bm.x;
+  r.valid = pos < bm.z;
+  r.row = r.valid ? (map.idx ? map.idx[pos] : pos) : 0;
+  return r;
+}
+
+// Aliev-Panfilov current and gating rate (paper Sec. 5.1).
+__device__ inline void ap_eval(double v, double w, const double* p, double& I, double& R) {
+  const double k = p[0], a = p[1], eps0 = p[2], mu1 = p[3], mu2 = p[4], s = p[5];
+  I = k * v * (v - a) * (v - 1.0) + v * w;
+  R = s * (eps0 + mu1 * w / (v + mu2)) * (-w - k * v * (v - a - 1.0));
+}
+
+template <class F>
+void dispatch_m(int M, F&& f) {
+  switch (M) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Spread: every collocation value starts at the step's initial state.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_spread(Map map, int64_t N, const double* __restrict__ ionic,
+                                                   const double* __restrict__ v0,
+                                                   const double* __restrict__ w0, double* v,
+                                                   double* w, double* I, double* R) {
+  const Row rw = map_row(map);
+  if (!rw.valid) return;
+  const int i = rw.row;
+  const double a = v0[i], b = w0[i];
+  double In, Rn;
+  ap_eval(a, b, ionic + 6 * rw.inst, In, Rn);
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    v[m * N + i] = a;
+    w[m * N + i] = b;
+    I[m * N + i] = In;
+    R[m * N + i] = Rn;
+  }
+}
+
+__global__ void k_set_values(const int32_t* __restrict__ nodes, int64_t n, double value, double* v) {
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (t < n) v[nodes[t]] = value;
+}
+
+// Sweep-start residuals on active rows (eq. final-sdc, right-hand sides):
+//   F_j   = -(A v_j)_i - ML_i I_j,i
+//   Phi_m = ML_i (v0_i - v_m,i) + dt sum_j Q[m][j] F_j
+//   Gam_m = w0_i - w_m,i + dt sum_j Q[m][j] R_j,i
+// and amax_i = 0 for this sweep's selection.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_sweep_start(
+    Map map, int64_t N, Csr A, const double* __restrict__ ml, const double* __restrict__ v0,
+    const double* __restrict__ w0, const double* __restrict__ v, const double* __restrict__ w,
+    const double* __restrict__ I, const double* __restrict__ R, double* __restrict__ Phi,
+    double* __restrict__ Gam, double* __restrict__ amax, CollArgs c) {
+  const Row rw = map_row(map);
+  if (!rw.valid) return;
+  const int i = rw.row;
+  double Av[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) Av[j] = 0.0;
+  const int e1 = A.rowptr[i + 1];
+  for (int e = A.rowptr[i]; e < e1; ++e) {
+    const int k = A.col[e];
+    const double a = A.val[e];
+#pragma unroll
+    for (int j = 0; j < M; ++j) Av[j] += a * v[j * N + k];
+  }
+  const double mli = ml[i];
+  double F[M], Rj[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    F[j] = -Av[j] - mli * I[j * N + i];
+    Rj[j] = R[j * N + i];
+  }
+  const double v0i = v0[i], w0i = w0[i];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double sf = 0.0, sr = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      sf += c.Q[m][j] * F[j];
+      sr += c.Q[m][j] * Rj[j];
+    }
+    Phi[m * N + i] = mli * (v0i - v[m * N + i]) + c.dt * sf;
+    Gam[m * N + i] = w0i - w[m * N + i] + c.dt * sr;
+  }
+  amax[i] = 0.0;
+}
+
+// Right-hand side of node m and CG start (x = 0, r = b):
+//   b_i = Phi_m,i - dt ML_i sum_{j<m} QE[m][j] dI_j,i - dt sum_k A_ik sum_{j<m} QI[m][j] dv_j,k
+// Partial sums r.z (z = dinv r) and b.b feed the instance scalars.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_rhs_init(
+    Map map, int m, int n_inst, int64_t N, Csr A, const double* __restrict__ ml,
+    const double* __restrict__ dinv, const double* __restrict__ Phi_m,
+    const double* __restrict__ dI, const double* __restrict__ dv, double* __restrict__ r,
+    double* __restrict__ x, CgState cg, CollArgs c) {
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t < n_inst; t += kBlock)
+      if (map.inst_nblk[t] == 0) {   // an instance without active rows has nothing to solve
+        cg.done[t] = 1;
+        cg.iters[t] = 0;
+      }
+  }
+  if (static_cast<int>(blockIdx.x) >= map.nblk) return;
+  const Row rw = map_row(map);
+  double s[2] = {0.0, 0.0};
+  if (rw.valid) {
+    const int i = rw.row;
+    double ay = 0.0;
+    if (m > 0) {
+      const int e1 = A.rowptr[i + 1];
+      for (int e = A.rowptr[i]; e < e1; ++e) {
+        const int k = A.col[e];
+        double y = 0.0;
+#pragma unroll
+        for (int j = 0; j < M - 1; ++j)
+          if (j < m) y += c.QI[m][j] * dv[j * N + k];
+        ay += A.val[e] * y;
+      }
+    }
+    double ex = 0.0;
+#pragma unroll
+    for (int j = 0; j < M - 1; ++j)
+      if (j < m) ex += c.QE[m][j] * dI[j * N + i];
+    const double b = Phi_m[i] - c.dt * ml[i] * ex - c.dt * ay;
+    r[i] = b;
+    x[i] = 0.0;
+    s[0] = b * (dinv[i] * b);
+    s[1] = b * b;
+  }
+  if (instance_reduce<2>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
+    double* sc = cg.scal + rw.inst * kScal;
+    sc[kRZ] = s[0];
+    sc[kBB] = s[1];
+    sc[kBeta] = 0.0;
+    cg.done[rw.inst] = (s[1] == 0.0) ? 1 : 0;
+    cg.iters[rw.inst] = 0;
+  }
+}
+
+// CG start from a given right-hand side b (component solve).
+__global__ __launch_bounds__(kBlock) void k_cg_init_b(Map map, int n_inst,
+                                                      const double* __restrict__ bvec,
+                                                      const double* __restrict__ dinv,
+                                                      double* __restrict__ r, double* __restrict__ x,
+                                                      CgState cg) {
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t < n_inst; t += kBlock)
+      if (map.inst_nblk[t] == 0) {   // an instance without active rows has nothing to solve
+        cg.done[t] = 1;
+        cg.iters[t] = 0;
+      }
+  }
+  if (static_cast<int>(blockIdx.x) >= map.nblk) return;
+  const Row rw = map_row(map);
+  double s[2] = {0.0, 0.0};
+  if (rw.valid) {
+    const int i = rw.row;
+    const double b = bvec[i];
+    r[i] = b;
+    x[i] = 0.0;
+    s[0] = b * (dinv[i] * b);
+    s[1] = b * b;
+  }
+  if (instance_reduce<2>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
+    double* sc = cg.scal + rw.inst * kScal;
+    sc[kRZ] = s[0];
+    sc[kBB] = s[1];
+    sc[kBeta] = 0.0;
+    cg.done[rw.inst] = (s[1] == 0.0) ? 1 : 0;
+    cg.iters[rw.inst] = 0;
+  }
+}
+
+// CG pass 1: p = z + beta p_old with z = dinv r, formed on the fly for every
+// column (inactive columns hold r = p = 0), q = H p on the active rows,
+// partial p.q; the last block sets alpha = r.z / p.q.
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(Map map, Csr H, const double* __restrict__ dinv,
+                                                    const double* __restrict__ r,
+                                                    const double* __restrict__ p_old,
+                                                    double* __restrict__ p_new,
+                                                    double* __restrict__ q, int first, CgState cg) {
+  const Row rw = map_row(map);
+  if (cg.done[rw.inst]) return;
+  const double beta = first ? 0.0 : cg.scal[rw.inst * kScal + kBeta];
+  double s[1] = {0.0};
+  if (rw.valid) {
+    const int i = rw.row;
+    double acc = 0.0;
+    const int e1 = H.rowptr[i + 1];
+    if (first) {
+      for (int e = H.rowptr[i]; e < e1; ++e) {
+        const int k = H.col[e];
+        acc += H.val[e] * (dinv[k] * r[k]);
+      }
+    } else {
+      for (int e = H.rowptr[i]; e < e1; ++e) {
+        const int k = H.col[e];
+        acc += H.val[e] * (dinv[k] * r[k] + beta * p_old[k]);
+      }
+    }
+    const double pi = first ? dinv[i] * r[i] : dinv[i] * r[i] + beta * p_old[i];
+    p_new[i] = pi;
+    q[i] = acc;
+    s[0] = pi * acc;
+  }
+  if (instance_reduce<1>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
+    double* sc = cg.scal + rw.inst * kScal;
+    const double alpha = sc[kRZ] / s[0];
+    if (!(s[0] > 0.0) || !isfinite(alpha)) cg.done[rw.inst] = 3;
+    sc[kAlpha] = alpha;
+  }
+}
+
+// CG pass 2: x += alpha p, r -= alpha q, partial r.z and r.r; the last block
+// counts the iteration, tests ||r|| <= rtol ||b|| and sets beta.
+__global__ __launch_bounds__(kBlock) void k_cg_update(Map map, const double* __restrict__ dinv,
+                                                      const double* __restrict__ p_new,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ x, double* __restrict__ r,
+                                                      double rtol2, int maxit, CgState cg) {
+  const Row rw = map_row(map);
+  if (cg.done[rw.inst]) return;
+  const double alpha = cg.scal[rw.inst * kScal + kAlpha];
+  double s[2] = {0.0, 0.0};
+  if (rw.valid) {
+    const int i = rw.row;
+    x[i] += alpha * p_new[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s[0] = ri * (dinv[i] * ri);
+    s[1] = ri * ri;
+  }
+  if (instance_reduce<2>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
+    double* sc = cg.scal + rw.inst * kScal;
+    const int it = cg.iters[rw.inst] + 1;
+    cg.iters[rw.inst] = it;
+    if (!isfinite(s[1])) cg.done[rw.inst] = 3;
+    else if (s[1] <= rtol2 * sc[kBB]) cg.done[rw.inst] = 1;
+    else if (it >= maxit) cg.done[rw.inst] = 2;
+    sc[kBeta] = s[0] / sc[kRZ];
+    sc[kRZ] = s[0];
+  }
+}
+
+// Post-solve update of node m (eq. final-sdc):
+//   v_m += dv_m;  w_m += Gam_m + dt sum_{j<m} QE[m][j] dR_j;
+//   (I_m, R_m) <- AP(v_m, w_m) with dI_m, dR_m their change;  amax = max(amax, |dv_m|).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_post(Map map, int m, int64_t N,
+                                                 const double* __restrict__ ionic,
+                                                 const double* __restrict__ x, double* v_m,
+                                                 double* w_m, double* I_m, double* R_m,
+                                                 double* dI_m, double* dR_m,
+                                                 const double* __restrict__ Gam_m,
+                                                 const double* __restrict__ dR, double* amax,
+                                                 CollArgs c) {
+  const Row rw = map_row(map);
+  if (!rw.valid) return;
+  const int i = rw.row;
+  const double d = x[i];
+  double g = 0.0;
+#pragma unroll
+  for (int j = 0; j < M - 1; ++j)
+    if (j < m) g += c.QE[m][j] * dR[j * N + i];
+  const double vm = v_m[i] + d;
+  const double wm = w_m[i] + (Gam_m[i] + c.dt * g);
+  v_m[i] = vm;
+  w_m[i] = wm;
+  double In, Rn;
+  ap_eval(vm, wm, ionic + 6 * rw.inst, In, Rn);
+  dI_m[i] = In - I_m[i];
+  dR_m[i] = Rn - R_m[i];
+  I_m[i] = In;
+  R_m[i] = Rn;
+  amax[i] = fmax(amax[i], fabs(d));
+}
+
+// ---- active-set compaction (eq. "subset"): keep i with amax_i >= theta.
+
+__device__ inline bool keep_row(double a, double theta) { return theta <= 0.0 || a >= theta; }
+
+// Pass 1: kept rows and their stored entries per block.
+__global__ __launch_bounds__(kBlock) void k_select_count(Map map, const int32_t* __restrict__ rowptr,
+                                                         const double* __restrict__ amax,
+                                                         double theta, int32_t* sel_cnt,
+                                                         int32_t* sel_nnz) {
+  __shared__ int sc[4], sn[4];
+  const Row rw = map_row(map);
+  const bool keep = rw.valid && keep_row(amax[rw.row], theta);
+  const unsigned long long mask = __ballot(keep);
+  int nz = keep ? rowptr[rw.row + 1] - rowptr[rw.row] : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) nz += __shfl_xor(nz, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sc[wid] = __popcll(mask);
+    sn[wid] = nz;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sel_cnt[blockIdx.x] = sc[0] + sc[1] + sc[2] + sc[3];
+    sel_nnz[blockIdx.x] = sn[0] + sn[1] + sn[2] + sn[3];
+  }
+}
+
+constexpr int kScanThreads = 1024;
+
+// Exclusive scan of one value per thread over a 1024-thread block.
+__device__ int64_t block_exscan(int64_t v, int64_t* sh, int64_t* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const int64_t add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const int64_t incl = sh[t];
+  *total = sh[kScanThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// In-place exclusive scan of a[0..n) (int32 or int64 values), one block.
+template <class T>
+__device__ int64_t scan_inplace(T* a, int n, int64_t* sh) {
+  const int t = threadIdx.x;
+  const int per = (n + kScanThreads - 1) / kScanThreads;
+  const int lo = min(n, t * per), hi = min(n, lo + per);
+  int64_t s = 0;
+  for (int q = lo; q < hi; ++q) s += a[q];
+  int64_t total;
+  int64_t run = block_exscan(s, sh, &total);
+  for (int q = lo; q < hi; ++q) {
+    const int64_t val = a[q];
+    a[q] = static_cast<T>(run);
+    run += val;
+  }
+  __syncthreads();
+  return total;
+}
+
+// Fill a work map from per-instance counts and list offsets (one block).
+__device__ void build_map(const int32_t* cnt, const int32_t* aoff, int n_inst, const NextMap& nm,
+                          int32_t total_rows) {
+  if (threadIdx.x == 0) {
+    int32_t b = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      const int32_t nb = (cnt[i] + kBlock - 1) / kBlock;
+      nm.inst_blk0[i] = b;
+      nm.inst_nblk[i] = nb;
+      b += nb;
+    }
+    nm.totals[0] = b;
+    nm.totals[1] = total_rows;
+  }
+  __syncthreads();
+  const int32_t nblk = nm.totals[0];
+  for (int b = threadIdx.x; b < nblk; b += kScanThreads) {
+    int lo = 0, hi = n_inst - 1;   // last instance with inst_blk0 <= b
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (nm.inst_blk0[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const int bi = b - nm.inst_blk0[lo];
+    const int beg = aoff[lo] + bi * kBlock;
+    const int end = min(beg + kBlock, aoff[lo] + cnt[lo]);
+    nm.blk[b] = make_int4(lo, beg, end, bi);
+  }
+}
+
+// Pass 2 (one block): block offsets, per-instance totals, next work map.
+__global__ __launch_bounds__(kScanThreads) void k_select_scan(Map map, int n_inst, int32_t* sel_cnt,
+                                                              int32_t* sel_nnz, NextMap nm) {
+  int32_t* aoff_scratch = nm.aoff;
+  __shared__ int64_t sh[kScanThreads];
+  const int nb = map.nblk;
+  // per-instance nnz before the scans overwrite the block counts
+  for (int i = threadIdx.x; i < n_inst; i += kScanThreads) {
+    int64_t z = 0;
+    int32_t c = 0;
+    const int b0 = map.inst_blk0[i], b1 = b0 + map.inst_nblk[i];
+    for (int b = b0; b < b1; ++b) {
+      z += sel_nnz[b];
+      c += sel_cnt[b];
+    }
+    nm.inst_nnz[i] = z;
+    nm.inst_cnt[i] = c;
+  }
+  __syncthreads();
+  const int64_t total = scan_inplace<int32_t>(sel_cnt, nb, sh);
+  // new list offset of instance i = exclusive prefix of kept counts
+  if (threadIdx.x == 0) {
+    int32_t a = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      aoff_scratch[i] = a;
+      a += nm.inst_cnt[i];
+    }
+    aoff_scratch[n_inst] = a;
+  }
+  __syncthreads();
+  build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, static_cast<int32_t>(total));
+  if (threadIdx.x == 0) nm.totals[2] = 0;
+}
+
+// Pass 3: stable write of the kept rows; zero the work vectors on dropped rows.
+__global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* __restrict__ amax,
+                                                         double theta,
+                                                         const int32_t* __restrict__ sel_off,
+                                                         int32_t* __restrict__ idx_out, ZeroVecs zv) {
+  __shared__ int wc[4];
+  const Row rw = map_row(map);
+  const bool keep = rw.valid && keep_row(amax[rw.row], theta);
+  const unsigned long long mask = __ballot(keep);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) wc[wid] = __popcll(mask);
+  __syncthreads();
+  int base = sel_off[blockIdx.x];
+  for (int q = 0; q < wid; ++q) base += wc[q];
+  const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+  if (keep) idx_out[base + rank] = rw.row;
+  if (rw.valid && !keep && zv.r) {
+    const int i = rw.row;
+    zv.r[i] = 0.0;
+    zv.p0[i] = 0.0;
+    zv.p1[i] = 0.0;
+    for (int m = 0; m < zv.M; ++m) zv.dv[m * zv.N + i] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_rows(Map map, ZeroVecs zv) {
+  const Row rw = map_row(map);
+  if (!rw.valid) return;
+  const int i = rw.row;
+  zv.r[i] = 0.0;
+  zv.p0[i] = 0.0;
+  zv.p1[i] = 0.0;
+  for (int m = 0; m < zv.M; ++m) zv.dv[m * zv.N + i] = 0.0;
+}
+
+// Work map of an ascending list: instance i's entries are those in
+// [node_off[i], node_off[i+1]); found by binary search.  One block.
+__global__ __launch_bounds__(kScanThreads) void k_map_from_list(const int32_t* __restrict__ idx,
+                                                                int32_t n, int64_t N,
+                                                                const int64_t* __restrict__ node_off,
+                                                                int n_inst,
+                                                                const int32_t* __restrict__ rowptr,
+                                                                NextMap nm) {
+  int32_t* aoff_scratch = nm.aoff;
+  // validate: entries in [0, N) and strictly ascending; a bad list gives an
+  // empty map and totals[2] = 1, so no later kernel indexes with it
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += kScanThreads) {
+    const int32_t v = idx[q];
+    if (v < 0 || v >= N || (q > 0 && idx[q - 1] >= v)) bad = 1;
+  }
+  __syncthreads();
+  if (bad) n = 0;
+  for (int i = threadIdx.x; i <= n_inst; i += kScanThreads) {
+    const int64_t key = node_off[i];
+    int lo = 0, hi = n;   // first position with idx >= key
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (idx[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    aoff_scratch[i] = lo;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_inst; i += kScanThreads) {
+    nm.inst_cnt[i] = aoff_scratch[i + 1] - aoff_scratch[i];
+    nm.inst_nnz[i] = 0;
+  }
+  __syncthreads();
+  // stored entries per instance (integer sums, order-independent)
+  for (int i = 0; i < n_inst; ++i) {
+    int64_t z = 0;
+    for (int q = aoff_scratch[i] + threadIdx.x; q < aoff_scratch[i + 1]; q += kScanThreads)
+      z += rowptr[idx[q] + 1] - rowptr[idx[q]];
+    if (z) atomicAdd(reinterpret_cast<unsigned long long*>(&nm.inst_nnz[i]),
+                     static_cast<unsigned long long>(z));
+  }
+  __syncthreads();
+  build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, n);
+  if (threadIdx.x == 0) nm.totals[2] = bad;
+}
+
+inline dim3 grid(int nblk) { return dim3(static_cast<unsigned>(nblk > 0 ? nblk : 1)); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+void launch_spread(hipStream_t s, int M, const Map& all, int64_t N, const double* ionic,
+                   const double* v0, const double* w0, double* v, double* w, double* I, double* R) {
+  if (all.nblk <= 0) return;
+  dispatch_m(M, [&](auto mm) {
+    k_spread<decltype(mm)::value><<<grid(all.nblk), kBlock, 0, s>>>(all, N, ionic, v0, w0, v, w, I, R);
+  });
+}
+
+void launch_set_values(hipStream_t s, const int32_t* nodes, int64_t n, double value, double* v) {
+  if (n <= 0) return;
+  k_set_values<<<dim3(static_cast<unsigned>((n + 255) / 256)), 256, 0, s>>>(nodes, n, value, v);
+}
+
+void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const Csr& A,
+                        const double* ml, const double* v0, const double* w0, const double* v,
+                        const double* w, const double* I, const double* R, double* Phi,
+                        double* Gam, double* amax, const CollArgs& c) {
+  if (map.nblk <= 0) return;
+  dispatch_m(M, [&](auto mm) {
+    k_sweep_start<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(
+        map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam, amax, c);
+  });
+}
+
+void launch_rhs_init(hipStream_t s, int M, int m, const Map& map, int n_inst, int64_t N,
+                     const Csr& A, const double* ml, const double* dinv, const double* Phi_m,
+                     const double* dI, const double* dv, double* r, double* x, const CgState& cg,
+                     const CollArgs& c) {
+  dispatch_m(M, [&](auto mm) {
+    k_rhs_init<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(
+        map, m, n_inst, N, A, ml, dinv, Phi_m, dI, dv, r, x, cg, c);
+  });
+}
+
+void launch_cg_init_from_b(hipStream_t s, const Map& map, int n_inst, const double* b,
+                           const double* dinv, double* r, double* x, const CgState& cg) {
+  k_cg_init_b<<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, b, dinv, r, x, cg);
+}
+
+void launch_cg_spmv(hipStream_t s, const Map& map, const Csr& H, const double* dinv,
+                    const double* r, const double* p_old, double* p_new, double* q, bool first,
+                    const CgState& cg) {
+  if (map.nblk <= 0) return;
+  k_cg_spmv<<<grid(map.nblk), kBlock, 0, s>>>(map, H, dinv, r, p_old, p_new, q, first ? 1 : 0, cg);
+}
+
+void launch_cg_update(hipStream_t s, const Map& map, const double* dinv, const double* p_new,
+                      const double* q, double* x, double* r, double rtol2, int maxit,
+                      const CgState& cg) {
+  if (map.nblk <= 0) return;
+  k_cg_update<<<grid(map.nblk), kBlock, 0, s>>>(map, dinv, p_new, q, x, r, rtol2, maxit, cg);
+}
+
+void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
+                 const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
+                 double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
+                 const CollArgs& c) {
+  if (map.nblk <= 0) return;
+  dispatch_m(M, [&](auto mm) {
+    k_post<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(
+        map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m, dR_m, Gam_m, dR, amax, c);
+  });
+}
+
+void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* rowptr,
+                   const double* amax, double theta, int32_t* sel_cnt, int32_t* sel_nnz,
+                   int32_t* idx_out, const NextMap& nm, const ZeroVecs& zv) {
+  if (map.nblk > 0)
+    k_select_count<<<grid(map.nblk), kBlock, 0, s>>>(map, rowptr, amax, theta, sel_cnt, sel_nnz);
+  k_select_scan<<<1, kScanThreads, 0, s>>>(map, n_inst, sel_cnt, sel_nnz, nm);
+  if (map.nblk > 0)
+    k_select_write<<<grid(map.nblk), kBlock, 0, s>>>(map, amax, theta, sel_cnt, idx_out, zv);
+}
+
+void launch_zero_rows(hipStream_t s, const Map& map, const ZeroVecs& zv) {
+  if (map.nblk <= 0) return;
+  k_zero_rows<<<grid(map.nblk), kBlock, 0, s>>>(map, zv);
+}
+
+void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t N,
+                          const int64_t* node_off, int n_inst, const int32_t* rowptr,
+                          const NextMap& nm) {
+  k_map_from_list<<<1, kScanThreads, 0, s>>>(idx, static_cast<int32_t>(n), N, node_off, n_inst,
+                                             rowptr, nm);
+}
+
+}  // namespace sdc
+
+namespace sdc {
+namespace {
+// H_m = ML + c_m A on the pattern of A, and dinv_m = 1 / diag(H_m).
+__global__ __launch_bounds__(kBlock) void k_build_h(int64_t N, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ diagpos,
+                                                    const double* __restrict__ A,
+                                                    const double* __restrict__ ml, double c,
+                                                    double* __restrict__ H, double* __restrict__ dinv) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  if (i >= N) return;
+  const int dg = diagpos[i];
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) H[e] = (e == dg) ? ml[i] + c * A[e] : c * A[e];
+  dinv[i] = 1.0 / H[dg];
+}
+
+__global__ void k_iota(int32_t* out, int64_t n) {
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (t < n) out[t] = static_cast<int32_t>(t);
+}
+}  // namespace
+
+void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32_t* diagpos,
+                    const double* A, const double* ml, double c, double* H, double* dinv) {
+  k_build_h<<<dim3(static_cast<unsigned>((N + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
+      N, rowptr, diagpos, A, ml, c, H, dinv);
+}
+
+void launch_iota(hipStream_t s, int32_t* out, int64_t n) {
+  if (n <= 0) return;
+  k_iota<<<dim3(static_cast<unsigned>((n + 255) / 256)), 256, 0, s>>>(out, n);
+}
+
+}  // namespace sdc

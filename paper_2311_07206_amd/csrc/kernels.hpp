@@ -1,0 +1,114 @@
+// Launch interface of the device kernels (gfx950, wave64, FP64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sdc {
+
+constexpr int kBlock = 256;      // threads per block = active rows per block
+constexpr int kMaxNodesDev = 6;  // collocation nodes supported by the kernels
+
+// Collocation matrices and step length, passed by value (kernel arguments
+// live in the scalar kernarg segment, read once per wave).
+struct CollArgs {
+  double Q[kMaxNodesDev][kMaxNodesDev];
+  double QI[kMaxNodesDev][kMaxNodesDev];
+  double QE[kMaxNodesDev][kMaxNodesDev];
+  double dt;
+};
+
+// Work map: block b processes positions [beg, end) of the active list of
+// instance `inst`; `bi` is its index among that instance's blocks.  Blocks of
+// one instance are consecutive starting at inst_blk0[inst].  When idx is null
+// the positions are row numbers (all rows active).
+struct Map {
+  const int4* blk;         // {inst, beg, end, bi}
+  const int32_t* inst_blk0;
+  const int32_t* inst_nblk;
+  const int32_t* idx;
+  int32_t nblk;            // grid size
+};
+
+struct Csr {
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+};
+
+// Per-instance CG scalars, layout [n_inst][kScal].
+enum { kRZ = 0, kBB, kAlpha, kBeta, kScal = 8 };
+
+struct CgState {
+  double* scal;        // [n_inst][kScal]
+  int32_t* done;       // 0 running, 1 converged, 2 maxit, 3 non-finite
+  int32_t* iters;
+  uint32_t* counter;   // last-block counters, zero between kernels
+  double* part;        // [nblk_max][4] block partial sums
+};
+
+void launch_spread(hipStream_t s, int M, const Map& all, int64_t N, const double* ionic,
+                   const double* v0, const double* w0, double* v, double* w, double* I, double* R);
+void launch_set_values(hipStream_t s, const int32_t* nodes, int64_t n, double value, double* v);
+void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const Csr& A,
+                        const double* ml, const double* v0, const double* w0, const double* v,
+                        const double* w, const double* I, const double* R, double* Phi,
+                        double* Gam, double* amax, const CollArgs& c);
+void launch_rhs_init(hipStream_t s, int M, int m, const Map& map, int n_inst, int64_t N,
+                     const Csr& A, const double* ml, const double* dinv, const double* Phi_m,
+                     const double* dI, const double* dv, double* r, double* x, const CgState& cg,
+                     const CollArgs& c);
+void launch_cg_init_from_b(hipStream_t s, const Map& map, int n_inst, const double* b,
+                           const double* dinv, double* r, double* x, const CgState& cg);
+void launch_cg_spmv(hipStream_t s, const Map& map, const Csr& H, const double* dinv,
+                    const double* r, const double* p_old, double* p_new, double* q, bool first,
+                    const CgState& cg);
+void launch_cg_update(hipStream_t s, const Map& map, const double* dinv, const double* p_new,
+                      const double* q, double* x, double* r, double rtol2, int maxit,
+                      const CgState& cg);
+void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
+                 const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
+                 double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
+                 const CollArgs& c);
+
+// Active-set compaction I_{k+1} = {i in I_k : amax_i >= theta} (three passes).
+// sel_cnt [nblk] and sel_nnz [nblk] are per-block scratch; next-map outputs
+// and per-instance totals are written by the scan pass.
+struct NextMap {
+  int4* blk;
+  int32_t* inst_blk0;
+  int32_t* inst_nblk;
+  int32_t* inst_cnt;       // kept rows per instance
+  int64_t* inst_nnz;       // stored A entries in kept rows per instance
+  int32_t* aoff;           // [n_inst+1] list offset of each instance's first row
+  int32_t* totals;         // [0] total blocks, [1] total rows in the list, [2] invalid list
+};
+// Vectors that must be zero on inactive rows: CG residual, both search
+// direction buffers and the M node corrections dv[M][N].
+struct ZeroVecs {
+  double* r;
+  double* p0;
+  double* p1;
+  double* dv;
+  int M;
+  int64_t N;
+};
+void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* rowptr,
+                   const double* amax, double theta, int32_t* sel_cnt, int32_t* sel_nnz,
+                   int32_t* idx_out, const NextMap& nm, const ZeroVecs& zv);
+// Zero the ZeroVecs entries on every row of the map (used before a pinned set).
+void launch_zero_rows(hipStream_t s, const Map& map, const ZeroVecs& zv);
+// Work map of an arbitrary ascending list (per-instance split by node_off).
+// A list with entries outside [0, N) or not strictly ascending yields an
+// empty map and totals[2] = 1.
+void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t N,
+                          const int64_t* node_off, int n_inst, const int32_t* rowptr,
+                          const NextMap& nm);
+
+// H_m = ML + c A (pattern of A) and its inverse diagonal.
+void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32_t* diagpos,
+                    const double* A, const double* ml, double c, double* H, double* dinv);
+void launch_iota(hipStream_t s, int32_t* out, int64_t n);
+
+}  // namespace sdc

@@ -1,0 +1,185 @@
+"""Python binding of the adaptive SDC library: argument marshalling only.
+
+Device memory and streams come from PyTorch (HIP build); every step of the
+method runs in the HIP library.  Tensors passed in must be contiguous and on
+the solver's device: float64 for values, int32 for index lists.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MAX_NODES, MAX_SWEEPS, Params, StepStats, SweepStats  # noqa: F401
+
+
+class SDCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def collocation(M):
+    """(tau, Q, QI, QE) as computed by the library (host call)."""
+    lib = _lib.load()
+    out = [np.zeros(M), np.zeros((M, M)), np.zeros((M, M)), np.zeros((M, M))]
+    rc = lib.sdc_collocation(M, *[o.ctypes.data_as(ctypes.c_void_p) for o in out])
+    if rc != 0:
+        raise SDCError(rc, "sdc_collocation")
+    return tuple(out)
+
+
+class Solver:
+    """One library context: an assembled mesh (possibly several instances)."""
+
+    def __init__(self, coords, elems, elem_tensor, node_sigma, ionic, node_off, elem_off,
+                 M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, device=None, stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        ctx = ctypes.c_void_p()
+        rc = self.lib.sdc_create(ctypes.byref(ctx), self.device.index, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise SDCError(rc, "sdc_create failed")
+        self.ctx = ctx
+        coords = np.asarray(coords, dtype=np.float64)
+        dim = coords.shape[1]
+        self.M, self.K = int(M), int(K)
+        prm = Params(M=self.M, K=self.K, dt=float(dt), theta=float(theta), cg_rtol=float(cg_rtol),
+                     cg_maxit=int(cg_maxit), reserved=0)
+        node_off_a, p_no = _host(node_off, np.int64)
+        coords_a, p_c = _host(coords, np.float64)
+        elem_off_a, p_eo = _host(elem_off, np.int64)
+        elems_a, p_e = _host(elems, np.int32)
+        tens_a, p_t = _host(elem_tensor, np.float64)
+        sig_a, p_s = _host(node_sigma, np.float64)
+        ion_a, p_i = _host(np.atleast_2d(ionic), np.float64)
+        self._check(self.lib.sdc_setup_mesh(self.ctx, ctypes.byref(prm), dim, len(node_off_a) - 1,
+                                            p_no, p_c, p_eo, p_e, p_t, p_s, p_i))
+        n, nnz, nw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.sdc_get_sizes(self.ctx, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(nw)))
+        self.N, self.nnz, self.Nw = n.value, nnz.value, nw.value
+        self.n_inst = len(node_off_a) - 1
+        self.dt = float(dt)
+
+    @classmethod
+    def from_problem(cls, P, **kw):
+        """Context for a workloads.Problem, with its stimuli registered."""
+        args = dict(M=P.M, K=P.K, dt=P.dt, theta=P.theta, cg_rtol=P.cg_rtol, cg_maxit=P.cg_maxit)
+        args.update(kw)
+        s = cls(P.coords, P.elems, P.elem_tensor, P.node_sigma, P.ionic, P.node_off, P.elem_off, **args)
+        for t_on, nodes, value in P.stimuli:
+            s.add_stimulus(t_on, nodes, value)
+        return s
+
+    # -- plumbing ---------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            msg = self.lib.sdc_last_error(self.ctx)
+            raise SDCError(rc, msg.decode() if msg else "")
+
+    def _vec(self, t, dtype=torch.float64, n=None):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous {dtype} tensor on {self.device}")
+        if n is not None and t.numel() < n:
+            raise ValueError(f"tensor too small: {t.numel()} < {n}")
+        return _ptr(t)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.sdc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- API --------------------------------------------------------------
+    def add_stimulus(self, t_on, nodes, value):
+        a, p = _host(nodes, np.int32)
+        self._check(self.lib.sdc_add_stimulus(self.ctx, float(t_on), p, a.size, float(value)))
+
+    def system(self):
+        """(rowptr, col, val, ml) of the assembled A and lumped mass (numpy)."""
+        rp = np.zeros(self.N + 1, np.int32)
+        col = np.zeros(self.nnz, np.int32)
+        val = np.zeros(self.nnz)
+        ml = np.zeros(self.N)
+        self._check(self.lib.sdc_get_system(self.ctx, *[x.ctypes.data_as(ctypes.c_void_p) for x in (rp, col, val, ml)]))
+        return rp, col, val, ml
+
+    def step(self, v, w, t, stats=False):
+        """Advance (v, w) in place by one step from time t."""
+        st = StepStats() if stats else None
+        self._check(self.lib.sdc_step(self.ctx, self._vec(v, n=self.N), self._vec(w, n=self.Nw), float(t),
+                                      ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            return [st.sweep[k].as_dict(self.M) for k in range(st.n_sweeps)]
+        return None
+
+    def begin_step(self, v, w, t):
+        self._check(self.lib.sdc_begin_step(self.ctx, self._vec(v, n=self.N), self._vec(w, n=self.Nw), float(t)))
+
+    def sweep(self):
+        st = SweepStats()
+        self._check(self.lib.sdc_sweep(self.ctx, ctypes.byref(st)))
+        return st.as_dict(self.M)
+
+    def end_step(self, v, w):
+        self._check(self.lib.sdc_end_step(self.ctx, self._vec(v, n=self.N), self._vec(w, n=self.Nw)))
+
+    def node(self, m):
+        v = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        w = torch.empty(self.Nw, dtype=torch.float64, device=self.device)
+        self._check(self.lib.sdc_get_node(self.ctx, int(m), _ptr(v), _ptr(w)))
+        return v, w
+
+    def active(self):
+        n = ctypes.c_int64()
+        self._check(self.lib.sdc_get_active(self.ctx, None, ctypes.byref(n)))
+        idx = torch.empty(max(self.N, 1), dtype=torch.int32, device=self.device)
+        self._check(self.lib.sdc_get_active(self.ctx, _ptr(idx), ctypes.byref(n)))
+        return idx[: n.value].clone()
+
+    def set_active(self, sweep, idx):
+        """Pin the set of sweep `sweep` (>= 1); idx=None clears every pin."""
+        if idx is None:
+            self._check(self.lib.sdc_set_active(self.ctx, -1, None, 0))
+            return
+        self._check(self.lib.sdc_set_active(self.ctx, int(sweep), self._vec(idx, torch.int32), idx.numel()))
+
+    def solve(self, m, idx, b):
+        x = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        iters = (ctypes.c_int32 * self.n_inst)()
+        self._check(self.lib.sdc_solve(self.ctx, int(m), self._vec(idx, torch.int32), idx.numel(),
+                                       self._vec(b, n=self.N), _ptr(x), iters))
+        return x, list(iters)
+
+    def profile(self, enable):
+        """Start (and clear) or stop event timing of the CG kernels."""
+        self._check(self.lib.sdc_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        st = _lib.ProfileStats()
+        self._check(self.lib.sdc_profile_read(self.ctx, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def select(self, amax, idx, theta):
+        out = torch.empty(max(idx.numel(), 1), dtype=torch.int32, device=self.device)
+        n = ctypes.c_int64()
+        self._check(self.lib.sdc_select(self.ctx, self._vec(amax, n=self.N), self._vec(idx, torch.int32),
+                                        idx.numel(), float(theta), _ptr(out), ctypes.byref(n)))
+        return out[: n.value].clone()
