@@ -46,22 +46,22 @@ def sweep_bytes(st, M, ident):
 
     Per active row (n_a rows, z_a stored entries of A in them; idx read only
     when not every row is active):
-      sweep start   12 z_a + 4 + idx + 8 (6M + 4)
-      rhs + CG init 12 z_a [m > 0] + 4 + idx + 8 (2m + 5)
-      CG SpMV pass  12 z + 4 + idx + 40  per iteration (z = entries of the
-                    rows still iterating)
-      CG update     idx + 56             per iteration
-      post-solve    idx + 8 (m + 14)
-      selection     2 idx + 24
+      sweep start    12 z_a + 4 + idx + 8 (6M + 4)
+      node RHS       12 z_a [m > 0] + 4 + idx + 8 (2m + 4)
+      CG start       12 z_a + 4 + idx + 24
+      CG iteration   12 z + 4 + idx + 88   per iteration (z = entries of the
+                     rows still iterating)
+      post-solve     idx + 8 (m + 14)
+      selection      2 idx + 24
     """
     na, za = st["n_active"], st["nnz_active"]
     idxb = 0 if ident else 4
     b = 12 * za + na * (4 + idxb + 8 * (6 * M + 4))
     for m in range(M):
         rows, nnz = st["cg_row_iters"][m], st["cg_nnz_iters"][m]
-        b += 12 * nnz + (44 + idxb) * rows
-        b += (56 + idxb) * rows
-        b += (12 * za if m > 0 else 0) + na * (4 + idxb + 8 * (2 * m + 5))
+        b += (12 * za if m > 0 else 0) + na * (4 + idxb + 8 * (2 * m + 4))
+        b += 12 * za + na * (28 + idxb)
+        b += 12 * nnz + (92 + idxb) * rows
         b += na * (idxb + 8 * (m + 14))
     b += na * (2 * idxb + 24)
     return b
@@ -148,19 +148,14 @@ def main():
         "mean_active_per_sweep": per_sweep_active,
         "mean_cg_iters_per_node": cg_iters,
     }
-    if prof and prof["spmv_launches"]:
-        ach = prof["spmv_bytes"] / (prof["spmv_ms"] * 1e-3) / 1e9
+    if prof and prof["cg_launches"]:
+        ach = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
         out["roofline"] = {
-            "kernel": "k_cg_spmv", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "kernel": "k_cg_iter", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": ROCPROF_TRAFFIC,
-            "avg_launch_us": 1e3 * prof["spmv_ms"] / prof["spmv_launches"],
-            "bytes_per_launch": prof["spmv_bytes"] / prof["spmv_launches"],
-            "launches": prof["spmv_launches"],
-        }
-        out["update_kernel"] = {
-            "kernel": "k_cg_update",
-            "achieved_GBps": prof["update_bytes"] / (prof["update_ms"] * 1e-3) / 1e9,
-            "avg_launch_us": 1e3 * prof["update_ms"] / prof["update_launches"],
+            "avg_launch_us": 1e3 * prof["cg_ms"] / prof["cg_launches"],
+            "bytes_per_launch": prof["cg_bytes"] / prof["cg_launches"],
+            "launches": prof["cg_launches"],
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)

@@ -168,20 +168,17 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
 
 /* ---- measurement ------------------------------------------------------ */
 
-/* Kernel timing of the two CG kernels (SpMV pass and update pass), taken
- * with HIP events on the context's stream around every launch that does
- * work for at least one instance.  Bytes are the algorithmic minimum per
- * launch over the instances still iterating:
- *   SpMV pass:   12 nnz_a + (4 rowptr + 4 idx + 3*8 gathers + 2*8 writes) n_a
- *   update pass: (4 idx + 5*8 reads + 2*8 writes) n_a
- * (the 4-byte idx read is absent when every row is active). */
+/* Kernel timing of the CG iteration kernel (one launch per iteration: SpMV,
+ * vector updates and the three dot products), taken with HIP events on the
+ * context's stream around every launch that does work for at least one
+ * instance.  Bytes are the algorithmic minimum per launch over the instances
+ * still iterating: 12 per stored entry of A in their active rows, plus per
+ * active row 4 (rowptr) + 4 (idx; absent when every row is active)
+ * + 6*8 reads (x, p, r, w, s, dinv) + 5*8 writes (x, p, r, w, s). */
 typedef struct {
-  int64_t spmv_launches;
-  double spmv_ms;
-  double spmv_bytes;
-  int64_t update_launches;
-  double update_ms;
-  double update_bytes;
+  int64_t cg_launches;
+  double cg_ms;
+  double cg_bytes;
 } sdc_profile_stats;
 
 /* enable != 0 starts timing (and clears the totals); 0 stops it. */

@@ -44,8 +44,7 @@ class StepStats(ctypes.Structure):
 
 
 class ProfileStats(ctypes.Structure):
-    _fields_ = [("spmv_launches", c_int64), ("spmv_ms", c_double), ("spmv_bytes", c_double),
-                ("update_launches", c_int64), ("update_ms", c_double), ("update_bytes", c_double)]
+    _fields_ = [("cg_launches", c_int64), ("cg_ms", c_double), ("cg_bytes", c_double)]
 
 
 PTR = c_void_p

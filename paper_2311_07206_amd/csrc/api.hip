@@ -78,7 +78,11 @@ struct sdc_ctx {
 
   double *v0 = nullptr, *w0 = nullptr, *v = nullptr, *w = nullptr, *I = nullptr, *R = nullptr;
   double *Phi = nullptr, *Gam = nullptr, *dv = nullptr, *dI = nullptr, *dR = nullptr;
-  double *amax = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+  double* amax = nullptr;
+  // CG vectors: p and the iterate (dv[m]) are read on own rows only; r, w, s
+  // are double-buffered because the SpMV reads them at neighbouring columns
+  double* p = nullptr;
+  double *r[2] = {nullptr, nullptr}, *wv[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
 
   double* cg_scal = nullptr;
   int32_t *cg_done = nullptr, *cg_iters = nullptr;
@@ -103,7 +107,7 @@ struct sdc_ctx {
 
   // kernel timing (bench only)
   bool prof = false;
-  std::vector<hipEvent_t> ev;   // 3 per iteration: before SpMV, between, after update
+  std::vector<hipEvent_t> ev;   // 2 per CG iteration launch
   sdc_profile_stats pst{};
   std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
 
@@ -111,7 +115,7 @@ struct sdc_ctx {
   CgState cg() const { return CgState{cg_scal, cg_done, cg_iters, cg_counter, part}; }
   Csr A() const { return Csr{rowptr, colidx, Aval}; }
   Csr H(int m) const { return Csr{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz}; }
-  ZeroVecs zv() const { return ZeroVecs{r, p[0], p[1], dv, prm.M, N}; }
+  ZeroVecs zv() const { return ZeroVecs{{r[0], r[1], wv[0], wv[1], s[0], s[1]}, dv, prm.M, N}; }
 };
 
 namespace {
@@ -189,23 +193,17 @@ int account_timing(sdc_ctx* ctx, const MapBuf& mb, int it0, int budget, const in
   const bool ident = mb.idx == nullptr;
   for (int b = 0; b < budget; ++b) {
     const int it = it0 + b;
-    double sp_bytes = 0.0, up_bytes = 0.0;
+    double bytes = 0.0;
     for (int i = 0; i < ctx->n_inst; ++i) {
       if (it >= iters[i] || mb.cnt[i] == 0) continue;
-      const double na = mb.cnt[i], za = static_cast<double>(mb.nnz[i]);
-      sp_bytes += 12.0 * za + (ident ? 44.0 : 48.0) * na;
-      up_bytes += (ident ? 56.0 : 60.0) * na;
+      bytes += 12.0 * static_cast<double>(mb.nnz[i]) + (ident ? 92.0 : 96.0) * mb.cnt[i];
     }
-    if (sp_bytes == 0.0) continue;
-    float t1 = 0.f, t2 = 0.f;
-    HIPC(hipEventElapsedTime(&t1, ctx->ev[3 * b], ctx->ev[3 * b + 1]));
-    HIPC(hipEventElapsedTime(&t2, ctx->ev[3 * b + 1], ctx->ev[3 * b + 2]));
-    ctx->pst.spmv_launches++;
-    ctx->pst.spmv_ms += t1;
-    ctx->pst.spmv_bytes += sp_bytes;
-    ctx->pst.update_launches++;
-    ctx->pst.update_ms += t2;
-    ctx->pst.update_bytes += up_bytes;
+    if (bytes == 0.0) continue;
+    float t = 0.f;
+    HIPC(hipEventElapsedTime(&t, ctx->ev[2 * b], ctx->ev[2 * b + 1]));
+    ctx->pst.cg_launches++;
+    ctx->pst.cg_ms += t;
+    ctx->pst.cg_bytes += bytes;
   }
   return SDC_OK;
 }
@@ -223,18 +221,18 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   int budget = pred_slot >= 0 ? std::max(1, ctx->pred[pred_slot]) : 8;
   int it = 0;
   iters->assign(ni, 0);
+  launch_cg_start(ctx->stream, map, ni, H, dinv, ctx->r[0], ctx->wv[0], ctx->cg());
+  HIPC(hipGetLastError());
   if (mb.nblk > 0) {
     for (;;) {
       const int it0 = it;
-      const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 3 * budget;
+      const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * budget;
       for (int b = 0; b < budget; ++b, ++it) {
-        double* pold = ctx->p[it & 1];
-        double* pnew = ctx->p[(it + 1) & 1];
-        if (timed) HIPC(hipEventRecord(ctx->ev[3 * b], ctx->stream));
-        launch_cg_spmv(ctx->stream, map, H, dinv, ctx->r, pold, pnew, ctx->q, it == 0, ctx->cg());
-        if (timed) HIPC(hipEventRecord(ctx->ev[3 * b + 1], ctx->stream));
-        launch_cg_update(ctx->stream, map, dinv, pnew, ctx->q, x, ctx->r, rtol2, ctx->prm.cg_maxit, ctx->cg());
-        if (timed) HIPC(hipEventRecord(ctx->ev[3 * b + 2], ctx->stream));
+        const int a = it & 1, o = a ^ 1;
+        if (timed) HIPC(hipEventRecord(ctx->ev[2 * b], ctx->stream));
+        launch_cg_iter(ctx->stream, map, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
+                       ctx->wv[o], ctx->s[o], it == 0, rtol2, ctx->prm.cg_maxit, ctx->cg());
+        if (timed) HIPC(hipEventRecord(ctx->ev[2 * b + 1], ctx->stream));
       }
       HIPC(hipGetLastError());
       HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
@@ -258,7 +256,14 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
       budget = std::max(2, budget / 2);
     }
     for (int i = 0; i < ni; ++i) (*iters)[i] = ctx->h_i32[ni + i];
+  } else {
+    HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
   }
+  for (int i = 0; i < ni; ++i)
+    if (ctx->h_i32[i] == 3)
+      return fail(ctx, SDC_ERR_NONFINITE, "CG: instance %d, node %d, sweep %d: non-finite right-hand side",
+                  i, m, ctx->k);
   if (pred_slot >= 0) {
     int mx = 0;
     for (int v : *iters) mx = std::max(mx, v);
@@ -294,8 +299,8 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next) {
   std::vector<int> iters;
   for (int m = 0; m < M; ++m) {
     double* x = ctx->dv + m * N;
-    launch_rhs_init(ctx->stream, M, m, map, ctx->n_inst, N, ctx->A(), ctx->ml, ctx->dinv + m * N,
-                    ctx->Phi + m * N, ctx->dI, ctx->dv, ctx->r, x, ctx->cg(), ctx->cargs);
+    launch_rhs(ctx->stream, M, m, map, N, ctx->A(), ctx->ml, ctx->Phi + m * N, ctx->dI, ctx->dv,
+               ctx->r[0], x, ctx->cargs);
     HIPC(hipGetLastError());
     const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
     TRY(run_cg(ctx, m, mb, x, slot, &iters));
@@ -477,10 +482,12 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   for (double** b : {&ctx->v, &ctx->w, &ctx->I, &ctx->R, &ctx->Phi, &ctx->Gam, &ctx->dv, &ctx->dI, &ctx->dR})
     TRY(dalloc(ctx, b, MN));
   TRY(dalloc(ctx, &ctx->amax, N));
-  TRY(dalloc(ctx, &ctx->r, N));
-  TRY(dalloc(ctx, &ctx->p[0], N));
-  TRY(dalloc(ctx, &ctx->p[1], N));
-  TRY(dalloc(ctx, &ctx->q, N));
+  TRY(dalloc(ctx, &ctx->p, N));
+  for (int q = 0; q < 2; ++q) {
+    TRY(dalloc(ctx, &ctx->r[q], N));
+    TRY(dalloc(ctx, &ctx->wv[q], N));
+    TRY(dalloc(ctx, &ctx->s[q], N));
+  }
 
   // all-rows work map (host-built)
   std::vector<int4> blk;
@@ -664,12 +671,14 @@ int sdc_solve(sdc_ctx* ctx, int32_t m, const int32_t* idx, int64_t n, const doub
   ctx->in_step = false;   // the step's work vectors are reused
   const int64_t N = ctx->N;
   HIPC(hipMemsetAsync(x, 0, N * 8, ctx->stream));
-  HIPC(hipMemsetAsync(ctx->r, 0, N * 8, ctx->stream));
-  HIPC(hipMemsetAsync(ctx->p[0], 0, N * 8, ctx->stream));
-  HIPC(hipMemsetAsync(ctx->p[1], 0, N * 8, ctx->stream));
+  for (int q = 0; q < 2; ++q) {
+    HIPC(hipMemsetAsync(ctx->r[q], 0, N * 8, ctx->stream));
+    HIPC(hipMemsetAsync(ctx->wv[q], 0, N * 8, ctx->stream));
+    HIPC(hipMemsetAsync(ctx->s[q], 0, N * 8, ctx->stream));
+  }
   TRY(map_list(ctx, 0, idx, n));
   const MapBuf& mb = ctx->dyn[0];
-  launch_cg_init_from_b(ctx->stream, mb.dev(), ctx->n_inst, b, ctx->dinv + m * N, ctx->r, x, ctx->cg());
+  launch_copy_b(ctx->stream, mb.dev(), b, ctx->r[0], x);
   HIPC(hipGetLastError());
   std::vector<int> it;
   TRY(run_cg(ctx, m, mb, x, -1, &it));
@@ -687,7 +696,7 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
   ctx->in_step = false;
   TRY(map_list(ctx, 0, idx_in, n_in));
   MapBuf& nm = ctx->dyn[1];
-  ZeroVecs none{nullptr, nullptr, nullptr, nullptr, 0, 0};
+  ZeroVecs none{{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}, nullptr, 0, 0};
   launch_select(ctx->stream, ctx->dyn[0].dev(), ctx->n_inst, ctx->rowptr, amax, theta, ctx->sel_cnt,
                 ctx->sel_nnz, idx_out, nm.next(), none);
   HIPC(hipGetLastError());
@@ -699,7 +708,7 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
 int sdc_profile(sdc_ctx* ctx, int32_t enable) {
   TRY(check_ready(ctx));
   if (enable && ctx->ev.empty()) {
-    const int n = 3 * 4096;
+    const int n = 2 * 4096;
     ctx->ev.resize(n);
     for (int i = 0; i < n; ++i) HIPC(hipEventCreate(&ctx->ev[i]));
   }

@@ -186,65 +186,62 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
   amax[i] = 0.0;
 }
 
-// Right-hand side of node m and CG start (x = 0, r = b):
+// Right-hand side of node m; CG start values x = 0, r = b on active rows:
 //   b_i = Phi_m,i - dt ML_i sum_{j<m} QE[m][j] dI_j,i - dt sum_k A_ik sum_{j<m} QI[m][j] dv_j,k
-// Partial sums r.z (z = dinv r) and b.b feed the instance scalars.
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_rhs_init(
-    Map map, int m, int n_inst, int64_t N, Csr A, const double* __restrict__ ml,
-    const double* __restrict__ dinv, const double* __restrict__ Phi_m,
-    const double* __restrict__ dI, const double* __restrict__ dv, double* __restrict__ r,
-    double* __restrict__ x, CgState cg, CollArgs c) {
-  if (blockIdx.x == 0) {
-    for (int t = threadIdx.x; t < n_inst; t += kBlock)
-      if (map.inst_nblk[t] == 0) {   // an instance without active rows has nothing to solve
-        cg.done[t] = 1;
-        cg.iters[t] = 0;
-      }
-  }
-  if (static_cast<int>(blockIdx.x) >= map.nblk) return;
+__global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Csr A,
+                                                const double* __restrict__ ml,
+                                                const double* __restrict__ Phi_m,
+                                                const double* __restrict__ dI,
+                                                const double* __restrict__ dv, double* __restrict__ r,
+                                                double* __restrict__ x, CollArgs c) {
   const Row rw = map_row(map);
-  double s[2] = {0.0, 0.0};
-  if (rw.valid) {
-    const int i = rw.row;
-    double ay = 0.0;
-    if (m > 0) {
-      const int e1 = A.rowptr[i + 1];
-      for (int e = A.rowptr[i]; e < e1; ++e) {
-        const int k = A.col[e];
-        double y = 0.0;
+  if (!rw.valid) return;
+  const int i = rw.row;
+  double ay = 0.0;
+  if (m > 0) {
+    const int e1 = A.rowptr[i + 1];
+    for (int e = A.rowptr[i]; e < e1; ++e) {
+      const int k = A.col[e];
+      double y = 0.0;
 #pragma unroll
-        for (int j = 0; j < M - 1; ++j)
-          if (j < m) y += c.QI[m][j] * dv[j * N + k];
-        ay += A.val[e] * y;
-      }
+      for (int j = 0; j < M - 1; ++j)
+        if (j < m) y += c.QI[m][j] * dv[j * N + k];
+      ay += A.val[e] * y;
     }
-    double ex = 0.0;
+  }
+  double ex = 0.0;
 #pragma unroll
-    for (int j = 0; j < M - 1; ++j)
-      if (j < m) ex += c.QE[m][j] * dI[j * N + i];
-    const double b = Phi_m[i] - c.dt * ml[i] * ex - c.dt * ay;
-    r[i] = b;
-    x[i] = 0.0;
-    s[0] = b * (dinv[i] * b);
-    s[1] = b * b;
-  }
-  if (instance_reduce<2>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
-    double* sc = cg.scal + rw.inst * kScal;
-    sc[kRZ] = s[0];
-    sc[kBB] = s[1];
-    sc[kBeta] = 0.0;
-    cg.done[rw.inst] = (s[1] == 0.0) ? 1 : 0;
-    cg.iters[rw.inst] = 0;
-  }
+  for (int j = 0; j < M - 1; ++j)
+    if (j < m) ex += c.QE[m][j] * dI[j * N + i];
+  r[i] = Phi_m[i] - c.dt * ml[i] * ex - c.dt * ay;
+  x[i] = 0.0;
 }
 
-// CG start from a given right-hand side b (component solve).
-__global__ __launch_bounds__(kBlock) void k_cg_init_b(Map map, int n_inst,
-                                                      const double* __restrict__ bvec,
-                                                      const double* __restrict__ dinv,
-                                                      double* __restrict__ r, double* __restrict__ x,
-                                                      CgState cg) {
+// CG start from a given right-hand side b (component solve): r = b, x = 0.
+__global__ __launch_bounds__(kBlock) void k_copy_b(Map map, const double* __restrict__ bvec,
+                                                   double* __restrict__ r, double* __restrict__ x) {
+  const Row rw = map_row(map);
+  if (!rw.valid) return;
+  r[rw.row] = bvec[rw.row];
+  x[rw.row] = 0.0;
+}
+
+// Jacobi-PCG in the single-reduction (Chronopoulos-Gear) arrangement: with
+// u = dinv r, w = H u and s = H p carried along, one iteration is
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//   u = dinv r,  w = H u,  gamma = r.u,  delta = w.u,  rr = r.r,
+//   beta' = gamma / gamma_old,  alpha' = gamma / (delta - beta' gamma / alpha),
+// the same iterates as standard PCG in exact arithmetic with one global
+// reduction per iteration, so one launch.  The SpMV forms u of every column
+// on the fly from the previous r, w, s (double-buffered; zero on inactive
+// rows, which is the restricted solve's Dirichlet condition).
+
+// Start: u0 = dinv r0, w0 = H u0, gamma0 = r0.u0, delta0 = w0.u0, bb = r0.r0.
+__global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, Csr H,
+                                                     const double* __restrict__ dinv,
+                                                     const double* __restrict__ r0,
+                                                     double* __restrict__ w0, CgState cg) {
   if (blockIdx.x == 0) {
     for (int t = threadIdx.x; t < n_inst; t += kBlock)
       if (map.inst_nblk[t] == 0) {   // an instance without active rows has nothing to solve
@@ -254,37 +251,50 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_b(Map map, int n_inst,
   }
   if (static_cast<int>(blockIdx.x) >= map.nblk) return;
   const Row rw = map_row(map);
-  double s[2] = {0.0, 0.0};
+  double s[3] = {0.0, 0.0, 0.0};
   if (rw.valid) {
     const int i = rw.row;
-    const double b = bvec[i];
-    r[i] = b;
-    x[i] = 0.0;
-    s[0] = b * (dinv[i] * b);
-    s[1] = b * b;
+    double acc = 0.0;
+    const int e1 = H.rowptr[i + 1];
+    for (int e = H.rowptr[i]; e < e1; ++e) {
+      const int k = H.col[e];
+      acc += H.val[e] * (dinv[k] * r0[k]);
+    }
+    const double ri = r0[i], ui = dinv[i] * ri;
+    w0[i] = acc;
+    s[0] = ri * ui;
+    s[1] = acc * ui;
+    s[2] = ri * ri;
   }
-  if (instance_reduce<2>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
+  if (instance_reduce<3>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
     double* sc = cg.scal + rw.inst * kScal;
+    const double alpha = s[0] / s[1];
     sc[kRZ] = s[0];
-    sc[kBB] = s[1];
+    sc[kBB] = s[2];
+    sc[kAlpha] = alpha;
     sc[kBeta] = 0.0;
-    cg.done[rw.inst] = (s[1] == 0.0) ? 1 : 0;
     cg.iters[rw.inst] = 0;
+    if (s[2] == 0.0) cg.done[rw.inst] = 1;
+    else if (!(s[1] > 0.0) || !isfinite(alpha)) cg.done[rw.inst] = 3;
+    else cg.done[rw.inst] = 0;
   }
 }
 
-// CG pass 1: p = z + beta p_old with z = dinv r, formed on the fly for every
-// column (inactive columns hold r = p = 0), q = H p on the active rows,
-// partial p.q; the last block sets alpha = r.z / p.q.
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(Map map, Csr H, const double* __restrict__ dinv,
-                                                    const double* __restrict__ r,
-                                                    const double* __restrict__ p_old,
-                                                    double* __restrict__ p_new,
-                                                    double* __restrict__ q, int first, CgState cg) {
+__global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, Csr H, const double* __restrict__ dinv,
+                                                    double* __restrict__ x, double* __restrict__ p,
+                                                    const double* __restrict__ r_in,
+                                                    const double* __restrict__ w_in,
+                                                    const double* __restrict__ s_in,
+                                                    double* __restrict__ r_out,
+                                                    double* __restrict__ w_out,
+                                                    double* __restrict__ s_out, int first,
+                                                    double rtol2, int maxit, CgState cg) {
   const Row rw = map_row(map);
   if (cg.done[rw.inst]) return;
-  const double beta = first ? 0.0 : cg.scal[rw.inst * kScal + kBeta];
-  double s[1] = {0.0};
+  const double* sc0 = cg.scal + rw.inst * kScal;
+  const double alpha = sc0[kAlpha];
+  const double beta = first ? 0.0 : sc0[kBeta];
+  double s[3] = {0.0, 0.0, 0.0};
   if (rw.valid) {
     const int i = rw.row;
     double acc = 0.0;
@@ -292,55 +302,43 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Map map, Csr H, const double
     if (first) {
       for (int e = H.rowptr[i]; e < e1; ++e) {
         const int k = H.col[e];
-        acc += H.val[e] * (dinv[k] * r[k]);
+        acc += H.val[e] * (dinv[k] * (r_in[k] - alpha * w_in[k]));
       }
     } else {
       for (int e = H.rowptr[i]; e < e1; ++e) {
         const int k = H.col[e];
-        acc += H.val[e] * (dinv[k] * r[k] + beta * p_old[k]);
+        acc += H.val[e] * (dinv[k] * (r_in[k] - alpha * (w_in[k] + beta * s_in[k])));
       }
     }
-    const double pi = first ? dinv[i] * r[i] : dinv[i] * r[i] + beta * p_old[i];
-    p_new[i] = pi;
-    q[i] = acc;
-    s[0] = pi * acc;
+    const double di = dinv[i], ri = r_in[i];
+    const double ui = di * ri;
+    const double pi = first ? ui : ui + beta * p[i];
+    const double si = first ? w_in[i] : w_in[i] + beta * s_in[i];
+    x[i] += alpha * pi;
+    p[i] = pi;
+    s_out[i] = si;
+    const double rn = ri - alpha * si;
+    r_out[i] = rn;
+    w_out[i] = acc;
+    const double un = di * rn;
+    s[0] = rn * un;
+    s[1] = acc * un;
+    s[2] = rn * rn;
   }
-  if (instance_reduce<1>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
-    double* sc = cg.scal + rw.inst * kScal;
-    const double alpha = sc[kRZ] / s[0];
-    if (!(s[0] > 0.0) || !isfinite(alpha)) cg.done[rw.inst] = 3;
-    sc[kAlpha] = alpha;
-  }
-}
-
-// CG pass 2: x += alpha p, r -= alpha q, partial r.z and r.r; the last block
-// counts the iteration, tests ||r|| <= rtol ||b|| and sets beta.
-__global__ __launch_bounds__(kBlock) void k_cg_update(Map map, const double* __restrict__ dinv,
-                                                      const double* __restrict__ p_new,
-                                                      const double* __restrict__ q,
-                                                      double* __restrict__ x, double* __restrict__ r,
-                                                      double rtol2, int maxit, CgState cg) {
-  const Row rw = map_row(map);
-  if (cg.done[rw.inst]) return;
-  const double alpha = cg.scal[rw.inst * kScal + kAlpha];
-  double s[2] = {0.0, 0.0};
-  if (rw.valid) {
-    const int i = rw.row;
-    x[i] += alpha * p_new[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    s[0] = ri * (dinv[i] * ri);
-    s[1] = ri * ri;
-  }
-  if (instance_reduce<2>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
+  if (instance_reduce<3>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
     double* sc = cg.scal + rw.inst * kScal;
     const int it = cg.iters[rw.inst] + 1;
     cg.iters[rw.inst] = it;
-    if (!isfinite(s[1])) cg.done[rw.inst] = 3;
-    else if (s[1] <= rtol2 * sc[kBB]) cg.done[rw.inst] = 1;
+    const double gamma = s[0], delta = s[1];
+    const double beta_n = gamma / sc[kRZ];
+    const double denom = delta - beta_n * gamma / sc[kAlpha];
+    if (!isfinite(s[2])) cg.done[rw.inst] = 3;
+    else if (s[2] <= rtol2 * sc[kBB]) cg.done[rw.inst] = 1;
     else if (it >= maxit) cg.done[rw.inst] = 2;
-    sc[kBeta] = s[0] / sc[kRZ];
-    sc[kRZ] = s[0];
+    else if (!(denom > 0.0) || !isfinite(gamma / denom)) cg.done[rw.inst] = 3;
+    sc[kRZ] = gamma;
+    sc[kBeta] = beta_n;
+    sc[kAlpha] = gamma / denom;
   }
 }
 
@@ -475,32 +473,21 @@ __device__ void build_map(const int32_t* cnt, const int32_t* aoff, int n_inst, c
 // Pass 2 (one block): block offsets, per-instance totals, next work map.
 __global__ __launch_bounds__(kScanThreads) void k_select_scan(Map map, int n_inst, int32_t* sel_cnt,
                                                               int32_t* sel_nnz, NextMap nm) {
-  int32_t* aoff_scratch = nm.aoff;
   __shared__ int64_t sh[kScanThreads];
+  int32_t* aoff_scratch = nm.aoff;
   const int nb = map.nblk;
-  // per-instance nnz before the scans overwrite the block counts
-  for (int i = threadIdx.x; i < n_inst; i += kScanThreads) {
-    int64_t z = 0;
-    int32_t c = 0;
-    const int b0 = map.inst_blk0[i], b1 = b0 + map.inst_nblk[i];
-    for (int b = b0; b < b1; ++b) {
-      z += sel_nnz[b];
-      c += sel_cnt[b];
-    }
-    nm.inst_nnz[i] = z;
-    nm.inst_cnt[i] = c;
-  }
-  __syncthreads();
   const int64_t total = scan_inplace<int32_t>(sel_cnt, nb, sh);
-  // new list offset of instance i = exclusive prefix of kept counts
-  if (threadIdx.x == 0) {
-    int32_t a = 0;
-    for (int i = 0; i < n_inst; ++i) {
-      aoff_scratch[i] = a;
-      a += nm.inst_cnt[i];
-    }
-    aoff_scratch[n_inst] = a;
+  const int64_t total_nnz = scan_inplace<int32_t>(sel_nnz, nb, sh);
+  // an instance's blocks are consecutive: its totals are differences of the prefixes
+  for (int i = threadIdx.x; i < n_inst; i += kScanThreads) {
+    const int b0 = map.inst_blk0[i], b1 = b0 + map.inst_nblk[i];
+    const int64_t c0 = b0 < nb ? sel_cnt[b0] : total, c1 = b1 < nb ? sel_cnt[b1] : total;
+    const int64_t z0 = b0 < nb ? sel_nnz[b0] : total_nnz, z1 = b1 < nb ? sel_nnz[b1] : total_nnz;
+    nm.inst_cnt[i] = static_cast<int32_t>(c1 - c0);
+    nm.inst_nnz[i] = z1 - z0;
+    aoff_scratch[i] = static_cast<int32_t>(c0);   // new list offset of instance i
   }
+  if (threadIdx.x == 0) aoff_scratch[n_inst] = static_cast<int32_t>(total);
   __syncthreads();
   build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, static_cast<int32_t>(total));
   if (threadIdx.x == 0) nm.totals[2] = 0;
@@ -522,11 +509,10 @@ __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* 
   for (int q = 0; q < wid; ++q) base += wc[q];
   const int rank = __popcll(mask & ((1ull << lane) - 1ull));
   if (keep) idx_out[base + rank] = rw.row;
-  if (rw.valid && !keep && zv.r) {
+  if (rw.valid && !keep && zv.dv) {
     const int i = rw.row;
-    zv.r[i] = 0.0;
-    zv.p0[i] = 0.0;
-    zv.p1[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kZeroVecs; ++q) zv.vec[q][i] = 0.0;
     for (int m = 0; m < zv.M; ++m) zv.dv[m * zv.N + i] = 0.0;
   }
 }
@@ -535,9 +521,8 @@ __global__ __launch_bounds__(kBlock) void k_zero_rows(Map map, ZeroVecs zv) {
   const Row rw = map_row(map);
   if (!rw.valid) return;
   const int i = rw.row;
-  zv.r[i] = 0.0;
-  zv.p0[i] = 0.0;
-  zv.p1[i] = 0.0;
+#pragma unroll
+  for (int q = 0; q < kZeroVecs; ++q) zv.vec[q][i] = 0.0;
   for (int m = 0; m < zv.M; ++m) zv.dv[m * zv.N + i] = 0.0;
 }
 
@@ -619,33 +604,32 @@ void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const C
   });
 }
 
-void launch_rhs_init(hipStream_t s, int M, int m, const Map& map, int n_inst, int64_t N,
-                     const Csr& A, const double* ml, const double* dinv, const double* Phi_m,
-                     const double* dI, const double* dv, double* r, double* x, const CgState& cg,
-                     const CollArgs& c) {
+void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Csr& A,
+                const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
+                double* x, const CollArgs& c) {
+  if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    k_rhs_init<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(
-        map, m, n_inst, N, A, ml, dinv, Phi_m, dI, dv, r, x, cg, c);
+    k_rhs<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c);
   });
 }
 
-void launch_cg_init_from_b(hipStream_t s, const Map& map, int n_inst, const double* b,
-                           const double* dinv, double* r, double* x, const CgState& cg) {
-  k_cg_init_b<<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, b, dinv, r, x, cg);
+void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, double* x) {
+  if (map.nblk <= 0) return;
+  k_copy_b<<<grid(map.nblk), kBlock, 0, s>>>(map, b, r, x);
 }
 
-void launch_cg_spmv(hipStream_t s, const Map& map, const Csr& H, const double* dinv,
-                    const double* r, const double* p_old, double* p_new, double* q, bool first,
+void launch_cg_start(hipStream_t s, const Map& map, int n_inst, const Csr& H, const double* dinv,
+                     const double* r0, double* w0, const CgState& cg) {
+  k_cg_start<<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, H, dinv, r0, w0, cg);
+}
+
+void launch_cg_iter(hipStream_t s, const Map& map, const Csr& H, const double* dinv, double* x,
+                    double* p, const double* r_in, const double* w_in, const double* s_in,
+                    double* r_out, double* w_out, double* s_out, bool first, double rtol2, int maxit,
                     const CgState& cg) {
   if (map.nblk <= 0) return;
-  k_cg_spmv<<<grid(map.nblk), kBlock, 0, s>>>(map, H, dinv, r, p_old, p_new, q, first ? 1 : 0, cg);
-}
-
-void launch_cg_update(hipStream_t s, const Map& map, const double* dinv, const double* p_new,
-                      const double* q, double* x, double* r, double rtol2, int maxit,
-                      const CgState& cg) {
-  if (map.nblk <= 0) return;
-  k_cg_update<<<grid(map.nblk), kBlock, 0, s>>>(map, dinv, p_new, q, x, r, rtol2, maxit, cg);
+  k_cg_iter<<<grid(map.nblk), kBlock, 0, s>>>(map, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out, s_out,
+                                              first ? 1 : 0, rtol2, maxit, cg);
 }
 
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,

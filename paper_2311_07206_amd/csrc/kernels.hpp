@@ -38,7 +38,7 @@ struct Csr {
 };
 
 // Per-instance CG scalars, layout [n_inst][kScal].
-enum { kRZ = 0, kBB, kAlpha, kBeta, kScal = 8 };
+enum { kRZ = 0, kBB, kAlpha, kBeta, kScal = 8 };   // kRZ holds gamma = r.z
 
 struct CgState {
   double* scal;        // [n_inst][kScal]
@@ -55,18 +55,19 @@ void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const C
                         const double* ml, const double* v0, const double* w0, const double* v,
                         const double* w, const double* I, const double* R, double* Phi,
                         double* Gam, double* amax, const CollArgs& c);
-void launch_rhs_init(hipStream_t s, int M, int m, const Map& map, int n_inst, int64_t N,
-                     const Csr& A, const double* ml, const double* dinv, const double* Phi_m,
-                     const double* dI, const double* dv, double* r, double* x, const CgState& cg,
-                     const CollArgs& c);
-void launch_cg_init_from_b(hipStream_t s, const Map& map, int n_inst, const double* b,
-                           const double* dinv, double* r, double* x, const CgState& cg);
-void launch_cg_spmv(hipStream_t s, const Map& map, const Csr& H, const double* dinv,
-                    const double* r, const double* p_old, double* p_new, double* q, bool first,
+// Right-hand side of node m; writes r = b and x = 0 on active rows.
+void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Csr& A,
+                const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
+                double* x, const CollArgs& c);
+void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, double* x);
+// Single-reduction Jacobi-PCG: start (w0 = H dinv r0 and the scalars), then
+// one launch per iteration reading buffers (r, w, s)_in, writing (r, w, s)_out.
+void launch_cg_start(hipStream_t s, const Map& map, int n_inst, const Csr& H, const double* dinv,
+                     const double* r0, double* w0, const CgState& cg);
+void launch_cg_iter(hipStream_t s, const Map& map, const Csr& H, const double* dinv, double* x,
+                    double* p, const double* r_in, const double* w_in, const double* s_in,
+                    double* r_out, double* w_out, double* s_out, bool first, double rtol2, int maxit,
                     const CgState& cg);
-void launch_cg_update(hipStream_t s, const Map& map, const double* dinv, const double* p_new,
-                      const double* q, double* x, double* r, double rtol2, int maxit,
-                      const CgState& cg);
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                  const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
                  double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
@@ -84,12 +85,11 @@ struct NextMap {
   int32_t* aoff;           // [n_inst+1] list offset of each instance's first row
   int32_t* totals;         // [0] total blocks, [1] total rows in the list, [2] invalid list
 };
-// Vectors that must be zero on inactive rows: CG residual, both search
-// direction buffers and the M node corrections dv[M][N].
+// Vectors that must be zero on inactive rows: the double-buffered CG vectors
+// gathered at neighbouring columns (r, w, s) and the M node corrections dv[M][N].
+constexpr int kZeroVecs = 6;
 struct ZeroVecs {
-  double* r;
-  double* p0;
-  double* p1;
+  double* vec[kZeroVecs];
   double* dv;
   int M;
   int64_t N;
