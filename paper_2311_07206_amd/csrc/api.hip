@@ -84,10 +84,9 @@ struct sdc_ctx {
   double* p = nullptr;
   double *r[2] = {nullptr, nullptr}, *wv[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
 
-  double* cg_scal = nullptr;
+  double* cg_scal[2] = {nullptr, nullptr};   // [n_inst][kScal] by launch parity
+  double* part[2] = {nullptr, nullptr};      // [nblk][4] by launch parity
   int32_t *cg_done = nullptr, *cg_iters = nullptr;
-  uint32_t* cg_counter = nullptr;
-  double* part = nullptr;
   int32_t *sel_cnt = nullptr, *sel_nnz = nullptr;
 
   MapBuf all;
@@ -104,6 +103,10 @@ struct sdc_ctx {
 
   bool in_step = false;
   int k = 0;
+  // per-node CG outcome of the current sweep, snapshot on the device (async steps)
+  int32_t* hist_done = nullptr;    // [M][n_inst]
+  int32_t* hist_iters = nullptr;   // [M][n_inst]
+  int64_t redone_steps = 0;
 
   // kernel timing (bench only)
   bool prof = false;
@@ -112,7 +115,7 @@ struct sdc_ctx {
   std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
 
   const MapBuf& curmap() const { return cur < 0 ? all : dyn[cur]; }
-  CgState cg() const { return CgState{cg_scal, cg_done, cg_iters, cg_counter, part}; }
+  CgState cg() const { return CgState{cg_done, cg_iters}; }
   Csr A() const { return Csr{rowptr, colidx, Aval}; }
   Csr H(int m) const { return Csr{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz}; }
   ZeroVecs zv() const { return ZeroVecs{{r[0], r[1], wv[0], wv[1], s[0], s[1]}, dv, prm.M, N}; }
@@ -189,7 +192,11 @@ int fetch_map(sdc_ctx* ctx, MapBuf* mb) {
 
 // Add the event timings of iterations [it0, it0 + budget) to the profile;
 // an iteration counts for the instances whose CG had not stopped before it.
-int account_timing(sdc_ctx* ctx, const MapBuf& mb, int it0, int budget, const int32_t* iters) {
+// Add the event timings of launches ev[2*(base+b)], ev[2*(base+b)+1] for
+// iterations b = 0..budget-1 of one solve (iteration it0 + b); an iteration
+// counts for the instances whose CG had not stopped before it.
+int account_timing_at(sdc_ctx* ctx, const MapBuf& mb, int base, int budget, const int32_t* iters,
+                      int it0 = 0) {
   const bool ident = mb.idx == nullptr;
   for (int b = 0; b < budget; ++b) {
     const int it = it0 + b;
@@ -200,12 +207,16 @@ int account_timing(sdc_ctx* ctx, const MapBuf& mb, int it0, int budget, const in
     }
     if (bytes == 0.0) continue;
     float t = 0.f;
-    HIPC(hipEventElapsedTime(&t, ctx->ev[2 * b], ctx->ev[2 * b + 1]));
+    HIPC(hipEventElapsedTime(&t, ctx->ev[2 * (base + b)], ctx->ev[2 * (base + b) + 1]));
     ctx->pst.cg_launches++;
     ctx->pst.cg_ms += t;
     ctx->pst.cg_bytes += bytes;
   }
   return SDC_OK;
+}
+
+int account_timing(sdc_ctx* ctx, const MapBuf& mb, int it0, int budget, const int32_t* iters) {
+  return account_timing_at(ctx, mb, 0, budget, iters, it0);
 }
 
 // Restricted Jacobi-PCG on H_m over the current map, starting from the state
@@ -221,7 +232,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   int budget = pred_slot >= 0 ? std::max(1, ctx->pred[pred_slot]) : 8;
   int it = 0;
   iters->assign(ni, 0);
-  launch_cg_start(ctx->stream, map, ni, H, dinv, ctx->r[0], ctx->wv[0], ctx->cg());
+  launch_cg_start(ctx->stream, map, ni, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
   HIPC(hipGetLastError());
   if (mb.nblk > 0) {
     for (;;) {
@@ -231,7 +242,8 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
         const int a = it & 1, o = a ^ 1;
         if (timed) HIPC(hipEventRecord(ctx->ev[2 * b], ctx->stream));
         launch_cg_iter(ctx->stream, map, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
-                       ctx->wv[o], ctx->s[o], it == 0, rtol2, ctx->prm.cg_maxit, ctx->cg());
+                       ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
+                       ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg());
         if (timed) HIPC(hipEventRecord(ctx->ev[2 * b + 1], ctx->stream));
       }
       HIPC(hipGetLastError());
@@ -251,7 +263,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
         if (d == 0) running = true;
       }
       if (!running) break;
-      if (it >= ctx->prm.cg_maxit + 1)
+      if (it >= ctx->prm.cg_maxit + 2)
         return fail(ctx, SDC_ERR_CG_MAXIT, "CG: iteration limit reached (node %d, sweep %d)", m, ctx->k);
       budget = std::max(2, budget / 2);
     }
@@ -282,58 +294,152 @@ int map_list(sdc_ctx* ctx, int slot, const int32_t* idx, int64_t n) {
   return SDC_OK;
 }
 
+// Launch node m's CG with the predicted iteration budget and no host
+// synchronisation; the done flags and iteration counts are copied to the
+// node's history slot on the device.  Launches after convergence return at
+// once, so the result equals the synchronous path whenever the budget
+// sufficed; do_sweep checks that once per sweep.
+int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, int* ev_off,
+                 std::vector<int>* ev_budget) {
+  const int ni = ctx->n_inst;
+  const Map map = mb.dev();
+  const Csr H = ctx->H(m);
+  const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
+  const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
+  const int budget = std::min(std::max(1, ctx->pred[pred_slot]) + 1, ctx->prm.cg_maxit + 1);
+  launch_cg_start(ctx->stream, map, ni, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+  const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * (*ev_off + budget);
+  for (int it = 0; mb.nblk > 0 && it < budget; ++it) {
+    const int a = it & 1, o = a ^ 1;
+    if (timed) HIPC(hipEventRecord(ctx->ev[2 * (*ev_off + it)], ctx->stream));
+    launch_cg_iter(ctx->stream, map, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
+                   ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
+                   rtol2, ctx->prm.cg_maxit, ctx->cg());
+    if (timed) HIPC(hipEventRecord(ctx->ev[2 * (*ev_off + it) + 1], ctx->stream));
+  }
+  HIPC(hipGetLastError());
+  (*ev_budget)[m] = timed && mb.nblk > 0 ? budget : 0;
+  if (timed) *ev_off += budget;
+  HIPC(hipMemcpyAsync(ctx->hist_done + m * ni, ctx->cg_done, ni * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->hist_iters + m * ni, ctx->cg_iters, ni * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  return SDC_OK;
+}
+
 // One sweep over the current active set; afterwards the current set is the
 // one the next sweep uses (pinned, selected, or unchanged).
-int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next) {
+int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async = false,
+             bool* short_budget = nullptr) {
   const int M = ctx->prm.M;
+  const int ni = ctx->n_inst;
   const int64_t N = ctx->N;
   const MapBuf& mb = ctx->curmap();
   const Map map = mb.dev();
+  // the statistics of this sweep refer to its own set, which the selection replaces
+  std::vector<int32_t> cnt = mb.cnt;
+  std::vector<int64_t> nnz = mb.nnz;
+  const bool ident = mb.idx == nullptr;
   if (st) {
     std::memset(st, 0, sizeof *st);
     st->n_active = mb.rows;
-    for (int i = 0; i < ctx->n_inst; ++i) st->nnz_active += mb.nnz[i];
+    for (int i = 0; i < ni; ++i) st->nnz_active += mb.nnz[i];
   }
   launch_sweep_start(ctx->stream, M, map, N, ctx->A(), ctx->ml, ctx->v0, ctx->w0, ctx->v, ctx->w,
                      ctx->I, ctx->R, ctx->Phi, ctx->Gam, ctx->amax, ctx->cargs);
-  std::vector<int> iters;
+  std::vector<std::vector<int>> iters(M);
+  std::vector<int> ev_budget(M, 0);
+  int ev_off = 0;
   for (int m = 0; m < M; ++m) {
     double* x = ctx->dv + m * N;
     launch_rhs(ctx->stream, M, m, map, N, ctx->A(), ctx->ml, ctx->Phi + m * N, ctx->dI, ctx->dv,
                ctx->r[0], x, ctx->cargs);
     HIPC(hipGetLastError());
     const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
-    TRY(run_cg(ctx, m, mb, x, slot, &iters));
+    if (async)
+      TRY(run_cg_async(ctx, m, mb, x, slot, &ev_off, &ev_budget));
+    else
+      TRY(run_cg(ctx, m, mb, x, slot, &iters[m]));
     launch_post(ctx->stream, M, m, map, N, ctx->ionic_d, x, ctx->v + m * N, ctx->w + m * N,
                 ctx->I + m * N, ctx->R + m * N, ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N,
                 ctx->dR, ctx->amax, ctx->cargs);
     HIPC(hipGetLastError());
-    if (st) {
-      for (int i = 0; i < ctx->n_inst; ++i) {
-        st->cg_iters_max[m] = std::max(st->cg_iters_max[m], iters[i]);
-        st->cg_row_iters[m] += static_cast<int64_t>(iters[i]) * mb.cnt[i];
-        st->cg_nnz_iters[m] += static_cast<int64_t>(iters[i]) * mb.nnz[i];
-      }
-    }
+  }
+  if (async) {
+    // one synchronisation per sweep: the nodes' CG outcomes (and below, the next set's size)
+    HIPC(hipMemcpyAsync(ctx->h_i32 + 8 + 2 * ni, ctx->hist_done, M * ni * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipMemcpyAsync(ctx->h_i32 + 8 + 2 * ni + M * ni, ctx->hist_iters, M * ni * 4, hipMemcpyDeviceToHost,
+                        ctx->stream));
   }
   const int next = ctx->k + 1;
+  bool synced = false;
   if (next < static_cast<int>(ctx->pin.size()) && ctx->pin[next]) {
     launch_zero_rows(ctx->stream, map, ctx->zv());
     const int slot = ctx->cur == 0 ? 1 : 0;
     TRY(map_list(ctx, slot, ctx->pin[next], ctx->pin_n[next]));
     ctx->cur = slot;
+    synced = true;
   } else if (ctx->prm.theta > 0.0 && select_next) {
     const int slot = ctx->cur == 0 ? 1 : 0;
     MapBuf& nm = ctx->dyn[slot];
-    launch_select(ctx->stream, map, ctx->n_inst, ctx->rowptr, ctx->amax, ctx->prm.theta, ctx->sel_cnt,
+    launch_select(ctx->stream, map, ni, ctx->rowptr, ctx->amax, ctx->prm.theta, ctx->sel_cnt,
                   ctx->sel_nnz, ctx->list[slot], nm.next(), ctx->zv());
     HIPC(hipGetLastError());
     TRY(fetch_map(ctx, &nm));
     nm.idx = ctx->list[slot];
     ctx->cur = slot;
+    synced = true;
   }
-  if (st) st->n_next = ctx->curmap().rows;
+  if (async) {
+    if (!synced) HIPC(hipStreamSynchronize(ctx->stream));
+    const int32_t* hd = ctx->h_i32 + 8 + 2 * ni;
+    const int32_t* hi = hd + M * ni;
+    for (int m = 0; m < M; ++m) {
+      iters[m].assign(hi + m * ni, hi + (m + 1) * ni);
+      int mx = 0;
+      for (int i = 0; i < ni; ++i) {
+        const int d = hd[m * ni + i];
+        if (d == 2)
+          return fail(ctx, SDC_ERR_CG_MAXIT, "CG: instance %d, node %d, sweep %d: no convergence in %d iterations",
+                      i, m, ctx->k, ctx->prm.cg_maxit);
+        if (d == 3)
+          return fail(ctx, SDC_ERR_NONFINITE, "CG: instance %d, node %d, sweep %d: non-finite or non-positive curvature",
+                      i, m, ctx->k);
+        if (d == 0 && short_budget) *short_budget = true;
+        mx = std::max(mx, iters[m][i]);
+      }
+      const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
+      ctx->pred[slot] = mx + 1;
+      if (ev_budget[m] > 0) {
+        MapBuf view;
+        view.idx = ident ? nullptr : mb.idx;
+        view.cnt = cnt;
+        view.nnz = nnz;
+        int base = 0;
+        for (int q = 0; q < m; ++q) base += ev_budget[q];
+        TRY(account_timing_at(ctx, view, base, ev_budget[m], iters[m].data()));
+      }
+    }
+  }
+  if (st) {
+    for (int m = 0; m < M; ++m)
+      for (int i = 0; i < ni; ++i) {
+        st->cg_iters_max[m] = std::max(st->cg_iters_max[m], iters[m][i]);
+        st->cg_row_iters[m] += static_cast<int64_t>(iters[m][i]) * cnt[i];
+        st->cg_nnz_iters[m] += static_cast<int64_t>(iters[m][i]) * nnz[i];
+      }
+    st->n_next = ctx->curmap().rows;
+  }
   ctx->k = next;
+  return SDC_OK;
+}
+
+// Spread the saved start state (v0, w0) to all nodes; all rows active.
+int restart_step(sdc_ctx* ctx) {
+  launch_spread(ctx->stream, ctx->prm.M, ctx->all.dev(), ctx->N, ctx->ionic_d, ctx->v0, ctx->w0, ctx->v,
+                ctx->w, ctx->I, ctx->R);
+  HIPC(hipGetLastError());
+  ctx->cur = -1;
+  ctx->k = 0;
+  ctx->in_step = true;
   return SDC_OK;
 }
 
@@ -523,14 +629,17 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   }
   TRY(dalloc(ctx, &ctx->list[0], N));
   TRY(dalloc(ctx, &ctx->list[1], N));
-  TRY(dalloc(ctx, &ctx->cg_scal, static_cast<size_t>(kScal) * n_inst));
+  for (int q = 0; q < 2; ++q) {
+    TRY(dalloc(ctx, &ctx->cg_scal[q], static_cast<size_t>(kScal) * n_inst));
+    TRY(dalloc(ctx, &ctx->part[q], 4 * static_cast<size_t>(nblk_all)));
+  }
   TRY(dalloc(ctx, &ctx->cg_done, n_inst));
   TRY(dalloc(ctx, &ctx->cg_iters, n_inst));
-  TRY(dalloc(ctx, &ctx->cg_counter, n_inst));
-  TRY(dalloc(ctx, &ctx->part, 4 * static_cast<size_t>(nblk_all)));
   TRY(dalloc(ctx, &ctx->sel_cnt, nblk_all));
   TRY(dalloc(ctx, &ctx->sel_nnz, nblk_all));
-  HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i32), (8 + 2 * n_inst) * sizeof(int32_t)));
+  HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i32), (8 + 2 * n_inst + 2 * M * n_inst) * sizeof(int32_t)));
+  TRY(dalloc(ctx, &ctx->hist_done, static_cast<size_t>(M) * n_inst));
+  TRY(dalloc(ctx, &ctx->hist_iters, static_cast<size_t>(M) * n_inst));
   HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i64), (8 + n_inst) * sizeof(int64_t)));
   HIPC(hipStreamSynchronize(ctx->stream));
   ctx->pred.assign(static_cast<size_t>(SDC_MAX_SWEEPS) * M, 8);
@@ -579,13 +688,7 @@ int sdc_begin_step(sdc_ctx* ctx, const double* v, const double* w, double t) {
   for (const auto& s : ctx->stims)
     if (t - 1e-9 * dt <= s.t_on && s.t_on < t + dt - 1e-9 * dt)
       launch_set_values(ctx->stream, s.nodes, s.n, s.value, ctx->v0);
-  launch_spread(ctx->stream, ctx->prm.M, ctx->all.dev(), N, ctx->ionic_d, ctx->v0, ctx->w0, ctx->v,
-                ctx->w, ctx->I, ctx->R);
-  HIPC(hipGetLastError());
-  ctx->cur = -1;
-  ctx->k = 0;
-  ctx->in_step = true;
-  return SDC_OK;
+  return restart_step(ctx);
 }
 
 int sdc_sweep(sdc_ctx* ctx, sdc_sweep_stats* stats) {
@@ -610,14 +713,27 @@ int sdc_end_step(sdc_ctx* ctx, double* v, double* w) {
 
 int sdc_step(sdc_ctx* ctx, double* v, double* w, double t, sdc_step_stats* stats) {
   TRY(sdc_begin_step(ctx, v, w, t));
-  if (stats) std::memset(stats, 0, sizeof *stats);
-  for (int k = 0; k < ctx->prm.K; ++k) {
-    int rc = do_sweep(ctx, stats ? &stats->sweep[k] : nullptr, k + 1 < ctx->prm.K);
-    if (rc != SDC_OK) {
-      ctx->in_step = false;
-      return rc;
+  // fast path: predicted CG budgets, one synchronisation per sweep; if a
+  // budget was short, redo the step from its saved start state with the
+  // synchronous CG loop (identical results, exact iteration counts)
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const bool async = attempt == 0;
+    if (!async) {
+      ++ctx->redone_steps;
+      TRY(restart_step(ctx));
     }
-    if (stats) stats->n_sweeps = k + 1;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    bool short_budget = false;
+    for (int k = 0; k < ctx->prm.K; ++k) {
+      int rc = do_sweep(ctx, stats ? &stats->sweep[k] : nullptr, k + 1 < ctx->prm.K, async, &short_budget);
+      if (rc != SDC_OK) {
+        ctx->in_step = false;
+        return rc;
+      }
+      if (short_budget) break;
+      if (stats) stats->n_sweeps = k + 1;
+    }
+    if (!short_budget) break;
   }
   return sdc_end_step(ctx, v, w);
 }

@@ -40,42 +40,6 @@ __device__ inline void block_sum(double (&v)[NV], double* sh /* [4 * NV] */) {
   }
 }
 
-// Block-sum v, publish this block's partial, and report whether this block is
-// the last of its instance; if so thread 0's v[] holds the instance totals
-// (summed over the instance's blocks in block order).
-template <int NV>
-__device__ bool instance_reduce(double (&v)[NV], const Map& map, int inst, double* part,
-                                uint32_t* counter) {
-  __shared__ double sh[4 * NV];
-  __shared__ int is_last;
-  block_sum<NV>(v, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) part[blockIdx.x * 4 + k] = v[k];
-    __threadfence();
-    const uint32_t prev = atomicAdd(&counter[inst], 1u);
-    is_last = (prev == static_cast<uint32_t>(map.inst_nblk[inst]) - 1u);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  const int b0 = map.inst_blk0[inst], nb = map.inst_nblk[inst];
-  double acc[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] += __builtin_nontemporal_load(&part[(b0 + b) * 4 + k]);
-  }
-  block_sum<NV>(acc, sh);
-  if (threadIdx.x == 0) {
-    counter[inst] = 0u;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = acc[k];
-  }
-  return true;
-}
-
 struct Row {
   int inst;
   int row;
@@ -231,23 +195,69 @@ __global__ __launch_bounds__(kBlock) void k_copy_b(Map map, const double* __rest
 // u = dinv r, w = H u and s = H p carried along, one iteration is
 //   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
 //   u = dinv r,  w = H u,  gamma = r.u,  delta = w.u,  rr = r.r,
-//   beta' = gamma / gamma_old,  alpha' = gamma / (delta - beta' gamma / alpha),
-// the same iterates as standard PCG in exact arithmetic with one global
-// reduction per iteration, so one launch.  The SpMV forms u of every column
-// on the fly from the previous r, w, s (double-buffered; zero on inactive
-// rows, which is the restricted solve's Dirichlet condition).
+// with beta = gamma / gamma_old and alpha = gamma / (delta - beta gamma / alpha_old):
+// the iterates of standard PCG in exact arithmetic, with one global
+// reduction per iteration.  The SpMV forms u of every column on the fly from
+// the previous r, w, s (double-buffered; zero on inactive rows, which is the
+// restricted solve's Dirichlet condition).
+//
+// Reductions without fences: every block writes its partial sums; each block
+// of the next launch sums the partials of its instance in block order (so
+// every block obtains bitwise the same scalars) and block 0 of the instance
+// records the scalars, the stopping decision and the iteration count.
+// Launch `it` first tests the residual left by `it` updates, then performs
+// update it+1; a solve that stops after n updates therefore takes n + 1
+// launches.
 
-// Start: u0 = dinv r0, w0 = H u0, gamma0 = r0.u0, delta0 = w0.u0, bb = r0.r0.
+struct CgBufs {
+  double* part[2];     // [nblk][4] partial sums written by launch parity
+  double* scal[2];     // [n_inst][kScal] scalars written by launch parity
+};
+
+// Sum this instance's partials of the previous launch (same in every block).
+__device__ inline void instance_totals(const Map& map, int inst, const double* __restrict__ part,
+                                       double (&tot)[3], double* sh) {
+  const int b0 = map.inst_blk0[inst], nb = map.inst_nblk[inst];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    const double* pp = part + 4 * (b0 + b);
+    acc[0] += pp[0];
+    acc[1] += pp[1];
+    acc[2] += pp[2];
+  }
+  block_sum<3>(acc, sh);
+  if (threadIdx.x == 0) {
+    sh[12] = acc[0];
+    sh[13] = acc[1];
+    sh[14] = acc[2];
+  }
+  __syncthreads();
+  tot[0] = sh[12];
+  tot[1] = sh[13];
+  tot[2] = sh[14];
+}
+
+template <int NV>
+__device__ inline void write_partials(double (&v)[NV], double* part, double* sh) {
+  block_sum<NV>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) part[4 * blockIdx.x + q] = v[q];
+  }
+}
+
+// Start: u0 = dinv r0, w0 = H u0; partials of gamma0 = r0.u0, delta0 = w0.u0, bb = r0.r0.
 __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, Csr H,
                                                      const double* __restrict__ dinv,
                                                      const double* __restrict__ r0,
-                                                     double* __restrict__ w0, CgState cg) {
+                                                     double* __restrict__ w0, double* part_out,
+                                                     CgState cg) {
+  __shared__ double sh[16];
   if (blockIdx.x == 0) {
-    for (int t = threadIdx.x; t < n_inst; t += kBlock)
-      if (map.inst_nblk[t] == 0) {   // an instance without active rows has nothing to solve
-        cg.done[t] = 1;
-        cg.iters[t] = 0;
-      }
+    for (int t = threadIdx.x; t < n_inst; t += kBlock) {
+      cg.done[t] = map.inst_nblk[t] == 0 ? 1 : 0;   // no active rows: nothing to solve
+      cg.iters[t] = 0;
+    }
   }
   if (static_cast<int>(blockIdx.x) >= map.nblk) return;
   const Row rw = map_row(map);
@@ -266,18 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, Csr H,
     s[1] = acc * ui;
     s[2] = ri * ri;
   }
-  if (instance_reduce<3>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
-    double* sc = cg.scal + rw.inst * kScal;
-    const double alpha = s[0] / s[1];
-    sc[kRZ] = s[0];
-    sc[kBB] = s[2];
-    sc[kAlpha] = alpha;
-    sc[kBeta] = 0.0;
-    cg.iters[rw.inst] = 0;
-    if (s[2] == 0.0) cg.done[rw.inst] = 1;
-    else if (!(s[1] > 0.0) || !isfinite(alpha)) cg.done[rw.inst] = 3;
-    else cg.done[rw.inst] = 0;
-  }
+  write_partials<3>(s, part_out, sh);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, Csr H, const double* __restrict__ dinv,
@@ -287,19 +286,51 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, Csr H, const double
                                                     const double* __restrict__ s_in,
                                                     double* __restrict__ r_out,
                                                     double* __restrict__ w_out,
-                                                    double* __restrict__ s_out, int first,
-                                                    double rtol2, int maxit, CgState cg) {
+                                                    double* __restrict__ s_out, int it,
+                                                    const double* __restrict__ part_in,
+                                                    double* __restrict__ part_out,
+                                                    const double* __restrict__ scal_in,
+                                                    double* __restrict__ scal_out, double rtol2,
+                                                    int maxit, CgState cg) {
+  __shared__ double sh[16];
   const Row rw = map_row(map);
-  if (cg.done[rw.inst]) return;
-  const double* sc0 = cg.scal + rw.inst * kScal;
-  const double alpha = sc0[kAlpha];
-  const double beta = first ? 0.0 : sc0[kBeta];
+  const int inst = rw.inst;
+  if (cg.done[inst]) return;
+  double tot[3];
+  instance_totals(map, inst, part_in, tot, sh);
+  const double gamma = tot[0], delta = tot[1], rr = tot[2];
+  double alpha, beta, bb;
+  if (it == 0) {
+    bb = rr;
+    beta = 0.0;
+    alpha = gamma / delta;
+  } else {
+    const double* sc = scal_in + inst * kScal;
+    bb = sc[kBB];
+    beta = gamma / sc[kRZ];
+    alpha = gamma / (delta - beta * gamma / sc[kAlpha]);
+  }
+  int status = 0;
+  if (!isfinite(rr)) status = 3;
+  else if (rr <= rtol2 * bb) status = 1;
+  else if (it >= maxit) status = 2;
+  else if (!isfinite(alpha) || !(alpha > 0.0)) status = 3;
+  if (rw.valid && map.blk[blockIdx.x].w == 0 && threadIdx.x == 0) {
+    // block 0 of the instance records the outcome and the scalars
+    cg.done[inst] = status;
+    cg.iters[inst] = it;
+    double* so = scal_out + inst * kScal;
+    so[kRZ] = gamma;
+    so[kAlpha] = alpha;
+    so[kBB] = bb;
+  }
+  if (status != 0) return;
   double s[3] = {0.0, 0.0, 0.0};
   if (rw.valid) {
     const int i = rw.row;
     double acc = 0.0;
     const int e1 = H.rowptr[i + 1];
-    if (first) {
+    if (it == 0) {
       for (int e = H.rowptr[i]; e < e1; ++e) {
         const int k = H.col[e];
         acc += H.val[e] * (dinv[k] * (r_in[k] - alpha * w_in[k]));
@@ -312,8 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, Csr H, const double
     }
     const double di = dinv[i], ri = r_in[i];
     const double ui = di * ri;
-    const double pi = first ? ui : ui + beta * p[i];
-    const double si = first ? w_in[i] : w_in[i] + beta * s_in[i];
+    const double pi = it == 0 ? ui : ui + beta * p[i];
+    const double si = it == 0 ? w_in[i] : w_in[i] + beta * s_in[i];
     x[i] += alpha * pi;
     p[i] = pi;
     s_out[i] = si;
@@ -325,21 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, Csr H, const double
     s[1] = acc * un;
     s[2] = rn * rn;
   }
-  if (instance_reduce<3>(s, map, rw.inst, cg.part, cg.counter) && threadIdx.x == 0) {
-    double* sc = cg.scal + rw.inst * kScal;
-    const int it = cg.iters[rw.inst] + 1;
-    cg.iters[rw.inst] = it;
-    const double gamma = s[0], delta = s[1];
-    const double beta_n = gamma / sc[kRZ];
-    const double denom = delta - beta_n * gamma / sc[kAlpha];
-    if (!isfinite(s[2])) cg.done[rw.inst] = 3;
-    else if (s[2] <= rtol2 * sc[kBB]) cg.done[rw.inst] = 1;
-    else if (it >= maxit) cg.done[rw.inst] = 2;
-    else if (!(denom > 0.0) || !isfinite(gamma / denom)) cg.done[rw.inst] = 3;
-    sc[kRZ] = gamma;
-    sc[kBeta] = beta_n;
-    sc[kAlpha] = gamma / denom;
-  }
+  write_partials<3>(s, part_out, sh);
 }
 
 // Post-solve update of node m (eq. final-sdc):
@@ -619,17 +636,18 @@ void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, do
 }
 
 void launch_cg_start(hipStream_t s, const Map& map, int n_inst, const Csr& H, const double* dinv,
-                     const double* r0, double* w0, const CgState& cg) {
-  k_cg_start<<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, H, dinv, r0, w0, cg);
+                     const double* r0, double* w0, double* part_out, const CgState& cg) {
+  k_cg_start<<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, H, dinv, r0, w0, part_out, cg);
 }
 
 void launch_cg_iter(hipStream_t s, const Map& map, const Csr& H, const double* dinv, double* x,
                     double* p, const double* r_in, const double* w_in, const double* s_in,
-                    double* r_out, double* w_out, double* s_out, bool first, double rtol2, int maxit,
-                    const CgState& cg) {
+                    double* r_out, double* w_out, double* s_out, int it, const double* part_in,
+                    double* part_out, const double* scal_in, double* scal_out, double rtol2,
+                    int maxit, const CgState& cg) {
   if (map.nblk <= 0) return;
   k_cg_iter<<<grid(map.nblk), kBlock, 0, s>>>(map, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out, s_out,
-                                              first ? 1 : 0, rtol2, maxit, cg);
+                                              it, part_in, part_out, scal_in, scal_out, rtol2, maxit, cg);
 }
 
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,

@@ -41,11 +41,8 @@ struct Csr {
 enum { kRZ = 0, kBB, kAlpha, kBeta, kScal = 8 };   // kRZ holds gamma = r.z
 
 struct CgState {
-  double* scal;        // [n_inst][kScal]
   int32_t* done;       // 0 running, 1 converged, 2 maxit, 3 non-finite
-  int32_t* iters;
-  uint32_t* counter;   // last-block counters, zero between kernels
-  double* part;        // [nblk_max][4] block partial sums
+  int32_t* iters;      // updates performed when the solve stopped
 };
 
 void launch_spread(hipStream_t s, int M, const Map& all, int64_t N, const double* ionic,
@@ -60,14 +57,18 @@ void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Cs
                 const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
                 double* x, const CollArgs& c);
 void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, double* x);
-// Single-reduction Jacobi-PCG: start (w0 = H dinv r0 and the scalars), then
+// Single-reduction Jacobi-PCG: start (w0 = H dinv r0 and partial sums), then
 // one launch per iteration reading buffers (r, w, s)_in, writing (r, w, s)_out.
+// Launch `it` reads the partial sums and scalars of launch it-1 (part_in,
+// scal_in) and writes its own (part_out, scal_out); the start kernel's
+// partials are the input of launch 0.
 void launch_cg_start(hipStream_t s, const Map& map, int n_inst, const Csr& H, const double* dinv,
-                     const double* r0, double* w0, const CgState& cg);
+                     const double* r0, double* w0, double* part_out, const CgState& cg);
 void launch_cg_iter(hipStream_t s, const Map& map, const Csr& H, const double* dinv, double* x,
                     double* p, const double* r_in, const double* w_in, const double* s_in,
-                    double* r_out, double* w_out, double* s_out, bool first, double rtol2, int maxit,
-                    const CgState& cg);
+                    double* r_out, double* w_out, double* s_out, int it, const double* part_in,
+                    double* part_out, const double* scal_in, double* scal_out, double rtol2,
+                    int maxit, const CgState& cg);
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                  const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
                  double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
