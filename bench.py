@@ -42,26 +42,28 @@ def parse():
 
 
 def sweep_bytes(st, M, ident):
-    """Algorithmic bytes of one sweep from its statistics (FP64 = 8 B, int32 = 4 B).
+    """Algorithmic bytes of one sweep from its statistics.
 
-    Per active row (n_a rows, z_a stored entries of A in them; idx read only
-    when not every row is active):
-      sweep start    12 z_a + 4 + idx + 8 (6M + 4)
-      node RHS       12 z_a [m > 0] + 4 + idx + 8 (2m + 4)
-      CG start       12 z_a + 4 + idx + 24
-      CG iteration   12 z + 4 + idx + 88   per iteration (z = entries of the
-                     rows still iterating)
+    8 B per FP64 value, 4 B per active-list entry (absent when every row is
+    active), 8 B per stored matrix value; index structure (CSR columns and
+    row pointers) is storage overhead and not counted.  Per active row
+    (n_a rows, z_a stored values of A in them):
+      sweep start    8 z_a + idx + 8 (6M + 4)
+      node RHS       8 z_a [m > 0] + idx + 8 (2m + 4)
+      CG start       8 z_a + idx + 24
+      CG iteration   8 z + idx + 88   per iteration (z = values of the rows
+                     still iterating)
       post-solve     idx + 8 (m + 14)
       selection      2 idx + 24
     """
     na, za = st["n_active"], st["nnz_active"]
     idxb = 0 if ident else 4
-    b = 12 * za + na * (4 + idxb + 8 * (6 * M + 4))
+    b = 8 * za + na * (idxb + 8 * (6 * M + 4))
     for m in range(M):
         rows, nnz = st["cg_row_iters"][m], st["cg_nnz_iters"][m]
-        b += (12 * za if m > 0 else 0) + na * (4 + idxb + 8 * (2 * m + 4))
-        b += 12 * za + na * (28 + idxb)
-        b += 12 * nnz + (92 + idxb) * rows
+        b += (8 * za if m > 0 else 0) + na * (idxb + 8 * (2 * m + 4))
+        b += 8 * za + na * (24 + idxb)
+        b += 8 * nnz + (88 + idxb) * rows
         b += na * (idxb + 8 * (m + 14))
     b += na * (2 * idxb + 24)
     return b
@@ -143,6 +145,7 @@ def main():
                         f"t={t_start:.1f}..{t_start + args.steps * P.dt:.1f} ms",
             "dofs": P.N, "nnz": s.nnz, "M": P.M, "K": P.K,
         },
+        "storage": s.info(),
         "algorithmic_GBps": nbytes / elapsed / 1e9,
         "algorithmic_frac_hbm": nbytes / elapsed / 1e9 / HBM_PEAK_GBS,
         "mean_active_per_sweep": per_sweep_active,

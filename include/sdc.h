@@ -67,7 +67,9 @@ typedef struct {
   double theta;       /* drop tolerance TOL_drop; <= 0: all rows stay active   */
   double cg_rtol;     /* stop when ||r||_2 <= cg_rtol * ||b||_2 (active rows)  */
   int32_t cg_maxit;   /* CG iteration limit per solve (SDC_ERR_CG_MAXIT)       */
-  int32_t reserved;   /* must be 0                                             */
+  int32_t format;     /* matrix storage: 0 = timed choice at setup, 1 = CSR,   */
+                      /* 2 = diagonal (every instance's rows use <= 32        */
+                      /* distinct column offsets; else SDC_ERR_ARG)           */
 } sdc_params;
 
 /* Per-sweep statistics (sums over instances unless stated). */
@@ -172,14 +174,29 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
  * vector updates and the three dot products), taken with HIP events on the
  * context's stream around every launch that does work for at least one
  * instance.  Bytes are the algorithmic minimum per launch over the instances
- * still iterating: 12 per stored entry of A in their active rows, plus per
- * active row 4 (rowptr) + 4 (idx; absent when every row is active)
- * + 6*8 reads (x, p, r, w, s, dinv) + 5*8 writes (x, p, r, w, s). */
+ * still iterating: 8 per stored matrix value in their active rows (index
+ * structure is storage overhead and not counted), plus per active row
+ * 4 (active-list entry; absent when every row is active) + 6*8 reads
+ * (x, p, r, w, s, dinv) + 5*8 writes (x, p, r, w, s). */
 typedef struct {
   int64_t cg_launches;
   double cg_ms;
   double cg_bytes;
 } sdc_profile_stats;
+
+/* Setup outcome: storage in use (1 CSR, 2 diagonal), diagonals per row in the
+ * diagonal storage (0 if not available), the setup timings of one SpMV-shaped
+ * CG start launch over all rows in each storage (0 if not timed), and the
+ * number of steps redone because a predicted CG budget was too small. */
+typedef struct {
+  int32_t format;
+  int32_t n_diagonals;
+  double t_csr_us;
+  double t_dia_us;
+  int64_t redone_steps;
+} sdc_info;
+
+int sdc_get_info(sdc_ctx* ctx, sdc_info* out);
 
 /* enable != 0 starts timing (and clears the totals); 0 stops it. */
 int sdc_profile(sdc_ctx* ctx, int32_t enable);

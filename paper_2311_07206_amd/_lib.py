@@ -22,7 +22,7 @@ ERRORS = {
 
 class Params(ctypes.Structure):
     _fields_ = [("M", c_int32), ("K", c_int32), ("dt", c_double), ("theta", c_double),
-                ("cg_rtol", c_double), ("cg_maxit", c_int32), ("reserved", c_int32)]
+                ("cg_rtol", c_double), ("cg_maxit", c_int32), ("format", c_int32)]
 
 
 class SweepStats(ctypes.Structure):
@@ -45,6 +45,11 @@ class StepStats(ctypes.Structure):
 
 class ProfileStats(ctypes.Structure):
     _fields_ = [("cg_launches", c_int64), ("cg_ms", c_double), ("cg_bytes", c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("format", c_int32), ("n_diagonals", c_int32), ("t_csr_us", c_double),
+                ("t_dia_us", c_double), ("redone_steps", c_int64)]
 
 
 PTR = c_void_p
@@ -72,6 +77,7 @@ SIGNATURES = {
     "sdc_select": (c_int32, [c_void_p, PTR, PTR, c_int64, c_double, PTR, P_I64]),
     "sdc_collocation": (c_int32, [c_int32, PTR, PTR, PTR, PTR]),
     "sdc_profile": (c_int32, [c_void_p, c_int32]),
+    "sdc_get_info": (c_int32, [c_void_p, POINTER(Info)]),
     "sdc_profile_read": (c_int32, [c_void_p, POINTER(ProfileStats)]),
 }
 

@@ -73,6 +73,12 @@ struct sdc_ctx {
 
   int32_t *rowptr = nullptr, *colidx = nullptr, *diagpos = nullptr;
   double *Aval = nullptr, *Hval = nullptr, *ml = nullptr, *dinv = nullptr;
+  // diagonal storage (nd > 0 when every instance has at most kMaxDiag offsets)
+  int nd = 0;
+  int32_t* dia_off = nullptr;      // [n_inst][nd]
+  double *dia_A = nullptr, *dia_H = nullptr;   // [nd][N], [M][nd][N]
+  bool use_dia = false;
+  double t_csr_us = 0.0, t_dia_us = 0.0;
   int64_t* node_off_d = nullptr;
   double* ionic_d = nullptr;
 
@@ -116,8 +122,15 @@ struct sdc_ctx {
 
   const MapBuf& curmap() const { return cur < 0 ? all : dyn[cur]; }
   CgState cg() const { return CgState{cg_done, cg_iters}; }
-  Csr A() const { return Csr{rowptr, colidx, Aval}; }
-  Csr H(int m) const { return Csr{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz}; }
+  Mat matA(bool dia) const {
+    return Mat{rowptr, colidx, Aval, dia_off, dia_A, node_off_d, dia ? nd : 0};
+  }
+  Mat matH(int m, bool dia) const {
+    return Mat{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz, dia_off,
+               dia_H ? dia_H + static_cast<int64_t>(m) * nd * N : nullptr, node_off_d, dia ? nd : 0};
+  }
+  Mat A() const { return matA(use_dia); }
+  Mat H(int m) const { return matH(m, use_dia); }
   ZeroVecs zv() const { return ZeroVecs{{r[0], r[1], wv[0], wv[1], s[0], s[1]}, dv, prm.M, N}; }
 };
 
@@ -203,7 +216,7 @@ int account_timing_at(sdc_ctx* ctx, const MapBuf& mb, int base, int budget, cons
     double bytes = 0.0;
     for (int i = 0; i < ctx->n_inst; ++i) {
       if (it >= iters[i] || mb.cnt[i] == 0) continue;
-      bytes += 12.0 * static_cast<double>(mb.nnz[i]) + (ident ? 92.0 : 96.0) * mb.cnt[i];
+      bytes += 8.0 * static_cast<double>(mb.nnz[i]) + (ident ? 88.0 : 92.0) * mb.cnt[i];
     }
     if (bytes == 0.0) continue;
     float t = 0.f;
@@ -226,13 +239,13 @@ int account_timing(sdc_ctx* ctx, const MapBuf& mb, int it0, int budget, const in
 int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std::vector<int>* iters) {
   const int ni = ctx->n_inst;
   const Map map = mb.dev();
-  const Csr H = ctx->H(m);
+  const Mat H = ctx->H(m);
   const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
   const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
   int budget = pred_slot >= 0 ? std::max(1, ctx->pred[pred_slot]) : 8;
   int it = 0;
   iters->assign(ni, 0);
-  launch_cg_start(ctx->stream, map, ni, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+  launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
   HIPC(hipGetLastError());
   if (mb.nblk > 0) {
     for (;;) {
@@ -241,7 +254,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
       for (int b = 0; b < budget; ++b, ++it) {
         const int a = it & 1, o = a ^ 1;
         if (timed) HIPC(hipEventRecord(ctx->ev[2 * b], ctx->stream));
-        launch_cg_iter(ctx->stream, map, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
+        launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
                        ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
                        ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg());
         if (timed) HIPC(hipEventRecord(ctx->ev[2 * b + 1], ctx->stream));
@@ -303,16 +316,16 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
                  std::vector<int>* ev_budget) {
   const int ni = ctx->n_inst;
   const Map map = mb.dev();
-  const Csr H = ctx->H(m);
+  const Mat H = ctx->H(m);
   const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
   const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
   const int budget = std::min(std::max(1, ctx->pred[pred_slot]) + 1, ctx->prm.cg_maxit + 1);
-  launch_cg_start(ctx->stream, map, ni, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+  launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
   const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * (*ev_off + budget);
   for (int it = 0; mb.nblk > 0 && it < budget; ++it) {
     const int a = it & 1, o = a ^ 1;
     if (timed) HIPC(hipEventRecord(ctx->ev[2 * (*ev_off + it)], ctx->stream));
-    launch_cg_iter(ctx->stream, map, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
+    launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
                    ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
                    rtol2, ctx->prm.cg_maxit, ctx->cg());
     if (timed) HIPC(hipEventRecord(ctx->ev[2 * (*ev_off + it) + 1], ctx->stream));
@@ -432,6 +445,100 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async = f
   return SDC_OK;
 }
 
+// Diagonal storage: per instance, the distinct column offsets (col - row) of
+// its rows; usable when no instance has more than kMaxDiag of them.
+int build_dia(sdc_ctx* ctx) {
+  const int ni = ctx->n_inst;
+  const int64_t N = ctx->N;
+  const HostSystem& hs = ctx->host;
+  std::vector<std::vector<int32_t>> offs(ni);
+  int nd = 0;
+  for (int i = 0; i < ni; ++i) {
+    std::vector<int32_t> o;
+    for (int64_t r = ctx->node_off_h[i]; r < ctx->node_off_h[i + 1]; ++r)
+      for (int32_t e = hs.rowptr[r]; e < hs.rowptr[r + 1]; ++e) {
+        const int32_t d = hs.col[e] - static_cast<int32_t>(r);
+        if (std::find(o.begin(), o.end(), d) == o.end()) {
+          o.push_back(d);
+          if (static_cast<int>(o.size()) > kMaxDiag) return SDC_OK;   // not diagonal-structured
+        }
+      }
+    std::sort(o.begin(), o.end());
+    nd = std::max(nd, static_cast<int>(o.size()));
+    offs[i] = std::move(o);
+  }
+  std::vector<int32_t> off(static_cast<size_t>(ni) * nd, 0);
+  std::vector<int> dg(ni, 0);
+  for (int i = 0; i < ni; ++i) {
+    for (int d = 0; d < static_cast<int>(offs[i].size()); ++d) {
+      off[i * nd + d] = offs[i][d];
+      if (offs[i][d] == 0) dg[i] = d;
+    }
+    // padding slots repeat offset 0 with zero values
+    for (int d = static_cast<int>(offs[i].size()); d < nd; ++d) off[i * nd + d] = 0;
+  }
+  std::vector<double> val(static_cast<size_t>(nd) * N, 0.0);
+  for (int i = 0; i < ni; ++i)
+    for (int64_t r = ctx->node_off_h[i]; r < ctx->node_off_h[i + 1]; ++r)
+      for (int32_t e = hs.rowptr[r]; e < hs.rowptr[r + 1]; ++e) {
+        const int32_t d = hs.col[e] - static_cast<int32_t>(r);
+        const auto& o = offs[i];
+        const int q = static_cast<int>(std::lower_bound(o.begin(), o.end(), d) - o.begin());
+        val[static_cast<size_t>(q) * N + r] = hs.val[e];
+      }
+  const int M = ctx->prm.M;
+  TRY(dalloc(ctx, &ctx->dia_off, off.size()));
+  TRY(dalloc(ctx, &ctx->dia_A, val.size()));
+  TRY(dalloc(ctx, &ctx->dia_H, val.size() * M));
+  HIPC(hipMemcpyAsync(ctx->dia_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->dia_A, val.data(), val.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  for (int m = 0; m < M; ++m)
+    for (int i = 0; i < ni; ++i)
+      launch_build_h_dia(ctx->stream, N, static_cast<int>(ctx->node_off_h[i]), static_cast<int>(ctx->node_off_h[i + 1]),
+                         nd, dg[i], ctx->dia_A, ctx->ml, ctx->prm.dt * ctx->col.QI[m][m],
+                         ctx->dia_H + static_cast<int64_t>(m) * nd * N);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(ctx->stream));   // the host staging vector goes out of scope
+  ctx->nd = nd;
+  return SDC_OK;
+}
+
+// Storage choice: time the CG start kernel (an SpMV with H_0 over all rows)
+// in each storage and keep the faster one (or the one the caller forced).
+int autotune(sdc_ctx* ctx) {
+  ctx->use_dia = false;
+  if (ctx->nd == 0 || ctx->prm.format == 1) return SDC_OK;
+  if (ctx->prm.format == 2) {
+    ctx->use_dia = true;
+    return SDC_OK;
+  }
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  const Map map = ctx->all.dev();
+  double t[2];
+  for (int f = 0; f < 2; ++f) {
+    const Mat H = ctx->matH(0, f == 1);
+    for (int rep = 0; rep < 3; ++rep)
+      launch_cg_start(ctx->stream, map, ctx->n_inst, ctx->N, H, ctx->dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+    const int reps = 10;
+    HIPC(hipEventRecord(e0, ctx->stream));
+    for (int rep = 0; rep < reps; ++rep)
+      launch_cg_start(ctx->stream, map, ctx->n_inst, ctx->N, H, ctx->dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+    HIPC(hipEventRecord(e1, ctx->stream));
+    HIPC(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    t[f] = 1e3 * ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->t_csr_us = t[0];
+  ctx->t_dia_us = t[1];
+  ctx->use_dia = t[1] < t[0];
+  return SDC_OK;
+}
+
 // Spread the saved start state (v0, w0) to all nodes; all rows active.
 int restart_step(sdc_ctx* ctx) {
   launch_spread(ctx->stream, ctx->prm.M, ctx->all.dev(), ctx->N, ctx->ionic_d, ctx->v0, ctx->w0, ctx->v,
@@ -521,8 +628,8 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     return fail(ctx, SDC_ERR_ARG, "null argument");
   if (prm->M < 1 || prm->M > SDC_MAX_NODES) return fail(ctx, SDC_ERR_ARG, "M must be in 1..%d", SDC_MAX_NODES);
   if (prm->K < 1 || prm->K > SDC_MAX_SWEEPS) return fail(ctx, SDC_ERR_ARG, "K must be in 1..%d", SDC_MAX_SWEEPS);
-  if (!(prm->dt > 0.0) || !(prm->cg_rtol > 0.0) || prm->cg_maxit < 1 || prm->reserved != 0)
-    return fail(ctx, SDC_ERR_ARG, "dt, cg_rtol must be > 0, cg_maxit >= 1, reserved = 0");
+  if (!(prm->dt > 0.0) || !(prm->cg_rtol > 0.0) || prm->cg_maxit < 1 || prm->format < 0 || prm->format > 2)
+    return fail(ctx, SDC_ERR_ARG, "dt, cg_rtol must be > 0, cg_maxit >= 1, format in 0..2");
   if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
   if (node_off[0] != 0 || elem_off[0] != 0) return fail(ctx, SDC_ERR_ARG, "offsets must start at 0");
   for (int i = 0; i < n_inst; ++i)
@@ -581,6 +688,9 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     launch_build_h(ctx->stream, N, ctx->rowptr, ctx->diagpos, ctx->Aval, ctx->ml,
                    prm->dt * ctx->col.QI[m][m], ctx->Hval + m * nnz, ctx->dinv + m * N);
   HIPC(hipGetLastError());
+  TRY(build_dia(ctx));
+  if (prm->format == 2 && ctx->nd == 0)
+    return fail(ctx, SDC_ERR_ARG, "diagonal storage requested but a row pattern has more than %d offsets", kMaxDiag);
 
   const size_t MN = static_cast<size_t>(M) * N;
   TRY(dalloc(ctx, &ctx->v0, N));
@@ -643,6 +753,7 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i64), (8 + n_inst) * sizeof(int64_t)));
   HIPC(hipStreamSynchronize(ctx->stream));
   ctx->pred.assign(static_cast<size_t>(SDC_MAX_SWEEPS) * M, 8);
+  TRY(autotune(ctx));
   ctx->pin.assign(SDC_MAX_SWEEPS, nullptr);
   ctx->pin_n.assign(SDC_MAX_SWEEPS, 0);
   ctx->ready = true;
@@ -818,6 +929,17 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
   HIPC(hipGetLastError());
   TRY(fetch_map(ctx, &nm));
   *n_out = nm.rows;
+  return SDC_OK;
+}
+
+int sdc_get_info(sdc_ctx* ctx, sdc_info* out) {
+  TRY(check_ready(ctx));
+  if (!out) return fail(ctx, SDC_ERR_ARG, "null output");
+  out->format = ctx->use_dia ? 2 : 1;
+  out->n_diagonals = ctx->nd;
+  out->t_csr_us = ctx->t_csr_us;
+  out->t_dia_us = ctx->t_dia_us;
+  out->redone_steps = ctx->redone_steps;
   return SDC_OK;
 }
 

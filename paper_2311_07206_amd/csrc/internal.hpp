@@ -8,6 +8,7 @@
 namespace sdc {
 
 constexpr int kMaxNodes = 6;
+constexpr int kMaxDiag = 32;   // diagonal storage limit (distinct column offsets per instance)
 
 struct Collocation {
   int M;

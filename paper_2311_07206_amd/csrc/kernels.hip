@@ -56,6 +56,22 @@ __device__ inline Row map_row(const Map& map) {
   return r;
 }
 
+// Visit the stored entries (value, column) of row i of matrix A.
+template <bool DIA, class F>
+__device__ __forceinline__ void for_entries(const Mat& A, int64_t N, int inst, int i, F&& f) {
+  if constexpr (DIA) {
+    const int32_t* off = A.off + inst * A.nd;
+    const int lo = static_cast<int>(A.node_off[inst]), hi = static_cast<int>(A.node_off[inst + 1]);
+    for (int d = 0; d < A.nd; ++d) {
+      const int c = i + off[d];
+      f(A.dval[d * N + i], (c < lo || c >= hi) ? i : c);
+    }
+  } else {
+    const int e1 = A.rowptr[i + 1];
+    for (int e = A.rowptr[i]; e < e1; ++e) f(A.val[e], A.col[e]);
+  }
+}
+
 // Aliev-Panfilov current and gating rate (paper Sec. 5.1).
 __device__ inline void ap_eval(double v, double w, const double* p, double& I, double& R) {
   const double k = p[0], a = p[1], eps0 = p[2], mu1 = p[3], mu2 = p[4], s = p[5];
@@ -109,9 +125,9 @@ __global__ void k_set_values(const int32_t* __restrict__ nodes, int64_t n, doubl
 //   Phi_m = ML_i (v0_i - v_m,i) + dt sum_j Q[m][j] F_j
 //   Gam_m = w0_i - w_m,i + dt sum_j Q[m][j] R_j,i
 // and amax_i = 0 for this sweep's selection.
-template <int M>
+template <int M, bool DIA>
 __global__ __launch_bounds__(kBlock) void k_sweep_start(
-    Map map, int64_t N, Csr A, const double* __restrict__ ml, const double* __restrict__ v0,
+    Map map, int64_t N, Mat A, const double* __restrict__ ml, const double* __restrict__ v0,
     const double* __restrict__ w0, const double* __restrict__ v, const double* __restrict__ w,
     const double* __restrict__ I, const double* __restrict__ R, double* __restrict__ Phi,
     double* __restrict__ Gam, double* __restrict__ amax, CollArgs c) {
@@ -121,13 +137,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
   double Av[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) Av[j] = 0.0;
-  const int e1 = A.rowptr[i + 1];
-  for (int e = A.rowptr[i]; e < e1; ++e) {
-    const int k = A.col[e];
-    const double a = A.val[e];
+  for_entries<DIA>(A, N, rw.inst, i, [&](double a, int k) {
 #pragma unroll
     for (int j = 0; j < M; ++j) Av[j] += a * v[j * N + k];
-  }
+  });
   const double mli = ml[i];
   double F[M], Rj[M];
 #pragma unroll
@@ -152,8 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
 
 // Right-hand side of node m; CG start values x = 0, r = b on active rows:
 //   b_i = Phi_m,i - dt ML_i sum_{j<m} QE[m][j] dI_j,i - dt sum_k A_ik sum_{j<m} QI[m][j] dv_j,k
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Csr A,
+template <int M, bool DIA>
+__global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A,
                                                 const double* __restrict__ ml,
                                                 const double* __restrict__ Phi_m,
                                                 const double* __restrict__ dI,
@@ -164,15 +177,13 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Csr A
   const int i = rw.row;
   double ay = 0.0;
   if (m > 0) {
-    const int e1 = A.rowptr[i + 1];
-    for (int e = A.rowptr[i]; e < e1; ++e) {
-      const int k = A.col[e];
+    for_entries<DIA>(A, N, rw.inst, i, [&](double a, int k) {
       double y = 0.0;
 #pragma unroll
       for (int j = 0; j < M - 1; ++j)
         if (j < m) y += c.QI[m][j] * dv[j * N + k];
-      ay += A.val[e] * y;
-    }
+      ay += a * y;
+    });
   }
   double ex = 0.0;
 #pragma unroll
@@ -247,7 +258,8 @@ __device__ inline void write_partials(double (&v)[NV], double* part, double* sh)
 }
 
 // Start: u0 = dinv r0, w0 = H u0; partials of gamma0 = r0.u0, delta0 = w0.u0, bb = r0.r0.
-__global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, Csr H,
+template <bool DIA>
+__global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_t N, Mat H,
                                                      const double* __restrict__ dinv,
                                                      const double* __restrict__ r0,
                                                      double* __restrict__ w0, double* part_out,
@@ -265,11 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, Csr H,
   if (rw.valid) {
     const int i = rw.row;
     double acc = 0.0;
-    const int e1 = H.rowptr[i + 1];
-    for (int e = H.rowptr[i]; e < e1; ++e) {
-      const int k = H.col[e];
-      acc += H.val[e] * (dinv[k] * r0[k]);
-    }
+    for_entries<DIA>(H, N, rw.inst, i, [&](double h, int k) { acc += h * (dinv[k] * r0[k]); });
     const double ri = r0[i], ui = dinv[i] * ri;
     w0[i] = acc;
     s[0] = ri * ui;
@@ -279,7 +287,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, Csr H,
   write_partials<3>(s, part_out, sh);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, Csr H, const double* __restrict__ dinv,
+template <bool DIA>
+__global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, const double* __restrict__ dinv,
                                                     double* __restrict__ x, double* __restrict__ p,
                                                     const double* __restrict__ r_in,
                                                     const double* __restrict__ w_in,
@@ -329,17 +338,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, Csr H, const double
   if (rw.valid) {
     const int i = rw.row;
     double acc = 0.0;
-    const int e1 = H.rowptr[i + 1];
     if (it == 0) {
-      for (int e = H.rowptr[i]; e < e1; ++e) {
-        const int k = H.col[e];
-        acc += H.val[e] * (dinv[k] * (r_in[k] - alpha * w_in[k]));
-      }
+      for_entries<DIA>(H, N, rw.inst, i, [&](double h, int k) {
+        acc += h * (dinv[k] * (r_in[k] - alpha * w_in[k]));
+      });
     } else {
-      for (int e = H.rowptr[i]; e < e1; ++e) {
-        const int k = H.col[e];
-        acc += H.val[e] * (dinv[k] * (r_in[k] - alpha * (w_in[k] + beta * s_in[k])));
-      }
+      for_entries<DIA>(H, N, rw.inst, i, [&](double h, int k) {
+        acc += h * (dinv[k] * (r_in[k] - alpha * (w_in[k] + beta * s_in[k])));
+      });
     }
     const double di = dinv[i], ri = r_in[i];
     const double ui = di * ri;
@@ -610,23 +616,30 @@ void launch_set_values(hipStream_t s, const int32_t* nodes, int64_t n, double va
   k_set_values<<<dim3(static_cast<unsigned>((n + 255) / 256)), 256, 0, s>>>(nodes, n, value, v);
 }
 
-void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const Csr& A,
+void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const Mat& A,
                         const double* ml, const double* v0, const double* w0, const double* v,
                         const double* w, const double* I, const double* R, double* Phi,
                         double* Gam, double* amax, const CollArgs& c) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    k_sweep_start<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(
-        map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam, amax, c);
+    if (A.nd > 0)
+      k_sweep_start<decltype(mm)::value, true><<<grid(map.nblk), kBlock, 0, s>>>(
+          map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam, amax, c);
+    else
+      k_sweep_start<decltype(mm)::value, false><<<grid(map.nblk), kBlock, 0, s>>>(
+          map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam, amax, c);
   });
 }
 
-void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Csr& A,
+void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Mat& A,
                 const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
                 double* x, const CollArgs& c) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    k_rhs<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c);
+    if (A.nd > 0)
+      k_rhs<decltype(mm)::value, true><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c);
+    else
+      k_rhs<decltype(mm)::value, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c);
   });
 }
 
@@ -635,19 +648,29 @@ void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, do
   k_copy_b<<<grid(map.nblk), kBlock, 0, s>>>(map, b, r, x);
 }
 
-void launch_cg_start(hipStream_t s, const Map& map, int n_inst, const Csr& H, const double* dinv,
-                     const double* r0, double* w0, double* part_out, const CgState& cg) {
-  k_cg_start<<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, H, dinv, r0, w0, part_out, cg);
+void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const Mat& H,
+                     const double* dinv, const double* r0, double* w0, double* part_out,
+                     const CgState& cg) {
+  if (H.nd > 0)
+    k_cg_start<true><<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, N, H, dinv, r0, w0, part_out, cg);
+  else
+    k_cg_start<false><<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, N, H, dinv, r0, w0, part_out, cg);
 }
 
-void launch_cg_iter(hipStream_t s, const Map& map, const Csr& H, const double* dinv, double* x,
-                    double* p, const double* r_in, const double* w_in, const double* s_in,
+void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
+                    double* x, double* p, const double* r_in, const double* w_in, const double* s_in,
                     double* r_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
                     int maxit, const CgState& cg) {
   if (map.nblk <= 0) return;
-  k_cg_iter<<<grid(map.nblk), kBlock, 0, s>>>(map, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out, s_out,
-                                              it, part_in, part_out, scal_in, scal_out, rtol2, maxit, cg);
+  if (H.nd > 0)
+    k_cg_iter<true><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out,
+                                                      s_out, it, part_in, part_out, scal_in, scal_out,
+                                                      rtol2, maxit, cg);
+  else
+    k_cg_iter<false><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out,
+                                                       s_out, it, part_in, part_out, scal_in, scal_out,
+                                                       rtol2, maxit, cg);
 }
 
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
@@ -710,6 +733,29 @@ void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32
                     const double* A, const double* ml, double c, double* H, double* dinv) {
   k_build_h<<<dim3(static_cast<unsigned>((N + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
       N, rowptr, diagpos, A, ml, c, H, dinv);
+}
+
+namespace {
+// Diagonal storage of H_m = ML + c A for the rows [lo, hi) of one instance:
+// the entry with offset 0 (index dg) carries the mass.
+__global__ __launch_bounds__(kBlock) void k_build_h_dia(int64_t N, int lo, int hi, int nd, int dg,
+                                                        const double* __restrict__ A,
+                                                        const double* __restrict__ ml, double c,
+                                                        double* __restrict__ H) {
+  const int i = lo + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+  if (i >= hi) return;
+  for (int d = 0; d < nd; ++d) {
+    const int64_t q = d * N + i;
+    H[q] = (d == dg) ? ml[i] + c * A[q] : c * A[q];
+  }
+}
+}  // namespace
+
+void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int nd, int dg, const double* A,
+                        const double* ml, double c, double* H) {
+  if (hi <= lo) return;
+  k_build_h_dia<<<dim3(static_cast<unsigned>((hi - lo + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
+      N, lo, hi, nd, dg, A, ml, c, H);
 }
 
 void launch_iota(hipStream_t s, int32_t* out, int64_t n) {

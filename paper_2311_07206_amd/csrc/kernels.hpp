@@ -37,6 +37,20 @@ struct Csr {
   const double* val;
 };
 
+// A matrix on the assembly pattern, stored either as CSR (nd == 0) or in
+// diagonal storage: for instance i, entry d of row r lies in column
+// r + off[i*nd + d] with value dval[d*N + r]; entries absent from the pattern
+// hold 0, and a column outside the instance is replaced by r itself.
+struct Mat {
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const int32_t* off;
+  const double* dval;
+  const int64_t* node_off;
+  int nd;
+};
+
 // Per-instance CG scalars, layout [n_inst][kScal].
 enum { kRZ = 0, kBB, kAlpha, kBeta, kScal = 8 };   // kRZ holds gamma = r.z
 
@@ -48,12 +62,12 @@ struct CgState {
 void launch_spread(hipStream_t s, int M, const Map& all, int64_t N, const double* ionic,
                    const double* v0, const double* w0, double* v, double* w, double* I, double* R);
 void launch_set_values(hipStream_t s, const int32_t* nodes, int64_t n, double value, double* v);
-void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const Csr& A,
+void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const Mat& A,
                         const double* ml, const double* v0, const double* w0, const double* v,
                         const double* w, const double* I, const double* R, double* Phi,
                         double* Gam, double* amax, const CollArgs& c);
 // Right-hand side of node m; writes r = b and x = 0 on active rows.
-void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Csr& A,
+void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Mat& A,
                 const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
                 double* x, const CollArgs& c);
 void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, double* x);
@@ -62,10 +76,11 @@ void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, do
 // Launch `it` reads the partial sums and scalars of launch it-1 (part_in,
 // scal_in) and writes its own (part_out, scal_out); the start kernel's
 // partials are the input of launch 0.
-void launch_cg_start(hipStream_t s, const Map& map, int n_inst, const Csr& H, const double* dinv,
-                     const double* r0, double* w0, double* part_out, const CgState& cg);
-void launch_cg_iter(hipStream_t s, const Map& map, const Csr& H, const double* dinv, double* x,
-                    double* p, const double* r_in, const double* w_in, const double* s_in,
+void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const Mat& H,
+                     const double* dinv, const double* r0, double* w0, double* part_out,
+                     const CgState& cg);
+void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
+                    double* x, double* p, const double* r_in, const double* w_in, const double* s_in,
                     double* r_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
                     int maxit, const CgState& cg);
@@ -111,5 +126,8 @@ void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t 
 void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32_t* diagpos,
                     const double* A, const double* ml, double c, double* H, double* dinv);
 void launch_iota(hipStream_t s, int32_t* out, int64_t n);
+// Diagonal storage of H_m for the rows [lo, hi) of one instance (dg = index of offset 0).
+void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int nd, int dg, const double* A,
+                        const double* ml, double c, double* H);
 
 }  // namespace sdc

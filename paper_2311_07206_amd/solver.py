@@ -42,7 +42,7 @@ class Solver:
     """One library context: an assembled mesh (possibly several instances)."""
 
     def __init__(self, coords, elems, elem_tensor, node_sigma, ionic, node_off, elem_off,
-                 M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, device=None, stream=None):
+                 M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None):
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         if stream is None:
@@ -57,7 +57,7 @@ class Solver:
         dim = coords.shape[1]
         self.M, self.K = int(M), int(K)
         prm = Params(M=self.M, K=self.K, dt=float(dt), theta=float(theta), cg_rtol=float(cg_rtol),
-                     cg_maxit=int(cg_maxit), reserved=0)
+                     cg_maxit=int(cg_maxit), format=int(fmt))
         node_off_a, p_no = _host(node_off, np.int64)
         coords_a, p_c = _host(coords, np.float64)
         elem_off_a, p_eo = _host(elem_off, np.int64)
@@ -167,6 +167,13 @@ class Solver:
         self._check(self.lib.sdc_solve(self.ctx, int(m), self._vec(idx, torch.int32), idx.numel(),
                                        self._vec(b, n=self.N), _ptr(x), iters))
         return x, list(iters)
+
+    def info(self):
+        """Storage in use ('csr' or 'dia'), diagonals, setup timings, redone steps."""
+        st = _lib.Info()
+        self._check(self.lib.sdc_get_info(self.ctx, ctypes.byref(st)))
+        return {"format": {1: "csr", 2: "dia"}[st.format], "n_diagonals": st.n_diagonals,
+                "t_csr_us": st.t_csr_us, "t_dia_us": st.t_dia_us, "redone_steps": st.redone_steps}
 
     def profile(self, enable):
         """Start (and clear) or stop event timing of the CG kernels."""

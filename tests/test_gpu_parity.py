@@ -290,6 +290,23 @@ def test_errors_are_reported():
         s2.sweep()
 
 
+@pytest.mark.parametrize("P", [config1(n=33, theta=1e-7, n_steps=6), config2(n=8, theta=1e-7, n_steps=4),
+                               config4(n_inst=3, sizes=(12, 20), n_steps=5)], ids=["2d", "3d", "batch"])
+def test_diagonal_and_csr_storage_agree_bitwise(P):
+    runs = []
+    for fmt in (1, 2):
+        s = _solver(P, fmt=fmt)
+        assert s.info()["format"] == {1: "csr", 2: "dia"}[fmt]
+        v = torch.tensor(P.v_init, device=DEV)
+        w = torch.tensor(P.w_init, device=DEV)
+        for n in range(P.n_steps):
+            s.step(v, w, n * P.dt)
+        runs.append((v.cpu().numpy(), w.cpu().numpy()))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli)
+    assert rel(runs[1][0], ov) < 1e-8   # free-running sets: flips near theta perturb by ~theta
+
+
 def test_invalid_index_lists_are_rejected():
     from paper_2311_07206_amd import SDCError
     P = config0(n=60)
