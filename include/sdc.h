@@ -152,6 +152,26 @@ int sdc_get_active(sdc_ctx* ctx, int32_t* idx, int64_t* n);
  * device int32[n] ascending list (copied).  sweep < 0 clears every pin. */
 int sdc_set_active(sdc_ctx* ctx, int32_t sweep, const int32_t* idx, int64_t n);
 
+/* Reverse-mode step (adjoint of sdc_step with every sweep's active set held
+ * fixed and each restricted solve taken as exact): recomputes the step from
+ * (v_n, w_n) at time t (device double[N] each, unchanged), then, given the
+ * adjoints lam_v, lam_w of (v, w) at t + dt (device double[N], in), writes the
+ * adjoints of (v_n, w_n) over them (out; zero on nodes a stimulus overwrote
+ * at this step) and ADDS the derivatives of the same scalar with respect to
+ * the nodal conductivity multipliers to g_sigma (device double[N]) and with
+ * respect to each instance's Aliev-Panfilov parameter a to g_a (device
+ * double[n_inst]).  The reverse solves use the forward's Jacobi-PCG on the
+ * same (symmetric) restricted matrices.  Uses about (2K + 4) M N + K N extra
+ * doubles of device memory, allocated on the first call. */
+int sdc_adjoint_step(sdc_ctx* ctx, const double* v_n, const double* w_n, double t, double* lam_v,
+                     double* lam_w, double* g_sigma, double* g_a);
+
+/* Replace the nodal conductivity multipliers (host double[N], or NULL to keep)
+ * and the Aliev-Panfilov parameters (host double[n_inst][6], or NULL): A is
+ * reassembled on the same pattern (paper Sec. 2.2) and the node matrices,
+ * Jacobi diagonals and diagonal storage are rebuilt. */
+int sdc_set_coefficients(sdc_ctx* ctx, const double* node_sigma, const double* ionic);
+
 /* ---- components (for kernel-level parity tests) ----------------------- */
 
 /* Restricted Jacobi-PCG (paper Sec. 4.2) on H_m = ML + dt*QI[m][m]*A:

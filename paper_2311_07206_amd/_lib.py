@@ -78,6 +78,8 @@ SIGNATURES = {
     "sdc_collocation": (c_int32, [c_int32, PTR, PTR, PTR, PTR]),
     "sdc_profile": (c_int32, [c_void_p, c_int32]),
     "sdc_get_info": (c_int32, [c_void_p, POINTER(Info)]),
+    "sdc_adjoint_step": (c_int32, [c_void_p, PTR, PTR, c_double, PTR, PTR, PTR, PTR]),
+    "sdc_set_coefficients": (c_int32, [c_void_p, PTR, PTR]),
     "sdc_profile_read": (c_int32, [c_void_p, POINTER(ProfileStats)]),
 }
 

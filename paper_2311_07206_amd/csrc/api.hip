@@ -20,121 +20,13 @@
 #include <string>
 #include <vector>
 
+#include "context.hpp"
 #include "internal.hpp"
 #include "kernels.hpp"
 
 using namespace sdc;
 
-namespace {
-
-struct MapBuf {
-  int4* blk = nullptr;
-  int32_t* inst_blk0 = nullptr;
-  int32_t* inst_nblk = nullptr;
-  int32_t* inst_cnt = nullptr;
-  int64_t* inst_nnz = nullptr;
-  int32_t* aoff = nullptr;
-  int32_t* totals = nullptr;
-  const int32_t* idx = nullptr;       // list the map indexes (null: all rows)
-  // host mirror, valid after the map is built
-  int32_t nblk = 0;
-  int64_t rows = 0;
-  std::vector<int32_t> cnt;
-  std::vector<int64_t> nnz;
-
-  Map dev() const { return Map{blk, inst_blk0, inst_nblk, idx, nblk}; }
-  NextMap next() const { return NextMap{blk, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals}; }
-};
-
-struct Stimulus {
-  double t_on;
-  int32_t* nodes;
-  int64_t n;
-  double value;
-};
-
-}  // namespace
-
-struct sdc_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  std::vector<void*> allocs;
-
-  bool ready = false;
-  sdc_params prm{};
-  Collocation col{};
-  CollArgs cargs{};
-  int dim = 0;
-  int64_t N = 0, nnz = 0;
-  int n_inst = 0;
-  std::vector<int64_t> node_off_h;
-  HostSystem host;   // kept for sdc_get_system
-
-  int32_t *rowptr = nullptr, *colidx = nullptr, *diagpos = nullptr;
-  double *Aval = nullptr, *Hval = nullptr, *ml = nullptr, *dinv = nullptr;
-  // diagonal storage (nd > 0 when every instance has at most kMaxDiag offsets)
-  int nd = 0;
-  int32_t* dia_off = nullptr;      // [n_inst][nd]
-  double *dia_A = nullptr, *dia_H = nullptr;   // [nd][N], [M][nd][N]
-  bool use_dia = false;
-  double t_csr_us = 0.0, t_dia_us = 0.0;
-  int64_t* node_off_d = nullptr;
-  double* ionic_d = nullptr;
-
-  double *v0 = nullptr, *w0 = nullptr, *v = nullptr, *w = nullptr, *I = nullptr, *R = nullptr;
-  double *Phi = nullptr, *Gam = nullptr, *dv = nullptr, *dI = nullptr, *dR = nullptr;
-  double* amax = nullptr;
-  // CG vectors: p and the iterate (dv[m]) are read on own rows only; r, w, s
-  // are double-buffered because the SpMV reads them at neighbouring columns
-  double* p = nullptr;
-  double *r[2] = {nullptr, nullptr}, *wv[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
-
-  double* cg_scal[2] = {nullptr, nullptr};   // [n_inst][kScal] by launch parity
-  double* part[2] = {nullptr, nullptr};      // [nblk][4] by launch parity
-  int32_t *cg_done = nullptr, *cg_iters = nullptr;
-  int32_t *sel_cnt = nullptr, *sel_nnz = nullptr;
-
-  MapBuf all;
-  MapBuf dyn[2];
-  int32_t* list[2] = {nullptr, nullptr};
-  int cur = -1;   // -1: all rows; 0/1: dyn slot
-
-  int32_t* h_i32 = nullptr;   // pinned staging
-  int64_t* h_i64 = nullptr;
-
-  std::vector<Stimulus> stims;
-  std::vector<int32_t*> pin;
-  std::vector<int64_t> pin_n;
-
-  bool in_step = false;
-  int k = 0;
-  // per-node CG outcome of the current sweep, snapshot on the device (async steps)
-  int32_t* hist_done = nullptr;    // [M][n_inst]
-  int32_t* hist_iters = nullptr;   // [M][n_inst]
-  int64_t redone_steps = 0;
-
-  // kernel timing (bench only)
-  bool prof = false;
-  std::vector<hipEvent_t> ev;   // 2 per CG iteration launch
-  sdc_profile_stats pst{};
-  std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
-
-  const MapBuf& curmap() const { return cur < 0 ? all : dyn[cur]; }
-  CgState cg() const { return CgState{cg_done, cg_iters}; }
-  Mat matA(bool dia) const {
-    return Mat{rowptr, colidx, Aval, dia_off, dia_A, node_off_d, dia ? nd : 0};
-  }
-  Mat matH(int m, bool dia) const {
-    return Mat{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz, dia_off,
-               dia_H ? dia_H + static_cast<int64_t>(m) * nd * N : nullptr, node_off_d, dia ? nd : 0};
-  }
-  Mat A() const { return matA(use_dia); }
-  Mat H(int m) const { return matH(m, use_dia); }
-  ZeroVecs zv() const { return ZeroVecs{{r[0], r[1], wv[0], wv[1], s[0], s[1]}, dv, prm.M, N}; }
-};
-
-namespace {
+namespace sdc {
 
 int fail(sdc_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -145,32 +37,6 @@ int fail(sdc_ctx* c, int code, const char* fmt, ...) {
   c->err = buf;
   return code;
 }
-
-#define HIPC(call)                                                                      \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(ctx, SDC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
-  } while (0)
-
-template <class T>
-int dalloc(sdc_ctx* ctx, T** out, size_t count) {
-  void* ptr = nullptr;
-  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  hipError_t e = hipMalloc(&ptr, bytes);
-  if (e != hipSuccess) return fail(ctx, SDC_ERR_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
-  e = hipMemsetAsync(ptr, 0, bytes, ctx->stream);
-  if (e != hipSuccess) return fail(ctx, SDC_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
-  ctx->allocs.push_back(ptr);
-  *out = static_cast<T*>(ptr);
-  return SDC_OK;
-}
-
-#define TRY(x)              \
-  do {                      \
-    int rc_ = (x);          \
-    if (rc_ != SDC_OK) return rc_; \
-  } while (0)
 
 int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap) {
   const int ni = ctx->n_inst;
@@ -340,8 +206,8 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
 
 // One sweep over the current active set; afterwards the current set is the
 // one the next sweep uses (pinned, selected, or unchanged).
-int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async = false,
-             bool* short_budget = nullptr) {
+int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
+             bool* short_budget) {
   const int M = ctx->prm.M;
   const int ni = ctx->n_inst;
   const int64_t N = ctx->N;
@@ -382,6 +248,9 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async = f
     HIPC(hipMemcpyAsync(ctx->h_i32 + 8 + 2 * ni + M * ni, ctx->hist_iters, M * ni * 4, hipMemcpyDeviceToHost,
                         ctx->stream));
   }
+  if (ctx->record_dv)   // the selection below zeroes dv on the rows it drops
+    HIPC(hipMemcpyAsync(ctx->record_dv, ctx->dv, static_cast<size_t>(M) * N * 8, hipMemcpyDeviceToDevice,
+                        ctx->stream));
   const int next = ctx->k + 1;
   bool synced = false;
   if (next < static_cast<int>(ctx->pin.size()) && ctx->pin[next]) {
@@ -487,9 +356,11 @@ int build_dia(sdc_ctx* ctx) {
         val[static_cast<size_t>(q) * N + r] = hs.val[e];
       }
   const int M = ctx->prm.M;
-  TRY(dalloc(ctx, &ctx->dia_off, off.size()));
-  TRY(dalloc(ctx, &ctx->dia_A, val.size()));
-  TRY(dalloc(ctx, &ctx->dia_H, val.size() * M));
+  if (!ctx->dia_off) {
+    TRY(dalloc(ctx, &ctx->dia_off, off.size()));
+    TRY(dalloc(ctx, &ctx->dia_A, val.size()));
+    TRY(dalloc(ctx, &ctx->dia_H, val.size() * M));
+  }
   HIPC(hipMemcpyAsync(ctx->dia_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(ctx->dia_A, val.data(), val.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   for (int m = 0; m < M; ++m)
@@ -557,7 +428,7 @@ int check_ready(sdc_ctx* ctx) {
   return SDC_OK;
 }
 
-}  // namespace
+}  // namespace sdc
 
 // ---------------------------------------------------------------- ABI
 
@@ -752,7 +623,11 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   TRY(dalloc(ctx, &ctx->hist_iters, static_cast<size_t>(M) * n_inst));
   HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i64), (8 + n_inst) * sizeof(int64_t)));
   HIPC(hipStreamSynchronize(ctx->stream));
-  ctx->pred.assign(static_cast<size_t>(SDC_MAX_SWEEPS) * M, 8);
+  ctx->pred.assign(2 * static_cast<size_t>(SDC_MAX_SWEEPS) * M, 8);   // forward and reverse solves
+  ctx->coords_h.assign(coords, coords + N * dim);
+  ctx->elems_h.assign(elems, elems + E * nv);
+  ctx->tensor_h.assign(elem_tensor, elem_tensor + E * dim * dim);
+  ctx->n_elem = E;
   TRY(autotune(ctx));
   ctx->pin.assign(SDC_MAX_SWEEPS, nullptr);
   ctx->pin_n.assign(SDC_MAX_SWEEPS, 0);
@@ -929,6 +804,31 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
   HIPC(hipGetLastError());
   TRY(fetch_map(ctx, &nm));
   *n_out = nm.rows;
+  return SDC_OK;
+}
+
+int sdc_set_coefficients(sdc_ctx* ctx, const double* node_sigma, const double* ionic) {
+  TRY(check_ready(ctx));
+  ctx->in_step = false;
+  if (ionic)
+    HIPC(hipMemcpyAsync(ctx->ionic_d, ionic, 6 * ctx->n_inst * 8, hipMemcpyHostToDevice, ctx->stream));
+  if (node_sigma) {
+    HostSystem hs;
+    std::string e = assemble_p1(ctx->dim, ctx->N, ctx->coords_h.data(), ctx->n_elem, ctx->elems_h.data(),
+                                ctx->tensor_h.data(), node_sigma, &hs);
+    if (!e.empty()) return fail(ctx, SDC_ERR_ARG, "assembly: %s", e.c_str());
+    if (hs.col != ctx->host.col) return fail(ctx, SDC_ERR_STATE, "pattern changed");
+    ctx->host.val.swap(hs.val);
+    const int64_t N = ctx->N, nnz = ctx->nnz;
+    const int M = ctx->prm.M;
+    HIPC(hipMemcpyAsync(ctx->Aval, ctx->host.val.data(), nnz * 8, hipMemcpyHostToDevice, ctx->stream));
+    for (int m = 0; m < M; ++m)
+      launch_build_h(ctx->stream, N, ctx->rowptr, ctx->diagpos, ctx->Aval, ctx->ml,
+                     ctx->prm.dt * ctx->col.QI[m][m], ctx->Hval + m * nnz, ctx->dinv + m * N);
+    HIPC(hipGetLastError());
+    if (ctx->nd > 0) TRY(build_dia(ctx));
+  }
+  HIPC(hipStreamSynchronize(ctx->stream));
   return SDC_OK;
 }
 

@@ -191,4 +191,37 @@ std::string assemble_p1(int dim, int64_t n, const double* coords, int64_t ne,
   return err;
 }
 
+std::string element_pairs(int dim, const double* coords, int64_t ne, const int32_t* elems,
+                          const double* elem_tensor, std::vector<double>* w) {
+  const int nv = dim + 1, np = nv * dim / 2;
+  w->assign(static_cast<size_t>(ne) * np, 0.0);
+  std::string err;
+  std::vector<std::string> terr(16);
+  parallel_ranges(ne, [&](int t, int64_t lo, int64_t hi) {
+    double X[4 * 3];
+    Geo geo;
+    for (int64_t e = lo; e < hi; ++e) {
+      const int32_t* ev = elems + e * nv;
+      for (int a = 0; a < nv; ++a)
+        for (int c = 0; c < dim; ++c) X[a * dim + c] = coords[int64_t(ev[a]) * dim + c];
+      if (!geometry(dim, X, &geo)) {
+        terr[t] = "degenerate element";
+        return;
+      }
+      const double* D = elem_tensor + e * dim * dim;
+      int q = 0;
+      for (int a = 0; a < nv; ++a)
+        for (int b = a + 1; b < nv; ++b, ++q) {
+          double kab = 0.0;
+          for (int r = 0; r < dim; ++r)
+            for (int c = 0; c < dim; ++c) kab += geo.g[a][r] * D[r * dim + c] * geo.g[b][c];
+          (*w)[static_cast<size_t>(e) * np + q] = geo.vol * kab;
+        }
+    }
+  });
+  for (auto& s : terr)
+    if (!s.empty()) return s;
+  return err;
+}
+
 }  // namespace sdc

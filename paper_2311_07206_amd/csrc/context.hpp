@@ -1,0 +1,194 @@
+// Library context and host-side helpers shared by the forward (api.hip) and
+// reverse (adjoint.hip) orchestration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "sdc.h"
+
+namespace sdc {
+
+struct MapBuf {
+  int4* blk = nullptr;
+  int32_t* inst_blk0 = nullptr;
+  int32_t* inst_nblk = nullptr;
+  int32_t* inst_cnt = nullptr;
+  int64_t* inst_nnz = nullptr;
+  int32_t* aoff = nullptr;
+  int32_t* totals = nullptr;
+  const int32_t* idx = nullptr;       // list the map indexes (null: all rows)
+  // host mirror, valid after the map is built
+  int32_t nblk = 0;
+  int64_t rows = 0;
+  std::vector<int32_t> cnt;
+  std::vector<int64_t> nnz;
+
+  Map dev() const { return Map{blk, inst_blk0, inst_nblk, idx, nblk}; }
+  NextMap next() const { return NextMap{blk, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals}; }
+};
+
+struct Stimulus {
+  double t_on;
+  int32_t* nodes;
+  int64_t n;
+  double value;
+};
+
+}  // namespace sdc
+
+using sdc::Collocation;
+using sdc::CollArgs;
+using sdc::HostSystem;
+using sdc::MapBuf;
+using sdc::Stimulus;
+using sdc::CgState;
+using sdc::Mat;
+using sdc::ZeroVecs;
+using sdc::kScal;
+
+struct sdc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<void*> allocs;
+
+  bool ready = false;
+  sdc_params prm{};
+  Collocation col{};
+  CollArgs cargs{};
+  int dim = 0;
+  int64_t N = 0, nnz = 0;
+  int n_inst = 0;
+  std::vector<int64_t> node_off_h;
+  HostSystem host;   // kept for sdc_get_system
+
+  int32_t *rowptr = nullptr, *colidx = nullptr, *diagpos = nullptr;
+  double *Aval = nullptr, *Hval = nullptr, *ml = nullptr, *dinv = nullptr;
+  // diagonal storage (nd > 0 when every instance has at most kMaxDiag offsets)
+  int nd = 0;
+  int32_t* dia_off = nullptr;      // [n_inst][nd]
+  double *dia_A = nullptr, *dia_H = nullptr;   // [nd][N], [M][nd][N]
+  bool use_dia = false;
+  double t_csr_us = 0.0, t_dia_us = 0.0;
+  int64_t* node_off_d = nullptr;
+  double* ionic_d = nullptr;
+
+  double *v0 = nullptr, *w0 = nullptr, *v = nullptr, *w = nullptr, *I = nullptr, *R = nullptr;
+  double *Phi = nullptr, *Gam = nullptr, *dv = nullptr, *dI = nullptr, *dR = nullptr;
+  double* amax = nullptr;
+  // CG vectors: p and the iterate (dv[m]) are read on own rows only; r, w, s
+  // are double-buffered because the SpMV reads them at neighbouring columns
+  double* p = nullptr;
+  double *r[2] = {nullptr, nullptr}, *wv[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
+
+  double* cg_scal[2] = {nullptr, nullptr};   // [n_inst][kScal] by launch parity
+  double* part[2] = {nullptr, nullptr};      // [nblk][4] by launch parity
+  int32_t *cg_done = nullptr, *cg_iters = nullptr;
+  int32_t *sel_cnt = nullptr, *sel_nnz = nullptr;
+
+  MapBuf all;
+  MapBuf dyn[2];
+  int32_t* list[2] = {nullptr, nullptr};
+  int cur = -1;   // -1: all rows; 0/1: dyn slot
+
+  int32_t* h_i32 = nullptr;   // pinned staging
+  int64_t* h_i64 = nullptr;
+
+  std::vector<Stimulus> stims;
+  std::vector<int32_t*> pin;
+  std::vector<int64_t> pin_n;
+
+  // host copy of the mesh (element data of the reverse step)
+  std::vector<double> coords_h, tensor_h;
+  std::vector<int32_t> elems_h;
+  int64_t n_elem = 0;
+
+  // reverse-step storage, allocated on first use
+  struct Adjoint {
+    bool ready = false;
+    int32_t *elems = nullptr, *nptr = nullptr, *nel = nullptr;
+    double* pairw = nullptr;
+    double *rec_v = nullptr, *rec_w = nullptr, *rec_dv = nullptr;   // [K+1][M][N], [K][M][N]
+    int32_t* rec_list = nullptr;                                    // [K][N]
+    std::vector<int64_t> rec_n;                                     // -1: all rows
+    double *Lv = nullptr, *Lw = nullptr, *Ldv = nullptr, *Ldw = nullptr;
+    double *Lv0 = nullptr, *Lw0 = nullptr, *psi = nullptr, *u = nullptr, *ga_row = nullptr, *qe = nullptr;
+    uint8_t* in_set = nullptr;
+  } adj;
+
+  bool in_step = false;
+  int k = 0;
+  double* record_dv = nullptr;   // when set, a sweep copies its corrections here before the selection
+  // per-node CG outcome of the current sweep, snapshot on the device (async steps)
+  int32_t* hist_done = nullptr;    // [M][n_inst]
+  int32_t* hist_iters = nullptr;   // [M][n_inst]
+  int64_t redone_steps = 0;
+
+  // kernel timing (bench only)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;   // 2 per CG iteration launch
+  sdc_profile_stats pst{};
+  std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
+
+  const MapBuf& curmap() const { return cur < 0 ? all : dyn[cur]; }
+  CgState cg() const { return CgState{cg_done, cg_iters}; }
+  Mat matA(bool dia) const {
+    return Mat{rowptr, colidx, Aval, dia_off, dia_A, node_off_d, dia ? nd : 0};
+  }
+  Mat matH(int m, bool dia) const {
+    return Mat{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz, dia_off,
+               dia_H ? dia_H + static_cast<int64_t>(m) * nd * N : nullptr, node_off_d, dia ? nd : 0};
+  }
+  Mat A() const { return matA(use_dia); }
+  Mat H(int m) const { return matH(m, use_dia); }
+  ZeroVecs zv() const { return ZeroVecs{{r[0], r[1], wv[0], wv[1], s[0], s[1]}, dv, prm.M, N}; }
+};
+
+
+namespace sdc {
+
+int fail(sdc_ctx* c, int code, const char* fmt, ...);
+
+#define HIPC(call)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return ::sdc::fail(ctx, SDC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(x)                     \
+  do {                             \
+    int rc_ = (x);                 \
+    if (rc_ != SDC_OK) return rc_; \
+  } while (0)
+
+template <class T>
+int dalloc(sdc_ctx* ctx, T** out, size_t count) {
+  void* ptr = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) return fail(ctx, SDC_ERR_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  e = hipMemsetAsync(ptr, 0, bytes, ctx->stream);
+  if (e != hipSuccess) return fail(ctx, SDC_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+  ctx->allocs.push_back(ptr);
+  *out = static_cast<T*>(ptr);
+  return SDC_OK;
+}
+
+int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap);
+int fetch_map(sdc_ctx* ctx, MapBuf* mb);
+int map_list(sdc_ctx* ctx, int slot, const int32_t* idx, int64_t n);
+int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std::vector<int>* iters);
+int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async = false,
+             bool* short_budget = nullptr);
+int restart_step(sdc_ctx* ctx);
+int check_ready(sdc_ctx* ctx);
+
+}  // namespace sdc

@@ -36,4 +36,10 @@ std::string assemble_p1(int dim, int64_t n_nodes, const double* coords, int64_t 
                         const int32_t* elems, const double* elem_tensor,
                         const double* node_sigma, HostSystem* out);
 
+// Off-diagonal entries Khat_T[a][b], a < b (lexicographic pairs), of every
+// element's unit-conductivity stiffness |T| g_a . D_T g_b.  Because the rows
+// of Khat_T sum to zero, psi^T Khat_T u = -sum_{a<b} Khat_ab (psi_a - psi_b)(u_a - u_b).
+std::string element_pairs(int dim, const double* coords, int64_t ne, const int32_t* elems,
+                          const double* elem_tensor, std::vector<double>* w);
+
 }  // namespace sdc

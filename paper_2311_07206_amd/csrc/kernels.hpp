@@ -130,4 +130,25 @@ void launch_iota(hipStream_t s, int32_t* out, int64_t n);
 void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int nd, int dg, const double* A,
                         const double* ml, double c, double* H);
 
+// ---- reverse (adjoint) step; see adjoint_kernels.hip for the equations
+void launch_adj_sweep_init(hipStream_t s, int M, const Map& map, int64_t N, const double* Lv,
+                           const double* Lw, double* Ldv, double* Ldw);
+void launch_adj_dw(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
+                   const double* V, const double* W, const double* Ve, const double* We, double* Lv,
+                   double* Lw, double* Ldv, double* Ldw, double* Lw0, double* ga_row, const CollArgs& c);
+void launch_adj_apsi(hipStream_t s, int M, int m, const Map& all, int64_t N, const Mat& A,
+                     const double* ml, const double* ionic, const uint8_t* in_set, const double* psi,
+                     const double* V, const double* W, const double* Ve, const double* We,
+                     const double* DV, double* Lv, double* Lw, double* Ldv, double* Ldw, double* Lv0,
+                     double* ga_row, double* u, const CollArgs& c);
+void launch_adj_elem(hipStream_t s, int nv, int64_t ne, const int32_t* elems, const double* pairw,
+                     const double* psi, const double* u, double* qe);
+void launch_adj_spread(hipStream_t s, int M, int64_t N, const double* Lv, const double* Lw, double* Lv0,
+                       double* Lw0);
+void launch_adj_gather_sigma(hipStream_t s, int64_t N, int nv, const int32_t* nptr, const int32_t* nel,
+                             const double* qe, double* g);
+void launch_adj_reduce_a(hipStream_t s, int n_inst, const int64_t* node_off, const double* ga_row, double* g_a);
+void launch_set_flags(hipStream_t s, const Map& map, uint8_t* flags, uint8_t value);
+void launch_zero_values(hipStream_t s, const int32_t* nodes, int64_t n, double* v);
+
 }  // namespace sdc

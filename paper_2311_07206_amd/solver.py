@@ -72,6 +72,7 @@ class Solver:
         self.N, self.nnz, self.Nw = n.value, nnz.value, nw.value
         self.n_inst = len(node_off_a) - 1
         self.dt = float(dt)
+        self.ionic = ion_a.copy()
 
     @classmethod
     def from_problem(cls, P, **kw):
@@ -167,6 +168,27 @@ class Solver:
         self._check(self.lib.sdc_solve(self.ctx, int(m), self._vec(idx, torch.int32), idx.numel(),
                                        self._vec(b, n=self.N), _ptr(x), iters))
         return x, list(iters)
+
+    def adjoint_step(self, v_n, w_n, t, lam_v, lam_w, g_sigma, g_a):
+        """Reverse of step(v_n, w_n, t): lam_v, lam_w updated in place to the
+        adjoints of (v_n, w_n); the sensitivities are added to g_sigma [N]
+        and g_a [n_inst]."""
+        self._check(self.lib.sdc_adjoint_step(
+            self.ctx, self._vec(v_n, n=self.N), self._vec(w_n, n=self.Nw), float(t), self._vec(lam_v, n=self.N),
+            self._vec(lam_w, n=self.Nw), self._vec(g_sigma, n=self.N), self._vec(g_a, n=self.n_inst)))
+
+    def set_coefficients(self, node_sigma=None, ionic=None):
+        """Reassemble with new nodal conductivity multipliers and/or ionic parameters (host arrays)."""
+        ps = pi = None
+        if node_sigma is not None:
+            s_a, ps = _host(node_sigma, np.float64)
+            assert s_a.size == self.N
+        if ionic is not None:
+            i_a, pi = _host(np.atleast_2d(ionic), np.float64)
+            assert i_a.shape == (self.n_inst, 6)
+        self._check(self.lib.sdc_set_coefficients(self.ctx, ps, pi))
+        if ionic is not None:
+            self.ionic = i_a.copy()
 
     def info(self):
         """Storage in use ('csr' or 'dia'), diagonals, setup timings, redone steps."""
