@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calib", action="store_true",
+                    help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
 
 
@@ -87,6 +89,13 @@ def main():
 
     P = config1(n=args.n, theta=1e-7)
     dev = torch.device("cuda", 0)
+    if args.calib:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s = Solver.from_problem(P)
     v = torch.tensor(P.v_init, device=dev)
     w = torch.tensor(P.w_init, device=dev)
