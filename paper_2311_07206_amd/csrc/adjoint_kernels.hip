@@ -26,8 +26,15 @@ struct Row {
   bool valid;
 };
 
+// Same XCD-aware order of map entries as the forward kernels.
+__device__ inline int logical_block(int nblk) {
+  const int b = static_cast<int>(blockIdx.x);
+  const int x = b & 7, q = nblk >> 3, rem = nblk & 7;
+  return x * q + min(x, rem) + (b >> 3);
+}
+
 __device__ inline Row map_row(const Map& map) {
-  const int4 bm = map.blk[blockIdx.x];
+  const int4 bm = map.blk[logical_block(map.nblk)];
   const int pos = bm.y + static_cast<int>(threadIdx.x);
   Row r;
   r.inst = bm.x;

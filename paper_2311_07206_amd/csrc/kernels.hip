@@ -40,35 +40,67 @@ __device__ inline void block_sum(double (&v)[NV], double* sh /* [4 * NV] */) {
   }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8).  Give each XCD a contiguous range of map entries instead, so that
+// neighbouring row blocks, which read each other's rows through the stencil,
+// share one L2.  A bijection of [0, nblk) when the grid has nblk workgroups.
+__device__ inline int logical_block(int nblk) {
+  const int b = static_cast<int>(blockIdx.x);
+  const int x = b & 7, q = nblk >> 3, rem = nblk & 7;
+  return x * q + min(x, rem) + (b >> 3);
+}
+
 struct Row {
   int inst;
   int row;
+  int blk;     // logical block: position of this block's entry in the work map
   bool valid;
 };
 
 __device__ inline Row map_row(const Map& map) {
-  const int4 bm = map.blk[blockIdx.x];
+  const int L = logical_block(map.nblk);
+  const int4 bm = map.blk[L];
   const int pos = bm.y + static_cast<int>(threadIdx.x);
   Row r;
   r.inst = bm.x;
+  r.blk = L;
   r.valid = pos < bm.z;
   r.row = r.valid ? (map.idx ? map.idx[pos] : pos) : 0;
   return r;
 }
 
-// Visit the stored entries (value, column) of row i of matrix A.
-template <bool DIA, class F>
+// Visit the stored entries (value, column) of row i of matrix A.  Storage S:
+// 0 = CSR, -1 = diagonal storage with A.nd diagonals, S > 0 = diagonal
+// storage with S diagonals known at compile time (fully unrolled, so all
+// loads of the row are in flight together).
+template <int S, class F>
 __device__ __forceinline__ void for_entries(const Mat& A, int64_t N, int inst, int i, F&& f) {
-  if constexpr (DIA) {
-    const int32_t* off = A.off + inst * A.nd;
+  if constexpr (S == 0) {
+    const int e1 = A.rowptr[i + 1];
+    for (int e = A.rowptr[i]; e < e1; ++e) f(A.val[e], A.col[e]);
+  } else {
+    constexpr int kUnroll = S > 0 ? S : 1;
+    const int nd = S > 0 ? S : A.nd;
+    const int32_t* off = A.off + inst * nd;
     const int lo = static_cast<int>(A.node_off[inst]), hi = static_cast<int>(A.node_off[inst + 1]);
-    for (int d = 0; d < A.nd; ++d) {
+#pragma unroll kUnroll
+    for (int d = 0; d < nd; ++d) {
       const int c = i + off[d];
       f(A.dval[d * N + i], (c < lo || c >= hi) ? i : c);
     }
-  } else {
-    const int e1 = A.rowptr[i + 1];
-    for (int e = A.rowptr[i]; e < e1; ++e) f(A.val[e], A.col[e]);
+  }
+}
+
+// Storage tags compiled: CSR, diagonal storage with 3 (1D), 7 (2D triangles)
+// or 19 (3D five-tet) diagonals, and diagonal storage with a runtime count.
+template <class F>
+void dispatch_storage(int nd, F&& f) {
+  switch (nd) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 19: f(std::integral_constant<int, 19>{}); break;
+    default: f(std::integral_constant<int, -1>{}); break;
   }
 }
 
@@ -125,7 +157,7 @@ __global__ void k_set_values(const int32_t* __restrict__ nodes, int64_t n, doubl
 //   Phi_m = ML_i (v0_i - v_m,i) + dt sum_j Q[m][j] F_j
 //   Gam_m = w0_i - w_m,i + dt sum_j Q[m][j] R_j,i
 // and amax_i = 0 for this sweep's selection.
-template <int M, bool DIA>
+template <int M, int S>
 __global__ __launch_bounds__(kBlock) void k_sweep_start(
     Map map, int64_t N, Mat A, const double* __restrict__ ml, const double* __restrict__ v0,
     const double* __restrict__ w0, const double* __restrict__ v, const double* __restrict__ w,
@@ -137,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
   double Av[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) Av[j] = 0.0;
-  for_entries<DIA>(A, N, rw.inst, i, [&](double a, int k) {
+  for_entries<S>(A, N, rw.inst, i, [&](double a, int k) {
 #pragma unroll
     for (int j = 0; j < M; ++j) Av[j] += a * v[j * N + k];
   });
@@ -165,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
 
 // Right-hand side of node m; CG start values x = 0, r = b on active rows:
 //   b_i = Phi_m,i - dt ML_i sum_{j<m} QE[m][j] dI_j,i - dt sum_k A_ik sum_{j<m} QI[m][j] dv_j,k
-template <int M, bool DIA>
+template <int M, int S>
 __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A,
                                                 const double* __restrict__ ml,
                                                 const double* __restrict__ Phi_m,
@@ -177,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A
   const int i = rw.row;
   double ay = 0.0;
   if (m > 0) {
-    for_entries<DIA>(A, N, rw.inst, i, [&](double a, int k) {
+    for_entries<S>(A, N, rw.inst, i, [&](double a, int k) {
       double y = 0.0;
 #pragma unroll
       for (int j = 0; j < M - 1; ++j)
@@ -225,40 +257,17 @@ struct CgBufs {
   double* scal[2];     // [n_inst][kScal] scalars written by launch parity
 };
 
-// Sum this instance's partials of the previous launch (same in every block).
-__device__ inline void instance_totals(const Map& map, int inst, const double* __restrict__ part,
-                                       double (&tot)[3], double* sh) {
-  const int b0 = map.inst_blk0[inst], nb = map.inst_nblk[inst];
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nb; b += kBlock) {
-    const double* pp = part + 4 * (b0 + b);
-    acc[0] += pp[0];
-    acc[1] += pp[1];
-    acc[2] += pp[2];
-  }
-  block_sum<3>(acc, sh);
-  if (threadIdx.x == 0) {
-    sh[12] = acc[0];
-    sh[13] = acc[1];
-    sh[14] = acc[2];
-  }
-  __syncthreads();
-  tot[0] = sh[12];
-  tot[1] = sh[13];
-  tot[2] = sh[14];
-}
-
 template <int NV>
-__device__ inline void write_partials(double (&v)[NV], double* part, double* sh) {
+__device__ inline void write_partials(double (&v)[NV], int blk, double* part, double* sh) {
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) part[4 * blockIdx.x + q] = v[q];
+    for (int q = 0; q < NV; ++q) part[4 * blk + q] = v[q];
   }
 }
 
 // Start: u0 = dinv r0, w0 = H u0; partials of gamma0 = r0.u0, delta0 = w0.u0, bb = r0.r0.
-template <bool DIA>
+template <int S>
 __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_t N, Mat H,
                                                      const double* __restrict__ dinv,
                                                      const double* __restrict__ r0,
@@ -277,17 +286,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_
   if (rw.valid) {
     const int i = rw.row;
     double acc = 0.0;
-    for_entries<DIA>(H, N, rw.inst, i, [&](double h, int k) { acc += h * (dinv[k] * r0[k]); });
+    for_entries<S>(H, N, rw.inst, i, [&](double h, int k) { acc += h * (dinv[k] * r0[k]); });
     const double ri = r0[i], ui = dinv[i] * ri;
     w0[i] = acc;
     s[0] = ri * ui;
     s[1] = acc * ui;
     s[2] = ri * ri;
   }
-  write_partials<3>(s, part_out, sh);
+  write_partials<3>(s, rw.blk, part_out, sh);
 }
 
-template <bool DIA>
+template <int S>
 __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, const double* __restrict__ dinv,
                                                     double* __restrict__ x, double* __restrict__ p,
                                                     const double* __restrict__ r_in,
@@ -305,9 +314,51 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
   const Row rw = map_row(map);
   const int inst = rw.inst;
   if (cg.done[inst]) return;
-  double tot[3];
-  instance_totals(map, inst, part_in, tot, sh);
-  const double gamma = tot[0], delta = tot[1], rr = tot[2];
+  const int i = rw.row;
+  // Everything that does not depend on this iteration's scalars is loaded
+  // before they are formed: the previous launch's partial sums of the
+  // instance, and the row's own values and neighbour sums
+  //   a_r = sum_k h_ik dinv_k r_k,  a_w = sum_k h_ik dinv_k w_k,  a_s = sum_k h_ik dinv_k s_k,
+  // so that H u with u = dinv (r - alpha (w + beta s)) is a_r - alpha (a_w + beta a_s).
+  const int b0 = map.inst_blk0[inst], nb = map.inst_nblk[inst];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    const double* pp = part_in + 4 * (b0 + b);
+    acc[0] += pp[0];
+    acc[1] += pp[1];
+    acc[2] += pp[2];
+  }
+  double a_r = 0.0, a_w = 0.0, a_s = 0.0;
+  double di = 0.0, ri = 0.0, wi = 0.0, si = 0.0, p_old = 0.0;
+  if (rw.valid) {
+    if (it == 0) {
+      for_entries<S>(H, N, inst, i, [&](double h, int k) {
+        const double hd = h * dinv[k];
+        a_r += hd * r_in[k];
+        a_w += hd * w_in[k];
+      });
+    } else {
+      for_entries<S>(H, N, inst, i, [&](double h, int k) {
+        const double hd = h * dinv[k];
+        a_r += hd * r_in[k];
+        a_w += hd * w_in[k];
+        a_s += hd * s_in[k];
+      });
+      si = s_in[i];
+      p_old = p[i];
+    }
+    di = dinv[i];
+    ri = r_in[i];
+    wi = w_in[i];
+  }
+  block_sum<3>(acc, sh);
+  if (threadIdx.x == 0) {
+    sh[12] = acc[0];
+    sh[13] = acc[1];
+    sh[14] = acc[2];
+  }
+  __syncthreads();
+  const double gamma = sh[12], delta = sh[13], rr = sh[14];
   double alpha, beta, bb;
   if (it == 0) {
     bb = rr;
@@ -324,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
   else if (rr <= rtol2 * bb) status = 1;
   else if (it >= maxit) status = 2;
   else if (!isfinite(alpha) || !(alpha > 0.0)) status = 3;
-  if (rw.valid && map.blk[blockIdx.x].w == 0 && threadIdx.x == 0) {
+  if (map.blk[rw.blk].w == 0 && threadIdx.x == 0) {
     // block 0 of the instance records the outcome and the scalars
     cg.done[inst] = status;
     cg.iters[inst] = it;
@@ -336,33 +387,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
   if (status != 0) return;
   double s[3] = {0.0, 0.0, 0.0};
   if (rw.valid) {
-    const int i = rw.row;
-    double acc = 0.0;
-    if (it == 0) {
-      for_entries<DIA>(H, N, rw.inst, i, [&](double h, int k) {
-        acc += h * (dinv[k] * (r_in[k] - alpha * w_in[k]));
-      });
-    } else {
-      for_entries<DIA>(H, N, rw.inst, i, [&](double h, int k) {
-        acc += h * (dinv[k] * (r_in[k] - alpha * (w_in[k] + beta * s_in[k])));
-      });
-    }
-    const double di = dinv[i], ri = r_in[i];
+    const double w_new = a_r - alpha * (a_w + beta * a_s);
     const double ui = di * ri;
-    const double pi = it == 0 ? ui : ui + beta * p[i];
-    const double si = it == 0 ? w_in[i] : w_in[i] + beta * s_in[i];
+    const double pi = ui + beta * p_old;
+    const double sv = wi + beta * si;
     x[i] += alpha * pi;
     p[i] = pi;
-    s_out[i] = si;
-    const double rn = ri - alpha * si;
+    s_out[i] = sv;
+    const double rn = ri - alpha * sv;
     r_out[i] = rn;
-    w_out[i] = acc;
+    w_out[i] = w_new;
     const double un = di * rn;
     s[0] = rn * un;
-    s[1] = acc * un;
+    s[1] = w_new * un;
     s[2] = rn * rn;
   }
-  write_partials<3>(s, part_out, sh);
+  write_partials<3>(s, rw.blk, part_out, sh);
 }
 
 // Post-solve update of node m (eq. final-sdc):
@@ -421,8 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_select_count(Map map, const int32_t*
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    sel_cnt[blockIdx.x] = sc[0] + sc[1] + sc[2] + sc[3];
-    sel_nnz[blockIdx.x] = sn[0] + sn[1] + sn[2] + sn[3];
+    sel_cnt[rw.blk] = sc[0] + sc[1] + sc[2] + sc[3];
+    sel_nnz[rw.blk] = sn[0] + sn[1] + sn[2] + sn[3];
   }
 }
 
@@ -528,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) wc[wid] = __popcll(mask);
   __syncthreads();
-  int base = sel_off[blockIdx.x];
+  int base = sel_off[rw.blk];
   for (int q = 0; q < wid; ++q) base += wc[q];
   const int rank = __popcll(mask & ((1ull << lane) - 1ull));
   if (keep) idx_out[base + rank] = rw.row;
@@ -622,12 +662,10 @@ void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const M
                         double* Gam, double* amax, const CollArgs& c) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    if (A.nd > 0)
-      k_sweep_start<decltype(mm)::value, true><<<grid(map.nblk), kBlock, 0, s>>>(
+    dispatch_storage(A.nd, [&](auto st) {
+      k_sweep_start<decltype(mm)::value, decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(
           map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam, amax, c);
-    else
-      k_sweep_start<decltype(mm)::value, false><<<grid(map.nblk), kBlock, 0, s>>>(
-          map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam, amax, c);
+    });
   });
 }
 
@@ -636,10 +674,10 @@ void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Ma
                 double* x, const CollArgs& c) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    if (A.nd > 0)
-      k_rhs<decltype(mm)::value, true><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c);
-    else
-      k_rhs<decltype(mm)::value, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c);
+    dispatch_storage(A.nd, [&](auto st) {
+      k_rhs<decltype(mm)::value, decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m,
+                                                                                       dI, dv, r, x, c);
+    });
   });
 }
 
@@ -651,10 +689,9 @@ void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, do
 void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const Mat& H,
                      const double* dinv, const double* r0, double* w0, double* part_out,
                      const CgState& cg) {
-  if (H.nd > 0)
-    k_cg_start<true><<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, N, H, dinv, r0, w0, part_out, cg);
-  else
-    k_cg_start<false><<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, N, H, dinv, r0, w0, part_out, cg);
+  dispatch_storage(H.nd, [&](auto st) {
+    k_cg_start<decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, N, H, dinv, r0, w0, part_out, cg);
+  });
 }
 
 void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
@@ -663,14 +700,11 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
                     int maxit, const CgState& cg) {
   if (map.nblk <= 0) return;
-  if (H.nd > 0)
-    k_cg_iter<true><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out,
-                                                      s_out, it, part_in, part_out, scal_in, scal_out,
-                                                      rtol2, maxit, cg);
-  else
-    k_cg_iter<false><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out,
-                                                       s_out, it, part_in, part_out, scal_in, scal_out,
-                                                       rtol2, maxit, cg);
+  dispatch_storage(H.nd, [&](auto st) {
+    k_cg_iter<decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, dinv, x, p, r_in, w_in, s_in,
+                                                                     r_out, w_out, s_out, it, part_in, part_out,
+                                                                     scal_in, scal_out, rtol2, maxit, cg);
+  });
 }
 
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
