@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -38,6 +40,9 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched / adjoint measurements")
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--with-3d", action="store_true", help="also time the 128^3 3D workload")
     ap.add_argument("--calib", action="store_true",
                     help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -169,9 +174,121 @@ def main():
             "bytes_per_launch": prof["cg_bytes"] / prof["cg_launches"],
             "launches": prof["cg_launches"],
         }
+    s.close()
+    if not args.no_batch:
+        out["batched"], out["adjoint"] = batched_and_adjoint(args.batch_steps)
+        out["adjoint_forward_ratio"] = out["adjoint"]["ratio_ckpt10"]
+    if args.with_3d:
+        out["workload_3d"] = workload_3d()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
+
+
+def _timed_steps(solver, v, w, t0, dt, n, sync):
+    sync()
+    t = time.perf_counter()
+    logs = [solver.step(v, w, t0 + k * dt, stats=True) for k in range(n)]
+    sync()
+    return time.perf_counter() - t, logs
+
+
+def batched_and_adjoint(nsteps):
+    """48 uneven 2D instances in one context: throughput vs each instance run
+    alone, and the reverse step's cost relative to the forward."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    from paper_2311_07206_amd.autograd import SDCRun
+    from workloads import config4
+
+    P = config4()
+    dev = torch.device("cuda", 0)
+    sync = torch.cuda.synchronize
+    s = Solver.from_problem(P)
+    v = torch.tensor(P.v_init, device=dev)
+    w = torch.tensor(P.w_init, device=dev)
+    warm = 10
+    for k in range(warm):
+        s.step(v, w, k * P.dt)
+    v0b, w0b, t0 = v.clone(), w.clone(), warm * P.dt
+    el, logs = _timed_steps(s, v, w, t0, P.dt, nsteps, sync)
+    dofs = sum(st["n_active"] for lg in logs for st in lg)
+    batched = {"workload": f"{P.n_inst} 2D instances, sides 96..384 ({P.N} dofs total), M={P.M} K={P.K} "
+                           f"dt={P.dt}, theta={P.theta}",
+               "value": dofs / el, "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
+               "storage": s.info()}
+    # each instance alone, same steps from the same state
+    seq = 0.0
+    v0h, w0h = v0b.cpu().numpy(), w0b.cpu().numpy()
+    for i in range(P.n_inst):
+        lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
+        e0, e1 = int(P.elem_off[i]), int(P.elem_off[i + 1])
+        si = Solver(P.coords[lo:hi], P.elems[e0:e1] - lo, P.elem_tensor[e0:e1], P.node_sigma[lo:hi],
+                    P.ionic[i:i + 1], [0, hi - lo], [0, e1 - e0], P.M, P.K, P.dt, P.theta)
+        vi = torch.tensor(v0h[lo:hi], device=dev)
+        wi = torch.tensor(w0h[lo:hi], device=dev)
+        si.step(vi.clone(), wi.clone(), t0)   # warm the iteration budgets
+        e, _ = _timed_steps(si, vi, wi, t0, P.dt, nsteps, sync)
+        seq += e
+        si.close()
+    batched["sequential_ms_per_step"] = 1e3 * seq / nsteps
+    batched["speedup_vs_sequential"] = seq / el
+    # reverse mode: loss 0.5 ||v(T) - target||^2 over nsteps steps
+    target = torch.rand(P.N, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    adj = {"workload": batched["workload"] + f", {nsteps} steps, gradients w.r.t. nodal sigma and per-instance a"}
+    for ck in (10, 1):
+        sigma = torch.tensor(P.node_sigma, device=dev, requires_grad=True)
+        a = torch.tensor(P.ionic[:, 1].copy(), device=dev, requires_grad=True)
+        v0 = v0b.clone().requires_grad_(True)
+        w0 = w0b.clone().requires_grad_(True)
+        sync()
+        t = time.perf_counter()
+        vT, _ = SDCRun.apply(sigma, a, v0, w0, s, nsteps, t0, ck)
+        sync()
+        tf = time.perf_counter() - t
+        loss = 0.5 * ((vT - target) ** 2).sum()
+        sync()
+        t = time.perf_counter()
+        loss.backward()
+        sync()
+        tb = time.perf_counter() - t
+        adj[f"forward_ms_ckpt{ck}"] = 1e3 * tf
+        adj[f"backward_ms_ckpt{ck}"] = 1e3 * tb
+        adj[f"ratio_ckpt{ck}"] = tb / tf
+    s.close()
+    return batched, adj
+
+
+def workload_3d(nsteps=10, warm=10):
+    """The 128^3 3D workload (2.1M dofs, 27M stored entries): HBM-resident."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    from workloads import config2
+
+    P = config2()
+    dev = torch.device("cuda", 0)
+    s = Solver.from_problem(P)
+    v = torch.tensor(P.v_init, device=dev)
+    w = torch.tensor(P.w_init, device=dev)
+    for k in range(warm):
+        s.step(v, w, k * P.dt)
+    s.profile(True)
+    el, logs = _timed_steps(s, v, w, warm * P.dt, P.dt, nsteps, torch.cuda.synchronize)
+    prof = s.profile_read()
+    s.profile(False)
+    dofs = sum(st["n_active"] for lg in logs for st in lg)
+    nbytes = sum(sweep_bytes(st, P.M, k == 0) for lg in logs for k, st in enumerate(lg)) + nsteps * step_bytes(P.N, P.M)
+    out = {"workload": f"3D monodomain 128^3 P1 tets ({P.N} dofs), M={P.M} K={P.K} dt={P.dt}, theta={P.theta}",
+           "value": dofs / el, "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
+           "algorithmic_GBps": nbytes / el / 1e9, "storage": s.info(),
+           "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)]}
+    if prof["cg_launches"]:
+        out["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
+        out["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]
+    s.close()
+    return out
 
 
 def cpu_baseline(P, v0, w0, t0, nsteps):

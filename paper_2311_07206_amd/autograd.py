@@ -8,6 +8,7 @@ reverse step (sdc_adjoint_step, which recomputes its step's sweeps and
 reverses them with the active sets held fixed) is applied step by step.
 All arithmetic runs in the HIP library; this module only sequences calls.
 """
+import numpy as np
 import torch
 
 
@@ -22,9 +23,12 @@ class SDCRun(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, sigma, a, v0, w0, solver, n_steps, t0, ckpt_every):
+        sig = sigma.detach().cpu().numpy()
         ionic = solver.ionic.copy()
         ionic[:, 1] = a.detach().cpu().numpy()
-        solver.set_coefficients(sigma.detach().cpu().numpy(), ionic)
+        # reassemble only when the coefficients differ from the solver's
+        solver.set_coefficients(None if np.array_equal(sig, solver.node_sigma) else sig,
+                                None if np.array_equal(ionic, solver.ionic) else ionic)
         v = v0.detach().clone()
         w = w0.detach().clone()
         ckpts = []

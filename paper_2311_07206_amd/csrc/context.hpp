@@ -17,6 +17,7 @@ namespace sdc {
 
 struct MapBuf {
   int4* blk = nullptr;
+  int32_t* blk_nb = nullptr;
   int32_t* inst_blk0 = nullptr;
   int32_t* inst_nblk = nullptr;
   int32_t* inst_cnt = nullptr;
@@ -30,8 +31,8 @@ struct MapBuf {
   std::vector<int32_t> cnt;
   std::vector<int64_t> nnz;
 
-  Map dev() const { return Map{blk, inst_blk0, inst_nblk, idx, nblk}; }
-  NextMap next() const { return NextMap{blk, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals}; }
+  Map dev() const { return Map{blk, blk_nb, inst_blk0, inst_nblk, idx, nblk}; }
+  NextMap next() const { return NextMap{blk, blk_nb, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals}; }
 };
 
 struct Stimulus {
@@ -90,7 +91,7 @@ struct sdc_ctx {
 
   double* cg_scal[2] = {nullptr, nullptr};   // [n_inst][kScal] by launch parity
   double* part[2] = {nullptr, nullptr};      // [nblk][4] by launch parity
-  int32_t *cg_done = nullptr, *cg_iters = nullptr;
+  int32_t *cg_done = nullptr, *cg_iters = nullptr, *cg_blk_done = nullptr;
   int32_t *sel_cnt = nullptr, *sel_nnz = nullptr;
 
   MapBuf all;
@@ -138,7 +139,7 @@ struct sdc_ctx {
   std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
 
   const MapBuf& curmap() const { return cur < 0 ? all : dyn[cur]; }
-  CgState cg() const { return CgState{cg_done, cg_iters}; }
+  CgState cg() const { return CgState{cg_done, cg_iters, cg_blk_done}; }
   Mat matA(bool dia) const {
     return Mat{rowptr, colidx, Aval, dia_off, dia_A, node_off_d, dia ? nd : 0};
   }

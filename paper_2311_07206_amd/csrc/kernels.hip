@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_
   }
   if (static_cast<int>(blockIdx.x) >= map.nblk) return;
   const Row rw = map_row(map);
+  if (threadIdx.x == 0) cg.blk_done[rw.blk] = 0;
   double s[3] = {0.0, 0.0, 0.0};
   if (rw.valid) {
     const int i = rw.row;
@@ -311,16 +312,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
                                                     double* __restrict__ scal_out, double rtol2,
                                                     int maxit, CgState cg) {
   __shared__ double sh[16];
-  const Row rw = map_row(map);
-  const int inst = rw.inst;
-  if (cg.done[inst]) return;
-  const int i = rw.row;
+  // first round trip: this block's map entry, its instance's block count and
+  // its own stop flag (all indexed by the logical block)
+  const int L = logical_block(map.nblk);
+  const int4 bm = map.blk[L];
+  const int nb = map.blk_nb[L];
+  if (cg.blk_done[L]) return;
+  const int inst = bm.x, b0 = L - bm.w;
+  const int pos = bm.y + static_cast<int>(threadIdx.x);
+  const bool valid = pos < bm.z;
+  const int i = valid ? (map.idx ? map.idx[pos] : pos) : 0;
   // Everything that does not depend on this iteration's scalars is loaded
   // before they are formed: the previous launch's partial sums of the
   // instance, and the row's own values and neighbour sums
   //   a_r = sum_k h_ik dinv_k r_k,  a_w = sum_k h_ik dinv_k w_k,  a_s = sum_k h_ik dinv_k s_k,
   // so that H u with u = dinv (r - alpha (w + beta s)) is a_r - alpha (a_w + beta a_s).
-  const int b0 = map.inst_blk0[inst], nb = map.inst_nblk[inst];
   double acc[3] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nb; b += kBlock) {
     const double* pp = part_in + 4 * (b0 + b);
@@ -330,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
   }
   double a_r = 0.0, a_w = 0.0, a_s = 0.0;
   double di = 0.0, ri = 0.0, wi = 0.0, si = 0.0, p_old = 0.0;
-  if (rw.valid) {
+  if (valid) {
     if (it == 0) {
       for_entries<S>(H, N, inst, i, [&](double h, int k) {
         const double hd = h * dinv[k];
@@ -375,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
   else if (rr <= rtol2 * bb) status = 1;
   else if (it >= maxit) status = 2;
   else if (!isfinite(alpha) || !(alpha > 0.0)) status = 3;
-  if (map.blk[rw.blk].w == 0 && threadIdx.x == 0) {
+  if (bm.w == 0 && threadIdx.x == 0) {
     // block 0 of the instance records the outcome and the scalars
     cg.done[inst] = status;
     cg.iters[inst] = it;
@@ -384,9 +390,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
     so[kAlpha] = alpha;
     so[kBB] = bb;
   }
-  if (status != 0) return;
+  if (status != 0) {
+    if (threadIdx.x == 0) cg.blk_done[L] = status;
+    return;
+  }
   double s[3] = {0.0, 0.0, 0.0};
-  if (rw.valid) {
+  if (valid) {
     const double w_new = a_r - alpha * (a_w + beta * a_s);
     const double ui = di * ri;
     const double pi = ui + beta * p_old;
@@ -402,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
     s[1] = w_new * un;
     s[2] = rn * rn;
   }
-  write_partials<3>(s, rw.blk, part_out, sh);
+  write_partials<3>(s, L, part_out, sh);
 }
 
 // Post-solve update of node m (eq. final-sdc):
@@ -530,6 +539,7 @@ __device__ void build_map(const int32_t* cnt, const int32_t* aoff, int n_inst, c
     const int beg = aoff[lo] + bi * kBlock;
     const int end = min(beg + kBlock, aoff[lo] + cnt[lo]);
     nm.blk[b] = make_int4(lo, beg, end, bi);
+    nm.blk_nb[b] = nm.inst_nblk[lo];
   }
 }
 

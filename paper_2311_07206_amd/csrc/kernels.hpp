@@ -25,6 +25,7 @@ struct CollArgs {
 // the positions are row numbers (all rows active).
 struct Map {
   const int4* blk;         // {inst, beg, end, bi}
+  const int32_t* blk_nb;   // per entry: number of blocks of its instance
   const int32_t* inst_blk0;
   const int32_t* inst_nblk;
   const int32_t* idx;
@@ -55,8 +56,9 @@ struct Mat {
 enum { kRZ = 0, kBB, kAlpha, kBeta, kScal = 8 };   // kRZ holds gamma = r.z
 
 struct CgState {
-  int32_t* done;       // 0 running, 1 converged, 2 maxit, 3 non-finite
-  int32_t* iters;      // updates performed when the solve stopped
+  int32_t* done;       // per instance: 0 running, 1 converged, 2 maxit, 3 non-finite
+  int32_t* iters;      // per instance: updates performed when the solve stopped
+  int32_t* blk_done;   // per map entry: its instance's solve has stopped
 };
 
 void launch_spread(hipStream_t s, int M, const Map& all, int64_t N, const double* ionic,
@@ -94,6 +96,7 @@ void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const d
 // and per-instance totals are written by the scan pass.
 struct NextMap {
   int4* blk;
+  int32_t* blk_nb;
   int32_t* inst_blk0;
   int32_t* inst_nblk;
   int32_t* inst_cnt;       // kept rows per instance

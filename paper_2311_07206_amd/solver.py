@@ -73,6 +73,7 @@ class Solver:
         self.n_inst = len(node_off_a) - 1
         self.dt = float(dt)
         self.ionic = ion_a.copy()
+        self.node_sigma = sig_a.copy()
 
     @classmethod
     def from_problem(cls, P, **kw):
@@ -189,6 +190,8 @@ class Solver:
         self._check(self.lib.sdc_set_coefficients(self.ctx, ps, pi))
         if ionic is not None:
             self.ionic = i_a.copy()
+        if node_sigma is not None:
+            self.node_sigma = s_a.copy()
 
     def info(self):
         """Storage in use ('csr' or 'dia'), diagonals, setup timings, redone steps."""
