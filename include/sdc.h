@@ -56,6 +56,7 @@ enum {
 
 #define SDC_MAX_NODES 6    /* collocation nodes M supported: 1..6            */
 #define SDC_MAX_SWEEPS 16  /* sweeps per step K supported: 1..16             */
+#define SDC_MAX_RECORDINGS 64  /* recorded steps held for the reverse pass   */
 
 typedef struct sdc_ctx sdc_ctx;
 
@@ -161,10 +162,21 @@ int sdc_set_active(sdc_ctx* ctx, int32_t sweep, const int32_t* idx, int64_t n);
  * the nodal conductivity multipliers to g_sigma (device double[N]) and with
  * respect to each instance's Aliev-Panfilov parameter a to g_a (device
  * double[n_inst]).  The reverse solves use the forward's Jacobi-PCG on the
- * same (symmetric) restricted matrices.  Uses about (2K + 4) M N + K N extra
+ * same (symmetric) restricted matrices.  Uses about (2K + 6) M N + K N extra
  * doubles of device memory, allocated on the first call. */
 int sdc_adjoint_step(sdc_ctx* ctx, const double* v_n, const double* w_n, double t, double* lam_v,
                      double* lam_w, double* g_sigma, double* g_a);
+
+/* The same reverse step in two parts, so that a checkpoint segment is
+ * recomputed once: sdc_adjoint_record advances (v, w) in place by one step
+ * from time t exactly like sdc_step and keeps what the reverse pass needs in
+ * recording `slot` (0..SDC_MAX_RECORDINGS-1; about (2K + 2) M N doubles of
+ * device memory per slot, allocated on first use); sdc_adjoint_reverse then
+ * applies the reverse step of that recording (same arguments and results as
+ * sdc_adjoint_step).  Slot 0 is also used by sdc_adjoint_step. */
+int sdc_adjoint_record(sdc_ctx* ctx, int32_t slot, double* v, double* w, double t);
+int sdc_adjoint_reverse(sdc_ctx* ctx, int32_t slot, double* lam_v, double* lam_w, double* g_sigma,
+                        double* g_a);
 
 /* Replace the nodal conductivity multipliers (host double[N], or NULL to keep)
  * and the Aliev-Panfilov parameters (host double[n_inst][6], or NULL): A is

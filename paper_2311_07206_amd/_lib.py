@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libsdc.so")
 
 MAX_NODES = 6
 MAX_SWEEPS = 16
+MAX_RECORDINGS = 64
 
 SDC_OK = 0
 ERRORS = {
@@ -80,6 +81,8 @@ SIGNATURES = {
     "sdc_get_info": (c_int32, [c_void_p, POINTER(Info)]),
     "sdc_adjoint_step": (c_int32, [c_void_p, PTR, PTR, c_double, PTR, PTR, PTR, PTR]),
     "sdc_set_coefficients": (c_int32, [c_void_p, PTR, PTR]),
+    "sdc_adjoint_record": (c_int32, [c_void_p, c_int32, PTR, PTR, c_double]),
+    "sdc_adjoint_reverse": (c_int32, [c_void_p, c_int32, PTR, PTR, PTR, PTR]),
     "sdc_profile_read": (c_int32, [c_void_p, POINTER(ProfileStats)]),
 }
 

@@ -2,10 +2,10 @@
 
 Forward: n steps of the library from (v0, w0) at the given coefficients,
 keeping the step-start state every `ckpt_every` steps.  Backward: for each
-checkpoint segment, last first, the start states of its steps are recomputed
-from the checkpoint (skipped when ckpt_every == 1), then the library's
-reverse step (sdc_adjoint_step, which recomputes its step's sweeps and
-reverses them with the active sets held fixed) is applied step by step.
+checkpoint segment, last first, the segment's steps are recomputed once from
+the checkpoint with every sweep recorded (sdc_adjoint_record, one recording
+slot per step), then reversed step by step, last first (sdc_adjoint_reverse,
+active sets held fixed).
 All arithmetic runs in the HIP library; this module only sequences calls.
 """
 import numpy as np
@@ -23,6 +23,8 @@ class SDCRun(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, sigma, a, v0, w0, solver, n_steps, t0, ckpt_every):
+        if not 1 <= ckpt_every <= solver.max_recordings:
+            raise ValueError(f"ckpt_every must be in 1..{solver.max_recordings}")
         sig = sigma.detach().cpu().numpy()
         ionic = solver.ionic.copy()
         ionic[:, 1] = a.detach().cpu().numpy()
@@ -52,12 +54,9 @@ class SDCRun(torch.autograd.Function):
         for q in range(len(ctx.ckpts) - 1, -1, -1):
             n0, v, w = ctx.ckpts[q]
             n1 = bounds[q + 1]
-            starts = [(v, w)]
             v, w = v.clone(), w.clone()
-            for n in range(n0, n1 - 1):
-                s.step(v, w, ctx.t0 + n * s.dt)
-                starts.append((v.clone(), w.clone()))
+            for n in range(n0, n1):
+                s.adjoint_record(n - n0, v, w, ctx.t0 + n * s.dt)
             for n in range(n1 - 1, n0 - 1, -1):
-                vn, wn = starts[n - n0]
-                s.adjoint_step(vn, wn, ctx.t0 + n * s.dt, lam_v, lam_w, g_sigma, g_a)
+                s.adjoint_reverse(n - n0, lam_v, lam_w, g_sigma, g_a)
         return g_sigma.to(dev), g_a.reshape(ctx.a_shape), lam_v, lam_w, None, None, None, None

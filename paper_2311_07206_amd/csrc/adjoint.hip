@@ -46,23 +46,38 @@ int adjoint_setup(sdc_ctx* ctx) {
   HIPC(hipMemcpyAsync(A.nptr, nptr.data(), (N + 1) * 4, hipMemcpyHostToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(A.nel, nel.data(), E * nv * 4, hipMemcpyHostToDevice, ctx->stream));
   const size_t MN = static_cast<size_t>(M) * N;
-  TRY(dalloc(ctx, &A.rec_v, (K + 1) * MN));
-  TRY(dalloc(ctx, &A.rec_w, (K + 1) * MN));
-  TRY(dalloc(ctx, &A.rec_dv, K * MN));
-  TRY(dalloc(ctx, &A.rec_list, static_cast<size_t>(K) * N));
+  (void)K;
   for (double** b : {&A.Lv, &A.Lw, &A.Ldv, &A.Ldw}) TRY(dalloc(ctx, b, MN));
   for (double** b : {&A.Lv0, &A.Lw0, &A.psi, &A.u, &A.ga_row}) TRY(dalloc(ctx, b, N));
   TRY(dalloc(ctx, &A.qe, E));
   TRY(dalloc(ctx, &A.in_set, N));
   HIPC(hipStreamSynchronize(ctx->stream));   // host staging vectors go out of scope
-  A.rec_n.assign(K, -1);
+  A.slots.resize(SDC_MAX_RECORDINGS);
   A.ready = true;
   return SDC_OK;
 }
 
-// Recompute the step from (v, w) at time t, recording what the reverse needs.
-int record_step(sdc_ctx* ctx, const double* v, const double* w, double t) {
-  auto& A = ctx->adj;
+int ensure_slot(sdc_ctx* ctx, int slot) {
+  if (slot < 0 || slot >= SDC_MAX_RECORDINGS) return fail(ctx, SDC_ERR_ARG, "recording slot out of range");
+  auto& R = ctx->adj.slots[slot];
+  if (R.v) return SDC_OK;
+  const int M = ctx->prm.M, K = ctx->prm.K;
+  const size_t MN = static_cast<size_t>(M) * ctx->N;
+  TRY(dalloc(ctx, &R.v, (K + 1) * MN));
+  TRY(dalloc(ctx, &R.w, (K + 1) * MN));
+  TRY(dalloc(ctx, &R.dv, K * MN));
+  TRY(dalloc(ctx, &R.list, static_cast<size_t>(K) * ctx->N));
+  R.n.assign(K, -1);
+  return SDC_OK;
+}
+
+// Recompute the step from (v, w) at time t, recording what the reverse needs
+// into `slot`.  The end state stays in the context's last collocation node.
+int record_step(sdc_ctx* ctx, int slot, const double* v, const double* w, double t) {
+  TRY(ensure_slot(ctx, slot));
+  auto& A = ctx->adj.slots[slot];
+  A.valid = false;
+  A.t = t;
   const int M = ctx->prm.M, K = ctx->prm.K;
   const int64_t N = ctx->N;
   const size_t MN = static_cast<size_t>(M) * N;
@@ -74,14 +89,14 @@ int record_step(sdc_ctx* ctx, const double* v, const double* w, double t) {
     for (int k = 0; k < K && !short_budget; ++k) {
       const MapBuf& mb = ctx->curmap();
       if (mb.idx) {
-        HIPC(hipMemcpyAsync(A.rec_list + k * N, mb.idx, mb.rows * 4, hipMemcpyDeviceToDevice, ctx->stream));
-        A.rec_n[k] = mb.rows;
+        HIPC(hipMemcpyAsync(A.list + k * N, mb.idx, mb.rows * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        A.n[k] = mb.rows;
       } else {
-        A.rec_n[k] = -1;
+        A.n[k] = -1;
       }
-      HIPC(hipMemcpyAsync(A.rec_v + k * MN, ctx->v, MN * 8, hipMemcpyDeviceToDevice, ctx->stream));
-      HIPC(hipMemcpyAsync(A.rec_w + k * MN, ctx->w, MN * 8, hipMemcpyDeviceToDevice, ctx->stream));
-      ctx->record_dv = A.rec_dv + k * MN;
+      HIPC(hipMemcpyAsync(A.v + k * MN, ctx->v, MN * 8, hipMemcpyDeviceToDevice, ctx->stream));
+      HIPC(hipMemcpyAsync(A.w + k * MN, ctx->w, MN * 8, hipMemcpyDeviceToDevice, ctx->stream));
+      ctx->record_dv = A.dv + k * MN;
       int rc = do_sweep(ctx, nullptr, k + 1 < K, async, &short_budget);
       ctx->record_dv = nullptr;
       if (rc != SDC_OK) {
@@ -91,26 +106,23 @@ int record_step(sdc_ctx* ctx, const double* v, const double* w, double t) {
     }
     if (!short_budget) break;
   }
-  HIPC(hipMemcpyAsync(A.rec_v + K * MN, ctx->v, MN * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  HIPC(hipMemcpyAsync(A.rec_w + K * MN, ctx->w, MN * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(A.v + K * MN, ctx->v, MN * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(A.w + K * MN, ctx->w, MN * 8, hipMemcpyDeviceToDevice, ctx->stream));
   ctx->in_step = false;
+  A.valid = true;
   return SDC_OK;
 }
 
-}  // namespace
-
-extern "C" int sdc_adjoint_step(sdc_ctx* ctx, const double* v_n, const double* w_n, double t, double* lam_v,
-                                double* lam_w, double* g_sigma, double* g_a) {
-  TRY(check_ready(ctx));
-  if (!v_n || !w_n || !lam_v || !lam_w || !g_sigma || !g_a) return fail(ctx, SDC_ERR_ARG, "null argument");
-  TRY(adjoint_setup(ctx));
+// Reverse the step recorded in `slot`.
+int reverse_step(sdc_ctx* ctx, int slot, double* lam_v, double* lam_w, double* g_sigma, double* g_a) {
   auto& A = ctx->adj;
+  const auto& Rec = A.slots[slot];
+  if (!Rec.valid) return fail(ctx, SDC_ERR_STATE, "recording slot %d holds no step", slot);
+  const double t = Rec.t;
   const int M = ctx->prm.M, K = ctx->prm.K, nv = ctx->dim + 1;
   const int64_t N = ctx->N, E = ctx->n_elem;
   const size_t MN = static_cast<size_t>(M) * N;
   hipStream_t s = ctx->stream;
-
-  TRY(record_step(ctx, v_n, w_n, t));
 
   // adjoints of the step's outputs: only the last node's values leave the step
   HIPC(hipMemsetAsync(A.Lv, 0, MN * 8, s));
@@ -129,19 +141,19 @@ extern "C" int sdc_adjoint_step(sdc_ctx* ctx, const double* v_n, const double* w
     // set reversed last (the forward leaves them zero off the last set)
     if (prev) launch_zero_rows(s, prev->dev(), ctx->zv());
     const MapBuf* mb = &ctx->all;
-    if (A.rec_n[k] >= 0) {
+    if (Rec.n[k] >= 0) {
       const int slot = (prev == &ctx->dyn[0]) ? 1 : 0;
-      TRY(map_list(ctx, slot, A.rec_list + k * N, A.rec_n[k]));
+      TRY(map_list(ctx, slot, Rec.list + k * N, Rec.n[k]));
       mb = &ctx->dyn[slot];
     }
     const Map map = mb->dev();
     HIPC(hipMemsetAsync(A.in_set, 0, N, s));
     launch_set_flags(s, map, A.in_set, 1);
-    const double* V = A.rec_v + k * MN;
-    const double* W = A.rec_w + k * MN;
-    const double* Ve = A.rec_v + (k + 1) * MN;
-    const double* We = A.rec_w + (k + 1) * MN;
-    const double* DV = A.rec_dv + k * MN;
+    const double* V = Rec.v + k * MN;
+    const double* W = Rec.w + k * MN;
+    const double* Ve = Rec.v + (k + 1) * MN;
+    const double* We = Rec.w + (k + 1) * MN;
+    const double* DV = Rec.dv + k * MN;
     launch_adj_sweep_init(s, M, map, N, A.Lv, A.Lw, A.Ldv, A.Ldw);
     for (int m = M - 1; m >= 0; --m) {
       launch_adj_dw(s, M, m, map, N, ctx->ionic_d, V, W, Ve, We, A.Lv, A.Lw, A.Ldv, A.Ldw, A.Lw0, A.ga_row,
@@ -171,3 +183,37 @@ extern "C" int sdc_adjoint_step(sdc_ctx* ctx, const double* v_n, const double* w
   if (prev) launch_zero_rows(s, prev->dev(), ctx->zv());
   return SDC_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int sdc_adjoint_record(sdc_ctx* ctx, int32_t slot, double* v, double* w, double t) {
+  TRY(check_ready(ctx));
+  if (!v || !w) return fail(ctx, SDC_ERR_ARG, "null argument");
+  TRY(adjoint_setup(ctx));
+  TRY(record_step(ctx, slot, v, w, t));
+  const int64_t N = ctx->N, last = static_cast<int64_t>(ctx->prm.M - 1) * N;
+  HIPC(hipMemcpyAsync(v, ctx->v + last, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(w, ctx->w + last, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return SDC_OK;
+}
+
+int sdc_adjoint_reverse(sdc_ctx* ctx, int32_t slot, double* lam_v, double* lam_w, double* g_sigma, double* g_a) {
+  TRY(check_ready(ctx));
+  if (!lam_v || !lam_w || !g_sigma || !g_a) return fail(ctx, SDC_ERR_ARG, "null argument");
+  TRY(adjoint_setup(ctx));
+  if (slot < 0 || slot >= SDC_MAX_RECORDINGS) return fail(ctx, SDC_ERR_ARG, "recording slot out of range");
+  return reverse_step(ctx, slot, lam_v, lam_w, g_sigma, g_a);
+}
+
+int sdc_adjoint_step(sdc_ctx* ctx, const double* v_n, const double* w_n, double t, double* lam_v, double* lam_w,
+                     double* g_sigma, double* g_a) {
+  TRY(check_ready(ctx));
+  if (!v_n || !w_n || !lam_v || !lam_w || !g_sigma || !g_a) return fail(ctx, SDC_ERR_ARG, "null argument");
+  TRY(adjoint_setup(ctx));
+  TRY(record_step(ctx, 0, v_n, w_n, t));
+  return reverse_step(ctx, 0, lam_v, lam_w, g_sigma, g_a);
+}
+
+}  // extern "C"

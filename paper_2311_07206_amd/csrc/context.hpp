@@ -112,13 +112,18 @@ struct sdc_ctx {
   int64_t n_elem = 0;
 
   // reverse-step storage, allocated on first use
+  struct Recording {                 // one recomputed step
+    double *v = nullptr, *w = nullptr, *dv = nullptr;   // [K+1][M][N], [K+1][M][N], [K][M][N]
+    int32_t* list = nullptr;                            // [K][N] active lists
+    std::vector<int64_t> n;                             // rows per sweep, -1: all rows
+    double t = 0.0;
+    bool valid = false;
+  };
   struct Adjoint {
     bool ready = false;
     int32_t *elems = nullptr, *nptr = nullptr, *nel = nullptr;
     double* pairw = nullptr;
-    double *rec_v = nullptr, *rec_w = nullptr, *rec_dv = nullptr;   // [K+1][M][N], [K][M][N]
-    int32_t* rec_list = nullptr;                                    // [K][N]
-    std::vector<int64_t> rec_n;                                     // -1: all rows
+    std::vector<Recording> slots;
     double *Lv = nullptr, *Lw = nullptr, *Ldv = nullptr, *Ldw = nullptr;
     double *Lv0 = nullptr, *Lw0 = nullptr, *psi = nullptr, *u = nullptr, *ga_row = nullptr, *qe = nullptr;
     uint8_t* in_set = nullptr;

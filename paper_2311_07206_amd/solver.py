@@ -74,6 +74,7 @@ class Solver:
         self.dt = float(dt)
         self.ionic = ion_a.copy()
         self.node_sigma = sig_a.copy()
+        self.max_recordings = _lib.MAX_RECORDINGS
 
     @classmethod
     def from_problem(cls, P, **kw):
@@ -177,6 +178,17 @@ class Solver:
         self._check(self.lib.sdc_adjoint_step(
             self.ctx, self._vec(v_n, n=self.N), self._vec(w_n, n=self.Nw), float(t), self._vec(lam_v, n=self.N),
             self._vec(lam_w, n=self.Nw), self._vec(g_sigma, n=self.N), self._vec(g_a, n=self.n_inst)))
+
+    def adjoint_record(self, slot, v, w, t):
+        """Advance (v, w) in place by one step from t, recording it in `slot` for adjoint_reverse."""
+        self._check(self.lib.sdc_adjoint_record(self.ctx, int(slot), self._vec(v, n=self.N),
+                                                self._vec(w, n=self.Nw), float(t)))
+
+    def adjoint_reverse(self, slot, lam_v, lam_w, g_sigma, g_a):
+        """Reverse step of recording `slot` (see adjoint_step)."""
+        self._check(self.lib.sdc_adjoint_reverse(self.ctx, int(slot), self._vec(lam_v, n=self.N),
+                                                 self._vec(lam_w, n=self.Nw), self._vec(g_sigma, n=self.N),
+                                                 self._vec(g_a, n=self.n_inst)))
 
     def set_coefficients(self, node_sigma=None, ionic=None):
         """Reassemble with new nodal conductivity multipliers and/or ionic parameters (host arrays)."""

@@ -151,3 +151,22 @@ def test_autograd_function_multi_step_against_oracle_tlm():
         rhs = (sigma.grad.cpu().numpy() @ ds + a.grad.cpu().numpy() @ da + v0t.grad.cpu().numpy() @ dv
                + w0t.grad.cpu().numpy() @ dw)
         assert abs(lhs - rhs) <= 1e-7 * (abs(lhs) + 1e-12), (lhs, rhs)
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    from paper_2311_07206_amd.autograd import SDCRun
+    P = config4(n_inst=2, sizes=(9, 13), theta=1e-6)
+    v0, w0 = _mid_state(P, 2)
+    s = _solver(P)
+    grads = []
+    for ck in (1, 3, 5):
+        sigma = torch.tensor(P.node_sigma, device=DEV, requires_grad=True)
+        a = torch.tensor(P.ionic[:, 1].copy(), device=DEV, requires_grad=True)
+        v = torch.tensor(v0, device=DEV, requires_grad=True)
+        w = torch.tensor(w0, device=DEV, requires_grad=True)
+        vT, wT = SDCRun.apply(sigma, a, v, w, s, 5, 2 * P.dt, ck)
+        (vT.square().sum() + 0.5 * wT.sum()).backward()
+        grads.append([x.grad.cpu().numpy() for x in (sigma, a, v, w)])
+    for g in grads[1:]:
+        for x, y in zip(grads[0], g):
+            assert np.array_equal(x, y)
