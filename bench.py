@@ -28,7 +28,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ROCPROF_TRAFFIC = None   # filled from profiles/ when counters exist for this kernel version
+COUNTERS = os.path.join(ROOT, "profiles", "k_cg_iter_2d512_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2311_07206_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """Bytes per k_cg_iter launch from the committed FETCH_SIZE/WRITE_SIZE runs,
+    or None when the kernel source changed since they were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
+    fields = {k[2:].strip(): v.strip() for k, v in fields.items()}
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if fields.get("kernels.hip sha256") != src:
+        return None
+    return float(fields["measured bytes per launch"]), float(fields["algorithmic bytes per launch"])
 
 
 def parse():
@@ -43,6 +60,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / adjoint measurements")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--with-3d", action="store_true", help="also time the 128^3 3D workload")
+    ap.add_argument("--profile-warmup", action="store_true",
+                    help="account CG kernel bytes from the first step (matches counter runs)")
     ap.add_argument("--calib", action="store_true",
                     help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -105,6 +124,8 @@ def main():
     v = torch.tensor(P.v_init, device=dev)
     w = torch.tensor(P.w_init, device=dev)
     t = 0.0
+    if args.profile_warmup:
+        s.profile(True)
     for n in range(args.warmup):
         s.step(v, w, t)
         t += P.dt
@@ -116,7 +137,7 @@ def main():
         tt = t_start
         logs = []
         if profile:
-            s.profile(True)
+            s.profile(True)   # clears the totals
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for n in range(args.steps):
@@ -129,10 +150,16 @@ def main():
             s.profile(False)
         return el, logs, prof
 
-    elapsed, logs, _ = timed(False)
-    prof = None
-    if not args.no_profile:
-        _, _, prof = timed(True)
+    if args.profile_warmup:
+        # one timed pass, accounted together with the warm-up (as the counter runs see it)
+        elapsed, logs, prof = timed(False)
+        prof = s.profile_read()
+        prof = {k: prof[k] for k in prof}
+    else:
+        elapsed, logs, _ = timed(False)
+        prof = None
+        if not args.no_profile:
+            _, _, prof = timed(True)
     sweeps = [st for lg in logs for st in lg]
     dof_sweeps = sum(st["n_active"] for st in sweeps)
     nbytes = sum(sweep_bytes(st, P.M, k == 0) for lg in logs for k, st in enumerate(lg))
@@ -169,11 +196,19 @@ def main():
         ach = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
         out["roofline"] = {
             "kernel": "k_cg_iter", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": ROCPROF_TRAFFIC,
+            "frac": ach / HBM_PEAK_GBS, "traffic": None,
             "avg_launch_us": 1e3 * prof["cg_ms"] / prof["cg_launches"],
             "bytes_per_launch": prof["cg_bytes"] / prof["cg_launches"],
             "launches": prof["cg_launches"],
         }
+        mt = measured_traffic()
+        if mt is not None:
+            # counters: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy calibration), per launch,
+            # averaged over the counter runs' launches; scaled to this run's mix
+            out["roofline"]["traffic"] = out["roofline"]["bytes_per_launch"] * mt[0] / mt[1]
+            out["roofline"]["traffic_over_algorithmic"] = mt[0] / mt[1]
+        if args.profile_warmup:
+            out["roofline"]["scope"] = "warm-up and timed steps"
     s.close()
     if not args.no_batch:
         out["batched"], out["adjoint"] = batched_and_adjoint(args.batch_steps)

@@ -203,9 +203,10 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
 /* ---- measurement ------------------------------------------------------ */
 
 /* Kernel timing of the CG iteration kernel (one launch per iteration: SpMV,
- * vector updates and the three dot products), taken with HIP events on the
- * context's stream around every launch that does work for at least one
- * instance.  Bytes are the algorithmic minimum per launch over the instances
+ * vector updates and the three dot products), taken with start/stop HIP
+ * events attached to each launch on the context's stream (stamped by the
+ * dispatch, so they time the kernel's execution), for every launch that
+ * does work for at least one instance.  Bytes are the algorithmic minimum per launch over the instances
  * still iterating: 8 per stored matrix value in their active rows (index
  * structure is storage overhead and not counted), plus per active row
  * 4 (active-list entry; absent when every row is active) + 6*8 reads

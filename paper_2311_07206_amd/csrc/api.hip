@@ -120,11 +120,10 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
       const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * budget;
       for (int b = 0; b < budget; ++b, ++it) {
         const int a = it & 1, o = a ^ 1;
-        if (timed) HIPC(hipEventRecord(ctx->ev[2 * b], ctx->stream));
         launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
                        ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
-                       ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg());
-        if (timed) HIPC(hipEventRecord(ctx->ev[2 * b + 1], ctx->stream));
+                       ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg(), timed ? ctx->ev[2 * b] : nullptr,
+                       timed ? ctx->ev[2 * b + 1] : nullptr);
       }
       HIPC(hipGetLastError());
       HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
@@ -191,11 +190,10 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
   const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * (*ev_off + budget);
   for (int it = 0; mb.nblk > 0 && it < budget; ++it) {
     const int a = it & 1, o = a ^ 1;
-    if (timed) HIPC(hipEventRecord(ctx->ev[2 * (*ev_off + it)], ctx->stream));
     launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
                    ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
-                   rtol2, ctx->prm.cg_maxit, ctx->cg());
-    if (timed) HIPC(hipEventRecord(ctx->ev[2 * (*ev_off + it) + 1], ctx->stream));
+                   rtol2, ctx->prm.cg_maxit, ctx->cg(), timed ? ctx->ev[2 * (*ev_off + it)] : nullptr,
+                   timed ? ctx->ev[2 * (*ev_off + it) + 1] : nullptr);
   }
   HIPC(hipGetLastError());
   (*ev_budget)[m] = timed && mb.nblk > 0 ? budget : 0;

@@ -9,6 +9,8 @@
 // atomics are used, so repeated runs are bitwise identical.
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 namespace sdc {
@@ -708,12 +710,19 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     double* x, double* p, const double* r_in, const double* w_in, const double* s_in,
                     double* r_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
-                    int maxit, const CgState& cg) {
+                    int maxit, const CgState& cg, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (map.nblk <= 0) return;
   dispatch_storage(H.nd, [&](auto st) {
-    k_cg_iter<decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, dinv, x, p, r_in, w_in, s_in,
-                                                                     r_out, w_out, s_out, it, part_in, part_out,
-                                                                     scal_in, scal_out, rtol2, maxit, cg);
+    if (ev_start) {
+      // events stamped by the dispatch itself: they time the kernel's execution
+      hipExtLaunchKernelGGL((k_cg_iter<decltype(st)::value>), grid(map.nblk), dim3(kBlock), 0, s, ev_start,
+                            ev_stop, 0, map, N, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out, s_out, it,
+                            part_in, part_out, scal_in, scal_out, rtol2, maxit, cg);
+    } else {
+      k_cg_iter<decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, dinv, x, p, r_in, w_in, s_in,
+                                                                       r_out, w_out, s_out, it, part_in, part_out,
+                                                                       scal_in, scal_out, rtol2, maxit, cg);
+    }
   });
 }
 

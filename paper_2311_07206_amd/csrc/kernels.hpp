@@ -85,7 +85,8 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     double* x, double* p, const double* r_in, const double* w_in, const double* s_in,
                     double* r_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
-                    int maxit, const CgState& cg);
+                    int maxit, const CgState& cg, hipEvent_t ev_start = nullptr,
+                    hipEvent_t ev_stop = nullptr);
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                  const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
                  double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
