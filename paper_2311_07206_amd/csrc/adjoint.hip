@@ -89,7 +89,8 @@ int record_step(sdc_ctx* ctx, int slot, const double* v, const double* w, double
     for (int k = 0; k < K && !short_budget; ++k) {
       const MapBuf& mb = ctx->curmap();
       if (mb.idx) {
-        HIPC(hipMemcpyAsync(A.list + k * N, mb.idx, mb.rows * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        launch_map_rows(ctx->stream, mb.dev(), A.list + k * N);
+        HIPC(hipGetLastError());
         A.n[k] = mb.rows;
       } else {
         A.n[k] = -1;

@@ -13,35 +13,13 @@
 // values, since v' = v + dv), Ldv_j, Ldw_j of the corrections, Lv0, Lw0 of the
 // step's initial state, and per-row / per-element sensitivity accumulators.
 #include "kernels.hpp"
+#include "device.hpp"
 
 #include <type_traits>
 
 namespace sdc {
 
 namespace {
-
-struct Row {
-  int inst;
-  int row;
-  bool valid;
-};
-
-// Same XCD-aware order of map entries as the forward kernels.
-__device__ inline int logical_block(int nblk) {
-  const int b = static_cast<int>(blockIdx.x);
-  const int x = b & 7, q = nblk >> 3, rem = nblk & 7;
-  return x * q + min(x, rem) + (b >> 3);
-}
-
-__device__ inline Row map_row(const Map& map) {
-  const int4 bm = map.blk[logical_block(map.nblk)];
-  const int pos = bm.y + static_cast<int>(threadIdx.x);
-  Row r;
-  r.inst = bm.x;
-  r.valid = pos < bm.z;
-  r.row = r.valid ? (map.idx ? map.idx[pos] : pos) : 0;
-  return r;
-}
 
 // Aliev-Panfilov partial derivatives (paper Sec. 5.1) with respect to v, w, a.
 __device__ inline void ap_partials(double v, double w, const double* p, double& Iv, double& Iw,
@@ -148,11 +126,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_apsi(Map all, int m, int64_t N, 
   const int i = rw.row;
   double aps = 0.0;
   if constexpr (DIA) {
-    const int32_t* off = A.off + rw.inst * A.nd;
-    const int lo = static_cast<int>(A.node_off[rw.inst]), hi = static_cast<int>(A.node_off[rw.inst + 1]);
     for (int d = 0; d < A.nd; ++d) {
-      const int k = i + off[d];
-      aps += A.dval[d * N + i] * psi[(k < lo || k >= hi) ? i : k];
+      const int k = i + rw.off(d);
+      aps += A.dval[d * N + i] * psi[(k < rw.lo || k >= rw.hi) ? i : k];
     }
   } else {
     for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) aps += A.val[e] * psi[A.col[e]];

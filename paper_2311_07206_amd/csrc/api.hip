@@ -40,8 +40,7 @@ int fail(sdc_ctx* c, int code, const char* fmt, ...) {
 
 int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap) {
   const int ni = ctx->n_inst;
-  TRY(dalloc(ctx, &mb->blk, nblk_cap));
-  TRY(dalloc(ctx, &mb->blk_nb, nblk_cap));
+  TRY(dalloc(ctx, &mb->rec, nblk_cap));
   TRY(dalloc(ctx, &mb->inst_blk0, ni + 1));
   TRY(dalloc(ctx, &mb->inst_nblk, ni + 1));
   TRY(dalloc(ctx, &mb->inst_cnt, ni + 1));
@@ -163,13 +162,14 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   return SDC_OK;
 }
 
-// Build the work map of a device list into dyn slot `slot` and fetch its sizes.
+// Build the work map of a device list into dyn slot `slot` (its padded copy
+// in list[slot]) and fetch its sizes.
 int map_list(sdc_ctx* ctx, int slot, const int32_t* idx, int64_t n) {
   MapBuf& mb = ctx->dyn[slot];
-  launch_map_from_list(ctx->stream, idx, n, ctx->N, ctx->node_off_d, ctx->n_inst, ctx->rowptr, mb.next());
+  launch_map_from_list(ctx->stream, idx, n, ctx->N, ctx->n_inst, ctx->rowptr, ctx->next(mb), ctx->list[slot]);
   HIPC(hipGetLastError());
   TRY(fetch_map(ctx, &mb));
-  mb.idx = idx;
+  mb.idx = ctx->list[slot];
   return SDC_OK;
 }
 
@@ -262,7 +262,7 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     const int slot = ctx->cur == 0 ? 1 : 0;
     MapBuf& nm = ctx->dyn[slot];
     launch_select(ctx->stream, map, ni, ctx->rowptr, ctx->amax, ctx->prm.theta, ctx->sel_cnt,
-                  ctx->sel_nnz, ctx->list[slot], nm.next(), ctx->zv());
+                  ctx->sel_nnz, ctx->list[slot], nullptr, ctx->next(nm), ctx->zv());
     HIPC(hipGetLastError());
     TRY(fetch_map(ctx, &nm));
     nm.idx = ctx->list[slot];
@@ -361,6 +361,7 @@ int build_dia(sdc_ctx* ctx) {
     TRY(dalloc(ctx, &ctx->dia_H, val.size() * M));
   }
   HIPC(hipMemcpyAsync(ctx->dia_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  ctx->dia_off_h = off;
   HIPC(hipMemcpyAsync(ctx->dia_A, val.data(), val.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   for (int m = 0; m < M; ++m)
     for (int i = 0; i < ni; ++i)
@@ -577,28 +578,35 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   }
 
   // all-rows work map (host-built)
-  std::vector<int4> blk;
+  std::vector<BlkRec> rec;
   std::vector<int32_t> blk0(n_inst + 1), nblk(n_inst + 1), cnt(n_inst + 1), aoff(n_inst + 1);
   std::vector<int64_t> innz(n_inst + 1, 0);
   for (int i = 0; i < n_inst; ++i) {
     const int32_t lo = static_cast<int32_t>(node_off[i]), hi = static_cast<int32_t>(node_off[i + 1]);
-    blk0[i] = static_cast<int32_t>(blk.size());
+    blk0[i] = static_cast<int32_t>(rec.size());
     cnt[i] = hi - lo;
     aoff[i] = lo;
     innz[i] = ctx->host.rowptr[hi] - ctx->host.rowptr[lo];
-    int bi = 0;
-    for (int32_t b = lo; b < hi; b += kBlock, ++bi) blk.push_back(make_int4(i, b, std::min(b + kBlock, hi), bi));
-    nblk[i] = bi;
+    nblk[i] = (hi - lo + kBlock - 1) / kBlock;
+    for (int bi = 0; bi < nblk[i]; ++bi) {
+      BlkRec r{};
+      r.inst = i;
+      r.beg = lo + bi * kBlock;
+      r.end = std::min(r.beg + kBlock, hi);
+      r.bi = bi;
+      r.nb = nblk[i];
+      r.lo = lo;
+      r.hi = hi;
+      for (int d = 0; d < ctx->nd; ++d) r.off[d] = ctx->dia_off_h[static_cast<size_t>(i) * ctx->nd + d];
+      rec.push_back(r);
+    }
   }
   aoff[n_inst] = static_cast<int32_t>(N);
-  const int32_t nblk_all = static_cast<int32_t>(blk.size());
+  const int32_t nblk_all = static_cast<int32_t>(rec.size());
   TRY(alloc_map(ctx, &ctx->all, nblk_all));
   TRY(alloc_map(ctx, &ctx->dyn[0], nblk_all));
   TRY(alloc_map(ctx, &ctx->dyn[1], nblk_all));
-  HIPC(hipMemcpyAsync(ctx->all.blk, blk.data(), blk.size() * sizeof(int4), hipMemcpyHostToDevice, ctx->stream));
-  std::vector<int32_t> blk_nb(blk.size());
-  for (size_t b = 0; b < blk.size(); ++b) blk_nb[b] = nblk[blk[b].x];
-  HIPC(hipMemcpyAsync(ctx->all.blk_nb, blk_nb.data(), blk_nb.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->all.rec, rec.data(), rec.size() * sizeof(BlkRec), hipMemcpyHostToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(ctx->all.inst_blk0, blk0.data(), n_inst * 4, hipMemcpyHostToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(ctx->all.inst_nblk, nblk.data(), n_inst * 4, hipMemcpyHostToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(ctx->all.inst_cnt, cnt.data(), n_inst * 4, hipMemcpyHostToDevice, ctx->stream));
@@ -611,8 +619,8 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     ctx->all.cnt[i] = cnt[i];
     ctx->all.nnz[i] = innz[i];
   }
-  TRY(dalloc(ctx, &ctx->list[0], N));
-  TRY(dalloc(ctx, &ctx->list[1], N));
+  TRY(dalloc(ctx, &ctx->list[0], static_cast<size_t>(nblk_all) * kBlock));
+  TRY(dalloc(ctx, &ctx->list[1], static_cast<size_t>(nblk_all) * kBlock));
   for (int q = 0; q < 2; ++q) {
     TRY(dalloc(ctx, &ctx->cg_scal[q], static_cast<size_t>(kScal) * n_inst));
     TRY(dalloc(ctx, &ctx->part[q], 4 * static_cast<size_t>(nblk_all)));
@@ -742,10 +750,7 @@ int sdc_get_active(sdc_ctx* ctx, int32_t* idx, int64_t* n) {
   const MapBuf& mb = ctx->curmap();
   if (n) *n = mb.rows;
   if (idx) {
-    if (mb.idx)
-      HIPC(hipMemcpyAsync(idx, mb.idx, mb.rows * 4, hipMemcpyDeviceToDevice, ctx->stream));
-    else
-      launch_iota(ctx->stream, idx, ctx->N);
+    launch_map_rows(ctx->stream, mb.dev(), idx);
     HIPC(hipGetLastError());
   }
   return SDC_OK;
@@ -804,7 +809,7 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
   MapBuf& nm = ctx->dyn[1];
   ZeroVecs none{{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}, nullptr, 0, 0};
   launch_select(ctx->stream, ctx->dyn[0].dev(), ctx->n_inst, ctx->rowptr, amax, theta, ctx->sel_cnt,
-                ctx->sel_nnz, idx_out, nm.next(), none);
+                ctx->sel_nnz, ctx->list[1], idx_out, ctx->next(nm), none);
   HIPC(hipGetLastError());
   TRY(fetch_map(ctx, &nm));
   *n_out = nm.rows;

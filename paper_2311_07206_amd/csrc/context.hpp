@@ -15,24 +15,27 @@
 
 namespace sdc {
 
+static_assert(kRecDiag >= kMaxDiag, "block records must hold every diagonal offset");
+
 struct MapBuf {
-  int4* blk = nullptr;
-  int32_t* blk_nb = nullptr;
+  BlkRec* rec = nullptr;
   int32_t* inst_blk0 = nullptr;
   int32_t* inst_nblk = nullptr;
   int32_t* inst_cnt = nullptr;
   int64_t* inst_nnz = nullptr;
   int32_t* aoff = nullptr;
   int32_t* totals = nullptr;
-  const int32_t* idx = nullptr;       // list the map indexes (null: all rows)
+  const int32_t* idx = nullptr;       // padded list the map indexes (null: all rows)
   // host mirror, valid after the map is built
   int32_t nblk = 0;
   int64_t rows = 0;
   std::vector<int32_t> cnt;
   std::vector<int64_t> nnz;
 
-  Map dev() const { return Map{blk, blk_nb, inst_blk0, inst_nblk, idx, nblk}; }
-  NextMap next() const { return NextMap{blk, blk_nb, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals}; }
+  Map dev() const { return Map{rec, inst_blk0, inst_nblk, idx, nblk}; }
+  NextMap next(const int64_t* node_off, const int32_t* dia_off, int nd) const {
+    return NextMap{rec, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals, node_off, dia_off, nd};
+  }
 };
 
 struct Stimulus {
@@ -51,6 +54,8 @@ using sdc::MapBuf;
 using sdc::Stimulus;
 using sdc::CgState;
 using sdc::Mat;
+using sdc::NextMap;
+using sdc::BlkRec;
 using sdc::ZeroVecs;
 using sdc::kScal;
 
@@ -75,6 +80,7 @@ struct sdc_ctx {
   // diagonal storage (nd > 0 when every instance has at most kMaxDiag offsets)
   int nd = 0;
   int32_t* dia_off = nullptr;      // [n_inst][nd]
+  std::vector<int32_t> dia_off_h;
   double *dia_A = nullptr, *dia_H = nullptr;   // [nd][N], [M][nd][N]
   bool use_dia = false;
   double t_csr_us = 0.0, t_dia_us = 0.0;
@@ -96,7 +102,7 @@ struct sdc_ctx {
 
   MapBuf all;
   MapBuf dyn[2];
-  int32_t* list[2] = {nullptr, nullptr};
+  int32_t* list[2] = {nullptr, nullptr};   // padded lists of dyn[0], dyn[1]: [nblk of all][kBlock]
   int cur = -1;   // -1: all rows; 0/1: dyn slot
 
   int32_t* h_i32 = nullptr;   // pinned staging
@@ -144,6 +150,8 @@ struct sdc_ctx {
   std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
 
   const MapBuf& curmap() const { return cur < 0 ? all : dyn[cur]; }
+  // output description for building a map into mb (records carry the diagonal offsets)
+  NextMap next(const MapBuf& mb) const { return mb.next(node_off_d, nd > 0 ? dia_off : nullptr, nd); }
   CgState cg() const { return CgState{cg_done, cg_iters, cg_blk_done}; }
   Mat matA(bool dia) const {
     return Mat{rowptr, colidx, Aval, dia_off, dia_A, node_off_d, dia ? nd : 0};

@@ -1,0 +1,60 @@
+// Device helpers shared by the forward and reverse kernels: block order and
+// the row a thread owns in a work map.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace sdc {
+
+constexpr int kRecWords = static_cast<int>(sizeof(BlkRec) / sizeof(int32_t));
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8).  Give each XCD a contiguous range of map entries instead, so that
+// neighbouring row blocks, which read each other's rows through the stencil,
+// share one L2.  A bijection of [0, nblk) when the grid has nblk workgroups.
+__device__ inline int logical_block(int nblk) {
+  const int b = static_cast<int>(blockIdx.x);
+  const int x = b & 7, q = nblk >> 3, rem = nblk & 7;
+  return x * q + min(x, rem) + (b >> 3);
+}
+
+// The thread's row and its block's map entry.  Each wave reads the entry with
+// one vector load (lane q holds word q) and takes the fields from the lanes:
+// vector loads complete in order, so the entry and the list entry of the row
+// (at a position known from the block index alone) arrive in one round trip.
+struct Row {
+  int word;   // word (lane mod kRecWords) of the block record
+  int inst, beg, end, bi, nb, lo, hi;
+  int listed; // the list entry at the thread's position (0 without a list)
+  int row;
+  int blk;    // logical block: position of the entry in the map
+  bool valid;
+  // diagonal offset d of the instance (uniform d)
+  __device__ int off(int d) const { return __builtin_amdgcn_readlane(word, offsetof(BlkRec, off) / 4 + d); }
+};
+
+// LIST: 1 the map has a list, 0 all rows, -1 decided at run time.
+template <int LIST = -1>
+__device__ inline Row map_row(const Map& map) {
+  const int L = logical_block(map.nblk);
+  const int t = static_cast<int>(threadIdx.x);
+  const int32_t* words = reinterpret_cast<const int32_t*>(map.rec + L);
+  Row r;
+  r.word = words[min(t & 63, kRecWords - 1)];
+  r.listed = 0;
+  if (LIST == 1 || (LIST < 0 && map.idx)) r.listed = map.idx[L * kBlock + t];
+  r.inst = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, inst) / 4);
+  r.beg = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, beg) / 4);
+  r.end = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, end) / 4);
+  r.bi = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, bi) / 4);
+  r.nb = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, nb) / 4);
+  r.lo = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, lo) / 4);
+  r.hi = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, hi) / 4);
+  r.blk = L;
+  r.valid = t < r.end - r.beg;
+  const bool listed_map = LIST == 1 || (LIST < 0 && map.idx);
+  r.row = r.valid ? (listed_map ? r.listed : r.beg + t) : 0;
+  return r;
+}
+
+}  // namespace sdc

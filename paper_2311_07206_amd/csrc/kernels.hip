@@ -3,11 +3,12 @@
 // Every active-row kernel is launched on a work map: block b owns up to
 // kBlock consecutive positions of the active list of one instance, one row
 // per thread.  Per-instance scalars (CG alpha/beta, norms) are reduced
-// deterministically: each block writes one partial per quantity, and the last
-// block of the instance to finish (a device-scope counter) sums the partials
-// of its instance in block order and writes the scalars.  No floating-point
-// atomics are used, so repeated runs are bitwise identical.
+// deterministically and without fences: each block writes one partial per
+// quantity, and every block of the next launch sums its instance's partials
+// in block order.  No floating-point atomics are used, so repeated runs are
+// bitwise identical.
 #include "kernels.hpp"
+#include "device.hpp"
 
 #include <hip/hip_ext.h>
 
@@ -42,53 +43,23 @@ __device__ inline void block_sum(double (&v)[NV], double* sh /* [4 * NV] */) {
   }
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
-// b mod 8).  Give each XCD a contiguous range of map entries instead, so that
-// neighbouring row blocks, which read each other's rows through the stencil,
-// share one L2.  A bijection of [0, nblk) when the grid has nblk workgroups.
-__device__ inline int logical_block(int nblk) {
-  const int b = static_cast<int>(blockIdx.x);
-  const int x = b & 7, q = nblk >> 3, rem = nblk & 7;
-  return x * q + min(x, rem) + (b >> 3);
-}
-
-struct Row {
-  int inst;
-  int row;
-  int blk;     // logical block: position of this block's entry in the work map
-  bool valid;
-};
-
-__device__ inline Row map_row(const Map& map) {
-  const int L = logical_block(map.nblk);
-  const int4 bm = map.blk[L];
-  const int pos = bm.y + static_cast<int>(threadIdx.x);
-  Row r;
-  r.inst = bm.x;
-  r.blk = L;
-  r.valid = pos < bm.z;
-  r.row = r.valid ? (map.idx ? map.idx[pos] : pos) : 0;
-  return r;
-}
-
 // Visit the stored entries (value, column) of row i of matrix A.  Storage S:
 // 0 = CSR, -1 = diagonal storage with A.nd diagonals, S > 0 = diagonal
 // storage with S diagonals known at compile time (fully unrolled, so all
-// loads of the row are in flight together).
+// loads of the row are in flight together).  The diagonal offsets and the
+// instance's row range come from the block's map entry.
 template <int S, class F>
-__device__ __forceinline__ void for_entries(const Mat& A, int64_t N, int inst, int i, F&& f) {
+__device__ __forceinline__ void for_entries(const Mat& A, int64_t N, const Row& rw, int i, F&& f) {
   if constexpr (S == 0) {
     const int e1 = A.rowptr[i + 1];
     for (int e = A.rowptr[i]; e < e1; ++e) f(A.val[e], A.col[e]);
   } else {
     constexpr int kUnroll = S > 0 ? S : 1;
     const int nd = S > 0 ? S : A.nd;
-    const int32_t* off = A.off + inst * nd;
-    const int lo = static_cast<int>(A.node_off[inst]), hi = static_cast<int>(A.node_off[inst + 1]);
 #pragma unroll kUnroll
     for (int d = 0; d < nd; ++d) {
-      const int c = i + off[d];
-      f(A.dval[d * N + i], (c < lo || c >= hi) ? i : c);
+      const int c = i + rw.off(d);
+      f(A.dval[d * N + i], (c < rw.lo || c >= rw.hi) ? i : c);
     }
   }
 }
@@ -171,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
   double Av[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) Av[j] = 0.0;
-  for_entries<S>(A, N, rw.inst, i, [&](double a, int k) {
+  for_entries<S>(A, N, rw, i, [&](double a, int k) {
 #pragma unroll
     for (int j = 0; j < M; ++j) Av[j] += a * v[j * N + k];
   });
@@ -211,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A
   const int i = rw.row;
   double ay = 0.0;
   if (m > 0) {
-    for_entries<S>(A, N, rw.inst, i, [&](double a, int k) {
+    for_entries<S>(A, N, rw, i, [&](double a, int k) {
       double y = 0.0;
 #pragma unroll
       for (int j = 0; j < M - 1; ++j)
@@ -289,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_
   if (rw.valid) {
     const int i = rw.row;
     double acc = 0.0;
-    for_entries<S>(H, N, rw.inst, i, [&](double h, int k) { acc += h * (dinv[k] * r0[k]); });
+    for_entries<S>(H, N, rw, i, [&](double h, int k) { acc += h * (dinv[k] * r0[k]); });
     const double ri = r0[i], ui = dinv[i] * ri;
     w0[i] = acc;
     s[0] = ri * ui;
@@ -299,8 +270,34 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_
   write_partials<3>(s, rw.blk, part_out, sh);
 }
 
-template <int S>
-__global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, const double* __restrict__ dinv,
+// Block total of NV values, formed by every thread in the same order
+// (bitwise the total block_sum leaves in thread 0).  One barrier.
+template <int NV>
+__device__ inline void block_total(double (&v)[NV], double* sh /* [4 * NV] */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wid * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = (sh[k] + sh[NV + k]) + (sh[2 * NV + k] + sh[3 * NV + k]);
+}
+
+// One launch per iteration; FIRST is launch 0 (beta = 0, no previous p, s).
+// Memory round trips before the arithmetic: (1) the block record, the list
+// entry of the thread's row and the block's stop flag; (2) everything else
+// the iteration reads: the instance's partial sums and scalars from the
+// previous launch and the row's values and neighbour sums
+//   a_r = sum_k h_ik dinv_k r_k,  a_w = sum_k h_ik dinv_k w_k,  a_s = sum_k h_ik dinv_k s_k,
+// so that H u with u = dinv (r - alpha (w + beta s)) is a_r - alpha (a_w + beta a_s).
+// Threads past the block's last row load row 0's values (in bounds) and
+// contribute zeros.
+template <int S, bool FIRST, int LIST>
+__global__ __launch_bounds__(kBlock) void k_cg_iter(CgState cg, Map map, int64_t N, Mat H,
+                                                    const double* __restrict__ dinv,
                                                     double* __restrict__ x, double* __restrict__ p,
                                                     const double* __restrict__ r_in,
                                                     const double* __restrict__ w_in,
@@ -312,78 +309,75 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
                                                     double* __restrict__ part_out,
                                                     const double* __restrict__ scal_in,
                                                     double* __restrict__ scal_out, double rtol2,
-                                                    int maxit, CgState cg) {
-  __shared__ double sh[16];
-  // first round trip: this block's map entry, its instance's block count and
-  // its own stop flag (all indexed by the logical block)
-  const int L = logical_block(map.nblk);
-  const int4 bm = map.blk[L];
-  const int nb = map.blk_nb[L];
-  if (cg.blk_done[L]) return;
-  const int inst = bm.x, b0 = L - bm.w;
-  const int pos = bm.y + static_cast<int>(threadIdx.x);
-  const bool valid = pos < bm.z;
-  const int i = valid ? (map.idx ? map.idx[pos] : pos) : 0;
-  // Everything that does not depend on this iteration's scalars is loaded
-  // before they are formed: the previous launch's partial sums of the
-  // instance, and the row's own values and neighbour sums
-  //   a_r = sum_k h_ik dinv_k r_k,  a_w = sum_k h_ik dinv_k w_k,  a_s = sum_k h_ik dinv_k s_k,
-  // so that H u with u = dinv (r - alpha (w + beta s)) is a_r - alpha (a_w + beta a_s).
+                                                    int maxit) {
+  __shared__ double sh_in[16], sh_out[16];
+  // first round trip: the block's map entry and stop flag, the list entry of the thread's row
+  const Row rw = map_row<LIST>(map);
+  const int L = rw.blk;
+  // Early exit of a stopped block.  The test includes invariants of the
+  // arguments (it >= 0, nd >= 0) and of the list (entries >= 0), so that
+  // every kernel-argument cache line and the list entry are read before the
+  // branch rather than after it.  (The map and the stop flags are in the
+  // first argument line.)
+  if (cg.blk_done[L] | (it < 0) | (H.nd < 0) | (rw.listed < 0)) return;
+  const int inst = rw.inst, nb = rw.nb, b0 = L - rw.bi;
+  const bool valid = rw.valid;
+  const int i = rw.row;
+  // second round trip, issued together: the row's values and neighbour sums,
+  // the instance's scalars and partial sums from the previous launch
+  double a_r = 0.0, a_w = 0.0, a_s = 0.0;
+  for_entries<S>(H, N, rw, i, [&](double h, int k) {
+    const double hd = h * dinv[k];
+    a_r += hd * r_in[k];
+    a_w += hd * w_in[k];
+    if (!FIRST) a_s += hd * s_in[k];
+  });
+  const double si = FIRST ? 0.0 : s_in[i];
+  const double p_old = FIRST ? 0.0 : p[i];
+  const double di = dinv[i], ri = r_in[i], wi = w_in[i], x_old = x[i];
+  double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
+  if (!FIRST) {
+    const double* sc = scal_in + inst * kScal;
+    sc_rz = sc[kRZ];
+    sc_alpha = sc[kAlpha];
+    sc_bb = sc[kBB];
+  }
+  // the first 4 kBlock partials by unconditional loads (a clamped index, a 0/1
+  // weight), the rest, if any, by a loop
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nb; b += kBlock) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = static_cast<int>(threadIdx.x) + q * kBlock;
+    const double* pp = part_in + 4 * (b0 + min(b, nb - 1));
+    const double wgt = b < nb ? 1.0 : 0.0;
+    acc[0] += wgt * pp[0];
+    acc[1] += wgt * pp[1];
+    acc[2] += wgt * pp[2];
+  }
+  for (int b = threadIdx.x + 4 * kBlock; b < nb; b += kBlock) {
     const double* pp = part_in + 4 * (b0 + b);
     acc[0] += pp[0];
     acc[1] += pp[1];
     acc[2] += pp[2];
   }
-  double a_r = 0.0, a_w = 0.0, a_s = 0.0;
-  double di = 0.0, ri = 0.0, wi = 0.0, si = 0.0, p_old = 0.0;
-  if (valid) {
-    if (it == 0) {
-      for_entries<S>(H, N, inst, i, [&](double h, int k) {
-        const double hd = h * dinv[k];
-        a_r += hd * r_in[k];
-        a_w += hd * w_in[k];
-      });
-    } else {
-      for_entries<S>(H, N, inst, i, [&](double h, int k) {
-        const double hd = h * dinv[k];
-        a_r += hd * r_in[k];
-        a_w += hd * w_in[k];
-        a_s += hd * s_in[k];
-      });
-      si = s_in[i];
-      p_old = p[i];
-    }
-    di = dinv[i];
-    ri = r_in[i];
-    wi = w_in[i];
-  }
-  block_sum<3>(acc, sh);
-  if (threadIdx.x == 0) {
-    sh[12] = acc[0];
-    sh[13] = acc[1];
-    sh[14] = acc[2];
-  }
-  __syncthreads();
-  const double gamma = sh[12], delta = sh[13], rr = sh[14];
+  block_total<3>(acc, sh_in);
+  const double gamma = acc[0], delta = acc[1], rr = acc[2];
   double alpha, beta, bb;
-  if (it == 0) {
+  if (FIRST) {
     bb = rr;
     beta = 0.0;
     alpha = gamma / delta;
   } else {
-    const double* sc = scal_in + inst * kScal;
-    bb = sc[kBB];
-    beta = gamma / sc[kRZ];
-    alpha = gamma / (delta - beta * gamma / sc[kAlpha]);
+    bb = sc_bb;
+    beta = gamma / sc_rz;
+    alpha = gamma / (delta - beta * gamma / sc_alpha);
   }
   int status = 0;
   if (!isfinite(rr)) status = 3;
   else if (rr <= rtol2 * bb) status = 1;
   else if (it >= maxit) status = 2;
   else if (!isfinite(alpha) || !(alpha > 0.0)) status = 3;
-  if (bm.w == 0 && threadIdx.x == 0) {
+  if (rw.bi == 0 && threadIdx.x == 0) {
     // block 0 of the instance records the outcome and the scalars
     cg.done[inst] = status;
     cg.iters[inst] = it;
@@ -402,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
     const double ui = di * ri;
     const double pi = ui + beta * p_old;
     const double sv = wi + beta * si;
-    x[i] += alpha * pi;
+    x[i] = x_old + alpha * pi;
     p[i] = pi;
     s_out[i] = sv;
     const double rn = ri - alpha * sv;
@@ -413,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Map map, int64_t N, Mat H, c
     s[1] = w_new * un;
     s[2] = rn * rn;
   }
-  write_partials<3>(s, L, part_out, sh);
+  write_partials<3>(s, L, part_out, sh_out);
 }
 
 // Post-solve update of node m (eq. final-sdc):
@@ -538,10 +532,16 @@ __device__ void build_map(const int32_t* cnt, const int32_t* aoff, int n_inst, c
       if (nm.inst_blk0[mid] <= b) lo = mid; else hi = mid - 1;
     }
     const int bi = b - nm.inst_blk0[lo];
-    const int beg = aoff[lo] + bi * kBlock;
-    const int end = min(beg + kBlock, aoff[lo] + cnt[lo]);
-    nm.blk[b] = make_int4(lo, beg, end, bi);
-    nm.blk_nb[b] = nm.inst_nblk[lo];
+    BlkRec& r = nm.rec[b];
+    r.inst = lo;
+    r.beg = aoff[lo] + bi * kBlock;
+    r.end = min(r.beg + kBlock, aoff[lo] + cnt[lo]);
+    r.bi = bi;
+    r.nb = nm.inst_nblk[lo];
+    r.lo = static_cast<int32_t>(nm.node_off[lo]);
+    r.hi = static_cast<int32_t>(nm.node_off[lo + 1]);
+    r.pad = 0;
+    for (int d = 0; d < nm.nd; ++d) r.off[d] = nm.dia_off[lo * nm.nd + d];
   }
 }
 
@@ -569,10 +569,13 @@ __global__ __launch_bounds__(kScanThreads) void k_select_scan(Map map, int n_ins
 }
 
 // Pass 3: stable write of the kept rows; zero the work vectors on dropped rows.
+// A kept row's list position q (over all instances) becomes position
+// inst_blk0 * kBlock + (q - aoff) of its instance in the padded list.
 __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* __restrict__ amax,
                                                          double theta,
-                                                         const int32_t* __restrict__ sel_off,
-                                                         int32_t* __restrict__ idx_out, ZeroVecs zv) {
+                                                         const int32_t* __restrict__ sel_off, NextMap nm,
+                                                         int32_t* __restrict__ idx_pad,
+                                                         int32_t* __restrict__ idx_compact, ZeroVecs zv) {
   __shared__ int wc[4];
   const Row rw = map_row(map);
   const bool keep = rw.valid && keep_row(amax[rw.row], theta);
@@ -583,7 +586,11 @@ __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* 
   int base = sel_off[rw.blk];
   for (int q = 0; q < wid; ++q) base += wc[q];
   const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-  if (keep) idx_out[base + rank] = rw.row;
+  if (keep) {
+    const int q = base + rank;
+    idx_pad[nm.inst_blk0[rw.inst] * kBlock + (q - nm.aoff[rw.inst])] = rw.row;
+    if (idx_compact) idx_compact[q] = rw.row;
+  }
   if (rw.valid && !keep && zv.dv) {
     const int i = rw.row;
 #pragma unroll
@@ -604,12 +611,11 @@ __global__ __launch_bounds__(kBlock) void k_zero_rows(Map map, ZeroVecs zv) {
 // Work map of an ascending list: instance i's entries are those in
 // [node_off[i], node_off[i+1]); found by binary search.  One block.
 __global__ __launch_bounds__(kScanThreads) void k_map_from_list(const int32_t* __restrict__ idx,
-                                                                int32_t n, int64_t N,
-                                                                const int64_t* __restrict__ node_off,
-                                                                int n_inst,
+                                                                int32_t n, int64_t N, int n_inst,
                                                                 const int32_t* __restrict__ rowptr,
                                                                 NextMap nm) {
   int32_t* aoff_scratch = nm.aoff;
+  const int64_t* node_off = nm.node_off;
   // validate: entries in [0, N) and strictly ascending; a bad list gives an
   // empty map and totals[2] = 1, so no later kernel indexes with it
   __shared__ int bad;
@@ -647,6 +653,25 @@ __global__ __launch_bounds__(kScanThreads) void k_map_from_list(const int32_t* _
   __syncthreads();
   build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, n);
   if (threadIdx.x == 0) nm.totals[2] = bad;
+}
+
+// Copy of a list (validated by k_map_from_list) into the padded layout of its map.
+__global__ __launch_bounds__(kBlock) void k_pad_list(const int32_t* __restrict__ idx, int32_t n, int n_inst,
+                                                     NextMap nm, int32_t* __restrict__ idx_pad) {
+  const int q = static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+  if (q >= n || nm.totals[2] != 0) return;
+  int lo = 0, hi = n_inst - 1;   // last instance whose list starts at or before q
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nm.aoff[mid] <= q) lo = mid; else hi = mid - 1;
+  }
+  idx_pad[nm.inst_blk0[lo] * kBlock + (q - nm.aoff[lo])] = idx[q];
+}
+
+// The rows of a map as one list: entry b's rows go to positions beg..end.
+__global__ __launch_bounds__(kBlock) void k_map_rows(Map map, int32_t* __restrict__ out) {
+  const Row rw = map_row(map);
+  if (rw.valid) out[rw.beg + static_cast<int>(threadIdx.x)] = rw.row;
 }
 
 inline dim3 grid(int nblk) { return dim3(static_cast<unsigned>(nblk > 0 ? nblk : 1)); }
@@ -712,17 +737,23 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
                     int maxit, const CgState& cg, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (map.nblk <= 0) return;
-  dispatch_storage(H.nd, [&](auto st) {
+  auto go = [&](auto kern) {
     if (ev_start) {
       // events stamped by the dispatch itself: they time the kernel's execution
-      hipExtLaunchKernelGGL((k_cg_iter<decltype(st)::value>), grid(map.nblk), dim3(kBlock), 0, s, ev_start,
-                            ev_stop, 0, map, N, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out, s_out, it,
-                            part_in, part_out, scal_in, scal_out, rtol2, maxit, cg);
+      hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(kBlock), 0, s, ev_start, ev_stop, 0, cg, map, N, H, dinv, x,
+                            p, r_in, w_in, s_in, r_out, w_out, s_out, it, part_in, part_out, scal_in, scal_out,
+                            rtol2, maxit);
     } else {
-      k_cg_iter<decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, dinv, x, p, r_in, w_in, s_in,
-                                                                       r_out, w_out, s_out, it, part_in, part_out,
-                                                                       scal_in, scal_out, rtol2, maxit, cg);
+      kern<<<grid(map.nblk), kBlock, 0, s>>>(cg, map, N, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out, s_out, it,
+                                             part_in, part_out, scal_in, scal_out, rtol2, maxit);
     }
+  };
+  dispatch_storage(H.nd, [&](auto st) {
+    constexpr int S = decltype(st)::value;
+    if (map.idx)
+      it == 0 ? go(k_cg_iter<S, true, 1>) : go(k_cg_iter<S, false, 1>);
+    else
+      it == 0 ? go(k_cg_iter<S, true, 0>) : go(k_cg_iter<S, false, 0>);
   });
 }
 
@@ -739,12 +770,12 @@ void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const d
 
 void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* rowptr,
                    const double* amax, double theta, int32_t* sel_cnt, int32_t* sel_nnz,
-                   int32_t* idx_out, const NextMap& nm, const ZeroVecs& zv) {
+                   int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm, const ZeroVecs& zv) {
   if (map.nblk > 0)
     k_select_count<<<grid(map.nblk), kBlock, 0, s>>>(map, rowptr, amax, theta, sel_cnt, sel_nnz);
   k_select_scan<<<1, kScanThreads, 0, s>>>(map, n_inst, sel_cnt, sel_nnz, nm);
   if (map.nblk > 0)
-    k_select_write<<<grid(map.nblk), kBlock, 0, s>>>(map, amax, theta, sel_cnt, idx_out, zv);
+    k_select_write<<<grid(map.nblk), kBlock, 0, s>>>(map, amax, theta, sel_cnt, nm, idx_pad, idx_compact, zv);
 }
 
 void launch_zero_rows(hipStream_t s, const Map& map, const ZeroVecs& zv) {
@@ -752,11 +783,17 @@ void launch_zero_rows(hipStream_t s, const Map& map, const ZeroVecs& zv) {
   k_zero_rows<<<grid(map.nblk), kBlock, 0, s>>>(map, zv);
 }
 
-void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t N,
-                          const int64_t* node_off, int n_inst, const int32_t* rowptr,
-                          const NextMap& nm) {
-  k_map_from_list<<<1, kScanThreads, 0, s>>>(idx, static_cast<int32_t>(n), N, node_off, n_inst,
-                                             rowptr, nm);
+void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t N, int n_inst,
+                          const int32_t* rowptr, const NextMap& nm, int32_t* idx_pad) {
+  k_map_from_list<<<1, kScanThreads, 0, s>>>(idx, static_cast<int32_t>(n), N, n_inst, rowptr, nm);
+  if (n > 0)
+    k_pad_list<<<dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
+        idx, static_cast<int32_t>(n), n_inst, nm, idx_pad);
+}
+
+void launch_map_rows(hipStream_t s, const Map& map, int32_t* out) {
+  if (map.nblk <= 0) return;
+  k_map_rows<<<grid(map.nblk), kBlock, 0, s>>>(map, out);
 }
 
 }  // namespace sdc

@@ -19,17 +19,32 @@ struct CollArgs {
   double dt;
 };
 
-// Work map: block b processes positions [beg, end) of the active list of
-// instance `inst`; `bi` is its index among that instance's blocks.  Blocks of
-// one instance are consecutive starting at inst_blk0[inst].  When idx is null
-// the positions are row numbers (all rows active).
+constexpr int kRecDiag = 32;   // diagonal offsets held per block record
+
+// Work map entry of one block.  The block processes kBlock consecutive
+// positions [beg, end) of its instance's active list; `bi` is its index among
+// that instance's blocks, which are consecutive entries of the map.  Every
+// field depends only on the entry, so a kernel reads the record with the
+// list entries of its rows in one round trip.
+struct BlkRec {
+  int32_t inst;
+  int32_t beg, end;   // list positions; row numbers when the map has no list
+  int32_t bi;
+  int32_t nb;         // blocks of the instance
+  int32_t lo, hi;     // the instance's rows [lo, hi)
+  int32_t pad;
+  int32_t off[kRecDiag];   // the instance's diagonal offsets (diagonal storage)
+};
+
+// Work map.  The list is stored padded by block: the rows of entry b are
+// idx[b * kBlock + t] for t < end - beg (the tail of each block is unused).
+// When idx is null the positions are row numbers (all rows active).
 struct Map {
-  const int4* blk;         // {inst, beg, end, bi}
-  const int32_t* blk_nb;   // per entry: number of blocks of its instance
-  const int32_t* inst_blk0;
-  const int32_t* inst_nblk;
+  const BlkRec* rec;
+  const int32_t* inst_blk0;   // first entry of each instance
+  const int32_t* inst_nblk;   // entries of each instance
   const int32_t* idx;
-  int32_t nblk;            // grid size
+  int32_t nblk;               // grid size
 };
 
 struct Csr {
@@ -94,16 +109,20 @@ void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const d
 
 // Active-set compaction I_{k+1} = {i in I_k : amax_i >= theta} (three passes).
 // sel_cnt [nblk] and sel_nnz [nblk] are per-block scratch; next-map outputs
-// and per-instance totals are written by the scan pass.
+// and per-instance totals are written by the scan pass.  The block records
+// take the instance ranges from node_off and, with diagonal storage (nd > 0),
+// the instance's offsets from dia_off [n_inst][nd].
 struct NextMap {
-  int4* blk;
-  int32_t* blk_nb;
+  BlkRec* rec;
   int32_t* inst_blk0;
   int32_t* inst_nblk;
   int32_t* inst_cnt;       // kept rows per instance
   int64_t* inst_nnz;       // stored A entries in kept rows per instance
-  int32_t* aoff;           // [n_inst+1] list offset of each instance's first row
+  int32_t* aoff;           // [n_inst+1] compact list position of each instance's first row
   int32_t* totals;         // [0] total blocks, [1] total rows in the list, [2] invalid list
+  const int64_t* node_off;
+  const int32_t* dia_off;
+  int nd;
 };
 // Vectors that must be zero on inactive rows: the double-buffered CG vectors
 // gathered at neighbouring columns (r, w, s) and the M node corrections dv[M][N].
@@ -114,17 +133,20 @@ struct ZeroVecs {
   int M;
   int64_t N;
 };
+// The kept rows are written to idx_pad (the padded list of the next map) and,
+// when idx_compact is not null, also as one ascending list there.
 void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* rowptr,
                    const double* amax, double theta, int32_t* sel_cnt, int32_t* sel_nnz,
-                   int32_t* idx_out, const NextMap& nm, const ZeroVecs& zv);
+                   int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm, const ZeroVecs& zv);
 // Zero the ZeroVecs entries on every row of the map (used before a pinned set).
 void launch_zero_rows(hipStream_t s, const Map& map, const ZeroVecs& zv);
-// Work map of an arbitrary ascending list (per-instance split by node_off).
-// A list with entries outside [0, N) or not strictly ascending yields an
-// empty map and totals[2] = 1.
-void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t N,
-                          const int64_t* node_off, int n_inst, const int32_t* rowptr,
-                          const NextMap& nm);
+// Work map of an arbitrary ascending list (per-instance split by node_off),
+// with the list copied padded to idx_pad.  A list with entries outside
+// [0, N) or not strictly ascending yields an empty map and totals[2] = 1.
+void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t N, int n_inst,
+                          const int32_t* rowptr, const NextMap& nm, int32_t* idx_pad);
+// The rows of a map as one ascending list (list positions beg..end of each entry).
+void launch_map_rows(hipStream_t s, const Map& map, int32_t* out);
 
 // H_m = ML + c A (pattern of A) and its inverse diagonal.
 void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32_t* diagpos,
