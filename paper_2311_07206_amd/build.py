@@ -11,6 +11,9 @@ SOURCES = ["api.hip", "adjoint.hip", "kernels.hip", "adjoint_kernels.hip", "asse
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments that lead the list are preloaded into scalar registers
+    # at wave launch (the CG iteration orders its arguments for this)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-result", "-Wno-unknown-pragmas",
 ]
 

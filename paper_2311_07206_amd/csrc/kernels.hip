@@ -295,8 +295,14 @@ __device__ inline void block_total(double (&v)[NV], double* sh /* [4 * NV] */) {
 // so that H u with u = dinv (r - alpha (w + beta s)) is a_r - alpha (a_w + beta a_s).
 // Threads past the block's last row load row 0's values (in bounds) and
 // contribute zeros.
+// The arguments the first round trip needs come first, as plain pointers and
+// integers, so that they can be preloaded into scalar registers at wave
+// launch (the library is built with kernel-argument preloading).
 template <int S, bool FIRST, int LIST>
-__global__ __launch_bounds__(kBlock) void k_cg_iter(CgState cg, Map map, int64_t N, Mat H,
+__global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_done, const BlkRec* __restrict__ rec,
+                                                    const int32_t* __restrict__ idx, int nblk, int it,
+                                                    const double* __restrict__ part_in,
+                                                    const double* __restrict__ scal_in, int64_t N, Mat H,
                                                     const double* __restrict__ dinv,
                                                     double* __restrict__ x, double* __restrict__ p,
                                                     const double* __restrict__ r_in,
@@ -304,22 +310,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(CgState cg, Map map, int64_t
                                                     const double* __restrict__ s_in,
                                                     double* __restrict__ r_out,
                                                     double* __restrict__ w_out,
-                                                    double* __restrict__ s_out, int it,
-                                                    const double* __restrict__ part_in,
+                                                    double* __restrict__ s_out,
                                                     double* __restrict__ part_out,
-                                                    const double* __restrict__ scal_in,
-                                                    double* __restrict__ scal_out, double rtol2,
-                                                    int maxit) {
+                                                    double* __restrict__ scal_out, double rtol2, int maxit,
+                                                    int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   __shared__ double sh_in[16], sh_out[16];
   // first round trip: the block's map entry and stop flag, the list entry of the thread's row
+  const Map map{rec, nullptr, nullptr, idx, nblk};
   const Row rw = map_row<LIST>(map);
   const int L = rw.blk;
   // Early exit of a stopped block.  The test includes invariants of the
-  // arguments (it >= 0, nd >= 0) and of the list (entries >= 0), so that
-  // every kernel-argument cache line and the list entry are read before the
-  // branch rather than after it.  (The map and the stop flags are in the
-  // first argument line.)
-  if (cg.blk_done[L] | (it < 0) | (H.nd < 0) | (rw.listed < 0)) return;
+  // arguments (it >= 0, nd >= 0, output buffers given) and of the list
+  // (entries >= 0), so that every cache line of the kernel arguments and the
+  // list entry are read before the branch rather than after it.
+  if (blk_done[L] | (it < 0) | (H.nd < 0) | (rw.listed < 0) | (s_out == nullptr) | (iters == nullptr)) return;
   const int inst = rw.inst, nb = rw.nb, b0 = L - rw.bi;
   const bool valid = rw.valid;
   const int i = rw.row;
@@ -379,15 +383,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(CgState cg, Map map, int64_t
   else if (!isfinite(alpha) || !(alpha > 0.0)) status = 3;
   if (rw.bi == 0 && threadIdx.x == 0) {
     // block 0 of the instance records the outcome and the scalars
-    cg.done[inst] = status;
-    cg.iters[inst] = it;
+    done[inst] = status;
+    iters[inst] = it;
     double* so = scal_out + inst * kScal;
     so[kRZ] = gamma;
     so[kAlpha] = alpha;
     so[kBB] = bb;
   }
   if (status != 0) {
-    if (threadIdx.x == 0) cg.blk_done[L] = status;
+    if (threadIdx.x == 0) blk_done[L] = status;
     return;
   }
   double s[3] = {0.0, 0.0, 0.0};
@@ -740,12 +744,13 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
   auto go = [&](auto kern) {
     if (ev_start) {
       // events stamped by the dispatch itself: they time the kernel's execution
-      hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(kBlock), 0, s, ev_start, ev_stop, 0, cg, map, N, H, dinv, x,
-                            p, r_in, w_in, s_in, r_out, w_out, s_out, it, part_in, part_out, scal_in, scal_out,
-                            rtol2, maxit);
+      hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(kBlock), 0, s, ev_start, ev_stop, 0, cg.blk_done, map.rec,
+                            map.idx, map.nblk, it, part_in, scal_in, N, H, dinv, x, p, r_in, w_in, s_in, r_out,
+                            w_out, s_out, part_out, scal_out, rtol2, maxit, cg.done, cg.iters);
     } else {
-      kern<<<grid(map.nblk), kBlock, 0, s>>>(cg, map, N, H, dinv, x, p, r_in, w_in, s_in, r_out, w_out, s_out, it,
-                                             part_in, part_out, scal_in, scal_out, rtol2, maxit);
+      kern<<<grid(map.nblk), kBlock, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, it, part_in, scal_in, N, H, dinv,
+                                             x, p, r_in, w_in, s_in, r_out, w_out, s_out, part_out, scal_out, rtol2,
+                                             maxit, cg.done, cg.iters);
     }
   };
   dispatch_storage(H.nd, [&](auto st) {
