@@ -49,6 +49,7 @@ int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap) {
   TRY(dalloc(ctx, &mb->totals, 4));
   mb->cnt.assign(ni, 0);
   mb->nnz.assign(ni, 0);
+  mb->n_inst = ni;
   return SDC_OK;
 }
 
@@ -62,9 +63,11 @@ int fetch_map(sdc_ctx* ctx, MapBuf* mb) {
   mb->nblk = ctx->h_i32[0];
   mb->rows = ctx->h_i32[1];
   if (ctx->h_i32[2] != 0) return fail(ctx, SDC_ERR_ARG, "index list not strictly ascending or out of range");
+  mb->max_nb = 0;
   for (int i = 0; i < ni; ++i) {
     mb->cnt[i] = ctx->h_i32[4 + i];
     mb->nnz[i] = ctx->h_i64[i];
+    mb->max_nb = std::max(mb->max_nb, (mb->cnt[i] + kBlock - 1) / kBlock);
   }
   return SDC_OK;
 }
@@ -121,7 +124,8 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
         const int a = it & 1, o = a ^ 1;
         launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
                        ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
-                       ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg(), timed ? ctx->ev[2 * b] : nullptr,
+                       ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
+                       timed ? ctx->ev[2 * b] : nullptr,
                        timed ? ctx->ev[2 * b + 1] : nullptr);
       }
       HIPC(hipGetLastError());
@@ -192,7 +196,8 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
     const int a = it & 1, o = a ^ 1;
     launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
                    ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
-                   rtol2, ctx->prm.cg_maxit, ctx->cg(), timed ? ctx->ev[2 * (*ev_off + it)] : nullptr,
+                   rtol2, ctx->prm.cg_maxit, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
+                   timed ? ctx->ev[2 * (*ev_off + it)] : nullptr,
                    timed ? ctx->ev[2 * (*ev_off + it) + 1] : nullptr);
   }
   HIPC(hipGetLastError());
@@ -618,11 +623,13 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   for (int i = 0; i < n_inst; ++i) {
     ctx->all.cnt[i] = cnt[i];
     ctx->all.nnz[i] = innz[i];
+    ctx->all.max_nb = std::max(ctx->all.max_nb, nblk[i]);
   }
   TRY(dalloc(ctx, &ctx->list[0], static_cast<size_t>(nblk_all) * kBlock));
   TRY(dalloc(ctx, &ctx->list[1], static_cast<size_t>(nblk_all) * kBlock));
   for (int q = 0; q < 2; ++q) {
     TRY(dalloc(ctx, &ctx->cg_scal[q], static_cast<size_t>(kScal) * n_inst));
+    if (q == 0) TRY(dalloc(ctx, &ctx->cg_tot, 4 * static_cast<size_t>(n_inst)));
     TRY(dalloc(ctx, &ctx->part[q], 4 * static_cast<size_t>(nblk_all)));
   }
   TRY(dalloc(ctx, &ctx->cg_done, n_inst));

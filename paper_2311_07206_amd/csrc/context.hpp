@@ -28,11 +28,14 @@ struct MapBuf {
   const int32_t* idx = nullptr;       // padded list the map indexes (null: all rows)
   // host mirror, valid after the map is built
   int32_t nblk = 0;
+  int32_t n_inst = 0;
+  int32_t max_nb = 0;                 // most blocks of one instance
   int64_t rows = 0;
   std::vector<int32_t> cnt;
   std::vector<int64_t> nnz;
 
-  Map dev() const { return Map{rec, inst_blk0, inst_nblk, idx, nblk}; }
+  Map dev() const { return Map{rec, inst_blk0, inst_nblk, idx, nblk, n_inst}; }
+  double* tot_if_large(double* tot) const { return max_nb > kTotBlocks ? tot : nullptr; }
   NextMap next(const int64_t* node_off, const int32_t* dia_off, int nd) const {
     return NextMap{rec, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals, node_off, dia_off, nd};
   }
@@ -96,6 +99,7 @@ struct sdc_ctx {
   double *r[2] = {nullptr, nullptr}, *wv[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
 
   double* cg_scal[2] = {nullptr, nullptr};   // [n_inst][kScal] by launch parity
+  double* cg_tot = nullptr;                  // [n_inst][4] partial-sum totals (large instances)
   double* part[2] = {nullptr, nullptr};      // [nblk][4] by launch parity
   int32_t *cg_done = nullptr, *cg_iters = nullptr, *cg_blk_done = nullptr;
   int32_t *sel_cnt = nullptr, *sel_nnz = nullptr;

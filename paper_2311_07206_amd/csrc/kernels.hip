@@ -298,7 +298,34 @@ __device__ inline void block_total(double (&v)[NV], double* sh /* [4 * NV] */) {
 // The arguments the first round trip needs come first, as plain pointers and
 // integers, so that they can be preloaded into scalar registers at wave
 // launch (the library is built with kernel-argument preloading).
-template <int S, bool FIRST, int LIST>
+// Per-instance totals of a launch's partial sums (one block per instance),
+// in the order the iteration kernel would sum them.
+__global__ __launch_bounds__(kBlock) void k_cg_totals(const int32_t* __restrict__ inst_blk0,
+                                                      const int32_t* __restrict__ inst_nblk,
+                                                      const double* __restrict__ part, double* __restrict__ tot) {
+  __shared__ double sh[16];
+  const int inst = blockIdx.x, b0 = inst_blk0[inst], nb = inst_nblk[inst];
+  double acc[3] = {0.0, 0.0, 0.0};
+  int b = threadIdx.x;
+  for (; b + 3 * kBlock < nb; b += 4 * kBlock) {   // four independent loads in flight
+    double v[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[q][k] = part[4 * (b0 + b + q * kBlock) + k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[k] += v[q][k];
+  }
+  for (; b < nb; b += kBlock)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] += part[4 * (b0 + b) + k];
+  block_total<3>(acc, sh);
+  if (threadIdx.x < 3) tot[4 * inst + threadIdx.x] = acc[threadIdx.x];
+}
+
+template <int S, bool FIRST, int LIST, bool TOT>
 __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_done, const BlkRec* __restrict__ rec,
                                                     const int32_t* __restrict__ idx, int nblk, int it,
                                                     const double* __restrict__ part_in,
@@ -316,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
                                                     int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   __shared__ double sh_in[16], sh_out[16];
   // first round trip: the block's map entry and stop flag, the list entry of the thread's row
-  const Map map{rec, nullptr, nullptr, idx, nblk};
+  const Map map{rec, nullptr, nullptr, idx, nblk, 0};
   const Row rw = map_row<LIST>(map);
   const int L = rw.blk;
   // Early exit of a stopped block.  The test includes invariants of the
@@ -346,25 +373,26 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     sc_alpha = sc[kAlpha];
     sc_bb = sc[kBB];
   }
-  // the first 4 kBlock partials by unconditional loads (a clamped index, a 0/1
-  // weight), the rest, if any, by a loop
   double acc[3] = {0.0, 0.0, 0.0};
+  if constexpr (TOT) {
+    // totals formed by k_cg_totals (part_in holds them, [n_inst][4])
+    acc[0] = part_in[4 * inst];
+    acc[1] = part_in[4 * inst + 1];
+    acc[2] = part_in[4 * inst + 2];
+  } else {
+    // the instance's partials (at most kTotBlocks of them) by unconditional
+    // loads: a clamped index and a 0/1 weight
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int b = static_cast<int>(threadIdx.x) + q * kBlock;
-    const double* pp = part_in + 4 * (b0 + min(b, nb - 1));
-    const double wgt = b < nb ? 1.0 : 0.0;
-    acc[0] += wgt * pp[0];
-    acc[1] += wgt * pp[1];
-    acc[2] += wgt * pp[2];
+    for (int q = 0; q < kTotBlocks / kBlock; ++q) {
+      const int b = static_cast<int>(threadIdx.x) + q * kBlock;
+      const double* pp = part_in + 4 * (b0 + min(b, nb - 1));
+      const double wgt = b < nb ? 1.0 : 0.0;
+      acc[0] += wgt * pp[0];
+      acc[1] += wgt * pp[1];
+      acc[2] += wgt * pp[2];
+    }
+    block_total<3>(acc, sh_in);
   }
-  for (int b = threadIdx.x + 4 * kBlock; b < nb; b += kBlock) {
-    const double* pp = part_in + 4 * (b0 + b);
-    acc[0] += pp[0];
-    acc[1] += pp[1];
-    acc[2] += pp[2];
-  }
-  block_total<3>(acc, sh_in);
   const double gamma = acc[0], delta = acc[1], rr = acc[2];
   double alpha, beta, bb;
   if (FIRST) {
@@ -739,26 +767,39 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     double* x, double* p, const double* r_in, const double* w_in, const double* s_in,
                     double* r_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
-                    int maxit, const CgState& cg, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                    int maxit, const CgState& cg, double* tot, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (map.nblk <= 0) return;
+  const double* pin = part_in;
+  if (tot) {
+    k_cg_totals<<<dim3(static_cast<unsigned>(map.n_inst)), kBlock, 0, s>>>(map.inst_blk0, map.inst_nblk,
+                                                                                 part_in, tot);
+    pin = tot;
+  }
   auto go = [&](auto kern) {
     if (ev_start) {
       // events stamped by the dispatch itself: they time the kernel's execution
       hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(kBlock), 0, s, ev_start, ev_stop, 0, cg.blk_done, map.rec,
-                            map.idx, map.nblk, it, part_in, scal_in, N, H, dinv, x, p, r_in, w_in, s_in, r_out,
+                            map.idx, map.nblk, it, pin, scal_in, N, H, dinv, x, p, r_in, w_in, s_in, r_out,
                             w_out, s_out, part_out, scal_out, rtol2, maxit, cg.done, cg.iters);
     } else {
-      kern<<<grid(map.nblk), kBlock, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, it, part_in, scal_in, N, H, dinv,
+      kern<<<grid(map.nblk), kBlock, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, it, pin, scal_in, N, H, dinv,
                                              x, p, r_in, w_in, s_in, r_out, w_out, s_out, part_out, scal_out, rtol2,
                                              maxit, cg.done, cg.iters);
     }
   };
   dispatch_storage(H.nd, [&](auto st) {
     constexpr int S = decltype(st)::value;
-    if (map.idx)
-      it == 0 ? go(k_cg_iter<S, true, 1>) : go(k_cg_iter<S, false, 1>);
+    auto pick = [&](auto tt) {
+      constexpr bool T = decltype(tt)::value;
+      if (map.idx)
+        it == 0 ? go(k_cg_iter<S, true, 1, T>) : go(k_cg_iter<S, false, 1, T>);
+      else
+        it == 0 ? go(k_cg_iter<S, true, 0, T>) : go(k_cg_iter<S, false, 0, T>);
+    };
+    if (tot)
+      pick(std::true_type{});
     else
-      it == 0 ? go(k_cg_iter<S, true, 0>) : go(k_cg_iter<S, false, 0>);
+      pick(std::false_type{});
   });
 }
 

@@ -45,6 +45,7 @@ struct Map {
   const int32_t* inst_nblk;   // entries of each instance
   const int32_t* idx;
   int32_t nblk;               // grid size
+  int32_t n_inst;
 };
 
 struct Csr {
@@ -92,7 +93,10 @@ void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, do
 // one launch per iteration reading buffers (r, w, s)_in, writing (r, w, s)_out.
 // Launch `it` reads the partial sums and scalars of launch it-1 (part_in,
 // scal_in) and writes its own (part_out, scal_out); the start kernel's
-// partials are the input of launch 0.
+// partials are the input of launch 0.  Every block sums its instance's
+// partials itself unless `tot` is given ([n_inst][4] scratch): then a
+// one-block-per-instance pass forms the totals first (for instances of more
+// than kTotBlocks blocks, where the per-block sums would dominate).
 void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const Mat& H,
                      const double* dinv, const double* r0, double* w0, double* part_out,
                      const CgState& cg);
@@ -100,8 +104,9 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     double* x, double* p, const double* r_in, const double* w_in, const double* s_in,
                     double* r_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
-                    int maxit, const CgState& cg, hipEvent_t ev_start = nullptr,
+                    int maxit, const CgState& cg, double* tot, hipEvent_t ev_start = nullptr,
                     hipEvent_t ev_stop = nullptr);
+constexpr int kTotBlocks = 4 * kBlock;
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                  const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
                  double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,

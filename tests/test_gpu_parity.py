@@ -105,6 +105,25 @@ def test_restricted_pcg_matches_oracle(M, m):
         assert abs(iters[0] - ito) <= 1
 
 
+def test_pcg_on_instance_larger_than_in_kernel_reduction():
+    # more than 1024 blocks of 256 rows: the partial sums go through the
+    # per-instance totals pass
+    P = config1(n=700)
+    s = _solver(P)
+    orc = build(P)
+    rng = np.random.default_rng(11)
+    for frac in (1.0, 0.6):
+        n = int(frac * P.N)
+        idx = np.arange(P.N) if frac == 1.0 else np.sort(rng.choice(P.N, size=n, replace=False))
+        assert (n + 255) // 256 > 1024
+        b = rng.standard_normal(P.N)
+        print(f"[pcg large] n={n}", flush=True)
+        x, iters = s.solve(2, torch.tensor(idx, dtype=torch.int32, device=DEV), torch.tensor(b, device=DEV))
+        xo, ito = jacobi_pcg(orc.H[2], b, idx, P.cg_rtol)
+        assert rel(x.cpu().numpy(), xo) < 1e-11
+        assert abs(iters[0] - ito) <= 1
+
+
 def test_pcg_edge_cases():
     P = config0(n=50)
     s = _solver(P)
@@ -271,6 +290,14 @@ def test_full_size_2d_steps():
     ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli, idx_replay=sets)
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
     assert stats[0][0]["n_active"] == 512 * 512
+
+
+def test_large_2d_step():
+    # one adaptive step on 600 x 600 (over 1024 blocks per sweep at the start)
+    P = config1(n=600, theta=1e-7, n_steps=1)
+    gv, gw, sets, stats, _ = gpu_run(P, 1)
+    ov, ow, _ = run(build(P), P.v_init, P.w_init, 1, P.K, P.stimuli, idx_replay=sets)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
 
 def test_errors_are_reported():
