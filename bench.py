@@ -48,6 +48,67 @@ def measured_traffic():
     return float(fields["measured bytes per launch"]), float(fields["algorithmic bytes per launch"])
 
 
+def summarize_trace(path):
+    """Markdown summary of a rocprofv3 --kernel-trace CSV: per-kernel totals and
+    the CG iteration kernel's duration by grid size."""
+    import collections
+    import csv
+    import re
+    durs, grid = collections.defaultdict(list), collections.defaultdict(list)
+    for row in csv.DictReader(open(path)):
+        m = re.search(r"(k_\w+)", row["Kernel_Name"])
+        name = m.group(1) if m else row["Kernel_Name"].split("(")[0][:60]
+        d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+        durs[name].append(d)
+        if name == "k_cg_iter":
+            grid[int(row["Grid_Size_X"]) // int(row["Workgroup_Size_X"])].append(d)
+    total = sum(sum(v) for v in durs.values())
+    out = ["| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
+    for k, v in sorted(durs.items(), key=lambda z: -sum(z[1])):
+        out.append(f"| {k} | {len(v)} | {sum(v) / 1e6:.2f} | {np.mean(v) / 1e3:.3f} | {100 * sum(v) / total:.1f}% |")
+    v = np.array(durs.get("k_cg_iter", [0]))
+    out += ["", f"k_cg_iter: {len(v)} dispatches, mean {v.mean() / 1e3:.3f} us", "",
+            "| blocks (256 rows) | dispatches | median us | mean us |", "|---|---|---|---|"]
+    bins = [(1, 128), (128, 256), (256, 512), (512, 1024), (1024, 1025), (1025, 1 << 30)]
+    for lo, hi in bins:
+        x = np.array([d for g, ds in grid.items() if lo <= g < hi for d in ds])
+        if len(x):
+            out.append(f"| {lo}..{hi - 1} | {len(x)} | {np.median(x) / 1e3:.2f} | {x.mean() / 1e3:.2f} |")
+    return "\n".join(out)
+
+
+def summarize_counters(fetch_csv, write_csv):
+    """Pair FETCH_SIZE and WRITE_SIZE runs dispatch by dispatch (KiB per
+    dispatch).  A 256 MiB device copy (reads and writes 262144 KiB) calibrates
+    each counter; the CG iteration's launches that perform an update (writes
+    above 1 KiB) give the measured HBM bytes per launch."""
+    import csv
+    rows = []
+    for path in (fetch_csv, write_csv):
+        r = sorted(csv.DictReader(open(path)), key=lambda x: int(x["Dispatch_Id"]))
+        rows.append(r)
+    f, w = rows
+    assert len(f) == len(w), "the two runs must dispatch the same kernels"
+    cg_f, cg_w, copy = [], [], []
+    for a, b in zip(f, w):
+        assert a["Kernel_Name"] == b["Kernel_Name"]
+        if "k_cg_iter" in a["Kernel_Name"]:
+            cg_f.append(float(a["Counter_Value"]))
+            cg_w.append(float(b["Counter_Value"]))
+        elif "copyBuffer" in a["Kernel_Name"] and float(b["Counter_Value"]) > 200000:
+            copy.append((float(a["Counter_Value"]), float(b["Counter_Value"])))
+    cg_f, cg_w = np.array(cg_f), np.array(cg_w)
+    work = cg_w > 1.0
+    ff = 262144.0 / np.mean([c[0] for c in copy])
+    fw = 262144.0 / np.mean([c[1] for c in copy])
+    fetch_kib, write_kib = cg_f[work].mean(), cg_w[work].mean()
+    measured = (ff * fetch_kib + fw * write_kib) * 1024.0
+    return {"copy_fetch_kib": [c[0] for c in copy], "copy_write_kib": [c[1] for c in copy],
+            "fetch_factor": ff, "write_factor": fw, "dispatches": int(len(cg_f)), "updating": int(work.sum()),
+            "fetch_kib_per_launch": fetch_kib, "write_kib_per_launch": write_kib,
+            "measured_bytes_per_launch": measured}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +125,10 @@ def parse():
                     help="account CG kernel bytes from the first step (matches counter runs)")
     ap.add_argument("--calib", action="store_true",
                     help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
+                    help="print a summary of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="pair rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, print JSON and exit")
     return ap.parse_args()
 
 
@@ -102,6 +167,12 @@ def step_bytes(N, M):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(*args.summarize_counters), indent=1))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
