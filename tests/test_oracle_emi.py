@@ -1,0 +1,155 @@
+"""Pins of the cell-by-cell (EMI) oracle against what the model and the mathematics fix.
+
+- the membrane jump mass annihilates constants and gives each cell's
+  indicator the energy C_m x (cell perimeter);
+- A maps constants to the Robin term only (eps x outer perimeter in total)
+  and annihilates affine functions on interior rows of every subdomain;
+- converged sweeps reproduce the Radau-IIA collocation solution of the DAE
+  (independent Newton solve of the collocation equations);
+- the collocation solution conserves charge: the Robin-weighted mean of the
+  potential on the outer boundary vanishes at every node (M 1 = 0, the ionic
+  currents cancel pairwise, A 1 = eps * robin);
+- in the lumped limit (huge conductivities and Robin coefficient) one cell
+  obeys the membrane ODE C_m v' = -I(v, w), w' = R(v, w) (SciPy's Radau);
+- restriction: rows outside the active set and sites with an inactive
+  intracellular node keep their values; the sets are nested.
+"""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle import ionic
+from oracle.emi import EMI, EmiSDC, build, collocation_solution, run
+from workloads.emi import config3
+
+
+def small(**kw):
+    base = dict(nc=3, nr=2, nx=5, ny=4)
+    base.update(kw)
+    return config3(**base)
+
+
+def test_membrane_mass():
+    P = small()
+    mod = EMI(P)
+    Mm = mod.M.toarray()
+    assert np.allclose(Mm, Mm.T, atol=0)
+    assert np.abs(Mm @ np.ones(P.N)).max() <= 1e-15 * np.abs(Mm).max()
+    assert np.linalg.eigvalsh(Mm).min() > -1e-15 * np.abs(Mm).max()
+    perim = 2 * (100e-4 + 16e-4)
+    for c in range(3 * 2):
+        ind = (P.node_cell == c).astype(float)
+        assert abs(ind @ Mm @ ind - P.cm * perim) <= 1e-12 * perim
+
+
+def test_stiffness_constants_and_affine_functions():
+    P = small()
+    mod = EMI(P)
+    A = mod.A
+    assert abs(A - A.T).max() == 0.0
+    # row sums of the element part cancel to rounding (entries up to |A|max)
+    assert np.allclose(A @ np.ones(P.N), P.eps * P.robin_len, rtol=0, atol=1e-15 * 16 * abs(A).max())
+    W = 3 * (100e-4 + 2e-4) + 2e-4
+    H = 2 * (16e-4 + 2e-4) + 2e-4
+    # the element part cancels to rounding of the nnz entries
+    assert abs(np.ones(P.N) @ A @ np.ones(P.N) - P.eps * 2 * (W + H)) <= 1e-15 * A.nnz * abs(A).max()
+    x, y = P.coords[:, 0], P.coords[:, 1]
+    u = 2 * x - 3 * y
+    interior = np.ones(P.N, dtype=bool)
+    interior[P.mem_intra] = False
+    interior[P.mem_extra] = False
+    interior[P.robin_len > 0] = False
+    interior[P.gap_a] = False
+    interior[P.gap_b] = False
+    assert interior.sum() > 20
+    assert np.abs((A @ u)[interior]).max() <= 1e-12 * np.abs(A).max() * np.abs(u).max()
+    # a cell's indicator only feels the gap junctions of its end faces:
+    # g_gap * cell height per neighbour in its row
+    for c in range(3 * 2):
+        ind = (P.node_cell == c).astype(float)
+        n_nb = (c % 3 > 0) + (c % 3 < 2)
+        assert abs(ind @ (A @ ind) - P.g_gap * 16e-4 * n_nb) <= 1e-12 * abs(A).max() * A.nnz * 1e-3
+
+
+@pytest.mark.parametrize("M", [2, 3])
+def test_converged_sweeps_equal_collocation_solution(M):
+    P = config3(nc=2, nr=1, nx=3, ny=3, M=M, dt=0.05, theta=0.0)
+    u0 = np.zeros(P.N)
+    u0[P.stimuli[0][1]] = 1.0
+    w0 = np.full(len(P.mem_intra), 0.05)
+    sdc = build(P, direct=True)
+    st = sdc.spread(u0, w0)
+    idx = np.arange(P.N)
+    for _ in range(60):
+        sdc.sweep(st, idx)
+    Uc, Wc = collocation_solution(sdc.model, M, P.dt, u0, w0)
+    d = st["u"] - Uc
+    si, se = sdc.model.si, sdc.model.se
+    # the constant mode of the potentials is fixed only by the weak Robin
+    # term (eigenvalue ~ dt eps |boundary|), so it carries rounding amplified
+    # by the condition number; the transmembrane voltage, the gating and the
+    # mean-free potential are well conditioned
+    assert np.abs(d[:, si] - d[:, se]).max() <= 1e-12
+    assert np.abs(d - d.mean(axis=1, keepdims=True)).max() <= 1e-12 * np.abs(Uc).max()
+    assert np.abs(d).max() <= 1e-8 * np.abs(Uc).max()
+    assert np.abs(st["w"] - Wc).max() <= 1e-12 * max(np.abs(Wc).max(), 1.0)
+    # charge conservation of the collocation solution: robin^T u_m = 0 at every
+    # node (to the accuracy of the constant mode)
+    for m in range(M):
+        assert abs(P.robin_len @ Uc[m]) <= 1e-8 * P.robin_len.sum() * np.abs(Uc).max()
+        assert abs(P.robin_len @ st["u"][m]) <= 1e-8 * P.robin_len.sum() * np.abs(Uc).max()
+
+
+def test_single_cell_lumped_limit_follows_membrane_ode():
+    big = 1e6
+    P = config3(nc=1, nr=1, nx=4, ny=3, sigma_i=big, sigma_e=big, eps=big, M=3, dt=0.02, theta=0.0)
+    sdc = build(P, direct=True)
+    u = np.zeros(P.N)
+    u[P.node_cell == 0] = 0.3          # transmembrane voltage 0.3 above the threshold a = 0.15
+    w = np.zeros(len(P.mem_intra))
+    n_steps, K = 25, 12
+    u, w, _ = run(sdc, u, w, n_steps, K)
+    p = np.asarray(P.ionic[0])
+
+    def rhs(t, y):
+        v, g = y
+        return [-ionic.current(v, g, p) / P.cm, ionic.rate(v, g, p)]
+
+    ref = solve_ivp(rhs, (0.0, n_steps * P.dt), [0.3, 0.0], method="Radau", rtol=1e-12, atol=1e-14)
+    v_end = u[P.mem_intra] - u[P.mem_extra]
+    assert np.abs(v_end - ref.y[0, -1]).max() <= 1e-5
+    assert np.abs(w - ref.y[1, -1]).max() <= 1e-5
+    assert abs(v_end.mean() - 0.3) > 0.05          # the voltage moved
+
+
+def test_restriction_freezes_inactive_rows_and_sites():
+    P = small(theta=1e-3)
+    sdc = build(P)
+    u0 = np.zeros(P.N)
+    u0[P.stimuli[0][1]] = 1.0
+    w0 = np.zeros(len(P.mem_intra))
+    st = sdc.spread(u0, w0)
+    idx, _ = sdc.sweep(st, np.arange(P.N))
+    assert 0 < idx.size < P.N
+    before = {k: st[k].copy() for k in ("u", "w", "I", "R")}
+    nxt, info = sdc.sweep(st, idx)
+    assert np.all(np.isin(nxt, idx))
+    off = np.setdiff1d(np.arange(P.N), idx)
+    assert np.array_equal(st["u"][:, off], before["u"][:, off])
+    active = np.zeros(P.N, dtype=bool)
+    active[idx] = True
+    frozen = ~active[sdc.model.si]
+    for k in ("w", "I", "R"):
+        assert np.array_equal(st[k][:, frozen], before[k][:, frozen])
+    assert np.all(info["du"][:, off] == 0.0)
+
+
+def test_adaptive_run_tracks_nonadaptive():
+    P = small(theta=1e-8)
+    u0 = np.zeros(P.N)
+    w0 = np.zeros(len(P.mem_intra))
+    ua, wa, loga = run(build(P), u0, w0, 4, P.K, P.stimuli)
+    P0 = small(theta=0.0)
+    un, wn, _ = run(build(P0), u0, w0, 4, P0.K, P0.stimuli)
+    assert any(info["n_active"] < P.N for step in loga for info in step)
+    assert np.abs(ua - un).max() <= 1e-5 * np.abs(un).max()
