@@ -1,6 +1,6 @@
 /*
  * sdc.h -- C ABI of the MI355X (gfx950) adaptive spectral-deferred-correction
- * library for monodomain reaction-diffusion systems.
+ * library for monodomain and cell-by-cell (EMI) reaction-diffusion systems.
  *
  * Problem (paper Sec. 2.2, eq. "abstract monodomain"; abstract form B z' = F(z),
  * Sec. 3):  P1 finite elements on simplices give
@@ -101,7 +101,43 @@ int sdc_set_stream(sdc_ctx* ctx, void* stream);
 
 /* ---- setup (paper Sec. 2.2: P1 discretisation) ------------------------ */
 
-/* Assemble ML and A on the host and upload everything the sweeps need.
+/* Cell-by-cell (EMI) model (paper Sec. 2.1, eq. "cell-by-cell model", its
+ * weak form, and the discrete system of eqs. "abstract reaction diffusion" /
+ * "abstract gating").  The unknowns are the potentials u of every subdomain
+ * (intracellular and extracellular nodes; a membrane point exists twice) and
+ * the gating variables of the membrane sites:
+ *
+ *     M u' = -A u - b(u, w),        w_s' = R(v_s, w_s),   v_s = u_i(s) - u_e(s),
+ *
+ *   M = C_m sum_s l_s (e_i - e_e)(e_i - e_e)^T      (membrane mass, singular)
+ *   b = sum_s l_s I(v_s, w_s) (e_i - e_e)
+ *   A = elements (per-subdomain conductivity in elem_tensor)
+ *       + eps * diag(robin_len)                     (Robin condition, outer boundary)
+ *       + g_gap sum_g l_g (e_a - e_b)(e_a - e_b)^T  (linear gap junctions, implicit)
+ *
+ * In sdc_step the arrays v, w hold u [N] and the gating variable of site s
+ * at its intracellular node (other entries of w are left unchanged).  The
+ * drop rule measures max_m |du_m| per node; a site is updated in a sweep iff
+ * its intracellular node is active.  One instance only; CSR storage; the
+ * reverse pass and sdc_set_coefficients are not available for this model
+ * (SDC_ERR_STATE). */
+typedef struct {
+  int64_t n_mem;              /* membrane sites                                 */
+  const int32_t* mem_intra;   /* host int32[n_mem]: intracellular node of site s */
+  const int32_t* mem_extra;   /* host int32[n_mem]: extracellular node of site s */
+  const double* mem_len;      /* host double[n_mem]: lumped membrane length > 0  */
+  double cm;                  /* membrane capacitance C_m > 0                   */
+  int64_t n_gap;              /* gap-junction node pairs                        */
+  const int32_t* gap_a;       /* host int32[n_gap]                              */
+  const int32_t* gap_b;       /* host int32[n_gap]                              */
+  const double* gap_len;      /* host double[n_gap]: lumped face length >= 0    */
+  double g_gap;               /* gap-junction conductance per length >= 0       */
+  const double* robin_len;    /* host double[N]: lumped outer-boundary length   */
+  double eps;                 /* Robin coefficient >= 0                         */
+} sdc_emi;
+
+/* Assemble ML and A (or, with emi, M and A) on the host and upload
+ * everything the sweeps need.
  *  dim          1, 2 or 3 (simplices with dim+1 vertices)
  *  n_inst       number of independent instances (>= 1)
  *  node_off     host int64[n_inst+1]: instance i owns nodes [node_off[i], node_off[i+1])
@@ -112,11 +148,14 @@ int sdc_set_stream(sdc_ctx* ctx, void* stream);
  *  node_sigma   host double[N]: conductivity multiplier; element value is the
  *               mean over its vertices, A = sum_T sigma_T |T| G_T D_T G_T^T
  *  ionic        host double[n_inst][6]: Aliev-Panfilov (k, a, eps0, mu1, mu2, s)
+ *  emi          NULL for the monodomain model; else the cell-by-cell
+ *               couplings above (n_inst must be 1; each node belongs to at
+ *               most one membrane site; SDC_ERR_ARG otherwise)
  * May be called once per context. */
 int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* params, int32_t dim, int32_t n_inst,
                    const int64_t* node_off, const double* coords, const int64_t* elem_off,
                    const int32_t* elems, const double* elem_tensor, const double* node_sigma,
-                   const double* ionic);
+                   const double* ionic, const sdc_emi* emi);
 
 /* Stimulus: at the start of the step whose interval [t, t+dt) contains t_on,
  * set v = value on the listed nodes (host int32[n]) before spreading. */
@@ -125,8 +164,9 @@ int sdc_add_stimulus(sdc_ctx* ctx, double t_on, const int32_t* nodes, int64_t n,
 /* Sizes of the assembled system: N, nnz of A, Nw (= N for monodomain). */
 int sdc_get_sizes(const sdc_ctx* ctx, int64_t* n, int64_t* nnz, int64_t* nw);
 
-/* Copy the assembled CSR of A and the lumped mass to host arrays
- * rowptr int32[N+1], col int32[nnz], val double[nnz], ml double[N]. */
+/* Copy the assembled CSR of A and the lumped mass (cell-by-cell model: the
+ * diagonal of the membrane mass) to host arrays rowptr int32[N+1],
+ * col int32[nnz], val double[nnz], ml double[N]. */
 int sdc_get_system(sdc_ctx* ctx, int32_t* rowptr, int32_t* col, double* val, double* ml);
 
 /* ---- time stepping (paper Sec. 3, eq. final-sdc; Sec. 4.2) ------------- */

@@ -53,6 +53,13 @@ class Info(ctypes.Structure):
                 ("t_dia_us", c_double), ("redone_steps", c_int64)]
 
 
+class Emi(ctypes.Structure):
+    """sdc_emi: cell-by-cell couplings (host arrays, copied by the setup)."""
+    _fields_ = [("n_mem", c_int64), ("mem_intra", c_void_p), ("mem_extra", c_void_p), ("mem_len", c_void_p),
+                ("cm", c_double), ("n_gap", c_int64), ("gap_a", c_void_p), ("gap_b", c_void_p),
+                ("gap_len", c_void_p), ("g_gap", c_double), ("robin_len", c_void_p), ("eps", c_double)]
+
+
 PTR = c_void_p
 P_I64 = POINTER(c_int64)
 P_I32 = POINTER(c_int32)
@@ -63,7 +70,7 @@ SIGNATURES = {
     "sdc_last_error": (c_char_p, [c_void_p]),
     "sdc_set_stream": (c_int32, [c_void_p, c_void_p]),
     "sdc_setup_mesh": (c_int32, [c_void_p, POINTER(Params), c_int32, c_int32, PTR, PTR, PTR, PTR,
-                                 PTR, PTR, PTR]),
+                                 PTR, PTR, PTR, POINTER(Emi)]),
     "sdc_add_stimulus": (c_int32, [c_void_p, c_double, PTR, c_int64, c_double]),
     "sdc_get_sizes": (c_int32, [c_void_p, P_I64, P_I64, P_I64]),
     "sdc_get_system": (c_int32, [c_void_p, PTR, PTR, PTR, PTR]),

@@ -226,15 +226,16 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     st->n_active = mb.rows;
     for (int i = 0; i < ni; ++i) st->nnz_active += mb.nnz[i];
   }
+  const EmiArgs emi = ctx->emi_args();
   launch_sweep_start(ctx->stream, M, map, N, ctx->A(), ctx->ml, ctx->v0, ctx->w0, ctx->v, ctx->w,
-                     ctx->I, ctx->R, ctx->Phi, ctx->Gam, ctx->amax, ctx->cargs);
+                     ctx->I, ctx->R, ctx->Phi, ctx->Gam, ctx->amax, ctx->cargs, emi);
   std::vector<std::vector<int>> iters(M);
   std::vector<int> ev_budget(M, 0);
   int ev_off = 0;
   for (int m = 0; m < M; ++m) {
     double* x = ctx->dv + m * N;
     launch_rhs(ctx->stream, M, m, map, N, ctx->A(), ctx->ml, ctx->Phi + m * N, ctx->dI, ctx->dv,
-               ctx->r[0], x, ctx->cargs);
+               ctx->r[0], x, ctx->cargs, emi);
     HIPC(hipGetLastError());
     const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
     if (async)
@@ -243,7 +244,10 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
       TRY(run_cg(ctx, m, mb, x, slot, &iters[m]));
     launch_post(ctx->stream, M, m, map, N, ctx->ionic_d, x, ctx->v + m * N, ctx->w + m * N,
                 ctx->I + m * N, ctx->R + m * N, ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N,
-                ctx->dR, ctx->amax, ctx->cargs);
+                ctx->dR, ctx->amax, ctx->cargs, emi);
+    launch_post_sites(ctx->stream, M, m, map, N, ctx->ionic_d, ctx->v + m * N, ctx->w + m * N,
+                      ctx->I + m * N, ctx->R + m * N, ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N,
+                      ctx->dR, ctx->cargs, emi);
     HIPC(hipGetLastError());
   }
   if (async) {
@@ -321,6 +325,7 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
 // Diagonal storage: per instance, the distinct column offsets (col - row) of
 // its rows; usable when no instance has more than kMaxDiag of them.
 int build_dia(sdc_ctx* ctx) {
+  if (ctx->emi) return SDC_OK;   // the membrane partner columns do not form diagonals
   const int ni = ctx->n_inst;
   const int64_t N = ctx->N;
   const HostSystem& hs = ctx->host;
@@ -419,11 +424,67 @@ int autotune(sdc_ctx* ctx) {
 // Spread the saved start state (v0, w0) to all nodes; all rows active.
 int restart_step(sdc_ctx* ctx) {
   launch_spread(ctx->stream, ctx->prm.M, ctx->all.dev(), ctx->N, ctx->ionic_d, ctx->v0, ctx->w0, ctx->v,
-                ctx->w, ctx->I, ctx->R);
+                ctx->w, ctx->I, ctx->R, ctx->emi_args());
   HIPC(hipGetLastError());
   ctx->cur = -1;
   ctx->k = 0;
   ctx->in_step = true;
+  return SDC_OK;
+}
+
+// Cell-by-cell model, host part of the setup: validate the couplings, merge
+// the gap junctions, the membrane pairs (pattern only) and the Robin term
+// into A, and form the membrane mass and the per-node site arrays.
+int emi_host_setup(sdc_ctx* ctx, const sdc_emi* emi, std::vector<int32_t>* part, std::vector<double>* sl,
+                   std::vector<int32_t>* ppos, std::vector<double>* pmass) {
+  const int64_t N = ctx->N;
+  if (ctx->n_inst != 1) return fail(ctx, SDC_ERR_ARG, "the cell-by-cell model takes one instance");
+  if (ctx->prm.format == 2) return fail(ctx, SDC_ERR_ARG, "the cell-by-cell model uses CSR storage");
+  if (emi->n_mem < 0 || emi->n_gap < 0 || !(emi->cm > 0.0) || !(emi->eps >= 0.0) || !(emi->g_gap >= 0.0) ||
+      !emi->robin_len || (emi->n_mem > 0 && (!emi->mem_intra || !emi->mem_extra || !emi->mem_len)) ||
+      (emi->n_gap > 0 && (!emi->gap_a || !emi->gap_b || !emi->gap_len)))
+    return fail(ctx, SDC_ERR_ARG, "bad cell-by-cell description");
+  part->assign(N, -1);
+  sl->assign(N, 0.0);
+  for (int64_t q = 0; q < emi->n_mem; ++q) {
+    const int32_t i = emi->mem_intra[q], x = emi->mem_extra[q];
+    if (i < 0 || i >= N || x < 0 || x >= N || i == x || !(emi->mem_len[q] > 0.0))
+      return fail(ctx, SDC_ERR_ARG, "membrane site %lld: bad nodes or length", static_cast<long long>(q));
+    if ((*part)[i] >= 0 || (*part)[x] >= 0)
+      return fail(ctx, SDC_ERR_ARG, "membrane site %lld: node already in a site", static_cast<long long>(q));
+    (*part)[i] = x;
+    (*part)[x] = i;
+    (*sl)[i] = emi->mem_len[q];
+    (*sl)[x] = -emi->mem_len[q];
+  }
+  for (int64_t q = 0; q < N; ++q)
+    if (!(emi->robin_len[q] >= 0.0)) return fail(ctx, SDC_ERR_ARG, "negative Robin length");
+  const int64_t np = emi->n_gap + emi->n_mem;
+  std::vector<int32_t> a(np), b(np);
+  std::vector<double> w(np, 0.0), robin(N);
+  for (int64_t q = 0; q < emi->n_gap; ++q) {
+    a[q] = emi->gap_a[q];
+    b[q] = emi->gap_b[q];
+    w[q] = emi->g_gap * emi->gap_len[q];
+  }
+  for (int64_t q = 0; q < emi->n_mem; ++q) {
+    a[emi->n_gap + q] = emi->mem_intra[q];
+    b[emi->n_gap + q] = emi->mem_extra[q];
+  }
+  for (int64_t q = 0; q < N; ++q) robin[q] = emi->eps * emi->robin_len[q];
+  std::string e = add_pair_couplings(&ctx->host, np, a.data(), b.data(), w.data(), robin.data());
+  if (!e.empty()) return fail(ctx, SDC_ERR_ARG, "cell-by-cell couplings: %s", e.c_str());
+  HostSystem& hs = ctx->host;
+  ppos->assign(N, -1);
+  pmass->assign(N, 0.0);
+  for (int64_t r = 0; r < N; ++r) {
+    hs.ml[r] = emi->cm * std::fabs((*sl)[r]);
+    if ((*part)[r] < 0) continue;
+    const int32_t* rc = hs.col.data() + hs.rowptr[r];
+    const int32_t len = hs.rowptr[r + 1] - hs.rowptr[r];
+    (*ppos)[r] = static_cast<int32_t>(std::lower_bound(rc, rc + len, (*part)[r]) - rc) + hs.rowptr[r];
+    (*pmass)[r] = -emi->cm * std::fabs((*sl)[r]);
+  }
   return SDC_OK;
 }
 
@@ -498,7 +559,7 @@ int sdc_collocation(int32_t M, double* tau, double* Q, double* QI, double* QE) {
 int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_inst,
                    const int64_t* node_off, const double* coords, const int64_t* elem_off,
                    const int32_t* elems, const double* elem_tensor, const double* node_sigma,
-                   const double* ionic) {
+                   const double* ionic, const sdc_emi* emi) {
   if (!ctx) return SDC_ERR_ARG;
   if (ctx->ready) return fail(ctx, SDC_ERR_STATE, "sdc_setup_mesh may be called once per context");
   if (!prm || !node_off || !coords || !elem_off || !elems || !elem_tensor || !node_sigma || !ionic)
@@ -541,6 +602,9 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
 
   std::string e = assemble_p1(dim, N, coords, E, elems, elem_tensor, node_sigma, &ctx->host);
   if (!e.empty()) return fail(ctx, SDC_ERR_ARG, "assembly: %s", e.c_str());
+  std::vector<int32_t> emi_part, emi_ppos;
+  std::vector<double> emi_sl, emi_pmass;
+  if (emi) TRY(emi_host_setup(ctx, emi, &emi_part, &emi_sl, &emi_ppos, &emi_pmass));
   ctx->nnz = ctx->host.rowptr[N];
   const int64_t nnz = ctx->nnz;
   const int M = prm->M;
@@ -561,9 +625,22 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   HIPC(hipMemcpyAsync(ctx->ml, ctx->host.ml.data(), N * 8, hipMemcpyHostToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(ctx->node_off_d, node_off, (n_inst + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(ctx->ionic_d, ionic, 6 * n_inst * 8, hipMemcpyHostToDevice, ctx->stream));
+  if (emi) {
+    TRY(dalloc(ctx, &ctx->emi_part, N));
+    TRY(dalloc(ctx, &ctx->emi_sl, N));
+    TRY(dalloc(ctx, &ctx->emi_ppos, N));
+    TRY(dalloc(ctx, &ctx->emi_pmass, N));
+    HIPC(hipMemcpyAsync(ctx->emi_part, emi_part.data(), N * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(ctx->emi_sl, emi_sl.data(), N * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(ctx->emi_ppos, emi_ppos.data(), N * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(ctx->emi_pmass, emi_pmass.data(), N * 8, hipMemcpyHostToDevice, ctx->stream));
+    ctx->emi = true;
+    ctx->emi_cm = emi->cm;
+  }
   for (int m = 0; m < M; ++m)
     launch_build_h(ctx->stream, N, ctx->rowptr, ctx->diagpos, ctx->Aval, ctx->ml,
-                   prm->dt * ctx->col.QI[m][m], ctx->Hval + m * nnz, ctx->dinv + m * N);
+                   prm->dt * ctx->col.QI[m][m], ctx->Hval + m * nnz, ctx->dinv + m * N, ctx->emi_ppos,
+                   ctx->emi_pmass);
   HIPC(hipGetLastError());
   TRY(build_dia(ctx));
   if (prm->format == 2 && ctx->nd == 0)
@@ -825,6 +902,7 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
 
 int sdc_set_coefficients(sdc_ctx* ctx, const double* node_sigma, const double* ionic) {
   TRY(check_ready(ctx));
+  if (ctx->emi) return fail(ctx, SDC_ERR_STATE, "sdc_set_coefficients is not available for the cell-by-cell model");
   ctx->in_step = false;
   if (ionic)
     HIPC(hipMemcpyAsync(ctx->ionic_d, ionic, 6 * ctx->n_inst * 8, hipMemcpyHostToDevice, ctx->stream));
@@ -840,7 +918,7 @@ int sdc_set_coefficients(sdc_ctx* ctx, const double* node_sigma, const double* i
     HIPC(hipMemcpyAsync(ctx->Aval, ctx->host.val.data(), nnz * 8, hipMemcpyHostToDevice, ctx->stream));
     for (int m = 0; m < M; ++m)
       launch_build_h(ctx->stream, N, ctx->rowptr, ctx->diagpos, ctx->Aval, ctx->ml,
-                     ctx->prm.dt * ctx->col.QI[m][m], ctx->Hval + m * nnz, ctx->dinv + m * N);
+                     ctx->prm.dt * ctx->col.QI[m][m], ctx->Hval + m * nnz, ctx->dinv + m * N, nullptr, nullptr);
     HIPC(hipGetLastError());
     if (ctx->nd > 0) TRY(build_dia(ctx));
   }

@@ -191,6 +191,56 @@ std::string assemble_p1(int dim, int64_t n, const double* coords, int64_t ne,
   return err;
 }
 
+std::string add_pair_couplings(HostSystem* hs, int64_t n_pairs, const int32_t* a, const int32_t* b,
+                               const double* w, const double* diag) {
+  const int64_t n = hs->n;
+  // extra columns per row (both directions), then a merged, sorted pattern
+  std::vector<std::vector<std::pair<int32_t, double>>> extra(n);
+  for (int64_t q = 0; q < n_pairs; ++q) {
+    const int32_t i = a[q], j = b[q];
+    if (i < 0 || i >= n || j < 0 || j >= n || i == j) return "pair node out of range or repeated";
+    const double wq = w ? w[q] : 0.0;
+    extra[i].emplace_back(j, -wq);
+    extra[j].emplace_back(i, -wq);
+    extra[i].emplace_back(i, wq);
+    extra[j].emplace_back(j, wq);
+  }
+  std::vector<int32_t> rowptr(n + 1, 0), col;
+  std::vector<double> val;
+  col.reserve(hs->col.size() + 2 * n_pairs);
+  val.reserve(hs->col.size() + 2 * n_pairs);
+  for (int64_t r = 0; r < n; ++r) {
+    std::vector<std::pair<int32_t, double>> row;
+    for (int32_t e = hs->rowptr[r]; e < hs->rowptr[r + 1]; ++e) row.emplace_back(hs->col[e], hs->val[e]);
+    for (const auto& x : extra[r]) row.push_back(x);
+    // stable sort keeps the element value first and the additions in pair order
+    std::stable_sort(row.begin(), row.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (size_t k = 0; k < row.size();) {
+      size_t k1 = k;
+      double v = 0.0;
+      for (; k1 < row.size() && row[k1].first == row[k].first; ++k1) v += row[k1].second;
+      col.push_back(row[k].first);
+      val.push_back(v);
+      k = k1;
+    }
+    if (static_cast<int64_t>(col.size()) >= (int64_t(1) << 31)) return "nnz exceeds int32 range";
+    rowptr[r + 1] = static_cast<int32_t>(col.size());
+  }
+  if (diag)
+    for (int64_t r = 0; r < n; ++r)
+      for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+        if (col[e] == r) val[e] += diag[r];
+  hs->rowptr.swap(rowptr);
+  hs->col.swap(col);
+  hs->val.swap(val);
+  for (int64_t r = 0; r < n; ++r) {
+    const int32_t* rc = hs->col.data() + hs->rowptr[r];
+    const int32_t len = hs->rowptr[r + 1] - hs->rowptr[r];
+    hs->diag[r] = static_cast<int32_t>(std::lower_bound(rc, rc + len, static_cast<int32_t>(r)) - rc) + hs->rowptr[r];
+  }
+  return "";
+}
+
 std::string element_pairs(int dim, const double* coords, int64_t ne, const int32_t* elems,
                           const double* elem_tensor, std::vector<double>* w) {
   const int nv = dim + 1, np = nv * dim / 2;

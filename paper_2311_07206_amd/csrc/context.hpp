@@ -58,6 +58,7 @@ using sdc::Stimulus;
 using sdc::CgState;
 using sdc::Mat;
 using sdc::NextMap;
+using sdc::EmiArgs;
 using sdc::BlkRec;
 using sdc::ZeroVecs;
 using sdc::kScal;
@@ -89,6 +90,14 @@ struct sdc_ctx {
   double t_csr_us = 0.0, t_dia_us = 0.0;
   int64_t* node_off_d = nullptr;
   double* ionic_d = nullptr;
+  // cell-by-cell model (see sdc_emi): membrane partner, signed site length,
+  // CSR position of the partner column and the off-diagonal membrane mass
+  bool emi = false;
+  double emi_cm = 0.0;
+  int32_t* emi_part = nullptr;
+  double* emi_sl = nullptr;
+  int32_t* emi_ppos = nullptr;
+  double* emi_pmass = nullptr;
 
   double *v0 = nullptr, *w0 = nullptr, *v = nullptr, *w = nullptr, *I = nullptr, *R = nullptr;
   double *Phi = nullptr, *Gam = nullptr, *dv = nullptr, *dI = nullptr, *dR = nullptr;
@@ -166,7 +175,10 @@ struct sdc_ctx {
   }
   Mat A() const { return matA(use_dia); }
   Mat H(int m) const { return matH(m, use_dia); }
-  ZeroVecs zv() const { return ZeroVecs{{r[0], r[1], wv[0], wv[1], s[0], s[1]}, dv, prm.M, N}; }
+  ZeroVecs zv() const {
+    return ZeroVecs{{r[0], r[1], wv[0], wv[1], s[0], s[1]}, dv, prm.M, N, emi ? dI : nullptr, emi ? dR : nullptr};
+  }
+  EmiArgs emi_args() const { return EmiArgs{emi ? emi_part : nullptr, emi_sl, emi_cm}; }
 };
 
 
@@ -208,5 +220,7 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async = f
              bool* short_budget = nullptr);
 int restart_step(sdc_ctx* ctx);
 int check_ready(sdc_ctx* ctx);
+int emi_host_setup(sdc_ctx* ctx, const sdc_emi* emi, std::vector<int32_t>* part, std::vector<double>* sl,
+                   std::vector<int32_t>* ppos, std::vector<double>* pmass);
 
 }  // namespace sdc

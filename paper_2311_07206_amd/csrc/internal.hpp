@@ -36,6 +36,13 @@ std::string assemble_p1(int dim, int64_t n_nodes, const double* coords, int64_t 
                         const int32_t* elems, const double* elem_tensor,
                         const double* node_sigma, HostSystem* out);
 
+// Add node-pair couplings w_q (e_a - e_b)(e_a - e_b)^T to the assembled A:
+// A_aa, A_bb += w_q, A_ab, A_ba -= w_q; pairs with w_q = 0 only extend the
+// pattern.  Then A_ii += diag[i] (diag may be null).  Recomputes the
+// diagonal positions.
+std::string add_pair_couplings(HostSystem* hs, int64_t n_pairs, const int32_t* a, const int32_t* b,
+                               const double* w, const double* diag);
+
 // Off-diagonal entries Khat_T[a][b], a < b (lexicographic pairs), of every
 // element's unit-conductivity stiffness |T| g_a . D_T g_b.  Because the rows
 // of Khat_T sum to zero, psi^T Khat_T u = -sum_{a<b} Khat_ab (psi_a - psi_b)(u_a - u_b).

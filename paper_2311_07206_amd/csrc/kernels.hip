@@ -99,18 +99,24 @@ void dispatch_m(int M, F&& f) {
 
 // ------------------------------------------------------------------ kernels
 
-// Spread: every collocation value starts at the step's initial state.
-template <int M>
+// Spread: every collocation value starts at the step's initial state.  With
+// the cell-by-cell model the currents live on membrane sites (intracellular
+// node, transmembrane voltage u_i - u_e); other nodes carry none.
+template <int M, bool EMI>
 __global__ __launch_bounds__(kBlock) void k_spread(Map map, int64_t N, const double* __restrict__ ionic,
                                                    const double* __restrict__ v0,
                                                    const double* __restrict__ w0, double* v,
-                                                   double* w, double* I, double* R) {
+                                                   double* w, double* I, double* R, EmiArgs e) {
   const Row rw = map_row(map);
   if (!rw.valid) return;
   const int i = rw.row;
   const double a = v0[i], b = w0[i];
-  double In, Rn;
-  ap_eval(a, b, ionic + 6 * rw.inst, In, Rn);
+  double In = 0.0, Rn = 0.0;
+  if constexpr (EMI) {
+    if (e.sl[i] > 0.0) ap_eval(a - v0[e.part[i]], b, ionic + 6 * rw.inst, In, Rn);
+  } else {
+    ap_eval(a, b, ionic + 6 * rw.inst, In, Rn);
+  }
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     v[m * N + i] = a;
@@ -118,6 +124,11 @@ __global__ __launch_bounds__(kBlock) void k_spread(Map map, int64_t N, const dou
     I[m * N + i] = In;
     R[m * N + i] = Rn;
   }
+}
+
+// Node that holds the membrane site of node i (cell-by-cell model).
+__device__ inline int site_of(const EmiArgs& e, int i, double l) {
+  return l > 0.0 ? i : (l < 0.0 ? e.part[i] : i);
 }
 
 __global__ void k_set_values(const int32_t* __restrict__ nodes, int64_t n, double value, double* v) {
@@ -130,12 +141,14 @@ __global__ void k_set_values(const int32_t* __restrict__ nodes, int64_t n, doubl
 //   Phi_m = ML_i (v0_i - v_m,i) + dt sum_j Q[m][j] F_j
 //   Gam_m = w0_i - w_m,i + dt sum_j Q[m][j] R_j,i
 // and amax_i = 0 for this sweep's selection.
-template <int M, int S>
+// Cell-by-cell model: ML I_j becomes sl I_j(site) and ML (v0 - v_m) the
+// membrane mass cm |sl| ((v0 - v_m)_i - (v0 - v_m)_partner).
+template <int M, int S, bool EMI>
 __global__ __launch_bounds__(kBlock) void k_sweep_start(
     Map map, int64_t N, Mat A, const double* __restrict__ ml, const double* __restrict__ v0,
     const double* __restrict__ w0, const double* __restrict__ v, const double* __restrict__ w,
     const double* __restrict__ I, const double* __restrict__ R, double* __restrict__ Phi,
-    double* __restrict__ Gam, double* __restrict__ amax, CollArgs c) {
+    double* __restrict__ Gam, double* __restrict__ amax, CollArgs c, EmiArgs e) {
   const Row rw = map_row(map);
   if (!rw.valid) return;
   const int i = rw.row;
@@ -147,13 +160,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
     for (int j = 0; j < M; ++j) Av[j] += a * v[j * N + k];
   });
   const double mli = ml[i];
+  double rwt = mli;   // weight of the site current in this row
+  int site = i, pt = i;
+  if constexpr (EMI) {
+    const double l = e.sl[i];
+    rwt = l;
+    site = site_of(e, i, l);
+    pt = l != 0.0 ? e.part[i] : i;
+  }
   double F[M], Rj[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    F[j] = -Av[j] - mli * I[j * N + i];
+    F[j] = -Av[j] - rwt * I[j * N + site];
     Rj[j] = R[j * N + i];
   }
-  const double v0i = v0[i], w0i = w0[i];
+  const double v0i = v0[i], w0i = w0[i], v0p = v0[pt];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     double sf = 0.0, sr = 0.0;
@@ -162,7 +183,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
       sf += c.Q[m][j] * F[j];
       sr += c.Q[m][j] * Rj[j];
     }
-    Phi[m * N + i] = mli * (v0i - v[m * N + i]) + c.dt * sf;
+    double mass;
+    if constexpr (EMI)
+      mass = mli * ((v0i - v[m * N + i]) - (v0p - v[m * N + pt]));
+    else
+      mass = mli * (v0i - v[m * N + i]);
+    Phi[m * N + i] = mass + c.dt * sf;
     Gam[m * N + i] = w0i - w[m * N + i] + c.dt * sr;
   }
   amax[i] = 0.0;
@@ -170,13 +196,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
 
 // Right-hand side of node m; CG start values x = 0, r = b on active rows:
 //   b_i = Phi_m,i - dt ML_i sum_{j<m} QE[m][j] dI_j,i - dt sum_k A_ik sum_{j<m} QI[m][j] dv_j,k
-template <int M, int S>
+template <int M, int S, bool EMI>
 __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A,
                                                 const double* __restrict__ ml,
                                                 const double* __restrict__ Phi_m,
                                                 const double* __restrict__ dI,
                                                 const double* __restrict__ dv, double* __restrict__ r,
-                                                double* __restrict__ x, CollArgs c) {
+                                                double* __restrict__ x, CollArgs c, EmiArgs e) {
   const Row rw = map_row(map);
   if (!rw.valid) return;
   const int i = rw.row;
@@ -190,11 +216,19 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A
       ay += a * y;
     });
   }
+  double rwt;
+  int site = i;
+  if constexpr (EMI) {
+    rwt = e.sl[i];
+    site = site_of(e, i, rwt);
+  } else {
+    rwt = ml[i];
+  }
   double ex = 0.0;
 #pragma unroll
   for (int j = 0; j < M - 1; ++j)
-    if (j < m) ex += c.QE[m][j] * dI[j * N + i];
-  r[i] = Phi_m[i] - c.dt * ml[i] * ex - c.dt * ay;
+    if (j < m) ex += c.QE[m][j] * dI[j * N + site];
+  r[i] = Phi_m[i] - c.dt * rwt * ex - c.dt * ay;
   x[i] = 0.0;
 }
 
@@ -445,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
 // Post-solve update of node m (eq. final-sdc):
 //   v_m += dv_m;  w_m += Gam_m + dt sum_{j<m} QE[m][j] dR_j;
 //   (I_m, R_m) <- AP(v_m, w_m) with dI_m, dR_m their change;  amax = max(amax, |dv_m|).
-template <int M>
+template <int M, bool EMI>
 __global__ __launch_bounds__(kBlock) void k_post(Map map, int m, int64_t N,
                                                  const double* __restrict__ ionic,
                                                  const double* __restrict__ x, double* v_m,
@@ -458,6 +492,12 @@ __global__ __launch_bounds__(kBlock) void k_post(Map map, int m, int64_t N,
   if (!rw.valid) return;
   const int i = rw.row;
   const double d = x[i];
+  if constexpr (EMI) {
+    // potentials only; the sites follow in k_post_sites
+    v_m[i] += d;
+    amax[i] = fmax(amax[i], fabs(d));
+    return;
+  }
   double g = 0.0;
 #pragma unroll
   for (int j = 0; j < M - 1; ++j)
@@ -473,6 +513,33 @@ __global__ __launch_bounds__(kBlock) void k_post(Map map, int m, int64_t N,
   I_m[i] = In;
   R_m[i] = Rn;
   amax[i] = fmax(amax[i], fabs(d));
+}
+
+// Cell-by-cell model, after k_post: the membrane sites whose intracellular
+// node is active take the gating update and the new current and rate at the
+// updated transmembrane voltage u_i - u_e.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_post_sites(Map map, int m, int64_t N,
+                                                       const double* __restrict__ ionic, const double* v_m,
+                                                       double* w_m, double* I_m, double* R_m, double* dI_m,
+                                                       double* dR_m, const double* __restrict__ Gam_m,
+                                                       const double* __restrict__ dR, CollArgs c, EmiArgs e) {
+  const Row rw = map_row(map);
+  if (!rw.valid) return;
+  const int i = rw.row;
+  if (!(e.sl[i] > 0.0)) return;
+  double g = 0.0;
+#pragma unroll
+  for (int j = 0; j < M - 1; ++j)
+    if (j < m) g += c.QE[m][j] * dR[j * N + i];
+  const double wm = w_m[i] + (Gam_m[i] + c.dt * g);
+  w_m[i] = wm;
+  double In, Rn;
+  ap_eval(v_m[i] - v_m[e.part[i]], wm, ionic + 6 * rw.inst, In, Rn);
+  dI_m[i] = In - I_m[i];
+  dR_m[i] = Rn - R_m[i];
+  I_m[i] = In;
+  R_m[i] = Rn;
 }
 
 // ---- active-set compaction (eq. "subset"): keep i with amax_i >= theta.
@@ -628,6 +695,11 @@ __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* 
 #pragma unroll
     for (int q = 0; q < kZeroVecs; ++q) zv.vec[q][i] = 0.0;
     for (int m = 0; m < zv.M; ++m) zv.dv[m * zv.N + i] = 0.0;
+    if (zv.dI)
+      for (int m = 0; m < zv.M; ++m) {
+        zv.dI[m * zv.N + i] = 0.0;
+        zv.dR[m * zv.N + i] = 0.0;
+      }
   }
 }
 
@@ -638,6 +710,11 @@ __global__ __launch_bounds__(kBlock) void k_zero_rows(Map map, ZeroVecs zv) {
 #pragma unroll
   for (int q = 0; q < kZeroVecs; ++q) zv.vec[q][i] = 0.0;
   for (int m = 0; m < zv.M; ++m) zv.dv[m * zv.N + i] = 0.0;
+  if (zv.dI)
+    for (int m = 0; m < zv.M; ++m) {
+      zv.dI[m * zv.N + i] = 0.0;
+      zv.dR[m * zv.N + i] = 0.0;
+    }
 }
 
 // Work map of an ascending list: instance i's entries are those in
@@ -713,10 +790,15 @@ inline dim3 grid(int nblk) { return dim3(static_cast<unsigned>(nblk > 0 ? nblk :
 // ------------------------------------------------------------------ launchers
 
 void launch_spread(hipStream_t s, int M, const Map& all, int64_t N, const double* ionic,
-                   const double* v0, const double* w0, double* v, double* w, double* I, double* R) {
+                   const double* v0, const double* w0, double* v, double* w, double* I, double* R,
+                   const EmiArgs& e) {
   if (all.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    k_spread<decltype(mm)::value><<<grid(all.nblk), kBlock, 0, s>>>(all, N, ionic, v0, w0, v, w, I, R);
+    constexpr int MM = decltype(mm)::value;
+    if (e.part)
+      k_spread<MM, true><<<grid(all.nblk), kBlock, 0, s>>>(all, N, ionic, v0, w0, v, w, I, R, e);
+    else
+      k_spread<MM, false><<<grid(all.nblk), kBlock, 0, s>>>(all, N, ionic, v0, w0, v, w, I, R, e);
   });
 }
 
@@ -728,24 +810,32 @@ void launch_set_values(hipStream_t s, const int32_t* nodes, int64_t n, double va
 void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const Mat& A,
                         const double* ml, const double* v0, const double* w0, const double* v,
                         const double* w, const double* I, const double* R, double* Phi,
-                        double* Gam, double* amax, const CollArgs& c) {
+                        double* Gam, double* amax, const CollArgs& c, const EmiArgs& e) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
     dispatch_storage(A.nd, [&](auto st) {
-      k_sweep_start<decltype(mm)::value, decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(
-          map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam, amax, c);
+      constexpr int MM = decltype(mm)::value, S = decltype(st)::value;
+      if (e.part)
+        k_sweep_start<MM, S, true><<<grid(map.nblk), kBlock, 0, s>>>(map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam,
+                                                                     amax, c, e);
+      else
+        k_sweep_start<MM, S, false><<<grid(map.nblk), kBlock, 0, s>>>(map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam,
+                                                                      amax, c, e);
     });
   });
 }
 
 void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Mat& A,
                 const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
-                double* x, const CollArgs& c) {
+                double* x, const CollArgs& c, const EmiArgs& e) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
     dispatch_storage(A.nd, [&](auto st) {
-      k_rhs<decltype(mm)::value, decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m,
-                                                                                       dI, dv, r, x, c);
+      constexpr int MM = decltype(mm)::value, S = decltype(st)::value;
+      if (e.part)
+        k_rhs<MM, S, true><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c, e);
+      else
+        k_rhs<MM, S, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c, e);
     });
   });
 }
@@ -806,11 +896,26 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                  const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
                  double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
-                 const CollArgs& c) {
+                 const CollArgs& c, const EmiArgs& e) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    k_post<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(
-        map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m, dR_m, Gam_m, dR, amax, c);
+    constexpr int MM = decltype(mm)::value;
+    if (e.part)
+      k_post<MM, true><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m, dR_m,
+                                                         Gam_m, dR, amax, c);
+    else
+      k_post<MM, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m, dR_m,
+                                                          Gam_m, dR, amax, c);
+  });
+}
+
+void launch_post_sites(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
+                       double* v_m, double* w_m, double* I_m, double* R_m, double* dI_m, double* dR_m,
+                       const double* Gam_m, const double* dR, const CollArgs& c, const EmiArgs& e) {
+  if (map.nblk <= 0 || !e.part) return;
+  dispatch_m(M, [&](auto mm) {
+    k_post_sites<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, ionic, v_m, w_m, I_m, R_m, dI_m,
+                                                                        dR_m, Gam_m, dR, c, e);
   });
 }
 
@@ -847,15 +952,24 @@ void launch_map_rows(hipStream_t s, const Map& map, int32_t* out) {
 namespace sdc {
 namespace {
 // H_m = ML + c_m A on the pattern of A, and dinv_m = 1 / diag(H_m).
+// With the cell-by-cell model the membrane mass also has the partner entry.
 __global__ __launch_bounds__(kBlock) void k_build_h(int64_t N, const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ diagpos,
                                                     const double* __restrict__ A,
                                                     const double* __restrict__ ml, double c,
-                                                    double* __restrict__ H, double* __restrict__ dinv) {
+                                                    double* __restrict__ H, double* __restrict__ dinv,
+                                                    const int32_t* __restrict__ ppos,
+                                                    const double* __restrict__ pmass) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   if (i >= N) return;
   const int dg = diagpos[i];
-  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) H[e] = (e == dg) ? ml[i] + c * A[e] : c * A[e];
+  const int pp = ppos ? ppos[i] : -1;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    // the diagonal in the same expression as the diagonal-storage build
+    double h = (e == dg) ? ml[i] + c * A[e] : c * A[e];
+    if (e == pp) h = pmass[i] + h;
+    H[e] = h;
+  }
   dinv[i] = 1.0 / H[dg];
 }
 
@@ -866,9 +980,10 @@ __global__ void k_iota(int32_t* out, int64_t n) {
 }  // namespace
 
 void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32_t* diagpos,
-                    const double* A, const double* ml, double c, double* H, double* dinv) {
+                    const double* A, const double* ml, double c, double* H, double* dinv,
+                    const int32_t* ppos, const double* pmass) {
   k_build_h<<<dim3(static_cast<unsigned>((N + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
-      N, rowptr, diagpos, A, ml, c, H, dinv);
+      N, rowptr, diagpos, A, ml, c, H, dinv, ppos, pmass);
 }
 
 namespace {

@@ -48,6 +48,18 @@ struct Map {
   int32_t n_inst;
 };
 
+// Cell-by-cell model: membrane node pairs.  part[i] is the other node of
+// node i's membrane site (-1: not a membrane node); sl[i] is the site's
+// lumped membrane length, positive at the intracellular node (which holds
+// the site's w, I, R), negative at the extracellular node, 0 elsewhere.  The
+// membrane mass is cm |sl| on the diagonal and -cm |sl| at the partner; the
+// ionic current enters node i as sl[i] * I(site).  part == null: monodomain.
+struct EmiArgs {
+  const int32_t* part;
+  const double* sl;
+  double cm;
+};
+
 struct Csr {
   const int32_t* rowptr;
   const int32_t* col;
@@ -78,16 +90,17 @@ struct CgState {
 };
 
 void launch_spread(hipStream_t s, int M, const Map& all, int64_t N, const double* ionic,
-                   const double* v0, const double* w0, double* v, double* w, double* I, double* R);
+                   const double* v0, const double* w0, double* v, double* w, double* I, double* R,
+                   const EmiArgs& e);
 void launch_set_values(hipStream_t s, const int32_t* nodes, int64_t n, double value, double* v);
 void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const Mat& A,
                         const double* ml, const double* v0, const double* w0, const double* v,
                         const double* w, const double* I, const double* R, double* Phi,
-                        double* Gam, double* amax, const CollArgs& c);
+                        double* Gam, double* amax, const CollArgs& c, const EmiArgs& e);
 // Right-hand side of node m; writes r = b and x = 0 on active rows.
 void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Mat& A,
                 const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
-                double* x, const CollArgs& c);
+                double* x, const CollArgs& c, const EmiArgs& e);
 void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, double* x);
 // Single-reduction Jacobi-PCG: start (w0 = H dinv r0 and partial sums), then
 // one launch per iteration reading buffers (r, w, s)_in, writing (r, w, s)_out.
@@ -107,10 +120,16 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     int maxit, const CgState& cg, double* tot, hipEvent_t ev_start = nullptr,
                     hipEvent_t ev_stop = nullptr);
 constexpr int kTotBlocks = 4 * kBlock;
+// Post-solve update of node m.  With the cell-by-cell model this updates the
+// potentials and amax only; launch_post_sites then updates the membrane
+// sites whose intracellular node is active, from the updated potentials.
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                  const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
                  double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
-                 const CollArgs& c);
+                 const CollArgs& c, const EmiArgs& e);
+void launch_post_sites(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
+                       double* v_m, double* w_m, double* I_m, double* R_m, double* dI_m, double* dR_m,
+                       const double* Gam_m, const double* dR, const CollArgs& c, const EmiArgs& e);
 
 // Active-set compaction I_{k+1} = {i in I_k : amax_i >= theta} (three passes).
 // sel_cnt [nblk] and sel_nnz [nblk] are per-block scratch; next-map outputs
@@ -137,6 +156,10 @@ struct ZeroVecs {
   double* dv;
   int M;
   int64_t N;
+  // cell-by-cell model: the site changes dI, dR [M][N] of dropped sites
+  // count as zero in later sweeps (null: monodomain)
+  double* dI;
+  double* dR;
 };
 // The kept rows are written to idx_pad (the padded list of the next map) and,
 // when idx_compact is not null, also as one ascending list there.
@@ -154,8 +177,11 @@ void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t 
 void launch_map_rows(hipStream_t s, const Map& map, int32_t* out);
 
 // H_m = ML + c A (pattern of A) and its inverse diagonal.
+// ppos[i] (or null): CSR position of node i's membrane partner column (-1:
+// none), where pmass[i] is added (the off-diagonal membrane mass).
 void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32_t* diagpos,
-                    const double* A, const double* ml, double c, double* H, double* dinv);
+                    const double* A, const double* ml, double c, double* H, double* dinv,
+                    const int32_t* ppos, const double* pmass);
 void launch_iota(hipStream_t s, int32_t* out, int64_t n);
 // Diagonal storage of H_m for the rows [lo, hi) of one instance (dg = index of offset 0).
 void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int nd, int dg, const double* A,

@@ -42,7 +42,10 @@ class Solver:
     """One library context: an assembled mesh (possibly several instances)."""
 
     def __init__(self, coords, elems, elem_tensor, node_sigma, ionic, node_off, elem_off,
-                 M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None):
+                 M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None, emi=None):
+        """emi: None (monodomain) or a dict with the cell-by-cell couplings
+        mem_intra, mem_extra, mem_len, cm, gap_a, gap_b, gap_len, g_gap,
+        robin_len, eps (see sdc_emi)."""
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         if stream is None:
@@ -65,8 +68,25 @@ class Solver:
         tens_a, p_t = _host(elem_tensor, np.float64)
         sig_a, p_s = _host(node_sigma, np.float64)
         ion_a, p_i = _host(np.atleast_2d(ionic), np.float64)
+        emi_arg = None
+        if emi is not None:
+            keep = []
+
+            def arr(x, dt):
+                a, ptr = _host(x, dt)
+                keep.append(a)
+                return ptr.value
+
+            emi_arg = _lib.Emi(n_mem=len(emi["mem_intra"]), mem_intra=arr(emi["mem_intra"], np.int32),
+                               mem_extra=arr(emi["mem_extra"], np.int32), mem_len=arr(emi["mem_len"], np.float64),
+                               cm=float(emi["cm"]), n_gap=len(emi["gap_a"]), gap_a=arr(emi["gap_a"], np.int32),
+                               gap_b=arr(emi["gap_b"], np.int32), gap_len=arr(emi["gap_len"], np.float64),
+                               g_gap=float(emi["g_gap"]), robin_len=arr(emi["robin_len"], np.float64),
+                               eps=float(emi["eps"]))
         self._check(self.lib.sdc_setup_mesh(self.ctx, ctypes.byref(prm), dim, len(node_off_a) - 1,
-                                            p_no, p_c, p_eo, p_e, p_t, p_s, p_i))
+                                            p_no, p_c, p_eo, p_e, p_t, p_s, p_i,
+                                            ctypes.byref(emi_arg) if emi_arg is not None else None))
+        self.emi = emi is not None
         n, nnz, nw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.sdc_get_sizes(self.ctx, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(nw)))
         self.N, self.nnz, self.Nw = n.value, nnz.value, nw.value
@@ -80,6 +100,9 @@ class Solver:
     def from_problem(cls, P, **kw):
         """Context for a workloads.Problem, with its stimuli registered."""
         args = dict(M=P.M, K=P.K, dt=P.dt, theta=P.theta, cg_rtol=P.cg_rtol, cg_maxit=P.cg_maxit)
+        if hasattr(P, "mem_intra"):   # cell-by-cell problem
+            args["emi"] = {k: getattr(P, k) for k in ("mem_intra", "mem_extra", "mem_len", "cm", "gap_a", "gap_b",
+                                                      "gap_len", "g_gap", "robin_len", "eps")}
         args.update(kw)
         s = cls(P.coords, P.elems, P.elem_tensor, P.node_sigma, P.ionic, P.node_off, P.elem_off, **args)
         for t_on, nodes, value in P.stimuli:
