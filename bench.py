@@ -121,6 +121,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / adjoint measurements")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--with-3d", action="store_true", help="also time the 128^3 3D workload")
+    ap.add_argument("--with-emi", action="store_true", help="also time the 64x16-cell cell-by-cell workload")
+    ap.add_argument("--emi-steps", type=int, default=3)
     ap.add_argument("--profile-warmup", action="store_true",
                     help="account CG kernel bytes from the first step (matches counter runs)")
     ap.add_argument("--calib", action="store_true",
@@ -286,6 +288,8 @@ def main():
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio_ckpt10"]
     if args.with_3d:
         out["workload_3d"] = workload_3d()
+    if args.with_emi:
+        out["workload_emi"] = workload_emi(args.emi_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
@@ -390,6 +394,40 @@ def workload_3d(nsteps=10, warm=10):
            "value": dofs / el, "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
            "algorithmic_GBps": nbytes / el / 1e9, "storage": s.info(),
            "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)]}
+    if prof["cg_launches"]:
+        out["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
+        out["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]
+    s.close()
+    return out
+
+
+def workload_emi(nsteps=3, warm=1):
+    """The cell-by-cell workload (64 x 16 myocytes, 390,564 potential dofs,
+    81,920 membrane sites), from the stimulus: CSR storage, Jacobi-PCG."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    from workloads import config3
+
+    P = config3()
+    dev = torch.device("cuda", 0)
+    s = Solver.from_problem(P, cg_maxit=200000)
+    u = torch.tensor(P.v_init, device=dev)
+    w = torch.tensor(P.w_init, device=dev)
+    for k in range(warm):
+        s.step(u, w, k * P.dt)
+    s.profile(True)
+    el, logs = _timed_steps(s, u, w, warm * P.dt, P.dt, nsteps, torch.cuda.synchronize)
+    prof = s.profile_read()
+    s.profile(False)
+    dofs = sum(st["n_active"] for lg in logs for st in lg)
+    nbytes = sum(sweep_bytes(st, P.M, k == 0) for lg in logs for k, st in enumerate(lg)) + nsteps * step_bytes(P.N, P.M)
+    out = {"workload": f"2D cell-by-cell {P.N} potential dofs, {len(P.mem_intra)} membrane sites, M={P.M} "
+                       f"K={P.K} dt={P.dt}, theta={P.theta}; steps {warm}..{warm + nsteps - 1} after the stimulus",
+           "value": dofs / el, "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
+           "algorithmic_GBps": nbytes / el / 1e9, "storage": s.info(),
+           "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)],
+           "cg_iters_sweep0": [int(np.max([lg[0]["cg_iters_max"][m] for lg in logs])) for m in range(P.M)]}
     if prof["cg_launches"]:
         out["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
         out["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]

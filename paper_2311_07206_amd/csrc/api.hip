@@ -111,13 +111,18 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   const Mat H = ctx->H(m);
   const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
   const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
-  int budget = pred_slot >= 0 ? std::max(1, ctx->pred[pred_slot]) : 8;
+  // budgets pred, pred/2, pred/4, ... (at least 2), each launched in chunks
+  // that fit the event pool while kernel timing is on
+  int vbudget = pred_slot >= 0 ? std::max(1, ctx->pred[pred_slot]) : 8;
+  const int cap = ctx->prof && !ctx->ev.empty() ? static_cast<int>(ctx->ev.size()) / 2 : vbudget;
+  int left = vbudget;
   int it = 0;
   iters->assign(ni, 0);
   launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
   HIPC(hipGetLastError());
   if (mb.nblk > 0) {
     for (;;) {
+      const int budget = std::min(left, cap);
       const int it0 = it;
       const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * budget;
       for (int b = 0; b < budget; ++b, ++it) {
@@ -147,7 +152,11 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
       if (!running) break;
       if (it >= ctx->prm.cg_maxit + 2)
         return fail(ctx, SDC_ERR_CG_MAXIT, "CG: iteration limit reached (node %d, sweep %d)", m, ctx->k);
-      budget = std::max(2, budget / 2);
+      left -= budget;
+      if (left <= 0) {
+        vbudget = std::max(2, vbudget / 2);
+        left = vbudget;
+      }
     }
     for (int i = 0; i < ni; ++i) (*iters)[i] = ctx->h_i32[ni + i];
   } else {
@@ -176,6 +185,11 @@ int map_list(sdc_ctx* ctx, int slot, const int32_t* idx, int64_t n) {
   mb.idx = ctx->list[slot];
   return SDC_OK;
 }
+
+// Solves predicted to take more iterations than this run synchronously in
+// async sweeps: a host check per budget costs little against the solve, and
+// an exact count avoids redoing the step when the prediction falls short.
+constexpr int kAsyncMaxBudget = 512;
 
 // Launch node m's CG with the predicted iteration budget and no host
 // synchronisation; the done flags and iteration counts are copied to the
@@ -238,10 +252,15 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
                ctx->r[0], x, ctx->cargs, emi);
     HIPC(hipGetLastError());
     const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
-    if (async)
+    if (async && ctx->pred[slot] <= kAsyncMaxBudget) {
       TRY(run_cg_async(ctx, m, mb, x, slot, &ev_off, &ev_budget));
-    else
+    } else {
       TRY(run_cg(ctx, m, mb, x, slot, &iters[m]));
+      if (async) {   // the outcome goes to the same history as an asynchronous solve's
+        HIPC(hipMemcpyAsync(ctx->hist_done + m * ni, ctx->cg_done, ni * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPC(hipMemcpyAsync(ctx->hist_iters + m * ni, ctx->cg_iters, ni * 4, hipMemcpyDeviceToDevice, ctx->stream));
+      }
+    }
     launch_post(ctx->stream, M, m, map, N, ctx->ionic_d, x, ctx->v + m * N, ctx->w + m * N,
                 ctx->I + m * N, ctx->R + m * N, ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N,
                 ctx->dR, ctx->amax, ctx->cargs, emi);
