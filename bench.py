@@ -120,8 +120,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / adjoint measurements")
     ap.add_argument("--batch-steps", type=int, default=20)
-    ap.add_argument("--with-3d", action="store_true", help="also time the 128^3 3D workload")
-    ap.add_argument("--with-emi", action="store_true", help="also time the 64x16-cell cell-by-cell workload")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 3D workload")
+    ap.add_argument("--no-emi", action="store_true", help="skip the 64x16-cell cell-by-cell workload")
     ap.add_argument("--emi-steps", type=int, default=3)
     ap.add_argument("--profile-warmup", action="store_true",
                     help="account CG kernel bytes from the first step (matches counter runs)")
@@ -286,9 +286,9 @@ def main():
     if not args.no_batch:
         out["batched"], out["adjoint"] = batched_and_adjoint(args.batch_steps)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio_ckpt10"]
-    if args.with_3d:
+    if not args.no_3d:
         out["workload_3d"] = workload_3d()
-    if args.with_emi:
+    if not args.no_emi:
         out["workload_emi"] = workload_emi(args.emi_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
