@@ -1,0 +1,135 @@
+"""Parity at the full workload sizes, on outputs the oracle can compute.
+
+- 48 batched 2D instances (3.69 M dofs, the batched benchmark's launch
+  configuration): two adaptive steps; the smallest and the largest instance
+  are recomputed alone by the oracle with the GPU's active sets.
+- 3D 128^3 (2.1 M dofs, 27 M entries, diagonal storage): the assembled
+  matrix against the oracle's, and restricted PCG solves on all rows and on
+  a random 5 % subset against the oracle's PCG.
+- Cell-by-cell 64 x 16 cells (390,564 dofs): the assembled system against
+  the oracle's, and restricted solves on the first four cell columns (a set
+  that removes the Robin-fixed constant mode) against the oracle's PCG.
+
+Tolerances as in the other parity tests: 1e-10 relative for states, 1e-11
+relative for CG solutions.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.assembly import lumped_mass, stiffness  # noqa: E402
+from oracle.pcg import jacobi_pcg  # noqa: E402
+from oracle.sdc import build, run  # noqa: E402
+from workloads import config2, config3, config4  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _solver(P, **kw):
+    from paper_2311_07206_amd import Solver
+    return Solver.from_problem(P, **kw)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _instance(P, i):
+    from workloads.configs import Problem
+    lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
+    e0, e1 = int(P.elem_off[i]), int(P.elem_off[i + 1])
+    stim = [(t, nodes[(nodes >= lo) & (nodes < hi)] - lo, val) for t, nodes, val in P.stimuli]
+    return Problem(name="inst", dim=P.dim, coords=P.coords[lo:hi], elems=P.elems[e0:e1] - lo,
+                   elem_tensor=P.elem_tensor[e0:e1], node_sigma=P.node_sigma[lo:hi],
+                   node_off=np.array([0, hi - lo]), elem_off=np.array([0, e1 - e0]),
+                   ionic=P.ionic[i:i + 1], M=P.M, K=P.K, dt=P.dt, n_steps=P.n_steps, theta=P.theta,
+                   cg_rtol=P.cg_rtol, cg_maxit=P.cg_maxit, stimuli=stim,
+                   v_init=P.v_init[lo:hi], w_init=P.w_init[lo:hi])
+
+
+def test_batched_full_size_sampled_instances():
+    P = config4()
+    s = _solver(P)
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    n_steps = 2
+    sets = []
+    for n in range(n_steps):
+        print(f"[batched full] step {n}", flush=True)
+        s.begin_step(v, w, n * P.dt)
+        step_sets = [None]
+        for k in range(P.K):
+            s.sweep()
+            if k + 1 < P.K:
+                step_sets.append(s.active().cpu().numpy().astype(np.int64))
+        s.end_step(v, w)
+        sets.append(step_sets)
+    gv, gw = v.cpu().numpy(), w.cpu().numpy()
+    sizes = np.diff(P.node_off)
+    for i in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        lo, hi = P.node_off[i], P.node_off[i + 1]
+        print(f"[batched full] oracle instance {i} ({hi - lo} dofs)", flush=True)
+        sub = _instance(P, i)
+        rep = [[None] + [s_[(s_ >= lo) & (s_ < hi)] - lo for s_ in st[1:]] for st in sets]
+        ov, ow, _ = run(build(sub), sub.v_init, sub.w_init, n_steps, P.K, sub.stimuli, idx_replay=rep)
+        assert rel(gv[lo:hi], ov) < 1e-10 and rel(gw[lo:hi], ow) < 1e-10
+
+
+def test_3d_full_size_assembly_and_restricted_pcg():
+    P = config2()
+    s = _solver(P)
+    assert s.info()["format"] == "dia"
+    print("[3d full] oracle assembly", flush=True)
+    A = stiffness(P.coords, P.elems, P.elem_tensor, P.node_sigma, P.N).tocsr()
+    ML = lumped_mass(P.coords, P.elems, P.N)
+    rp, col, val, ml = s.system()
+    G = sp.csr_matrix((val, col, rp), shape=(P.N, P.N))
+    assert abs(G - A).max() <= 1e-14 * abs(A).max()
+    assert np.allclose(ml, ML, rtol=1e-14, atol=0)
+    from oracle.collocation import Collocation
+    col_ = Collocation(P.M)
+    rng = np.random.default_rng(21)
+    for m, frac in ((0, 1.0), (3, 0.05)):
+        H = (sp.diags(ML) + P.dt * col_.QI[m, m] * A).tocsr()
+        n = int(frac * P.N)
+        idx = np.arange(P.N) if frac == 1.0 else np.sort(rng.choice(P.N, size=n, replace=False))
+        b = rng.standard_normal(P.N)
+        print(f"[3d full] solve m={m} n={n}", flush=True)
+        x, it = s.solve(m, torch.tensor(idx, dtype=torch.int32, device=DEV), torch.tensor(b, device=DEV))
+        xo, ito = jacobi_pcg(H, b, idx, P.cg_rtol, maxit=P.cg_maxit)
+        assert rel(x.cpu().numpy(), xo) < 1e-11
+        assert abs(it[0] - ito) <= 1
+
+
+def test_emi_full_size_assembly_and_restricted_pcg():
+    from oracle.emi import EMI, build as emi_build
+    P = config3()
+    s = _solver(P)
+    print("[emi full] oracle assembly", flush=True)
+    mod = EMI(P)
+    rp, col, val, ml = s.system()
+    G = sp.csr_matrix((val, col, rp), shape=(P.N, P.N))
+    assert abs(G - mod.A).max() <= 1e-14 * abs(mod.A).max()
+    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-15, atol=0)
+    orc = emi_build(P)
+    # the intracellular and extracellular nodes of the first four cell columns
+    x0 = P.coords[:, 0]
+    first = np.nonzero(x0 <= 4 * (100e-4 + 2e-4) + 1e-12)[0]
+    rng = np.random.default_rng(23)
+    for m in (0, 2):
+        b = rng.standard_normal(P.N) * 1e-4
+        print(f"[emi full] solve m={m} n={first.size}", flush=True)
+        x, it = s.solve(m, torch.tensor(first, dtype=torch.int32, device=DEV), torch.tensor(b, device=DEV))
+        xo, ito = jacobi_pcg(orc.H[m], b, first, P.cg_rtol, maxit=P.cg_maxit)
+        assert rel(x.cpu().numpy(), xo) < 1e-11
