@@ -126,9 +126,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_apsi(Map all, int m, int64_t N, 
   const int i = rw.row;
   double aps = 0.0;
   if constexpr (DIA) {
+    const int h = A.nd / 2;   // symmetric diagonal storage, see kernels.hpp
     for (int d = 0; d < A.nd; ++d) {
       const int k = i + rw.off(d);
-      aps += A.dval[d * N + i] * psi[(k < rw.lo || k >= rw.hi) ? i : k];
+      const bool in = k >= rw.lo && k < rw.hi;
+      const double a = d < h ? (in ? A.dval[(A.nd - 1 - d - h) * N + k] : 0.0) : A.dval[(d - h) * N + i];
+      aps += a * psi[in ? k : i];
     }
   } else {
     for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) aps += A.val[e] * psi[A.col[e]];

@@ -342,14 +342,17 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
 }
 
 // Diagonal storage: per instance, the distinct column offsets (col - row) of
-// its rows; usable when no instance has more than kMaxDiag of them.
+// its rows, sorted; usable when every instance has the same number nd <=
+// kMaxDiag of them, as a set symmetric about 0 (a symmetric pattern).  Since
+// A and H_m are symmetric, only the nd/2 + 1 diagonals with offset >= 0 are
+// stored: entry (r, r + o), o >= 0, at dval[o's index][r], and (r, r - o) is
+// read as (r - o, r).  Entries absent from the pattern hold 0.
 int build_dia(sdc_ctx* ctx) {
   if (ctx->emi) return SDC_OK;   // the membrane partner columns do not form diagonals
   const int ni = ctx->n_inst;
   const int64_t N = ctx->N;
   const HostSystem& hs = ctx->host;
   std::vector<std::vector<int32_t>> offs(ni);
-  int nd = 0;
   for (int i = 0; i < ni; ++i) {
     std::vector<int32_t> o;
     for (int64_t r = ctx->node_off_h[i]; r < ctx->node_off_h[i + 1]; ++r)
@@ -361,27 +364,28 @@ int build_dia(sdc_ctx* ctx) {
         }
       }
     std::sort(o.begin(), o.end());
-    nd = std::max(nd, static_cast<int>(o.size()));
     offs[i] = std::move(o);
   }
-  std::vector<int32_t> off(static_cast<size_t>(ni) * nd, 0);
-  std::vector<int> dg(ni, 0);
+  const int nd = static_cast<int>(offs[0].size());
   for (int i = 0; i < ni; ++i) {
-    for (int d = 0; d < static_cast<int>(offs[i].size()); ++d) {
-      off[i * nd + d] = offs[i][d];
-      if (offs[i][d] == 0) dg[i] = d;
-    }
-    // padding slots repeat offset 0 with zero values
-    for (int d = static_cast<int>(offs[i].size()); d < nd; ++d) off[i * nd + d] = 0;
+    if (static_cast<int>(offs[i].size()) != nd) return SDC_OK;
+    for (int d = 0; d < nd; ++d)
+      if (offs[i][d] != -offs[i][nd - 1 - d]) return SDC_OK;
   }
-  std::vector<double> val(static_cast<size_t>(nd) * N, 0.0);
+  const int h = nd / 2;   // index of offset 0
+  std::vector<int32_t> off(static_cast<size_t>(ni) * nd, 0);
+  for (int i = 0; i < ni; ++i)
+    for (int d = 0; d < nd; ++d) off[i * nd + d] = offs[i][d];
+  const int ns = h + 1;   // stored diagonals
+  std::vector<double> val(static_cast<size_t>(ns) * N, 0.0);
   for (int i = 0; i < ni; ++i)
     for (int64_t r = ctx->node_off_h[i]; r < ctx->node_off_h[i + 1]; ++r)
       for (int32_t e = hs.rowptr[r]; e < hs.rowptr[r + 1]; ++e) {
         const int32_t d = hs.col[e] - static_cast<int32_t>(r);
+        if (d < 0) continue;
         const auto& o = offs[i];
         const int q = static_cast<int>(std::lower_bound(o.begin(), o.end(), d) - o.begin());
-        val[static_cast<size_t>(q) * N + r] = hs.val[e];
+        val[static_cast<size_t>(q - h) * N + r] = hs.val[e];
       }
   const int M = ctx->prm.M;
   if (!ctx->dia_off) {
@@ -393,10 +397,8 @@ int build_dia(sdc_ctx* ctx) {
   ctx->dia_off_h = off;
   HIPC(hipMemcpyAsync(ctx->dia_A, val.data(), val.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   for (int m = 0; m < M; ++m)
-    for (int i = 0; i < ni; ++i)
-      launch_build_h_dia(ctx->stream, N, static_cast<int>(ctx->node_off_h[i]), static_cast<int>(ctx->node_off_h[i + 1]),
-                         nd, dg[i], ctx->dia_A, ctx->ml, ctx->prm.dt * ctx->col.QI[m][m],
-                         ctx->dia_H + static_cast<int64_t>(m) * nd * N);
+    launch_build_h_dia(ctx->stream, N, 0, static_cast<int>(N), ns, ctx->dia_A, ctx->ml,
+                       ctx->prm.dt * ctx->col.QI[m][m], ctx->dia_H + static_cast<int64_t>(m) * ns * N);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(ctx->stream));   // the host staging vector goes out of scope
   ctx->nd = nd;

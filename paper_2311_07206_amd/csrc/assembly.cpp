@@ -170,12 +170,16 @@ std::string assemble_p1(int dim, int64_t n, const double* coords, int64_t ne,
         for (int a = 0; a < nv; ++a) sig += node_sigma[ev[a]];
         sig /= nv;
         const double* D = elem_tensor + e * dim * dim;
-        double Dg[3] = {0, 0, 0};  // D g_la
-        for (int r = 0; r < dim; ++r)
-          for (int c = 0; c < dim; ++c) Dg[r] += D[r * dim + c] * geo.g[la][c];
+        double Dg[4][3] = {};  // D g_a for every vertex
+        for (int a = 0; a < nv; ++a)
+          for (int r = 0; r < dim; ++r)
+            for (int c = 0; c < dim; ++c) Dg[a][r] += D[r * dim + c] * geo.g[a][c];
         for (int b = 0; b < nv; ++b) {
+          // Khat_ab = g_q . D g_p with (p, q) = (min, max)(la, b): rows la and
+          // b evaluate the same expression, so A is exactly symmetric
+          const int pa = std::min(la, b), qa = std::max(la, b);
           double kab = 0.0;
-          for (int c = 0; c < dim; ++c) kab += geo.g[b][c] * Dg[c];
+          for (int c = 0; c < dim; ++c) kab += geo.g[qa][c] * Dg[pa][c];
           const int32_t* p = std::lower_bound(rc, rc + len, ev[b]);
           rv[p - rc] += sig * geo.vol * kab;
         }

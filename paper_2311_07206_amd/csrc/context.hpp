@@ -85,7 +85,7 @@ struct sdc_ctx {
   int nd = 0;
   int32_t* dia_off = nullptr;      // [n_inst][nd]
   std::vector<int32_t> dia_off_h;
-  double *dia_A = nullptr, *dia_H = nullptr;   // [nd][N], [M][nd][N]
+  double *dia_A = nullptr, *dia_H = nullptr;   // [nd/2+1][N], [M][nd/2+1][N] (offsets >= 0)
   bool use_dia = false;
   double t_csr_us = 0.0, t_dia_us = 0.0;
   int64_t* node_off_d = nullptr;
@@ -171,7 +171,7 @@ struct sdc_ctx {
   }
   Mat matH(int m, bool dia) const {
     return Mat{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz, dia_off,
-               dia_H ? dia_H + static_cast<int64_t>(m) * nd * N : nullptr, node_off_d, dia ? nd : 0};
+               dia_H ? dia_H + static_cast<int64_t>(m) * (nd / 2 + 1) * N : nullptr, node_off_d, dia ? nd : 0};
   }
   Mat A() const { return matA(use_dia); }
   Mat H(int m) const { return matH(m, use_dia); }

@@ -56,10 +56,17 @@ __device__ __forceinline__ void for_entries(const Mat& A, int64_t N, const Row& 
   } else {
     constexpr int kUnroll = S > 0 ? S : 1;
     const int nd = S > 0 ? S : A.nd;
+    const int h = nd / 2;
 #pragma unroll kUnroll
     for (int d = 0; d < nd; ++d) {
       const int c = i + rw.off(d);
-      f(A.dval[d * N + i], (c < rw.lo || c >= rw.hi) ? i : c);
+      const bool in = c >= rw.lo && c < rw.hi;
+      double a;
+      if (d < h)   // offset -o: the stored entry (c, c + o) of row c
+        a = in ? A.dval[(nd - 1 - d - h) * N + c] : 0.0;
+      else
+        a = A.dval[(d - h) * N + i];
+      f(a, in ? c : i);
     }
   }
 }
@@ -987,26 +994,26 @@ void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32
 }
 
 namespace {
-// Diagonal storage of H_m = ML + c A for the rows [lo, hi) of one instance:
-// the entry with offset 0 (index dg) carries the mass.
-__global__ __launch_bounds__(kBlock) void k_build_h_dia(int64_t N, int lo, int hi, int nd, int dg,
+// Diagonal storage of H_m = ML + c A for the rows [lo, hi): the stored
+// diagonal 0 is offset 0 and carries the mass (same expression as the CSR build).
+__global__ __launch_bounds__(kBlock) void k_build_h_dia(int64_t N, int lo, int hi, int ns,
                                                         const double* __restrict__ A,
                                                         const double* __restrict__ ml, double c,
                                                         double* __restrict__ H) {
   const int i = lo + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
   if (i >= hi) return;
-  for (int d = 0; d < nd; ++d) {
+  for (int d = 0; d < ns; ++d) {
     const int64_t q = d * N + i;
-    H[q] = (d == dg) ? ml[i] + c * A[q] : c * A[q];
+    H[q] = (d == 0) ? ml[i] + c * A[q] : c * A[q];
   }
 }
 }  // namespace
 
-void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int nd, int dg, const double* A,
+void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int ns, const double* A,
                         const double* ml, double c, double* H) {
   if (hi <= lo) return;
   k_build_h_dia<<<dim3(static_cast<unsigned>((hi - lo + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
-      N, lo, hi, nd, dg, A, ml, c, H);
+      N, lo, hi, ns, A, ml, c, H);
 }
 
 void launch_iota(hipStream_t s, int32_t* out, int64_t n) {

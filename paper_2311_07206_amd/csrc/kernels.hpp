@@ -67,9 +67,12 @@ struct Csr {
 };
 
 // A matrix on the assembly pattern, stored either as CSR (nd == 0) or in
-// diagonal storage: for instance i, entry d of row r lies in column
-// r + off[i*nd + d] with value dval[d*N + r]; entries absent from the pattern
-// hold 0, and a column outside the instance is replaced by r itself.
+// symmetric diagonal storage: for instance i, entry d of row r lies in
+// column r + off[i*nd + d] (offsets sorted, symmetric about 0, offset 0 at
+// d = nd/2); the entries with offset o >= 0 are dval[(d - nd/2)*N + r], an
+// entry with offset -o is read as the entry (r - o, r).  Entries absent from
+// the pattern hold 0, and a column outside the instance is replaced by r
+// itself (with value 0).
 struct Mat {
   const int32_t* rowptr;
   const int32_t* col;
@@ -183,8 +186,9 @@ void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32
                     const double* A, const double* ml, double c, double* H, double* dinv,
                     const int32_t* ppos, const double* pmass);
 void launch_iota(hipStream_t s, int32_t* out, int64_t n);
-// Diagonal storage of H_m for the rows [lo, hi) of one instance (dg = index of offset 0).
-void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int nd, int dg, const double* A,
+// Diagonal storage of H_m = ML + c A for the rows [lo, hi): ns stored
+// diagonals, the first of which is offset 0.
+void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int ns, const double* A,
                         const double* ml, double c, double* H);
 
 // ---- reverse (adjoint) step; see adjoint_kernels.hip for the equations

@@ -75,6 +75,7 @@ def test_assembly_matches_oracle(P):
     A.eliminate_zeros()
     G = sp.csr_matrix((val, col, rp), shape=(P.N, P.N))
     assert abs(G - A).max() <= 1e-14 * abs(A).max()
+    assert (G != G.T).nnz == 0          # exactly symmetric (the diagonal storage keeps offsets >= 0)
     assert np.allclose(ml, lumped_mass(P.coords, P.elems, P.N), rtol=1e-14, atol=0)
     for i in range(P.N):   # sorted columns, diagonal present
         c = col[rp[i]:rp[i + 1]]
