@@ -63,9 +63,22 @@ class Monodomain:
 
 
 class SDC:
-    """IMEX SDC on Radau-IIA nodes with nested active index sets."""
+    """IMEX SDC on Radau-IIA nodes with nested active index sets.
 
-    def __init__(self, model, M, dt, theta, cg_rtol=1e-12, cg_maxit=1000):
+    Optional energy-norm termination (Sec. 3.2): with tol_sdc > 0, an
+    instance stops sweeping once, after at least K_min sweeps,
+
+        sum_m dv_m^T H_m dv_m  <=  ((1 - rho) / rho * tol_sdc)^2,
+
+    the energy norm of the sweep's corrections with the system matrices
+    H_m (reading: the paper's lumped reaction Jacobian is not part of H_m, as
+    in the sweep itself).  A stopped instance's rows leave the active set;
+    the step ends when every instance has stopped or after K sweeps.
+    ``inst_of`` maps rows to instances (default: one instance).
+    """
+
+    def __init__(self, model, M, dt, theta, cg_rtol=1e-12, cg_maxit=1000, tol_sdc=0.0, rho=0.05, K_min=1,
+                 inst_of=None):
         self.model = model
         self.col = Collocation(M)
         self.M = M
@@ -73,8 +86,20 @@ class SDC:
         self.theta = float(theta)
         self.cg_rtol = cg_rtol
         self.cg_maxit = cg_maxit
+        self.tol_sdc = float(tol_sdc)
+        self.rho = float(rho)
+        self.K_min = int(K_min)
+        self.inst_of = np.zeros(model.N, dtype=np.int64) if inst_of is None else np.asarray(inst_of, dtype=np.int64)
+        self.n_inst = int(self.inst_of.max()) + 1 if self.inst_of.size else 1
         ML, A = model.ML, model.A
         self.H = [(sp.diags(ML) + self.dt * self.col.QI[m, m] * A).tocsr() for m in range(M)]
+
+    def energy(self, dv):
+        """Per instance: sum_m dv_m^T H_m dv_m."""
+        e = np.zeros(self.n_inst)
+        for m in range(self.M):
+            np.add.at(e, self.inst_of, dv[m] * (self.H[m] @ dv[m]))
+        return e
 
     # -- one step -------------------------------------------------------
     def spread(self, v0, w0):
@@ -149,15 +174,24 @@ class SDC:
         st = self.spread(v0, w0)
         idx = np.arange(self.model.N)
         infos = []
+        stopped = np.zeros(self.n_inst, dtype=bool)
         for k in range(K):
             if idx_replay is not None and idx_replay[k] is not None:
                 idx = np.asarray(idx_replay[k], dtype=np.int64)
             nxt, info = self.sweep(st, idx, None if cg_replay is None else cg_replay[k])
+            if self.tol_sdc > 0.0:
+                e = self.energy(info["dv"])
+                info["energy"] = e
+                if k + 1 >= self.K_min:
+                    stopped |= e <= ((1.0 - self.rho) / self.rho * self.tol_sdc) ** 2
+                nxt = nxt[~stopped[self.inst_of[nxt]]]
             if not keep:
                 info.pop("dv")
                 info.pop("amax")
             infos.append(info)
             idx = nxt
+            if stopped.all():
+                break
         return st["v"][-1].copy(), st["w"][-1].copy(), infos
 
 
@@ -191,10 +225,12 @@ def run(sdc, v, w, n_steps, K, stimuli=(), t0=0.0, idx_replay=None, cg_replay=No
     return v, w, log
 
 
-def build(problem):
+def build(problem, tol_sdc=0.0, rho=0.05, K_min=1):
     """Assemble the oracle model and SDC integrator for a workload Problem."""
     from .assembly import lumped_mass, stiffness
     ML = lumped_mass(problem.coords, problem.elems, problem.N)
     A = stiffness(problem.coords, problem.elems, problem.elem_tensor, problem.node_sigma, problem.N)
     model = Monodomain(ML, A, problem.node_ionic())
-    return SDC(model, problem.M, problem.dt, problem.theta, problem.cg_rtol, problem.cg_maxit)
+    inst_of = np.repeat(np.arange(problem.n_inst), np.diff(problem.node_off))
+    return SDC(model, problem.M, problem.dt, problem.theta, problem.cg_rtol, problem.cg_maxit,
+               tol_sdc=tol_sdc, rho=rho, K_min=K_min, inst_of=inst_of)

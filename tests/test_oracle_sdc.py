@@ -303,3 +303,71 @@ def test_selection_uses_max_correction_over_nodes():
     nxt, _ = s.sweep(copy.deepcopy(st1), idx)
     brute = np.array([r for r in idx if max(abs(dv[m, r]) for m in range(s.M)) >= s.theta])
     assert np.array_equal(nxt, brute) and i in nxt
+
+
+# ---------------------------------------------------------------- energy-norm termination (Sec. 3.2)
+
+def _sdc_energy_setup():
+    model, x = _line_model(12, D=1e-2)
+    v0 = np.where(x < 0.3, 1.0, 0.0) + 0.05 * np.sin(7 * x)
+    w0 = 0.1 * np.cos(3 * x) ** 2
+    return model, v0, w0
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-7])
+def test_energy_termination_meets_its_tolerance(tol):
+    # the criterion estimates the remaining error by the geometric series
+    # rho/(1-rho) ||delta^k||: with rho at least the actual contraction, the
+    # last node's value is within tol of the collocation solution in the H norm
+    model, v0, w0 = _sdc_energy_setup()
+    M, dt = 3, 0.1
+    V, _ = collocation_solve(model, M, dt, v0, w0)
+    s = SDC(model, M, dt, theta=0.0, cg_rtol=1e-15, tol_sdc=tol, rho=0.6)
+    v_end, _, infos = s.step(v0, w0, 60)
+    assert 1 < len(infos) < 60
+    e = v_end - V[-1]
+    assert np.sqrt(e @ (s.H[M - 1] @ e)) <= tol
+    # one sweep earlier the criterion did not hold
+    thr = ((1 - 0.6) / 0.6 * tol) ** 2
+    assert infos[-2]["energy"][0] > thr >= infos[-1]["energy"][0]
+
+
+def test_energy_termination_extremes_equal_fixed_sweep_counts():
+    model, v0, w0 = _sdc_energy_setup()
+    fixed = SDC(model, 3, 0.1, theta=0.0)
+    v4, w4, _ = fixed.step(v0, w0, 4)
+    v2, w2, _ = fixed.step(v0, w0, 2)
+    tiny = SDC(model, 3, 0.1, theta=0.0, tol_sdc=1e-300)
+    vt, wt, it = tiny.step(v0, w0, 4)
+    assert len(it) == 4 and np.array_equal(vt, v4) and np.array_equal(wt, w4)
+    huge = SDC(model, 3, 0.1, theta=0.0, tol_sdc=1e10, K_min=2)
+    vh, wh, ih = huge.step(v0, w0, 4)
+    assert len(ih) == 2 and np.array_equal(vh, v2) and np.array_equal(wh, w2)
+
+
+def test_energy_termination_is_per_instance():
+    # batched instances stop independently: each equals its own run alone
+    from workloads import config4
+    from workloads.configs import Problem
+    P = config4(n_inst=3, sizes=(10, 18), n_steps=3)
+    # no stimulus in instance 0: it stays at rest and stops after one sweep
+    lo1 = P.node_off[1]
+    P.stimuli = [(t, nodes[nodes >= lo1], val) for t, nodes, val in P.stimuli]
+    tol = 3e-6
+    batched = build(P, tol_sdc=tol, rho=0.3, K_min=1)
+    vb, wb, logb = run(batched, P.v_init, P.w_init, 3, 8, P.stimuli)
+    n_sweeps = set()
+    for i in range(P.n_inst):
+        lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
+        e0, e1 = int(P.elem_off[i]), int(P.elem_off[i + 1])
+        stim = [(t, nodes[(nodes >= lo) & (nodes < hi)] - lo, val) for t, nodes, val in P.stimuli]
+        sub = Problem(name="inst", dim=P.dim, coords=P.coords[lo:hi], elems=P.elems[e0:e1] - lo,
+                      elem_tensor=P.elem_tensor[e0:e1], node_sigma=P.node_sigma[lo:hi],
+                      node_off=np.array([0, hi - lo]), elem_off=np.array([0, e1 - e0]),
+                      ionic=P.ionic[i:i + 1], M=P.M, K=P.K, dt=P.dt, n_steps=3, theta=P.theta,
+                      stimuli=stim, v_init=P.v_init[lo:hi], w_init=P.w_init[lo:hi])
+        alone = build(sub, tol_sdc=tol, rho=0.3, K_min=1)
+        va, wa, loga = run(alone, sub.v_init, sub.w_init, 3, 8, sub.stimuli)
+        assert np.abs(vb[lo:hi] - va).max() <= 1e-12 * max(np.abs(va).max(), 1.0)
+        n_sweeps.add(tuple(len(st) for st in loga))
+    assert len(n_sweeps) > 1          # the instances did stop at different sweeps
