@@ -71,6 +71,14 @@ typedef struct {
   int32_t format;     /* matrix storage: 0 = timed choice at setup, 1 = CSR,   */
                       /* 2 = diagonal (every instance's rows use <= 32        */
                       /* distinct column offsets; else SDC_ERR_ARG)           */
+  /* Energy-norm termination (paper Sec. 3.2), off when tol_sdc <= 0: after  */
+  /* at least K_min sweeps an instance stops once                            */
+  /*   sum_m dv_m^T H_m dv_m <= ((1 - rho) / rho * tol_sdc)^2                 */
+  /* (its rows leave the active set); the step ends when every instance has  */
+  /* stopped, or after K sweeps.  Not combined with the reverse pass.        */
+  int32_t K_min;      /* 1..K (values <= 0 mean 1)                             */
+  double tol_sdc;     /* TOL_SDC                                               */
+  double rho;         /* assumed contraction factor, 0 < rho < 1               */
 } sdc_params;
 
 /* Per-sweep statistics (sums over instances unless stated). */
@@ -81,6 +89,9 @@ typedef struct {
   int32_t cg_iters_max[SDC_MAX_NODES]; /* max CG iterations over instances      */
   int64_t cg_row_iters[SDC_MAX_NODES]; /* sum_inst iters * active rows          */
   int64_t cg_nnz_iters[SDC_MAX_NODES]; /* sum_inst iters * active entries       */
+  double energy;                       /* sum_inst sum_m dv_m^T H_m dv_m (only   */
+                                       /* with the energy-norm termination on)   */
+  int32_t n_stopped;                   /* instances stopped after this sweep     */
 } sdc_sweep_stats;
 
 typedef struct {

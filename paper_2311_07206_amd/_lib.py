@@ -23,13 +23,14 @@ ERRORS = {
 
 class Params(ctypes.Structure):
     _fields_ = [("M", c_int32), ("K", c_int32), ("dt", c_double), ("theta", c_double),
-                ("cg_rtol", c_double), ("cg_maxit", c_int32), ("format", c_int32)]
+                ("cg_rtol", c_double), ("cg_maxit", c_int32), ("format", c_int32),
+                ("K_min", c_int32), ("tol_sdc", c_double), ("rho", c_double)]
 
 
 class SweepStats(ctypes.Structure):
     _fields_ = [("n_active", c_int64), ("nnz_active", c_int64), ("n_next", c_int64),
                 ("cg_iters_max", c_int32 * MAX_NODES), ("cg_row_iters", c_int64 * MAX_NODES),
-                ("cg_nnz_iters", c_int64 * MAX_NODES)]
+                ("cg_nnz_iters", c_int64 * MAX_NODES), ("energy", c_double), ("n_stopped", c_int32)]
 
     def as_dict(self, M):
         return {
@@ -37,6 +38,7 @@ class SweepStats(ctypes.Structure):
             "cg_iters_max": list(self.cg_iters_max[:M]),
             "cg_row_iters": list(self.cg_row_iters[:M]),
             "cg_nnz_iters": list(self.cg_nnz_iters[:M]),
+            "energy": self.energy, "n_stopped": self.n_stopped,
         }
 
 

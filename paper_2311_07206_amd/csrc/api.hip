@@ -267,7 +267,18 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     launch_post_sites(ctx->stream, M, m, map, N, ctx->ionic_d, ctx->v + m * N, ctx->w + m * N,
                       ctx->I + m * N, ctx->R + m * N, ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N,
                       ctx->dR, ctx->cargs, emi);
+    if (ctx->terminate()) launch_energy(ctx->stream, map, N, ctx->H(m), x, ctx->e_part + m * ctx->all.nblk);
     HIPC(hipGetLastError());
+  }
+  if (ctx->terminate()) {
+    // energy-norm termination: per-instance energy and stop decision on the device
+    const double q = (1.0 - ctx->prm.rho) / ctx->prm.rho * ctx->prm.tol_sdc;
+    launch_energy_stop(ctx->stream, map, M, ctx->all.nblk, ctx->e_part, q * q, ctx->k + 1 >= ctx->k_min(),
+                       ctx->inst_energy, ctx->inst_stop);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(ctx->h_term, ctx->inst_energy, ni * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipMemcpyAsync(reinterpret_cast<int32_t*>(ctx->h_term + ni), ctx->inst_stop, ni * 4,
+                        hipMemcpyDeviceToHost, ctx->stream));
   }
   if (async) {
     // one synchronisation per sweep: the nodes' CG outcomes (and below, the next set's size)
@@ -286,11 +297,12 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     TRY(map_list(ctx, slot, ctx->pin[next], ctx->pin_n[next]));
     ctx->cur = slot;
     synced = true;
-  } else if (ctx->prm.theta > 0.0 && select_next) {
+  } else if ((ctx->prm.theta > 0.0 || ctx->terminate()) && select_next) {
     const int slot = ctx->cur == 0 ? 1 : 0;
     MapBuf& nm = ctx->dyn[slot];
     launch_select(ctx->stream, map, ni, ctx->rowptr, ctx->amax, ctx->prm.theta, ctx->sel_cnt,
-                  ctx->sel_nnz, ctx->list[slot], nullptr, ctx->next(nm), ctx->zv());
+                  ctx->sel_nnz, ctx->list[slot], nullptr, ctx->next(nm), ctx->zv(),
+                  ctx->terminate() ? ctx->inst_stop : nullptr);
     HIPC(hipGetLastError());
     TRY(fetch_map(ctx, &nm));
     nm.idx = ctx->list[slot];
@@ -326,6 +338,18 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
         for (int q = 0; q < m; ++q) base += ev_budget[q];
         TRY(account_timing_at(ctx, view, base, ev_budget[m], iters[m].data()));
       }
+    }
+  }
+  if (ctx->terminate()) {
+    if (!synced && !async) HIPC(hipStreamSynchronize(ctx->stream));
+    const int32_t* stop = reinterpret_cast<const int32_t*>(ctx->h_term + ni);
+    ctx->all_stopped = true;
+    for (int i = 0; i < ni; ++i) {
+      if (st) {
+        st->energy += ctx->h_term[i];
+        st->n_stopped += stop[i] != 0;
+      }
+      ctx->all_stopped = ctx->all_stopped && stop[i] != 0;
     }
   }
   if (st) {
@@ -450,6 +474,10 @@ int restart_step(sdc_ctx* ctx) {
   ctx->cur = -1;
   ctx->k = 0;
   ctx->in_step = true;
+  if (ctx->terminate()) {
+    HIPC(hipMemsetAsync(ctx->inst_stop, 0, ctx->n_inst * 4, ctx->stream));
+    ctx->all_stopped = false;
+  }
   return SDC_OK;
 }
 
@@ -552,6 +580,7 @@ void sdc_destroy(sdc_ctx* ctx) {
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->h_i32) (void)hipHostFree(ctx->h_i32);
   if (ctx->h_i64) (void)hipHostFree(ctx->h_i64);
+  if (ctx->h_term) (void)hipHostFree(ctx->h_term);
   delete ctx;
 }
 
@@ -589,6 +618,8 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   if (prm->K < 1 || prm->K > SDC_MAX_SWEEPS) return fail(ctx, SDC_ERR_ARG, "K must be in 1..%d", SDC_MAX_SWEEPS);
   if (!(prm->dt > 0.0) || !(prm->cg_rtol > 0.0) || prm->cg_maxit < 1 || prm->format < 0 || prm->format > 2)
     return fail(ctx, SDC_ERR_ARG, "dt, cg_rtol must be > 0, cg_maxit >= 1, format in 0..2");
+  if (prm->tol_sdc > 0.0 && !(prm->rho > 0.0 && prm->rho < 1.0))
+    return fail(ctx, SDC_ERR_ARG, "energy-norm termination needs 0 < rho < 1");
   if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
   if (node_off[0] != 0 || elem_off[0] != 0) return fail(ctx, SDC_ERR_ARG, "offsets must start at 0");
   for (int i = 0; i < n_inst; ++i)
@@ -731,6 +762,12 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     TRY(dalloc(ctx, &ctx->part[q], 4 * static_cast<size_t>(nblk_all)));
   }
   TRY(dalloc(ctx, &ctx->cg_done, n_inst));
+  if (prm->tol_sdc > 0.0) {
+    TRY(dalloc(ctx, &ctx->e_part, static_cast<size_t>(M) * nblk_all));
+    TRY(dalloc(ctx, &ctx->inst_energy, n_inst));
+    TRY(dalloc(ctx, &ctx->inst_stop, n_inst));
+    HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_term), 2 * n_inst * sizeof(double)));
+  }
   TRY(dalloc(ctx, &ctx->cg_iters, n_inst));
   TRY(dalloc(ctx, &ctx->cg_blk_done, nblk_all));
   TRY(dalloc(ctx, &ctx->sel_cnt, nblk_all));
@@ -835,6 +872,7 @@ int sdc_step(sdc_ctx* ctx, double* v, double* w, double t, sdc_step_stats* stats
       }
       if (short_budget) break;
       if (stats) stats->n_sweeps = k + 1;
+      if (ctx->terminate() && ctx->all_stopped) break;   // energy-norm termination
     }
     if (!short_budget) break;
   }
@@ -914,7 +952,7 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
   MapBuf& nm = ctx->dyn[1];
   ZeroVecs none{{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}, nullptr, 0, 0};
   launch_select(ctx->stream, ctx->dyn[0].dev(), ctx->n_inst, ctx->rowptr, amax, theta, ctx->sel_cnt,
-                ctx->sel_nnz, ctx->list[1], idx_out, ctx->next(nm), none);
+                ctx->sel_nnz, ctx->list[1], idx_out, ctx->next(nm), none, nullptr);
   HIPC(hipGetLastError());
   TRY(fetch_map(ctx, &nm));
   *n_out = nm.rows;

@@ -155,6 +155,14 @@ struct sdc_ctx {
   int32_t* hist_done = nullptr;    // [M][n_inst]
   int32_t* hist_iters = nullptr;   // [M][n_inst]
   int64_t redone_steps = 0;
+  // energy-norm termination (prm.tol_sdc > 0)
+  double* e_part = nullptr;        // [M][nblk of all] per-block energies of the sweep
+  double* inst_energy = nullptr;   // [n_inst]
+  int32_t* inst_stop = nullptr;    // [n_inst] instance stopped in this step
+  double* h_term = nullptr;        // pinned: energies [n_inst], then stop flags (int32)
+  bool all_stopped = false;
+  bool terminate() const { return prm.tol_sdc > 0.0; }
+  int k_min() const { return std::max(1, std::min(prm.K_min, prm.K)); }
 
   // kernel timing (bench only)
   bool prof = false;

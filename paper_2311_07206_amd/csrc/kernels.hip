@@ -557,10 +557,10 @@ __device__ inline bool keep_row(double a, double theta) { return theta <= 0.0 ||
 __global__ __launch_bounds__(kBlock) void k_select_count(Map map, const int32_t* __restrict__ rowptr,
                                                          const double* __restrict__ amax,
                                                          double theta, int32_t* sel_cnt,
-                                                         int32_t* sel_nnz) {
+                                                         int32_t* sel_nnz, const int32_t* __restrict__ stop) {
   __shared__ int sc[4], sn[4];
   const Row rw = map_row(map);
-  const bool keep = rw.valid && keep_row(amax[rw.row], theta);
+  const bool keep = rw.valid && !(stop && stop[rw.inst]) && keep_row(amax[rw.row], theta);
   const unsigned long long mask = __ballot(keep);
   int nz = keep ? rowptr[rw.row + 1] - rowptr[rw.row] : 0;
 #pragma unroll
@@ -681,10 +681,11 @@ __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* 
                                                          double theta,
                                                          const int32_t* __restrict__ sel_off, NextMap nm,
                                                          int32_t* __restrict__ idx_pad,
-                                                         int32_t* __restrict__ idx_compact, ZeroVecs zv) {
+                                                         int32_t* __restrict__ idx_compact, ZeroVecs zv,
+                                                         const int32_t* __restrict__ stop) {
   __shared__ int wc[4];
   const Row rw = map_row(map);
-  const bool keep = rw.valid && keep_row(amax[rw.row], theta);
+  const bool keep = rw.valid && !(stop && stop[rw.inst]) && keep_row(amax[rw.row], theta);
   const unsigned long long mask = __ballot(keep);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) wc[wid] = __popcll(mask);
@@ -769,6 +770,41 @@ __global__ __launch_bounds__(kScanThreads) void k_map_from_list(const int32_t* _
   __syncthreads();
   build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, n);
   if (threadIdx.x == 0) nm.totals[2] = bad;
+}
+
+// Energy of node m's correction on the map's rows: partial sums of x_i (H x)_i.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_energy(Map map, int64_t N, Mat H, const double* __restrict__ x,
+                                                   double* __restrict__ e_part) {
+  __shared__ double sh[16];
+  const Row rw = map_row(map);
+  double e[1] = {0.0};
+  if (rw.valid) {
+    const int i = rw.row;
+    double hx = 0.0;
+    for_entries<S>(H, N, rw, i, [&](double h, int k) { hx += h * x[k]; });
+    e[0] = x[i] * hx;
+  }
+  block_sum<1>(e, sh);
+  if (threadIdx.x == 0) e_part[rw.blk] = e[0];
+}
+
+// One block per instance: energy over the M nodes and the stopping decision.
+__global__ __launch_bounds__(kBlock) void k_energy_stop(const int32_t* __restrict__ inst_blk0,
+                                                        const int32_t* __restrict__ inst_nblk, int M,
+                                                        int64_t stride, const double* __restrict__ e_part,
+                                                        double thr, int allow, double* __restrict__ energy,
+                                                        int32_t* __restrict__ stop) {
+  __shared__ double sh[16];
+  const int inst = blockIdx.x, b0 = inst_blk0[inst], nb = inst_nblk[inst];
+  double acc[1] = {0.0};
+  for (int m = 0; m < M; ++m)
+    for (int b = threadIdx.x; b < nb; b += kBlock) acc[0] += e_part[m * stride + b0 + b];
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) {
+    energy[inst] = acc[0];
+    if (allow && acc[0] <= thr) stop[inst] = 1;
+  }
 }
 
 // Copy of a list (validated by k_map_from_list) into the padded layout of its map.
@@ -928,12 +964,27 @@ void launch_post_sites(hipStream_t s, int M, int m, const Map& map, int64_t N, c
 
 void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* rowptr,
                    const double* amax, double theta, int32_t* sel_cnt, int32_t* sel_nnz,
-                   int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm, const ZeroVecs& zv) {
+                   int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm, const ZeroVecs& zv,
+                   const int32_t* stop) {
   if (map.nblk > 0)
-    k_select_count<<<grid(map.nblk), kBlock, 0, s>>>(map, rowptr, amax, theta, sel_cnt, sel_nnz);
+    k_select_count<<<grid(map.nblk), kBlock, 0, s>>>(map, rowptr, amax, theta, sel_cnt, sel_nnz, stop);
   k_select_scan<<<1, kScanThreads, 0, s>>>(map, n_inst, sel_cnt, sel_nnz, nm);
   if (map.nblk > 0)
-    k_select_write<<<grid(map.nblk), kBlock, 0, s>>>(map, amax, theta, sel_cnt, nm, idx_pad, idx_compact, zv);
+    k_select_write<<<grid(map.nblk), kBlock, 0, s>>>(map, amax, theta, sel_cnt, nm, idx_pad, idx_compact, zv,
+                                                     stop);
+}
+
+void launch_energy(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* x, double* e_part) {
+  if (map.nblk <= 0) return;
+  dispatch_storage(H.nd, [&](auto st) {
+    k_energy<decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, x, e_part);
+  });
+}
+
+void launch_energy_stop(hipStream_t s, const Map& map, int M, int64_t stride, const double* e_part,
+                        double thr, int allow, double* energy, int32_t* stop) {
+  k_energy_stop<<<dim3(static_cast<unsigned>(map.n_inst)), kBlock, 0, s>>>(map.inst_blk0, map.inst_nblk, M, stride,
+                                                                           e_part, thr, allow, energy, stop);
 }
 
 void launch_zero_rows(hipStream_t s, const Map& map, const ZeroVecs& zv) {

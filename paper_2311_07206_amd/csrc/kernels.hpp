@@ -166,9 +166,18 @@ struct ZeroVecs {
 };
 // The kept rows are written to idx_pad (the padded list of the next map) and,
 // when idx_compact is not null, also as one ascending list there.
+// Rows of instances with stop[inst] != 0 (stop may be null) are dropped too.
 void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* rowptr,
                    const double* amax, double theta, int32_t* sel_cnt, int32_t* sel_nnz,
-                   int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm, const ZeroVecs& zv);
+                   int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm, const ZeroVecs& zv,
+                   const int32_t* stop);
+// Energy-norm termination (Sec. 3.2): per block of the map, the partial sum
+// of x_i (H x)_i over its rows -> e_part[block]; then, per instance, the sum
+// over the M nodes' partials (node-major, blocks in order) -> energy[inst],
+// and stop[inst] |= allow && energy <= thr.
+void launch_energy(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* x, double* e_part);
+void launch_energy_stop(hipStream_t s, const Map& map, int M, int64_t stride, const double* e_part,
+                        double thr, int allow, double* energy, int32_t* stop);
 // Zero the ZeroVecs entries on every row of the map (used before a pinned set).
 void launch_zero_rows(hipStream_t s, const Map& map, const ZeroVecs& zv);
 // Work map of an arbitrary ascending list (per-instance split by node_off),

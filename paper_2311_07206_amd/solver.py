@@ -42,7 +42,8 @@ class Solver:
     """One library context: an assembled mesh (possibly several instances)."""
 
     def __init__(self, coords, elems, elem_tensor, node_sigma, ionic, node_off, elem_off,
-                 M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None, emi=None):
+                 M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None, emi=None,
+                 tol_sdc=0.0, rho=0.05, K_min=1):
         """emi: None (monodomain) or a dict with the cell-by-cell couplings
         mem_intra, mem_extra, mem_len, cm, gap_a, gap_b, gap_len, g_gap,
         robin_len, eps (see sdc_emi)."""
@@ -60,7 +61,8 @@ class Solver:
         dim = coords.shape[1]
         self.M, self.K = int(M), int(K)
         prm = Params(M=self.M, K=self.K, dt=float(dt), theta=float(theta), cg_rtol=float(cg_rtol),
-                     cg_maxit=int(cg_maxit), format=int(fmt))
+                     cg_maxit=int(cg_maxit), format=int(fmt), K_min=int(K_min), tol_sdc=float(tol_sdc),
+                     rho=float(rho))
         node_off_a, p_no = _host(node_off, np.int64)
         coords_a, p_c = _host(coords, np.float64)
         elem_off_a, p_eo = _host(elem_off, np.int64)
