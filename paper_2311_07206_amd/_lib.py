@@ -104,7 +104,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run python -m paper_2311_07206_amd.build "
                            "(or python paper_2311_07206_amd/build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():

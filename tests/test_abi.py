@@ -31,7 +31,7 @@ def _declared(root):
 def lib(root):
     path = _lib_path(root)
     if not os.path.exists(path):
-        pytest.skip("libsdc.so not built (run __graft_entry__.build())")
+        pytest.skip("libsdc.so not built (run python -m paper_2311_07206_amd.build)")
     return ctypes.CDLL(path)
 
 
