@@ -828,6 +828,15 @@ __global__ __launch_bounds__(kBlock) void k_map_rows(Map map, int32_t* __restric
 
 inline dim3 grid(int nblk) { return dim3(static_cast<unsigned>(nblk > 0 ? nblk : 1)); }
 
+// The matrix-vector kernels outside the CG iteration (initial residual,
+// energy) need few registers and run ~7-8 blocks per CU; on large maps
+// their rows and the neighbour rows the stencil reaches (in 3D a plane
+// away) then exceed the L2 and are fetched several times (128^3: 1.2 GB
+// instead of 0.3 GB).  A dynamic LDS reservation caps such launches at 3
+// blocks per CU.  The sweep kernels are register-limited already and lose
+// time under the cap.
+inline size_t cap_lds(const Map& map) { return map.nblk > 2048 ? 48 * 1024 : 0; }
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -891,8 +900,10 @@ void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, do
 void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const Mat& H,
                      const double* dinv, const double* r0, double* w0, double* part_out,
                      const CgState& cg) {
+  const size_t lds = cap_lds(map);
   dispatch_storage(H.nd, [&](auto st) {
-    k_cg_start<decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, n_inst, N, H, dinv, r0, w0, part_out, cg);
+    k_cg_start<decltype(st)::value><<<grid(map.nblk), kBlock, lds, s>>>(map, n_inst, N, H, dinv, r0, w0, part_out,
+                                                                        cg);
   });
 }
 
@@ -977,7 +988,7 @@ void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* row
 void launch_energy(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* x, double* e_part) {
   if (map.nblk <= 0) return;
   dispatch_storage(H.nd, [&](auto st) {
-    k_energy<decltype(st)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, H, x, e_part);
+    k_energy<decltype(st)::value><<<grid(map.nblk), kBlock, cap_lds(map), s>>>(map, N, H, x, e_part);
   });
 }
 
