@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# wall-clock speedups of adaptive over non-adaptive SDC that the paper
+# reports on CPUs (Kaskade 7; 2D: Core i7-9700T, 3D: Xeon E5), for context
+PAPER_SPEEDUP = {"2d_monodomain": 2.13, "2d_emi": 3.336, "3d_monodomain": 3.29, "3d_emi": 4.344}
 COUNTERS = os.path.join(ROOT, "profiles", "k_cg_iter_2d512_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2311_07206_amd", "csrc", "kernels.hip")
 
@@ -95,7 +98,7 @@ def summarize_counters(fetch_csv, write_csv):
         if "k_cg_iter" in a["Kernel_Name"]:
             cg_f.append(float(a["Counter_Value"]))
             cg_w.append(float(b["Counter_Value"]))
-        elif "copyBuffer" in a["Kernel_Name"] and float(b["Counter_Value"]) > 200000:
+        elif "copyBuffer" in a["Kernel_Name"] and abs(float(b["Counter_Value"]) - 262144.0) < 13000.0:
             copy.append((float(a["Counter_Value"]), float(b["Counter_Value"])))
     cg_f, cg_w = np.array(cg_f), np.array(cg_w)
     work = cg_w > 1.0
@@ -123,6 +126,8 @@ def parse():
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 3D workload")
     ap.add_argument("--no-emi", action="store_true", help="skip the 64x16-cell cell-by-cell workload")
     ap.add_argument("--emi-steps", type=int, default=3)
+    ap.add_argument("--no-speedup", action="store_true",
+                    help="skip the non-adaptive (theta = 0) runs over the same steps")
     ap.add_argument("--profile-warmup", action="store_true",
                     help="account CG kernel bytes from the first step (matches counter runs)")
     ap.add_argument("--calib", action="store_true",
@@ -283,16 +288,61 @@ def main():
         if args.profile_warmup:
             out["roofline"]["scope"] = "warm-up and timed steps"
     s.close()
+    out["copy_GBps"] = copy_bandwidth()
+    if "roofline" in out:
+        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / out["copy_GBps"]
+    if not args.no_speedup:
+        # the same timed steps without the drop tolerance (every row in every sweep)
+        el0 = nonadaptive_run(P, v_start, w_start, t_start, args.steps)
+        out["adaptive_vs_nonadaptive"] = {
+            "nonadaptive_ms_per_step": 1e3 * el0 / args.steps, "adaptive_ms_per_step": out["ms_per_step"],
+            "speedup": el0 / elapsed, "paper_cpu_speedup_2d_monodomain": PAPER_SPEEDUP["2d_monodomain"]}
     if not args.no_batch:
         out["batched"], out["adjoint"] = batched_and_adjoint(args.batch_steps)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio_ckpt10"]
     if not args.no_3d:
-        out["workload_3d"] = workload_3d()
+        out["workload_3d"] = workload_3d(speedup=not args.no_speedup)
     if not args.no_emi:
-        out["workload_emi"] = workload_emi(args.emi_steps)
+        out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Device-to-device copy of 1 GiB (read + write counted), best of `reps`,
+    timed with events: the bandwidth a plain streaming kernel reaches."""
+    import torch
+    dev = torch.device("cuda", 0)
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2 * nbytes / best / 1e9
+
+
+def nonadaptive_run(P, v0, w0, t0, nsteps, warm_budget=True, **kw):
+    """Wall time of `nsteps` steps with theta = 0 (all rows in every sweep) from
+    the given state, for the adaptive/non-adaptive speedup."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    s = Solver.from_problem(P, theta=0.0, **kw)
+    v, w = torch.tensor(v0, device=dev), torch.tensor(w0, device=dev)
+    if warm_budget:
+        s.step(v.clone(), w.clone(), t0)   # iteration history for the budgets
+    el, _ = _timed_steps(s, v, w, t0, P.dt, nsteps, torch.cuda.synchronize)
+    s.close()
+    return el
 
 
 def _timed_steps(solver, v, w, t0, dt, n, sync):
@@ -370,7 +420,7 @@ def batched_and_adjoint(nsteps):
     return batched, adj
 
 
-def workload_3d(nsteps=10, warm=10):
+def workload_3d(nsteps=10, warm=10, speedup=True):
     """The 128^3 3D workload (2.1M dofs, 27M stored entries): HBM-resident."""
     import torch
 
@@ -384,6 +434,7 @@ def workload_3d(nsteps=10, warm=10):
     w = torch.tensor(P.w_init, device=dev)
     for k in range(warm):
         s.step(v, w, k * P.dt)
+    v0, w0 = v.cpu().numpy().copy(), w.cpu().numpy().copy()
     s.profile(True)
     el, logs = _timed_steps(s, v, w, warm * P.dt, P.dt, nsteps, torch.cuda.synchronize)
     prof = s.profile_read()
@@ -398,10 +449,14 @@ def workload_3d(nsteps=10, warm=10):
         out["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
         out["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]
     s.close()
+    if speedup:
+        el0 = nonadaptive_run(P, v0, w0, warm * P.dt, nsteps)
+        out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / nsteps, "speedup": el0 / el,
+                                          "paper_cpu_speedup_3d_monodomain": PAPER_SPEEDUP["3d_monodomain"]}
     return out
 
 
-def workload_emi(nsteps=3, warm=1):
+def workload_emi(nsteps=3, warm=1, speedup=True):
     """The cell-by-cell workload (64 x 16 myocytes, 390,564 potential dofs,
     81,920 membrane sites), from the stimulus: CSR storage, Jacobi-PCG."""
     import torch
@@ -416,6 +471,7 @@ def workload_emi(nsteps=3, warm=1):
     w = torch.tensor(P.w_init, device=dev)
     for k in range(warm):
         s.step(u, w, k * P.dt)
+    u0, w0 = u.cpu().numpy().copy(), w.cpu().numpy().copy()
     s.profile(True)
     el, logs = _timed_steps(s, u, w, warm * P.dt, P.dt, nsteps, torch.cuda.synchronize)
     prof = s.profile_read()
@@ -432,6 +488,12 @@ def workload_emi(nsteps=3, warm=1):
         out["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
         out["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]
     s.close()
+    if speedup:
+        # solves above the asynchronous budget limit run synchronously, so
+        # the missing iteration history costs little here
+        el0 = nonadaptive_run(P, u0, w0, warm * P.dt, nsteps, warm_budget=False, cg_maxit=200000)
+        out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / nsteps, "speedup": el0 / el,
+                                          "paper_cpu_speedup_2d_emi": PAPER_SPEEDUP["2d_emi"]}
     return out
 
 

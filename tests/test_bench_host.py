@@ -1,0 +1,96 @@
+"""Host-side logic of bench.py: the single-GPU guard, the rocprofv3 CSV
+summaries and the link between committed counters and the kernel source."""
+import csv
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def _counter_csv(path, rows):
+    with open(path, "w", newline="") as f:
+        wr = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Value"])
+        wr.writeheader()
+        for i, (name, val) in enumerate(rows):
+            wr.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Counter_Value": val})
+
+
+def test_summarize_counters_calibrates_on_the_256_mib_copy(tmp_path):
+    # a 256 MiB copy whose counters read half the fetched and all written
+    # bytes, a 1 GiB copy (not a calibration), and CG launches: two updating,
+    # one that exits early
+    names = ["__amd_rocclr_copyBuffer", "__amd_rocclr_copyBuffer",
+             "void sdc::k_cg_iter<7, false, 1, false>(...)", "void sdc::k_cg_iter<7, false, 1, false>(...)",
+             "void sdc::k_cg_iter<7, false, 1, false>(...)", "void sdc::k_post<4>(...)"]
+    fetch = [131072.0, 524288.0, 100.0, 300.0, 0.5, 7.0]
+    write = [262144.0, 1048576.0, 50.0, 150.0, 0.2, 9.0]
+    _counter_csv(tmp_path / "f.csv", zip(names, fetch))
+    _counter_csv(tmp_path / "w.csv", zip(names, write))
+    out = bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+    assert out["fetch_factor"] == pytest.approx(2.0) and out["write_factor"] == pytest.approx(1.0)
+    assert out["dispatches"] == 3 and out["updating"] == 2
+    assert out["fetch_kib_per_launch"] == pytest.approx(200.0)
+    assert out["write_kib_per_launch"] == pytest.approx(100.0)
+    assert out["measured_bytes_per_launch"] == pytest.approx((2.0 * 200.0 + 100.0) * 1024.0)
+
+
+def test_summarize_counters_rejects_mismatched_runs(tmp_path):
+    _counter_csv(tmp_path / "f.csv", [("a", 1.0), ("b", 2.0)])
+    _counter_csv(tmp_path / "w.csv", [("a", 1.0)])
+    with pytest.raises(AssertionError):
+        bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+
+
+def test_summarize_trace_bins_cg_launches_by_grid(tmp_path):
+    path = tmp_path / "kt.csv"
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Workgroup_Size_X"]
+    rows = [("void sdc::k_cg_iter<7, false, 1, false>(...)", 0, 5000, 200 * 256, 256),
+            ("void sdc::k_cg_iter<7, false, 1, false>(...)", 0, 7000, 200 * 256, 256),
+            ("void sdc::k_cg_iter<7, false, 0, false>(...)", 0, 11000, 1024 * 256, 256),
+            ("void sdc::k_rhs<4, 7, false>(...)", 0, 6000, 1024 * 256, 256)]
+    with open(path, "w", newline="") as f:
+        wr = csv.DictWriter(f, fieldnames=fields)
+        wr.writeheader()
+        for r in rows:
+            wr.writerow(dict(zip(fields, r)))
+    text = bench.summarize_trace(str(path))
+    assert "| k_cg_iter | 3 | 0.02 | 7.667 |" in text
+    assert "| k_rhs | 1 | 0.01 | 6.000 |" in text
+    assert "| 128..255 | 2 | 6.00 | 6.00 |" in text
+    assert "| 1024..1024 | 1 | 11.00 | 11.00 |" in text
+
+
+def test_measured_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_bytes(b"kernel source")
+    sha = hashlib.sha256(b"kernel source").hexdigest()
+    md = tmp_path / "c.md"
+    md.write_text(f"# x\n\n- kernels.hip sha256: {sha}\n- measured bytes per launch: 90.5\n"
+                  f"- algorithmic bytes per launch: 100.0\n")
+    monkeypatch.setattr(bench, "COUNTERS", str(md))
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
+    assert bench.measured_traffic() == (90.5, 100.0)
+    src.write_bytes(b"kernel source, edited")
+    assert bench.measured_traffic() is None
+
+
+def test_committed_counters_name_the_current_kernel_source():
+    """The profile summary bench.py reads carries the hash of kernels.hip as
+    committed; a kernel edit without new counters makes `traffic` null."""
+    text = open(bench.COUNTERS).read()
+    assert "kernels.hip sha256:" in text and "measured bytes per launch:" in text
