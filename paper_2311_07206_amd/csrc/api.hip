@@ -101,8 +101,8 @@ int account_timing(sdc_ctx* ctx, const MapBuf& mb, int it0, int budget, const in
   return account_timing_at(ctx, mb, 0, budget, iters, it0);
 }
 
-// Restricted Jacobi-PCG on H_m over the current map, starting from the state
-// prepared by an init kernel (r = b, x = 0, scalars).  Iterations are
+// Restricted Jacobi-PCG on H_m over the current map, starting from b in
+// r[0] and x = 0 (prepared by the right-hand-side kernel).  Iterations are
 // launched in budgets; after each budget the host reads the per-instance
 // done flags.  Kernels of converged instances return immediately.
 int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std::vector<int>* iters) {
@@ -118,7 +118,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   int left = vbudget;
   int it = 0;
   iters->assign(ni, 0);
-  launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+  launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0], ctx->cg());
   HIPC(hipGetLastError());
   if (mb.nblk > 0) {
     for (;;) {
@@ -126,9 +126,10 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
       const int it0 = it;
       const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * budget;
       for (int b = 0; b < budget; ++b, ++it) {
+        // the start wrote the vectors to buffer 1 and the partials to buffer 0
         const int a = it & 1, o = a ^ 1;
-        launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
-                       ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
+        launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
+                       ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
                        ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
                        timed ? ctx->ev[2 * b] : nullptr,
                        timed ? ctx->ev[2 * b + 1] : nullptr);
@@ -204,12 +205,12 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
   const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
   const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
   const int budget = std::min(std::max(1, ctx->pred[pred_slot]) + 1, ctx->prm.cg_maxit + 1);
-  launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+  launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0], ctx->cg());
   const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * (*ev_off + budget);
   for (int it = 0; mb.nblk > 0 && it < budget; ++it) {
     const int a = it & 1, o = a ^ 1;
-    launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[a], ctx->wv[a], ctx->s[a], ctx->r[o],
-                   ctx->wv[o], ctx->s[o], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
+    launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
+                   ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
                    rtol2, ctx->prm.cg_maxit, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
                    timed ? ctx->ev[2 * (*ev_off + it)] : nullptr,
                    timed ? ctx->ev[2 * (*ev_off + it) + 1] : nullptr);
@@ -452,10 +453,12 @@ int autotune(sdc_ctx* ctx) {
   for (int round = 0; round < 4; ++round)
     for (int f = 0; f < 2; ++f) {
       const Mat H = ctx->matH(0, f == 1);
-      launch_cg_start(ctx->stream, map, ctx->n_inst, ctx->N, H, ctx->dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+      launch_cg_start(ctx->stream, map, ctx->n_inst, ctx->N, H, ctx->dinv, ctx->r[0], ctx->r[1], ctx->wv[1],
+                      ctx->part[0], ctx->cg());
       HIPC(hipEventRecord(e0, ctx->stream));
       for (int rep = 0; rep < reps; ++rep)
-        launch_cg_start(ctx->stream, map, ctx->n_inst, ctx->N, H, ctx->dinv, ctx->r[0], ctx->wv[0], ctx->part[0], ctx->cg());
+        launch_cg_start(ctx->stream, map, ctx->n_inst, ctx->N, H, ctx->dinv, ctx->r[0], ctx->r[1], ctx->wv[1],
+                        ctx->part[0], ctx->cg());
       HIPC(hipEventRecord(e1, ctx->stream));
       HIPC(hipEventSynchronize(e1));
       float ms = 0.f;

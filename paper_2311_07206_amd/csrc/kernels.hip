@@ -43,7 +43,8 @@ __device__ inline void block_sum(double (&v)[NV], double* sh /* [4 * NV] */) {
   }
 }
 
-// Visit the stored entries (value, column) of row i of matrix A.  Storage S:
+// Visit the stored entries (value, column, is the row's diagonal) of row i
+// of matrix A; f may ignore the third argument.  Storage S:
 // 0 = CSR, -1 = diagonal storage with A.nd diagonals, S > 0 = diagonal
 // storage with S diagonals known at compile time (fully unrolled, so all
 // loads of the row are in flight together).  The diagonal offsets and the
@@ -52,7 +53,10 @@ template <int S, class F>
 __device__ __forceinline__ void for_entries(const Mat& A, int64_t N, const Row& rw, int i, F&& f) {
   if constexpr (S == 0) {
     const int e1 = A.rowptr[i + 1];
-    for (int e = A.rowptr[i]; e < e1; ++e) f(A.val[e], A.col[e]);
+    for (int e = A.rowptr[i]; e < e1; ++e) {
+      const int c = A.col[e];
+      f(A.val[e], c, c == i);
+    }
   } else {
     constexpr int kUnroll = S > 0 ? S : 1;
     const int nd = S > 0 ? S : A.nd;
@@ -66,7 +70,7 @@ __device__ __forceinline__ void for_entries(const Mat& A, int64_t N, const Row& 
         a = in ? A.dval[(nd - 1 - d - h) * N + c] : 0.0;
       else
         a = A.dval[(d - h) * N + i];
-      f(a, in ? c : i);
+      f(a, in ? c : i, d == h);   // offset 0 sits at index h of the symmetric offset list
     }
   }
 }
@@ -162,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
   double Av[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) Av[j] = 0.0;
-  for_entries<S>(A, N, rw, i, [&](double a, int k) {
+  for_entries<S>(A, N, rw, i, [&](double a, int k, bool) {
 #pragma unroll
     for (int j = 0; j < M; ++j) Av[j] += a * v[j * N + k];
   });
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A
   const int i = rw.row;
   double ay = 0.0;
   if (m > 0) {
-    for_entries<S>(A, N, rw, i, [&](double a, int k) {
+    for_entries<S>(A, N, rw, i, [&](double a, int k, bool) {
       double y = 0.0;
 #pragma unroll
       for (int j = 0; j < M - 1; ++j)
@@ -254,9 +258,13 @@ __global__ __launch_bounds__(kBlock) void k_copy_b(Map map, const double* __rest
 //   u = dinv r,  w = H u,  gamma = r.u,  delta = w.u,  rr = r.r,
 // with beta = gamma / gamma_old and alpha = gamma / (delta - beta gamma / alpha_old):
 // the iterates of standard PCG in exact arithmetic, with one global
-// reduction per iteration.  The SpMV forms u of every column on the fly from
-// the previous r, w, s (double-buffered; zero on inactive rows, which is the
-// restricted solve's Dirichlet condition).
+// reduction per iteration.  The vectors are kept scaled by the
+// preconditioner, u = dinv r, w~ = dinv w, s~ = dinv s (double-buffered;
+// zero on inactive rows, which is the restricted solve's Dirichlet
+// condition), so the new H u = H dinv r - alpha H dinv (w + beta s) is a
+// sum over the row's entries of h times u, w~ and s~ of the column: four
+// loads per entry, no gather of dinv.  The row's own residual is
+// r = H_ii u.
 //
 // Reductions without fences: every block writes its partial sums; each block
 // of the next launch sums the partials of its instance in block order (so
@@ -280,13 +288,14 @@ __device__ inline void write_partials(double (&v)[NV], int blk, double* part, do
   }
 }
 
-// Start: u0 = dinv r0, w0 = H u0; partials of gamma0 = r0.u0, delta0 = w0.u0, bb = r0.r0.
+// Start from r0 = b: u0 = dinv r0 and w~0 = dinv H u0 (written for the first
+// iteration); partials of gamma0 = r0.u0, delta0 = w0.u0, bb = r0.r0.
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_t N, Mat H,
                                                      const double* __restrict__ dinv,
                                                      const double* __restrict__ r0,
-                                                     double* __restrict__ w0, double* part_out,
-                                                     CgState cg) {
+                                                     double* __restrict__ u0, double* __restrict__ w0,
+                                                     double* part_out, CgState cg) {
   __shared__ double sh[16];
   if (blockIdx.x == 0) {
     for (int t = threadIdx.x; t < n_inst; t += kBlock) {
@@ -301,9 +310,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_
   if (rw.valid) {
     const int i = rw.row;
     double acc = 0.0;
-    for_entries<S>(H, N, rw, i, [&](double h, int k) { acc += h * (dinv[k] * r0[k]); });
-    const double ri = r0[i], ui = dinv[i] * ri;
-    w0[i] = acc;
+    for_entries<S>(H, N, rw, i, [&](double h, int k, bool) { acc += h * (dinv[k] * r0[k]); });
+    const double di = dinv[i], ri = r0[i], ui = di * ri;
+    u0[i] = ui;
+    w0[i] = di * acc;
     s[0] = ri * ui;
     s[1] = acc * ui;
     s[2] = ri * ri;
@@ -373,10 +383,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
                                                     const double* __restrict__ scal_in, int64_t N, Mat H,
                                                     const double* __restrict__ dinv,
                                                     double* __restrict__ x, double* __restrict__ p,
-                                                    const double* __restrict__ r_in,
+                                                    const double* __restrict__ u_in,
                                                     const double* __restrict__ w_in,
                                                     const double* __restrict__ s_in,
-                                                    double* __restrict__ r_out,
+                                                    double* __restrict__ u_out,
                                                     double* __restrict__ w_out,
                                                     double* __restrict__ s_out,
                                                     double* __restrict__ part_out,
@@ -397,16 +407,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   const int i = rw.row;
   // second round trip, issued together: the row's values and neighbour sums,
   // the instance's scalars and partial sums from the previous launch
-  double a_r = 0.0, a_w = 0.0, a_s = 0.0;
-  for_entries<S>(H, N, rw, i, [&](double h, int k) {
-    const double hd = h * dinv[k];
-    a_r += hd * r_in[k];
-    a_w += hd * w_in[k];
-    if (!FIRST) a_s += hd * s_in[k];
+  double a_r = 0.0, a_w = 0.0, a_s = 0.0, hii = 0.0;
+  for_entries<S>(H, N, rw, i, [&](double h, int k, bool diag) {
+    a_r += h * u_in[k];
+    a_w += h * w_in[k];
+    if (!FIRST) a_s += h * s_in[k];
+    if (diag) hii = h;
   });
   const double si = FIRST ? 0.0 : s_in[i];
   const double p_old = FIRST ? 0.0 : p[i];
-  const double di = dinv[i], ri = r_in[i], wi = w_in[i], x_old = x[i];
+  const double di = dinv[i], ui = u_in[i], wi = w_in[i], x_old = x[i];
   double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
   if (!FIRST) {
     const double* sc = scal_in + inst * kScal;
@@ -465,17 +475,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   }
   double s[3] = {0.0, 0.0, 0.0};
   if (valid) {
-    const double w_new = a_r - alpha * (a_w + beta * a_s);
-    const double ui = di * ri;
+    const double w_new = a_r - alpha * (a_w + beta * a_s);   // H u of the new residual
     const double pi = ui + beta * p_old;
-    const double sv = wi + beta * si;
+    const double sv = wi + beta * si;                         // dinv (w + beta s)
     x[i] = x_old + alpha * pi;
     p[i] = pi;
     s_out[i] = sv;
-    const double rn = ri - alpha * sv;
-    r_out[i] = rn;
-    w_out[i] = w_new;
-    const double un = di * rn;
+    const double un = ui - alpha * sv;                        // dinv (r - alpha s)
+    u_out[i] = un;
+    w_out[i] = di * w_new;
+    const double rn = hii * un;
     s[0] = rn * un;
     s[1] = w_new * un;
     s[2] = rn * rn;
@@ -782,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Map map, int64_t N, Mat H, co
   if (rw.valid) {
     const int i = rw.row;
     double hx = 0.0;
-    for_entries<S>(H, N, rw, i, [&](double h, int k) { hx += h * x[k]; });
+    for_entries<S>(H, N, rw, i, [&](double h, int k, bool) { hx += h * x[k]; });
     e[0] = x[i] * hx;
   }
   block_sum<1>(e, sh);
@@ -898,18 +907,18 @@ void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, do
 }
 
 void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const Mat& H,
-                     const double* dinv, const double* r0, double* w0, double* part_out,
+                     const double* dinv, const double* r0, double* u0, double* w0, double* part_out,
                      const CgState& cg) {
   const size_t lds = cap_lds(map);
   dispatch_storage(H.nd, [&](auto st) {
-    k_cg_start<decltype(st)::value><<<grid(map.nblk), kBlock, lds, s>>>(map, n_inst, N, H, dinv, r0, w0, part_out,
-                                                                        cg);
+    k_cg_start<decltype(st)::value><<<grid(map.nblk), kBlock, lds, s>>>(map, n_inst, N, H, dinv, r0, u0, w0,
+                                                                        part_out, cg);
   });
 }
 
 void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
-                    double* x, double* p, const double* r_in, const double* w_in, const double* s_in,
-                    double* r_out, double* w_out, double* s_out, int it, const double* part_in,
+                    double* x, double* p, const double* u_in, const double* w_in, const double* s_in,
+                    double* u_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
                     int maxit, const CgState& cg, double* tot, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (map.nblk <= 0) return;
@@ -923,11 +932,11 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
     if (ev_start) {
       // events stamped by the dispatch itself: they time the kernel's execution
       hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(kBlock), 0, s, ev_start, ev_stop, 0, cg.blk_done, map.rec,
-                            map.idx, map.nblk, it, pin, scal_in, N, H, dinv, x, p, r_in, w_in, s_in, r_out,
+                            map.idx, map.nblk, it, pin, scal_in, N, H, dinv, x, p, u_in, w_in, s_in, u_out,
                             w_out, s_out, part_out, scal_out, rtol2, maxit, cg.done, cg.iters);
     } else {
       kern<<<grid(map.nblk), kBlock, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, it, pin, scal_in, N, H, dinv,
-                                             x, p, r_in, w_in, s_in, r_out, w_out, s_out, part_out, scal_out, rtol2,
+                                             x, p, u_in, w_in, s_in, u_out, w_out, s_out, part_out, scal_out, rtol2,
                                              maxit, cg.done, cg.iters);
     }
   };

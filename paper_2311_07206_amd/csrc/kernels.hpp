@@ -113,12 +113,16 @@ void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, do
 // partials itself unless `tot` is given ([n_inst][4] scratch): then a
 // one-block-per-instance pass forms the totals first (for instances of more
 // than kTotBlocks blocks, where the per-block sums would dominate).
+// CG start from r0 = b: writes u0 = dinv b and dinv H u0 (the first
+// iteration's u_in and w_in) and the partial sums.
 void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const Mat& H,
-                     const double* dinv, const double* r0, double* w0, double* part_out,
+                     const double* dinv, const double* r0, double* u0, double* w0, double* part_out,
                      const CgState& cg);
+// One CG launch; u, w, s are the preconditioner-scaled vectors dinv r,
+// dinv H u and dinv H p (read from one buffer, written to the other).
 void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
-                    double* x, double* p, const double* r_in, const double* w_in, const double* s_in,
-                    double* r_out, double* w_out, double* s_out, int it, const double* part_in,
+                    double* x, double* p, const double* u_in, const double* w_in, const double* s_in,
+                    double* u_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
                     int maxit, const CgState& cg, double* tot, hipEvent_t ev_start = nullptr,
                     hipEvent_t ev_stop = nullptr);
