@@ -62,6 +62,26 @@ class Monodomain:
         return ionic.current(v, w, p), ionic.rate(v, w, p)
 
 
+def sweeps_needed(c, rho, tol, cap=10000):
+    """Smallest integer r >= 0 with c rho^r <= (1 - rho) tol: the iteration
+    count of Thm. 2 (eq. r-condition, r >= log((1-rho) TOL / c) / log rho),
+    found by repeated multiplication so that the integer is decided by the
+    same floating-point products wherever it is computed."""
+    bound = (1.0 - rho) * tol
+    r, q = 0, float(c)
+    while q > bound and r < cap:
+        q *= rho
+        r += 1
+    return r
+
+
+def apriori_drop_tolerance(c, eta, dt, rho, tol):
+    """Eq. drop-tolerance: TOL_drop = exp(-eta T) (1 - rho) / (r + 1) TOL over
+    a step of length T = dt, with r from Thm. 2 for the correction size c."""
+    r = sweeps_needed(c, rho, tol)
+    return np.exp(-eta * dt) * (1.0 - rho) / (r + 1) * tol, r
+
+
 class SDC:
     """IMEX SDC on Radau-IIA nodes with nested active index sets.
 
@@ -75,10 +95,20 @@ class SDC:
     in the sweep itself).  A stopped instance's rows leave the active set;
     the step ends when every instance has stopped or after K sweeps.
     ``inst_of`` maps rows to instances (default: one instance).
+
+    A-priori drop tolerance (``drop="apriori"``, Sec. 4.1): instead of the
+    fixed theta, each instance's sets after the first sweep use
+    TOL_drop = exp(-eta dt) (1 - rho) / (r + 1) tol_sdc (eq.
+    drop-tolerance), with the error constant c estimated from the first
+    sweep as the instance's largest correction max |dv| (rho taken as
+    known, as the paper suggests), r from Thm. 2, and
+    eta = max(0, -min dI/dv) / (beta C_m) (Thm. 1, beta C_m = 1) over the
+    instance's rows at the step's start state and at the collocation
+    values after the first sweep.
     """
 
     def __init__(self, model, M, dt, theta, cg_rtol=1e-12, cg_maxit=1000, tol_sdc=0.0, rho=0.05, K_min=1,
-                 inst_of=None):
+                 inst_of=None, drop="theta"):
         self.model = model
         self.col = Collocation(M)
         self.M = M
@@ -89,6 +119,11 @@ class SDC:
         self.tol_sdc = float(tol_sdc)
         self.rho = float(rho)
         self.K_min = int(K_min)
+        if drop not in ("theta", "apriori"):
+            raise ValueError("drop must be 'theta' or 'apriori'")
+        if drop == "apriori" and not (self.tol_sdc > 0.0 and 0.0 < self.rho < 1.0):
+            raise ValueError("the a-priori drop tolerance needs tol_sdc > 0 and 0 < rho < 1")
+        self.drop = drop
         self.inst_of = np.zeros(model.N, dtype=np.int64) if inst_of is None else np.asarray(inst_of, dtype=np.int64)
         self.n_inst = int(self.inst_of.max()) + 1 if self.inst_of.size else 1
         ML, A = model.ML, model.A
@@ -114,8 +149,24 @@ class SDC:
         st["R"] = np.tile(R0, (M, 1))
         return st
 
-    def sweep(self, st, idx, cg_iters=None):
-        """One sweep on rows idx (ascending int array); returns (next idx, info)."""
+    def drop_tolerances(self, st, amax, idx):
+        """Per instance (TOL_drop, r, c, eta) after the first sweep on idx."""
+        n = self.n_inst
+        c = np.zeros(n)
+        np.maximum.at(c, self.inst_of[idx], amax[idx])
+        p = self.model.p[:, idx]
+        dmin = np.full(n, np.inf)
+        states = [(st["v0"][idx], st["w0"][idx])] + [(st["v"][m, idx], st["w"][m, idx]) for m in range(self.M)]
+        for v, w in states:
+            np.minimum.at(dmin, self.inst_of[idx], ionic.current_partials(v, w, p)[0])
+        eta = np.maximum(0.0, -dmin)
+        eta[~np.isfinite(eta)] = 0.0   # an instance without rows
+        out = [apriori_drop_tolerance(c[i], eta[i], self.dt, self.rho, self.tol_sdc) for i in range(n)]
+        return np.array([o[0] for o in out]), np.array([o[1] for o in out]), c, eta
+
+    def sweep(self, st, idx, cg_iters=None, theta=None):
+        """One sweep on rows idx (ascending int array); returns (next idx, info).
+        theta: the drop tolerance (default self.theta), or one per instance."""
         M, dt = self.M, self.dt
         Q, QI, QE = self.col.Q, self.col.QI, self.col.QE
         ML, A = self.model.ML, self.model.A
@@ -161,7 +212,10 @@ class SDC:
             I[m, idx] = In
             R[m, idx] = Rn
             amax[idx] = np.maximum(amax[idx], np.abs(x[idx]))
-        nxt = select(idx, amax, self.theta)
+        if theta is None or np.ndim(theta) == 0:
+            nxt = select(idx, amax, self.theta if theta is None else float(theta))
+        else:
+            nxt = idx[amax[idx] >= np.asarray(theta)[self.inst_of[idx]]]
         return nxt, {"idx": idx, "n_active": int(idx.size), "cg_iters": iters, "amax": amax, "dv": dv}
 
     def step(self, v0, w0, K, idx_replay=None, cg_replay=None, keep=False):
@@ -175,10 +229,15 @@ class SDC:
         idx = np.arange(self.model.N)
         infos = []
         stopped = np.zeros(self.n_inst, dtype=bool)
+        theta = None
         for k in range(K):
             if idx_replay is not None and idx_replay[k] is not None:
                 idx = np.asarray(idx_replay[k], dtype=np.int64)
-            nxt, info = self.sweep(st, idx, None if cg_replay is None else cg_replay[k])
+            nxt, info = self.sweep(st, idx, None if cg_replay is None else cg_replay[k], theta)
+            if self.drop == "apriori" and k == 0:
+                theta, r, c, eta = self.drop_tolerances(st, info["amax"], idx)
+                info.update(drop_tol=theta, drop_r=r, drop_c=c, drop_eta=eta)
+                nxt = idx[info["amax"][idx] >= theta[self.inst_of[idx]]]
             if self.tol_sdc > 0.0:
                 e = self.energy(info["dv"])
                 info["energy"] = e
@@ -225,7 +284,7 @@ def run(sdc, v, w, n_steps, K, stimuli=(), t0=0.0, idx_replay=None, cg_replay=No
     return v, w, log
 
 
-def build(problem, tol_sdc=0.0, rho=0.05, K_min=1):
+def build(problem, tol_sdc=0.0, rho=0.05, K_min=1, drop="theta"):
     """Assemble the oracle model and SDC integrator for a workload Problem."""
     from .assembly import lumped_mass, stiffness
     ML = lumped_mass(problem.coords, problem.elems, problem.N)
@@ -233,4 +292,4 @@ def build(problem, tol_sdc=0.0, rho=0.05, K_min=1):
     model = Monodomain(ML, A, problem.node_ionic())
     inst_of = np.repeat(np.arange(problem.n_inst), np.diff(problem.node_off))
     return SDC(model, problem.M, problem.dt, problem.theta, problem.cg_rtol, problem.cg_maxit,
-               tol_sdc=tol_sdc, rho=rho, K_min=K_min, inst_of=inst_of)
+               tol_sdc=tol_sdc, rho=rho, K_min=K_min, inst_of=inst_of, drop=drop)
