@@ -79,6 +79,16 @@ typedef struct {
   int32_t K_min;      /* 1..K (values <= 0 mean 1)                             */
   double tol_sdc;     /* TOL_SDC                                               */
   double rho;         /* assumed contraction factor, 0 < rho < 1               */
+  /* Drop tolerance of the active sets.  0: theta above.  1: a-priori per     */
+  /* instance and step (paper Sec. 4.1, eqs. subset and drop-tolerance):      */
+  /*   TOL_drop = exp(-eta dt) (1 - rho) / (r + 1) tol_sdc,                   */
+  /* from the step's first sweep: c = the instance's max_m |dv_m| (the error  */
+  /* constant of Thm. 2, rho taken as known), r = the least r >= 0 with      */
+  /* c rho^r <= (1 - rho) tol_sdc, eta = max(0, -min dI/dv) over its rows at  */
+  /* the step's start state and the collocation values (Thm. 1, beta C_m =   */
+  /* 1).  Needs tol_sdc > 0 (which also switches the energy-norm termination */
+  /* on) and the monodomain model; else SDC_ERR_ARG.                          */
+  int32_t drop_mode;
 } sdc_params;
 
 /* Per-sweep statistics (sums over instances unless stated). */
@@ -228,6 +238,12 @@ int sdc_adjoint_step(sdc_ctx* ctx, const double* v_n, const double* w_n, double 
 int sdc_adjoint_record(sdc_ctx* ctx, int32_t slot, double* v, double* w, double t);
 int sdc_adjoint_reverse(sdc_ctx* ctx, int32_t slot, double* lam_v, double* lam_w, double* g_sigma,
                         double* g_a);
+
+/* The a-priori drop tolerance of the current step (drop_mode 1, after the
+ * step's first sweep; zeros before any), per instance, written to host
+ * out[4 * n_inst]: (TOL_drop, r, c, eta) as defined at sdc_params.drop_mode.
+ * SDC_ERR_STATE when drop_mode is 0.  Synchronises the stream. */
+int sdc_get_drop_tolerance(sdc_ctx* ctx, double* out);
 
 /* Replace the nodal conductivity multipliers (host double[N], or NULL to keep)
  * and the Aliev-Panfilov parameters (host double[n_inst][6], or NULL): A is

@@ -24,7 +24,7 @@ ERRORS = {
 class Params(ctypes.Structure):
     _fields_ = [("M", c_int32), ("K", c_int32), ("dt", c_double), ("theta", c_double),
                 ("cg_rtol", c_double), ("cg_maxit", c_int32), ("format", c_int32),
-                ("K_min", c_int32), ("tol_sdc", c_double), ("rho", c_double)]
+                ("K_min", c_int32), ("tol_sdc", c_double), ("rho", c_double), ("drop_mode", c_int32)]
 
 
 class SweepStats(ctypes.Structure):
@@ -88,6 +88,7 @@ SIGNATURES = {
     "sdc_collocation": (c_int32, [c_int32, PTR, PTR, PTR, PTR]),
     "sdc_profile": (c_int32, [c_void_p, c_int32]),
     "sdc_get_info": (c_int32, [c_void_p, POINTER(Info)]),
+    "sdc_get_drop_tolerance": (c_int32, [c_void_p, PTR]),
     "sdc_adjoint_step": (c_int32, [c_void_p, PTR, PTR, c_double, PTR, PTR, PTR, PTR]),
     "sdc_set_coefficients": (c_int32, [c_void_p, PTR, PTR]),
     "sdc_adjoint_record": (c_int32, [c_void_p, c_int32, PTR, PTR, c_double]),

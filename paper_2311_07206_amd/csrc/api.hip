@@ -271,6 +271,13 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     if (ctx->terminate()) launch_energy(ctx->stream, map, N, ctx->H(m), x, ctx->e_part + m * ctx->all.nblk);
     HIPC(hipGetLastError());
   }
+  if (ctx->apriori_drop() && ctx->k == 0) {
+    // a-priori drop tolerance of each instance for the rest of the step, from this first sweep
+    launch_drop_tolerance(ctx->stream, map, M, N, ctx->ionic_d, ctx->amax, ctx->v0, ctx->w0, ctx->v, ctx->w,
+                          ctx->drop_part, ctx->prm.dt, ctx->prm.rho, ctx->prm.tol_sdc, ctx->drop_theta,
+                          ctx->drop_info);
+    HIPC(hipGetLastError());
+  }
   if (ctx->terminate()) {
     // energy-norm termination: per-instance energy and stop decision on the device
     const double q = (1.0 - ctx->prm.rho) / ctx->prm.rho * ctx->prm.tol_sdc;
@@ -298,12 +305,12 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     TRY(map_list(ctx, slot, ctx->pin[next], ctx->pin_n[next]));
     ctx->cur = slot;
     synced = true;
-  } else if ((ctx->prm.theta > 0.0 || ctx->terminate()) && select_next) {
+  } else if ((ctx->prm.theta > 0.0 || ctx->terminate() || ctx->apriori_drop()) && select_next) {
     const int slot = ctx->cur == 0 ? 1 : 0;
     MapBuf& nm = ctx->dyn[slot];
-    launch_select(ctx->stream, map, ni, ctx->rowptr, ctx->amax, ctx->prm.theta, ctx->sel_cnt,
-                  ctx->sel_nnz, ctx->list[slot], nullptr, ctx->next(nm), ctx->zv(),
-                  ctx->terminate() ? ctx->inst_stop : nullptr);
+    launch_select(ctx->stream, map, ni, ctx->rowptr, ctx->amax, ctx->prm.theta,
+                  ctx->apriori_drop() ? ctx->drop_theta : nullptr, ctx->sel_cnt, ctx->sel_nnz, ctx->list[slot],
+                  nullptr, ctx->next(nm), ctx->zv(), ctx->terminate() ? ctx->inst_stop : nullptr);
     HIPC(hipGetLastError());
     TRY(fetch_map(ctx, &nm));
     nm.idx = ctx->list[slot];
@@ -627,6 +634,11 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     return fail(ctx, SDC_ERR_ARG, "dt, cg_rtol must be > 0, cg_maxit >= 1, format in 0..2");
   if (prm->tol_sdc > 0.0 && !(prm->rho > 0.0 && prm->rho < 1.0))
     return fail(ctx, SDC_ERR_ARG, "energy-norm termination needs 0 < rho < 1");
+  if (prm->drop_mode < 0 || prm->drop_mode > 1) return fail(ctx, SDC_ERR_ARG, "drop_mode must be 0 or 1");
+  if (prm->drop_mode == 1 && !(prm->tol_sdc > 0.0))
+    return fail(ctx, SDC_ERR_ARG, "the a-priori drop tolerance needs tol_sdc > 0 (and 0 < rho < 1)");
+  if (prm->drop_mode == 1 && emi)
+    return fail(ctx, SDC_ERR_ARG, "the a-priori drop tolerance is defined for the monodomain model only");
   if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
   if (node_off[0] != 0 || elem_off[0] != 0) return fail(ctx, SDC_ERR_ARG, "offsets must start at 0");
   for (int i = 0; i < n_inst; ++i)
@@ -774,6 +786,11 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     TRY(dalloc(ctx, &ctx->inst_energy, n_inst));
     TRY(dalloc(ctx, &ctx->inst_stop, n_inst));
     HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_term), 2 * n_inst * sizeof(double)));
+  }
+  if (prm->drop_mode == 1) {
+    TRY(dalloc(ctx, &ctx->drop_part, 2 * static_cast<size_t>(nblk_all)));
+    TRY(dalloc(ctx, &ctx->drop_theta, n_inst));
+    TRY(dalloc(ctx, &ctx->drop_info, 4 * static_cast<size_t>(n_inst)));
   }
   TRY(dalloc(ctx, &ctx->cg_iters, n_inst));
   TRY(dalloc(ctx, &ctx->cg_blk_done, nblk_all));
@@ -958,11 +975,20 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
   TRY(map_list(ctx, 0, idx_in, n_in));
   MapBuf& nm = ctx->dyn[1];
   ZeroVecs none{{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}, nullptr, 0, 0};
-  launch_select(ctx->stream, ctx->dyn[0].dev(), ctx->n_inst, ctx->rowptr, amax, theta, ctx->sel_cnt,
+  launch_select(ctx->stream, ctx->dyn[0].dev(), ctx->n_inst, ctx->rowptr, amax, theta, nullptr, ctx->sel_cnt,
                 ctx->sel_nnz, ctx->list[1], idx_out, ctx->next(nm), none, nullptr);
   HIPC(hipGetLastError());
   TRY(fetch_map(ctx, &nm));
   *n_out = nm.rows;
+  return SDC_OK;
+}
+
+int sdc_get_drop_tolerance(sdc_ctx* ctx, double* out) {
+  TRY(check_ready(ctx));
+  if (!out) return fail(ctx, SDC_ERR_ARG, "null argument");
+  if (!ctx->apriori_drop()) return fail(ctx, SDC_ERR_STATE, "the a-priori drop tolerance is not enabled");
+  HIPC(hipMemcpyAsync(out, ctx->drop_info, 4 * ctx->n_inst * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));
   return SDC_OK;
 }
 

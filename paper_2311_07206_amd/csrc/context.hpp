@@ -162,6 +162,11 @@ struct sdc_ctx {
   double* h_term = nullptr;        // pinned: energies [n_inst], then stop flags (int32)
   bool all_stopped = false;
   bool terminate() const { return prm.tol_sdc > 0.0; }
+  // a-priori drop tolerance (drop_mode 1): per instance, from each step's first sweep
+  double* drop_part = nullptr;     // [nblk of all][2] per-block max |dv| and min dI/dv
+  double* drop_theta = nullptr;    // [n_inst] TOL_drop of the current step
+  double* drop_info = nullptr;     // [n_inst][4] TOL_drop, r, c, eta
+  bool apriori_drop() const { return prm.drop_mode == 1; }
   int k_min() const { return std::max(1, std::min(prm.K_min, prm.K)); }
 
   // kernel timing (bench only)

@@ -563,13 +563,16 @@ __global__ __launch_bounds__(kBlock) void k_post_sites(Map map, int m, int64_t N
 __device__ inline bool keep_row(double a, double theta) { return theta <= 0.0 || a >= theta; }
 
 // Pass 1: kept rows and their stored entries per block.
+// theta: one drop tolerance, or (inst_theta not null) one per instance.
 __global__ __launch_bounds__(kBlock) void k_select_count(Map map, const int32_t* __restrict__ rowptr,
                                                          const double* __restrict__ amax,
-                                                         double theta, int32_t* sel_cnt,
-                                                         int32_t* sel_nnz, const int32_t* __restrict__ stop) {
+                                                         double theta, const double* __restrict__ inst_theta,
+                                                         int32_t* sel_cnt, int32_t* sel_nnz,
+                                                         const int32_t* __restrict__ stop) {
   __shared__ int sc[4], sn[4];
   const Row rw = map_row(map);
-  const bool keep = rw.valid && !(stop && stop[rw.inst]) && keep_row(amax[rw.row], theta);
+  const double th = inst_theta ? inst_theta[rw.inst] : theta;
+  const bool keep = rw.valid && !(stop && stop[rw.inst]) && keep_row(amax[rw.row], th);
   const unsigned long long mask = __ballot(keep);
   int nz = keep ? rowptr[rw.row + 1] - rowptr[rw.row] : 0;
 #pragma unroll
@@ -687,14 +690,15 @@ __global__ __launch_bounds__(kScanThreads) void k_select_scan(Map map, int n_ins
 // A kept row's list position q (over all instances) becomes position
 // inst_blk0 * kBlock + (q - aoff) of its instance in the padded list.
 __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* __restrict__ amax,
-                                                         double theta,
+                                                         double theta, const double* __restrict__ inst_theta,
                                                          const int32_t* __restrict__ sel_off, NextMap nm,
                                                          int32_t* __restrict__ idx_pad,
                                                          int32_t* __restrict__ idx_compact, ZeroVecs zv,
                                                          const int32_t* __restrict__ stop) {
   __shared__ int wc[4];
   const Row rw = map_row(map);
-  const bool keep = rw.valid && !(stop && stop[rw.inst]) && keep_row(amax[rw.row], theta);
+  const double th = inst_theta ? inst_theta[rw.inst] : theta;
+  const bool keep = rw.valid && !(stop && stop[rw.inst]) && keep_row(amax[rw.row], th);
   const unsigned long long mask = __ballot(keep);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) wc[wid] = __popcll(mask);
@@ -813,6 +817,95 @@ __global__ __launch_bounds__(kBlock) void k_energy_stop(const int32_t* __restric
   if (threadIdx.x == 0) {
     energy[inst] = acc[0];
     if (allow && acc[0] <= thr) stop[inst] = 1;
+  }
+}
+
+// ---- a-priori drop tolerance (Sec. 4.1, eq. drop-tolerance) after the first sweep
+
+// dI/dv of the Aliev-Panfilov current: k ((v-a)(v-1) + v(v-1) + v(v-a)) + w.
+__device__ inline double ap_didv(double v, double w, const double* p) {
+  const double k = p[0], a = p[1];
+  return k * ((v - a) * (v - 1.0) + v * (v - 1.0) + v * (v - a)) + w;
+}
+
+// Per block: the largest correction max_m |dv_m| (amax) of its rows, and the
+// smallest dI/dv at the step's start state and at the collocation values.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_drop_part(Map map, int64_t N, const double* __restrict__ ionic,
+                                                      const double* __restrict__ amax,
+                                                      const double* __restrict__ v0,
+                                                      const double* __restrict__ w0,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ w,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[8];
+  const Row rw = map_row(map);
+  double c = 0.0, d = INFINITY;
+  if (rw.valid) {
+    const int i = rw.row;
+    const double* p = ionic + 6 * rw.inst;
+    c = amax[i];
+    d = ap_didv(v0[i], w0[i], p);
+#pragma unroll
+    for (int m = 0; m < M; ++m) d = fmin(d, ap_didv(v[m * N + i], w[m * N + i], p));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c = fmax(c, __shfl_xor(c, off, 64));
+    d = fmin(d, __shfl_xor(d, off, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wid] = c;
+    sh[4 + wid] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * rw.blk] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    part[2 * rw.blk + 1] = fmin(fmin(sh[4], sh[5]), fmin(sh[6], sh[7]));
+  }
+}
+
+// One block per instance: c = max |dv|, eta = max(0, -min dI/dv) (beta C_m = 1),
+// r = the least r >= 0 with c rho^r <= (1 - rho) tol (Thm. 2, by repeated
+// multiplication), TOL_drop = exp(-eta dt) (1 - rho) / (r + 1) tol.
+// out[inst] = TOL_drop; info[4 inst ..] = (TOL_drop, r, c, eta).
+__global__ __launch_bounds__(kBlock) void k_drop_tol(const int32_t* __restrict__ inst_blk0,
+                                                     const int32_t* __restrict__ inst_nblk,
+                                                     const double* __restrict__ part, double dt, double rho,
+                                                     double tol, double* __restrict__ out,
+                                                     double* __restrict__ info) {
+  __shared__ double sh[8];
+  const int inst = blockIdx.x, b0 = inst_blk0[inst], nb = inst_nblk[inst];
+  double c = 0.0, d = INFINITY;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    c = fmax(c, part[2 * (b0 + b)]);
+    d = fmin(d, part[2 * (b0 + b) + 1]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c = fmax(c, __shfl_xor(c, off, 64));
+    d = fmin(d, __shfl_xor(d, off, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wid] = c;
+    sh[4 + wid] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    d = fmin(fmin(sh[4], sh[5]), fmin(sh[6], sh[7]));
+    const double eta = d < 0.0 ? -d : 0.0;   // also 0 for an instance without rows (d = inf)
+    const double bound = (1.0 - rho) * tol;
+    int r = 0;
+    for (double q = c; q > bound && r < 10000; ++r) q *= rho;
+    const double th = exp(-eta * dt) * (1.0 - rho) / (r + 1) * tol;
+    out[inst] = th;
+    info[4 * inst] = th;
+    info[4 * inst + 1] = r;
+    info[4 * inst + 2] = c;
+    info[4 * inst + 3] = eta;
   }
 }
 
@@ -983,15 +1076,28 @@ void launch_post_sites(hipStream_t s, int M, int m, const Map& map, int64_t N, c
 }
 
 void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* rowptr,
-                   const double* amax, double theta, int32_t* sel_cnt, int32_t* sel_nnz,
-                   int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm, const ZeroVecs& zv,
-                   const int32_t* stop) {
+                   const double* amax, double theta, const double* inst_theta, int32_t* sel_cnt,
+                   int32_t* sel_nnz, int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm,
+                   const ZeroVecs& zv, const int32_t* stop) {
   if (map.nblk > 0)
-    k_select_count<<<grid(map.nblk), kBlock, 0, s>>>(map, rowptr, amax, theta, sel_cnt, sel_nnz, stop);
+    k_select_count<<<grid(map.nblk), kBlock, 0, s>>>(map, rowptr, amax, theta, inst_theta, sel_cnt, sel_nnz,
+                                                     stop);
   k_select_scan<<<1, kScanThreads, 0, s>>>(map, n_inst, sel_cnt, sel_nnz, nm);
   if (map.nblk > 0)
-    k_select_write<<<grid(map.nblk), kBlock, 0, s>>>(map, amax, theta, sel_cnt, nm, idx_pad, idx_compact, zv,
-                                                     stop);
+    k_select_write<<<grid(map.nblk), kBlock, 0, s>>>(map, amax, theta, inst_theta, sel_cnt, nm, idx_pad,
+                                                     idx_compact, zv, stop);
+}
+
+void launch_drop_tolerance(hipStream_t s, const Map& map, int M, int64_t N, const double* ionic,
+                           const double* amax, const double* v0, const double* w0, const double* v,
+                           const double* w, double* part, double dt, double rho, double tol, double* out,
+                           double* info) {
+  if (map.nblk > 0)
+    dispatch_m(M, [&](auto mm) {
+      k_drop_part<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, ionic, amax, v0, w0, v, w, part);
+    });
+  k_drop_tol<<<dim3(static_cast<unsigned>(map.n_inst)), kBlock, 0, s>>>(map.inst_blk0, map.inst_nblk, part, dt, rho,
+                                                                       tol, out, info);
 }
 
 void launch_energy(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* x, double* e_part) {

@@ -172,9 +172,16 @@ struct ZeroVecs {
 // when idx_compact is not null, also as one ascending list there.
 // Rows of instances with stop[inst] != 0 (stop may be null) are dropped too.
 void launch_select(hipStream_t s, const Map& map, int n_inst, const int32_t* rowptr,
-                   const double* amax, double theta, int32_t* sel_cnt, int32_t* sel_nnz,
-                   int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm, const ZeroVecs& zv,
-                   const int32_t* stop);
+                   const double* amax, double theta, const double* inst_theta, int32_t* sel_cnt,
+                   int32_t* sel_nnz, int32_t* idx_pad, int32_t* idx_compact, const NextMap& nm,
+                   const ZeroVecs& zv, const int32_t* stop);
+// A-priori drop tolerance per instance from the first sweep on map (Sec. 4.1):
+// out[inst] = TOL_drop, info[4 inst ..] = (TOL_drop, r, c, eta); part holds
+// 2 doubles per map block.
+void launch_drop_tolerance(hipStream_t s, const Map& map, int M, int64_t N, const double* ionic,
+                           const double* amax, const double* v0, const double* w0, const double* v,
+                           const double* w, double* part, double dt, double rho, double tol, double* out,
+                           double* info);
 // Energy-norm termination (Sec. 3.2): per block of the map, the partial sum
 // of x_i (H x)_i over its rows -> e_part[block]; then, per instance, the sum
 // over the M nodes' partials (node-major, blocks in order) -> energy[inst],

@@ -43,10 +43,14 @@ class Solver:
 
     def __init__(self, coords, elems, elem_tensor, node_sigma, ionic, node_off, elem_off,
                  M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None, emi=None,
-                 tol_sdc=0.0, rho=0.05, K_min=1):
+                 tol_sdc=0.0, rho=0.05, K_min=1, drop="theta"):
         """emi: None (monodomain) or a dict with the cell-by-cell couplings
         mem_intra, mem_extra, mem_len, cm, gap_a, gap_b, gap_len, g_gap,
-        robin_len, eps (see sdc_emi)."""
+        robin_len, eps (see sdc_emi).  drop: "theta" (fixed drop tolerance)
+        or "apriori" (per instance and step from tol_sdc and rho, see
+        sdc_params.drop_mode)."""
+        if drop not in ("theta", "apriori"):
+            raise ValueError("drop must be 'theta' or 'apriori'")
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         if stream is None:
@@ -62,7 +66,7 @@ class Solver:
         self.M, self.K = int(M), int(K)
         prm = Params(M=self.M, K=self.K, dt=float(dt), theta=float(theta), cg_rtol=float(cg_rtol),
                      cg_maxit=int(cg_maxit), format=int(fmt), K_min=int(K_min), tol_sdc=float(tol_sdc),
-                     rho=float(rho))
+                     rho=float(rho), drop_mode=1 if drop == "apriori" else 0)
         node_off_a, p_no = _host(node_off, np.int64)
         coords_a, p_c = _host(coords, np.float64)
         elem_off_a, p_eo = _host(elem_off, np.int64)
@@ -245,6 +249,15 @@ class Solver:
         st = _lib.ProfileStats()
         self._check(self.lib.sdc_profile_read(self.ctx, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def drop_tolerance(self):
+        """The current step's a-priori drop tolerance per instance: a dict of
+        arrays TOL_drop, r, c, eta (drop="apriori" only)."""
+        out = np.zeros(4 * self.n_inst)
+        self._check(self.lib.sdc_get_drop_tolerance(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
+        out = out.reshape(self.n_inst, 4)
+        return {"tol_drop": out[:, 0].copy(), "r": out[:, 1].astype(np.int64), "c": out[:, 2].copy(),
+                "eta": out[:, 3].copy()}
 
     def select(self, amax, idx, theta):
         out = torch.empty(max(idx.numel(), 1), dtype=torch.int32, device=self.device)
