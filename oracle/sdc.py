@@ -108,7 +108,7 @@ class SDC:
     """
 
     def __init__(self, model, M, dt, theta, cg_rtol=1e-12, cg_maxit=1000, tol_sdc=0.0, rho=0.05, K_min=1,
-                 inst_of=None, drop="theta"):
+                 inst_of=None, drop="theta", scheme="imex"):
         self.model = model
         self.col = Collocation(M)
         self.M = M
@@ -124,16 +124,22 @@ class SDC:
         if drop == "apriori" and not (self.tol_sdc > 0.0 and 0.0 < self.rho < 1.0):
             raise ValueError("the a-priori drop tolerance needs tol_sdc > 0 and 0 < rho < 1")
         self.drop = drop
+        if scheme not in ("imex", "linearized"):
+            raise ValueError("scheme must be 'imex' or 'linearized'")
+        self.scheme = scheme
+        self._Hk = None   # the linearized scheme's system matrices of the last sweep
         self.inst_of = np.zeros(model.N, dtype=np.int64) if inst_of is None else np.asarray(inst_of, dtype=np.int64)
         self.n_inst = int(self.inst_of.max()) + 1 if self.inst_of.size else 1
         ML, A = model.ML, model.A
         self.H = [(sp.diags(ML) + self.dt * self.col.QI[m, m] * A).tocsr() for m in range(M)]
 
     def energy(self, dv):
-        """Per instance: sum_m dv_m^T H_m dv_m."""
+        """Per instance: sum_m dv_m^T H_m dv_m (the last sweep's matrices in
+        the linearized scheme)."""
+        H = self._Hk if self.scheme == "linearized" else self.H
         e = np.zeros(self.n_inst)
         for m in range(self.M):
-            np.add.at(e, self.inst_of, dv[m] * (self.H[m] @ dv[m]))
+            np.add.at(e, self.inst_of, dv[m] * (H[m] @ dv[m]))
         return e
 
     # -- one step -------------------------------------------------------
@@ -184,6 +190,23 @@ class SDC:
             Phi[m, idx] = ML[idx] * (v0[idx] - v[m, idx]) + dt * (Q[m, :] @ F[:, idx])
             Gam[m, idx] = w0[idx] - w[m, idx] + dt * (Q[m, :] @ R[:, idx])
 
+        if self.scheme == "linearized":
+            dv, amax, iters = self._solve_linearized(st, idx, Phi, cg_iters)
+        else:
+            dv, amax, iters = self._solve_imex(st, idx, Phi, Gam, cg_iters)
+        if theta is None or np.ndim(theta) == 0:
+            nxt = select(idx, amax, self.theta if theta is None else float(theta))
+        else:
+            nxt = idx[amax[idx] >= np.asarray(theta)[self.inst_of[idx]]]
+        return nxt, {"idx": idx, "n_active": int(idx.size), "cg_iters": iters, "amax": amax, "dv": dv}
+
+    def _solve_imex(self, st, idx, Phi, Gam, cg_iters):
+        """Node by node: implicit diffusion, explicit reaction and gating."""
+        M, dt = self.M, self.dt
+        QI, QE = self.col.QI, self.col.QE
+        ML, A = self.model.ML, self.model.A
+        N = self.model.N
+        v, w, I, R = st["v"], st["w"], st["I"], st["R"]
         dv = np.zeros((M, N))
         dI = np.zeros((M, N))
         dR = np.zeros((M, N))
@@ -212,11 +235,64 @@ class SDC:
             I[m, idx] = In
             R[m, idx] = Rn
             amax[idx] = np.maximum(amax[idx], np.abs(x[idx]))
-        if theta is None or np.ndim(theta) == 0:
-            nxt = select(idx, amax, self.theta if theta is None else float(theta))
-        else:
-            nxt = idx[amax[idx] >= np.asarray(theta)[self.inst_of[idx]]]
-        return nxt, {"idx": idx, "n_active": int(idx.size), "cg_iters": iters, "amax": amax, "dv": dv}
+        return dv, amax, iters
+
+    def _solve_linearized(self, st, idx, Phi, cg_iters):
+        """The paper's basic scheme (eq. final-sdc): per node, the potential
+        correction with the lumped reaction Jacobian G_j = ML dI/dv(v_j, w_j)
+        (at the sweep's iterate) beside A in the LU-trick operator,
+
+            (ML + dt QI[m,m] (A + G_m)) dv_m = Phi_m - dt sum_{j<m} QI[m,j] (A + G_j) dv_j,
+
+        then, with the new potentials, the gating correction with the
+        implicit dR/dw (Gauss-Seidel, u then w):
+
+            (1 - dt QI[m,m] R'_m) dw_m = w0 - w_m + dt sum_j Q[m,j] R(v_j^new, w_j)
+                                         + dt sum_{j<m} QI[m,j] R'_j dw_j,
+            R'_j = dR/dw(v_j^new, w_j)."""
+        M, dt = self.M, self.dt
+        Q, QI = self.col.Q, self.col.QI
+        ML, A = self.model.ML, self.model.A
+        N = self.model.N
+        v, w, I, R = st["v"], st["w"], st["I"], st["R"]
+        w0 = st["w0"]
+        p = self.model.p[:, idx]
+        G = np.zeros((M, N))
+        for j in range(M):
+            G[j, idx] = ML[idx] * ionic.current_partials(v[j, idx], w[j, idx], p)[0]
+        dv = np.zeros((M, N))
+        amax = np.zeros(N)
+        iters, Hk = [], []
+        for m in range(M):
+            rhs = Phi[m, idx].copy()
+            y = np.zeros(N)
+            for j in range(m):
+                y += dt * QI[m, j] * dv[j]
+                rhs -= dt * QI[m, j] * G[j, idx] * dv[j, idx]
+            rhs -= (A @ y)[idx]
+            Hm = (sp.diags(ML + dt * QI[m, m] * G[m]) + dt * QI[m, m] * A).tocsr()
+            b = np.zeros(N)
+            b[idx] = rhs
+            fixed = None if cg_iters is None else cg_iters[m]
+            x, it = jacobi_pcg(Hm, b, idx, self.cg_rtol, self.cg_maxit, fixed)
+            iters.append(it)
+            Hk.append(Hm)
+            dv[m] = x
+            v[m, idx] += x[idx]
+            amax[idx] = np.maximum(amax[idx], np.abs(x[idx]))
+        Rn = [ionic.rate(v[j, idx], w[j, idx], p) for j in range(M)]
+        Rw = [ionic.rate_partials(v[j, idx], w[j, idx], p)[1] for j in range(M)]
+        dw = []
+        for m in range(M):
+            g = w0[idx] - w[m, idx] + dt * sum(Q[m, j] * Rn[j] for j in range(M))
+            for j in range(m):
+                g = g + dt * QI[m, j] * Rw[j] * dw[j]
+            dw.append(g / (1.0 - dt * QI[m, m] * Rw[m]))
+        for m in range(M):
+            w[m, idx] += dw[m]
+            I[m, idx], R[m, idx] = self.model.reaction(v[m, idx], w[m, idx], idx)
+        self._Hk = Hk
+        return dv, amax, iters
 
     def step(self, v0, w0, K, idx_replay=None, cg_replay=None, keep=False):
         """K sweeps from the spread state; returns (v_end, w_end, infos).
@@ -284,7 +360,7 @@ def run(sdc, v, w, n_steps, K, stimuli=(), t0=0.0, idx_replay=None, cg_replay=No
     return v, w, log
 
 
-def build(problem, tol_sdc=0.0, rho=0.05, K_min=1, drop="theta"):
+def build(problem, tol_sdc=0.0, rho=0.05, K_min=1, drop="theta", scheme="imex"):
     """Assemble the oracle model and SDC integrator for a workload Problem."""
     from .assembly import lumped_mass, stiffness
     ML = lumped_mass(problem.coords, problem.elems, problem.N)
@@ -292,4 +368,4 @@ def build(problem, tol_sdc=0.0, rho=0.05, K_min=1, drop="theta"):
     model = Monodomain(ML, A, problem.node_ionic())
     inst_of = np.repeat(np.arange(problem.n_inst), np.diff(problem.node_off))
     return SDC(model, problem.M, problem.dt, problem.theta, problem.cg_rtol, problem.cg_maxit,
-               tol_sdc=tol_sdc, rho=rho, K_min=K_min, inst_of=inst_of, drop=drop)
+               tol_sdc=tol_sdc, rho=rho, K_min=K_min, inst_of=inst_of, drop=drop, scheme=scheme)
