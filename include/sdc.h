@@ -89,6 +89,16 @@ typedef struct {
   /* 1).  Needs tol_sdc > 0 (which also switches the energy-norm termination */
   /* on) and the monodomain model; else SDC_ERR_ARG.                          */
   int32_t drop_mode;
+  /* Sweep scheme.  0: implicit diffusion, explicit reaction and gating      */
+  /* (the system matrices H_m = ML + dt QI[m][m] A are fixed).  1: the       */
+  /* paper's basic scheme (Sec. 3.2, eq. final-sdc): the lumped reaction     */
+  /* Jacobian G_j = ML dI/dv(v_j, w_j) of the sweep's iterate joins A in the */
+  /* implicit operator, H_m = ML + dt QI[m][m] (A + G_m), and the right-hand  */
+  /* side carries dt sum_{j<m} QI[m][j] (A + G_j) dv_j; the gating follows    */
+  /* all potentials with implicit dR/dw (Gauss-Seidel).  Monodomain only,     */
+  /* not with the reverse pass; sdc_solve then uses the diagonals of the     */
+  /* last sweep on its rows.                                                 */
+  int32_t scheme;
 } sdc_params;
 
 /* Per-sweep statistics (sums over instances unless stated). */

@@ -242,15 +242,20 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     for (int i = 0; i < ni; ++i) st->nnz_active += mb.nnz[i];
   }
   const EmiArgs emi = ctx->emi_args();
+  const bool lin = ctx->linearized();
   launch_sweep_start(ctx->stream, M, map, N, ctx->A(), ctx->ml, ctx->v0, ctx->w0, ctx->v, ctx->w,
                      ctx->I, ctx->R, ctx->Phi, ctx->Gam, ctx->amax, ctx->cargs, emi);
+  if (lin)   // this sweep's reaction Jacobian on the diagonals of H_m (rows of the map)
+    launch_lin_diag(ctx->stream, M, map, N, ctx->ml, ctx->diagpos, ctx->Aval, ctx->ionic_d, ctx->v, ctx->w,
+                    ctx->cargs, ctx->G, ctx->Hval, ctx->nnz, ctx->dia_H,
+                    static_cast<int64_t>(ctx->nd / 2 + 1) * N, ctx->dinv);
   std::vector<std::vector<int>> iters(M);
   std::vector<int> ev_budget(M, 0);
   int ev_off = 0;
   for (int m = 0; m < M; ++m) {
     double* x = ctx->dv + m * N;
     launch_rhs(ctx->stream, M, m, map, N, ctx->A(), ctx->ml, ctx->Phi + m * N, ctx->dI, ctx->dv,
-               ctx->r[0], x, ctx->cargs, emi);
+               ctx->r[0], x, ctx->cargs, emi, lin ? ctx->G : nullptr);
     HIPC(hipGetLastError());
     const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
     if (async && ctx->pred[slot] <= kAsyncMaxBudget) {
@@ -264,13 +269,14 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     }
     launch_post(ctx->stream, M, m, map, N, ctx->ionic_d, x, ctx->v + m * N, ctx->w + m * N,
                 ctx->I + m * N, ctx->R + m * N, ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N,
-                ctx->dR, ctx->amax, ctx->cargs, emi);
+                ctx->dR, ctx->amax, ctx->cargs, emi, lin);
     launch_post_sites(ctx->stream, M, m, map, N, ctx->ionic_d, ctx->v + m * N, ctx->w + m * N,
                       ctx->I + m * N, ctx->R + m * N, ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N,
                       ctx->dR, ctx->cargs, emi);
     if (ctx->terminate()) launch_energy(ctx->stream, map, N, ctx->H(m), x, ctx->e_part + m * ctx->all.nblk);
     HIPC(hipGetLastError());
   }
+  if (lin) launch_wsweep(ctx->stream, M, map, N, ctx->ionic_d, ctx->v, ctx->w, ctx->w0, ctx->I, ctx->R, ctx->cargs);
   if (ctx->apriori_drop() && ctx->k == 0) {
     // a-priori drop tolerance of each instance for the rest of the step, from this first sweep
     launch_drop_tolerance(ctx->stream, map, M, N, ctx->ionic_d, ctx->amax, ctx->v0, ctx->w0, ctx->v, ctx->w,
@@ -639,6 +645,9 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     return fail(ctx, SDC_ERR_ARG, "the a-priori drop tolerance needs tol_sdc > 0 (and 0 < rho < 1)");
   if (prm->drop_mode == 1 && emi)
     return fail(ctx, SDC_ERR_ARG, "the a-priori drop tolerance is defined for the monodomain model only");
+  if (prm->scheme < 0 || prm->scheme > 1) return fail(ctx, SDC_ERR_ARG, "scheme must be 0 or 1");
+  if (prm->scheme == 1 && emi)
+    return fail(ctx, SDC_ERR_ARG, "the linearized scheme is implemented for the monodomain model only");
   if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
   if (node_off[0] != 0 || elem_off[0] != 0) return fail(ctx, SDC_ERR_ARG, "offsets must start at 0");
   for (int i = 0; i < n_inst; ++i)
@@ -787,6 +796,7 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     TRY(dalloc(ctx, &ctx->inst_stop, n_inst));
     HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_term), 2 * n_inst * sizeof(double)));
   }
+  if (prm->scheme == 1) TRY(dalloc(ctx, &ctx->G, static_cast<size_t>(M) * N));
   if (prm->drop_mode == 1) {
     TRY(dalloc(ctx, &ctx->drop_part, 2 * static_cast<size_t>(nblk_all)));
     TRY(dalloc(ctx, &ctx->drop_theta, n_inst));

@@ -167,6 +167,9 @@ struct sdc_ctx {
   double* drop_theta = nullptr;    // [n_inst] TOL_drop of the current step
   double* drop_info = nullptr;     // [n_inst][4] TOL_drop, r, c, eta
   bool apriori_drop() const { return prm.drop_mode == 1; }
+  // linearized scheme (scheme 1): lumped reaction Jacobian of the sweep
+  double* G = nullptr;             // [M][N] ML dI/dv(v_m, w_m) at the sweep's iterate
+  bool linearized() const { return prm.scheme == 1; }
   int k_min() const { return std::max(1, std::min(prm.K_min, prm.K)); }
 
   // kernel timing (bench only)

@@ -95,6 +95,12 @@ __device__ inline void ap_eval(double v, double w, const double* p, double& I, d
   R = s * (eps0 + mu1 * w / (v + mu2)) * (-w - k * v * (v - a - 1.0));
 }
 
+// dI/dv of the Aliev-Panfilov current: k ((v-a)(v-1) + v(v-1) + v(v-a)) + w.
+__device__ inline double ap_didv(double v, double w, const double* p) {
+  const double k = p[0], a = p[1];
+  return k * ((v - a) * (v - 1.0) + v * (v - 1.0) + v * (v - a)) + w;
+}
+
 template <class F>
 void dispatch_m(int M, F&& f) {
   switch (M) {
@@ -207,13 +213,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_start(
 
 // Right-hand side of node m; CG start values x = 0, r = b on active rows:
 //   b_i = Phi_m,i - dt ML_i sum_{j<m} QE[m][j] dI_j,i - dt sum_k A_ik sum_{j<m} QI[m][j] dv_j,k
-template <int M, int S, bool EMI>
+// or, in the linearized scheme (LIN, G = ML dI/dv at the sweep's iterate),
+//   b_i = Phi_m,i - dt sum_{j<m} QI[m][j] G_j,i dv_j,i - dt sum_k A_ik sum_{j<m} QI[m][j] dv_j,k.
+template <int M, int S, bool EMI, bool LIN>
 __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A,
                                                 const double* __restrict__ ml,
                                                 const double* __restrict__ Phi_m,
                                                 const double* __restrict__ dI,
                                                 const double* __restrict__ dv, double* __restrict__ r,
-                                                double* __restrict__ x, CollArgs c, EmiArgs e) {
+                                                double* __restrict__ x, CollArgs c, EmiArgs e,
+                                                const double* __restrict__ G) {
   const Row rw = map_row(map);
   if (!rw.valid) return;
   const int i = rw.row;
@@ -236,10 +245,17 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Map map, int m, int64_t N, Mat A
     rwt = ml[i];
   }
   double ex = 0.0;
+  if constexpr (LIN) {
 #pragma unroll
-  for (int j = 0; j < M - 1; ++j)
-    if (j < m) ex += c.QE[m][j] * dI[j * N + site];
-  r[i] = Phi_m[i] - c.dt * rwt * ex - c.dt * ay;
+    for (int j = 0; j < M - 1; ++j)
+      if (j < m) ex += c.QI[m][j] * (G[j * N + i] * dv[j * N + i]);
+    r[i] = Phi_m[i] - c.dt * ex - c.dt * ay;
+  } else {
+#pragma unroll
+    for (int j = 0; j < M - 1; ++j)
+      if (j < m) ex += c.QE[m][j] * dI[j * N + site];
+    r[i] = Phi_m[i] - c.dt * rwt * ex - c.dt * ay;
+  }
   x[i] = 0.0;
 }
 
@@ -495,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
 // Post-solve update of node m (eq. final-sdc):
 //   v_m += dv_m;  w_m += Gam_m + dt sum_{j<m} QE[m][j] dR_j;
 //   (I_m, R_m) <- AP(v_m, w_m) with dI_m, dR_m their change;  amax = max(amax, |dv_m|).
-template <int M, bool EMI>
+template <int M, bool EMI, bool LIN>
 __global__ __launch_bounds__(kBlock) void k_post(Map map, int m, int64_t N,
                                                  const double* __restrict__ ionic,
                                                  const double* __restrict__ x, double* v_m,
@@ -508,8 +524,9 @@ __global__ __launch_bounds__(kBlock) void k_post(Map map, int m, int64_t N,
   if (!rw.valid) return;
   const int i = rw.row;
   const double d = x[i];
-  if constexpr (EMI) {
-    // potentials only; the sites follow in k_post_sites
+  if constexpr (EMI || LIN) {
+    // potentials only; the sites (cell-by-cell) follow in k_post_sites, the
+    // gating (linearized scheme) in k_wsweep after the last node
     v_m[i] += d;
     amax[i] = fmax(amax[i], fabs(d));
     return;
@@ -529,6 +546,96 @@ __global__ __launch_bounds__(kBlock) void k_post(Map map, int m, int64_t N,
   I_m[i] = In;
   R_m[i] = Rn;
   amax[i] = fmax(amax[i], fabs(d));
+}
+
+// ---- the linearized scheme (the paper's basic scheme, eq. final-sdc)
+
+// dR/dw of the Aliev-Panfilov rate: s (e_w g - e) with e = eps0 + mu1 w/(v + mu2),
+// e_w = mu1 / (v + mu2), g = -w - k v (v - a - 1).
+__device__ inline double ap_drdw(double v, double w, const double* p) {
+  const double k = p[0], a = p[1], eps0 = p[2], mu1 = p[3], mu2 = p[4], s = p[5];
+  const double e = eps0 + mu1 * w / (v + mu2);
+  const double g = -w - k * v * (v - a - 1.0);
+  return s * (mu1 / (v + mu2) * g - e);
+}
+
+// Sweep start of the linearized scheme: on the active rows, the lumped
+// reaction Jacobian G_m = ML dI/dv(v_m, w_m) at the sweep's iterate, and the
+// diagonal of every H_m = ML + dt QI[m][m] (A + G_m) (both storages, when
+// present) with its Jacobi inverse.  Only the rows' own diagonals change,
+// and a restricted solve reads no other row's diagonal.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_lin_diag(Map map, int64_t N, const double* __restrict__ ml,
+                                                     const int32_t* __restrict__ diagpos,
+                                                     const double* __restrict__ Aval,
+                                                     const double* __restrict__ ionic,
+                                                     const double* __restrict__ v, const double* __restrict__ w,
+                                                     CollArgs c, double* __restrict__ G, double* __restrict__ Hval,
+                                                     int64_t nnz, double* __restrict__ diaH, int64_t dstride,
+                                                     double* __restrict__ dinv) {
+  const Row rw = map_row(map);
+  if (!rw.valid) return;
+  const int i = rw.row;
+  const double* p = ionic + 6 * rw.inst;
+  const double mli = ml[i];
+  const int dg = diagpos[i];
+  const double aii = Aval[dg];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double g = mli * ap_didv(v[m * N + i], w[m * N + i], p);
+    const double cm = c.dt * c.QI[m][m];
+    const double h = mli + cm * aii + cm * g;
+    G[m * N + i] = g;
+    Hval[m * nnz + dg] = h;
+    if (diaH) diaH[m * dstride + i] = h;
+    dinv[m * N + i] = 1.0 / h;
+  }
+}
+
+// Gating of the linearized scheme after the potentials of all nodes
+// (Gauss-Seidel, implicit dR/dw), per active row:
+//   (1 - dt QI[m][m] R'_m) dw_m = w0 - w_m + dt sum_j Q[m][j] R(v_j, w_j) + dt sum_{j<m} QI[m][j] R'_j dw_j
+// with R'_j = dR/dw(v_j, w_j) at the new potentials and the sweep's gating;
+// then w_m += dw_m and (I_m, R_m) <- AP(v_m, w_m).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_wsweep(Map map, int64_t N, const double* __restrict__ ionic,
+                                                   const double* __restrict__ v, double* __restrict__ w,
+                                                   const double* __restrict__ w0, double* __restrict__ I,
+                                                   double* __restrict__ R, CollArgs c) {
+  const Row rw = map_row(map);
+  if (!rw.valid) return;
+  const int i = rw.row;
+  const double* p = ionic + 6 * rw.inst;
+  double vj[M], wj[M], Rn[M], Rw[M], dw[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    vj[j] = v[j * N + i];
+    wj[j] = w[j * N + i];
+    double In;
+    ap_eval(vj[j], wj[j], p, In, Rn[j]);
+    Rw[j] = ap_drdw(vj[j], wj[j], p);
+  }
+  const double w0i = w0[i];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double sq = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) sq += c.Q[m][j] * Rn[j];
+    double g = w0i - wj[m] + c.dt * sq;
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+      if (j < m) g += c.dt * c.QI[m][j] * Rw[j] * dw[j];
+    dw[m] = g / (1.0 - c.dt * c.QI[m][m] * Rw[m]);
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double wm = wj[m] + dw[m];
+    double In, Rm;
+    ap_eval(vj[m], wm, p, In, Rm);
+    w[m * N + i] = wm;
+    I[m * N + i] = In;
+    R[m * N + i] = Rm;
+  }
 }
 
 // Cell-by-cell model, after k_post: the membrane sites whose intracellular
@@ -822,12 +929,6 @@ __global__ __launch_bounds__(kBlock) void k_energy_stop(const int32_t* __restric
 
 // ---- a-priori drop tolerance (Sec. 4.1, eq. drop-tolerance) after the first sweep
 
-// dI/dv of the Aliev-Panfilov current: k ((v-a)(v-1) + v(v-1) + v(v-a)) + w.
-__device__ inline double ap_didv(double v, double w, const double* p) {
-  const double k = p[0], a = p[1];
-  return k * ((v - a) * (v - 1.0) + v * (v - 1.0) + v * (v - a)) + w;
-}
-
 // Per block: the largest correction max_m |dv_m| (amax) of its rows, and the
 // smallest dI/dv at the step's start state and at the collocation values.
 template <int M>
@@ -981,16 +1082,38 @@ void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const M
 
 void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Mat& A,
                 const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
-                double* x, const CollArgs& c, const EmiArgs& e) {
+                double* x, const CollArgs& c, const EmiArgs& e, const double* G) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
     dispatch_storage(A.nd, [&](auto st) {
       constexpr int MM = decltype(mm)::value, S = decltype(st)::value;
       if (e.part)
-        k_rhs<MM, S, true><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c, e);
+        k_rhs<MM, S, true, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c, e,
+                                                                    nullptr);
+      else if (G)
+        k_rhs<MM, S, false, true><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c, e, G);
       else
-        k_rhs<MM, S, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c, e);
+        k_rhs<MM, S, false, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c, e,
+                                                                     nullptr);
     });
+  });
+}
+
+void launch_lin_diag(hipStream_t s, int M, const Map& map, int64_t N, const double* ml, const int32_t* diagpos,
+                     const double* Aval, const double* ionic, const double* v, const double* w, const CollArgs& c,
+                     double* G, double* Hval, int64_t nnz, double* diaH, int64_t dstride, double* dinv) {
+  if (map.nblk <= 0) return;
+  dispatch_m(M, [&](auto mm) {
+    k_lin_diag<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, ml, diagpos, Aval, ionic, v, w, c, G,
+                                                                      Hval, nnz, diaH, dstride, dinv);
+  });
+}
+
+void launch_wsweep(hipStream_t s, int M, const Map& map, int64_t N, const double* ionic, const double* v,
+                   double* w, const double* w0, double* I, double* R, const CollArgs& c) {
+  if (map.nblk <= 0) return;
+  dispatch_m(M, [&](auto mm) {
+    k_wsweep<decltype(mm)::value><<<grid(map.nblk), kBlock, 0, s>>>(map, N, ionic, v, w, w0, I, R, c);
   });
 }
 
@@ -1052,16 +1175,19 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                  const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
                  double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
-                 const CollArgs& c, const EmiArgs& e) {
+                 const CollArgs& c, const EmiArgs& e, bool lin) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
     constexpr int MM = decltype(mm)::value;
     if (e.part)
-      k_post<MM, true><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m, dR_m,
-                                                         Gam_m, dR, amax, c);
+      k_post<MM, true, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m,
+                                                                dR_m, Gam_m, dR, amax, c);
+    else if (lin)
+      k_post<MM, false, true><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m,
+                                                                dR_m, Gam_m, dR, amax, c);
     else
-      k_post<MM, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m, dR_m,
-                                                          Gam_m, dR, amax, c);
+      k_post<MM, false, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, ionic, x, v_m, w_m, I_m, R_m, dI_m,
+                                                                 dR_m, Gam_m, dR, amax, c);
   });
 }
 

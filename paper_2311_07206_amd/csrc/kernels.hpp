@@ -103,7 +103,8 @@ void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const M
 // Right-hand side of node m; writes r = b and x = 0 on active rows.
 void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Mat& A,
                 const double* ml, const double* Phi_m, const double* dI, const double* dv, double* r,
-                double* x, const CollArgs& c, const EmiArgs& e);
+                double* x, const CollArgs& c, const EmiArgs& e,
+                const double* G = nullptr);
 void launch_copy_b(hipStream_t s, const Map& map, const double* b, double* r, double* x);
 // Single-reduction Jacobi-PCG: start (w0 = H dinv r0 and partial sums), then
 // one launch per iteration reading buffers (r, w, s)_in, writing (r, w, s)_out.
@@ -133,7 +134,16 @@ constexpr int kTotBlocks = 4 * kBlock;
 void launch_post(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                  const double* x, double* v_m, double* w_m, double* I_m, double* R_m,
                  double* dI_m, double* dR_m, const double* Gam_m, const double* dR, double* amax,
-                 const CollArgs& c, const EmiArgs& e);
+                 const CollArgs& c, const EmiArgs& e, bool lin = false);
+// Linearized scheme (the paper's basic scheme): at the sweep start, G_m =
+// ML dI/dv(v_m, w_m) and the diagonals of every H_m (CSR values, and the
+// diagonal copy when diaH is not null; dstride = the copy's per-node stride)
+// with dinv, on the map's rows; after the last node, the gating sweep.
+void launch_lin_diag(hipStream_t s, int M, const Map& map, int64_t N, const double* ml, const int32_t* diagpos,
+                     const double* Aval, const double* ionic, const double* v, const double* w, const CollArgs& c,
+                     double* G, double* Hval, int64_t nnz, double* diaH, int64_t dstride, double* dinv);
+void launch_wsweep(hipStream_t s, int M, const Map& map, int64_t N, const double* ionic, const double* v,
+                   double* w, const double* w0, double* I, double* R, const CollArgs& c);
 void launch_post_sites(hipStream_t s, int M, int m, const Map& map, int64_t N, const double* ionic,
                        double* v_m, double* w_m, double* I_m, double* R_m, double* dI_m, double* dR_m,
                        const double* Gam_m, const double* dR, const CollArgs& c, const EmiArgs& e);

@@ -1,0 +1,120 @@
+"""GPU parity of the linearized scheme (the paper's basic scheme, eq.
+final-sdc: lumped reaction Jacobian in the implicit operator, gating by
+Gauss-Seidel with implicit dR/dw) against the oracle.
+
+The library rewrites the diagonals of H_m on each sweep's rows; the oracle
+assembles H_m^k afresh.  States within 1e-10 relative with the oracle
+replaying the GPU's active sets (1D, 2D ragged, batched, with the a-priori
+drop tolerance and the energy termination); diagonal storage equals CSR
+storage bitwise.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.sdc import apply_stimuli, build  # noqa: E402
+from workloads import config0, config1, config3, config4  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _solver(P, **kw):
+    from paper_2311_07206_amd import Solver
+    return Solver.from_problem(P, **kw)
+
+
+def _run_gpu(P, s, n_steps, K, stop_aware=False):
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    sets = []
+    for n in range(n_steps):
+        s.begin_step(v, w, n * P.dt)
+        step_sets = [None]
+        for k in range(K):
+            st = s.sweep()
+            if k + 1 == K or (stop_aware and st["n_stopped"] == P.n_inst):
+                break
+            step_sets.append(s.active().cpu().numpy().astype(np.int64))
+        s.end_step(v, w)
+        sets.append(step_sets)
+    return v.cpu().numpy(), w.cpu().numpy(), sets
+
+
+def _run_oracle(P, orc, n_steps, K, sets):
+    v, w = P.v_init.copy(), P.w_init.copy()
+    for n in range(n_steps):
+        apply_stimuli(v, n * P.dt, P.dt, P.stimuli)
+        v, w, _ = orc.step(v, w, K, idx_replay=sets[n])
+    return v, w
+
+
+@pytest.mark.parametrize("case", ["1d", "2d", "batched"])
+def test_linearized_scheme_matches_oracle(case):
+    if case == "1d":
+        P, n_steps = config0(theta=1e-6), 30
+    elif case == "2d":
+        P, n_steps = config1(n=37, theta=1e-7, n_steps=3), 3
+    else:
+        P, n_steps = config4(n_inst=3, sizes=(10, 18), n_steps=2), 2
+    K = P.K
+    s = _solver(P, scheme="linearized")
+    print(f"[linearized {case}] N={P.N} format={s.info()['format']}", flush=True)
+    gv, gw, sets = _run_gpu(P, s, n_steps, K)
+    assert any(st is not None and st.size < P.N for steps in sets for st in steps)
+    ov, ow = _run_oracle(P, build(P, scheme="linearized"), n_steps, K, sets)
+    print(f"   rel v {rel(gv, ov):.2e} w {rel(gw, ow):.2e}", flush=True)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+    # a different scheme from the default one on the same steps
+    iv, _ = _run_oracle(P, build(P), n_steps, K, sets)
+    assert rel(iv, ov) > 1e-9
+
+
+def test_linearized_diagonal_storage_equals_csr_bitwise():
+    P = config1(n=33, theta=1e-7, n_steps=3)
+    a = _solver(P, scheme="linearized", fmt=2)
+    b = _solver(P, scheme="linearized", fmt=1)
+    assert a.info()["format"] == "dia" and b.info()["format"] == "csr"
+    va, wa, sa = _run_gpu(P, a, 3, P.K)
+    vb, wb, sb = _run_gpu(P, b, 3, P.K)
+    assert all(np.array_equal(x, y) for p, q in zip(sa, sb) for x, y in zip(p[1:], q[1:]))
+    assert np.array_equal(va, vb) and np.array_equal(wa, wb)
+
+
+def test_linearized_with_apriori_drop_and_termination():
+    P = config4(n_inst=2, sizes=(12, 16), n_steps=2)
+    K, tol, rho = 6, 1e-5, 0.3
+    s = _solver(P, scheme="linearized", K=K, tol_sdc=tol, rho=rho, K_min=2, drop="apriori")
+    gv, gw, sets = _run_gpu(P, s, P.n_steps, K, stop_aware=True)
+    orc = build(P, tol_sdc=tol, rho=rho, K_min=2, drop="apriori", scheme="linearized")
+    v, w = P.v_init.copy(), P.w_init.copy()
+    for n in range(P.n_steps):
+        apply_stimuli(v, n * P.dt, P.dt, P.stimuli)
+        v, w, infos = orc.step(v, w, K, idx_replay=sets[n])
+        assert len(infos) == len(sets[n])
+    assert rel(gv, v) < 1e-10 and rel(gw, w) < 1e-10
+
+
+def test_linearized_rejections():
+    from paper_2311_07206_amd import SDCError
+    with pytest.raises(SDCError, match="monodomain"):
+        _solver(config3(nc=2, nr=1, nx=3, ny=3), scheme="linearized")
+    P = config1(n=12, theta=1e-7)
+    s = _solver(P, scheme="linearized")
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    with pytest.raises(SDCError, match="STATE"):
+        s.adjoint_record(0, v, w, 0.0)
