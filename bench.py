@@ -128,6 +128,8 @@ def parse():
     ap.add_argument("--emi-steps", type=int, default=3)
     ap.add_argument("--no-speedup", action="store_true",
                     help="skip the non-adaptive (theta = 0) runs over the same steps")
+    ap.add_argument("--no-linearized", action="store_true",
+                    help="skip the 512x512 run with the paper's linearized basic scheme")
     ap.add_argument("--profile-warmup", action="store_true",
                     help="account CG kernel bytes from the first step (matches counter runs)")
     ap.add_argument("--calib", action="store_true",
@@ -297,6 +299,9 @@ def main():
         out["adaptive_vs_nonadaptive"] = {
             "nonadaptive_ms_per_step": 1e3 * el0 / args.steps, "adaptive_ms_per_step": out["ms_per_step"],
             "speedup": el0 / elapsed, "paper_cpu_speedup_2d_monodomain": PAPER_SPEEDUP["2d_monodomain"]}
+    if not args.no_linearized:
+        out["workload_2d_linearized"] = workload_linearized(P, v_start, w_start, t_start, min(args.steps, 100),
+                                                            speedup=not args.no_speedup)
     if not args.no_batch:
         out["batched"], out["adjoint"] = batched_and_adjoint(args.batch_steps)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio_ckpt10"]
@@ -418,6 +423,33 @@ def batched_and_adjoint(nsteps):
         adj[f"ratio_ckpt{ck}"] = tb / tf
     s.close()
     return batched, adj
+
+
+def workload_linearized(P, v0, w0, t0, nsteps, speedup=True):
+    """The 512^2 workload with the paper's basic scheme (reaction Jacobian in
+    the implicit operator, Gauss-Seidel gating), the same steps from the same
+    state as the main measurement."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    s = Solver.from_problem(P, scheme="linearized")
+    v, w = torch.tensor(v0, device=dev), torch.tensor(w0, device=dev)
+    s.step(v.clone(), w.clone(), t0)   # iteration history for the budgets
+    el, logs = _timed_steps(s, v, w, t0, P.dt, nsteps, torch.cuda.synchronize)
+    s.close()
+    dofs = sum(st["n_active"] for lg in logs for st in lg)
+    out = {"workload": f"2D monodomain {int(round(P.N ** 0.5))}^2, the paper's linearized basic scheme, "
+                       f"M={P.M} K={P.K} dt={P.dt}, theta={P.theta}; {nsteps} steps from t={t0:.1f} ms",
+           "value": dofs / el, "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
+           "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)],
+           "mean_cg_iters_per_node": [float(np.mean([lg[k]["cg_iters_max"][m] for lg in logs for k in range(P.K)]))
+                                      for m in range(P.M)]}
+    if speedup:
+        el0 = nonadaptive_run(P, v0, w0, t0, nsteps, scheme="linearized")
+        out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / nsteps, "speedup": el0 / el,
+                                          "paper_cpu_speedup_2d_monodomain": PAPER_SPEEDUP["2d_monodomain"]}
+    return out
 
 
 def workload_3d(nsteps=10, warm=10, speedup=True):
