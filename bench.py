@@ -124,7 +124,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / adjoint measurements")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 3D workload")
-    ap.add_argument("--no-emi", action="store_true", help="skip the 64x16-cell cell-by-cell workload")
+    ap.add_argument("--no-emi", action="store_true", help="skip the cell-by-cell workloads (2D and 3D)")
     ap.add_argument("--emi-steps", type=int, default=3)
     ap.add_argument("--no-speedup", action="store_true",
                     help="skip the non-adaptive (theta = 0) runs over the same steps")
@@ -309,6 +309,7 @@ def main():
         out["workload_3d"] = workload_3d(speedup=not args.no_speedup)
     if not args.no_emi:
         out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
+        out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
@@ -488,15 +489,17 @@ def workload_3d(nsteps=10, warm=10, speedup=True):
     return out
 
 
-def workload_emi(nsteps=3, warm=1, speedup=True):
-    """The cell-by-cell workload (64 x 16 myocytes, 390,564 potential dofs,
-    81,920 membrane sites), from the stimulus: CSR storage, Jacobi-PCG."""
+def workload_emi(nsteps=3, warm=1, speedup=True, three_d=False):
+    """The cell-by-cell workload, from the stimulus: CSR storage, Jacobi-PCG.
+    2D: 64 x 16 myocytes (390,564 potential dofs, 81,920 membrane sites);
+    3D: 8 x 3 x 2 brick myocytes (209,672 dofs, 55,392 sites, tetrahedra)."""
     import torch
 
     from paper_2311_07206_amd import Solver
     from workloads import config3
+    from workloads.emi import config5
 
-    P = config3()
+    P = config5() if three_d else config3()
     dev = torch.device("cuda", 0)
     s = Solver.from_problem(P, cg_maxit=200000)
     u = torch.tensor(P.v_init, device=dev)
@@ -510,7 +513,8 @@ def workload_emi(nsteps=3, warm=1, speedup=True):
     s.profile(False)
     dofs = sum(st["n_active"] for lg in logs for st in lg)
     nbytes = sum(sweep_bytes(st, P.M, k == 0) for lg in logs for k, st in enumerate(lg)) + nsteps * step_bytes(P.N, P.M)
-    out = {"workload": f"2D cell-by-cell {P.N} potential dofs, {len(P.mem_intra)} membrane sites, M={P.M} "
+    out = {"workload": f"{'3D' if three_d else '2D'} cell-by-cell {P.N} potential dofs, "
+                       f"{len(P.mem_intra)} membrane sites, M={P.M} "
                        f"K={P.K} dt={P.dt}, theta={P.theta}; steps {warm}..{warm + nsteps - 1} after the stimulus",
            "value": dofs / el, "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
            "algorithmic_GBps": nbytes / el / 1e9, "storage": s.info(),
@@ -524,8 +528,9 @@ def workload_emi(nsteps=3, warm=1, speedup=True):
         # solves above the asynchronous budget limit run synchronously, so
         # the missing iteration history costs little here
         el0 = nonadaptive_run(P, u0, w0, warm * P.dt, nsteps, warm_budget=False, cg_maxit=200000)
+        key = "3d_emi" if three_d else "2d_emi"
         out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / nsteps, "speedup": el0 / el,
-                                          "paper_cpu_speedup_2d_emi": PAPER_SPEEDUP["2d_emi"]}
+                                          f"paper_cpu_speedup_{key}": PAPER_SPEEDUP[key]}
     return out
 
 
