@@ -49,13 +49,29 @@ __device__ inline void block_sum(double (&v)[NV], double* sh /* [4 * NV] */) {
 // storage with S diagonals known at compile time (fully unrolled, so all
 // loads of the row are in flight together).  The diagonal offsets and the
 // instance's row range come from the block's map entry.
+constexpr int kCsrChunk = 8;
+
 template <int S, class F>
 __device__ __forceinline__ void for_entries(const Mat& A, int64_t N, const Row& rw, int i, F&& f) {
   if constexpr (S == 0) {
-    const int e1 = A.rowptr[i + 1];
-    for (int e = A.rowptr[i]; e < e1; ++e) {
-      const int c = A.col[e];
-      f(A.val[e], c, c == i);
+    // Entries in chunks of kCsrChunk whose loads are issued together: the
+    // chunk's tail past the row's end reads the row's last entry with
+    // weight 0 (adding exact zeros, so the sums equal the plain loop's).
+    const int e0 = A.rowptr[i], e1 = A.rowptr[i + 1];
+    for (int eb = e0; eb < e1; eb += kCsrChunk) {
+      double a[kCsrChunk];
+      int cq[kCsrChunk];
+#pragma unroll
+      for (int q = 0; q < kCsrChunk; ++q) {
+        const int e = min(eb + q, e1 - 1);
+        a[q] = A.val[e];
+        cq[q] = A.col[e];
+      }
+#pragma unroll
+      for (int q = 0; q < kCsrChunk; ++q) {
+        const bool in = eb + q < e1;
+        f(in ? a[q] : 0.0, cq[q], in && cq[q] == i);
+      }
     }
   } else {
     constexpr int kUnroll = S > 0 ? S : 1;
