@@ -20,9 +20,11 @@ namespace {
 
 // ------------------------------------------------------------------ helpers
 
+// Butterfly over the wave, adjacent lanes first (the two-rows-per-thread CG
+// kernel reproduces this order with the pair sum in the thread).
 __device__ inline double wave_sum(double x) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  for (int off = 1; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
 
@@ -522,6 +524,239 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     s[2] = rn * rn;
   }
   write_partials<3>(s, L, part_out, sh_out);
+}
+
+// ---- the CG iteration on all rows of an instance, two adjacent rows per thread
+
+constexpr int kPairThreads = kBlock / 2;
+
+// Sum over a 128-thread block of per-thread values that are already the sum
+// of the thread's two rows, in the order block_sum / block_total take over
+// the same 256 rows at one row per lane (the adjacent-lane step is the pair
+// sum, the remaining steps are the lane butterfly within 32 lanes, then the
+// four 64-row groups), so both kernels produce bitwise the same block sums.
+// The total ends in every thread.
+template <int NV>
+__device__ inline void pair_block_total(double (&v)[NV], double* sh /* [4 * NV] */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) v[k] += __shfl_xor(v[k], off, 64);
+  }
+  if ((lane & 31) == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[(2 * wid + (lane >> 5)) * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = (sh[k] + sh[NV + k]) + (sh[2 * NV + k] + sh[3 * NV + k]);
+}
+
+// k_cg_iter for maps without a list (every row of the instances: the first
+// sweep of a step) and diagonal storage, with 128 threads per 256-row map
+// entry.  Thread t owns rows beg + 2t and beg + 2t + 1; in blocks whose
+// stencil stays inside the instance, every value of the two rows sits at
+// adjacent addresses, so each pair is one 16-byte load and the address work
+// per row halves.  Other blocks take the rows one after the other.  The
+// arithmetic per row and the order of every sum are those of k_cg_iter, so
+// the two kernels agree bitwise.
+template <int S, bool FIRST, bool TOT>
+__global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__ blk_done,
+                                                           const BlkRec* __restrict__ rec,
+                                                           const int32_t* __restrict__ idx, int nblk, int it,
+                                                           const double* __restrict__ part_in,
+                                                           const double* __restrict__ scal_in, int64_t N, Mat H,
+                                                           const double* __restrict__ dinv,
+                                                           double* __restrict__ x, double* __restrict__ p,
+                                                           const double* __restrict__ u_in,
+                                                           const double* __restrict__ w_in,
+                                                           const double* __restrict__ s_in,
+                                                           double* __restrict__ u_out,
+                                                           double* __restrict__ w_out,
+                                                           double* __restrict__ s_out,
+                                                           double* __restrict__ part_out,
+                                                           double* __restrict__ scal_out, double rtol2, int maxit,
+                                                           int32_t* __restrict__ done, int32_t* __restrict__ iters) {
+  static_assert(S > 0, "diagonal storage with a compile-time count");
+  __shared__ double sh_in[16], sh_out[16];
+  const int L = logical_block(nblk);
+  const int t = static_cast<int>(threadIdx.x);
+  Row rw;
+  rw.word = reinterpret_cast<const int32_t*>(rec + L)[min(t & 63, kRecWords - 1)];
+  rw.inst = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, inst) / 4);
+  rw.beg = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, beg) / 4);
+  rw.end = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, end) / 4);
+  rw.bi = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, bi) / 4);
+  rw.nb = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, nb) / 4);
+  rw.lo = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, lo) / 4);
+  rw.hi = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, hi) / 4);
+  rw.blk = L;
+  rw.listed = 0;
+  if (blk_done[L] | (it < 0) | (H.nd < 0) | (s_out == nullptr) | (iters == nullptr) | (idx != nullptr)) return;
+  const int inst = rw.inst, nb = rw.nb, b0 = L - rw.bi;
+  const int n_rows = rw.end - rw.beg;
+  const bool va = 2 * t < n_rows, vb = 2 * t + 1 < n_rows;
+  const int ia = va ? rw.beg + 2 * t : 0, ib = vb ? rw.beg + 2 * t + 1 : 0;
+  constexpr int h = S / 2;
+  const bool interior = (n_rows == kBlock) & (rw.beg + rw.off(0) >= rw.lo) & (rw.end - 1 + rw.off(S - 1) < rw.hi);
+  double ar[2] = {0.0, 0.0}, aw[2] = {0.0, 0.0}, as[2] = {0.0, 0.0}, hii[2] = {0.0, 0.0};
+  double si[2], pold[2], di[2], ui[2], wi[2], xold[2];
+  if (interior) {
+    // both rows valid, ib = ia + 1, every column inside the instance
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+      const int c = ia + rw.off(d);
+      const double* hp = d < h ? H.dval + static_cast<int64_t>(S - 1 - d - h) * N + c
+                               : H.dval + static_cast<int64_t>(d - h) * N + ia;
+      const double h0 = hp[0], h1 = hp[1];
+      ar[0] += h0 * u_in[c];
+      ar[1] += h1 * u_in[c + 1];
+      aw[0] += h0 * w_in[c];
+      aw[1] += h1 * w_in[c + 1];
+      if (!FIRST) {
+        as[0] += h0 * s_in[c];
+        as[1] += h1 * s_in[c + 1];
+      }
+      if (d == h) {
+        hii[0] = h0;
+        hii[1] = h1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      si[q] = FIRST ? 0.0 : s_in[ia + q];
+      pold[q] = FIRST ? 0.0 : p[ia + q];
+      di[q] = dinv[ia + q];
+      ui[q] = u_in[ia + q];
+      wi[q] = w_in[ia + q];
+      xold[q] = x[ia + q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = q ? ib : ia;
+      for_entries<S>(H, N, rw, i, [&](double hv, int k, bool diag) {
+        ar[q] += hv * u_in[k];
+        aw[q] += hv * w_in[k];
+        if (!FIRST) as[q] += hv * s_in[k];
+        if (diag) hii[q] = hv;
+      });
+      si[q] = FIRST ? 0.0 : s_in[i];
+      pold[q] = FIRST ? 0.0 : p[i];
+      di[q] = dinv[i];
+      ui[q] = u_in[i];
+      wi[q] = w_in[i];
+      xold[q] = x[i];
+    }
+  }
+  double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
+  if (!FIRST) {
+    const double* sc = scal_in + inst * kScal;
+    sc_rz = sc[kRZ];
+    sc_alpha = sc[kAlpha];
+    sc_bb = sc[kBB];
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  if constexpr (TOT) {
+    acc[0] = part_in[4 * inst];
+    acc[1] = part_in[4 * inst + 1];
+    acc[2] = part_in[4 * inst + 2];
+  } else {
+    // the partials of the one-row kernel's threads 2t and 2t+1, each summed
+    // in that kernel's order, then their pair sum
+    double pa[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int q = 0; q < kTotBlocks / kBlock; ++q) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int b = 2 * t + v + q * kBlock;
+        const double* pp = part_in + 4 * (b0 + min(b, nb - 1));
+        const double wgt = b < nb ? 1.0 : 0.0;
+        pa[v][0] += wgt * pp[0];
+        pa[v][1] += wgt * pp[1];
+        pa[v][2] += wgt * pp[2];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] = pa[0][k] + pa[1][k];
+    pair_block_total<3>(acc, sh_in);
+  }
+  const double gamma = acc[0], delta = acc[1], rr = acc[2];
+  double alpha, beta, bb;
+  if (FIRST) {
+    bb = rr;
+    beta = 0.0;
+    alpha = gamma / delta;
+  } else {
+    bb = sc_bb;
+    beta = gamma / sc_rz;
+    alpha = gamma / (delta - beta * gamma / sc_alpha);
+  }
+  int status = 0;
+  if (!isfinite(rr)) status = 3;
+  else if (rr <= rtol2 * bb) status = 1;
+  else if (it >= maxit) status = 2;
+  else if (!isfinite(alpha) || !(alpha > 0.0)) status = 3;
+  if (rw.bi == 0 && t == 0) {
+    done[inst] = status;
+    iters[inst] = it;
+    double* so = scal_out + inst * kScal;
+    so[kRZ] = gamma;
+    so[kAlpha] = alpha;
+    so[kBB] = bb;
+  }
+  if (status != 0) {
+    if (t == 0) blk_done[L] = status;
+    return;
+  }
+  double sp[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  double xn[2], pn[2], sn[2], un[2], wn[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double w_new = ar[q] - alpha * (aw[q] + beta * as[q]);
+    pn[q] = ui[q] + beta * pold[q];
+    sn[q] = wi[q] + beta * si[q];
+    xn[q] = xold[q] + alpha * pn[q];
+    un[q] = ui[q] - alpha * sn[q];
+    wn[q] = di[q] * w_new;
+    const double rn = hii[q] * un[q];
+    sp[q][0] = rn * un[q];
+    sp[q][1] = w_new * un[q];
+    sp[q][2] = rn * rn;
+  }
+  if (interior) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      x[ia + q] = xn[q];
+      p[ia + q] = pn[q];
+      s_out[ia + q] = sn[q];
+      u_out[ia + q] = un[q];
+      w_out[ia + q] = wn[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (!(q ? vb : va)) {
+        sp[q][0] = sp[q][1] = sp[q][2] = 0.0;
+        continue;
+      }
+      const int i = q ? ib : ia;
+      x[i] = xn[q];
+      p[i] = pn[q];
+      s_out[i] = sn[q];
+      u_out[i] = un[q];
+      w_out[i] = wn[q];
+    }
+  }
+  double tot[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) tot[k] = sp[0][k] + sp[1][k];
+  pair_block_total<3>(tot, sh_out);
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) part_out[4 * L + k] = tot[k];
+  }
 }
 
 // Post-solve update of node m (eq. final-sdc):
@@ -1160,26 +1395,30 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                                                                                  part_in, tot);
     pin = tot;
   }
-  auto go = [&](auto kern) {
+  auto go = [&](auto kern, int threads) {
     if (ev_start) {
       // events stamped by the dispatch itself: they time the kernel's execution
-      hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(kBlock), 0, s, ev_start, ev_stop, 0, cg.blk_done, map.rec,
+      hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(threads), 0, s, ev_start, ev_stop, 0, cg.blk_done, map.rec,
                             map.idx, map.nblk, it, pin, scal_in, N, H, dinv, x, p, u_in, w_in, s_in, u_out,
                             w_out, s_out, part_out, scal_out, rtol2, maxit, cg.done, cg.iters);
     } else {
-      kern<<<grid(map.nblk), kBlock, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, it, pin, scal_in, N, H, dinv,
-                                             x, p, u_in, w_in, s_in, u_out, w_out, s_out, part_out, scal_out, rtol2,
-                                             maxit, cg.done, cg.iters);
+      kern<<<grid(map.nblk), threads, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, it, pin, scal_in, N, H, dinv,
+                                              x, p, u_in, w_in, s_in, u_out, w_out, s_out, part_out, scal_out, rtol2,
+                                              maxit, cg.done, cg.iters);
     }
   };
   dispatch_storage(H.nd, [&](auto st) {
     constexpr int S = decltype(st)::value;
     auto pick = [&](auto tt) {
       constexpr bool T = decltype(tt)::value;
-      if (map.idx)
-        it == 0 ? go(k_cg_iter<S, true, 1, T>) : go(k_cg_iter<S, false, 1, T>);
-      else
-        it == 0 ? go(k_cg_iter<S, true, 0, T>) : go(k_cg_iter<S, false, 0, T>);
+      if (map.idx) {
+        it == 0 ? go(k_cg_iter<S, true, 1, T>, kBlock) : go(k_cg_iter<S, false, 1, T>, kBlock);
+      } else if constexpr (S > 0) {
+        // every row of the instances: two rows per thread
+        it == 0 ? go(k_cg_iter2<S, true, T>, kPairThreads) : go(k_cg_iter2<S, false, T>, kPairThreads);
+      } else {
+        it == 0 ? go(k_cg_iter<S, true, 0, T>, kBlock) : go(k_cg_iter<S, false, 0, T>, kBlock);
+      }
     };
     if (tot)
       pick(std::true_type{});
