@@ -63,14 +63,14 @@ def summarize_trace(path):
         name = m.group(1) if m else row["Kernel_Name"].split("(")[0][:60]
         d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
         durs[name].append(d)
-        if name == "k_cg_iter":
+        if name in ("k_cg_iter", "k_cg_iter2"):   # one or two rows per thread; 256-row map entries either way
             grid[int(row["Grid_Size_X"]) // int(row["Workgroup_Size_X"])].append(d)
     total = sum(sum(v) for v in durs.values())
     out = ["| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
     for k, v in sorted(durs.items(), key=lambda z: -sum(z[1])):
         out.append(f"| {k} | {len(v)} | {sum(v) / 1e6:.2f} | {np.mean(v) / 1e3:.3f} | {100 * sum(v) / total:.1f}% |")
-    v = np.array(durs.get("k_cg_iter", [0]))
-    out += ["", f"k_cg_iter: {len(v)} dispatches, mean {v.mean() / 1e3:.3f} us", "",
+    v = np.array(durs.get("k_cg_iter", []) + durs.get("k_cg_iter2", []) or [0])
+    out += ["", f"CG iteration (k_cg_iter, k_cg_iter2): {len(v)} dispatches, mean {v.mean() / 1e3:.3f} us", "",
             "| blocks (256 rows) | dispatches | median us | mean us |", "|---|---|---|---|"]
     bins = [(1, 128), (128, 256), (256, 512), (512, 1024), (1024, 1025), (1025, 1 << 30)]
     for lo, hi in bins:

@@ -57,11 +57,12 @@ def test_summarize_counters_rejects_mismatched_runs(tmp_path):
 
 
 def test_summarize_trace_bins_cg_launches_by_grid(tmp_path):
+    # the two-rows-per-thread kernel has 128-thread blocks over the same 256-row entries
     path = tmp_path / "kt.csv"
     fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Workgroup_Size_X"]
     rows = [("void sdc::k_cg_iter<7, false, 1, false>(...)", 0, 5000, 200 * 256, 256),
             ("void sdc::k_cg_iter<7, false, 1, false>(...)", 0, 7000, 200 * 256, 256),
-            ("void sdc::k_cg_iter<7, false, 0, false>(...)", 0, 11000, 1024 * 256, 256),
+            ("void sdc::k_cg_iter2<7, false, false>(...)", 0, 11000, 1024 * 128, 128),
             ("void sdc::k_rhs<4, 7, false>(...)", 0, 6000, 1024 * 256, 256)]
     with open(path, "w", newline="") as f:
         wr = csv.DictWriter(f, fieldnames=fields)
@@ -69,7 +70,8 @@ def test_summarize_trace_bins_cg_launches_by_grid(tmp_path):
         for r in rows:
             wr.writerow(dict(zip(fields, r)))
     text = bench.summarize_trace(str(path))
-    assert "| k_cg_iter | 3 | 0.02 | 7.667 |" in text
+    assert "| k_cg_iter | 2 | 0.01 | 6.000 |" in text and "| k_cg_iter2 | 1 | 0.01 | 11.000 |" in text
+    assert "CG iteration (k_cg_iter, k_cg_iter2): 3 dispatches, mean 7.667 us" in text
     assert "| k_rhs | 1 | 0.01 | 6.000 |" in text
     assert "| 128..255 | 2 | 6.00 | 6.00 |" in text
     assert "| 1024..1024 | 1 | 11.00 | 11.00 |" in text
