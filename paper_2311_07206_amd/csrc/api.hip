@@ -443,12 +443,14 @@ int build_dia(sdc_ctx* ctx) {
   return SDC_OK;
 }
 
-// Storage choice: time the CG start kernel (an SpMV with H_0 over all rows)
-// in each storage (or take the one the caller forced).  Diagonal storage
-// moves fewer bytes per row (half the diagonals, no column indices), so it
-// is kept unless CSR is faster by more than 5 %: on small systems both
-// times are launch overhead, and a profiler's per-dispatch cost can invert
-// them by chance.
+// Storage choice (unless the caller forced one): the diagonal copy when it
+// reads at most 0.6 of CSR's matrix bytes (8 B per stored diagonal and row
+// against 12 B per entry with its column index: 2D triangles 0.38, 3D
+// tetrahedra 0.52); otherwise time the CG start kernel (an SpMV with H_0
+// over all rows) in both storages and keep the diagonal copy unless CSR is
+// faster by more than 5 %.  On small systems both times are launch
+// overhead, and a profiler's per-dispatch cost can invert them by chance;
+// the timings are taken and reported either way.
 int autotune(sdc_ctx* ctx) {
   ctx->use_dia = false;
   if (ctx->nd == 0 || ctx->prm.format == 1) return SDC_OK;
@@ -482,7 +484,9 @@ int autotune(sdc_ctx* ctx) {
   (void)hipEventDestroy(e1);
   ctx->t_csr_us = t[0];
   ctx->t_dia_us = t[1];
-  ctx->use_dia = t[1] < 1.05 * t[0];
+  const double dia_bytes = 8.0 * (ctx->nd / 2 + 1) * static_cast<double>(ctx->N);
+  const double csr_bytes = 12.0 * static_cast<double>(ctx->nnz);
+  ctx->use_dia = dia_bytes <= 0.6 * csr_bytes || t[1] < 1.05 * t[0];
   return SDC_OK;
 }
 
