@@ -80,11 +80,12 @@ def summarize_trace(path):
     return "\n".join(out)
 
 
-def summarize_counters(fetch_csv, write_csv):
+def summarize_counters(fetch_csv, write_csv, min_blocks=0):
     """Pair FETCH_SIZE and WRITE_SIZE runs dispatch by dispatch (KiB per
     dispatch).  A 256 MiB device copy (reads and writes 262144 KiB) calibrates
     each counter; the CG iteration's launches that perform an update (writes
-    above 1 KiB) give the measured HBM bytes per launch."""
+    above 1 KiB), with at least min_blocks map entries, give the measured HBM
+    bytes per launch."""
     import csv
     rows = []
     for path in (fetch_csv, write_csv):
@@ -96,6 +97,8 @@ def summarize_counters(fetch_csv, write_csv):
     for a, b in zip(f, w):
         assert a["Kernel_Name"] == b["Kernel_Name"]
         if "k_cg_iter" in a["Kernel_Name"]:
+            if min_blocks and int(a["Grid_Size"]) // int(a["Workgroup_Size"]) < min_blocks:
+                continue
             cg_f.append(float(a["Counter_Value"]))
             cg_w.append(float(b["Counter_Value"]))
         elif "copyBuffer" in a["Kernel_Name"] and abs(float(b["Counter_Value"]) - 262144.0) < 13000.0:
@@ -136,6 +139,8 @@ def parse():
                     help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
                     help="print a summary of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--min-blocks", type=int, default=0,
+                    help="with --summarize-counters: only CG launches with at least this many map entries")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="pair rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, print JSON and exit")
     return ap.parse_args()
@@ -180,7 +185,7 @@ def main():
         print(summarize_trace(args.summarize_trace))
         return
     if args.summarize_counters:
-        print(json.dumps(summarize_counters(*args.summarize_counters), indent=1))
+        print(json.dumps(summarize_counters(*args.summarize_counters, min_blocks=args.min_blocks), indent=1))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

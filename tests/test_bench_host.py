@@ -22,12 +22,15 @@ def test_more_than_one_gpu_exits_with_message():
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
 
 
-def _counter_csv(path, rows):
+def _counter_csv(path, rows, grids=None):
     with open(path, "w", newline="") as f:
-        wr = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Value"])
+        wr = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Grid_Size", "Workgroup_Size",
+                                           "Counter_Value"])
         wr.writeheader()
         for i, (name, val) in enumerate(rows):
-            wr.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Counter_Value": val})
+            g = 256 * (grids[i] if grids else 1)
+            wr.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Grid_Size": g, "Workgroup_Size": 256,
+                         "Counter_Value": val})
 
 
 def test_summarize_counters_calibrates_on_the_256_mib_copy(tmp_path):
@@ -47,6 +50,18 @@ def test_summarize_counters_calibrates_on_the_256_mib_copy(tmp_path):
     assert out["fetch_kib_per_launch"] == pytest.approx(200.0)
     assert out["write_kib_per_launch"] == pytest.approx(100.0)
     assert out["measured_bytes_per_launch"] == pytest.approx((2.0 * 200.0 + 100.0) * 1024.0)
+
+
+def test_summarize_counters_filters_by_launch_size(tmp_path):
+    names = ["__amd_rocclr_copyBuffer", "void sdc::k_cg_iter<7, false, 1, false>(...)",
+             "void sdc::k_cg_iter2<19, false, true>(...)"]
+    grids = [1, 200, 8192]
+    _counter_csv(tmp_path / "f.csv", zip(names, [131072.0, 100.0, 1000.0]), grids)
+    _counter_csv(tmp_path / "w.csv", zip(names, [262144.0, 50.0, 400.0]), grids)
+    out = bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), min_blocks=2048)
+    assert out["dispatches"] == 1 and out["fetch_kib_per_launch"] == pytest.approx(1000.0)
+    out = bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+    assert out["dispatches"] == 2
 
 
 def test_summarize_counters_rejects_mismatched_runs(tmp_path):
