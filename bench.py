@@ -486,6 +486,15 @@ def workload_3d(nsteps=10, warm=10, speedup=True):
     if prof["cg_launches"]:
         out["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
         out["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]
+    if prof["cg_all_launches"]:
+        # the first sweep's launches on all 2.1 M rows (0.4 GB each): beyond the
+        # Infinity Cache, so these time HBM
+        ach = prof["cg_all_bytes"] / (prof["cg_all_ms"] * 1e-3) / 1e9
+        out["roofline_all_rows"] = {
+            "kernel": "k_cg_iter2", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "avg_launch_us": 1e3 * prof["cg_all_ms"] / prof["cg_all_launches"],
+            "bytes_per_launch": prof["cg_all_bytes"] / prof["cg_all_launches"],
+            "launches": prof["cg_all_launches"]}
     s.close()
     if speedup:
         el0 = nonadaptive_run(P, v0, w0, warm * P.dt, nsteps)

@@ -287,11 +287,17 @@ int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t 
  * still iterating: 8 per stored matrix value in their active rows (index
  * structure is storage overhead and not counted), plus per active row
  * 4 (active-list entry; absent when every row is active) + 6*8 reads
- * (x, p, r, w, s, dinv) + 5*8 writes (x, p, r, w, s). */
+ * (x, p, dinv and the three preconditioner-scaled CG vectors) + 5*8 writes
+ * (x, p and the three vectors). */
 typedef struct {
   int64_t cg_launches;
   double cg_ms;
   double cg_bytes;
+  /* the same over the launches on every row of the instances (no active */
+  /* list: the first sweep of each step), a subset of the above          */
+  int64_t cg_all_launches;
+  double cg_all_ms;
+  double cg_all_bytes;
 } sdc_profile_stats;
 
 /* Setup outcome: storage in use (1 CSR, 2 diagonal), diagonals per row in the

@@ -48,7 +48,8 @@ class StepStats(ctypes.Structure):
 
 
 class ProfileStats(ctypes.Structure):
-    _fields_ = [("cg_launches", c_int64), ("cg_ms", c_double), ("cg_bytes", c_double)]
+    _fields_ = [("cg_launches", c_int64), ("cg_ms", c_double), ("cg_bytes", c_double),
+                ("cg_all_launches", c_int64), ("cg_all_ms", c_double), ("cg_all_bytes", c_double)]
 
 
 class Info(ctypes.Structure):

@@ -93,6 +93,11 @@ int account_timing_at(sdc_ctx* ctx, const MapBuf& mb, int base, int budget, cons
     ctx->pst.cg_launches++;
     ctx->pst.cg_ms += t;
     ctx->pst.cg_bytes += bytes;
+    if (ident) {
+      ctx->pst.cg_all_launches++;
+      ctx->pst.cg_all_ms += t;
+      ctx->pst.cg_all_bytes += bytes;
+    }
   }
   return SDC_OK;
 }

@@ -375,9 +375,10 @@ __device__ inline void block_total(double (&v)[NV], double* sh /* [4 * NV] */) {
 // Memory round trips before the arithmetic: (1) the block record, the list
 // entry of the thread's row and the block's stop flag; (2) everything else
 // the iteration reads: the instance's partial sums and scalars from the
-// previous launch and the row's values and neighbour sums
-//   a_r = sum_k h_ik dinv_k r_k,  a_w = sum_k h_ik dinv_k w_k,  a_s = sum_k h_ik dinv_k s_k,
-// so that H u with u = dinv (r - alpha (w + beta s)) is a_r - alpha (a_w + beta a_s).
+// previous launch and the row's values and neighbour sums over the scaled vectors
+//   a_r = sum_k h_ik u_k,  a_w = sum_k h_ik w~_k,  a_s = sum_k h_ik s~_k,
+// so that H u of the new residual, u = dinv (r - alpha (w + beta s)), is
+// a_r - alpha (a_w + beta a_s).
 // Threads past the block's last row load row 0's values (in bounds) and
 // contribute zeros.
 // The arguments the first round trip needs come first, as plain pointers and
