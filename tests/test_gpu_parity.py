@@ -318,8 +318,11 @@ def test_errors_are_reported():
         s2.sweep()
 
 
-@pytest.mark.parametrize("P", [config1(n=33, theta=1e-7, n_steps=6), config2(n=8, theta=1e-7, n_steps=4),
-                               config4(n_inst=3, sizes=(12, 20), n_steps=5)], ids=["2d", "3d", "batch"])
+# sizes with map entries whose stencil stays inside the instance, so that the
+# all-rows iteration's two-rows-per-thread path is compared with CSR too
+@pytest.mark.parametrize("P", [config0(n=1100, theta=1e-6, n_steps=20), config1(n=33, theta=1e-7, n_steps=6),
+                               config2(n=16, theta=1e-7, n_steps=4), config4(n_inst=3, sizes=(12, 20), n_steps=5)],
+                         ids=["1d", "2d", "3d", "batch"])
 def test_diagonal_and_csr_storage_agree_bitwise(P):
     runs = []
     for fmt in (1, 2):
