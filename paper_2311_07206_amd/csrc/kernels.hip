@@ -451,7 +451,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   });
   const double si = FIRST ? 0.0 : s_in[i];
   const double p_old = FIRST ? 0.0 : p[i];
-  const double di = dinv[i], ui = u_in[i], wi = w_in[i], x_old = x[i];
+  const double ui = u_in[i], wi = w_in[i], x_old = x[i];
+  // the Jacobi factor from the row's diagonal, as the stored dinv was formed
+  const double di = 1.0 / hii;
   double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
   if (!FIRST) {
     const double* sc = scal_in + inst * kScal;
@@ -628,7 +630,6 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
     for (int q = 0; q < 2; ++q) {
       si[q] = FIRST ? 0.0 : s_in[ia + q];
       pold[q] = FIRST ? 0.0 : p[ia + q];
-      di[q] = dinv[ia + q];
       ui[q] = u_in[ia + q];
       wi[q] = w_in[ia + q];
       xold[q] = x[ia + q];
@@ -645,7 +646,6 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
       });
       si[q] = FIRST ? 0.0 : s_in[i];
       pold[q] = FIRST ? 0.0 : p[i];
-      di[q] = dinv[i];
       ui[q] = u_in[i];
       wi[q] = w_in[i];
       xold[q] = x[i];
@@ -711,6 +711,8 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
     if (t == 0) blk_done[L] = status;
     return;
   }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) di[q] = 1.0 / hii[q];   // as the stored dinv was formed
   double sp[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   double xn[2], pn[2], sn[2], un[2], wn[2];
 #pragma unroll
