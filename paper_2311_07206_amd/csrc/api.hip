@@ -210,21 +210,21 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
   const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
   const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
   const int budget = std::min(std::max(1, ctx->pred[pred_slot]) + 1, ctx->prm.cg_maxit + 1);
-  launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0], ctx->cg());
+  // the kernels record the outcome straight into the node's history slot
+  const CgState cg{ctx->hist_done + m * ni, ctx->hist_iters + m * ni, ctx->cg_blk_done};
+  launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0], cg);
   const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * (*ev_off + budget);
   for (int it = 0; mb.nblk > 0 && it < budget; ++it) {
     const int a = it & 1, o = a ^ 1;
     launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
                    ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
-                   rtol2, ctx->prm.cg_maxit, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
+                   rtol2, ctx->prm.cg_maxit, cg, mb.tot_if_large(ctx->cg_tot),
                    timed ? ctx->ev[2 * (*ev_off + it)] : nullptr,
                    timed ? ctx->ev[2 * (*ev_off + it) + 1] : nullptr);
   }
   HIPC(hipGetLastError());
   (*ev_budget)[m] = timed && mb.nblk > 0 ? budget : 0;
   if (timed) *ev_off += budget;
-  HIPC(hipMemcpyAsync(ctx->hist_done + m * ni, ctx->cg_done, ni * 4, hipMemcpyDeviceToDevice, ctx->stream));
-  HIPC(hipMemcpyAsync(ctx->hist_iters + m * ni, ctx->cg_iters, ni * 4, hipMemcpyDeviceToDevice, ctx->stream));
   return SDC_OK;
 }
 

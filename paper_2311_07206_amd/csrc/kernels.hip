@@ -602,7 +602,7 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
   const bool va = 2 * t < n_rows, vb = 2 * t + 1 < n_rows;
   const int ia = va ? rw.beg + 2 * t : 0, ib = vb ? rw.beg + 2 * t + 1 : 0;
   constexpr int h = S / 2;
-  const bool interior = (n_rows == kBlock) & (rw.beg + rw.off(0) >= rw.lo) & (rw.end - 1 + rw.off(S - 1) < rw.hi);
+  const bool interior = n_rows == kBlock && rw.beg + rw.off(0) >= rw.lo && rw.end - 1 + rw.off(S - 1) < rw.hi;
   double ar[2] = {0.0, 0.0}, aw[2] = {0.0, 0.0}, as[2] = {0.0, 0.0}, hii[2] = {0.0, 0.0};
   double si[2], pold[2], di[2], ui[2], wi[2], xold[2];
   if (interior) {
