@@ -123,3 +123,39 @@ def test_single_cell_lumped_limit_follows_membrane_ode():
     assert np.abs(v_end - ref.y[0, -1]).max() <= 1e-5
     assert np.abs(w - ref.y[1, -1]).max() <= 1e-5
     assert abs(v_end.mean() - 0.3) > 0.05
+
+
+def test_tetrahedra_are_conforming():
+    """Every triangle face of the tetrahedra is shared by two of them, except
+    the faces on the box boundary and on cell surfaces (where intra- and
+    extracellular nodes differ): a face seen once anywhere else would mean
+    that neighbouring hexahedra cut a grid face along different diagonals."""
+    nc, nr, nl = 2, 2, 1
+    P = config5(nc=nc, nr=nr, nl=nl, nx=5, ny=4, nz=4)
+    faces = {}
+    for t in P.elems:
+        for drop in range(4):
+            f = tuple(sorted(np.delete(t, drop)))
+            faces[f] = faces.get(f, 0) + 1
+    assert max(faces.values()) == 2
+    W, Hb, Db = box(nc, nr, nl)
+    planes = [{0.0, W}, {0.0, Hb}, {0.0, Db}]
+    for k, (n, size) in enumerate(((nc, L), (nr, H), (nl, D))):
+        for c in range(n):
+            planes[k] |= {GAP + c * (size + GAP), GAP + c * (size + GAP) + size}
+    n_single = 0
+    for f, n in faces.items():
+        if n == 2:
+            continue
+        n_single += 1
+        c = P.coords[list(f)]
+        flat = [k for k in range(3) if np.ptp(c[:, k]) < 1e-12]
+        assert len(flat) == 1
+        k = flat[0]
+        assert min(abs(c[0, k] - v) for v in planes[k]) < 1e-12
+    # two triangles per boundary grid rectangle; cell surfaces seen from both sides
+    nx, ny, nz = 5, 4, 4
+    NX, NY, NZ = nc * nx + 2, nr * ny + 2, nl * nz + 2
+    box_tris = 2 * 2 * ((NX - 1) * (NY - 1) + (NX - 1) * (NZ - 1) + (NY - 1) * (NZ - 1))
+    cell_tris = 2 * 2 * 2 * ((nx - 1) * (ny - 1) + (nx - 1) * (nz - 1) + (ny - 1) * (nz - 1)) * nc * nr * nl
+    assert n_single == box_tris + cell_tris
