@@ -549,14 +549,16 @@ def workload_emi(nsteps=3, warm=1, speedup=True, three_d=False):
 
 
 def cpu_baseline(P, v0, w0, t0, nsteps):
-    """The oracle on one core, a few steps from the timed region's start state."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+    """The oracle on one core, a few steps from the timed region's start state
+    (native thread pools limited to one thread for the timed run)."""
+    from threadpoolctl import threadpool_limits
+
     from oracle.sdc import build, run
     orc = build(P)
-    t = time.perf_counter()
-    _, _, log = run(orc, v0, w0, nsteps, P.K, P.stimuli, t0=t0)
-    el = time.perf_counter() - t
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        _, _, log = run(orc, v0, w0, nsteps, P.K, P.stimuli, t0=t0)
+        el = time.perf_counter() - t
     dof_sweeps = sum(info["n_active"] for step in log for info in step)
     return {"value": dof_sweeps / el, "unit": "active dof-sweeps/s", "cores": 1, "kind": "oracle",
             "sample": f"{nsteps} oracle steps of the same workload from t={t0:.1f} ms ({el:.1f} s)"}
