@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 from oracle.assembly import lumped_mass, stiffness  # noqa: E402
 from oracle.pcg import jacobi_pcg  # noqa: E402
 from oracle.sdc import build, run  # noqa: E402
-from workloads import config2, config3, config4  # noqa: E402
+from workloads import config1, config2, config3, config4  # noqa: E402
 
 DEV = torch.device("cuda", 0)
 
@@ -133,3 +133,49 @@ def test_emi_full_size_assembly_and_restricted_pcg():
         x, it = s.solve(m, torch.tensor(first, dtype=torch.int32, device=DEV), torch.tensor(b, device=DEV))
         xo, ito = jacobi_pcg(orc.H[m], b, first, P.cg_rtol, maxit=P.cg_maxit)
         assert rel(x.cpu().numpy(), xo) < 1e-11
+
+
+def _full_2d_step(P, s, n_steps=1, drop=False):
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    sets, drops = [], []
+    for n in range(n_steps):
+        s.begin_step(v, w, n * P.dt)
+        step_sets = [None]
+        for k in range(P.K):
+            s.sweep()
+            if k == 0 and drop:
+                drops.append(s.drop_tolerance())
+            if k + 1 < P.K:
+                step_sets.append(s.active().cpu().numpy().astype(np.int64))
+        s.end_step(v, w)
+        sets.append(step_sets)
+    return v.cpu().numpy(), w.cpu().numpy(), sets, drops
+
+
+@pytest.mark.parametrize("option", ["linearized", "apriori"])
+def test_2d_full_size_options_match_oracle(option):
+    """The 512^2 workload (262,144 dofs), two steps from the stimulus, with the
+    paper's linearized scheme or with the a-priori drop tolerance (TOL 1e-6,
+    rho 0.3, all K sweeps): the oracle replays the GPU's sets."""
+    from oracle.sdc import apply_stimuli
+    P = config1()
+    if option == "linearized":
+        s = _solver(P, scheme="linearized")
+        orc = build(P, scheme="linearized")
+    else:
+        s = _solver(P, tol_sdc=1e-6, rho=0.3, K_min=P.K, drop="apriori")
+        orc = build(P, tol_sdc=1e-6, rho=0.3, K_min=P.K, drop="apriori")
+    print(f"[2d full {option}] GPU", flush=True)
+    gv, gw, sets, drops = _full_2d_step(P, s, n_steps=2, drop=option == "apriori")
+    v, w = P.v_init.copy(), P.w_init.copy()
+    for n in range(2):
+        print(f"[2d full {option}] oracle step {n}", flush=True)
+        apply_stimuli(v, n * P.dt, P.dt, P.stimuli)
+        v, w, infos = orc.step(v, w, P.K, idx_replay=sets[n])
+        if option == "apriori":
+            assert np.array_equal(drops[n]["r"], infos[0]["drop_r"])
+            assert np.allclose(drops[n]["tol_drop"], infos[0]["drop_tol"], rtol=1e-10, atol=0)
+    assert any(st.size < P.N for steps in sets for st in steps[1:])
+    print(f"   rel v {rel(gv, v):.2e} w {rel(gw, w):.2e}", flush=True)
+    assert rel(gv, v) < 1e-10 and rel(gw, w) < 1e-10
