@@ -88,9 +88,14 @@ class EmiSDC:
 
     ``direct=True`` solves the restricted systems with a sparse LU instead of
     Jacobi-PCG (same solution to rounding; for extreme test parameters).
+
+    Optional energy-norm termination (Sec. 3.2, stated for the abstract form
+    of both models): with tol_sdc > 0 the step ends after the first sweep k
+    (k + 1 >= K_min) with  sum_m du_m^T H_m du_m <= ((1 - rho) / rho * tol_sdc)^2.
     """
 
-    def __init__(self, model, M, dt, theta, cg_rtol=1e-12, cg_maxit=20000, direct=False):
+    def __init__(self, model, M, dt, theta, cg_rtol=1e-12, cg_maxit=20000, direct=False, tol_sdc=0.0,
+                 rho=0.05, K_min=1):
         self.model = model
         self.col = Collocation(M)
         self.M = M
@@ -99,7 +104,14 @@ class EmiSDC:
         self.cg_rtol = cg_rtol
         self.cg_maxit = cg_maxit
         self.direct = direct
+        self.tol_sdc = float(tol_sdc)
+        self.rho = float(rho)
+        self.K_min = int(K_min)
         self.H = [(model.M + self.dt * self.col.QI[m, m] * model.A).tocsr() for m in range(M)]
+
+    def energy(self, du):
+        """sum_m du_m^T H_m du_m."""
+        return float(sum(du[m] @ (self.H[m] @ du[m]) for m in range(self.M)))
 
     def spread(self, u0, w0_sites):
         M, S = self.M, self.model.S
@@ -172,16 +184,22 @@ class EmiSDC:
         st = self.spread(u0, w0_sites)
         idx = np.arange(self.model.N)
         infos = []
+        thr = ((1.0 - self.rho) / self.rho * self.tol_sdc) ** 2
         for k in range(K):
             if idx_replay is not None and k > 0 and idx_replay[k] is not None:
                 idx = np.asarray(idx_replay[k], dtype=np.int64)
             idx, info = self.sweep(st, idx)
             infos.append(info)
+            if self.tol_sdc > 0.0:
+                info["energy"] = self.energy(info["du"])
+                if k + 1 >= self.K_min and info["energy"] <= thr:
+                    break
         return st["u"][-1].copy(), st["w"][-1].copy(), infos
 
 
-def build(P, direct=False):
-    return EmiSDC(EMI(P), P.M, P.dt, P.theta, P.cg_rtol, P.cg_maxit, direct=direct)
+def build(P, direct=False, tol_sdc=0.0, rho=0.05, K_min=1):
+    return EmiSDC(EMI(P), P.M, P.dt, P.theta, P.cg_rtol, P.cg_maxit, direct=direct, tol_sdc=tol_sdc, rho=rho,
+                  K_min=K_min)
 
 
 def run(sdc, u, w_sites, n_steps, K, stimuli=(), t0=0.0, idx_replay=None):

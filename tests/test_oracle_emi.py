@@ -153,3 +153,39 @@ def test_adaptive_run_tracks_nonadaptive():
     un, wn, _ = run(build(P0), u0, w0, 4, P0.K, P0.stimuli)
     assert any(info["n_active"] < P.N for step in loga for info in step)
     assert np.abs(ua - un).max() <= 1e-5 * np.abs(un).max()
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-6])
+def test_energy_termination_meets_its_tolerance(tol):
+    """Sec. 3.2 for the cell-by-cell model: with rho at least the actual
+    contraction, the terminated step's last node lies within tol of the
+    collocation solution in the H norm (the gauge mode of the potentials
+    carries no energy: H annihilates it up to the weak Robin term)."""
+    P = config3(nc=2, nr=1, nx=3, ny=3, M=3, dt=0.05, theta=0.0)
+    u0 = np.zeros(P.N)
+    u0[P.stimuli[0][1]] = 1.0
+    w0 = np.full(len(P.mem_intra), 0.05)
+    sdc = build(P, direct=True, tol_sdc=tol, rho=0.6)
+    Uc, _ = collocation_solution(sdc.model, P.M, P.dt, u0, w0)
+    u_end, _, infos = sdc.step(u0, w0, 60)
+    assert 1 < len(infos) < 60
+    e = u_end - Uc[-1]
+    assert np.sqrt(e @ (sdc.H[P.M - 1] @ e)) <= tol
+    thr = ((1 - 0.6) / 0.6 * tol) ** 2
+    assert infos[-2]["energy"] > thr >= infos[-1]["energy"]
+
+
+def test_energy_termination_extremes_equal_fixed_sweep_counts():
+    P = small(theta=1e-8)
+    u0 = np.zeros(P.N)
+    u0[P.stimuli[0][1]] = 1.0
+    w0 = np.zeros(len(P.mem_intra))
+    fixed = build(P)
+    u4, w4, _ = fixed.step(u0, w0, 4)
+    u2, w2, _ = fixed.step(u0, w0, 2)
+    tiny = build(P, tol_sdc=1e-300)
+    ut, wt, it = tiny.step(u0, w0, 4)
+    assert len(it) == 4 and np.array_equal(ut, u4) and np.array_equal(wt, w4)
+    huge = build(P, tol_sdc=1e10, K_min=2)
+    uh, wh, ih = huge.step(u0, w0, 4)
+    assert len(ih) == 2 and np.array_equal(uh, u2) and np.array_equal(wh, w2)
