@@ -133,3 +133,37 @@ def test_emi_unavailable_calls_are_rejected():
     s = _solver(P)
     with pytest.raises(SDCError, match="STATE"):
         s.set_coefficients(np.ones(P.N), None)
+
+
+def test_emi_energy_termination_matches_oracle():
+    """Sec. 3.2 on the cell-by-cell model: the library decides on the device
+    after each sweep; the oracle, replaying the GPU's sets, takes the same
+    number of sweeps per step and reaches the same state."""
+    K, tol, rho = 8, 1e-5, 0.3
+    P = small(theta=1e-7)
+    s = _solver(P, K=K, tol_sdc=tol, rho=rho, K_min=1)
+    u = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    n_steps, sets, counts = 3, [], []
+    for n in range(n_steps):
+        s.begin_step(u, w, n * P.dt)
+        step_sets = [None]
+        for k in range(K):
+            st = s.sweep()
+            if st["n_stopped"] == 1 or k + 1 == K:
+                break
+            step_sets.append(s.active().cpu().numpy().astype(np.int64))
+        s.end_step(u, w)
+        sets.append(step_sets)
+        counts.append(k + 1)
+    print(f"[emi termination] sweeps per step {counts}", flush=True)
+    assert any(c < K for c in counts)
+    ug, wg = u.cpu().numpy(), w.cpu().numpy()
+    orc = build(P, tol_sdc=tol, rho=rho, K_min=1)
+    uo, wo, log = run(orc, P.v_init, P.w_init[P.mem_intra], n_steps, K, P.stimuli, idx_replay=sets)
+    assert [len(st) for st in log] == counts
+    si, se = P.mem_intra, P.mem_extra
+    vg, vo = ug[si] - ug[se], uo[si] - uo[se]
+    assert np.linalg.norm(vg - vo) <= 1e-10 * np.linalg.norm(vo)
+    assert np.abs(wg[si] - wo).max() <= 1e-10 * max(np.abs(wo).max(), 1e-3)
+    assert np.linalg.norm(mean_free(ug) - mean_free(uo)) <= 1e-10 * np.linalg.norm(uo)
