@@ -4,7 +4,7 @@ Gauss-Seidel with implicit dR/dw) against the oracle.
 
 The library rewrites the diagonals of H_m on each sweep's rows; the oracle
 assembles H_m^k afresh.  States within 1e-10 relative with the oracle
-replaying the GPU's active sets (1D, 2D ragged, batched, with the a-priori
+replaying the GPU's active sets (1D, 2D ragged, 3D, batched, with the a-priori
 drop tolerance and the energy termination); diagonal storage equals CSR
 storage bitwise.
 """
@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from oracle.sdc import apply_stimuli, build  # noqa: E402
-from workloads import config0, config1, config3, config4  # noqa: E402
+from workloads import config0, config1, config2, config3, config4  # noqa: E402
 
 DEV = torch.device("cuda", 0)
 
@@ -62,12 +62,14 @@ def _run_oracle(P, orc, n_steps, K, sets):
     return v, w
 
 
-@pytest.mark.parametrize("case", ["1d", "2d", "batched"])
+@pytest.mark.parametrize("case", ["1d", "2d", "3d", "batched"])
 def test_linearized_scheme_matches_oracle(case):
     if case == "1d":
         P, n_steps = config0(theta=1e-6), 30
     elif case == "2d":
         P, n_steps = config1(n=37, theta=1e-7, n_steps=3), 3
+    elif case == "3d":
+        P, n_steps = config2(n=16, theta=1e-7, n_steps=2), 2
     else:
         P, n_steps = config4(n_inst=3, sizes=(10, 18), n_steps=2), 2
     K = P.K
