@@ -133,6 +133,8 @@ def parse():
                     help="skip the non-adaptive (theta = 0) runs over the same steps")
     ap.add_argument("--no-linearized", action="store_true",
                     help="skip the 512x512 run with the paper's linearized basic scheme")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the time-per-sweep curve over front-shell active sets")
     ap.add_argument("--profile-warmup", action="store_true",
                     help="account CG kernel bytes from the first step (matches counter runs)")
     ap.add_argument("--calib", action="store_true",
@@ -315,9 +317,100 @@ def main():
     if not args.no_emi:
         out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
         out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
+    if not args.no_latency:
+        out["latency_curve"] = latency_curve(P)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
+
+
+def front_shell_masks(coords, elems, v, densities, level=0.5):
+    """Synthetic active sets shaped like a front's shell: one ascending row
+    list per density (fraction of the rows, at least one row).  The nodes at
+    either end of a mesh edge across which v crosses `level` rank first
+    (distance 0), then every other node by its Euclidean distance to the
+    nearest of them, ties by index; without a crossing the node whose v is
+    closest to `level` is the seed.  The lists are nested."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    e = np.asarray(elems)
+    nv = e.shape[1]
+    a = np.concatenate([e[:, i] for i in range(nv) for j in range(i + 1, nv)])
+    b = np.concatenate([e[:, j] for i in range(nv) for j in range(i + 1, nv)])
+    cross = (v[a] - level) * (v[b] - level) < 0
+    seeds = np.unique(np.concatenate([a[cross], b[cross]]))
+    if seeds.size == 0:
+        seeds = np.array([int(np.argmin(np.abs(v - level)))])
+    dist, _ = cKDTree(coords[seeds]).query(coords)
+    order = np.lexsort((np.arange(v.size), dist))
+    return [np.sort(order[:max(1, int(round(d * v.size)))]).astype(np.int32) for d in densities]
+
+
+def latency_curve(P, snapshots=(10.0, 50.0, 150.0), densities=(1.0, 0.5, 0.1, 0.01, 0.001), reps=5):
+    """Time per sweep against the size of its active set.  The run goes from
+    the initial state (sets chosen by the drop tolerance) to each snapshot
+    time; there, sweeps 1..K-1 of one step are pinned to front-shell masks of
+    the given densities, and the step is repeated from the snapshot state,
+    once untimed and `reps` times timed.  A sweep's time is its stream time
+    by events (its launches, the next set's mapping and the host
+    synchronisation); a second set of `reps` steps with kernel timing on
+    gives the mean duration of the CG iteration launches on the pinned sets."""
+    import numpy as np
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    s = Solver.from_problem(P)
+    v = torch.tensor(P.v_init, device=dev)
+    w = torch.tensor(P.w_init, device=dev)
+    n_done, out = 0, []
+    redone0 = s.info()["redone_steps"]
+    for ts in snapshots:
+        while n_done < int(round(ts / P.dt)):
+            s.step(v, w, n_done * P.dt)
+            n_done += 1
+        t_snap = n_done * P.dt
+        sel = s.step(v.clone(), w.clone(), t_snap, stats=True)
+        masks = front_shell_masks(P.coords, P.elems, v.cpu().numpy(), densities)
+        rows = []
+        for d, idx in zip(densities, masks):
+            pin = torch.tensor(idx, dtype=torch.int32, device=dev)
+            for k in range(1, P.K):
+                s.set_active(k, pin)
+            ms, first, iters, nbytes = [], [], [], []
+            for r in range(reps + 1):
+                lg = s.step(v.clone(), w.clone(), t_snap, stats=True)
+                if r == 0:
+                    continue
+                first.append(lg[0]["ms"])
+                for st in lg[1:]:
+                    ms.append(st["ms"])
+                    iters.append(sum(st["cg_iters_max"]))
+                    nbytes.append(sweep_bytes(st, P.M, False))
+            s.profile(True)
+            for r in range(reps):
+                s.step(v.clone(), w.clone(), t_snap)
+            torch.cuda.synchronize()
+            pr = s.profile_read()
+            s.profile(False)
+            s.set_active(0, None)
+            nl = pr["cg_launches"] - pr["cg_all_launches"]
+            cg_ms, cg_b = pr["cg_ms"] - pr["cg_all_ms"], pr["cg_bytes"] - pr["cg_all_bytes"]
+            row = {"density": d, "n_active": int(idx.size), "ms_per_sweep": float(np.median(ms)),
+                   "cg_iterations_per_sweep": float(np.mean(iters)),
+                   "sweep_us_per_cg_iteration": 1e3 * float(np.mean(ms)) / max(float(np.mean(iters)), 1.0),
+                   "algorithmic_GBps": float(np.mean(nbytes)) / float(np.mean(ms)) / 1e6,
+                   "first_sweep_ms": float(np.median(first))}
+            if nl > 0:
+                row["cg_launch_us"] = 1e3 * cg_ms / nl
+                row["cg_launch_GBps"] = cg_b / (cg_ms * 1e-3) / 1e9
+            rows.append(row)
+        out.append({"t_ms": t_snap, "selected_n_active": [st["n_active"] for st in sel], "masks": rows})
+    redone = s.info()["redone_steps"] - redone0
+    s.close()
+    return {"workload": f"2D monodomain {int(round(P.N ** 0.5))}x{int(round(P.N ** 0.5))}, sweeps 1..{P.K - 1} "
+                        f"pinned to front-shell masks (level v = 0.5)",
+            "snapshots": out, "redone_steps": redone}
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):
@@ -561,7 +654,20 @@ def cpu_baseline(P, v0, w0, t0, nsteps):
         el = time.perf_counter() - t
     dof_sweeps = sum(info["n_active"] for step in log for info in step)
     return {"value": dof_sweeps / el, "unit": "active dof-sweeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} oracle steps of the same workload from t={t0:.1f} ms ({el:.1f} s)"}
+            "sample": f"{nsteps} oracle steps of the same workload from t={t0:.1f} ms ({el:.1f} s)",
+            "host_cpu": cpu_model(), "host_cpu_count": os.cpu_count()}
+
+
+def cpu_model():
+    """The host CPU's model name as /proc/cpuinfo gives it (None elsewhere)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -112,6 +112,10 @@ typedef struct {
   double energy;                       /* sum_inst sum_m dv_m^T H_m dv_m (only   */
                                        /* with the energy-norm termination on)   */
   int32_t n_stopped;                   /* instances stopped after this sweep     */
+  double ms;                           /* stream time of the sweep, by events:   */
+                                       /* from its first launch to its return    */
+                                       /* (selection of the next set and the     */
+                                       /* host synchronisation included)         */
 } sdc_sweep_stats;
 
 typedef struct {

@@ -31,7 +31,8 @@ class Params(ctypes.Structure):
 class SweepStats(ctypes.Structure):
     _fields_ = [("n_active", c_int64), ("nnz_active", c_int64), ("n_next", c_int64),
                 ("cg_iters_max", c_int32 * MAX_NODES), ("cg_row_iters", c_int64 * MAX_NODES),
-                ("cg_nnz_iters", c_int64 * MAX_NODES), ("energy", c_double), ("n_stopped", c_int32)]
+                ("cg_nnz_iters", c_int64 * MAX_NODES), ("energy", c_double), ("n_stopped", c_int32),
+                ("ms", c_double)]
 
     def as_dict(self, M):
         return {
@@ -39,7 +40,7 @@ class SweepStats(ctypes.Structure):
             "cg_iters_max": list(self.cg_iters_max[:M]),
             "cg_row_iters": list(self.cg_row_iters[:M]),
             "cg_nnz_iters": list(self.cg_nnz_iters[:M]),
-            "energy": self.energy, "n_stopped": self.n_stopped,
+            "energy": self.energy, "n_stopped": self.n_stopped, "ms": self.ms,
         }
 
 

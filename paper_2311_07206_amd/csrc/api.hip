@@ -245,6 +245,9 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     std::memset(st, 0, sizeof *st);
     st->n_active = mb.rows;
     for (int i = 0; i < ni; ++i) st->nnz_active += mb.nnz[i];
+    for (auto& e : ctx->sweep_ev)
+      if (!e) HIPC(hipEventCreate(&e));
+    HIPC(hipEventRecord(ctx->sweep_ev[0], ctx->stream));
   }
   const EmiArgs emi = ctx->emi_args();
   const bool lin = ctx->linearized();
@@ -379,6 +382,11 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
         st->cg_nnz_iters[m] += static_cast<int64_t>(iters[m][i]) * nnz[i];
       }
     st->n_next = ctx->curmap().rows;
+    float ms = 0.0f;
+    HIPC(hipEventRecord(ctx->sweep_ev[1], ctx->stream));
+    HIPC(hipEventSynchronize(ctx->sweep_ev[1]));
+    HIPC(hipEventElapsedTime(&ms, ctx->sweep_ev[0], ctx->sweep_ev[1]));
+    st->ms = ms;
   }
   ctx->k = next;
   return SDC_OK;
@@ -607,6 +615,7 @@ void sdc_destroy(sdc_ctx* ctx) {
   for (auto& s : ctx->stims) (void)hipFree(s.nodes);
   for (auto* p : ctx->pin) if (p) (void)hipFree(p);
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
+  for (auto e : ctx->sweep_ev) if (e) (void)hipEventDestroy(e);
   if (ctx->h_i32) (void)hipHostFree(ctx->h_i32);
   if (ctx->h_i64) (void)hipHostFree(ctx->h_i64);
   if (ctx->h_term) (void)hipHostFree(ctx->h_term);

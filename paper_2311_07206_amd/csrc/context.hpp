@@ -175,6 +175,7 @@ struct sdc_ctx {
   // kernel timing (bench only)
   bool prof = false;
   std::vector<hipEvent_t> ev;   // 2 per CG iteration launch
+  hipEvent_t sweep_ev[2] = {nullptr, nullptr};   // around a sweep whose statistics are asked for
   sdc_profile_stats pst{};
   std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
 

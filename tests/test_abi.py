@@ -75,3 +75,39 @@ def test_library_collocation_rejects_bad_M(lib):
     f.restype = ctypes.c_int32
     assert f(ctypes.c_int32(0), None, None, None, None) != 0
     assert f(ctypes.c_int32(7), None, None, None, None) != 0
+
+
+# C structures of the header and their ctypes mirrors in the binding
+_STRUCTS = {"sdc_params": "Params", "sdc_sweep_stats": "SweepStats", "sdc_step_stats": "StepStats",
+            "sdc_emi": "Emi", "sdc_profile_stats": "ProfileStats", "sdc_info": "Info"}
+
+
+def test_binding_structures_match_the_header_layout(root, tmp_path):
+    """Size and every field offset of each structure, as the C compiler lays
+    them out from include/sdc.h, equal the binding's ctypes layout."""
+    import shutil
+    import subprocess
+    from paper_2311_07206_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "sdc.h"', "int main(void) {"]
+    for cname, pyname in _STRUCTS.items():
+        lines.append(f'  printf("{pyname} . %zu\\n", sizeof({cname}));')
+        for field, _ in getattr(_lib, pyname)._fields_:
+            lines.append(f'  printf("{pyname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    n_checked = 0
+    for line in filter(None, out):
+        pyname, field, value = line.split()
+        cls = getattr(_lib, pyname)
+        got = ctypes.sizeof(cls) if field == "." else getattr(cls, field).offset
+        assert got == int(value), (pyname, field, got, value)
+        n_checked += 1
+    assert n_checked == sum(len(getattr(_lib, p)._fields_) + 1 for p in _STRUCTS.values())

@@ -111,3 +111,29 @@ def test_committed_counters_name_the_current_kernel_source():
     committed; a kernel edit without new counters makes `traffic` null."""
     text = open(bench.COUNTERS).read()
     assert "kernels.hip sha256:" in text and "measured bytes per launch:" in text
+
+
+def test_front_shell_masks_are_nested_shells_around_the_level_crossing():
+    import numpy as np
+    from workloads import meshes
+    coords, elems = meshes.square_tri_mesh(21, 21, 1.0, 1.0)
+    N = coords.shape[0]
+    v = (coords[:, 0] < 0.42).astype(float)
+    dens = (1.0, 0.5, 0.1, 1e-3)
+    masks = bench.front_shell_masks(coords, elems, v, dens)
+    assert [m.size for m in masks] == [max(1, round(d * N)) for d in dens]
+    for m in masks:
+        assert m.dtype == np.int32 and np.all(np.diff(m) > 0)
+    for big, small in zip(masks, masks[1:]):
+        assert np.isin(small, big).all()
+    # the edges v crosses 0.5 on join the columns x = 0.40 and x = 0.45 (spacing 0.05)
+    seeds = np.nonzero(np.isclose(coords[:, 0], 0.40) | np.isclose(coords[:, 0], 0.45))[0]
+    assert np.isin(seeds, masks[2]).all()
+    x = coords[masks[2], 0]
+    assert x.min() >= 0.35 - 1e-12 and x.max() <= 0.50 + 1e-12
+    assert masks[3][0] == seeds.min()
+    # no crossing: the shells grow from the node whose value is nearest the level
+    flat = bench.front_shell_masks(coords, elems, np.zeros(N), (1e-3, 0.05))
+    assert flat[0].tolist() == [0]
+    d = np.linalg.norm(coords[flat[1]] - coords[0], axis=1)
+    assert d.max() <= np.sort(np.linalg.norm(coords - coords[0], axis=1))[flat[1].size - 1] + 1e-12

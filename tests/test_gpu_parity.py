@@ -226,6 +226,29 @@ def test_pinned_all_rows_equals_nonadaptive_bitwise():
     s.set_active(0, None)
 
 
+@pytest.mark.parametrize("density", [0.2, 0.01])
+def test_pinned_front_shell_sets_match_oracle(density):
+    """Sweeps 1..K-1 pinned to a front-shell mask (the sets the sweep latency
+    measurement times) compute what the oracle computes on those sets."""
+    import bench
+    P = config1(n=41, theta=1e-7, n_steps=3)
+    v = P.v_init.copy()
+    apply_stimuli(v, 0.0, P.dt, P.stimuli)
+    mask = bench.front_shell_masks(P.coords, P.elems, v, (density,))[0]
+    assert 0 < mask.size < P.N
+    s = _solver(P)
+    pin = torch.tensor(mask, dtype=torch.int32, device=DEV)
+    for k in range(1, P.K):
+        s.set_active(k, pin)
+    gv, gw, sets, _, _ = gpu_run(P, P.n_steps, s=s)
+    s.set_active(0, None)
+    assert all(np.array_equal(st, mask) for step in sets for st in step[1:])
+    ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli,
+                    idx_replay=[[None] + [mask.astype(np.int64)] * (P.K - 1)] * P.n_steps)
+    print(f"[pinned shell] density {density}: {mask.size} rows, rel v {rel(gv, ov):.2e}", flush=True)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+
+
 def test_ragged_2d_adaptive_run():
     P = config1(n=23, theta=1e-7, n_steps=12)
     gv, gw, sets, _, _ = gpu_run(P, P.n_steps)
