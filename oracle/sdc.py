@@ -31,6 +31,14 @@ taken (the bound of Thm. 1 is in L-infinity over the step); the gating
 correction does not enter the rule; theta <= 0 keeps every row (the
 non-adaptive method); every step starts with all rows active and with the
 collocation values spread from the step's initial state.
+
+Optionally (``run(..., first=FirstSweepSubset(...))``) a step's first sweep
+takes a heuristic a-priori set instead of all rows; the paper names such a
+subset (Sec. 6) without fixing a rule, and the one here is a reading: the
+set the previous step carried after its first sweep and this step's
+stimulated rows, grown by rings of mesh neighbours, with a full first sweep
+on the run's first step and on every full_every-th step.  Rows outside the
+set keep their spread values (no change over the step).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -306,6 +314,7 @@ class SDC:
         infos = []
         stopped = np.zeros(self.n_inst, dtype=bool)
         theta = None
+        self.carried = None
         for k in range(K):
             if idx_replay is not None and idx_replay[k] is not None:
                 idx = np.asarray(idx_replay[k], dtype=np.int64)
@@ -320,6 +329,12 @@ class SDC:
                 if k + 1 >= self.K_min:
                     stopped |= e <= ((1.0 - self.rho) / self.rho * self.tol_sdc) ** 2
                 nxt = nxt[~stopped[self.inst_of[nxt]]]
+            if k == 0:
+                # the set the step carries: that of its second sweep (its
+                # first sweep's own set when the step has one sweep)
+                self.carried = nxt if K > 1 else idx
+                if K > 1 and idx_replay is not None and len(idx_replay) > 1 and idx_replay[1] is not None:
+                    self.carried = np.asarray(idx_replay[1], dtype=np.int64)
             if not keep:
                 info.pop("dv")
                 info.pop("amax")
@@ -328,6 +343,49 @@ class SDC:
             if stopped.all():
                 break
         return st["v"][-1].copy(), st["w"][-1].copy(), infos
+
+
+def mesh_adjacency(elems, N):
+    """Pattern of the P1 matrices: rows i and j are adjacent when the two
+    vertices share a simplex (every row is adjacent to itself)."""
+    e = np.asarray(elems, dtype=np.int64)
+    nv = e.shape[1]
+    r = np.repeat(e, nv, axis=1).ravel()
+    c = np.tile(e, (1, nv)).ravel()
+    return sp.csr_matrix((np.ones(r.size), (r, c)), shape=(N, N))
+
+
+def first_sweep_set(adj, carried, forced, rings):
+    """Heuristic a-priori set of a step's first sweep.  The paper (Sec. 6)
+    names a heuristic a-priori subset for the first sweep as a way past the
+    full first sweep, which bounds the speedup, without fixing one; the rule
+    here is a reading: the rows the previous step carried after its first
+    sweep, with the rows a stimulus overwrote at this step's start, grown
+    `rings` times by all their mesh neighbours.  Ascending rows."""
+    mark = np.zeros(adj.shape[0], dtype=bool)
+    mark[np.asarray(carried, dtype=np.int64)] = True
+    mark[np.asarray(forced, dtype=np.int64)] = True
+    for _ in range(rings):
+        mark = mark | (adj @ mark.astype(np.float64) > 0.0)
+    return np.nonzero(mark)[0]
+
+
+class FirstSweepSubset:
+    """When a step's first sweep uses the heuristic set: not on the first
+    step of a run (nothing is carried yet) and not on every `full_every`-th
+    step counted from it (full_every <= 0: only the first), which take all
+    rows."""
+
+    def __init__(self, adj, rings, full_every):
+        if rings < 1:
+            raise ValueError("rings must be >= 1")
+        self.adj, self.rings, self.full_every = adj, int(rings), int(full_every)
+
+    def rows(self, n, carried, forced):
+        full = n == 0 if self.full_every <= 0 else n % self.full_every == 0
+        if full or carried is None:
+            return None
+        return first_sweep_set(self.adj, carried, forced, self.rings)
 
 
 def select(idx, amax, theta):
@@ -345,17 +403,31 @@ def apply_stimuli(v, t, dt, stimuli):
     return v
 
 
-def run(sdc, v, w, n_steps, K, stimuli=(), t0=0.0, idx_replay=None, cg_replay=None):
-    """Advance n_steps; returns (v, w, per-step infos)."""
+def stimulus_nodes(t, dt, stimuli):
+    """Node lists of the stimuli that apply at the step starting at t."""
+    return [np.asarray(nodes, dtype=np.int64) for t_on, nodes, _ in stimuli
+            if t - 1e-9 * dt <= t_on < t + dt - 1e-9 * dt]
+
+
+def run(sdc, v, w, n_steps, K, stimuli=(), t0=0.0, idx_replay=None, cg_replay=None, first=None):
+    """Advance n_steps; returns (v, w, per-step infos).  first: None (every
+    first sweep on all rows) or a FirstSweepSubset; a replayed first-sweep
+    set takes precedence over it."""
     v = np.array(v, dtype=np.float64)
     w = np.array(w, dtype=np.float64)
     log = []
+    carried = None
     for n in range(n_steps):
         t = t0 + n * sdc.dt
         apply_stimuli(v, t, sdc.dt, stimuli)
-        v, w, infos = sdc.step(v, w, K,
-                               None if idx_replay is None else idx_replay[n],
-                               None if cg_replay is None else cg_replay[n])
+        replay = None if idx_replay is None else idx_replay[n]
+        if first is not None and (replay is None or replay[0] is None):
+            forced = stimulus_nodes(t, sdc.dt, stimuli)
+            rows = first.rows(n, carried, np.concatenate(forced) if forced else np.zeros(0, np.int64))
+            if rows is not None:
+                replay = [rows] + ([None] * (K - 1) if replay is None else list(replay[1:]))
+        v, w, infos = sdc.step(v, w, K, replay, None if cg_replay is None else cg_replay[n])
+        carried = sdc.carried
         log.append(infos)
     return v, w, log
 
