@@ -99,6 +99,19 @@ typedef struct {
   /* not with the reverse pass; sdc_solve then uses the diagonals of the     */
   /* last sweep on its rows.                                                 */
   int32_t scheme;
+  /* Rows of each step's first sweep.  0: all rows (the paper's method).     */
+  /* R >= 1: a heuristic a-priori set (paper Sec. 6 names one for the first  */
+  /* sweep without fixing a rule; this is the library's): each step carries  */
+  /* the set its second sweep uses (its first sweep's own set when K = 1);   */
+  /* a later step's first sweep takes that set and the rows a stimulus       */
+  /* overwrites at its start, grown R times by their mesh neighbours         */
+  /* (vertices sharing a simplex).  Rows outside keep the step's start       */
+  /* values.  All rows on the first step after setup or after               */
+  /* sdc_set_active(ctx, -1, ...), and on every first_full_every-th step     */
+  /* counted from there (<= 0: never again).  Monodomain only, not with the */
+  /* reverse pass.                                                           */
+  int32_t first_rings;
+  int32_t first_full_every;
 } sdc_params;
 
 /* Per-sweep statistics (sums over instances unless stated). */
@@ -223,9 +236,11 @@ int sdc_get_node(sdc_ctx* ctx, int32_t m, double* v_m, double* w_m);
  * with room for N entries (may be NULL to query only), *n receives its length. */
 int sdc_get_active(sdc_ctx* ctx, int32_t* idx, int64_t* n);
 
-/* Pin the active set of sweep `sweep` (1..K-1; sweep 0 always uses all rows)
- * for all following steps, replacing the selection rule there: idx is a
- * device int32[n] ascending list (copied).  sweep < 0 clears every pin. */
+/* Pin the active set of sweep `sweep` (1..K-1; sweep 0 uses all rows, or
+ * the heuristic set of first_rings) for all following steps, replacing the
+ * selection rule there: idx is a device int32[n] ascending list (copied).
+ * sweep < 0 clears every pin and the set carried for the next first sweep
+ * (restarting the step count of first_full_every). */
 int sdc_set_active(sdc_ctx* ctx, int32_t sweep, const int32_t* idx, int64_t n);
 
 /* Reverse-mode step (adjoint of sdc_step with every sweep's active set held

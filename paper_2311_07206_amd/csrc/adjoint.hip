@@ -25,6 +25,8 @@ int adjoint_setup(sdc_ctx* ctx) {
     return fail(ctx, SDC_ERR_STATE, "the reverse pass needs a fixed sweep count (no energy-norm termination)");
   if (ctx->linearized())
     return fail(ctx, SDC_ERR_STATE, "the reverse pass differentiates the implicit-explicit scheme (scheme 0)");
+  if (ctx->first_subset())
+    return fail(ctx, SDC_ERR_STATE, "the reverse pass needs first sweeps on all rows (first_rings = 0)");
   auto& A = ctx->adj;
   if (A.ready) return SDC_OK;
   const int nv = ctx->dim + 1, np = nv * ctx->dim / 2;

@@ -362,6 +362,17 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
       }
     }
   }
+  if (ctx->first_subset() && ctx->k == 0) {
+    // the set this step carries to the next one's first sweep: that of the
+    // second sweep (or, without a selection, this sweep's own)
+    if (ctx->cur < 0) {
+      ctx->carry_n = -1;
+    } else {
+      launch_map_rows(ctx->stream, ctx->curmap().dev(), ctx->carry_list);
+      HIPC(hipGetLastError());
+      ctx->carry_n = ctx->curmap().rows;
+    }
+  }
   if (ctx->terminate()) {
     if (!synced && !async) HIPC(hipStreamSynchronize(ctx->stream));
     const int32_t* stop = reinterpret_cast<const int32_t*>(ctx->h_term + ni);
@@ -504,6 +515,40 @@ int autotune(sdc_ctx* ctx) {
 }
 
 // Spread the saved start state (v0, w0) to all nodes; all rows active.
+bool stimulus_applies(const Stimulus& s, double t, double dt) {
+  return t - 1e-9 * dt <= s.t_on && s.t_on < t + dt - 1e-9 * dt;
+}
+
+// The rows of the first sweep of the step starting at t (first_rings > 0):
+// all rows (first_n = -1) on the first step, on every first_full_every-th
+// and when nothing is carried; else the carried rows and this step's
+// stimulated rows, grown first_rings times by their mesh neighbours,
+// compacted into first_list.
+int build_first_set(sdc_ctx* ctx, double t) {
+  ctx->first_n = -1;
+  if (!ctx->first_subset()) return SDC_OK;
+  const int64_t step = ctx->step_count++;
+  const int F = ctx->prm.first_full_every;
+  if (ctx->carry_n < 0 || (F <= 0 ? step == 0 : step % F == 0)) return SDC_OK;
+  const int64_t N = ctx->N;
+  launch_mark_clear(ctx->stream, ctx->mark[0], N);
+  launch_mark_rows(ctx->stream, ctx->carry_list, ctx->carry_n, ctx->mark[0]);
+  for (const auto& s : ctx->stims)
+    if (stimulus_applies(s, t, ctx->prm.dt)) launch_mark_rows(ctx->stream, s.nodes, s.n, ctx->mark[0]);
+  int a = 0;
+  for (int r = 0; r < ctx->prm.first_rings; ++r, a ^= 1)
+    launch_mark_grow(ctx->stream, ctx->rowptr, ctx->colidx, ctx->mark[a], ctx->mark[a ^ 1], N);
+  HIPC(hipGetLastError());
+  // the marked rows, in order: a selection over all rows with threshold 1/2
+  MapBuf& nm = ctx->dyn[0];
+  launch_select(ctx->stream, ctx->all.dev(), ctx->n_inst, ctx->rowptr, ctx->mark[a], 0.5, nullptr, ctx->sel_cnt,
+                ctx->sel_nnz, ctx->list[0], ctx->first_list, ctx->next(nm), ctx->zv(), nullptr);
+  HIPC(hipGetLastError());
+  TRY(fetch_map(ctx, &nm));
+  ctx->first_n = nm.rows;
+  return SDC_OK;
+}
+
 int restart_step(sdc_ctx* ctx) {
   launch_spread(ctx->stream, ctx->prm.M, ctx->all.dev(), ctx->N, ctx->ionic_d, ctx->v0, ctx->w0, ctx->v,
                 ctx->w, ctx->I, ctx->R, ctx->emi_args());
@@ -511,6 +556,14 @@ int restart_step(sdc_ctx* ctx) {
   ctx->cur = -1;
   ctx->k = 0;
   ctx->in_step = true;
+  if (ctx->first_n >= 0) {
+    // a heuristic first-sweep set: the vectors read at neighbouring columns
+    // start at zero off it
+    launch_zero_rows(ctx->stream, ctx->all.dev(), ctx->zv());
+    HIPC(hipGetLastError());
+    TRY(map_list(ctx, 0, ctx->first_list, ctx->first_n));
+    ctx->cur = 0;
+  }
   if (ctx->terminate()) {
     HIPC(hipMemsetAsync(ctx->inst_stop, 0, ctx->n_inst * 4, ctx->stream));
     ctx->all_stopped = false;
@@ -666,6 +719,9 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   if (prm->scheme < 0 || prm->scheme > 1) return fail(ctx, SDC_ERR_ARG, "scheme must be 0 or 1");
   if (prm->scheme == 1 && emi)
     return fail(ctx, SDC_ERR_ARG, "the linearized scheme is implemented for the monodomain model only");
+  if (prm->first_rings < 0) return fail(ctx, SDC_ERR_ARG, "first_rings must be >= 0");
+  if (prm->first_rings > 0 && emi)
+    return fail(ctx, SDC_ERR_ARG, "the heuristic first-sweep set is implemented for the monodomain model only");
   if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
   if (node_off[0] != 0 || elem_off[0] != 0) return fail(ctx, SDC_ERR_ARG, "offsets must start at 0");
   for (int i = 0; i < n_inst; ++i)
@@ -815,6 +871,12 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_term), 2 * n_inst * sizeof(double)));
   }
   if (prm->scheme == 1) TRY(dalloc(ctx, &ctx->G, static_cast<size_t>(M) * N));
+  if (prm->first_rings > 0) {
+    TRY(dalloc(ctx, &ctx->carry_list, N));
+    TRY(dalloc(ctx, &ctx->first_list, N));
+    TRY(dalloc(ctx, &ctx->mark[0], N));
+    TRY(dalloc(ctx, &ctx->mark[1], N));
+  }
   if (prm->drop_mode == 1) {
     TRY(dalloc(ctx, &ctx->drop_part, 2 * static_cast<size_t>(nblk_all)));
     TRY(dalloc(ctx, &ctx->drop_theta, n_inst));
@@ -876,10 +938,9 @@ int sdc_begin_step(sdc_ctx* ctx, const double* v, const double* w, double t) {
   const int64_t N = ctx->N;
   HIPC(hipMemcpyAsync(ctx->v0, v, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(ctx->w0, w, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  const double dt = ctx->prm.dt;
   for (const auto& s : ctx->stims)
-    if (t - 1e-9 * dt <= s.t_on && s.t_on < t + dt - 1e-9 * dt)
-      launch_set_values(ctx->stream, s.nodes, s.n, s.value, ctx->v0);
+    if (stimulus_applies(s, t, ctx->prm.dt)) launch_set_values(ctx->stream, s.nodes, s.n, s.value, ctx->v0);
+  TRY(build_first_set(ctx, t));
   return restart_step(ctx);
 }
 
@@ -959,6 +1020,8 @@ int sdc_set_active(sdc_ctx* ctx, int32_t sweep, const int32_t* idx, int64_t n) {
       if (p) (void)hipFree(p);
       p = nullptr;
     }
+    ctx->carry_n = -1;
+    ctx->step_count = 0;
     return SDC_OK;
   }
   if (sweep == 0 || sweep >= SDC_MAX_SWEEPS || n < 0 || n > ctx->N || (n > 0 && !idx))

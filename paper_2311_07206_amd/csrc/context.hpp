@@ -172,6 +172,15 @@ struct sdc_ctx {
   bool linearized() const { return prm.scheme == 1; }
   int k_min() const { return std::max(1, std::min(prm.K_min, prm.K)); }
 
+  // heuristic first-sweep set (prm.first_rings > 0)
+  int32_t* carry_list = nullptr;     // [N] the set the last step carried (ascending)
+  int64_t carry_n = -1;              // its length; -1: none (next first sweep on all rows)
+  int32_t* first_list = nullptr;     // [N] the current step's first-sweep set
+  int64_t first_n = -1;              // its length; -1: all rows
+  int64_t step_count = 0;            // steps begun since setup or the last reset
+  double* mark[2] = {nullptr, nullptr};   // [N] row marks, ping-pong over the rings
+  bool first_subset() const { return prm.first_rings > 0; }
+
   // kernel timing (bench only)
   bool prof = false;
   std::vector<hipEvent_t> ev;   // 2 per CG iteration launch

@@ -209,6 +209,13 @@ void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t 
 // The rows of a map as one ascending list (list positions beg..end of each entry).
 void launch_map_rows(hipStream_t s, const Map& map, int32_t* out);
 
+// Heuristic first-sweep set (subset.hip): mark[0..n) = 0; mark[rows[q]] = 1
+// (rows in [0, n)); one ring of growth out_i = max of in over row i's pattern.
+void launch_mark_clear(hipStream_t s, double* mark, int64_t n);
+void launch_mark_rows(hipStream_t s, const int32_t* rows, int64_t n, double* mark);
+void launch_mark_grow(hipStream_t s, const int32_t* rowptr, const int32_t* col, const double* in, double* out,
+                      int64_t n);
+
 // H_m = ML + c A (pattern of A) and its inverse diagonal.
 // ppos[i] (or null): CSR position of node i's membrane partner column (-1:
 // none), where pmass[i] is added (the off-diagonal membrane mass).

@@ -1,0 +1,147 @@
+"""GPU parity of the heuristic first-sweep set (a reading of the a-priori
+subset the paper names for the first sweep, Sec. 6) against the oracle.
+
+Each first-sweep set is compared bit for bit with the oracle's rule applied
+to the set the GPU carried from the previous step (its second sweep's set)
+and the step's stimulated rows; the states match the oracle replaying every
+set of the run (first sweeps included) within 1e-10; a full first sweep on
+every step, or growth that covers the mesh, reproduces the default run bit
+for bit; the carried set is dropped with the pins.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.sdc import (apply_stimuli, build, first_sweep_set, mesh_adjacency,  # noqa: E402
+                        stimulus_nodes)
+from workloads import config0, config1, config2, config3, config4  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _solver(P, **kw):
+    from paper_2311_07206_amd import Solver
+    return Solver.from_problem(P, **kw)
+
+
+def _run_gpu(P, s, n_steps, K, stop_aware=False):
+    """Steps sweep by sweep; per step the sets of every sweep, the first one
+    read right after the step's start."""
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    sets = []
+    for n in range(n_steps):
+        s.begin_step(v, w, n * P.dt)
+        step_sets = [s.active().cpu().numpy().astype(np.int64)]
+        for k in range(K):
+            st = s.sweep()
+            if k + 1 == K or (stop_aware and st["n_stopped"] == P.n_inst):
+                break
+            step_sets.append(s.active().cpu().numpy().astype(np.int64))
+        s.end_step(v, w)
+        sets.append(step_sets)
+    return v.cpu().numpy(), w.cpu().numpy(), sets
+
+
+def _check_first_sets(P, sets, rings, full_every):
+    adj = mesh_adjacency(P.elems, P.N)
+    restricted = 0
+    for n, step in enumerate(sets):
+        full = n == 0 if full_every <= 0 else n % full_every == 0
+        if full:
+            assert np.array_equal(step[0], np.arange(P.N)), n
+            continue
+        forced = stimulus_nodes(n * P.dt, P.dt, P.stimuli)
+        want = first_sweep_set(adj, sets[n - 1][1], np.concatenate(forced) if forced else [], rings)
+        assert np.array_equal(step[0], want), n
+        restricted += step[0].size < P.N
+    return restricted
+
+
+def _oracle_replay(orc, P, n_steps, K, sets):
+    v, w = P.v_init.copy(), P.w_init.copy()
+    for n in range(n_steps):
+        apply_stimuli(v, n * P.dt, P.dt, P.stimuli)
+        v, w, infos = orc.step(v, w, K, idx_replay=sets[n])
+        assert len(infos) == len(sets[n])
+    return v, w
+
+
+@pytest.mark.parametrize("case", ["1d", "2d", "3d", "batched"])
+def test_first_sweep_sets_and_states_match_oracle(case):
+    if case == "1d":
+        P, n_steps, rings, every = config0(theta=1e-6), 40, 2, 10
+    elif case == "2d":
+        P, n_steps, rings, every = config1(n=41, theta=1e-7), 12, 3, 5
+    elif case == "3d":
+        P, n_steps, rings, every = config2(n=12, theta=1e-7), 4, 2, 0
+    else:
+        P, n_steps, rings, every = config4(n_inst=3, sizes=(10, 18)), 6, 2, 4
+    s = _solver(P, first_rings=rings, first_full_every=every)
+    print(f"[first sweep {case}] N={P.N} rings={rings} every={every}", flush=True)
+    gv, gw, sets = _run_gpu(P, s, n_steps, P.K)
+    assert _check_first_sets(P, sets, rings, every) > 0
+    ov, ow = _oracle_replay(build(P), P, n_steps, P.K, sets)
+    print(f"   first-sweep rows {[st[0].size for st in sets]}; rel v {rel(gv, ov):.2e} w {rel(gw, ow):.2e}",
+          flush=True)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+
+
+def test_first_sweep_set_with_termination_and_apriori_drop():
+    P = config4(n_inst=2, sizes=(12, 16), n_steps=5)
+    K, tol, rho = 6, 1e-5, 0.3
+    s = _solver(P, K=K, tol_sdc=tol, rho=rho, K_min=2, drop="apriori", first_rings=2, first_full_every=0)
+    gv, gw, sets = _run_gpu(P, s, P.n_steps, K, stop_aware=True)
+    assert _check_first_sets(P, sets, 2, 0) > 0
+    orc = build(P, tol_sdc=tol, rho=rho, K_min=2, drop="apriori")
+    ov, ow = _oracle_replay(orc, P, P.n_steps, K, sets)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+
+
+@pytest.mark.parametrize("kw", [dict(first_rings=2, first_full_every=1), dict(first_rings=64, first_full_every=0)])
+def test_reductions_to_the_default_run_are_bitwise(kw):
+    P = config0(n=64, theta=1e-6, n_steps=30)
+    a = _solver(P, **kw)
+    b = _solver(P)
+    va, wa, sa = _run_gpu(P, a, P.n_steps, P.K)
+    vb, wb, _ = _run_gpu(P, b, P.n_steps, P.K)
+    assert all(step[0].size == P.N for step in sa)
+    assert np.array_equal(va, vb) and np.array_equal(wa, wb)
+
+
+def test_clearing_the_pins_drops_the_carried_set():
+    P = config0(theta=1e-6, n_steps=6)
+    s = _solver(P, first_rings=2, first_full_every=0)
+    _, _, sets = _run_gpu(P, s, 3, P.K)
+    assert sets[1][0].size < P.N and sets[2][0].size < P.N
+    s.set_active(0, None)
+    _, _, again = _run_gpu(P, s, 2, P.K)
+    assert again[0][0].size == P.N and again[1][0].size < P.N
+
+
+def test_first_sweep_set_rejections():
+    from paper_2311_07206_amd import SDCError
+    with pytest.raises(SDCError, match="monodomain"):
+        _solver(config3(nc=2, nr=1, nx=3, ny=3), first_rings=2)
+    with pytest.raises(SDCError, match="first_rings"):
+        _solver(config0(n=16), first_rings=-1)
+    P = config0(n=32, theta=1e-6)
+    s = _solver(P, first_rings=2)
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    with pytest.raises(SDCError, match="STATE"):
+        s.adjoint_record(0, v, w, 0.0)
