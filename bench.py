@@ -133,6 +133,8 @@ def parse():
                     help="skip the non-adaptive (theta = 0) runs over the same steps")
     ap.add_argument("--no-linearized", action="store_true",
                     help="skip the 512x512 run with the paper's linearized basic scheme")
+    ap.add_argument("--no-first-sweep", action="store_true",
+                    help="skip the runs with the heuristic first-sweep set")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the time-per-sweep curve over front-shell active sets")
     ap.add_argument("--profile-warmup", action="store_true",
@@ -219,6 +221,8 @@ def main():
     torch.cuda.synchronize()
     v_start, w_start, t_start = v.cpu().numpy().copy(), w.cpu().numpy().copy(), t
 
+    final = {}
+
     def timed(profile):
         vv, ww = torch.tensor(v_start, device=dev), torch.tensor(w_start, device=dev)
         tt = t_start
@@ -232,6 +236,7 @@ def main():
             tt += P.dt
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        final["v"] = vv.cpu().numpy()
         prof = s.profile_read() if profile else None
         if profile:
             s.profile(False)
@@ -302,10 +307,13 @@ def main():
         out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / out["copy_GBps"]
     if not args.no_speedup:
         # the same timed steps without the drop tolerance (every row in every sweep)
-        el0 = nonadaptive_run(P, v_start, w_start, t_start, args.steps)
+        el0, final["v_non"] = nonadaptive_run(P, v_start, w_start, t_start, args.steps, return_state=True)
         out["adaptive_vs_nonadaptive"] = {
             "nonadaptive_ms_per_step": 1e3 * el0 / args.steps, "adaptive_ms_per_step": out["ms_per_step"],
             "speedup": el0 / elapsed, "paper_cpu_speedup_2d_monodomain": PAPER_SPEEDUP["2d_monodomain"]}
+    if not args.no_first_sweep:
+        out["first_sweep_subset"] = first_sweep_variant(P, v_start, w_start, t_start, args.steps,
+                                                        out["ms_per_step"], final["v"], final.get("v_non"))
     if not args.no_linearized:
         out["workload_2d_linearized"] = workload_linearized(P, v_start, w_start, t_start, min(args.steps, 100),
                                                             speedup=not args.no_speedup)
@@ -313,7 +321,7 @@ def main():
         out["batched"], out["adjoint"] = batched_and_adjoint(args.batch_steps)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio_ckpt10"]
     if not args.no_3d:
-        out["workload_3d"] = workload_3d(speedup=not args.no_speedup)
+        out["workload_3d"] = workload_3d(speedup=not args.no_speedup, first_sweep=not args.no_first_sweep)
     if not args.no_emi:
         out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
         out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
@@ -433,9 +441,10 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2 * nbytes / best / 1e9
 
 
-def nonadaptive_run(P, v0, w0, t0, nsteps, warm_budget=True, **kw):
+def nonadaptive_run(P, v0, w0, t0, nsteps, warm_budget=True, return_state=False, **kw):
     """Wall time of `nsteps` steps with theta = 0 (all rows in every sweep) from
-    the given state, for the adaptive/non-adaptive speedup."""
+    the given state, for the adaptive/non-adaptive speedup (and the final
+    potential, with return_state)."""
     import torch
 
     from paper_2311_07206_amd import Solver
@@ -446,7 +455,34 @@ def nonadaptive_run(P, v0, w0, t0, nsteps, warm_budget=True, **kw):
         s.step(v.clone(), w.clone(), t0)   # iteration history for the budgets
     el, _ = _timed_steps(s, v, w, t0, P.dt, nsteps, torch.cuda.synchronize)
     s.close()
-    return el
+    return (el, v.cpu().numpy()) if return_state else el
+
+
+def first_sweep_variant(P, v0, w0, t0, nsteps, ms_std, v_std, v_non=None, rings=4, every=10):
+    """The same timed steps with the heuristic first-sweep set (first_rings
+    rings of growth, all rows every first_full_every steps): throughput, the
+    share of rows the first sweeps took, and how far the final potential
+    lies from the standard adaptive run's (and, with the non-adaptive run's
+    v_non, how far each of the two lies from that)."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    s = Solver.from_problem(P, first_rings=rings, first_full_every=every)
+    v, w = torch.tensor(v0, device=dev), torch.tensor(w0, device=dev)
+    s.step(v.clone(), w.clone(), t0)   # iteration history for the budgets
+    s.set_active(0, None)              # the timed run carries nothing in
+    el, logs = _timed_steps(s, v, w, t0, P.dt, nsteps, torch.cuda.synchronize)
+    s.close()
+    vf = v.cpu().numpy()
+    out = {"first_rings": rings, "first_full_every": every, "value": sum(st["n_active"] for lg in logs for st in lg) / el,
+           "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps, "speedup_vs_standard": ms_std / (1e3 * el / nsteps),
+           "first_sweep_rows_frac": float(np.mean([lg[0]["n_active"] for lg in logs])) / P.N,
+           "max_abs_v_vs_standard": float(np.abs(vf - v_std).max()), "theta": P.theta}
+    if v_non is not None:
+        out["max_abs_v_vs_nonadaptive"] = float(np.abs(vf - v_non).max())
+        out["standard_max_abs_v_vs_nonadaptive"] = float(np.abs(v_std - v_non).max())
+    return out
 
 
 def _timed_steps(solver, v, w, t0, dt, n, sync):
@@ -551,7 +587,7 @@ def workload_linearized(P, v0, w0, t0, nsteps, speedup=True):
     return out
 
 
-def workload_3d(nsteps=10, warm=10, speedup=True):
+def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True):
     """The 128^3 3D workload (2.1M dofs, 27M stored entries): HBM-resident."""
     import torch
 
@@ -566,8 +602,11 @@ def workload_3d(nsteps=10, warm=10, speedup=True):
     for k in range(warm):
         s.step(v, w, k * P.dt)
     v0, w0 = v.cpu().numpy().copy(), w.cpu().numpy().copy()
-    s.profile(True)
     el, logs = _timed_steps(s, v, w, warm * P.dt, P.dt, nsteps, torch.cuda.synchronize)
+    # the kernel timings from a second pass over the same steps
+    s.profile(True)
+    _timed_steps(s, torch.tensor(v0, device=dev), torch.tensor(w0, device=dev), warm * P.dt, P.dt, nsteps,
+                 torch.cuda.synchronize)
     prof = s.profile_read()
     s.profile(False)
     dofs = sum(st["n_active"] for lg in logs for st in lg)
@@ -589,10 +628,14 @@ def workload_3d(nsteps=10, warm=10, speedup=True):
             "bytes_per_launch": prof["cg_all_bytes"] / prof["cg_all_launches"],
             "launches": prof["cg_all_launches"]}
     s.close()
+    v_std, v_non = v.cpu().numpy(), None
     if speedup:
-        el0 = nonadaptive_run(P, v0, w0, warm * P.dt, nsteps)
+        el0, v_non = nonadaptive_run(P, v0, w0, warm * P.dt, nsteps, return_state=True)
         out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / nsteps, "speedup": el0 / el,
                                           "paper_cpu_speedup_3d_monodomain": PAPER_SPEEDUP["3d_monodomain"]}
+    if first_sweep:
+        out["first_sweep_subset"] = first_sweep_variant(P, v0, w0, warm * P.dt, nsteps, out["ms_per_step"], v_std,
+                                                        v_non, rings=3)
     return out
 
 
