@@ -472,13 +472,15 @@ def first_sweep_variant(P, v0, w0, t0, nsteps, ms_std, v_std, v_non=None, rings=
     v, w = torch.tensor(v0, device=dev), torch.tensor(w0, device=dev)
     s.step(v.clone(), w.clone(), t0)   # iteration history for the budgets
     s.set_active(0, None)              # the timed run carries nothing in
+    redone = s.info()["redone_steps"]
     el, logs = _timed_steps(s, v, w, t0, P.dt, nsteps, torch.cuda.synchronize)
+    redone = s.info()["redone_steps"] - redone
     s.close()
     vf = v.cpu().numpy()
     out = {"first_rings": rings, "first_full_every": every, "value": sum(st["n_active"] for lg in logs for st in lg) / el,
            "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps, "speedup_vs_standard": ms_std / (1e3 * el / nsteps),
            "first_sweep_rows_frac": float(np.mean([lg[0]["n_active"] for lg in logs])) / P.N,
-           "max_abs_v_vs_standard": float(np.abs(vf - v_std).max()), "theta": P.theta}
+           "max_abs_v_vs_standard": float(np.abs(vf - v_std).max()), "theta": P.theta, "redone_steps": redone}
     if v_non is not None:
         out["max_abs_v_vs_nonadaptive"] = float(np.abs(vf - v_non).max())
         out["standard_max_abs_v_vs_nonadaptive"] = float(np.abs(v_std - v_non).max())

@@ -265,7 +265,7 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     launch_rhs(ctx->stream, M, m, map, N, ctx->A(), ctx->ml, ctx->Phi + m * N, ctx->dI, ctx->dv,
                ctx->r[0], x, ctx->cargs, emi, lin ? ctx->G : nullptr);
     HIPC(hipGetLastError());
-    const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
+    const int slot = ctx->pred_slot(m);
     if (async && ctx->pred[slot] <= kAsyncMaxBudget) {
       TRY(run_cg_async(ctx, m, mb, x, slot, &ev_off, &ev_budget));
     } else {
@@ -349,7 +349,7 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
         if (d == 0 && short_budget) *short_budget = true;
         mx = std::max(mx, iters[m][i]);
       }
-      const int slot = std::min(ctx->k, SDC_MAX_SWEEPS - 1) * M + m;
+      const int slot = ctx->pred_slot(m);
       ctx->pred[slot] = mx + 1;
       if (ev_budget[m] > 0) {
         MapBuf view;
@@ -891,7 +891,9 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   TRY(dalloc(ctx, &ctx->hist_iters, static_cast<size_t>(M) * n_inst));
   HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i64), (8 + n_inst) * sizeof(int64_t)));
   HIPC(hipStreamSynchronize(ctx->stream));
-  ctx->pred.assign(2 * static_cast<size_t>(SDC_MAX_SWEEPS) * M, 8);   // forward and reverse solves
+  // forward solves, reverse solves, forward solves of full-first-sweep steps
+  // among heuristic ones
+  ctx->pred.assign(3 * static_cast<size_t>(SDC_MAX_SWEEPS) * M, 8);
   ctx->coords_h.assign(coords, coords + N * dim);
   ctx->elems_h.assign(elems, elems + E * nv);
   ctx->tensor_h.assign(elem_tensor, elem_tensor + E * dim * dim);

@@ -186,7 +186,14 @@ struct sdc_ctx {
   std::vector<hipEvent_t> ev;   // 2 per CG iteration launch
   hipEvent_t sweep_ev[2] = {nullptr, nullptr};   // around a sweep whose statistics are asked for
   sdc_profile_stats pst{};
-  std::vector<int> pred;   // predicted CG iterations [SDC_MAX_SWEEPS][M]
+  std::vector<int> pred;   // predicted CG iterations [3][SDC_MAX_SWEEPS][M]
+  // prediction slot of node m in the current sweep: steps whose first sweep
+  // takes all rows while heuristic first-sweep sets are on keep their own
+  // history (their solves differ from the other steps')
+  int pred_slot(int m) const {
+    const int fam = first_subset() && first_n < 0 ? 2 : 0;
+    return (fam * SDC_MAX_SWEEPS + std::min(k, SDC_MAX_SWEEPS - 1)) * prm.M + m;
+  }
 
   const MapBuf& curmap() const { return cur < 0 ? all : dyn[cur]; }
   // output description for building a map into mb (records carry the diagonal offsets)
