@@ -112,6 +112,15 @@ def test_first_sweep_set_with_termination_and_apriori_drop():
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
 
+def test_first_sweep_set_with_the_linearized_scheme():
+    P = config1(n=33, theta=1e-7)
+    s = _solver(P, scheme="linearized", first_rings=3, first_full_every=0)
+    gv, gw, sets = _run_gpu(P, s, 5, P.K)
+    assert _check_first_sets(P, sets, 3, 0) > 0
+    ov, ow = _oracle_replay(build(P, scheme="linearized"), P, 5, P.K, sets)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+
+
 @pytest.mark.parametrize("kw", [dict(first_rings=2, first_full_every=1), dict(first_rings=64, first_full_every=0)])
 def test_reductions_to_the_default_run_are_bitwise(kw):
     P = config0(n=64, theta=1e-6, n_steps=30)
