@@ -135,6 +135,8 @@ def parse():
                     help="skip the 512x512 run with the paper's linearized basic scheme")
     ap.add_argument("--no-first-sweep", action="store_true",
                     help="skip the runs with the heuristic first-sweep set")
+    ap.add_argument("--small-set-rows", type=int, default=0,
+                    help="the latency curve's solver option (0: default one-launch solves of small sets, -1: off)")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the time-per-sweep curve over front-shell active sets")
     ap.add_argument("--profile-warmup", action="store_true",
@@ -326,7 +328,7 @@ def main():
         out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
         out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
     if not args.no_latency:
-        out["latency_curve"] = latency_curve(P)
+        out["latency_curve"] = latency_curve(P, small_set_rows=args.small_set_rows)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
@@ -354,7 +356,8 @@ def front_shell_masks(coords, elems, v, densities, level=0.5):
     return [np.sort(order[:max(1, int(round(d * v.size)))]).astype(np.int32) for d in densities]
 
 
-def latency_curve(P, snapshots=(10.0, 50.0, 150.0), densities=(1.0, 0.5, 0.1, 0.01, 0.001), reps=5):
+def latency_curve(P, snapshots=(10.0, 50.0, 150.0), densities=(1.0, 0.5, 0.1, 0.01, 0.003, 0.001), reps=5,
+                  small_set_rows=0):
     """Time per sweep against the size of its active set.  The run goes from
     the initial state (sets chosen by the drop tolerance) to each snapshot
     time; there, sweeps 1..K-1 of one step are pinned to front-shell masks of
@@ -362,13 +365,15 @@ def latency_curve(P, snapshots=(10.0, 50.0, 150.0), densities=(1.0, 0.5, 0.1, 0.
     once untimed and `reps` times timed.  A sweep's time is its stream time
     by events (its launches, the next set's mapping and the host
     synchronisation); a second set of `reps` steps with kernel timing on
-    gives the mean duration of the CG iteration launches on the pinned sets."""
+    gives the mean duration of the CG iteration launches on the pinned sets
+    (sets solved by one workgroup in one launch, see small_set_rows, have
+    none)."""
     import numpy as np
     import torch
 
     from paper_2311_07206_amd import Solver
     dev = torch.device("cuda", 0)
-    s = Solver.from_problem(P)
+    s = Solver.from_problem(P, small_set_rows=small_set_rows)
     v = torch.tensor(P.v_init, device=dev)
     w = torch.tensor(P.w_init, device=dev)
     n_done, out = 0, []
@@ -418,7 +423,7 @@ def latency_curve(P, snapshots=(10.0, 50.0, 150.0), densities=(1.0, 0.5, 0.1, 0.
     s.close()
     return {"workload": f"2D monodomain {int(round(P.N ** 0.5))}x{int(round(P.N ** 0.5))}, sweeps 1..{P.K - 1} "
                         f"pinned to front-shell masks (level v = 0.5)",
-            "snapshots": out, "redone_steps": redone}
+            "small_set_rows": small_set_rows, "snapshots": out, "redone_steps": redone}
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):

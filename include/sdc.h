@@ -112,6 +112,12 @@ typedef struct {
   /* reverse pass.                                                           */
   int32_t first_rings;
   int32_t first_full_every;
+  /* Solves whose instances each have at most this many active rows run as  */
+  /* one launch (the whole Jacobi-PCG of an instance in one workgroup)        */
+  /* instead of one launch per iteration.  0: the default and largest value  */
+  /* (2048 rows; 1024 when a row of A has more than 8 stored entries);       */
+  /* -1: never.  Same stopping rule, results equal to rounding.              */
+  int32_t small_set_rows;
 } sdc_params;
 
 /* Per-sweep statistics (sums over instances unless stated). */

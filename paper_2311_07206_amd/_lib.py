@@ -25,7 +25,8 @@ class Params(ctypes.Structure):
     _fields_ = [("M", c_int32), ("K", c_int32), ("dt", c_double), ("theta", c_double),
                 ("cg_rtol", c_double), ("cg_maxit", c_int32), ("format", c_int32),
                 ("K_min", c_int32), ("tol_sdc", c_double), ("rho", c_double), ("drop_mode", c_int32),
-                ("scheme", c_int32), ("first_rings", c_int32), ("first_full_every", c_int32)]
+                ("scheme", c_int32), ("first_rings", c_int32), ("first_full_every", c_int32),
+                ("small_set_rows", c_int32)]
 
 
 class SweepStats(ctypes.Structure):

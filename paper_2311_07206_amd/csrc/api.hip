@@ -106,6 +106,18 @@ int account_timing(sdc_ctx* ctx, const MapBuf& mb, int it0, int budget, const in
   return account_timing_at(ctx, mb, 0, budget, iters, it0);
 }
 
+// Maps whose instances each hold at most small_set_rows rows (default and
+// cap: what one workgroup takes, kWgThreads times its rows per thread) are
+// solved by one workgroup per instance in a single launch.
+bool wg_solve(const sdc_ctx* ctx, const MapBuf& mb) {
+  const int cap = kWgThreads * ctx->wg_rows_per_thread();
+  const int lim = ctx->prm.small_set_rows == 0 ? cap : std::min(ctx->prm.small_set_rows, cap);
+  if (lim <= 0 || mb.nblk <= 0 || mb.max_nb > cap / kBlock) return false;
+  for (int i = 0; i < ctx->n_inst; ++i)
+    if (mb.cnt[i] > lim) return false;
+  return true;
+}
+
 // Restricted Jacobi-PCG on H_m over the current map, starting from b in
 // r[0] and x = 0 (prepared by the right-hand-side kernel).  Iterations are
 // launched in budgets; after each budget the host reads the per-instance
@@ -123,6 +135,28 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   int left = vbudget;
   int it = 0;
   iters->assign(ni, 0);
+  if (wg_solve(ctx, mb)) {
+    launch_cg_wg(ctx->stream, map, ctx->N, H, dinv, ctx->r[0], x, ctx->wg_p, rtol2, ctx->prm.cg_maxit, ctx->cg(),
+                 ctx->wg_rows_per_thread());
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipMemcpyAsync(ctx->h_i32 + ni, ctx->cg_iters, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    int mx = 0;
+    for (int i = 0; i < ni; ++i) {
+      const int d = ctx->h_i32[i];
+      if (d == 2)
+        return fail(ctx, SDC_ERR_CG_MAXIT, "CG: instance %d, node %d, sweep %d: no convergence in %d iterations",
+                    i, m, ctx->k, ctx->prm.cg_maxit);
+      if (d == 3)
+        return fail(ctx, SDC_ERR_NONFINITE, "CG: instance %d, node %d, sweep %d: non-finite or non-positive curvature",
+                    i, m, ctx->k);
+      (*iters)[i] = ctx->h_i32[ni + i];
+      mx = std::max(mx, (*iters)[i]);
+    }
+    if (pred_slot >= 0) ctx->pred[pred_slot] = mx + 1;
+    return SDC_OK;
+  }
   launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0], ctx->cg());
   HIPC(hipGetLastError());
   if (mb.nblk > 0) {
@@ -212,6 +246,13 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
   const int budget = std::min(std::max(1, ctx->pred[pred_slot]) + 1, ctx->prm.cg_maxit + 1);
   // the kernels record the outcome straight into the node's history slot
   const CgState cg{ctx->hist_done + m * ni, ctx->hist_iters + m * ni, ctx->cg_blk_done};
+  if (wg_solve(ctx, mb)) {
+    launch_cg_wg(ctx->stream, map, ctx->N, H, dinv, ctx->r[0], x, ctx->wg_p, rtol2, ctx->prm.cg_maxit, cg,
+                 ctx->wg_rows_per_thread());
+    HIPC(hipGetLastError());
+    (*ev_budget)[m] = 0;
+    return SDC_OK;
+  }
   launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0], cg);
   const bool timed = ctx->prof && static_cast<int>(ctx->ev.size()) >= 2 * (*ev_off + budget);
   for (int it = 0; mb.nblk > 0 && it < budget; ++it) {
@@ -720,6 +761,7 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   if (prm->scheme == 1 && emi)
     return fail(ctx, SDC_ERR_ARG, "the linearized scheme is implemented for the monodomain model only");
   if (prm->first_rings < 0) return fail(ctx, SDC_ERR_ARG, "first_rings must be >= 0");
+  if (prm->small_set_rows < -1) return fail(ctx, SDC_ERR_ARG, "small_set_rows must be >= -1");
   if (prm->first_rings > 0 && emi)
     return fail(ctx, SDC_ERR_ARG, "the heuristic first-sweep set is implemented for the monodomain model only");
   if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
@@ -760,6 +802,8 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   std::vector<double> emi_sl, emi_pmass;
   if (emi) TRY(emi_host_setup(ctx, emi, &emi_part, &emi_sl, &emi_ppos, &emi_pmass));
   ctx->nnz = ctx->host.rowptr[N];
+  for (int64_t i = 0; i < N; ++i)
+    ctx->max_row = std::max<int64_t>(ctx->max_row, ctx->host.rowptr[i + 1] - ctx->host.rowptr[i]);
   const int64_t nnz = ctx->nnz;
   const int M = prm->M;
 
@@ -864,6 +908,7 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     TRY(dalloc(ctx, &ctx->part[q], 4 * static_cast<size_t>(nblk_all)));
   }
   TRY(dalloc(ctx, &ctx->cg_done, n_inst));
+  TRY(dalloc(ctx, &ctx->wg_p, N));   // zero, and zero again after every workgroup solve
   if (prm->tol_sdc > 0.0) {
     TRY(dalloc(ctx, &ctx->e_part, static_cast<size_t>(M) * nblk_all));
     TRY(dalloc(ctx, &ctx->inst_energy, n_inst));

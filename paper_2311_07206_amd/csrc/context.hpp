@@ -105,6 +105,11 @@ struct sdc_ctx {
   // CG vectors: p and the iterate (dv[m]) are read on own rows only; r, w, s
   // are double-buffered because the SpMV reads them at neighbouring columns
   double* p = nullptr;
+  double* wg_p = nullptr;   // search direction of the one-workgroup solves (zero between solves)
+  int64_t max_row = 0;      // most stored entries in a row of A
+  // rows per thread of the one-workgroup solves: a property of the pattern,
+  // so that both storages of a matrix solve alike
+  int wg_rows_per_thread() const { return max_row <= 8 ? 2 : 1; }
   double *r[2] = {nullptr, nullptr}, *wv[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
 
   double* cg_scal[2] = {nullptr, nullptr};   // [n_inst][kScal] by launch parity

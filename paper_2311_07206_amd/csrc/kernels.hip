@@ -1285,6 +1285,145 @@ __global__ __launch_bounds__(kBlock) void k_map_rows(Map map, int32_t* __restric
 
 inline dim3 grid(int nblk) { return dim3(static_cast<unsigned>(nblk > 0 ? nblk : 1)); }
 
+// Whole restricted Jacobi-PCG of one instance in one workgroup (sets of at
+// most kWgThreads * R rows): thread t owns list positions t + q kWgThreads,
+// q < R.  R is a property of the matrix pattern (one row per thread for
+// rows of more than 8 entries, whose unrolled loads need the 128 registers
+// a wave of a 1024-thread workgroup has), so both storages of a matrix
+// assign rows to threads alike and reduce in the same order.  Plain PCG with z = dinv r; the search direction
+// is exchanged through pbuf (zero off the set, and everywhere again when the
+// solve ends), with a workgroup barrier between its writes and the
+// matrix-vector product that gathers it.  The reductions run in a fixed
+// order (wave butterfly, then the waves in order), so every thread holds the
+// same scalars and takes the same branches.
+constexpr int kWgWaves = kWgThreads / 64;
+
+template <int NV>
+__device__ inline void wg_sum(double (&v)[NV], double* sh /* [kWgWaves * NV] */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wid * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < kWgWaves; ++q) a += sh[q * NV + k];
+    v[k] = a;
+  }
+}
+
+template <int S, int kWgRows>
+__global__ __launch_bounds__(kWgThreads) void k_cg_wg(Map map, int64_t N, Mat H, const double* __restrict__ dinv,
+                                                      const double* __restrict__ b, double* __restrict__ x,
+                                                      double* __restrict__ pbuf, double rtol2, int maxit,
+                                                      int32_t* __restrict__ done, int32_t* __restrict__ iters) {
+  // one LDS array per reduction of an iteration, so that a reduction never
+  // overwrites values another thread may still be reading
+  __shared__ double sh_a[2 * kWgWaves], sh_b[kWgWaves], sh_c[2 * kWgWaves];
+  const int inst = static_cast<int>(blockIdx.x);
+  const int t = static_cast<int>(threadIdx.x);
+  const int blk0 = map.inst_blk0[inst], nb = map.inst_nblk[inst];
+  Row rw{};
+  if (nb > 0) {
+    // the instance's diagonal offsets and row range, from its first entry
+    const int32_t* words = reinterpret_cast<const int32_t*>(map.rec + blk0);
+    rw.word = words[min(t & 63, kRecWords - 1)];
+    rw.lo = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, lo) / 4);
+    rw.hi = __builtin_amdgcn_readlane(rw.word, offsetof(BlkRec, hi) / 4);
+  }
+  int row[kWgRows];
+  bool valid[kWgRows];
+  double xv[kWgRows], rv[kWgRows], pv[kWgRows], di[kWgRows];
+  double acc[2] = {0.0, 0.0};   // r.z, b.b
+#pragma unroll
+  for (int q = 0; q < kWgRows; ++q) {
+    const int pos = t + q * kWgThreads, e = pos / kBlock, lane = pos % kBlock;
+    valid[q] = false;
+    row[q] = 0;
+    if (e < nb) {
+      const BlkRec& rec = map.rec[blk0 + e];
+      if (lane < rec.end - rec.beg) {
+        valid[q] = true;
+        row[q] = map.idx ? map.idx[(blk0 + e) * kBlock + lane] : rec.beg + lane;
+      }
+    }
+    xv[q] = rv[q] = pv[q] = di[q] = 0.0;
+    if (valid[q]) {
+      const int i = row[q];
+      rv[q] = b[i];
+      di[q] = dinv[i];
+      pv[q] = di[q] * rv[q];
+      pbuf[i] = pv[q];
+      acc[0] += rv[q] * pv[q];
+      acc[1] += rv[q] * rv[q];
+    }
+  }
+  wg_sum<2>(acc, sh_a);
+  double rz = acc[0], rr = acc[1];
+  const double bb = acc[1];
+  int it = 0, status = 0;
+  for (;; ++it) {
+    if (!isfinite(rr) || !isfinite(rz)) { status = 3; break; }
+    if (rr <= rtol2 * bb) { status = 1; break; }
+    if (it >= maxit) { status = 2; break; }
+    __syncthreads();   // pbuf holds the direction on every row of the set
+    double qv[kWgRows];
+    double pq[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < kWgRows; ++q) {
+      qv[q] = 0.0;
+      if (valid[q]) {
+        double a = 0.0;
+        for_entries<S>(H, N, rw, row[q], [&](double h, int k, bool) { a += h * pbuf[k]; });
+        qv[q] = a;
+        pq[0] += pv[q] * a;
+      }
+    }
+    wg_sum<1>(pq, sh_b);
+    if (!(pq[0] > 0.0)) { status = 3; break; }
+    const double alpha = rz / pq[0];
+    double nr[2] = {0.0, 0.0};   // r.z, r.r after the update
+#pragma unroll
+    for (int q = 0; q < kWgRows; ++q) {
+      if (valid[q]) {
+        xv[q] += alpha * pv[q];
+        rv[q] -= alpha * qv[q];
+        const double z = di[q] * rv[q];
+        nr[0] += rv[q] * z;
+        nr[1] += rv[q] * rv[q];
+      }
+    }
+    wg_sum<2>(nr, sh_c);
+    const double beta = nr[0] / rz;
+    rz = nr[0];
+    rr = nr[1];
+#pragma unroll
+    for (int q = 0; q < kWgRows; ++q) {
+      if (valid[q]) {
+        pv[q] = di[q] * rv[q] + beta * pv[q];
+        pbuf[row[q]] = pv[q];
+      }
+    }
+  }
+  __syncthreads();   // every gather of pbuf is done before it is cleared
+#pragma unroll
+  for (int q = 0; q < kWgRows; ++q) {
+    if (valid[q]) {
+      x[row[q]] = xv[q];
+      pbuf[row[q]] = 0.0;
+    }
+  }
+  if (t == 0) {
+    done[inst] = status;
+    iters[inst] = it;
+  }
+}
+
 // The matrix-vector kernels outside the CG iteration (initial residual,
 // energy) need few registers and run ~7-8 blocks per CU; on large maps
 // their rows and the neighbour rows the stencil reaches (in 3D a plane
@@ -1482,6 +1621,19 @@ void launch_drop_tolerance(hipStream_t s, const Map& map, int M, int64_t N, cons
     });
   k_drop_tol<<<dim3(static_cast<unsigned>(map.n_inst)), kBlock, 0, s>>>(map.inst_blk0, map.inst_nblk, part, dt, rho,
                                                                        tol, out, info);
+}
+
+void launch_cg_wg(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv, const double* b,
+                  double* x, double* pbuf, double rtol2, int maxit, const CgState& cg, int rows_per_thread) {
+  if (map.n_inst <= 0) return;
+  const dim3 g(static_cast<unsigned>(map.n_inst));
+  dispatch_storage(H.nd, [&](auto st) {
+    constexpr int S = decltype(st)::value;
+    if (rows_per_thread == 2)
+      k_cg_wg<S, 2><<<g, kWgThreads, 0, s>>>(map, N, H, dinv, b, x, pbuf, rtol2, maxit, cg.done, cg.iters);
+    else
+      k_cg_wg<S, 1><<<g, kWgThreads, 0, s>>>(map, N, H, dinv, b, x, pbuf, rtol2, maxit, cg.done, cg.iters);
+  });
 }
 
 void launch_energy(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* x, double* e_part) {

@@ -128,6 +128,16 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     int maxit, const CgState& cg, double* tot, hipEvent_t ev_start = nullptr,
                     hipEvent_t ev_stop = nullptr);
 constexpr int kTotBlocks = 4 * kBlock;
+// The whole restricted PCG of each instance in one workgroup of kWgThreads
+// threads, rows_per_thread (1 or 2) rows each, for maps whose instances hold
+// at most kWgThreads * rows_per_thread rows: x (zero on entry) receives the
+// solution on the set, done/iters of cg the outcome; b is the right-hand
+// side on the set; pbuf (double[N]) must be zero on entry and is zero again
+// on return.  Plain PCG (z = dinv r) with the same stopping rule as the
+// launch-per-iteration kernels.
+constexpr int kWgThreads = 1024;
+void launch_cg_wg(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv, const double* b,
+                  double* x, double* pbuf, double rtol2, int maxit, const CgState& cg, int rows_per_thread);
 // Post-solve update of node m.  With the cell-by-cell model this updates the
 // potentials and amax only; launch_post_sites then updates the membrane
 // sites whose intracellular node is active, from the updated potentials.

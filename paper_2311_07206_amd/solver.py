@@ -44,7 +44,7 @@ class Solver:
     def __init__(self, coords, elems, elem_tensor, node_sigma, ionic, node_off, elem_off,
                  M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None, emi=None,
                  tol_sdc=0.0, rho=0.05, K_min=1, drop="theta", scheme="imex", first_rings=0,
-                 first_full_every=10):
+                 first_full_every=10, small_set_rows=0):
         """emi: None (monodomain) or a dict with the cell-by-cell couplings
         mem_intra, mem_extra, mem_len, cm, gap_a, gap_b, gap_len, g_gap,
         robin_len, eps (see sdc_emi).  drop: "theta" (fixed drop tolerance)
@@ -53,7 +53,9 @@ class Solver:
         "linearized" (the paper's basic scheme, see sdc_params.scheme).
         first_rings >= 1: heuristic first-sweep sets grown by that many rings
         of mesh neighbours, with all rows every first_full_every steps (see
-        sdc_params.first_rings)."""
+        sdc_params.first_rings).  small_set_rows: solves of at most that many
+        rows per instance run in one launch each (0: up to 2048, 1024 when rows
+        hold more than 8 entries; -1: never)."""
         if drop not in ("theta", "apriori"):
             raise ValueError("drop must be 'theta' or 'apriori'")
         if scheme not in ("imex", "linearized"):
@@ -75,7 +77,7 @@ class Solver:
                      cg_maxit=int(cg_maxit), format=int(fmt), K_min=int(K_min), tol_sdc=float(tol_sdc),
                      rho=float(rho), drop_mode=1 if drop == "apriori" else 0,
                      scheme=1 if scheme == "linearized" else 0, first_rings=int(first_rings),
-                     first_full_every=int(first_full_every))
+                     first_full_every=int(first_full_every), small_set_rows=int(small_set_rows))
         node_off_a, p_no = _host(node_off, np.int64)
         coords_a, p_c = _host(coords, np.float64)
         elem_off_a, p_eo = _host(elem_off, np.int64)
