@@ -249,6 +249,24 @@ def test_pinned_front_shell_sets_match_oracle(density):
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
 
+@pytest.mark.parametrize("P", [config0(n=200, theta=1e-6, n_steps=10), config1(n=33, theta=1e-7, n_steps=4),
+                               config2(n=7, theta=1e-7, n_steps=3)], ids=["1d", "2d", "3d"])
+def test_small_sets_are_solved_in_one_launch(P):
+    """Sets of one workgroup's size run the whole solve in one launch (no
+    per-iteration launches in the kernel timing); with that path off, one
+    launch per iteration.  Both match the oracle on their own sets."""
+    for rows, per_iteration in ((0, False), (-1, True)):
+        s = _solver(P, small_set_rows=rows)
+        s.profile(True)
+        gv, gw, sets, _, _ = gpu_run(P, P.n_steps, s=s)
+        launches = s.profile_read()["cg_launches"]
+        s.profile(False)
+        print(f"[small sets] {P.name} N={P.N} small_set_rows={rows}: {launches} CG launches", flush=True)
+        assert (launches > 0) == per_iteration
+        ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli, idx_replay=sets)
+        assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+
+
 def test_ragged_2d_adaptive_run():
     P = config1(n=23, theta=1e-7, n_steps=12)
     gv, gw, sets, _, _ = gpu_run(P, P.n_steps)
