@@ -38,15 +38,21 @@ int fail(sdc_ctx* c, int code, const char* fmt, ...) {
   return code;
 }
 
+// The sizes a built map reports to the host, in one block so that one copy
+// reads them: int64 inst_nnz[ni + 1], int32 totals[4], int32 inst_cnt[ni + 1].
+size_t map_sizes_words(int ni) { return static_cast<size_t>(ni + 1) + 2 + (ni + 2) / 2; }
+
 int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap) {
   const int ni = ctx->n_inst;
   TRY(dalloc(ctx, &mb->rec, nblk_cap));
   TRY(dalloc(ctx, &mb->inst_blk0, ni + 1));
   TRY(dalloc(ctx, &mb->inst_nblk, ni + 1));
-  TRY(dalloc(ctx, &mb->inst_cnt, ni + 1));
-  TRY(dalloc(ctx, &mb->inst_nnz, ni + 1));
+  int64_t* sizes = nullptr;
+  TRY(dalloc(ctx, &sizes, map_sizes_words(ni)));
+  mb->inst_nnz = sizes;
+  mb->totals = reinterpret_cast<int32_t*>(sizes + ni + 1);
+  mb->inst_cnt = mb->totals + 4;
   TRY(dalloc(ctx, &mb->aoff, ni + 1));
-  TRY(dalloc(ctx, &mb->totals, 4));
   mb->cnt.assign(ni, 0);
   mb->nnz.assign(ni, 0);
   mb->n_inst = ni;
@@ -56,16 +62,16 @@ int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap) {
 // Read a freshly built map's sizes back to the host (synchronises).
 int fetch_map(sdc_ctx* ctx, MapBuf* mb) {
   const int ni = ctx->n_inst;
-  HIPC(hipMemcpyAsync(ctx->h_i32, mb->totals, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-  HIPC(hipMemcpyAsync(ctx->h_i32 + 4, mb->inst_cnt, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-  HIPC(hipMemcpyAsync(ctx->h_i64, mb->inst_nnz, ni * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->h_i64, mb->inst_nnz, map_sizes_words(ni) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                      ctx->stream));
   HIPC(hipStreamSynchronize(ctx->stream));
-  mb->nblk = ctx->h_i32[0];
-  mb->rows = ctx->h_i32[1];
-  if (ctx->h_i32[2] != 0) return fail(ctx, SDC_ERR_ARG, "index list not strictly ascending or out of range");
+  const int32_t* tot = reinterpret_cast<const int32_t*>(ctx->h_i64 + ni + 1);
+  mb->nblk = tot[0];
+  mb->rows = tot[1];
+  if (tot[2] != 0) return fail(ctx, SDC_ERR_ARG, "index list not strictly ascending or out of range");
   mb->max_nb = 0;
   for (int i = 0; i < ni; ++i) {
-    mb->cnt[i] = ctx->h_i32[4 + i];
+    mb->cnt[i] = tot[4 + i];
     mb->nnz[i] = ctx->h_i64[i];
     mb->max_nb = std::max(mb->max_nb, (mb->cnt[i] + kBlock - 1) / kBlock);
   }
@@ -139,8 +145,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
     launch_cg_wg(ctx->stream, map, ctx->N, H, dinv, ctx->r[0], x, ctx->wg_p, rtol2, ctx->prm.cg_maxit, ctx->cg(),
                  ctx->wg_rows_per_thread());
     HIPC(hipGetLastError());
-    HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    HIPC(hipMemcpyAsync(ctx->h_i32 + ni, ctx->cg_iters, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, 2 * ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));
     int mx = 0;
     for (int i = 0; i < ni; ++i) {
@@ -174,8 +179,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
                        timed ? ctx->ev[2 * b + 1] : nullptr);
       }
       HIPC(hipGetLastError());
-      HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-      HIPC(hipMemcpyAsync(ctx->h_i32 + ni, ctx->cg_iters, ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+      HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, 2 * ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
       HIPC(hipStreamSynchronize(ctx->stream));
       if (timed) TRY(account_timing(ctx, mb, it0, budget, ctx->h_i32 + ni));
       bool running = false;
@@ -345,8 +349,8 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
   }
   if (async) {
     // one synchronisation per sweep: the nodes' CG outcomes (and below, the next set's size)
-    HIPC(hipMemcpyAsync(ctx->h_i32 + 8 + 2 * ni, ctx->hist_done, M * ni * 4, hipMemcpyDeviceToHost, ctx->stream));
-    HIPC(hipMemcpyAsync(ctx->h_i32 + 8 + 2 * ni + M * ni, ctx->hist_iters, M * ni * 4, hipMemcpyDeviceToHost,
+    // (hist_iters follows hist_done in one allocation)
+    HIPC(hipMemcpyAsync(ctx->h_i32 + 8 + 2 * ni, ctx->hist_done, 2 * M * ni * 4, hipMemcpyDeviceToHost,
                         ctx->stream));
   }
   if (ctx->record_dv)   // the selection below zeroes dv on the rows it drops
@@ -907,7 +911,9 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     if (q == 0) TRY(dalloc(ctx, &ctx->cg_tot, 4 * static_cast<size_t>(n_inst)));
     TRY(dalloc(ctx, &ctx->part[q], 4 * static_cast<size_t>(nblk_all)));
   }
-  TRY(dalloc(ctx, &ctx->cg_done, n_inst));
+  // done flags and iteration counts side by side: one copy reads both
+  TRY(dalloc(ctx, &ctx->cg_done, 2 * static_cast<size_t>(n_inst)));
+  ctx->cg_iters = ctx->cg_done + n_inst;
   TRY(dalloc(ctx, &ctx->wg_p, N));   // zero, and zero again after every workgroup solve
   if (prm->tol_sdc > 0.0) {
     TRY(dalloc(ctx, &ctx->e_part, static_cast<size_t>(M) * nblk_all));
@@ -927,14 +933,13 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     TRY(dalloc(ctx, &ctx->drop_theta, n_inst));
     TRY(dalloc(ctx, &ctx->drop_info, 4 * static_cast<size_t>(n_inst)));
   }
-  TRY(dalloc(ctx, &ctx->cg_iters, n_inst));
   TRY(dalloc(ctx, &ctx->cg_blk_done, nblk_all));
   TRY(dalloc(ctx, &ctx->sel_cnt, nblk_all));
   TRY(dalloc(ctx, &ctx->sel_nnz, nblk_all));
   HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i32), (8 + 2 * n_inst + 2 * M * n_inst) * sizeof(int32_t)));
-  TRY(dalloc(ctx, &ctx->hist_done, static_cast<size_t>(M) * n_inst));
-  TRY(dalloc(ctx, &ctx->hist_iters, static_cast<size_t>(M) * n_inst));
-  HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i64), (8 + n_inst) * sizeof(int64_t)));
+  TRY(dalloc(ctx, &ctx->hist_done, 2 * static_cast<size_t>(M) * n_inst));
+  ctx->hist_iters = ctx->hist_done + static_cast<size_t>(M) * n_inst;
+  HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->h_i64), map_sizes_words(n_inst) * sizeof(int64_t)));
   HIPC(hipStreamSynchronize(ctx->stream));
   // forward solves, reverse solves, forward solves of full-first-sweep steps
   // among heuristic ones

@@ -250,7 +250,7 @@ def test_pinned_front_shell_sets_match_oracle(density):
 
 
 @pytest.mark.parametrize("P", [config0(n=200, theta=1e-6, n_steps=10), config1(n=33, theta=1e-7, n_steps=4),
-                               config2(n=7, theta=1e-7, n_steps=3)], ids=["1d", "2d", "3d"])
+                               config2(n=10, theta=1e-7, n_steps=3)], ids=["1d", "2d", "3d"])
 def test_small_sets_are_solved_in_one_launch(P):
     """Sets of one workgroup's size run the whole solve in one launch (no
     per-iteration launches in the kernel timing); with that path off, one
@@ -263,6 +263,7 @@ def test_small_sets_are_solved_in_one_launch(P):
         s.profile(False)
         print(f"[small sets] {P.name} N={P.N} small_set_rows={rows}: {launches} CG launches", flush=True)
         assert (launches > 0) == per_iteration
+        assert np.abs(gv).max() > 1e-3   # a stimulated run, not the rest state
         ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli, idx_replay=sets)
         assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
@@ -275,8 +276,10 @@ def test_ragged_2d_adaptive_run():
 
 
 def test_3d_adaptive_steps():
-    P = config2(n=9, theta=1e-7, n_steps=6)
+    P = config2(n=11, theta=1e-7, n_steps=6)   # the smallest grids miss the stimulus balls
+    assert all(len(nodes) > 0 for _, nodes, _ in P.stimuli)
     gv, gw, sets, _, _ = gpu_run(P, P.n_steps)
+    assert np.abs(gv).max() > 1e-3
     ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli, idx_replay=sets)
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
