@@ -35,7 +35,13 @@ struct MapBuf {
   std::vector<int64_t> nnz;
 
   Map dev() const { return Map{rec, inst_blk0, inst_nblk, idx, nblk, n_inst}; }
-  double* tot_if_large(double* tot) const { return max_nb > kTotBlocks ? tot : nullptr; }
+  // the per-instance totals pass: for instances over kTotBlocks blocks, and
+  // on maps long enough (over kTotMapBlocks blocks, i.e. launches that
+  // stream from HBM) that one more launch costs less than every block
+  // re-reading its instance's partials (instances over kTotMinBlocks)
+  double* tot_if_large(double* tot) const {
+    return max_nb > kTotBlocks || (nblk > kTotMapBlocks && max_nb > kTotMinBlocks) ? tot : nullptr;
+  }
   NextMap next(const int64_t* node_off, const int32_t* dia_off, int nd) const {
     return NextMap{rec, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals, node_off, dia_off, nd};
   }

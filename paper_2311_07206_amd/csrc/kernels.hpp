@@ -128,6 +128,8 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     int maxit, const CgState& cg, double* tot, hipEvent_t ev_start = nullptr,
                     hipEvent_t ev_stop = nullptr);
 constexpr int kTotBlocks = 4 * kBlock;
+constexpr int kTotMapBlocks = 4096;
+constexpr int kTotMinBlocks = 64;
 // The whole restricted PCG of each instance in one workgroup of kWgThreads
 // threads, rows_per_thread (1 or 2) rows each, for maps whose instances hold
 // at most kWgThreads * rows_per_thread rows: x (zero on entry) receives the
