@@ -111,3 +111,24 @@ def test_binding_structures_match_the_header_layout(root, tmp_path):
         assert got == int(value), (pyname, field, got, value)
         n_checked += 1
     assert n_checked == sum(len(getattr(_lib, p)._fields_) + 1 for p in _STRUCTS.values())
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built HIP library the binding raises."""
+    from paper_2311_07206_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libsdc.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.load()
+
+
+def test_product_package_does_not_import_the_oracle(root):
+    import ast
+    pkg = os.path.join(root, "paper_2311_07206_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            tree = ast.parse(open(os.path.join(pkg, fn)).read())
+            for node in ast.walk(tree):
+                names = [a.name for a in node.names] if isinstance(node, ast.Import) else \
+                    [node.module or ""] if isinstance(node, ast.ImportFrom) else []
+                assert not any(n.split(".")[0] == "oracle" for n in names), fn
