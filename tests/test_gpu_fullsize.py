@@ -112,6 +112,27 @@ def test_3d_full_size_assembly_and_restricted_pcg():
         assert abs(it[0] - ito) <= 1
 
 
+def test_3d_full_size_steps_diagonal_equal_csr_bitwise():
+    """Two steps of the 128^3 workload from the stimulus: the first sweeps'
+    all-rows launches in diagonal storage (two rows per thread, paired loads
+    in interior blocks, per-instance totals pass) against CSR storage (one
+    row per thread), and the listed sets of the later sweeps, bit for bit."""
+    P = config2()
+    out = []
+    for fmt in (2, 1):
+        s = _solver(P, fmt=fmt)
+        assert s.info()["format"] == {2: "dia", 1: "csr"}[fmt]
+        v = torch.tensor(P.v_init, device=DEV)
+        w = torch.tensor(P.w_init, device=DEV)
+        for n in range(2):
+            print(f"[3d full] storage {fmt} step {n}", flush=True)
+            s.step(v, w, n * P.dt)
+        out.append((v.cpu().numpy(), w.cpu().numpy()))
+        s.close()
+    assert np.abs(out[0][0]).max() > 0.5   # the stimulus is in
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def test_emi_full_size_assembly_and_restricted_pcg():
     from oracle.emi import EMI, build as emi_build
     P = config3()
