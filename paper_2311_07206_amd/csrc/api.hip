@@ -409,13 +409,16 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
   }
   if (ctx->first_subset() && ctx->k == 0) {
     // the set this step carries to the next one's first sweep: that of the
-    // second sweep (or, without a selection, this sweep's own)
-    if (ctx->cur < 0) {
+    // second sweep, or this sweep's own with one sweep per step (sdc_sweep
+    // selects a next set even then; mb's slot is not the one it wrote)
+    const bool own = ctx->prm.K == 1;
+    const MapBuf& cm = own ? mb : ctx->curmap();
+    if (own ? ident : ctx->cur < 0) {
       ctx->carry_n = -1;
     } else {
-      launch_map_rows(ctx->stream, ctx->curmap().dev(), ctx->carry_list);
+      launch_map_rows(ctx->stream, cm.dev(), ctx->carry_list);
       HIPC(hipGetLastError());
-      ctx->carry_n = ctx->curmap().rows;
+      ctx->carry_n = cm.rows;
     }
   }
   if (ctx->terminate()) {

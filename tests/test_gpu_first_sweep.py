@@ -112,6 +112,20 @@ def test_first_sweep_set_with_termination_and_apriori_drop():
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
 
+def test_first_sweep_set_with_one_sweep_per_step():
+    """K = 1: no selection happens, the step carries its first sweep's own set."""
+    P = config0(theta=1e-6)
+    K = 1
+    s = _solver(P, K=K, first_rings=2, first_full_every=0)
+    gv, gw, sets = _run_gpu(P, s, 8, K)
+    adj = mesh_adjacency(P.elems, P.N)
+    # the first step takes all rows and carries them: the set stays all rows
+    assert all(np.array_equal(st[0], np.arange(P.N)) for st in sets)
+    ov, ow = _oracle_replay(build(P), P, 8, K, sets)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+    assert np.array_equal(first_sweep_set(adj, np.arange(P.N), [], 2), np.arange(P.N))
+
+
 def test_first_sweep_set_with_the_linearized_scheme():
     P = config1(n=33, theta=1e-7)
     s = _solver(P, scheme="linearized", first_rings=3, first_full_every=0)

@@ -268,6 +268,27 @@ def test_small_sets_are_solved_in_one_launch(P):
         assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
 
+def test_solve_path_switches_within_a_step():
+    """A threshold between the all-rows set and the later sets: the first
+    sweep launches per iteration, smaller sweeps solve in one launch."""
+    P = config0(n=200, theta=1e-6, n_steps=12)
+    s = _solver(P, small_set_rows=150)
+    s.profile(True)
+    gv, gw, sets, stats, _ = gpu_run(P, P.n_steps, s=s)
+    assert s.profile_read()["cg_launches"] > 0
+    s.profile(False)
+    assert any(0 < len(st) <= 150 for step in sets for st in step[1:])
+    ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli, idx_replay=sets)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+    # the synchronous and the asynchronous sweeps agree bitwise across the switch
+    s2 = _solver(P, small_set_rows=150)
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    for n in range(P.n_steps):
+        s2.step(v, w, n * P.dt)
+    assert np.array_equal(v.cpu().numpy(), gv) and np.array_equal(w.cpu().numpy(), gw)
+
+
 def test_ragged_2d_adaptive_run():
     P = config1(n=23, theta=1e-7, n_steps=12)
     gv, gw, sets, _, _ = gpu_run(P, P.n_steps)
