@@ -358,6 +358,18 @@ def test_full_size_2d_steps():
     assert stats[0][0]["n_active"] == 512 * 512
 
 
+def test_full_size_3d_steps():
+    # the 128^3 workload at full size: two steps from the stimulus, the first
+    # sweeps on all 2.1 M rows (about a minute of oracle work on the host)
+    P = config2(theta=1e-7, n_steps=2)
+    gv, gw, sets, stats, _ = gpu_run(P, P.n_steps)
+    print("[3d full steps] oracle replay", flush=True)
+    ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli, idx_replay=sets)
+    print(f"[3d full steps] rel v {rel(gv, ov):.2e} w {rel(gw, ow):.2e}", flush=True)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+    assert stats[0][0]["n_active"] == P.N and all(len(st) < P.N for st in sets[1][1:])
+
+
 def test_large_2d_step():
     # one adaptive step on 600 x 600 (over 1024 blocks per sweep at the start)
     P = config1(n=600, theta=1e-7, n_steps=1)
