@@ -132,3 +132,31 @@ def test_emi3d_full_size_assembly_and_restricted_pcg():
         rel = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
         print(f"  iters gpu {it[0]} oracle {ito}; rel {rel:.2e}", flush=True)
         assert rel < 1e-11
+
+
+def test_emi3d_full_size_step_matches_oracle():
+    """The 3D cell-by-cell workload at full size (209,672 potential dofs):
+    the step from the stimulus, the oracle replaying the GPU's sets (about a
+    minute and a half of oracle work on the host)."""
+    P = config5()
+    s = _solver(P)
+    u = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    s.begin_step(u, w, 0.0)
+    sets = [None]
+    for k in range(P.K):
+        print(f"[emi3d full step] sweep {k}", flush=True)
+        s.sweep()
+        if k + 1 < P.K:
+            sets.append(s.active().cpu().numpy().astype(np.int64))
+    s.end_step(u, w)
+    ug, wg = u.cpu().numpy(), w.cpu().numpy()
+    print("[emi3d full step] oracle replay", flush=True)
+    uo, wo, _ = run(build(P), P.v_init, P.w_init[P.mem_intra], 1, P.K, P.stimuli, idx_replay=[sets])
+    si, se = P.mem_intra, P.mem_extra
+    vg, vo = ug[si] - ug[se], uo[si] - uo[se]
+    print(f"[emi3d full step] v rel {np.linalg.norm(vg - vo) / np.linalg.norm(vo):.2e}", flush=True)
+    assert np.linalg.norm(vg - vo) <= 1e-10 * np.linalg.norm(vo)
+    assert np.abs(wg[si] - wo).max() <= 1e-10 * max(np.abs(wo).max(), 1e-3)
+    assert np.linalg.norm(mean_free(ug) - mean_free(uo)) <= 1e-10 * np.linalg.norm(uo)
+    assert np.linalg.norm(ug - uo) <= 1e-6 * np.linalg.norm(uo)
