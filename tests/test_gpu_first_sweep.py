@@ -101,6 +101,22 @@ def test_first_sweep_sets_and_states_match_oracle(case):
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
 
+def test_first_sweep_sets_full_size_3d():
+    """The 128^3 workload with the benchmarked settings (3 rings, all rows
+    every 10th step): three steps from the stimulus, every first-sweep set
+    bit-exact with the oracle's rule and the states with the oracle's replay
+    (about a minute of oracle work on the host)."""
+    P = config2(theta=1e-7)
+    s = _solver(P, first_rings=3, first_full_every=10)
+    print(f"[first sweep 3d full] N={P.N}", flush=True)
+    gv, gw, sets = _run_gpu(P, s, 3, P.K)
+    assert _check_first_sets(P, sets, 3, 10) == 2
+    print(f"[first sweep 3d full] first-sweep rows {[st[0].size for st in sets]}; oracle replay", flush=True)
+    ov, ow = _oracle_replay(build(P), P, 3, P.K, sets)
+    print(f"[first sweep 3d full] rel v {rel(gv, ov):.2e} w {rel(gw, ow):.2e}", flush=True)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+
+
 def test_first_sweep_set_with_termination_and_apriori_drop():
     P = config4(n_inst=2, sizes=(12, 16), n_steps=5)
     K, tol, rho = 6, 1e-5, 0.3
