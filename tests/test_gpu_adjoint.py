@@ -170,3 +170,62 @@ def test_checkpoint_interval_does_not_change_gradients():
     for g in grads[1:]:
         for x, y in zip(grads[0], g):
             assert np.array_equal(x, y)
+
+
+def _instance(P, i):
+    from workloads.configs import Problem
+    lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
+    e0, e1 = int(P.elem_off[i]), int(P.elem_off[i + 1])
+    stim = [(t, nodes[(nodes >= lo) & (nodes < hi)] - lo, val) for t, nodes, val in P.stimuli]
+    return Problem(name="inst", dim=P.dim, coords=P.coords[lo:hi], elems=P.elems[e0:e1] - lo,
+                   elem_tensor=P.elem_tensor[e0:e1], node_sigma=P.node_sigma[lo:hi],
+                   node_off=np.array([0, hi - lo]), elem_off=np.array([0, e1 - e0]),
+                   ionic=P.ionic[i:i + 1], M=P.M, K=P.K, dt=P.dt, n_steps=P.n_steps, theta=P.theta,
+                   cg_rtol=P.cg_rtol, cg_maxit=P.cg_maxit, stimuli=stim,
+                   v_init=P.v_init[lo:hi], w_init=P.w_init[lo:hi])
+
+
+def test_adjoint_full_size_batched_sampled_instances():
+    """The full 48-instance workload (3.7 M dofs): the reverse step of the
+    whole context with the adjoint seeded on one instance, against the
+    oracle's tangent-linear model of that instance alone (its smallest and
+    its largest), all directions at once."""
+    P = config4()
+    s = _solver(P)
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    for n in range(2):
+        s.step(v, w, n * P.dt)
+    t = 2 * P.dt
+    v0, w0 = v.cpu().numpy(), w.cpu().numpy()
+    sets = _gpu_sets(s, P, v0, w0, t)
+    sizes = np.diff(P.node_off)
+    rng = np.random.default_rng(23)
+    for i in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
+        n = hi - lo
+        print(f"[adjoint full] instance {i} ({n} dofs)", flush=True)
+        lam_v, lam_w = np.zeros(P.N), np.zeros(P.N)
+        lam_v[lo:hi] = rng.standard_normal(n)
+        lam_w[lo:hi] = rng.standard_normal(n)
+        ds, dv, dw = rng.standard_normal(n) * P.node_sigma[lo:hi], rng.standard_normal(n), rng.standard_normal(n)
+        da = rng.standard_normal()
+        Lv = torch.tensor(lam_v, device=DEV)
+        Lw = torch.tensor(lam_w, device=DEV)
+        gs = torch.zeros(P.N, dtype=torch.float64, device=DEV)
+        ga = torch.zeros(P.n_inst, dtype=torch.float64, device=DEV)
+        s.adjoint_step(torch.tensor(v0, device=DEV), torch.tensor(w0, device=DEV), t, Lv, Lw, gs, ga)
+        Lv, Lw, gs, ga = (x.cpu().numpy() for x in (Lv, Lw, gs, ga))
+        # the other instances see no adjoint
+        assert not np.any(Lv[:lo]) and not np.any(Lv[hi:]) and not np.any(gs[:lo]) and not np.any(gs[hi:])
+        sub = _instance(P, i)
+        sub_sets = [np.arange(n)] + [x[(x >= lo) & (x < hi)] - lo for x in sets[1:]]
+        tp = tlm.TLMProblem(sub)
+        _, _, vt, wt = tlm.step(tp, sub.node_sigma, sub.ionic[:, 1].copy(), v0[lo:hi], w0[lo:hi], sub_sets,
+                                ds, np.array([da]), dv, dw)
+        lhs = lam_v[lo:hi] @ vt + lam_w[lo:hi] @ wt
+        rhs = Lv[lo:hi] @ dv + Lw[lo:hi] @ dw + gs[lo:hi] @ ds + ga[i] * da
+        scale = abs(lam_v[lo:hi]) @ abs(vt) + abs(lam_w[lo:hi]) @ abs(wt)
+        print(f"[adjoint full] instance {i}: lhs {lhs:.6e} rhs {rhs:.6e} rel {abs(lhs - rhs) / scale:.2e}",
+              flush=True)
+        assert abs(lhs - rhs) <= 1e-8 * scale, (lhs, rhs)
