@@ -156,44 +156,54 @@ def test_emi_full_size_assembly_and_restricted_pcg():
         assert rel(x.cpu().numpy(), xo) < 1e-11
 
 
-def _full_2d_step(P, s, n_steps=1, drop=False):
+def _full_2d_step(P, s, n_steps=1, drop=False, K=None):
+    K = P.K if K is None else K
     v = torch.tensor(P.v_init, device=DEV)
     w = torch.tensor(P.w_init, device=DEV)
     sets, drops = [], []
     for n in range(n_steps):
         s.begin_step(v, w, n * P.dt)
         step_sets = [None]
-        for k in range(P.K):
-            s.sweep()
+        for k in range(K):
+            st = s.sweep()
             if k == 0 and drop:
                 drops.append(s.drop_tolerance())
-            if k + 1 < P.K:
-                step_sets.append(s.active().cpu().numpy().astype(np.int64))
+            if k + 1 == K or st["n_stopped"] == P.n_inst:
+                break
+            step_sets.append(s.active().cpu().numpy().astype(np.int64))
         s.end_step(v, w)
         sets.append(step_sets)
     return v.cpu().numpy(), w.cpu().numpy(), sets, drops
 
 
-@pytest.mark.parametrize("option", ["linearized", "apriori"])
+@pytest.mark.parametrize("option", ["linearized", "apriori", "termination"])
 def test_2d_full_size_options_match_oracle(option):
     """The 512^2 workload (262,144 dofs), two steps from the stimulus, with the
-    paper's linearized scheme or with the a-priori drop tolerance (TOL 1e-6,
-    rho 0.3, all K sweeps): the oracle replays the GPU's sets."""
+    paper's linearized scheme, with the a-priori drop tolerance (TOL 1e-6,
+    rho 0.3, all K sweeps), or with the energy-norm termination (TOL 1e-5,
+    rho 0.3, 2 to 6 sweeps): the oracle replays the GPU's sets and ends each
+    step after the same number of sweeps."""
     from oracle.sdc import apply_stimuli
     P = config1()
+    K = P.K
     if option == "linearized":
         s = _solver(P, scheme="linearized")
         orc = build(P, scheme="linearized")
-    else:
+    elif option == "apriori":
         s = _solver(P, tol_sdc=1e-6, rho=0.3, K_min=P.K, drop="apriori")
         orc = build(P, tol_sdc=1e-6, rho=0.3, K_min=P.K, drop="apriori")
+    else:
+        K = 6
+        s = _solver(P, K=K, tol_sdc=1e-5, rho=0.3, K_min=2)
+        orc = build(P, tol_sdc=1e-5, rho=0.3, K_min=2)
     print(f"[2d full {option}] GPU", flush=True)
-    gv, gw, sets, drops = _full_2d_step(P, s, n_steps=2, drop=option == "apriori")
+    gv, gw, sets, drops = _full_2d_step(P, s, n_steps=2, drop=option == "apriori", K=K)
     v, w = P.v_init.copy(), P.w_init.copy()
     for n in range(2):
-        print(f"[2d full {option}] oracle step {n}", flush=True)
+        print(f"[2d full {option}] oracle step {n} ({len(sets[n])} sweeps on the GPU)", flush=True)
         apply_stimuli(v, n * P.dt, P.dt, P.stimuli)
-        v, w, infos = orc.step(v, w, P.K, idx_replay=sets[n])
+        v, w, infos = orc.step(v, w, K, idx_replay=sets[n])
+        assert len(infos) == len(sets[n])
         if option == "apriori":
             assert np.array_equal(drops[n]["r"], infos[0]["drop_r"])
             assert np.allclose(drops[n]["tol_drop"], infos[0]["drop_tol"], rtol=1e-10, atol=0)
