@@ -118,6 +118,10 @@ typedef struct {
   /* (2048 rows; 1024 when a row of A has more than 8 stored entries);       */
   /* -1: never.  Same stopping rule, results equal to rounding.              */
   int32_t small_set_rows;
+  /* CG launches over all rows with diagonal storage of 3, 7 or 19          */
+  /* diagonals: 1 or 2 rows per thread, 0 = the faster of the two, timed on  */
+  /* one CG iteration at setup.  Bitwise the same results either way.        */
+  int32_t rows_per_thread;
 } sdc_params;
 
 /* Per-sweep statistics (sums over instances unless stated). */
@@ -327,14 +331,20 @@ typedef struct {
 
 /* Setup outcome: storage in use (1 CSR, 2 diagonal), diagonals per row in the
  * diagonal storage (0 if not available), the setup timings of one SpMV-shaped
- * CG start launch over all rows in each storage (0 if not timed), and the
- * number of steps redone because a predicted CG budget was too small. */
+ * CG start launch over all rows in each storage (0 if not timed), the
+ * number of steps redone because a predicted CG budget was too small, the
+ * rows per thread of the all-rows CG launches, and the setup timings of one
+ * all-rows CG iteration with one and with two rows per thread (0 if not
+ * timed). */
 typedef struct {
   int32_t format;
   int32_t n_diagonals;
   double t_csr_us;
   double t_dia_us;
   int64_t redone_steps;
+  int32_t rows_per_thread;
+  double t_rows1_us;
+  double t_rows2_us;
 } sdc_info;
 
 int sdc_get_info(sdc_ctx* ctx, sdc_info* out);

@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
                 ("cg_rtol", c_double), ("cg_maxit", c_int32), ("format", c_int32),
                 ("K_min", c_int32), ("tol_sdc", c_double), ("rho", c_double), ("drop_mode", c_int32),
                 ("scheme", c_int32), ("first_rings", c_int32), ("first_full_every", c_int32),
-                ("small_set_rows", c_int32)]
+                ("small_set_rows", c_int32), ("rows_per_thread", c_int32)]
 
 
 class SweepStats(ctypes.Structure):
@@ -56,7 +56,8 @@ class ProfileStats(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("format", c_int32), ("n_diagonals", c_int32), ("t_csr_us", c_double),
-                ("t_dia_us", c_double), ("redone_steps", c_int64)]
+                ("t_dia_us", c_double), ("redone_steps", c_int64), ("rows_per_thread", c_int32),
+                ("t_rows1_us", c_double), ("t_rows2_us", c_double)]
 
 
 class Emi(ctypes.Structure):

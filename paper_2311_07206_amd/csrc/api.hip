@@ -175,7 +175,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
         launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
                        ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
                        ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
-                       timed ? ctx->ev[2 * b] : nullptr,
+                       ctx->pair_all, timed ? ctx->ev[2 * b] : nullptr,
                        timed ? ctx->ev[2 * b + 1] : nullptr);
       }
       HIPC(hipGetLastError());
@@ -263,7 +263,7 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
     const int a = it & 1, o = a ^ 1;
     launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
                    ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
-                   rtol2, ctx->prm.cg_maxit, cg, mb.tot_if_large(ctx->cg_tot),
+                   rtol2, ctx->prm.cg_maxit, cg, mb.tot_if_large(ctx->cg_tot), ctx->pair_all,
                    timed ? ctx->ev[2 * (*ev_off + it)] : nullptr,
                    timed ? ctx->ev[2 * (*ev_off + it) + 1] : nullptr);
   }
@@ -562,6 +562,67 @@ int autotune(sdc_ctx* ctx) {
   return SDC_OK;
 }
 
+// Rows per thread of the CG launches over all rows with diagonal storage
+// (rows_per_thread 0): a CG started from b = ML on all rows, its first
+// iteration, then alternating rounds of its second iteration with one and
+// with two rows per thread.  That launch reads one parity of the buffers and
+// writes the other (x and p in place), so every repetition has the same
+// inputs and the same work; the fastest round of each counts, and two rows
+// stay unless one row is faster by 3 %.  The work buffers are cleared after.
+int tune_rows_per_thread(sdc_ctx* ctx) {
+  ctx->pair_all = ctx->prm.rows_per_thread != 1;
+  if (!ctx->use_dia || ctx->prm.rows_per_thread != 0 || !compiled_diagonals(ctx->nd)) return SDC_OK;
+  const Map map = ctx->all.dev();
+  const Mat H = ctx->H(0);
+  const int64_t N = ctx->N;
+  double* const tot = ctx->all.tot_if_large(ctx->cg_tot);
+  const auto iterate = [&](int it, bool pair) {
+    const int a = it & 1, o = a ^ 1;
+    launch_cg_iter(ctx->stream, map, N, H, ctx->dinv, ctx->dv, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
+                   ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o], 0.0,
+                   ctx->prm.cg_maxit + 2, ctx->cg(), tot, pair);
+  };
+  launch_copy_b(ctx->stream, map, ctx->ml, ctx->r[0], ctx->dv);
+  launch_cg_start(ctx->stream, map, ctx->n_inst, N, H, ctx->dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0],
+                  ctx->cg());
+  iterate(0, true);
+  HIPC(hipGetLastError());
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  double t[2] = {1e30, 1e30};   // one row, two rows per thread
+  const int reps = 10;
+  for (int round = 0; round < 4; ++round)
+    for (int v = 0; v < 2; ++v) {
+      iterate(1, v == 1);
+      HIPC(hipEventRecord(e0, ctx->stream));
+      for (int rep = 0; rep < reps; ++rep) iterate(1, v == 1);
+      HIPC(hipEventRecord(e1, ctx->stream));
+      HIPC(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPC(hipEventElapsedTime(&ms, e0, e1));
+      t[v] = std::min(t[v], 1e3 * ms / reps);
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPC(hipGetLastError());
+  ctx->t_rows_us[0] = t[0];
+  ctx->t_rows_us[1] = t[1];
+  ctx->pair_all = !(t[0] < 0.97 * t[1]);
+  // back to the state a new context has
+  for (int q = 0; q < 2; ++q) {
+    for (double* b : {ctx->r[q], ctx->wv[q], ctx->s[q]}) HIPC(hipMemsetAsync(b, 0, N * 8, ctx->stream));
+    HIPC(hipMemsetAsync(ctx->part[q], 0, 4 * sizeof(double) * ctx->all.nblk, ctx->stream));
+    HIPC(hipMemsetAsync(ctx->cg_scal[q], 0, kScal * sizeof(double) * ctx->n_inst, ctx->stream));
+  }
+  HIPC(hipMemsetAsync(ctx->p, 0, N * 8, ctx->stream));
+  HIPC(hipMemsetAsync(ctx->dv, 0, static_cast<size_t>(ctx->prm.M) * N * 8, ctx->stream));
+  HIPC(hipMemsetAsync(ctx->cg_done, 0, 2 * ctx->n_inst * sizeof(int32_t), ctx->stream));
+  HIPC(hipMemsetAsync(ctx->cg_blk_done, 0, ctx->all.nblk * sizeof(int32_t), ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));
+  return SDC_OK;
+}
+
 // Spread the saved start state (v0, w0) to all nodes; all rows active.
 bool stimulus_applies(const Stimulus& s, double t, double dt) {
   return t - 1e-9 * dt <= s.t_on && s.t_on < t + dt - 1e-9 * dt;
@@ -769,6 +830,8 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     return fail(ctx, SDC_ERR_ARG, "the linearized scheme is implemented for the monodomain model only");
   if (prm->first_rings < 0) return fail(ctx, SDC_ERR_ARG, "first_rings must be >= 0");
   if (prm->small_set_rows < -1) return fail(ctx, SDC_ERR_ARG, "small_set_rows must be >= -1");
+  if (prm->rows_per_thread < 0 || prm->rows_per_thread > 2)
+    return fail(ctx, SDC_ERR_ARG, "rows_per_thread must be 0, 1 or 2");
   if (prm->first_rings > 0 && emi)
     return fail(ctx, SDC_ERR_ARG, "the heuristic first-sweep set is implemented for the monodomain model only");
   if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
@@ -952,6 +1015,7 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   ctx->tensor_h.assign(elem_tensor, elem_tensor + E * dim * dim);
   ctx->n_elem = E;
   TRY(autotune(ctx));
+  TRY(tune_rows_per_thread(ctx));
   ctx->pin.assign(SDC_MAX_SWEEPS, nullptr);
   ctx->pin_n.assign(SDC_MAX_SWEEPS, 0);
   ctx->ready = true;
@@ -1172,6 +1236,9 @@ int sdc_get_info(sdc_ctx* ctx, sdc_info* out) {
   out->t_csr_us = ctx->t_csr_us;
   out->t_dia_us = ctx->t_dia_us;
   out->redone_steps = ctx->redone_steps;
+  out->rows_per_thread = ctx->use_dia && ctx->pair_all && compiled_diagonals(ctx->nd) ? 2 : 1;
+  out->t_rows1_us = ctx->t_rows_us[0];
+  out->t_rows2_us = ctx->t_rows_us[1];
   return SDC_OK;
 }
 

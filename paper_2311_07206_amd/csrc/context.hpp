@@ -94,6 +94,10 @@ struct sdc_ctx {
   double *dia_A = nullptr, *dia_H = nullptr;   // [nd/2+1][N], [M][nd/2+1][N] (offsets >= 0)
   bool use_dia = false;
   double t_csr_us = 0.0, t_dia_us = 0.0;
+  // all-rows CG launches with diagonal storage: two rows per thread (else
+  // one), and the setup timings of one and two rows per thread (0: not timed)
+  bool pair_all = true;
+  double t_rows_us[2] = {0.0, 0.0};
   int64_t* node_off_d = nullptr;
   double* ionic_d = nullptr;
   // cell-by-cell model (see sdc_emi): membrane partner, signed site length,

@@ -1525,11 +1525,18 @@ void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const
   });
 }
 
+bool compiled_diagonals(int nd) {
+  bool fixed = false;
+  dispatch_storage(nd, [&](auto st) { fixed = decltype(st)::value > 0; });
+  return fixed;
+}
+
 void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
                     double* x, double* p, const double* u_in, const double* w_in, const double* s_in,
                     double* u_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
-                    int maxit, const CgState& cg, double* tot, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                    int maxit, const CgState& cg, double* tot, bool pair_all, hipEvent_t ev_start,
+                    hipEvent_t ev_stop) {
   if (map.nblk <= 0) return;
   const double* pin = part_in;
   if (tot) {
@@ -1555,9 +1562,10 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
       constexpr bool T = decltype(tt)::value;
       if (map.idx) {
         it == 0 ? go(k_cg_iter<S, true, 1, T>, kBlock) : go(k_cg_iter<S, false, 1, T>, kBlock);
-      } else if constexpr (S > 0) {
+      } else if (S > 0 && pair_all) {
         // every row of the instances: two rows per thread
-        it == 0 ? go(k_cg_iter2<S, true, T>, kPairThreads) : go(k_cg_iter2<S, false, T>, kPairThreads);
+        if constexpr (S > 0)
+          it == 0 ? go(k_cg_iter2<S, true, T>, kPairThreads) : go(k_cg_iter2<S, false, T>, kPairThreads);
       } else {
         it == 0 ? go(k_cg_iter<S, true, 0, T>, kBlock) : go(k_cg_iter<S, false, 0, T>, kBlock);
       }

@@ -121,12 +121,17 @@ void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const
                      const CgState& cg);
 // One CG launch; u, w, s are the preconditioner-scaled vectors dinv r,
 // dinv H u and dinv H p (read from one buffer, written to the other).
+// pair_all: maps without a list and diagonal storage take two rows per
+// thread (else one); both give bitwise the same results.  compiled_diagonals:
+// the diagonal count has a compile-time instantiation (3, 7, 19), where two
+// rows per thread are available.
+bool compiled_diagonals(int nd);
 void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
                     double* x, double* p, const double* u_in, const double* w_in, const double* s_in,
                     double* u_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, double rtol2,
-                    int maxit, const CgState& cg, double* tot, hipEvent_t ev_start = nullptr,
-                    hipEvent_t ev_stop = nullptr);
+                    int maxit, const CgState& cg, double* tot, bool pair_all = true,
+                    hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 constexpr int kTotBlocks = 4 * kBlock;
 constexpr int kTotMapBlocks = 4096;
 constexpr int kTotMinBlocks = 64;

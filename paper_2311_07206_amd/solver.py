@@ -44,7 +44,7 @@ class Solver:
     def __init__(self, coords, elems, elem_tensor, node_sigma, ionic, node_off, elem_off,
                  M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None, emi=None,
                  tol_sdc=0.0, rho=0.05, K_min=1, drop="theta", scheme="imex", first_rings=0,
-                 first_full_every=10, small_set_rows=0):
+                 first_full_every=10, small_set_rows=0, rows_per_thread=0):
         """emi: None (monodomain) or a dict with the cell-by-cell couplings
         mem_intra, mem_extra, mem_len, cm, gap_a, gap_b, gap_len, g_gap,
         robin_len, eps (see sdc_emi).  drop: "theta" (fixed drop tolerance)
@@ -55,7 +55,9 @@ class Solver:
         of mesh neighbours, with all rows every first_full_every steps (see
         sdc_params.first_rings).  small_set_rows: solves of at most that many
         rows per instance run in one launch each (0: up to 2048, 1024 when rows
-        hold more than 8 entries; -1: never)."""
+        hold more than 8 entries; -1: never).  rows_per_thread: all-rows CG
+        launches with diagonal storage take 1 or 2 rows per thread (0: the
+        faster, timed at setup)."""
         if drop not in ("theta", "apriori"):
             raise ValueError("drop must be 'theta' or 'apriori'")
         if scheme not in ("imex", "linearized"):
@@ -77,7 +79,8 @@ class Solver:
                      cg_maxit=int(cg_maxit), format=int(fmt), K_min=int(K_min), tol_sdc=float(tol_sdc),
                      rho=float(rho), drop_mode=1 if drop == "apriori" else 0,
                      scheme=1 if scheme == "linearized" else 0, first_rings=int(first_rings),
-                     first_full_every=int(first_full_every), small_set_rows=int(small_set_rows))
+                     first_full_every=int(first_full_every), small_set_rows=int(small_set_rows),
+                     rows_per_thread=int(rows_per_thread))
         node_off_a, p_no = _host(node_off, np.int64)
         coords_a, p_c = _host(coords, np.float64)
         elem_off_a, p_eo = _host(elem_off, np.int64)
@@ -246,11 +249,13 @@ class Solver:
             self.node_sigma = s_a.copy()
 
     def info(self):
-        """Storage in use ('csr' or 'dia'), diagonals, setup timings, redone steps."""
+        """Storage in use ('csr' or 'dia'), diagonals, setup timings, redone
+        steps, rows per thread of the all-rows CG launches and their timings."""
         st = _lib.Info()
         self._check(self.lib.sdc_get_info(self.ctx, ctypes.byref(st)))
         return {"format": {1: "csr", 2: "dia"}[st.format], "n_diagonals": st.n_diagonals,
-                "t_csr_us": st.t_csr_us, "t_dia_us": st.t_dia_us, "redone_steps": st.redone_steps}
+                "t_csr_us": st.t_csr_us, "t_dia_us": st.t_dia_us, "redone_steps": st.redone_steps,
+                "rows_per_thread": st.rows_per_thread, "t_rows1_us": st.t_rows1_us, "t_rows2_us": st.t_rows2_us}
 
     def profile(self, enable):
         """Start (and clear) or stop event timing of the CG kernels."""

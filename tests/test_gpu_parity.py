@@ -289,6 +289,29 @@ def test_solve_path_switches_within_a_step():
     assert np.array_equal(v.cpu().numpy(), gv) and np.array_equal(w.cpu().numpy(), gw)
 
 
+@pytest.mark.parametrize("P", [config0(n=300, theta=0.0, n_steps=6), config1(n=40, theta=0.0, n_steps=3),
+                               config2(n=11, theta=0.0, n_steps=2)], ids=["1d", "2d", "3d"])
+def test_rows_per_thread_of_all_rows_launches_agree_bitwise(P):
+    """Every sweep on all rows (theta = 0, one launch per CG iteration): one
+    and two rows per thread give the same bits, and the oracle's result."""
+    runs = []
+    for rpt in (1, 2):
+        s = _solver(P, rows_per_thread=rpt, small_set_rows=-1)
+        assert s.info()["format"] == "dia" and s.info()["rows_per_thread"] == rpt
+        runs.append(gpu_run(P, P.n_steps, s=s)[:2])
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    ov, ow, _ = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli)
+    assert rel(runs[0][0], ov) < 1e-10 and rel(runs[0][1], ow) < 1e-10
+
+
+def test_rows_per_thread_timed_at_setup():
+    info = _solver(config1(n=64, theta=1e-7)).info()
+    assert info["format"] == "dia" and info["rows_per_thread"] in (1, 2)
+    assert info["t_rows1_us"] > 0 and info["t_rows2_us"] > 0
+    csr = _solver(config1(n=64, theta=1e-7), fmt=1).info()
+    assert csr["rows_per_thread"] == 1 and csr["t_rows1_us"] == 0
+
+
 def test_ragged_2d_adaptive_run():
     P = config1(n=23, theta=1e-7, n_steps=12)
     gv, gw, sets, _, _ = gpu_run(P, P.n_steps)
