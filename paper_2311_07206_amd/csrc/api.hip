@@ -569,9 +569,16 @@ int autotune(sdc_ctx* ctx) {
 // writes the other (x and p in place), so every repetition has the same
 // inputs and the same work; the fastest round of each counts, and two rows
 // stay unless one row is faster by 3 %.  The work buffers are cleared after.
+// Maps under kTuneMinBlocks keep two rows untimed: such launches are
+// latency-bound, the two variants time alike within noise, and a timed
+// choice there would only make otherwise identical runs differ.
+constexpr int kTuneMinBlocks = 2048;
+
 int tune_rows_per_thread(sdc_ctx* ctx) {
   ctx->pair_all = ctx->prm.rows_per_thread != 1;
-  if (!ctx->use_dia || ctx->prm.rows_per_thread != 0 || !compiled_diagonals(ctx->nd)) return SDC_OK;
+  if (!ctx->use_dia || ctx->prm.rows_per_thread != 0 || !compiled_diagonals(ctx->nd) ||
+      ctx->all.nblk < kTuneMinBlocks)
+    return SDC_OK;
   const Map map = ctx->all.dev();
   const Mat H = ctx->H(0);
   const int64_t N = ctx->N;

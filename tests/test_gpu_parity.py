@@ -305,9 +305,12 @@ def test_rows_per_thread_of_all_rows_launches_agree_bitwise(P):
 
 
 def test_rows_per_thread_timed_at_setup():
-    info = _solver(config1(n=64, theta=1e-7)).info()
+    # timed on maps of 2048 blocks and more; smaller ones keep two rows
+    info = _solver(config1(n=800, theta=1e-7)).info()
     assert info["format"] == "dia" and info["rows_per_thread"] in (1, 2)
     assert info["t_rows1_us"] > 0 and info["t_rows2_us"] > 0
+    small = _solver(config1(n=64, theta=1e-7)).info()
+    assert small["rows_per_thread"] == 2 and small["t_rows1_us"] == 0
     csr = _solver(config1(n=64, theta=1e-7), fmt=1).info()
     assert csr["rows_per_thread"] == 1 and csr["t_rows1_us"] == 0
 
