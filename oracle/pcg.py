@@ -9,6 +9,21 @@ Stopping rule (a reading; the paper stops at an estimated energy-error
 reduction of 1e-3): ||r||_2 <= rtol * ||b||_2 over the active rows, x0 = 0.
 A zero right-hand side or an empty index set returns x = 0 after 0
 iterations.  ``fixed_iters`` replays a given iteration count instead.
+
+Optional energy-error stop (Sec. 5.1 names an estimated energy-error
+reduction; the estimator is a reading).  With x0 = 0, CG step j reduces the
+squared energy error by exactly t_j = alpha_j (r_j . z_j) (z = the
+preconditioned residual), so
+    ||x - x_n||_A^2 = sum_{j >= n} t_j   and   ||x||_A^2 - ||x - x_n||_A^2 = sum_{j < n} t_j.
+After n >= d steps the last d terms, sum_{j=n-d}^{n-1} t_j, are a lower
+estimate of the squared error of x_{n-d} (the estimate of Hestenes and
+Stiefel, with the delay d of Strakos and Tichy), and sum_{j<n} t_j is the
+squared energy of x_n.  The solve stops after step n when the residual test
+holds or when n >= d and
+    sum_{j=n-d}^{n-1} t_j <= energy_tol^2 * sum_{j<n} t_j,
+i.e. an estimated relative energy error of at most energy_tol; x_n is
+returned.  Both sums are formed left to right in j.  energy_tol = 0 (the
+default) leaves only the residual test.
 """
 import numpy as np
 
@@ -17,8 +32,10 @@ class CGNotConverged(RuntimeError):
     pass
 
 
-def jacobi_pcg(H, b, idx, rtol, maxit=1000, fixed_iters=None):
+def jacobi_pcg(H, b, idx, rtol, maxit=1000, fixed_iters=None, energy_tol=0.0, delay=0):
     """Solve H[idx, idx] x = b[idx]; return (x full-length, zero off idx; iterations)."""
+    if energy_tol > 0.0 and delay < 1:
+        raise ValueError("the energy-error stop needs a delay d >= 1")
     n = H.shape[0]
     x_full = np.zeros(n)
     idx = np.asarray(idx, dtype=np.int64)
@@ -36,15 +53,20 @@ def jacobi_pcg(H, b, idx, rtol, maxit=1000, fixed_iters=None):
     p = z.copy()
     rz = r @ z
     it = 0
+    terms = []   # t_j = alpha_j (r_j . z_j), the energy-error reduction of step j
     limit = maxit if fixed_iters is None else fixed_iters
     while it < limit:
         q = Hs @ p
         alpha = rz / (p @ q)
+        terms.append(alpha * rz)
         x = x + alpha * p
         r = r - alpha * q
         it += 1
         if fixed_iters is None and np.sqrt(r @ r) <= rtol * bnorm:
             break
+        if fixed_iters is None and energy_tol > 0.0 and it >= delay:
+            if sum(terms[it - delay:]) <= energy_tol ** 2 * sum(terms):
+                break
         z = dinv * r
         rz_new = r @ z
         beta = rz_new / rz

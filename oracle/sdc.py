@@ -116,7 +116,7 @@ class SDC:
     """
 
     def __init__(self, model, M, dt, theta, cg_rtol=1e-12, cg_maxit=1000, tol_sdc=0.0, rho=0.05, K_min=1,
-                 inst_of=None, drop="theta", scheme="imex"):
+                 inst_of=None, drop="theta", scheme="imex", cg_energy_tol=0.0, cg_delay=0):
         self.model = model
         self.col = Collocation(M)
         self.M = M
@@ -124,6 +124,9 @@ class SDC:
         self.theta = float(theta)
         self.cg_rtol = cg_rtol
         self.cg_maxit = cg_maxit
+        # optional energy-error stop of every solve (see jacobi_pcg)
+        self.cg_energy_tol = float(cg_energy_tol)
+        self.cg_delay = int(cg_delay)
         self.tol_sdc = float(tol_sdc)
         self.rho = float(rho)
         self.K_min = int(K_min)
@@ -232,7 +235,8 @@ class SDC:
             b = np.zeros(N)
             b[idx] = rhs
             fixed = None if cg_iters is None else cg_iters[m]
-            x, it = jacobi_pcg(self.H[m], b, idx, self.cg_rtol, self.cg_maxit, fixed)
+            x, it = jacobi_pcg(self.H[m], b, idx, self.cg_rtol, self.cg_maxit, fixed,
+                               self.cg_energy_tol, self.cg_delay)
             iters.append(it)
             dv[m] = x
             v[m, idx] += x[idx]
@@ -282,7 +286,8 @@ class SDC:
             b = np.zeros(N)
             b[idx] = rhs
             fixed = None if cg_iters is None else cg_iters[m]
-            x, it = jacobi_pcg(Hm, b, idx, self.cg_rtol, self.cg_maxit, fixed)
+            x, it = jacobi_pcg(Hm, b, idx, self.cg_rtol, self.cg_maxit, fixed,
+                               self.cg_energy_tol, self.cg_delay)
             iters.append(it)
             Hk.append(Hm)
             dv[m] = x
@@ -432,7 +437,7 @@ def run(sdc, v, w, n_steps, K, stimuli=(), t0=0.0, idx_replay=None, cg_replay=No
     return v, w, log
 
 
-def build(problem, tol_sdc=0.0, rho=0.05, K_min=1, drop="theta", scheme="imex"):
+def build(problem, tol_sdc=0.0, rho=0.05, K_min=1, drop="theta", scheme="imex", cg_energy_tol=0.0, cg_delay=0):
     """Assemble the oracle model and SDC integrator for a workload Problem."""
     from .assembly import lumped_mass, stiffness
     ML = lumped_mass(problem.coords, problem.elems, problem.N)
@@ -440,4 +445,5 @@ def build(problem, tol_sdc=0.0, rho=0.05, K_min=1, drop="theta", scheme="imex"):
     model = Monodomain(ML, A, problem.node_ionic())
     inst_of = np.repeat(np.arange(problem.n_inst), np.diff(problem.node_off))
     return SDC(model, problem.M, problem.dt, problem.theta, problem.cg_rtol, problem.cg_maxit,
-               tol_sdc=tol_sdc, rho=rho, K_min=K_min, inst_of=inst_of, drop=drop, scheme=scheme)
+               tol_sdc=tol_sdc, rho=rho, K_min=K_min, inst_of=inst_of, drop=drop, scheme=scheme,
+               cg_energy_tol=cg_energy_tol, cg_delay=cg_delay)
