@@ -122,6 +122,17 @@ typedef struct {
   /* diagonals: 1 or 2 rows per thread, 0 = the faster of the two, timed on  */
   /* one CG iteration at setup.  Bitwise the same results either way.        */
   int32_t rows_per_thread;
+  /* Optional energy-error stop of every CG solve (paper Sec. 5.1 stops at  */
+  /* an estimated energy-error reduction; the estimator is the library's).  */
+  /* With x0 = 0, step j lowers the squared energy error by                 */
+  /* t_j = alpha_j (r_j . z_j); a solve stops after n >= cg_delay steps     */
+  /* once the last cg_delay terms sum to at most cg_energy_tol^2 times all   */
+  /* n terms (an estimated relative energy error of x_{n - cg_delay}), or   */
+  /* at the residual test, whichever comes first.  0: off (the default);    */
+  /* > 0 needs cg_delay in 1..8.  Monodomain only, not with the reverse      */
+  /* pass.                                                                   */
+  double cg_energy_tol;
+  int32_t cg_delay;
 } sdc_params;
 
 /* Per-sweep statistics (sums over instances unless stated). */

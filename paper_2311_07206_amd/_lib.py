@@ -26,7 +26,8 @@ class Params(ctypes.Structure):
                 ("cg_rtol", c_double), ("cg_maxit", c_int32), ("format", c_int32),
                 ("K_min", c_int32), ("tol_sdc", c_double), ("rho", c_double), ("drop_mode", c_int32),
                 ("scheme", c_int32), ("first_rings", c_int32), ("first_full_every", c_int32),
-                ("small_set_rows", c_int32), ("rows_per_thread", c_int32)]
+                ("small_set_rows", c_int32), ("rows_per_thread", c_int32), ("cg_energy_tol", c_double),
+                ("cg_delay", c_int32)]
 
 
 class SweepStats(ctypes.Structure):

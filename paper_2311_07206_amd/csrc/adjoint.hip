@@ -27,6 +27,8 @@ int adjoint_setup(sdc_ctx* ctx) {
     return fail(ctx, SDC_ERR_STATE, "the reverse pass differentiates the implicit-explicit scheme (scheme 0)");
   if (ctx->first_subset())
     return fail(ctx, SDC_ERR_STATE, "the reverse pass needs first sweeps on all rows (first_rings = 0)");
+  if (ctx->prm.cg_energy_tol > 0.0)
+    return fail(ctx, SDC_ERR_STATE, "the reverse pass needs solves to the residual tolerance (cg_energy_tol = 0)");
   auto& A = ctx->adj;
   if (A.ready) return SDC_OK;
   const int nv = ctx->dim + 1, np = nv * ctx->dim / 2;

@@ -133,7 +133,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   const Map map = mb.dev();
   const Mat H = ctx->H(m);
   const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
-  const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
+  const CgStop stop = ctx->cg_stop();
   // budgets pred, pred/2, pred/4, ... (at least 2), each launched in chunks
   // that fit the event pool while kernel timing is on
   int vbudget = pred_slot >= 0 ? std::max(1, ctx->pred[pred_slot]) : 8;
@@ -142,7 +142,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   int it = 0;
   iters->assign(ni, 0);
   if (wg_solve(ctx, mb)) {
-    launch_cg_wg(ctx->stream, map, ctx->N, H, dinv, ctx->r[0], x, ctx->wg_p, rtol2, ctx->prm.cg_maxit, ctx->cg(),
+    launch_cg_wg(ctx->stream, map, ctx->N, H, dinv, ctx->r[0], x, ctx->wg_p, stop, ctx->cg(),
                  ctx->wg_rows_per_thread());
     HIPC(hipGetLastError());
     HIPC(hipMemcpyAsync(ctx->h_i32, ctx->cg_done, 2 * ni * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
@@ -174,7 +174,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
         const int a = it & 1, o = a ^ 1;
         launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
                        ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
-                       ctx->cg_scal[o], rtol2, ctx->prm.cg_maxit, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
+                       ctx->cg_scal[o], stop, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
                        ctx->pair_all, timed ? ctx->ev[2 * b] : nullptr,
                        timed ? ctx->ev[2 * b + 1] : nullptr);
       }
@@ -246,13 +246,12 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
   const Map map = mb.dev();
   const Mat H = ctx->H(m);
   const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
-  const double rtol2 = ctx->prm.cg_rtol * ctx->prm.cg_rtol;
+  const CgStop stop = ctx->cg_stop();
   const int budget = std::min(std::max(1, ctx->pred[pred_slot]) + 1, ctx->prm.cg_maxit + 1);
   // the kernels record the outcome straight into the node's history slot
   const CgState cg{ctx->hist_done + m * ni, ctx->hist_iters + m * ni, ctx->cg_blk_done};
   if (wg_solve(ctx, mb)) {
-    launch_cg_wg(ctx->stream, map, ctx->N, H, dinv, ctx->r[0], x, ctx->wg_p, rtol2, ctx->prm.cg_maxit, cg,
-                 ctx->wg_rows_per_thread());
+    launch_cg_wg(ctx->stream, map, ctx->N, H, dinv, ctx->r[0], x, ctx->wg_p, stop, cg, ctx->wg_rows_per_thread());
     HIPC(hipGetLastError());
     (*ev_budget)[m] = 0;
     return SDC_OK;
@@ -263,7 +262,7 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
     const int a = it & 1, o = a ^ 1;
     launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
                    ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
-                   rtol2, ctx->prm.cg_maxit, cg, mb.tot_if_large(ctx->cg_tot), ctx->pair_all,
+                   stop, cg, mb.tot_if_large(ctx->cg_tot), ctx->pair_all,
                    timed ? ctx->ev[2 * (*ev_off + it)] : nullptr,
                    timed ? ctx->ev[2 * (*ev_off + it) + 1] : nullptr);
   }
@@ -586,8 +585,8 @@ int tune_rows_per_thread(sdc_ctx* ctx) {
   const auto iterate = [&](int it, bool pair) {
     const int a = it & 1, o = a ^ 1;
     launch_cg_iter(ctx->stream, map, N, H, ctx->dinv, ctx->dv, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
-                   ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o], 0.0,
-                   ctx->prm.cg_maxit + 2, ctx->cg(), tot, pair);
+                   ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
+                   CgStop{0.0, 0.0, ctx->prm.cg_maxit + 2, 0}, ctx->cg(), tot, pair);
   };
   launch_copy_b(ctx->stream, map, ctx->ml, ctx->r[0], ctx->dv);
   launch_cg_start(ctx->stream, map, ctx->n_inst, N, H, ctx->dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0],
@@ -841,6 +840,12 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     return fail(ctx, SDC_ERR_ARG, "rows_per_thread must be 0, 1 or 2");
   if (prm->first_rings > 0 && emi)
     return fail(ctx, SDC_ERR_ARG, "the heuristic first-sweep set is implemented for the monodomain model only");
+  if (!(prm->cg_energy_tol >= 0.0) || !std::isfinite(prm->cg_energy_tol))
+    return fail(ctx, SDC_ERR_ARG, "cg_energy_tol must be finite and >= 0");
+  if (prm->cg_energy_tol > 0.0 && (prm->cg_delay < 1 || prm->cg_delay > kMaxDelay))
+    return fail(ctx, SDC_ERR_ARG, "the energy-error stop needs cg_delay in 1..%d", kMaxDelay);
+  if (prm->cg_energy_tol > 0.0 && emi)
+    return fail(ctx, SDC_ERR_ARG, "the energy-error CG stop is implemented for the monodomain model only");
   if (dim < 1 || dim > 3 || n_inst < 1) return fail(ctx, SDC_ERR_ARG, "dim in 1..3 and n_inst >= 1 required");
   if (node_off[0] != 0 || elem_off[0] != 0) return fail(ctx, SDC_ERR_ARG, "offsets must start at 0");
   for (int i = 0; i < n_inst; ++i)

@@ -68,6 +68,8 @@ using sdc::EmiArgs;
 using sdc::BlkRec;
 using sdc::ZeroVecs;
 using sdc::kScal;
+using sdc::CgStop;
+using sdc::kMaxDelay;
 
 struct sdc_ctx {
   int device = 0;
@@ -195,6 +197,11 @@ struct sdc_ctx {
   int64_t step_count = 0;            // steps begun since setup or the last reset
   double* mark[2] = {nullptr, nullptr};   // [N] row marks, ping-pong over the rings
   bool first_subset() const { return prm.first_rings > 0; }
+  CgStop cg_stop() const {
+    const bool e = prm.cg_energy_tol > 0.0;
+    return CgStop{prm.cg_rtol * prm.cg_rtol, e ? prm.cg_energy_tol * prm.cg_energy_tol : 0.0, prm.cg_maxit,
+                  e ? prm.cg_delay : 0};
+  }
 
   // kernel timing (bench only)
   bool prof = false;

@@ -411,6 +411,35 @@ __global__ __launch_bounds__(kBlock) void k_cg_totals(const int32_t* __restrict_
   if (threadIdx.x < 3) tot[4 * inst + threadIdx.x] = acc[threadIdx.x];
 }
 
+// Energy-error stop of launch `it` >= 1 (stop.delay >= 1): the step terms
+// t_j = alpha_j gamma_j for j < it are t_{it-1} from the previous launch's
+// scalars (sc) and the earlier ones from its ring.  Returns the running sum
+// sum_{j<it} t_j in e_sum and t_{it-1} in e_last, and whether the last
+// min(d, it) terms, summed left to right, are at most etol2 times it (the
+// test applies from it >= d).
+__device__ inline bool energy_stop(const double* sc, double sc_alpha, double sc_rz, int it, const CgStop& stop,
+                                   double& e_sum, double& e_last) {
+  const int d = stop.delay;
+  e_last = sc_alpha * sc_rz;
+  e_sum = sc[kE] + e_last;
+  double win = 0.0;
+  for (int j = max(it - d, 0); j < it - 1; ++j) win += sc[kRing + j % d];
+  win += e_last;
+  return it >= d && win <= stop.etol2 * e_sum;
+}
+
+// Block 0 of the instance carries the running sum and the ring forward.
+__device__ inline void energy_record(const double* sc, double* so, bool first, int it, int d, double e_sum,
+                                     double e_last) {
+  if (first) {
+    so[kE] = 0.0;
+    return;
+  }
+  so[kE] = e_sum;
+  for (int q = 0; q < d; ++q) so[kRing + q] = sc[kRing + q];
+  so[kRing + (it - 1) % d] = e_last;
+}
+
 template <int S, bool FIRST, int LIST, bool TOT>
 __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_done, const BlkRec* __restrict__ rec,
                                                     const int32_t* __restrict__ idx, int nblk, int it,
@@ -425,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
                                                     double* __restrict__ w_out,
                                                     double* __restrict__ s_out,
                                                     double* __restrict__ part_out,
-                                                    double* __restrict__ scal_out, double rtol2, int maxit,
+                                                    double* __restrict__ scal_out, CgStop stop,
                                                     int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   __shared__ double sh_in[16], sh_out[16];
   // first round trip: the block's map entry and stop flag, the list entry of the thread's row
@@ -455,8 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   // the Jacobi factor from the row's diagonal, as the stored dinv was formed
   const double di = 1.0 / hii;
   double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
+  const double* sc = scal_in + inst * kScal;
   if (!FIRST) {
-    const double* sc = scal_in + inst * kScal;
     sc_rz = sc[kRZ];
     sc_alpha = sc[kAlpha];
     sc_bb = sc[kBB];
@@ -492,10 +521,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     beta = gamma / sc_rz;
     alpha = gamma / (delta - beta * gamma / sc_alpha);
   }
+  double e_sum = 0.0, e_last = 0.0;
+  const bool e_stop = !FIRST && stop.delay > 0 && energy_stop(sc, sc_alpha, sc_rz, it, stop, e_sum, e_last);
   int status = 0;
   if (!isfinite(rr)) status = 3;
-  else if (rr <= rtol2 * bb) status = 1;
-  else if (it >= maxit) status = 2;
+  else if (rr <= stop.rtol2 * bb) status = 1;
+  else if (e_stop) status = 1;
+  else if (it >= stop.maxit) status = 2;
   else if (!isfinite(alpha) || !(alpha > 0.0)) status = 3;
   if (rw.bi == 0 && threadIdx.x == 0) {
     // block 0 of the instance records the outcome and the scalars
@@ -505,6 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     so[kRZ] = gamma;
     so[kAlpha] = alpha;
     so[kBB] = bb;
+    if (stop.delay > 0) energy_record(sc, so, FIRST, it, stop.delay, e_sum, e_last);
   }
   if (status != 0) {
     if (threadIdx.x == 0) blk_done[L] = status;
@@ -579,7 +612,7 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
                                                            double* __restrict__ w_out,
                                                            double* __restrict__ s_out,
                                                            double* __restrict__ part_out,
-                                                           double* __restrict__ scal_out, double rtol2, int maxit,
+                                                           double* __restrict__ scal_out, CgStop stop,
                                                            int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   static_assert(S > 0, "diagonal storage with a compile-time count");
   __shared__ double sh_in[16], sh_out[16];
@@ -652,8 +685,8 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
     }
   }
   double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
+  const double* sc = scal_in + inst * kScal;
   if (!FIRST) {
-    const double* sc = scal_in + inst * kScal;
     sc_rz = sc[kRZ];
     sc_alpha = sc[kAlpha];
     sc_bb = sc[kBB];
@@ -694,10 +727,13 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
     beta = gamma / sc_rz;
     alpha = gamma / (delta - beta * gamma / sc_alpha);
   }
+  double e_sum = 0.0, e_last = 0.0;
+  const bool e_stop = !FIRST && stop.delay > 0 && energy_stop(sc, sc_alpha, sc_rz, it, stop, e_sum, e_last);
   int status = 0;
   if (!isfinite(rr)) status = 3;
-  else if (rr <= rtol2 * bb) status = 1;
-  else if (it >= maxit) status = 2;
+  else if (rr <= stop.rtol2 * bb) status = 1;
+  else if (e_stop) status = 1;
+  else if (it >= stop.maxit) status = 2;
   else if (!isfinite(alpha) || !(alpha > 0.0)) status = 3;
   if (rw.bi == 0 && t == 0) {
     done[inst] = status;
@@ -706,6 +742,7 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
     so[kRZ] = gamma;
     so[kAlpha] = alpha;
     so[kBB] = bb;
+    if (stop.delay > 0) energy_record(sc, so, FIRST, it, stop.delay, e_sum, e_last);
   }
   if (status != 0) {
     if (t == 0) blk_done[L] = status;
@@ -1320,11 +1357,15 @@ __device__ inline void wg_sum(double (&v)[NV], double* sh /* [kWgWaves * NV] */)
 template <int S, int kWgRows>
 __global__ __launch_bounds__(kWgThreads) void k_cg_wg(Map map, int64_t N, Mat H, const double* __restrict__ dinv,
                                                       const double* __restrict__ b, double* __restrict__ x,
-                                                      double* __restrict__ pbuf, double rtol2, int maxit,
+                                                      double* __restrict__ pbuf, CgStop stop,
                                                       int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   // one LDS array per reduction of an iteration, so that a reduction never
   // overwrites values another thread may still be reading
   __shared__ double sh_a[2 * kWgWaves], sh_b[kWgWaves], sh_c[2 * kWgWaves];
+  // the energy-error stop's last step terms, t_j at ring[j % delay]; thread 0
+  // writes the slot of step it after the barrier that follows the reads of
+  // iteration it, and the reads of iteration it + 1 follow another barrier
+  __shared__ double ring[kMaxDelay];
   const int inst = static_cast<int>(blockIdx.x);
   const int t = static_cast<int>(threadIdx.x);
   const int blk0 = map.inst_blk0[inst], nb = map.inst_nblk[inst];
@@ -1367,10 +1408,17 @@ __global__ __launch_bounds__(kWgThreads) void k_cg_wg(Map map, int64_t N, Mat H,
   double rz = acc[0], rr = acc[1];
   const double bb = acc[1];
   int it = 0, status = 0;
+  const int d = stop.delay;
+  double e_sum = 0.0;   // sum_{j<it} t_j, t_j = alpha_j (r_j . z_j)
   for (;; ++it) {
     if (!isfinite(rr) || !isfinite(rz)) { status = 3; break; }
-    if (rr <= rtol2 * bb) { status = 1; break; }
-    if (it >= maxit) { status = 2; break; }
+    if (rr <= stop.rtol2 * bb) { status = 1; break; }
+    if (d > 0 && it >= d) {
+      double win = 0.0;   // sum_{j=it-d}^{it-1} t_j, left to right
+      for (int j = it - d; j < it; ++j) win += ring[j % d];
+      if (win <= stop.etol2 * e_sum) { status = 1; break; }
+    }
+    if (it >= stop.maxit) { status = 2; break; }
     __syncthreads();   // pbuf holds the direction on every row of the set
     double qv[kWgRows];
     double pq[1] = {0.0};
@@ -1387,6 +1435,11 @@ __global__ __launch_bounds__(kWgThreads) void k_cg_wg(Map map, int64_t N, Mat H,
     wg_sum<1>(pq, sh_b);
     if (!(pq[0] > 0.0)) { status = 3; break; }
     const double alpha = rz / pq[0];
+    if (d > 0) {
+      const double tj = alpha * rz;
+      e_sum += tj;
+      if (t == 0) ring[it % d] = tj;
+    }
     double nr[2] = {0.0, 0.0};   // r.z, r.r after the update
 #pragma unroll
     for (int q = 0; q < kWgRows; ++q) {
@@ -1534,8 +1587,8 @@ bool compiled_diagonals(int nd) {
 void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
                     double* x, double* p, const double* u_in, const double* w_in, const double* s_in,
                     double* u_out, double* w_out, double* s_out, int it, const double* part_in,
-                    double* part_out, const double* scal_in, double* scal_out, double rtol2,
-                    int maxit, const CgState& cg, double* tot, bool pair_all, hipEvent_t ev_start,
+                    double* part_out, const double* scal_in, double* scal_out, const CgStop& stop,
+                    const CgState& cg, double* tot, bool pair_all, hipEvent_t ev_start,
                     hipEvent_t ev_stop) {
   if (map.nblk <= 0) return;
   const double* pin = part_in;
@@ -1549,11 +1602,11 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
       // events stamped by the dispatch itself: they time the kernel's execution
       hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(threads), 0, s, ev_start, ev_stop, 0, cg.blk_done, map.rec,
                             map.idx, map.nblk, it, pin, scal_in, N, H, dinv, x, p, u_in, w_in, s_in, u_out,
-                            w_out, s_out, part_out, scal_out, rtol2, maxit, cg.done, cg.iters);
+                            w_out, s_out, part_out, scal_out, stop, cg.done, cg.iters);
     } else {
       kern<<<grid(map.nblk), threads, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, it, pin, scal_in, N, H, dinv,
-                                              x, p, u_in, w_in, s_in, u_out, w_out, s_out, part_out, scal_out, rtol2,
-                                              maxit, cg.done, cg.iters);
+                                              x, p, u_in, w_in, s_in, u_out, w_out, s_out, part_out, scal_out, stop,
+                                              cg.done, cg.iters);
     }
   };
   dispatch_storage(H.nd, [&](auto st) {
@@ -1632,15 +1685,15 @@ void launch_drop_tolerance(hipStream_t s, const Map& map, int M, int64_t N, cons
 }
 
 void launch_cg_wg(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv, const double* b,
-                  double* x, double* pbuf, double rtol2, int maxit, const CgState& cg, int rows_per_thread) {
+                  double* x, double* pbuf, const CgStop& stop, const CgState& cg, int rows_per_thread) {
   if (map.n_inst <= 0) return;
   const dim3 g(static_cast<unsigned>(map.n_inst));
   dispatch_storage(H.nd, [&](auto st) {
     constexpr int S = decltype(st)::value;
     if (rows_per_thread == 2)
-      k_cg_wg<S, 2><<<g, kWgThreads, 0, s>>>(map, N, H, dinv, b, x, pbuf, rtol2, maxit, cg.done, cg.iters);
+      k_cg_wg<S, 2><<<g, kWgThreads, 0, s>>>(map, N, H, dinv, b, x, pbuf, stop, cg.done, cg.iters);
     else
-      k_cg_wg<S, 1><<<g, kWgThreads, 0, s>>>(map, N, H, dinv, b, x, pbuf, rtol2, maxit, cg.done, cg.iters);
+      k_cg_wg<S, 1><<<g, kWgThreads, 0, s>>>(map, N, H, dinv, b, x, pbuf, stop, cg.done, cg.iters);
   });
 }
 

@@ -83,8 +83,25 @@ struct Mat {
   int nd;
 };
 
-// Per-instance CG scalars, layout [n_inst][kScal].
-enum { kRZ = 0, kBB, kAlpha, kBeta, kScal = 8 };   // kRZ holds gamma = r.z
+// Per-instance CG scalars, layout [n_inst][kScal] (one 128-byte line each).
+// kRZ holds gamma = r.z; kE the running sum of the step terms alpha_j gamma_j
+// and kRing.. the last kMaxDelay terms (term j at kRing + j % delay), kept
+// for the energy-error stop.
+enum { kRZ = 0, kBB, kAlpha, kBeta, kE, kRing = 8, kScal = 16 };
+constexpr int kMaxDelay = kScal - kRing;
+
+// Stopping rule of every CG solve.  The residual test ||r||^2 <= rtol2 ||b||^2;
+// with delay d >= 1 also the energy-error test after update n >= d
+//   sum_{j=n-d}^{n-1} t_j <= etol2 sum_{j<n} t_j,   t_j = alpha_j (r_j . z_j),
+// (the last d terms estimate the squared energy error of x_{n-d}, the full sum
+// is the squared energy of x_n, x0 = 0; Sec. 5.1 stops at an estimated
+// energy-error reduction); maxit bounds the updates.
+struct CgStop {
+  double rtol2;
+  double etol2;
+  int maxit;
+  int delay;   // 0: residual test only; 1..kMaxDelay
+};
 
 struct CgState {
   int32_t* done;       // per instance: 0 running, 1 converged, 2 maxit, 3 non-finite
@@ -129,8 +146,8 @@ bool compiled_diagonals(int nd);
 void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv,
                     double* x, double* p, const double* u_in, const double* w_in, const double* s_in,
                     double* u_out, double* w_out, double* s_out, int it, const double* part_in,
-                    double* part_out, const double* scal_in, double* scal_out, double rtol2,
-                    int maxit, const CgState& cg, double* tot, bool pair_all = true,
+                    double* part_out, const double* scal_in, double* scal_out, const CgStop& stop,
+                    const CgState& cg, double* tot, bool pair_all = true,
                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 constexpr int kTotBlocks = 4 * kBlock;
 constexpr int kTotMapBlocks = 4096;
@@ -140,11 +157,11 @@ constexpr int kTotMinBlocks = 64;
 // at most kWgThreads * rows_per_thread rows: x (zero on entry) receives the
 // solution on the set, done/iters of cg the outcome; b is the right-hand
 // side on the set; pbuf (double[N]) must be zero on entry and is zero again
-// on return.  Plain PCG (z = dinv r) with the same stopping rule as the
+// on return.  Plain PCG (z = dinv r) with the same stopping rules as the
 // launch-per-iteration kernels.
 constexpr int kWgThreads = 1024;
 void launch_cg_wg(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* dinv, const double* b,
-                  double* x, double* pbuf, double rtol2, int maxit, const CgState& cg, int rows_per_thread);
+                  double* x, double* pbuf, const CgStop& stop, const CgState& cg, int rows_per_thread);
 // Post-solve update of node m.  With the cell-by-cell model this updates the
 // potentials and amax only; launch_post_sites then updates the membrane
 // sites whose intracellular node is active, from the updated potentials.

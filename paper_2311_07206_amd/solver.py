@@ -44,7 +44,7 @@ class Solver:
     def __init__(self, coords, elems, elem_tensor, node_sigma, ionic, node_off, elem_off,
                  M, K, dt, theta, cg_rtol=1e-12, cg_maxit=1000, fmt=0, device=None, stream=None, emi=None,
                  tol_sdc=0.0, rho=0.05, K_min=1, drop="theta", scheme="imex", first_rings=0,
-                 first_full_every=10, small_set_rows=0, rows_per_thread=0):
+                 first_full_every=10, small_set_rows=0, rows_per_thread=0, cg_energy_tol=0.0, cg_delay=4):
         """emi: None (monodomain) or a dict with the cell-by-cell couplings
         mem_intra, mem_extra, mem_len, cm, gap_a, gap_b, gap_len, g_gap,
         robin_len, eps (see sdc_emi).  drop: "theta" (fixed drop tolerance)
@@ -57,7 +57,9 @@ class Solver:
         rows per instance run in one launch each (0: up to 2048, 1024 when rows
         hold more than 8 entries; -1: never).  rows_per_thread: all-rows CG
         launches with diagonal storage take 1 or 2 rows per thread (0: the
-        faster, timed at setup)."""
+        faster, timed at setup).  cg_energy_tol > 0: every CG solve also stops
+        at that estimated relative energy error, estimated over cg_delay
+        steps (see sdc_params.cg_energy_tol; 1e-3 is the paper's value)."""
         if drop not in ("theta", "apriori"):
             raise ValueError("drop must be 'theta' or 'apriori'")
         if scheme not in ("imex", "linearized"):
@@ -80,7 +82,8 @@ class Solver:
                      rho=float(rho), drop_mode=1 if drop == "apriori" else 0,
                      scheme=1 if scheme == "linearized" else 0, first_rings=int(first_rings),
                      first_full_every=int(first_full_every), small_set_rows=int(small_set_rows),
-                     rows_per_thread=int(rows_per_thread))
+                     rows_per_thread=int(rows_per_thread), cg_energy_tol=float(cg_energy_tol),
+                     cg_delay=int(cg_delay))
         node_off_a, p_no = _host(node_off, np.int64)
         coords_a, p_c = _host(coords, np.float64)
         elem_off_a, p_eo = _host(elem_off, np.int64)
