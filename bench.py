@@ -135,6 +135,8 @@ def parse():
                     help="skip the 512x512 run with the paper's linearized basic scheme")
     ap.add_argument("--no-first-sweep", action="store_true",
                     help="skip the runs with the heuristic first-sweep set")
+    ap.add_argument("--no-cg-energy", action="store_true",
+                    help="skip the runs with the energy-error CG stop (the paper's 1e-3)")
     ap.add_argument("--small-set-rows", type=int, default=0,
                     help="the latency curve's solver option (0: default one-launch solves of small sets, -1: off)")
     ap.add_argument("--no-latency", action="store_true",
@@ -316,6 +318,9 @@ def main():
     if not args.no_first_sweep:
         out["first_sweep_subset"] = first_sweep_variant(P, v_start, w_start, t_start, args.steps,
                                                         out["ms_per_step"], final["v"], final.get("v_non"))
+    if not args.no_cg_energy:
+        out["cg_energy_stop"] = cg_energy_variant(P, v_start, w_start, t_start, args.steps, out["ms_per_step"],
+                                                  final["v"], final.get("v_non"), speedup=not args.no_speedup)
     if not args.no_linearized:
         out["workload_2d_linearized"] = workload_linearized(P, v_start, w_start, t_start, min(args.steps, 100),
                                                             speedup=not args.no_speedup)
@@ -323,7 +328,8 @@ def main():
         out["batched"], out["adjoint"] = batched_and_adjoint(args.batch_steps)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio_ckpt10"]
     if not args.no_3d:
-        out["workload_3d"] = workload_3d(speedup=not args.no_speedup, first_sweep=not args.no_first_sweep)
+        out["workload_3d"] = workload_3d(speedup=not args.no_speedup, first_sweep=not args.no_first_sweep,
+                                         cg_energy=not args.no_cg_energy)
     if not args.no_emi:
         out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
         out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
@@ -492,6 +498,39 @@ def first_sweep_variant(P, v0, w0, t0, nsteps, ms_std, v_std, v_non=None, rings=
     return out
 
 
+def cg_energy_variant(P, v0, w0, t0, nsteps, ms_std, v_std, v_non=None, tol=1e-3, delay=4, speedup=True):
+    """The same timed steps with every CG solve stopped at an estimated
+    relative energy error of tol (the paper's setting, Sec. 5.1; estimated
+    over delay steps) instead of the residual tolerance: throughput, CG steps
+    per solve against the residual stop's, how far the final potential lies
+    from the residual-stop run's (and from the non-adaptive one's), and the
+    adaptive/non-adaptive speedup with the energy stop on both sides."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    s = Solver.from_problem(P, cg_energy_tol=tol, cg_delay=delay)
+    v, w = torch.tensor(v0, device=dev), torch.tensor(w0, device=dev)
+    s.step(v.clone(), w.clone(), t0)   # iteration history for the budgets
+    redone = s.info()["redone_steps"]
+    el, logs = _timed_steps(s, v, w, t0, P.dt, nsteps, torch.cuda.synchronize)
+    redone = s.info()["redone_steps"] - redone
+    s.close()
+    vf = v.cpu().numpy()
+    solves = [it for lg in logs for st in lg if st["n_active"] > 0 for it in st["cg_iters_max"]]
+    out = {"cg_energy_tol": tol, "cg_delay": delay, "value": sum(st["n_active"] for lg in logs for st in lg) / el,
+           "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
+           "speedup_vs_residual_stop": ms_std / (1e3 * el / nsteps),
+           "mean_cg_steps_per_solve": float(np.mean(solves)) if solves else 0.0,
+           "max_abs_v_vs_residual_stop": float(np.abs(vf - v_std).max()), "redone_steps": redone}
+    if v_non is not None:
+        out["max_abs_v_vs_nonadaptive"] = float(np.abs(vf - v_non).max())
+    if speedup:
+        el0 = nonadaptive_run(P, v0, w0, t0, nsteps, cg_energy_tol=tol, cg_delay=delay)
+        out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / nsteps, "speedup": el0 / el}
+    return out
+
+
 def _timed_steps(solver, v, w, t0, dt, n, sync):
     sync()
     t = time.perf_counter()
@@ -610,7 +649,7 @@ def workload_linearized(P, v0, w0, t0, nsteps, speedup=True):
     return out
 
 
-def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True):
+def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True, cg_energy=True):
     """The 128^3 3D workload (2.1M dofs, 27M stored entries): HBM-resident."""
     import torch
 
@@ -659,6 +698,9 @@ def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True):
     if first_sweep:
         out["first_sweep_subset"] = first_sweep_variant(P, v0, w0, warm * P.dt, nsteps, out["ms_per_step"], v_std,
                                                         v_non, rings=3)
+    if cg_energy:
+        out["cg_energy_stop"] = cg_energy_variant(P, v0, w0, warm * P.dt, nsteps, out["ms_per_step"], v_std, v_non,
+                                                  speedup=speedup)
     return out
 
 

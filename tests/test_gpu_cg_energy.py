@@ -121,3 +121,19 @@ def test_energy_stop_rejections():
     w = torch.tensor(P.w_init, device=DEV)
     with pytest.raises(SDCError, match="STATE"):
         s.adjoint_record(0, v, w, 0.0)
+
+
+@pytest.mark.parametrize("n,n_steps", [(512, 3), (600, 1)])
+def test_energy_stop_at_full_size(n, n_steps):
+    """The 512 x 512 workload with the paper's tolerance (1e-3) over three
+    steps from the stimulus, and 600 x 600 (over 1024 map entries per
+    instance: the separate totals pass) for one step."""
+    P = config1(n=n, theta=1e-7, n_steps=n_steps)
+    s = _solver(P, cg_energy_tol=1e-3, cg_delay=4)
+    print(f"[cg energy full] N={P.N}", flush=True)
+    gv, gw, sets, giters = _run_gpu(P, s, n_steps, P.K)
+    print(f"[cg energy full] steps per solve {giters}; oracle replay", flush=True)
+    ov, ow, oiters = _run_oracle(P, build(P, cg_energy_tol=1e-3, cg_delay=4), n_steps, P.K, sets)
+    print(f"[cg energy full] rel v {rel(gv, ov):.2e} w {rel(gw, ow):.2e}", flush=True)
+    assert giters == oiters
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
