@@ -41,29 +41,93 @@ from . import ionic
 from .assembly import stiffness
 from .collocation import Collocation
 from .pcg import jacobi_pcg
+from .sdc import apply_stimuli
+
+
+def _facets(elems):
+    """Every facet of every simplex (a simplex without one vertex), vertex
+    ids ascending, with the simplex it belongs to."""
+    e = np.asarray(elems, dtype=np.int64)
+    nv = e.shape[1]
+    f = np.concatenate([np.delete(e, q, axis=1) for q in range(nv)])
+    return np.sort(f, axis=1), np.tile(np.arange(e.shape[0]), nv)
+
+
+def _facet_measure(coords, f):
+    """Length of each edge (2D) or area of each triangle (3D)."""
+    x = coords[f]
+    if f.shape[1] == 2:
+        return np.linalg.norm(x[:, 1] - x[:, 0], axis=1)
+    return 0.5 * np.linalg.norm(np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0]), axis=1)
+
+
+def lumped_measures(coords, elems, node_cell, mem_intra, gap_a):
+    """The P1-lumped measures of the cell-by-cell couplings, from the mesh.
+
+    A coupling on a curve (2D) or surface (3D) is lumped like the mass: each
+    boundary facet gives 1/d of its measure to each of its d vertices (the
+    integral of the vertex's hat function over the facet).  The facets are
+    found from the simplices: a cell's membrane is the set of facets that
+    belong to exactly one of the cell's simplices; the outer boundary is the
+    set of facets of exactly one extracellular simplex that lie in a face of
+    the domain's bounding box; a gap-junction face of a cell is its membrane
+    in the plane x = const through the node.  Returns (membrane measure of
+    each site, at its intracellular node; gap-face measure of each pair, at
+    its first node; outer-boundary measure of every node)."""
+    coords = np.asarray(coords, dtype=np.float64)
+    N, d = coords.shape
+    f, owner = _facets(elems)
+    cell = np.asarray(node_cell)[np.asarray(elems, dtype=np.int64)[:, 0]][owner]   # subdomain of each facet's simplex
+    key = np.concatenate([cell[:, None], f], axis=1)
+    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    boundary = cnt[inv.ravel()] == 1
+    share = np.repeat(_facet_measure(coords, f) / d, d)
+    x = coords[f]                                                # [F, d, d]
+
+    def lump(mask):
+        out = np.zeros(N)
+        np.add.at(out, f[mask].ravel(), share.reshape(-1, d)[mask].ravel())
+        return out
+
+    membrane = boundary & (cell >= 0)
+    lo, hi = coords.min(axis=0), coords.max(axis=0)
+    on_box = np.zeros(len(f), dtype=bool)
+    for ax in range(d):
+        on_box |= np.all(x[:, :, ax] == lo[ax], axis=1) | np.all(x[:, :, ax] == hi[ax], axis=1)
+    in_x_plane = np.all(x[:, :, 0] == x[:, :1, 0], axis=1)
+    mem = lump(membrane)[np.asarray(mem_intra, dtype=np.int64)]
+    gap = lump(membrane & in_x_plane)[np.asarray(gap_a, dtype=np.int64)]
+    robin = lump(boundary & (cell < 0) & on_box)
+    return mem, gap, robin
 
 
 class EMI:
-    """A, M, membrane sites and ionic parameters of a cell-by-cell mesh."""
+    """A, M, membrane sites and ionic parameters of a cell-by-cell mesh.
+
+    The lumped membrane, gap-face and outer-boundary measures are computed
+    here from the mesh (lumped_measures); the problem supplies only which
+    node pairs are coupled."""
 
     def __init__(self, P):
         N = P.N
         self.N = N
+        mem_len, gap_len, robin_len = lumped_measures(P.coords, P.elems, P.node_cell, P.mem_intra, P.gap_a)
+        self.mem_len, self.gap_len, self.robin_len = mem_len, gap_len, robin_len
         A = stiffness(P.coords, P.elems, P.elem_tensor, P.node_sigma, N)
-        ga, gb, gw = np.asarray(P.gap_a), np.asarray(P.gap_b), P.g_gap * np.asarray(P.gap_len)
+        ga, gb, gw = np.asarray(P.gap_a), np.asarray(P.gap_b), P.g_gap * gap_len
         rows = np.concatenate([ga, gb, ga, gb])
         cols = np.concatenate([ga, gb, gb, ga])
         vals = np.concatenate([gw, gw, -gw, -gw])
         Agap = sp.coo_matrix((vals, (rows, cols)), shape=(N, N))
-        self.A = (A + Agap + sp.diags(P.eps * np.asarray(P.robin_len))).tocsr()
+        self.A = (A + Agap + sp.diags(P.eps * robin_len)).tocsr()
         si, se = np.asarray(P.mem_intra, dtype=np.int64), np.asarray(P.mem_extra, dtype=np.int64)
-        ml = P.cm * np.asarray(P.mem_len)
+        ml = P.cm * mem_len
         rows = np.concatenate([si, se, si, se])
         cols = np.concatenate([si, se, se, si])
         vals = np.concatenate([ml, ml, -ml, -ml])
         self.M = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
         self.si, self.se = si, se
-        self.l = np.asarray(P.mem_len, dtype=np.float64)
+        self.l = mem_len
         self.S = si.size
         self.p = np.asarray(P.ionic[0], dtype=np.float64)[:, None]   # [6, 1] broadcast over sites
 
@@ -209,9 +273,7 @@ def run(sdc, u, w_sites, n_steps, K, stimuli=(), t0=0.0, idx_replay=None):
     log = []
     for n in range(n_steps):
         t = t0 + n * sdc.dt
-        for t_on, nodes, value in stimuli:
-            if t - 1e-9 * sdc.dt <= t_on < t + sdc.dt - 1e-9 * sdc.dt:
-                u[np.asarray(nodes, dtype=np.int64)] = value
+        apply_stimuli(u, t, sdc.dt, stimuli)
         u, w, infos = sdc.step(u, w, K, None if idx_replay is None else idx_replay[n])
         log.append(infos)
     return u, w, log

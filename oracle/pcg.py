@@ -77,3 +77,39 @@ def jacobi_pcg(H, b, idx, rtol, maxit=1000, fixed_iters=None, energy_tol=0.0, de
             raise CGNotConverged(f"PCG: no convergence in {maxit} iterations")
     x_full[idx] = x
     return x_full, it
+
+
+def stop_rule_values(H, b, idx, n, delay=0):
+    """The two quantities the stopping rules of jacobi_pcg compare, after each
+    step j = 1..n of the restricted solve from x0 = 0 (textbook PCG):
+    res[j] = ||r_j||_2 / ||b||_2 (against rtol) and, for j >= delay >= 1,
+    en[j] = sum_{i=j-d}^{j-1} t_i / sum_{i<j} t_i (against energy_tol^2),
+    t_i = alpha_i (r_i . z_i); en[j] = inf where the rule does not apply.
+    Index 0 of both arrays is the start (res 1, en inf).  For checking a step
+    count that another implementation of CG chose against the rules."""
+    idx = np.asarray(idx, dtype=np.int64)
+    res = np.full(n + 1, np.inf)
+    en = np.full(n + 1, np.inf)
+    Hs = H[idx][:, idx]
+    bs = np.asarray(b, dtype=np.float64)[idx]
+    bnorm = np.sqrt(bs @ bs)
+    res[0] = 1.0
+    dinv = 1.0 / Hs.diagonal()
+    r = bs.copy()
+    z = dinv * r
+    p = z.copy()
+    rz = r @ z
+    terms = []
+    for j in range(1, n + 1):
+        q = Hs @ p
+        alpha = rz / (p @ q)
+        terms.append(alpha * rz)
+        r = r - alpha * q
+        res[j] = np.sqrt(r @ r) / bnorm
+        if delay >= 1 and j >= delay:
+            en[j] = sum(terms[j - delay:]) / sum(terms)
+        z = dinv * r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return res, en

@@ -209,26 +209,28 @@ class SDC:
             nxt = select(idx, amax, self.theta if theta is None else float(theta))
         else:
             nxt = idx[amax[idx] >= np.asarray(theta)[self.inst_of[idx]]]
-        return nxt, {"idx": idx, "n_active": int(idx.size), "cg_iters": iters, "amax": amax, "dv": dv}
+        # per node: the largest step count over instances, and every instance's
+        return nxt, {"idx": idx, "n_active": int(idx.size), "cg_iters": [int(np.max(it)) for it in iters],
+                     "cg_iters_inst": [np.asarray(it).copy() for it in iters], "amax": amax, "dv": dv}
 
     def _pcg(self, H, b, idx, fixed):
-        """The restricted solve of one node.  With the residual stop alone,
-        one CG over the block-diagonal system of all instances (its solution
-        is each instance's to rounding).  With the energy-error stop the stop
-        depends on an instance's own sums, so each instance is solved by a
-        CG of its own; the count returned is the largest over instances, and
-        a replayed count is one per instance."""
-        if not (self.cg_energy_tol > 0.0) or self.n_inst == 1:
-            return jacobi_pcg(H, b, idx, self.cg_rtol, self.cg_maxit, fixed, self.cg_energy_tol, self.cg_delay)
+        """The restricted solve of one node.  The instances are independent
+        systems, so each is solved by a CG of its own (its own scalars and
+        stopping test).  Returns x and the per-instance step counts; `fixed`
+        replays counts, one per instance or one for all."""
         x = np.zeros(H.shape[0])
-        its = []
+        its = np.zeros(self.n_inst, dtype=np.int64)
+        log = getattr(self, "solve_log", None)   # a list: record (H, b, rows, steps) of every solve
+        if fixed is not None:
+            fixed = np.broadcast_to(np.asarray(fixed, dtype=np.int64).reshape(-1), (self.n_inst,))
         for i in range(self.n_inst):
-            sub = idx[self.inst_of[idx] == i]
-            fi = None if fixed is None else int(np.asarray(fixed).reshape(-1)[i])
-            xi, it = jacobi_pcg(H, b, sub, self.cg_rtol, self.cg_maxit, fi, self.cg_energy_tol, self.cg_delay)
+            sub = idx if self.n_inst == 1 else idx[self.inst_of[idx] == i]
+            fi = None if fixed is None else int(fixed[i])
+            xi, its[i] = jacobi_pcg(H, b, sub, self.cg_rtol, self.cg_maxit, fi, self.cg_energy_tol, self.cg_delay)
             x[sub] = xi[sub]
-            its.append(it)
-        return x, max(its)
+            if log is not None:
+                log.append((H, b, sub, int(its[i])))
+        return x, its
 
     def _solve_imex(self, st, idx, Phi, Gam, cg_iters):
         """Node by node: implicit diffusion, explicit reaction and gating."""
@@ -329,7 +331,8 @@ class SDC:
 
         idx_replay[k], when given, replaces the computed index set of sweep k
         (the first sweep always uses all rows unless replayed);
-        cg_replay[k][m] replays CG iteration counts.
+        cg_replay[k][m] replays CG iteration counts (one per instance, or one
+        for all).
         """
         st = self.spread(v0, w0)
         idx = np.arange(self.model.N)
@@ -417,18 +420,26 @@ def select(idx, amax, theta):
     return idx[amax[idx] >= theta]
 
 
+def stimulus_applies(t_on, t, dt):
+    """Whether a stimulus at time t_on belongs to the step [t, t + dt) (a
+    stimulus overwrites the state at the start of the step that contains its
+    time).  Both ends of the interval are moved down by 1e-9 dt, so that a
+    t_on on a step boundary belongs to the step starting there even when
+    that step's t was accumulated with rounding just above it."""
+    return t - 1e-9 * dt <= t_on < t + dt - 1e-9 * dt
+
+
 def apply_stimuli(v, t, dt, stimuli):
-    """Set v = value on the listed nodes when t_on lies in [t, t + dt)."""
+    """Set v = value on the listed nodes of the stimuli of the step at t."""
     for t_on, nodes, value in stimuli:
-        if t - 1e-9 * dt <= t_on < t + dt - 1e-9 * dt:
+        if stimulus_applies(t_on, t, dt):
             v[np.asarray(nodes, dtype=np.int64)] = value
     return v
 
 
 def stimulus_nodes(t, dt, stimuli):
     """Node lists of the stimuli that apply at the step starting at t."""
-    return [np.asarray(nodes, dtype=np.int64) for t_on, nodes, _ in stimuli
-            if t - 1e-9 * dt <= t_on < t + dt - 1e-9 * dt]
+    return [np.asarray(nodes, dtype=np.int64) for t_on, nodes, _ in stimuli if stimulus_applies(t_on, t, dt)]
 
 
 def run(sdc, v, w, n_steps, K, stimuli=(), t0=0.0, idx_replay=None, cg_replay=None, first=None):

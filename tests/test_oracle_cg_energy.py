@@ -93,3 +93,15 @@ def test_sdc_run_with_the_energy_stop_takes_fewer_steps_and_replays_itself():
                   idx_replay=[[sw["idx"] for sw in step] for step in le],
                   cg_replay=[[sw["cg_iters"] for sw in step] for step in le])
     assert np.array_equal(v, ve) and np.array_equal(w, we)
+
+
+def test_stop_rule_values_reproduce_the_stop_decisions():
+    """stop_rule_values gives the quantities the two rules test: the step
+    where jacobi_pcg stops is the first at which one of them passes."""
+    from oracle.pcg import stop_rule_values
+    for seed, tol, d in ((3, 1e-3, 4), (7, 1e-2, 2), (11, 1e-12, 3)):
+        H, b, idx = _system(17, seed, 0.6)
+        x, n = jacobi_pcg(H, b, idx, 1e-12, energy_tol=tol, delay=d)
+        res, en = stop_rule_values(H, b, idx, n, d)
+        passes = (res <= 1e-12) | (en <= tol ** 2)
+        assert passes[n] and not passes[:n].any()

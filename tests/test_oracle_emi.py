@@ -1,5 +1,9 @@
 """Pins of the cell-by-cell (EMI) oracle against what the model and the mathematics fix.
 
+- the lumped membrane, gap-face and outer-boundary measures, computed by
+  the oracle from the mesh's facets, equal their closed forms site by site
+  (half of each adjacent boundary segment) and agree with the workload's
+  arrays (which the library takes as input);
 - the membrane jump mass annihilates constants and gives each cell's
   indicator the energy C_m x (cell perimeter);
 - A maps constants to the Robin term only (eps x outer perimeter in total)
@@ -19,7 +23,7 @@ import pytest
 from scipy.integrate import solve_ivp
 
 from oracle import ionic
-from oracle.emi import EMI, EmiSDC, build, collocation_solution, run
+from oracle.emi import EMI, EmiSDC, build, collocation_solution, lumped_measures, run
 from workloads.emi import config3
 
 
@@ -29,13 +33,57 @@ def small(**kw):
     return config3(**base)
 
 
+def test_lumped_measures_per_site():
+    """Cells of nx x ny nodes with spacings hx = 100 um / (nx - 1) and
+    hy = 16 um / (ny - 1): a corner site carries (hx + hy) / 2, a site inside
+    a long side hx, inside a short side hy; a gap-junction node hy at a face
+    end, else hy... halved at the ends; an outer-boundary node half of its two
+    boundary segments (from the sorted node positions on each side)."""
+    nx, ny = 5, 4
+    P = small(nx=nx, ny=ny)
+    mod = EMI(P)
+    hx, hy = 100e-4 / (nx - 1), 16e-4 / (ny - 1)
+    xy = P.coords[P.mem_intra]
+    cell = P.node_cell[P.mem_intra]
+    for c in np.unique(cell):
+        s = cell == c
+        lo, hi = xy[s].min(axis=0), xy[s].max(axis=0)
+        on_x = np.isclose(xy[s, 0], lo[0], rtol=0, atol=1e-12) | np.isclose(xy[s, 0], hi[0], rtol=0, atol=1e-12)
+        on_y = np.isclose(xy[s, 1], lo[1], rtol=0, atol=1e-12) | np.isclose(xy[s, 1], hi[1], rtol=0, atol=1e-12)
+        want = np.where(on_x & on_y, 0.5 * (hx + hy), np.where(on_y, hx, hy))
+        assert np.allclose(mod.mem_len[s], want, rtol=1e-13, atol=0)
+    gy = P.coords[P.gap_a, 1]
+    cy = P.node_cell[P.gap_a] // 3
+    end = np.isclose(gy - (2e-4 + cy * 18e-4), 0, atol=1e-12) | np.isclose(gy - (2e-4 + cy * 18e-4 + 16e-4), 0, atol=1e-12)
+    assert np.allclose(mod.gap_len, np.where(end, 0.5 * hy, hy), rtol=1e-13, atol=0)
+    # outer boundary: every box side, nodes sorted along it
+    W = 3 * (100e-4 + 2e-4) + 2e-4
+    Hb = 2 * (16e-4 + 2e-4) + 2e-4
+    want = np.zeros(P.N)
+    ext = P.node_cell < 0
+    for ax, val in ((1, 0.0), (1, Hb), (0, 0.0), (0, W)):
+        on = np.nonzero(ext & np.isclose(P.coords[:, ax], val, rtol=0, atol=1e-12))[0]
+        t = P.coords[on, 1 - ax]
+        o = np.argsort(t)
+        seg = np.diff(t[o])
+        share = np.zeros(len(on))
+        share[:-1] += seg / 2
+        share[1:] += seg / 2
+        want[on[o]] += share
+    assert np.allclose(mod.robin_len, want, rtol=1e-13, atol=0)
+    assert abs(mod.robin_len.sum() - 2 * (W + Hb)) <= 1e-15
+    # the workload's arrays (the library's input) carry the same measures
+    for a, b in ((mod.mem_len, P.mem_len), (mod.gap_len, P.gap_len), (mod.robin_len, P.robin_len)):
+        assert np.allclose(a, b, rtol=1e-13, atol=0)
+
+
 def test_membrane_mass():
     P = small()
     mod = EMI(P)
     Mm = mod.M.toarray()
     assert np.allclose(Mm, Mm.T, atol=0)
     assert np.abs(Mm @ np.ones(P.N)).max() <= 1e-15 * np.abs(Mm).max()
-    assert np.linalg.eigvalsh(Mm).min() > -1e-15 * np.abs(Mm).max()
+    assert np.linalg.eigvalsh(Mm).min() > -1e-15 * P.N * np.abs(Mm).max()   # eigensolver rounding
     perim = 2 * (100e-4 + 16e-4)
     for c in range(3 * 2):
         ind = (P.node_cell == c).astype(float)
@@ -48,7 +96,7 @@ def test_stiffness_constants_and_affine_functions():
     A = mod.A
     assert abs(A - A.T).max() == 0.0
     # row sums of the element part cancel to rounding (entries up to |A|max)
-    assert np.allclose(A @ np.ones(P.N), P.eps * P.robin_len, rtol=0, atol=1e-15 * 16 * abs(A).max())
+    assert np.allclose(A @ np.ones(P.N), P.eps * mod.robin_len, rtol=0, atol=1e-15 * 16 * abs(A).max())
     W = 3 * (100e-4 + 2e-4) + 2e-4
     H = 2 * (16e-4 + 2e-4) + 2e-4
     # the element part cancels to rounding of the nnz entries
@@ -58,7 +106,7 @@ def test_stiffness_constants_and_affine_functions():
     interior = np.ones(P.N, dtype=bool)
     interior[P.mem_intra] = False
     interior[P.mem_extra] = False
-    interior[P.robin_len > 0] = False
+    interior[mod.robin_len > 0] = False
     interior[P.gap_a] = False
     interior[P.gap_b] = False
     assert interior.sum() > 20
@@ -95,9 +143,10 @@ def test_converged_sweeps_equal_collocation_solution(M):
     assert np.abs(st["w"] - Wc).max() <= 1e-12 * max(np.abs(Wc).max(), 1.0)
     # charge conservation of the collocation solution: robin^T u_m = 0 at every
     # node (to the accuracy of the constant mode)
+    rl = sdc.model.robin_len
     for m in range(M):
-        assert abs(P.robin_len @ Uc[m]) <= 1e-8 * P.robin_len.sum() * np.abs(Uc).max()
-        assert abs(P.robin_len @ st["u"][m]) <= 1e-8 * P.robin_len.sum() * np.abs(Uc).max()
+        assert abs(rl @ Uc[m]) <= 1e-8 * rl.sum() * np.abs(Uc).max()
+        assert abs(rl @ st["u"][m]) <= 1e-8 * rl.sum() * np.abs(Uc).max()
 
 
 def test_single_cell_lumped_limit_follows_membrane_ode():

@@ -2,8 +2,11 @@
 
 The same facts as in 2D, with areas for lengths:
 - the mesh fills the box exactly with positively oriented tetrahedra, and
-  the lumped membrane, gap-face and outer-boundary measures sum to the
-  exact areas;
+  the lumped membrane, gap-face and outer-boundary measures (computed by the
+  oracle from the mesh's boundary triangles) sum to the exact areas, take
+  their closed forms at face-interior sites (hu hv: six triangles of area
+  hu hv / 2, a third each) and at the cells' two diagonal corners, and agree
+  with the workload's arrays;
 - the membrane jump mass annihilates constants and gives each cell's
   indicator the energy C_m x (cell surface area);
 - A maps constants to the Robin term only (eps x box surface in total),
@@ -35,14 +38,50 @@ def box(nc, nr, nl):
 
 def test_mesh_measures():
     P = small()
+    mod = EMI(P)
     W, Hb, Db = box(2, 2, 1)
     x = P.coords[P.elems]
     det = np.einsum("ij,ij->i", np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0]), x[:, 3] - x[:, 0])
     assert det.min() > 0
     assert abs(det.sum() / 6 - W * Hb * Db) <= 1e-12 * W * Hb * Db
-    assert abs(P.robin_len.sum() - 2 * (W * Hb + W * Db + Hb * Db)) <= 1e-14
-    assert abs(P.mem_len.sum() - 4 * 2 * (L * H + L * D + H * D)) <= 1e-14
-    assert abs(P.gap_len.sum() - 2 * H * D) <= 1e-15   # one neighbour pair per row, two rows
+    assert abs(mod.robin_len.sum() - 2 * (W * Hb + W * Db + Hb * Db)) <= 1e-14
+    assert abs(mod.mem_len.sum() - 4 * 2 * (L * H + L * D + H * D)) <= 1e-14
+    assert abs(mod.gap_len.sum() - 2 * H * D) <= 1e-15   # one neighbour pair per row, two rows
+    for a, b in ((mod.mem_len, P.mem_len), (mod.gap_len, P.gap_len), (mod.robin_len, P.robin_len)):
+        assert np.allclose(a, b, rtol=1e-13, atol=0)
+
+
+def test_lumped_measures_per_site():
+    nx, ny, nz = 5, 4, 4
+    P = small(nx=nx, ny=ny, nz=nz)
+    mod = EMI(P)
+    hx, hy, hz = L / (nx - 1), H / (ny - 1), D / (nz - 1)
+    xyz = P.coords[P.mem_intra]
+    cell = P.node_cell[P.mem_intra]
+    for c in np.unique(cell):
+        s = cell == c
+        lo, hi = xyz[s].min(axis=0), xyz[s].max(axis=0)
+        at_lo = np.isclose(xyz[s], lo, rtol=0, atol=1e-12)
+        at_hi = np.isclose(xyz[s], hi, rtol=0, atol=1e-12)
+        faces = (at_lo | at_hi).sum(axis=1)
+        # on one face only: hu hv of that face's grid
+        one = faces == 1
+        ax = np.argmax((at_lo | at_hi)[one], axis=1)
+        area = np.array([hy * hz, hx * hz, hx * hy])[ax]
+        assert one.sum() > 10 and np.allclose(mod.mem_len[s][one], area, rtol=1e-13, atol=0)
+        # the low and the high corner: the diagonal end of all three faces'
+        # grid squares, two triangles each: (hx hy + hx hz + hy hz) / 3
+        corner = np.all(at_lo, axis=1) | np.all(at_hi, axis=1)
+        assert corner.sum() == 2
+        assert np.allclose(mod.mem_len[s][corner], (hx * hy + hx * hz + hy * hz) / 3, rtol=1e-13, atol=0)
+    # gap faces (x = const): interior nodes hy hz, total H D per pair of faces
+    gyz = P.coords[P.gap_a, 1:]
+    inner = np.zeros(len(P.gap_a), dtype=bool)
+    for c in np.unique(P.node_cell[P.gap_a]):
+        s = P.node_cell[P.gap_a] == c
+        lo, hi = gyz[s].min(axis=0), gyz[s].max(axis=0)
+        inner[np.nonzero(s)[0]] = np.all((gyz[s] > lo + 1e-12) & (gyz[s] < hi - 1e-12), axis=1)
+    assert inner.sum() > 0 and np.allclose(mod.gap_len[inner], hy * hz, rtol=1e-13, atol=0)
 
 
 def test_membrane_mass():
@@ -62,7 +101,7 @@ def test_stiffness_constants_and_affine_functions():
     A = EMI(P).A
     # the plain element products sigma (G_a . G_b) are symmetric to rounding
     assert abs(A - A.T).max() <= 4e-16 * abs(A).max()
-    assert np.allclose(A @ np.ones(P.N), P.eps * P.robin_len, rtol=0, atol=1e-15 * 24 * abs(A).max())
+    assert np.allclose(A @ np.ones(P.N), P.eps * EMI(P).robin_len, rtol=0, atol=1e-15 * 24 * abs(A).max())
     W, Hb, Db = box(2, 2, 1)
     assert abs(np.ones(P.N) @ A @ np.ones(P.N) - P.eps * 2 * (W * Hb + W * Db + Hb * Db)) \
         <= 1e-15 * A.nnz * abs(A).max()

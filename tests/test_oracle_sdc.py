@@ -371,3 +371,30 @@ def test_energy_termination_is_per_instance():
         assert np.abs(vb[lo:hi] - va).max() <= 1e-12 * max(np.abs(va).max(), 1.0)
         n_sweeps.add(tuple(len(st) for st in loga))
     assert len(n_sweeps) > 1          # the instances did stop at different sweeps
+
+
+def test_batched_instances_are_stepped_as_if_alone():
+    """Independent instances in one state vector (block-diagonal A, one CG per
+    instance): every instance's state, active sets and CG step counts equal
+    those of the instance integrated alone.  A single CG over the stacked
+    system would couple the instances through its shared scalars and its
+    stopping test (a common step count, the residual over all instances)."""
+    from workloads import config4
+    P = config4(n_inst=3, sizes=(9, 17), n_steps=3)
+    orc = build(P)
+    vb, wb, lb = run(orc, P.v_init, P.w_init, P.n_steps, P.K, P.stimuli)
+    for i in range(P.n_inst):
+        lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
+        e0, e1 = int(P.elem_off[i]), int(P.elem_off[i + 1])
+        ML = lumped_mass(P.coords[lo:hi], P.elems[e0:e1] - lo, hi - lo)
+        A = stiffness(P.coords[lo:hi], P.elems[e0:e1] - lo, P.elem_tensor[e0:e1], P.node_sigma[lo:hi], hi - lo)
+        solo = SDC(Monodomain(ML, A, P.ionic[i]), P.M, P.dt, P.theta, P.cg_rtol, P.cg_maxit)
+        stim = [(t, np.asarray(n)[(n >= lo) & (n < hi)] - lo, val) for t, n, val in P.stimuli]
+        v, w, ls = run(solo, P.v_init[lo:hi], P.w_init[lo:hi], P.n_steps, P.K, stim)
+        assert np.abs(v - vb[lo:hi]).max() <= 1e-14 and np.abs(w - wb[lo:hi]).max() <= 1e-14
+        for sb, s in zip(lb, ls):
+            for kb, k in zip(sb, s):
+                assert np.array_equal(kb["idx"][(kb["idx"] >= lo) & (kb["idx"] < hi)] - lo, k["idx"])
+                assert [int(c[i]) for c in kb["cg_iters_inst"]] == k["cg_iters"]
+    # the instances take different step counts somewhere in the run
+    assert any(len(set(c.tolist())) > 1 for s in lb for k in s for c in k["cg_iters_inst"])
