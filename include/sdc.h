@@ -253,6 +253,12 @@ int sdc_end_step(sdc_ctx* ctx, double* v, double* w);
 /* Copy collocation node m's current values (device double[N] each). */
 int sdc_get_node(sdc_ctx* ctx, int32_t m, double* v_m, double* w_m);
 
+/* CG step counts of the last sweep's restricted solves (Sec. 4.2), per node
+ * and instance: host out int32[M][n_inst] (element m * n_inst + i), the
+ * updates instance i's solve of node m performed (0 for an instance without
+ * active rows).  SDC_ERR_STATE before the first sweep. */
+int sdc_get_cg_iters(sdc_ctx* ctx, int32_t* out);
+
 /* Current active set (the set the next sweep will use): idx device int32
  * with room for N entries (may be NULL to query only), *n receives its length. */
 int sdc_get_active(sdc_ctx* ctx, int32_t* idx, int64_t* n);

@@ -88,6 +88,7 @@ SIGNATURES = {
     "sdc_end_step": (c_int32, [c_void_p, PTR, PTR]),
     "sdc_get_node": (c_int32, [c_void_p, c_int32, PTR, PTR]),
     "sdc_get_active": (c_int32, [c_void_p, PTR, P_I64]),
+    "sdc_get_cg_iters": (c_int32, [c_void_p, PTR]),
     "sdc_set_active": (c_int32, [c_void_p, c_int32, PTR, c_int64]),
     "sdc_solve": (c_int32, [c_void_p, c_int32, PTR, c_int64, PTR, PTR, P_I32]),
     "sdc_select": (c_int32, [c_void_p, PTR, PTR, c_int64, c_double, PTR, P_I64]),

@@ -183,7 +183,7 @@ int reverse_step(sdc_ctx* ctx, int slot, double* lam_v, double* lam_w, double* g
   // a stimulus overwrite at the step start cuts the dependence on those values
   const double dt = ctx->prm.dt;
   for (const auto& st : ctx->stims)
-    if (t - 1e-9 * dt <= st.t_on && st.t_on < t + dt - 1e-9 * dt) launch_zero_values(s, st.nodes, st.n, A.Lv0);
+    if (stimulus_applies(st, t, dt)) launch_zero_values(s, st.nodes, st.n, A.Lv0);
   HIPC(hipMemcpyAsync(lam_v, A.Lv0, N * 8, hipMemcpyDeviceToDevice, s));
   HIPC(hipMemcpyAsync(lam_w, A.Lw0, N * 8, hipMemcpyDeviceToDevice, s));
   launch_adj_gather_sigma(s, N, nv, A.nptr, A.nel, A.qe, g_sigma);

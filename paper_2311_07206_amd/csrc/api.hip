@@ -432,6 +432,9 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
       ctx->all_stopped = ctx->all_stopped && stop[i] != 0;
     }
   }
+  ctx->last_iters.assign(static_cast<size_t>(M) * ni, 0);
+  for (int m = 0; m < M; ++m)
+    for (int i = 0; i < ni && i < static_cast<int>(iters[m].size()); ++i) ctx->last_iters[m * ni + i] = iters[m][i];
   if (st) {
     for (int m = 0; m < M; ++m)
       for (int i = 0; i < ni; ++i) {
@@ -629,11 +632,6 @@ int tune_rows_per_thread(sdc_ctx* ctx) {
   return SDC_OK;
 }
 
-// Spread the saved start state (v0, w0) to all nodes; all rows active.
-bool stimulus_applies(const Stimulus& s, double t, double dt) {
-  return t - 1e-9 * dt <= s.t_on && s.t_on < t + dt - 1e-9 * dt;
-}
-
 // The rows of the first sweep of the step starting at t (first_rings > 0):
 // all rows (first_n = -1) on the first step, on every first_full_every-th
 // and when nothing is carried; else the carried rows and this step's
@@ -664,6 +662,8 @@ int build_first_set(sdc_ctx* ctx, double t) {
   return SDC_OK;
 }
 
+// Spread the saved start state (v0, w0) to all nodes; all rows active (or
+// the step's heuristic first-sweep set).
 int restart_step(sdc_ctx* ctx) {
   launch_spread(ctx->stream, ctx->prm.M, ctx->all.dev(), ctx->N, ctx->ionic_d, ctx->v0, ctx->w0, ctx->v,
                 ctx->w, ctx->I, ctx->R, ctx->emi_args());
@@ -1129,6 +1129,14 @@ int sdc_get_node(sdc_ctx* ctx, int32_t m, double* v_m, double* w_m) {
   const int64_t N = ctx->N;
   if (v_m) HIPC(hipMemcpyAsync(v_m, ctx->v + m * N, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
   if (w_m) HIPC(hipMemcpyAsync(w_m, ctx->w + m * N, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return SDC_OK;
+}
+
+int sdc_get_cg_iters(sdc_ctx* ctx, int32_t* out) {
+  TRY(check_ready(ctx));
+  if (!out) return fail(ctx, SDC_ERR_ARG, "null output");
+  if (ctx->last_iters.empty()) return fail(ctx, SDC_ERR_STATE, "no sweep has run");
+  std::memcpy(out, ctx->last_iters.data(), ctx->last_iters.size() * sizeof(int32_t));
   return SDC_OK;
 }
 

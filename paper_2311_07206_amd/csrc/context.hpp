@@ -54,6 +54,16 @@ struct Stimulus {
   double value;
 };
 
+// Whether stimulus s belongs to the step [t, t + dt): it overwrites the state
+// at the start of the step that contains its time.  Both ends of the
+// interval are moved down by 1e-9 dt, so that a time on a step boundary goes
+// to the step starting there even when the caller's t was accumulated with
+// rounding just above it.  The one rule for the forward step, the
+// first-sweep set and the reverse step.
+inline bool stimulus_applies(const Stimulus& s, double t, double dt) {
+  return t - 1e-9 * dt <= s.t_on && s.t_on < t + dt - 1e-9 * dt;
+}
+
 }  // namespace sdc
 
 using sdc::Collocation;
@@ -167,6 +177,8 @@ struct sdc_ctx {
 
   bool in_step = false;
   int k = 0;
+  // CG updates of the last sweep's restricted solves, [M][n_inst] (empty before any sweep)
+  std::vector<int32_t> last_iters;
   double* record_dv = nullptr;   // when set, a sweep copies its corrections here before the selection
   // per-node CG outcome of the current sweep, snapshot on the device (async steps)
   int32_t* hist_done = nullptr;    // [M][n_inst]

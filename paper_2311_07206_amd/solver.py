@@ -196,6 +196,12 @@ class Solver:
         self._check(self.lib.sdc_get_node(self.ctx, int(m), _ptr(v), _ptr(w)))
         return v, w
 
+    def cg_iters(self):
+        """CG updates of the last sweep's solves: int array [M, n_inst]."""
+        out = np.zeros((self.M, self.n_inst), dtype=np.int32)
+        self._check(self.lib.sdc_get_cg_iters(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
     def active(self):
         n = ctypes.c_int64()
         self._check(self.lib.sdc_get_active(self.ctx, None, ctypes.byref(n)))

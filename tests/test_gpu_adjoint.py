@@ -229,3 +229,52 @@ def test_adjoint_full_size_batched_sampled_instances():
         print(f"[adjoint full] instance {i}: lhs {lhs:.6e} rhs {rhs:.6e} rel {abs(lhs - rhs) / scale:.2e}",
               flush=True)
         assert abs(lhs - rhs) <= 1e-8 * scale, (lhs, rhs)
+
+
+def test_adjoint_elementwise_against_oracle_tlm_basis():
+    """Every component of the reverse step's outputs against the oracle: on
+    three instances of 7^2, 8^2 and 8^2 nodes, the oracle's tangent-linear model is
+    run in every basis direction (each node's v0, w0 and sigma, each
+    instance's a), which gives each component of J^T lam as <lam, J e>.  The
+    library's lam_v, lam_w (adjoints of v0, w0), g_sigma and g_a must match
+    component by component within 1e-8 of that component's scale
+    s_q = sum |lam| |J e_q|, with the scale floored at 1e-3 of the largest
+    scale of its kind: the library's solves stop at rtol 1e-12 relative to
+    the whole vector (the oracle's are direct), so a component a million
+    times below the largest carries that absolute rounding."""
+    P = config4(n_inst=3, sizes=(4, 8), theta=1e-6)
+    n0 = 3
+    v0, w0 = _mid_state(P, n0)
+    t = n0 * P.dt
+    s = _solver(P)
+    sets = _gpu_sets(s, P, v0, w0, t)
+    assert any(len(x) < P.N for x in sets[1:])
+    rng = np.random.default_rng(23)
+    lam_v = rng.standard_normal(P.N)
+    lam_w = rng.standard_normal(P.N)
+    Lv = torch.tensor(lam_v, device=DEV)
+    Lw = torch.tensor(lam_w, device=DEV)
+    gs = torch.zeros(P.N, dtype=torch.float64, device=DEV)
+    ga = torch.zeros(P.n_inst, dtype=torch.float64, device=DEV)
+    s.adjoint_step(torch.tensor(v0, device=DEV), torch.tensor(w0, device=DEV), t, Lv, Lw, gs, ga)
+    got = {"v": Lv.cpu().numpy(), "w": Lw.cpu().numpy(), "sigma": gs.cpu().numpy(), "a": ga.cpu().numpy()}
+    tp = tlm.TLMProblem(P)
+    a = P.ionic[:, 1].copy()
+    zN, zI = np.zeros(P.N), np.zeros(P.n_inst)
+    print(f"[adjoint elementwise] N={P.N}, {3 * P.N + P.n_inst} tangent directions", flush=True)
+    for name, size in (("v", P.N), ("w", P.N), ("sigma", P.N), ("a", P.n_inst)):
+        want, scale = np.zeros(size), np.zeros(size)
+        for q in range(size):
+            e = np.zeros(size)
+            e[q] = 1.0
+            dv, dw, ds, da = (e if name == "v" else zN, e if name == "w" else zN,
+                              e if name == "sigma" else zN, e if name == "a" else zI)
+            _, _, vt, wt = tlm.step(tp, P.node_sigma, a, v0, w0, sets, ds, da, dv, dw)
+            want[q] = lam_v @ vt + lam_w @ wt
+            scale[q] = abs(lam_v) @ abs(vt) + abs(lam_w) @ abs(wt)
+        err = np.abs(got[name] - want)
+        floor = np.maximum(scale, 1e-3 * scale.max())
+        print(f"   {name}: largest |component| {np.abs(want).max():.3e}, worst err/scale "
+              f"{(err / np.maximum(scale, 1e-300)).max():.2e}, worst err/floored scale {(err / floor).max():.2e}",
+              flush=True)
+        assert np.all(err <= 1e-8 * floor), name

@@ -61,8 +61,10 @@ def test_apriori_drop_tolerance_matches_oracle(case):
         print(f"[drop {case}] step {n}", flush=True)
         s.begin_step(v, w, t)
         sets, drop = [None], None
+        counts = []
         for k in range(K):
             s.sweep()
+            counts.append(s.cg_iters())
             if k == 0:
                 drop = s.drop_tolerance()
             if k + 1 < K:
@@ -87,6 +89,9 @@ def test_apriori_drop_tolerance_matches_oracle(case):
         assert np.array_equal(got[clear], keep[clear])
         assert 0 < sets[1].size < P.N
         assert rel(v.cpu().numpy(), ov) < 1e-10 and rel(w.cpu().numpy(), ow) < 1e-10
+        assert np.abs(v.cpu().numpy() - ov).max() <= 1e-10 * np.abs(ov).max()
+        # per node and instance, every solve's CG step count within one of the oracle's
+        assert all(np.abs(g - np.stack(i["cg_iters_inst"])).max() <= 1 for g, i in zip(counts, infos))
         if case == "batched":
             # the instance at rest: c = 0, r = 0, eta = 0, so exactly (1 - rho) tol; none of its rows stays
             assert drop["tol_drop"][0] == (1.0 - rho) / 1 * tol and drop["r"][0] == 0

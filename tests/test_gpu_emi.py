@@ -52,7 +52,10 @@ def test_emi_assembly_matches_oracle():
     mod = EMI(P)
     G = sp.csr_matrix((val, col, rp), shape=(P.N, P.N))
     assert abs(G - mod.A).max() <= 1e-14 * abs(mod.A).max()
-    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-15, atol=0)
+    # the oracle sums facet shares whose lengths come from coordinate
+    # differences (coordinates up to ~2000 segment lengths: ~3 digits lost);
+    # the library takes the workload's closed-form arrays: equal to 1e-12
+    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-12, atol=0)
     for q in range(len(P.mem_intra)):     # the membrane partner is in the pattern
         i, e = P.mem_intra[q], P.mem_extra[q]
         assert e in col[rp[i]:rp[i + 1]] and i in col[rp[e]:rp[e + 1]]

@@ -49,7 +49,10 @@ def test_emi3d_assembly_matches_oracle():
     G = sp.csr_matrix((val, col, rp), shape=(P.N, P.N))
     assert abs(G - mod.A).max() <= 1e-14 * abs(mod.A).max()
     assert abs(G - G.T).max() == 0.0          # the library's assembly is exactly symmetric
-    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-15, atol=0)
+    # the oracle sums facet shares whose lengths come from coordinate
+    # differences (coordinates up to ~2000 segment lengths: ~3 digits lost);
+    # the library takes the workload's closed-form arrays: equal to 1e-12
+    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-12, atol=0)
 
 
 @pytest.mark.parametrize("m", [0, 2])
@@ -119,7 +122,10 @@ def test_emi3d_full_size_assembly_and_restricted_pcg():
     rp, col, val, ml = s.system()
     G = sp.csr_matrix((val, col, rp), shape=(P.N, P.N))
     assert abs(G - mod.A).max() <= 1e-14 * abs(mod.A).max()
-    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-15, atol=0)
+    # the oracle sums facet shares whose lengths come from coordinate
+    # differences (coordinates up to ~2000 segment lengths: ~3 digits lost);
+    # the library takes the workload's closed-form arrays: equal to 1e-12
+    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-12, atol=0)
     orc = build(P)
     # the nodes of the first two cell columns and their surroundings: no constant mode
     first = np.nonzero(P.coords[:, 0] <= 2 * (100e-4 + 2e-4) + 1e-12)[0]

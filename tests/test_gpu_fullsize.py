@@ -142,7 +142,10 @@ def test_emi_full_size_assembly_and_restricted_pcg():
     rp, col, val, ml = s.system()
     G = sp.csr_matrix((val, col, rp), shape=(P.N, P.N))
     assert abs(G - mod.A).max() <= 1e-14 * abs(mod.A).max()
-    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-15, atol=0)
+    # the oracle sums facet shares whose lengths come from coordinate
+    # differences (coordinates up to ~2000 segment lengths: ~3 digits lost);
+    # the library takes the workload's closed-form arrays: equal to 1e-12
+    assert np.allclose(ml, mod.M.diagonal(), rtol=1e-12, atol=0)
     orc = emi_build(P)
     # the intracellular and extracellular nodes of the first four cell columns
     x0 = P.coords[:, 0]

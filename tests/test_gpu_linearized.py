@@ -37,7 +37,9 @@ def _solver(P, **kw):
     return Solver.from_problem(P, **kw)
 
 
-def _run_gpu(P, s, n_steps, K, stop_aware=False):
+def _run_gpu(P, s, n_steps, K, stop_aware=False, counts=None):
+    """Steps sweep by sweep: final state and the sets after the first sweep;
+    counts (a list) receives every sweep's CG step counts [M][n_inst]."""
     v = torch.tensor(P.v_init, device=DEV)
     w = torch.tensor(P.w_init, device=DEV)
     sets = []
@@ -46,6 +48,8 @@ def _run_gpu(P, s, n_steps, K, stop_aware=False):
         step_sets = [None]
         for k in range(K):
             st = s.sweep()
+            if counts is not None:
+                counts.append(s.cg_iters())
             if k + 1 == K or (stop_aware and st["n_stopped"] == P.n_inst):
                 break
             step_sets.append(s.active().cpu().numpy().astype(np.int64))
@@ -54,11 +58,13 @@ def _run_gpu(P, s, n_steps, K, stop_aware=False):
     return v.cpu().numpy(), w.cpu().numpy(), sets
 
 
-def _run_oracle(P, orc, n_steps, K, sets):
+def _run_oracle(P, orc, n_steps, K, sets, counts=None):
     v, w = P.v_init.copy(), P.w_init.copy()
     for n in range(n_steps):
         apply_stimuli(v, n * P.dt, P.dt, P.stimuli)
-        v, w, _ = orc.step(v, w, K, idx_replay=sets[n])
+        v, w, infos = orc.step(v, w, K, idx_replay=sets[n])
+        if counts is not None:
+            counts += [np.stack(i["cg_iters_inst"]) for i in infos]
     return v, w
 
 
@@ -75,11 +81,15 @@ def test_linearized_scheme_matches_oracle(case):
     K = P.K
     s = _solver(P, scheme="linearized")
     print(f"[linearized {case}] N={P.N} format={s.info()['format']}", flush=True)
-    gv, gw, sets = _run_gpu(P, s, n_steps, K)
+    gc, oc = [], []
+    gv, gw, sets = _run_gpu(P, s, n_steps, K, counts=gc)
     assert any(st is not None and st.size < P.N for steps in sets for st in steps)
-    ov, ow = _run_oracle(P, build(P, scheme="linearized"), n_steps, K, sets)
+    ov, ow = _run_oracle(P, build(P, scheme="linearized"), n_steps, K, sets, counts=oc)
     print(f"   rel v {rel(gv, ov):.2e} w {rel(gw, ow):.2e}", flush=True)
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+    assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
+    # every solve's step count, per node and instance, within one of the oracle's
+    assert len(gc) == len(oc) and all(np.abs(g - o).max() <= 1 for g, o in zip(gc, oc))
     # a different scheme from the default one on the same steps
     iv, _ = _run_oracle(P, build(P), n_steps, K, sets)
     assert rel(iv, ov) > 1e-9

@@ -55,6 +55,7 @@ def gpu_run(P, n_steps, s=None, t0=0.0, v=None, w=None):
         step_stats = []
         for k in range(P.K):
             step_stats.append(s.sweep())
+            step_stats[-1]["iters_inst"] = s.cg_iters()
             if k + 1 < P.K:
                 step_sets.append(s.active().cpu().numpy().astype(np.int64))
         s.end_step(v, w)
@@ -331,11 +332,28 @@ def test_3d_adaptive_steps():
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
 
 
+def assert_counts(stats, log, slack=1):
+    """Every restricted solve's CG step count, per node and instance, within
+    `slack` of the oracle's (the library's single-reduction recurrences round
+    differently from textbook PCG near the stopping test)."""
+    for gs, os_ in zip(stats, log):
+        for g, o in zip(gs, os_):
+            got = np.asarray(g["iters_inst"])
+            want = np.stack([np.asarray(c) for c in o["cg_iters_inst"]])
+            assert got.shape == want.shape and np.abs(got - want).max() <= slack, (got, want)
+
+
 def test_batched_instances_match_oracle_per_instance():
     P = config4(n_inst=3, sizes=(16, 24), n_steps=8)
     gv, gw, sets, stats, _ = gpu_run(P, P.n_steps)
     orc = build(P)
-    # the oracle solves each instance separately (own CG stopping test)
+    ov, ow, log = run(orc, P.v_init, P.w_init, P.n_steps, P.K, P.stimuli, idx_replay=sets)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+    assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
+    assert_counts(stats, log)
+    # the instances' solves stop at different step counts
+    assert any(len(set(st["iters_inst"][m].tolist())) > 1 for step in stats for st in step for m in range(P.M))
+    # each instance alone in the oracle (own mesh, own CG stopping test)
     for i in range(P.n_inst):
         lo, hi = P.node_off[i], P.node_off[i + 1]
         sub = _instance(P, i)

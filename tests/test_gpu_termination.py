@@ -45,6 +45,7 @@ def _gpu_steps(P, s, n_steps, K):
         for k in range(K):
             st = s.sweep()
             es.append(st["energy"])
+            s._counts.append(s.cg_iters())
             if st["n_stopped"] == P.n_inst or k + 1 == K:
                 break
             step_sets.append(s.active().cpu().numpy().astype(np.int64))
@@ -65,6 +66,7 @@ def test_energy_termination_matches_oracle(case):
         lo1 = P.node_off[1]   # instance 0 without stimulus: at rest, stops after one sweep
         P.stimuli = [(t, nodes[nodes >= lo1], val) for t, nodes, val in P.stimuli]
     s = _solver(P, K=K, tol_sdc=tol, rho=rho, K_min=1)
+    s._counts = []
     gv, gw, sets, counts, energies = _gpu_steps(P, s, P.n_steps, K)
     thr = ((1 - rho) / rho * tol) ** 2
     print(f"[termination {case}] sweeps per step {counts}, threshold {thr:.3e}", flush=True)
@@ -75,6 +77,10 @@ def test_energy_termination_matches_oracle(case):
     assert [len(st) for st in log] == counts
     assert any(c < K for c in counts)
     assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+    assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
+    # per node and instance, every solve's CG step count within one of the oracle's
+    oc = [np.stack(i["cg_iters_inst"]) for st in log for i in st]
+    assert len(oc) == len(s._counts) and all(np.abs(g - o).max() <= 1 for g, o in zip(s._counts, oc))
     # the step entry point takes the same decisions
     s2 = _solver(P, K=K, tol_sdc=tol, rho=rho, K_min=1)
     v = torch.tensor(P.v_init, device=DEV)
