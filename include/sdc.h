@@ -323,6 +323,34 @@ int sdc_solve(sdc_ctx* ctx, int32_t m, const int32_t* idx, int64_t n, const doub
 int sdc_select(sdc_ctx* ctx, const double* amax, const int32_t* idx_in, int64_t n_in,
                double theta, int32_t* idx_out, int64_t* n_out);
 
+/* ---- allocation-free entry point -------------------------------------- */
+
+/* For callers that cannot allocate device memory or synchronise: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The active-set compaction of sdc_select (idx_out = the entries i of idx_in
+ * with amax[i] >= theta, in their order; theta <= 0 keeps every entry; NaN
+ * is dropped otherwise) with no context: it allocates nothing, does not
+ * synchronise, and enqueues three kernels on `stream` (a hipStream_t; NULL =
+ * the null stream) of HIP device `device`.
+ *  amax     device double[n_amax]
+ *  idx_in   device int32[n_in], n_in <= SDC_NOALLOC_MAX_IN
+ *  idx_out  device int32[n_in] (room for all entries; only the kept ones
+ *           are written)
+ *  n_out    device int64[1]: the number of kept entries, or -1 when an entry
+ *           of idx_in lies outside [0, n_amax) (then idx_out is not written)
+ * Scratch: the per-block counts live in a library-held device array of
+ * SDC_NOALLOC_MAX_IN / 256 int32 (256 KiB) per device, set up on the first
+ * call on that device and kept until the process ends.  Every call on a
+ * device shares it: calls that overlap on one device (different streams)
+ * race and must be serialised by the caller.
+ * Returns SDC_ERR_ARG for a null pointer, a negative size, n_in above
+ * SDC_NOALLOC_MAX_IN or a device out of range (nothing enqueued), and
+ * SDC_ERR_HIP when a launch fails. */
+#define SDC_NOALLOC_MAX_IN (1 << 24)
+int sdc_select_noalloc(int32_t device, void* stream, const double* amax, int64_t n_amax,
+                       const int32_t* idx_in, int64_t n_in, double theta, int32_t* idx_out,
+                       int64_t* n_out);
+
 /* ---- measurement ------------------------------------------------------ */
 
 /* Kernel timing of the CG iteration kernel (one launch per iteration: SpMV,

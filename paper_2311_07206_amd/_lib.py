@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libsdc.so")
 MAX_NODES = 6
 MAX_SWEEPS = 16
 MAX_RECORDINGS = 64
+NOALLOC_MAX_IN = 1 << 24
 
 SDC_OK = 0
 ERRORS = {
@@ -101,6 +102,7 @@ SIGNATURES = {
     "sdc_adjoint_record": (c_int32, [c_void_p, c_int32, PTR, PTR, c_double]),
     "sdc_adjoint_reverse": (c_int32, [c_void_p, c_int32, PTR, PTR, PTR, PTR]),
     "sdc_profile_read": (c_int32, [c_void_p, POINTER(ProfileStats)]),
+    "sdc_select_noalloc": (c_int32, [c_int32, c_void_p, PTR, c_int64, PTR, c_int64, c_double, PTR, PTR]),
 }
 
 _lib = None

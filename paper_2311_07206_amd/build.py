@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdc.so")
-SOURCES = ["api.hip", "adjoint.hip", "kernels.hip", "adjoint_kernels.hip", "subset.hip", "assembly.cpp", "collocation.cpp"]
+SOURCES = ["api.hip", "adjoint.hip", "kernels.hip", "adjoint_kernels.hip", "subset.hip", "noalloc.hip", "assembly.cpp",
+           "collocation.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

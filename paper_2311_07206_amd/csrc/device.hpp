@@ -6,6 +6,11 @@
 
 namespace sdc {
 
+// The drop rule of the active sets (eq. "subset"): a row stays when its
+// largest correction reached the drop tolerance; theta <= 0 keeps every row
+// (the non-adaptive method); NaN is dropped otherwise.
+__device__ inline bool keep_row(double a, double theta) { return theta <= 0.0 || a >= theta; }
+
 constexpr int kRecWords = static_cast<int>(sizeof(BlkRec) / sizeof(int32_t));
 
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD

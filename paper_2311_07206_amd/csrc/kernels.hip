@@ -956,9 +956,8 @@ __global__ __launch_bounds__(kBlock) void k_post_sites(Map map, int m, int64_t N
   R_m[i] = Rn;
 }
 
-// ---- active-set compaction (eq. "subset"): keep i with amax_i >= theta.
-
-__device__ inline bool keep_row(double a, double theta) { return theta <= 0.0 || a >= theta; }
+// ---- active-set compaction (eq. "subset"): keep i with amax_i >= theta
+// (keep_row in device.hpp).
 
 // Pass 1: kept rows and their stored entries per block.
 // theta: one drop tolerance, or (inst_theta not null) one per instance.

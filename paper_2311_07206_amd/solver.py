@@ -38,6 +38,30 @@ def collocation(M):
     return tuple(out)
 
 
+def select_noalloc(amax, idx, theta, idx_out, n_out, stream=None):
+    """Allocation-free compaction (sdc_select_noalloc): writes the entries i
+    of idx with amax[i] >= theta to idx_out and their count to n_out[0] (-1
+    when an entry lies outside amax), on the given stream, without
+    allocating or synchronising.  amax float64, idx and idx_out int32 (room
+    for idx.numel() entries), n_out int64 [1]: contiguous tensors on one
+    device."""
+    lib = _lib.load()
+    dev = amax.device
+    for t, dt in ((amax, torch.float64), (idx, torch.int32), (idx_out, torch.int32), (n_out, torch.int64)):
+        if t.device != dev or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous {dt} tensor on {dev}")
+    if idx_out.numel() < idx.numel() or n_out.numel() < 1:
+        raise ValueError("idx_out needs room for every entry of idx, n_out one entry")
+    if idx.numel() > _lib.NOALLOC_MAX_IN:
+        raise ValueError(f"at most {_lib.NOALLOC_MAX_IN} entries (the library's fixed scratch)")
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc = lib.sdc_select_noalloc(dev.index, ctypes.c_void_p(st.cuda_stream), _ptr(amax), amax.numel(), _ptr(idx),
+                                idx.numel(), float(theta), _ptr(idx_out), _ptr(n_out))
+    if rc != 0:
+        raise SDCError(rc, "sdc_select_noalloc: bad arguments (sizes, pointers, device)" if rc == -1 else
+                       "sdc_select_noalloc: launch failed")
+
+
 class Solver:
     """One library context: an assembled mesh (possibly several instances)."""
 
