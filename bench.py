@@ -1,20 +1,30 @@
-"""Benchmark: adaptive SDC steps on the 2D monodomain workload on one MI355X.
+"""Benchmark: adaptive SDC steps of the batched workload on one MI355X.
 
-Workload: 512 x 512 P1 triangle mesh (262,144 dofs) on [0,2]^2 cm,
-anisotropic fibre conductivity, Aliev-Panfilov reaction, SDC on M = 4
+Headline workload (the metric's configuration): 48 independent 2D
+monodomain instances of sides 96..384 (3,694,813 dofs in one context), P1
+triangles on [0,2]^2 cm, isotropic conductivity 1e-3 exp(0.3 g) with g a
+smoothed seeded Gaussian field, Aliev-Panfilov reaction, SDC on M = 3
 Radau-IIA nodes, K = 4 sweeps per step, dt = 0.2 ms, drop tolerance 1e-7,
 Jacobi-PCG to rtol 1e-12 (synthetic seeded inputs).  A "step" is one SDC
-time step: K sweeps, each with M restricted solves, the reaction and the
-active-set selection.  `--warmup` steps run first (the front leaves the
-stimulus strip), then exactly `--steps` steps are timed with the device
-synchronised on both sides.
+time step of every instance: K sweeps, each with M restricted solves per
+instance, the reaction and the active-set selection.  `--warmup` steps run
+first from t = 0 (the stimulus), then exactly `--steps` steps are timed with
+the device synchronised on both sides; the timed window is repeated
+`--repeats` times from the same state and the median repeat is reported.
 
-Reported value: active dof-sweeps per second = sum over timed steps and
-sweeps of the active rows, divided by the timed wall time.  The roofline
-entry is for the dominant kernel (the CG SpMV pass), timed with HIP events
-on the library's stream; its bytes are the algorithmic minimum per launch.
-The CPU baseline is the FP64 oracle on one host core, run on a bounded
-sample of the same workload (a few steps from the same state).
+Reported value: active dof-sweeps per second = sum over the window's steps
+and sweeps of the active rows, divided by its wall time.  The roofline
+entry is for the dominant kernel (the CG iteration, one launch per CG
+iteration over all instances still iterating), timed with HIP events on the
+library's stream in a second pass over the same window; its bytes per
+launch are given three ways: the per-iteration count of the scope table
+(12 B per stored entry, 120 B per row), the minimum the chosen matrix
+storage must move, and HBM traffic from committed rocprofv3 counters.  The
+adjoint/forward ratio is the reverse pass of 100 steps (checkpoint every
+10) over the forward pass of the same steps.  The CPU baseline is the FP64
+oracle on one host core over the first step(s) of the same window.  Further
+legs: the 2D 512^2 and 3D 128^3 single-instance workloads and the
+cell-by-cell workloads.
 """
 import argparse
 import json
@@ -31,16 +41,18 @@ HBM_PEAK_GBS = 8000.0
 # wall-clock speedups of adaptive over non-adaptive SDC that the paper
 # reports on CPUs (Kaskade 7; 2D: Core i7-9700T, 3D: Xeon E5), for context
 PAPER_SPEEDUP = {"2d_monodomain": 2.13, "2d_emi": 3.336, "3d_monodomain": 3.29, "3d_emi": 4.344}
-COUNTERS = os.path.join(ROOT, "profiles", "k_cg_iter_2d512_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "k_cg_iter_batched48_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2311_07206_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic():
-    """Bytes per k_cg_iter launch from the committed FETCH_SIZE/WRITE_SIZE runs,
-    or None when the kernel source changed since they were taken."""
+def measured_traffic(path=None):
+    """HBM bytes per updating CG-iteration launch from committed FETCH_SIZE /
+    WRITE_SIZE runs, as a dict with "all" and, when the summary has them,
+    "listed" and "all_rows" launches; None when the kernel source changed
+    since the counters were taken."""
     import hashlib
     try:
-        text = open(COUNTERS).read()
+        text = open(path or COUNTERS).read()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
@@ -48,30 +60,56 @@ def measured_traffic():
     src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     if fields.get("kernels.hip sha256") != src:
         return None
-    return float(fields["measured bytes per launch"]), float(fields["algorithmic bytes per launch"])
+    out = {"all": float(fields["measured bytes per launch"])}
+    for key, name in (("listed", "measured bytes per listed launch"),
+                      ("all_rows", "measured bytes per all-rows launch")):
+        if name in fields:
+            out[key] = float(fields[name])
+    if "algorithmic bytes per launch" in fields:
+        out["algorithmic"] = float(fields["algorithmic bytes per launch"])
+    return out
 
 
 def summarize_trace(path):
     """Markdown summary of a rocprofv3 --kernel-trace CSV: per-kernel totals and
-    the CG iteration kernel's duration by grid size."""
+    the CG iteration kernel's duration by grid size and by launch class.
+    When the run made calibration copies (the longest copies of the run),
+    only the dispatches after the last of them count (the timed window)."""
     import collections
     import csv
     import re
-    durs, grid = collections.defaultdict(list), collections.defaultdict(list)
-    for row in csv.DictReader(open(path)):
-        m = re.search(r"(k_\w+)", row["Kernel_Name"])
-        name = m.group(1) if m else row["Kernel_Name"].split("(")[0][:60]
-        d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+    rows = list(csv.DictReader(open(path)))
+    dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
+    copies = [q for q, r in enumerate(rows) if "copyBuffer" in r["Kernel_Name"]]
+    start = 0
+    if copies:
+        longest = max(dur[q] for q in copies)
+        start = max(q for q in copies if dur[q] >= 0.5 * longest) + 1 if longest > 50000 else 0
+    durs, grid, by_cls = collections.defaultdict(list), collections.defaultdict(list), collections.defaultdict(list)
+    for r, d in list(zip(rows, dur))[start:]:
+        m = re.search(r"(k_\w+)", r["Kernel_Name"])
+        name = m.group(1) if m else r["Kernel_Name"].split("(")[0][:60]
         durs[name].append(d)
         if name in ("k_cg_iter", "k_cg_iter2"):   # one or two rows per thread; 256-row map entries either way
-            grid[int(row["Grid_Size_X"]) // int(row["Workgroup_Size_X"])].append(d)
+            grid[int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])].append(d)
+            by_cls[cg_launch_class(r["Kernel_Name"])].append(d)
     total = sum(sum(v) for v in durs.values())
-    out = ["| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
+    out = [f"dispatches counted: {len(rows) - start} of {len(rows)}"
+           + (" (after the calibration copies)" if start else ""), "",
+           "| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
     for k, v in sorted(durs.items(), key=lambda z: -sum(z[1])):
         out.append(f"| {k} | {len(v)} | {sum(v) / 1e6:.2f} | {np.mean(v) / 1e3:.3f} | {100 * sum(v) / total:.1f}% |")
     v = np.array(durs.get("k_cg_iter", []) + durs.get("k_cg_iter2", []) or [0])
     out += ["", f"CG iteration (k_cg_iter, k_cg_iter2): {len(v)} dispatches, mean {v.mean() / 1e3:.3f} us", "",
-            "| blocks (256 rows) | dispatches | median us | mean us |", "|---|---|---|---|"]
+            "| launch class | dispatches | mean us | median us | dispatches >= 5 us | their mean us |",
+            "|---|---|---|---|---|---|"]
+    for c in ("all_rows", "listed"):
+        x = np.array(by_cls.get(c, []))
+        if len(x):
+            big = x[x >= 5000]
+            out.append(f"| {c} | {len(x)} | {x.mean() / 1e3:.2f} | {np.median(x) / 1e3:.2f} | {len(big)} | "
+                       f"{(big.mean() if len(big) else 0) / 1e3:.2f} |")
+    out += ["", "| blocks (256 rows) | dispatches | median us | mean us |", "|---|---|---|---|"]
     bins = [(1, 128), (128, 256), (256, 512), (512, 1024), (1024, 1025), (1025, 1 << 30)]
     for lo, hi in bins:
         x = np.array([d for g, ds in grid.items() if lo <= g < hi for d in ds])
@@ -80,12 +118,26 @@ def summarize_trace(path):
     return "\n".join(out)
 
 
+def cg_launch_class(name):
+    """'listed' or 'all_rows' for a CG-iteration kernel name, else None
+    (k_cg_iter2: every row, two per thread; k_cg_iter<S, FIRST, LIST, TOT>:
+    LIST 1 a listed set, 0 every row)."""
+    import re
+    if "k_cg_iter2" in name:
+        return "all_rows"
+    m = re.search(r"k_cg_iter<\s*-?\d+\s*,\s*\w+\s*,\s*(-?\d+)", name)
+    if m:
+        return "listed" if m.group(1) == "1" else "all_rows"
+    return None
+
+
 def summarize_counters(fetch_csv, write_csv, min_blocks=0):
     """Pair FETCH_SIZE and WRITE_SIZE runs dispatch by dispatch (KiB per
     dispatch).  A 256 MiB device copy (reads and writes 262144 KiB) calibrates
     each counter; the CG iteration's launches that perform an update (writes
     above 1 KiB), with at least min_blocks map entries, give the measured HBM
-    bytes per launch."""
+    bytes per launch, over all of them and by launch class (listed set or
+    every row)."""
     import csv
     rows = []
     for path in (fetch_csv, write_csv):
@@ -93,39 +145,58 @@ def summarize_counters(fetch_csv, write_csv, min_blocks=0):
         rows.append(r)
     f, w = rows
     assert len(f) == len(w), "the two runs must dispatch the same kernels"
-    cg_f, cg_w, copy = [], [], []
+    cg_f, cg_w, cls, copy = [], [], [], []
     for a, b in zip(f, w):
         assert a["Kernel_Name"] == b["Kernel_Name"]
-        if "k_cg_iter" in a["Kernel_Name"]:
+    # only the launches after the last calibration copy (the timed window)
+    last = max([q for q, b in enumerate(w) if "copyBuffer" in b["Kernel_Name"]
+                and abs(float(b["Counter_Value"]) - 262144.0) < 13000.0] or [-1])
+    for q, (a, b) in enumerate(zip(f, w)):
+        if "k_cg_iter" in a["Kernel_Name"] and q > last:
             if min_blocks and int(a["Grid_Size"]) // int(a["Workgroup_Size"]) < min_blocks:
                 continue
             cg_f.append(float(a["Counter_Value"]))
             cg_w.append(float(b["Counter_Value"]))
+            cls.append(cg_launch_class(a["Kernel_Name"]))
         elif "copyBuffer" in a["Kernel_Name"] and abs(float(b["Counter_Value"]) - 262144.0) < 13000.0:
             copy.append((float(a["Counter_Value"]), float(b["Counter_Value"])))
-    cg_f, cg_w = np.array(cg_f), np.array(cg_w)
+    cg_f, cg_w, cls = np.array(cg_f), np.array(cg_w), np.array(cls, dtype=object)
     work = cg_w > 1.0
     ff = 262144.0 / np.mean([c[0] for c in copy])
     fw = 262144.0 / np.mean([c[1] for c in copy])
     fetch_kib, write_kib = cg_f[work].mean(), cg_w[work].mean()
-    measured = (ff * fetch_kib + fw * write_kib) * 1024.0
-    return {"copy_fetch_kib": [c[0] for c in copy], "copy_write_kib": [c[1] for c in copy],
-            "fetch_factor": ff, "write_factor": fw, "dispatches": int(len(cg_f)), "updating": int(work.sum()),
-            "fetch_kib_per_launch": fetch_kib, "write_kib_per_launch": write_kib,
-            "measured_bytes_per_launch": measured}
+    out = {"copy_fetch_kib": [c[0] for c in copy], "copy_write_kib": [c[1] for c in copy],
+           "fetch_factor": ff, "write_factor": fw, "dispatches": int(len(cg_f)), "updating": int(work.sum()),
+           "fetch_kib_per_launch": fetch_kib, "write_kib_per_launch": write_kib,
+           "measured_bytes_per_launch": (ff * fetch_kib + fw * write_kib) * 1024.0}
+    for c in ("listed", "all_rows"):
+        sel = work & (cls == c)
+        if sel.any():
+            out[f"{c}_updating"] = int(sel.sum())
+            out[f"{c}_bytes_per_launch"] = (ff * cg_f[sel].mean() + fw * cg_w[sel].mean()) * 1024.0
+    return out
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--n", type=int, default=512, help="grid side (workload uses 512)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps of the batched workload")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps from t = 0 before the window")
+    ap.add_argument("--repeats", type=int, default=5, help="repeats of the timed window (median reported)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the batched workload's window and its kernel pass (profiling runs)")
+    ap.add_argument("--adjoint-steps", type=int, default=100)
+    ap.add_argument("--ckpt-every", type=int, default=10)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the 48 instances run one after another")
+    ap.add_argument("--n", type=int, default=512, help="grid side of the 2D leg (workload uses 512)")
+    ap.add_argument("--steps-2d", type=int, default=20)
+    ap.add_argument("--warmup-2d", type=int, default=5)
+    ap.add_argument("--cpu-sample-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched / adjoint measurements")
-    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-2d", action="store_true", help="skip the 512^2 single-instance leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 3D workload")
     ap.add_argument("--no-emi", action="store_true", help="skip the cell-by-cell workloads (2D and 3D)")
     ap.add_argument("--emi-steps", type=int, default=3)
@@ -141,8 +212,6 @@ def parse():
                     help="the latency curve's solver option (0: default one-launch solves of small sets, -1: off)")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the time-per-sweep curve over front-shell active sets")
-    ap.add_argument("--profile-warmup", action="store_true",
-                    help="account CG kernel bytes from the first step (matches counter runs)")
     ap.add_argument("--calib", action="store_true",
                     help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
@@ -152,6 +221,75 @@ def parse():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="pair rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, print JSON and exit")
     return ap.parse_args()
+
+
+def cg_roofline(prof, storage, n_diag, peak=None):
+    """The CG iteration's roofline over the profiled launches: bytes per
+    launch three ways and the event-timed mean launch duration.
+
+    scope_table: 12 B per stored entry (8 value + 4 column) and, per row,
+      4 (row pointer) + 4 (list entry, listed sets only) + 112 (14 vector
+      touches) -- the per-iteration count of the scope table;
+    storage_min: what the chosen storage must move at least: the symmetric
+      diagonal storage reads its nd/2 + 1 stored diagonals per row (8 B each),
+      CSR 12 B per entry and a 4 B row pointer; per row 5 vectors read once
+      (u, w, s scaled by the preconditioner, p, x) and the same 5 written
+      (dinv is formed from the diagonal), plus the list entry;
+    achieved: scope_table bytes / mean launch duration (the reported frac).
+    """
+    peak = peak or HBM_PEAK_GBS
+    L, ms = prof["cg_launches"], prof["cg_ms"]
+    rows, nnz = prof["cg_rows"], prof["cg_nnz"]
+    listed_rows = rows - prof["cg_all_rows"]
+    b_scope = 12.0 * nnz + 116.0 * rows + 4.0 * listed_rows
+    if storage == "dia":
+        b_min = (8.0 * (n_diag // 2 + 1) + 80.0) * rows + 4.0 * listed_rows
+    else:
+        b_min = 12.0 * nnz + 84.0 * rows + 4.0 * listed_rows
+    sec = ms * 1e-3
+    out = {"kernel": "k_cg_iter (all CG-iteration launches: listed sets k_cg_iter, every row k_cg_iter2)",
+           "bound": "hbm", "achieved": b_scope / sec / 1e9, "peak": peak, "unit": "GB/s",
+           "frac": b_scope / sec / 1e9 / peak, "traffic": None,
+           "avg_launch_us": 1e3 * ms / L, "launches": L,
+           "bytes_per_launch_scope_table": b_scope / L, "bytes_per_launch_storage_min": b_min / L,
+           "storage_min_GBps": b_min / sec / 1e9, "frac_storage_min": b_min / sec / 1e9 / peak,
+           "rows_per_launch": rows / L}
+    for cls, launches, lms, lrows, lnnz, listed in (
+            ("all_rows", prof["cg_all_launches"], prof["cg_all_ms"], prof["cg_all_rows"], prof["cg_all_nnz"], 0.0),
+            ("listed", L - prof["cg_all_launches"], ms - prof["cg_all_ms"], listed_rows, nnz - prof["cg_all_nnz"],
+             1.0)):
+        if launches <= 0 or lms <= 0:
+            continue
+        bs = 12.0 * lnnz + (116.0 + 4.0 * listed) * lrows
+        bm = ((8.0 * (n_diag // 2 + 1) + 80.0) * lrows if storage == "dia" else 12.0 * lnnz + 84.0 * lrows) \
+            + 4.0 * listed * lrows
+        out[cls] = {"launches": launches, "avg_launch_us": 1e3 * lms / launches, "rows_per_launch": lrows / launches,
+                    "scope_table_GBps": bs / (lms * 1e-3) / 1e9, "frac": bs / (lms * 1e-3) / 1e9 / peak,
+                    "storage_min_GBps": bm / (lms * 1e-3) / 1e9, "frac_storage_min": bm / (lms * 1e-3) / 1e9 / peak}
+    return out
+
+
+def add_traffic(roof, mt, prof):
+    """Counter-measured HBM bytes per launch (committed profile of the same
+    command) beside the byte models, weighted by this run's launch mix."""
+    if mt is None:
+        return roof
+    L, La = prof["cg_launches"], prof["cg_all_launches"]
+    if "listed" in mt and "all_rows" in mt:
+        per = (mt["all_rows"] * La + mt["listed"] * (L - La)) / L
+    else:
+        per = mt["all"]
+    sec = prof["cg_ms"] * 1e-3
+    roof["traffic"] = per
+    roof["measured_GBps"] = per * L / sec / 1e9
+    roof["frac_measured"] = roof["measured_GBps"] / roof["peak"]
+    for cls in ("all_rows", "listed"):
+        if cls in mt and cls in roof:
+            t = roof[cls]["avg_launch_us"] * 1e-6
+            roof[cls]["traffic"] = mt[cls]
+            roof[cls]["measured_GBps"] = mt[cls] / t / 1e9
+            roof[cls]["frac_measured"] = mt[cls] / t / 1e9 / roof["peak"]
+    return roof
 
 
 def sweep_bytes(st, M, ident):
@@ -198,71 +336,60 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
+    out, window = headline(args)
+    if not args.headline_only:
+        out["copy_GBps"] = copy_bandwidth()
+        if "roofline" in out:
+            out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / out["copy_GBps"]
+        if not args.no_2d:
+            out["workload_2d"] = workload_2d(args)
+        if not args.no_3d:
+            out["workload_3d"] = workload_3d(speedup=not args.no_speedup, first_sweep=not args.no_first_sweep,
+                                             cg_energy=not args.no_cg_energy)
+        if not args.no_emi:
+            out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
+            out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
+    if not args.no_cpu and not args.headline_only:
+        out["cpu_baseline"] = cpu_baseline(*window, args.cpu_sample_steps, args.steps)
+    print(json.dumps(out), flush=True)
+
+
+def headline(args):
+    """The batched workload: `warmup` steps from t = 0, then the window of
+    `steps` steps, timed `repeats` times from the same state (median
+    reported), a kernel-timing pass over the same window, and the legs that
+    belong to this workload (each instance alone, non-adaptive, adjoint)."""
     import torch
 
     from paper_2311_07206_amd import Solver
-    from workloads import config1
+    from workloads import config4
 
-    P = config1(n=args.n, theta=1e-7)
+    P = config4()
     dev = torch.device("cuda", 0)
-    if args.calib:
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    sync = torch.cuda.synchronize
     s = Solver.from_problem(P)
     v = torch.tensor(P.v_init, device=dev)
     w = torch.tensor(P.w_init, device=dev)
-    t = 0.0
-    if args.profile_warmup:
-        s.profile(True)
     for n in range(args.warmup):
-        s.step(v, w, t)
-        t += P.dt
-    torch.cuda.synchronize()
-    v_start, w_start, t_start = v.cpu().numpy().copy(), w.cpu().numpy().copy(), t
-
-    final = {}
-
-    def timed(profile):
-        vv, ww = torch.tensor(v_start, device=dev), torch.tensor(w_start, device=dev)
-        tt = t_start
-        logs = []
-        if profile:
-            s.profile(True)   # clears the totals
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for n in range(args.steps):
-            logs.append(s.step(vv, ww, tt, stats=True))
-            tt += P.dt
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        final["v"] = vv.cpu().numpy()
-        prof = s.profile_read() if profile else None
-        if profile:
-            s.profile(False)
-        return el, logs, prof
-
-    if args.profile_warmup:
-        # one timed pass, accounted together with the warm-up (as the counter runs see it)
-        elapsed, logs, prof = timed(False)
-        prof = s.profile_read()
-        prof = {k: prof[k] for k in prof}
-    else:
-        elapsed, logs, _ = timed(False)
-        prof = None
-        if not args.no_profile:
-            _, _, prof = timed(True)
-    sweeps = [st for lg in logs for st in lg]
-    dof_sweeps = sum(st["n_active"] for st in sweeps)
+        s.step(v, w, n * P.dt)
+    sync()
+    v_start, w_start, t_start = v.clone(), w.clone(), args.warmup * P.dt
+    if args.calib:
+        calibration_copies(dev)   # counter calibration, and the window's start in traces
+    times, logs, v_end = [], None, None
+    for r in range(max(1, args.repeats)):
+        vv, ww = v_start.clone(), w_start.clone()
+        el, lg = _timed_steps(s, vv, ww, t_start, P.dt, args.steps, sync)
+        times.append(el)
+        if logs is None:
+            logs, v_end = lg, vv.cpu().numpy()
+        else:   # the same window from the same state: the same sets every repeat
+            assert [st["n_active"] for x in lg for st in x] == [st["n_active"] for x in logs for st in x]
+    elapsed = float(np.median(times))
+    dof_sweeps = sum(st["n_active"] for lg in logs for st in lg)
     nbytes = sum(sweep_bytes(st, P.M, k == 0) for lg in logs for k, st in enumerate(lg))
     nbytes += args.steps * step_bytes(P.N, P.M)
-    per_sweep_active = [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)]
-    cg_iters = [float(np.mean([lg[k]["cg_iters_max"][m] for lg in logs for k in range(P.K)])) for m in range(P.M)]
-
+    info = s.info()
     out = {
         "metric": "active dof-sweeps/sec + HBM GB/s (% peak); adjoint/forward time ratio",
         "value": dof_sweeps / elapsed,
@@ -277,67 +404,178 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"2D monodomain {args.n}x{args.n} P1 ({P.N} dofs), Aliev-Panfilov, SDC M={P.M} K={P.K} "
-                        f"dt={P.dt} ms, theta={P.theta}, Jacobi-PCG rtol {P.cg_rtol}; timed steps "
-                        f"t={t_start:.1f}..{t_start + args.steps * P.dt:.1f} ms",
-            "dofs": P.N, "nnz": s.nnz, "M": P.M, "K": P.K,
-        },
-        "storage": s.info(),
+            "workload": f"batched: {P.n_inst} 2D monodomain instances, sides 96..384 ({P.N} dofs), "
+                        f"Aliev-Panfilov, SDC M={P.M} K={P.K} dt={P.dt} ms, theta={P.theta}, Jacobi-PCG rtol "
+                        f"{P.cg_rtol}; timed steps {args.warmup}..{args.warmup + args.steps - 1} "
+                        f"(t={t_start:.1f}..{t_start + args.steps * P.dt:.1f} ms), median of {len(times)} repeats",
+            "instances": P.n_inst, "dofs": P.N, "nnz": s.nnz, "M": P.M, "K": P.K},
+        "repeats_ms_per_step": [1e3 * t / args.steps for t in times],
+        "storage": info,
         "algorithmic_GBps": nbytes / elapsed / 1e9,
-        "algorithmic_frac_hbm": nbytes / elapsed / 1e9 / HBM_PEAK_GBS,
-        "mean_active_per_sweep": per_sweep_active,
-        "mean_cg_iters_per_node": cg_iters,
+        "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)],
+        "mean_cg_iters_per_node": [float(np.mean([lg[k]["cg_iters_max"][m] for lg in logs for k in range(P.K)]))
+                                   for m in range(P.M)],
     }
-    if prof and prof["cg_launches"]:
-        ach = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
-        out["roofline"] = {
-            "kernel": "k_cg_iter", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None,
-            "avg_launch_us": 1e3 * prof["cg_ms"] / prof["cg_launches"],
-            "bytes_per_launch": prof["cg_bytes"] / prof["cg_launches"],
-            "launches": prof["cg_launches"],
-        }
-        mt = measured_traffic()
-        if mt is not None:
-            # counters: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy calibration), per launch,
-            # averaged over the counter runs' launches; scaled to this run's mix
-            out["roofline"]["traffic"] = out["roofline"]["bytes_per_launch"] * mt[0] / mt[1]
-            out["roofline"]["traffic_over_algorithmic"] = mt[0] / mt[1]
-        if args.profile_warmup:
-            out["roofline"]["scope"] = "warm-up and timed steps"
+    if not args.no_profile:
+        # kernel timing in a second pass over the same window (events around each CG launch)
+        s.profile(True)
+        _timed_steps(s, v_start.clone(), w_start.clone(), t_start, P.dt, args.steps, sync)
+        prof = s.profile_read()
+        s.profile(False)
+        if prof["cg_launches"]:
+            roof = cg_roofline(prof, info["format"], info["n_diagonals"])
+            out["roofline"] = add_traffic(roof, measured_traffic(COUNTERS), prof)
+    if not args.headline_only:
+        if not args.no_speedup:
+            el0 = nonadaptive_run(P, v_start.cpu().numpy(), w_start.cpu().numpy(), t_start, args.steps)
+            out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / args.steps,
+                                              "speedup": el0 / elapsed}
+        if not args.no_sequential:
+            seq = sequential_instances(P, v_start.cpu().numpy(), w_start.cpu().numpy(), t_start, args.steps)
+            out["sequential_ms_per_step"] = 1e3 * seq / args.steps
+            out["speedup_vs_sequential"] = seq / elapsed
+        if not args.no_adjoint:
+            out["adjoint"] = adjoint_ratio(P, s, args.adjoint_steps, args.ckpt_every)
+            out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
     s.close()
-    out["copy_GBps"] = copy_bandwidth()
-    if "roofline" in out:
-        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / out["copy_GBps"]
+    return out, (P, v_start.cpu().numpy(), w_start.cpu().numpy(), t_start)
+
+
+def calibration_copies(dev, n=3):
+    """n device copies of 256 MiB: they calibrate FETCH_SIZE / WRITE_SIZE
+    (known bytes) and, being the longest copies of the run, mark where the
+    timed window starts in a kernel trace."""
+    import torch
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(n):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def sequential_instances(P, v0, w0, t0, nsteps):
+    """Wall time of the same window with each instance in a context of its
+    own, run one after another."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    seq = 0.0
+    for i in range(P.n_inst):
+        lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
+        e0, e1 = int(P.elem_off[i]), int(P.elem_off[i + 1])
+        si = Solver(P.coords[lo:hi], P.elems[e0:e1] - lo, P.elem_tensor[e0:e1], P.node_sigma[lo:hi],
+                    P.ionic[i:i + 1], [0, hi - lo], [0, e1 - e0], P.M, P.K, P.dt, P.theta)
+        vi = torch.tensor(v0[lo:hi], device=dev)
+        wi = torch.tensor(w0[lo:hi], device=dev)
+        si.step(vi.clone(), wi.clone(), t0)   # warm the iteration budgets
+        e, _ = _timed_steps(si, vi, wi, t0, P.dt, nsteps, torch.cuda.synchronize)
+        seq += e
+        si.close()
+    return seq
+
+
+def adjoint_ratio(P, s, nsteps=100, ckpt=10):
+    """Reverse mode over the batched workload's forward run of nsteps steps
+    from t = 0 with checkpoints every ckpt steps: the gradient of
+    0.5 ||v(T) - v_target||^2 with respect to the nodal conductivity and each
+    instance's Aliev-Panfilov a, v_target from a forward run of the same
+    steps with the seeded perturbed conductivity (the workload's target).
+    Ratio = backward wall time (checkpoint recomputation included) / forward
+    wall time."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    from paper_2311_07206_amd.autograd import SDCRun
+    from workloads import config4
+
+    dev = torch.device("cuda", 0)
+    sync = torch.cuda.synchronize
+    T = config4(target=True)
+    st = Solver.from_problem(T)
+    vt = torch.tensor(T.v_init, device=dev)
+    wt = torch.tensor(T.w_init, device=dev)
+    for n in range(nsteps):
+        st.step(vt, wt, n * T.dt)
+    st.close()
+    sigma = torch.tensor(P.node_sigma, device=dev, requires_grad=True)
+    a = torch.tensor(P.ionic[:, 1].copy(), device=dev, requires_grad=True)
+    v0 = torch.tensor(P.v_init, device=dev, requires_grad=True)
+    w0 = torch.tensor(P.w_init, device=dev, requires_grad=True)
+    sync()
+    t = time.perf_counter()
+    vT, _ = SDCRun.apply(sigma, a, v0, w0, s, nsteps, 0.0, ckpt)
+    sync()
+    tf = time.perf_counter() - t
+    loss = 0.5 * ((vT - vt) ** 2).sum()
+    sync()
+    t = time.perf_counter()
+    loss.backward()
+    sync()
+    tb = time.perf_counter() - t
+    return {"workload": f"{P.n_inst} instances, {nsteps} steps from t = 0, checkpoint every {ckpt} steps; "
+                        f"loss 0.5 ||v(T) - v_target||^2, v_target from the seeded perturbed-sigma forward run; "
+                        f"gradients w.r.t. nodal sigma and per-instance a",
+            "forward_ms": 1e3 * tf, "backward_ms": 1e3 * tb, "ratio": tb / tf, "loss": float(loss),
+            "grad_sigma_norm": float(sigma.grad.norm()), "grad_a": a.grad.cpu().numpy().tolist()[:4]}
+
+
+def workload_2d(args):
+    """The 512^2 single-instance workload: `warmup_2d` steps from t = 0, then
+    `steps_2d` timed steps; its own roofline, adaptive/non-adaptive speedup,
+    the heuristic first-sweep set, the paper's CG stop, the linearized scheme
+    and the time-per-sweep curve over front-shell sets."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    from workloads import config1
+
+    P = config1(n=args.n, theta=1e-7)
+    dev = torch.device("cuda", 0)
+    sync = torch.cuda.synchronize
+    s = Solver.from_problem(P)
+    v = torch.tensor(P.v_init, device=dev)
+    w = torch.tensor(P.w_init, device=dev)
+    for n in range(args.warmup_2d):
+        s.step(v, w, n * P.dt)
+    sync()
+    v_start, w_start, t_start = v.cpu().numpy().copy(), w.cpu().numpy().copy(), args.warmup_2d * P.dt
+    nsteps = args.steps_2d
+    vv, ww = torch.tensor(v_start, device=dev), torch.tensor(w_start, device=dev)
+    elapsed, logs = _timed_steps(s, vv, ww, t_start, P.dt, nsteps, sync)
+    v_std = vv.cpu().numpy()
+    out = {"workload": f"2D monodomain {args.n}x{args.n} P1 ({P.N} dofs), M={P.M} K={P.K} dt={P.dt} ms, "
+                       f"theta={P.theta}; timed steps t={t_start:.1f}..{t_start + nsteps * P.dt:.1f} ms",
+           "value": sum(st["n_active"] for lg in logs for st in lg) / elapsed, "unit": "active dof-sweeps/s",
+           "ms_per_step": 1e3 * elapsed / nsteps, "storage": s.info(),
+           "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)]}
+    if not args.no_profile:
+        s.profile(True)
+        _timed_steps(s, torch.tensor(v_start, device=dev), torch.tensor(w_start, device=dev), t_start, P.dt,
+                     nsteps, sync)
+        prof = s.profile_read()
+        s.profile(False)
+        if prof["cg_launches"]:
+            info = out["storage"]
+            out["roofline"] = cg_roofline(prof, info["format"], info["n_diagonals"])
+    s.close()
+    v_non = None
     if not args.no_speedup:
-        # the same timed steps without the drop tolerance (every row in every sweep)
-        el0, final["v_non"] = nonadaptive_run(P, v_start, w_start, t_start, args.steps, return_state=True)
-        out["adaptive_vs_nonadaptive"] = {
-            "nonadaptive_ms_per_step": 1e3 * el0 / args.steps, "adaptive_ms_per_step": out["ms_per_step"],
-            "speedup": el0 / elapsed, "paper_cpu_speedup_2d_monodomain": PAPER_SPEEDUP["2d_monodomain"]}
+        el0, v_non = nonadaptive_run(P, v_start, w_start, t_start, nsteps, return_state=True)
+        out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / nsteps, "speedup": el0 / elapsed,
+                                          "paper_cpu_speedup_2d_monodomain": PAPER_SPEEDUP["2d_monodomain"]}
     if not args.no_first_sweep:
-        out["first_sweep_subset"] = first_sweep_variant(P, v_start, w_start, t_start, args.steps,
-                                                        out["ms_per_step"], final["v"], final.get("v_non"))
+        out["first_sweep_subset"] = first_sweep_variant(P, v_start, w_start, t_start, nsteps, out["ms_per_step"],
+                                                        v_std, v_non)
     if not args.no_cg_energy:
-        out["cg_energy_stop"] = cg_energy_variant(P, v_start, w_start, t_start, args.steps, out["ms_per_step"],
-                                                  final["v"], final.get("v_non"), speedup=not args.no_speedup)
+        out["cg_energy_stop"] = cg_energy_variant(P, v_start, w_start, t_start, nsteps, out["ms_per_step"], v_std,
+                                                  v_non, speedup=not args.no_speedup)
     if not args.no_linearized:
-        out["workload_2d_linearized"] = workload_linearized(P, v_start, w_start, t_start, min(args.steps, 100),
-                                                            speedup=not args.no_speedup)
-    if not args.no_batch:
-        out["batched"], out["adjoint"] = batched_and_adjoint(args.batch_steps)
-        out["adjoint_forward_ratio"] = out["adjoint"]["ratio_ckpt10"]
-    if not args.no_3d:
-        out["workload_3d"] = workload_3d(speedup=not args.no_speedup, first_sweep=not args.no_first_sweep,
-                                         cg_energy=not args.no_cg_energy)
-    if not args.no_emi:
-        out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
-        out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
+        out["linearized"] = workload_linearized(P, v_start, w_start, t_start, nsteps, speedup=not args.no_speedup)
     if not args.no_latency:
         out["latency_curve"] = latency_curve(P, small_set_rows=args.small_set_rows)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(P, v_start, w_start, t_start, args.cpu_sample_steps)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def front_shell_masks(coords, elems, v, densities, level=0.5):
@@ -539,89 +777,6 @@ def _timed_steps(solver, v, w, t0, dt, n, sync):
     return time.perf_counter() - t, logs
 
 
-def batched_and_adjoint(nsteps):
-    """48 uneven 2D instances in one context: throughput vs each instance run
-    alone, and the reverse step's cost relative to the forward."""
-    import torch
-
-    from paper_2311_07206_amd import Solver
-    from paper_2311_07206_amd.autograd import SDCRun
-    from workloads import config4
-
-    P = config4()
-    dev = torch.device("cuda", 0)
-    sync = torch.cuda.synchronize
-    s = Solver.from_problem(P)
-    v = torch.tensor(P.v_init, device=dev)
-    w = torch.tensor(P.w_init, device=dev)
-    warm = 10
-    for k in range(warm):
-        s.step(v, w, k * P.dt)
-    v0b, w0b, t0 = v.clone(), w.clone(), warm * P.dt
-    el, logs = _timed_steps(s, v, w, t0, P.dt, nsteps, sync)
-    dofs = sum(st["n_active"] for lg in logs for st in lg)
-    batched = {"workload": f"{P.n_inst} 2D instances, sides 96..384 ({P.N} dofs total), M={P.M} K={P.K} "
-                           f"dt={P.dt}, theta={P.theta}",
-               "value": dofs / el, "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
-               "storage": s.info()}
-    # kernel timings from a second pass over the same steps; the first
-    # sweep's launches over all 3.7 M rows (0.4 GB) leave the Infinity Cache
-    s.profile(True)
-    _timed_steps(s, v0b.clone(), w0b.clone(), t0, P.dt, nsteps, sync)
-    prof = s.profile_read()
-    s.profile(False)
-    if prof["cg_launches"]:
-        batched["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
-        batched["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]
-    if prof["cg_all_launches"]:
-        ach = prof["cg_all_bytes"] / (prof["cg_all_ms"] * 1e-3) / 1e9
-        batched["roofline_all_rows"] = {
-            "kernel": "k_cg_iter2", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "avg_launch_us": 1e3 * prof["cg_all_ms"] / prof["cg_all_launches"],
-            "bytes_per_launch": prof["cg_all_bytes"] / prof["cg_all_launches"],
-            "launches": prof["cg_all_launches"]}
-    # each instance alone, same steps from the same state
-    seq = 0.0
-    v0h, w0h = v0b.cpu().numpy(), w0b.cpu().numpy()
-    for i in range(P.n_inst):
-        lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
-        e0, e1 = int(P.elem_off[i]), int(P.elem_off[i + 1])
-        si = Solver(P.coords[lo:hi], P.elems[e0:e1] - lo, P.elem_tensor[e0:e1], P.node_sigma[lo:hi],
-                    P.ionic[i:i + 1], [0, hi - lo], [0, e1 - e0], P.M, P.K, P.dt, P.theta)
-        vi = torch.tensor(v0h[lo:hi], device=dev)
-        wi = torch.tensor(w0h[lo:hi], device=dev)
-        si.step(vi.clone(), wi.clone(), t0)   # warm the iteration budgets
-        e, _ = _timed_steps(si, vi, wi, t0, P.dt, nsteps, sync)
-        seq += e
-        si.close()
-    batched["sequential_ms_per_step"] = 1e3 * seq / nsteps
-    batched["speedup_vs_sequential"] = seq / el
-    # reverse mode: loss 0.5 ||v(T) - target||^2 over nsteps steps
-    target = torch.rand(P.N, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(5))
-    adj = {"workload": batched["workload"] + f", {nsteps} steps, gradients w.r.t. nodal sigma and per-instance a"}
-    for ck in (10, 1):
-        sigma = torch.tensor(P.node_sigma, device=dev, requires_grad=True)
-        a = torch.tensor(P.ionic[:, 1].copy(), device=dev, requires_grad=True)
-        v0 = v0b.clone().requires_grad_(True)
-        w0 = w0b.clone().requires_grad_(True)
-        sync()
-        t = time.perf_counter()
-        vT, _ = SDCRun.apply(sigma, a, v0, w0, s, nsteps, t0, ck)
-        sync()
-        tf = time.perf_counter() - t
-        loss = 0.5 * ((vT - target) ** 2).sum()
-        sync()
-        t = time.perf_counter()
-        loss.backward()
-        sync()
-        tb = time.perf_counter() - t
-        adj[f"forward_ms_ckpt{ck}"] = 1e3 * tf
-        adj[f"backward_ms_ckpt{ck}"] = 1e3 * tb
-        adj[f"ratio_ckpt{ck}"] = tb / tf
-    s.close()
-    return batched, adj
-
-
 def workload_linearized(P, v0, w0, t0, nsteps, speedup=True):
     """The 512^2 workload with the paper's basic scheme (reaction Jacobian in
     the implicit operator, Gauss-Seidel gating), the same steps from the same
@@ -749,9 +904,9 @@ def workload_emi(nsteps=3, warm=1, speedup=True, three_d=False):
     return out
 
 
-def cpu_baseline(P, v0, w0, t0, nsteps):
-    """The oracle on one core, a few steps from the timed region's start state
-    (native thread pools limited to one thread for the timed run)."""
+def cpu_baseline(P, v0, w0, t0, nsteps, window_steps):
+    """The oracle on one core over the first nsteps steps of the timed window,
+    from the same state (native thread pools limited to one thread)."""
     from threadpoolctl import threadpool_limits
 
     from oracle.sdc import build, run
@@ -762,7 +917,8 @@ def cpu_baseline(P, v0, w0, t0, nsteps):
         el = time.perf_counter() - t
     dof_sweeps = sum(info["n_active"] for step in log for info in step)
     return {"value": dof_sweeps / el, "unit": "active dof-sweeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} oracle steps of the same workload from t={t0:.1f} ms ({el:.1f} s)",
+            "sample": f"the first {nsteps} of the {window_steps} timed steps of the same workload, from the "
+                      f"same state at t={t0:.1f} ms ({el:.1f} s on one core)",
             "host_cpu": cpu_model(), "host_cpu_count": os.cpu_count()}
 
 

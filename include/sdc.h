@@ -372,6 +372,11 @@ typedef struct {
   int64_t cg_all_launches;
   double cg_all_ms;
   double cg_all_bytes;
+  /* sums over the timed launches of the rows and stored entries of A of the */
+  /* instances still iterating (for other byte models), all launches and   */
+  /* those on every row                                                     */
+  double cg_rows, cg_nnz;
+  double cg_all_rows, cg_all_nnz;
 } sdc_profile_stats;
 
 /* Setup outcome: storage in use (1 CSR, 2 diagonal), diagonals per row in the

@@ -53,7 +53,8 @@ class StepStats(ctypes.Structure):
 
 class ProfileStats(ctypes.Structure):
     _fields_ = [("cg_launches", c_int64), ("cg_ms", c_double), ("cg_bytes", c_double),
-                ("cg_all_launches", c_int64), ("cg_all_ms", c_double), ("cg_all_bytes", c_double)]
+                ("cg_all_launches", c_int64), ("cg_all_ms", c_double), ("cg_all_bytes", c_double),
+                ("cg_rows", c_double), ("cg_nnz", c_double), ("cg_all_rows", c_double), ("cg_all_nnz", c_double)]
 
 
 class Info(ctypes.Structure):

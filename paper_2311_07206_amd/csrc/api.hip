@@ -88,10 +88,12 @@ int account_timing_at(sdc_ctx* ctx, const MapBuf& mb, int base, int budget, cons
   const bool ident = mb.idx == nullptr;
   for (int b = 0; b < budget; ++b) {
     const int it = it0 + b;
-    double bytes = 0.0;
+    double bytes = 0.0, rows = 0.0, nnz = 0.0;
     for (int i = 0; i < ctx->n_inst; ++i) {
       if (it >= iters[i] || mb.cnt[i] == 0) continue;
       bytes += 8.0 * static_cast<double>(mb.nnz[i]) + (ident ? 88.0 : 92.0) * mb.cnt[i];
+      rows += mb.cnt[i];
+      nnz += static_cast<double>(mb.nnz[i]);
     }
     if (bytes == 0.0) continue;
     float t = 0.f;
@@ -99,10 +101,14 @@ int account_timing_at(sdc_ctx* ctx, const MapBuf& mb, int base, int budget, cons
     ctx->pst.cg_launches++;
     ctx->pst.cg_ms += t;
     ctx->pst.cg_bytes += bytes;
+    ctx->pst.cg_rows += rows;
+    ctx->pst.cg_nnz += nnz;
     if (ident) {
       ctx->pst.cg_all_launches++;
       ctx->pst.cg_all_ms += t;
       ctx->pst.cg_all_bytes += bytes;
+      ctx->pst.cg_all_rows += rows;
+      ctx->pst.cg_all_nnz += nnz;
     }
   }
   return SDC_OK;

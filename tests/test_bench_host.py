@@ -98,12 +98,11 @@ def test_measured_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     sha = hashlib.sha256(b"kernel source").hexdigest()
     md = tmp_path / "c.md"
     md.write_text(f"# x\n\n- kernels.hip sha256: {sha}\n- measured bytes per launch: 90.5\n"
-                  f"- algorithmic bytes per launch: 100.0\n")
-    monkeypatch.setattr(bench, "COUNTERS", str(md))
+                  f"- measured bytes per listed launch: 40.0\n- measured bytes per all-rows launch: 120.0\n")
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
-    assert bench.measured_traffic() == (90.5, 100.0)
+    assert bench.measured_traffic(str(md)) == {"all": 90.5, "listed": 40.0, "all_rows": 120.0}
     src.write_bytes(b"kernel source, edited")
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic(str(md)) is None
 
 
 def test_committed_counters_name_the_current_kernel_source():
@@ -111,6 +110,26 @@ def test_committed_counters_name_the_current_kernel_source():
     committed; a kernel edit without new counters makes `traffic` null."""
     text = open(bench.COUNTERS).read()
     assert "kernels.hip sha256:" in text and "measured bytes per launch:" in text
+
+
+def test_cg_launch_classes_and_roofline_byte_models():
+    assert bench.cg_launch_class("void sdc::k_cg_iter2<7, false, true>(...)") == "all_rows"
+    assert bench.cg_launch_class("void sdc::k_cg_iter<7, false, 1, false>(...)") == "listed"
+    assert bench.cg_launch_class("void sdc::k_cg_iter<0, true, 0, false>(...)") == "all_rows"
+    assert bench.cg_launch_class("void sdc::k_post<4>(...)") is None
+    # two launches: one over all 1000 rows (7000 entries), one over a list of 200 rows (1400 entries), 1 ms each
+    prof = {"cg_launches": 2, "cg_ms": 2.0, "cg_rows": 1200.0, "cg_nnz": 8400.0, "cg_all_launches": 1,
+            "cg_all_ms": 1.0, "cg_all_rows": 1000.0, "cg_all_nnz": 7000.0}
+    r = bench.cg_roofline(prof, "dia", 7)
+    assert r["bytes_per_launch_scope_table"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2)
+    assert r["bytes_per_launch_storage_min"] == pytest.approx(((8 * 4 + 80) * 1200 + 4 * 200) / 2)
+    assert r["achieved"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2e-3 / 1e9)
+    assert r["listed"]["launches"] == 1 and r["all_rows"]["rows_per_launch"] == 1000.0
+    c = bench.cg_roofline(prof, "csr", 0)
+    assert c["bytes_per_launch_storage_min"] == pytest.approx((12 * 8400 + 84 * 1200 + 4 * 200) / 2)
+    t = bench.add_traffic(dict(r), {"all": 50.0, "listed": 20.0, "all_rows": 100.0}, prof)
+    assert t["traffic"] == pytest.approx(60.0) and t["listed"]["traffic"] == 20.0
+    assert t["frac_measured"] == pytest.approx(120.0 / 2e-3 / 1e9 / 8000.0)
 
 
 def test_front_shell_masks_are_nested_shells_around_the_level_crossing():
