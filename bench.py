@@ -188,6 +188,7 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--ckpt-every", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured runs of the same windows")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the 48 instances run one after another")
     ap.add_argument("--n", type=int, default=512, help="grid side of the 2D leg (workload uses 512)")
@@ -426,6 +427,9 @@ def headline(args):
             roof = cg_roofline(prof, info["format"], info["n_diagonals"])
             out["roofline"] = add_traffic(roof, measured_traffic(COUNTERS), prof)
     if not args.headline_only:
+        if not args.no_graph:
+            out["graph"] = graph_window(P, v_start.cpu().numpy(), w_start.cpu().numpy(), t_start, args.steps,
+                                        args.repeats, out["ms_per_step"])
         if not args.no_speedup:
             el0 = nonadaptive_run(P, v_start.cpu().numpy(), w_start.cpu().numpy(), t_start, args.steps)
             out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / args.steps,
@@ -452,6 +456,33 @@ def calibration_copies(dev, n=3):
         dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+
+def graph_window(P, v0, w0, t0, nsteps, repeats, ms_host):
+    """The same window with graph-captured sweeps (sdc_set_graph): one
+    untimed pass (captures, budgets), then `repeats` timed passes from the
+    same state, median reported beside the host-launched steps' time."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    sync = torch.cuda.synchronize
+    s = Solver.from_problem(P)
+    s.set_graph(True)
+    _timed_steps(s, torch.tensor(v0, device=dev), torch.tensor(w0, device=dev), t0, P.dt, nsteps, sync)
+    i0 = s.info()
+    times, dofs = [], None
+    for _ in range(max(1, repeats)):
+        el, logs = _timed_steps(s, torch.tensor(v0, device=dev), torch.tensor(w0, device=dev), t0, P.dt, nsteps, sync)
+        times.append(el)
+        dofs = sum(st["n_active"] for lg in logs for st in lg)
+    i1 = s.info()
+    s.close()
+    el = float(np.median(times))
+    return {"ms_per_step": 1e3 * el / nsteps, "value": dofs / el, "unit": "active dof-sweeps/s",
+            "host_launched_ms_per_step": ms_host, "speedup_vs_host_launched": ms_host / (1e3 * el / nsteps),
+            "graph_steps": i1["graph_steps"] - i0["graph_steps"], "redone": i1["graph_redone"] - i0["graph_redone"],
+            "captures": i1["graph_captures"] - i0["graph_captures"], "repeats": len(times)}
 
 
 def sequential_instances(P, v0, w0, t0, nsteps):
@@ -560,6 +591,8 @@ def workload_2d(args):
             info = out["storage"]
             out["roofline"] = cg_roofline(prof, info["format"], info["n_diagonals"])
     s.close()
+    if not args.no_graph:
+        out["graph"] = graph_window(P, v_start, w_start, t_start, nsteps, 3, out["ms_per_step"])
     v_non = None
     if not args.no_speedup:
         el0, v_non = nonadaptive_run(P, v_start, w_start, t_start, nsteps, return_state=True)

@@ -395,9 +395,37 @@ typedef struct {
   int32_t rows_per_thread;
   double t_rows1_us;
   double t_rows2_us;
+  /* graph-captured sweeps (sdc_set_graph): steps taken that way, captures */
+  /* made, and steps redone by the synchronous loop after a short budget  */
+  int64_t graph_steps;
+  int64_t graph_captures;
+  int64_t graph_redone;
 } sdc_info;
 
 int sdc_get_info(sdc_ctx* ctx, sdc_info* out);
+
+/* Graph-captured sweeps for sdc_step (enable != 0; 0 returns to launches
+ * from the host).  Each sweep k of a step becomes one HIP graph with a fixed
+ * launch sequence: the sweep start, then per node the right-hand side, the
+ * CG start, a fixed number of CG iteration launches (the last step's count
+ * for that sweep and node plus one, and an eighth more, at least two;
+ * launches after a solve has converged return at once) and the post-solve
+ * update, then the selection of the next set.  The sets stay on the device:
+ * the kernels of sweeps k >= 1 read the selected set's size there, on grids
+ * of the all-rows capacity, blocks past the set returning at once.  A step
+ * is K graph launches and one synchronisation, after which the CG outcomes
+ * are checked; a solve that did not finish within its launches makes the
+ * step be redone by the synchronous loop (the same results), and the graphs
+ * are captured again when the predicted counts outgrow them.  Results equal
+ * those of host-launched steps bitwise when the latter do not use the
+ * one-workgroup solves (small_set_rows = -1, or sets above their size),
+ * which graph steps never use.  The default options of the monodomain
+ * model only (scheme 0, fixed K and theta, first sweeps on all rows,
+ * residual CG stop): else SDC_ERR_ARG.  Steps with pinned sets or kernel
+ * timing on run from the host.  Work memory: 2 K M n_inst int32 on the
+ * device and in pinned host memory; the graphs are captured on a stream of
+ * the library's own and launched on the context's stream. */
+int sdc_set_graph(sdc_ctx* ctx, int32_t enable);
 
 /* enable != 0 starts timing (and clears the totals); 0 stops it. */
 int sdc_profile(sdc_ctx* ctx, int32_t enable);

@@ -60,7 +60,8 @@ class ProfileStats(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("format", c_int32), ("n_diagonals", c_int32), ("t_csr_us", c_double),
                 ("t_dia_us", c_double), ("redone_steps", c_int64), ("rows_per_thread", c_int32),
-                ("t_rows1_us", c_double), ("t_rows2_us", c_double)]
+                ("t_rows1_us", c_double), ("t_rows2_us", c_double), ("graph_steps", c_int64),
+                ("graph_captures", c_int64), ("graph_redone", c_int64)]
 
 
 class Emi(ctypes.Structure):
@@ -96,6 +97,7 @@ SIGNATURES = {
     "sdc_select": (c_int32, [c_void_p, PTR, PTR, c_int64, c_double, PTR, P_I64]),
     "sdc_collocation": (c_int32, [c_int32, PTR, PTR, PTR, PTR]),
     "sdc_profile": (c_int32, [c_void_p, c_int32]),
+    "sdc_set_graph": (c_int32, [c_void_p, c_int32]),
     "sdc_get_info": (c_int32, [c_void_p, POINTER(Info)]),
     "sdc_get_drop_tolerance": (c_int32, [c_void_p, PTR]),
     "sdc_adjoint_step": (c_int32, [c_void_p, PTR, PTR, c_double, PTR, PTR, PTR, PTR]),

@@ -56,6 +56,26 @@ int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap) {
   mb->cnt.assign(ni, 0);
   mb->nnz.assign(ni, 0);
   mb->n_inst = ni;
+  mb->cap = nblk_cap;
+  return SDC_OK;
+}
+
+// The host mirror of a map from its sizes block (map_sizes_words int64 words
+// as the map's builder wrote them).
+int parse_map_sizes(sdc_ctx* ctx, MapBuf* mb, const int64_t* words) {
+  const int ni = ctx->n_inst;
+  const int32_t* tot = reinterpret_cast<const int32_t*>(words + ni + 1);
+  mb->nblk = tot[0];
+  mb->rows = tot[1];
+  if (tot[2] != 0)
+    return fail(ctx, SDC_ERR_ARG, tot[2] == 1 ? "index list not strictly ascending or out of range"
+                                             : "work map larger than its capacity");
+  mb->max_nb = 0;
+  for (int i = 0; i < ni; ++i) {
+    mb->cnt[i] = tot[4 + i];
+    mb->nnz[i] = words[i];
+    mb->max_nb = std::max(mb->max_nb, (mb->cnt[i] + kBlock - 1) / kBlock);
+  }
   return SDC_OK;
 }
 
@@ -65,17 +85,7 @@ int fetch_map(sdc_ctx* ctx, MapBuf* mb) {
   HIPC(hipMemcpyAsync(ctx->h_i64, mb->inst_nnz, map_sizes_words(ni) * sizeof(int64_t), hipMemcpyDeviceToHost,
                       ctx->stream));
   HIPC(hipStreamSynchronize(ctx->stream));
-  const int32_t* tot = reinterpret_cast<const int32_t*>(ctx->h_i64 + ni + 1);
-  mb->nblk = tot[0];
-  mb->rows = tot[1];
-  if (tot[2] != 0) return fail(ctx, SDC_ERR_ARG, "index list not strictly ascending or out of range");
-  mb->max_nb = 0;
-  for (int i = 0; i < ni; ++i) {
-    mb->cnt[i] = tot[4 + i];
-    mb->nnz[i] = ctx->h_i64[i];
-    mb->max_nb = std::max(mb->max_nb, (mb->cnt[i] + kBlock - 1) / kBlock);
-  }
-  return SDC_OK;
+  return parse_map_sizes(ctx, mb, ctx->h_i64);
 }
 
 // Add the event timings of iterations [it0, it0 + budget) to the profile;
@@ -287,6 +297,10 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
   const int64_t N = ctx->N;
   const MapBuf& mb = ctx->curmap();
   const Map map = mb.dev();
+  if (ctx->k < SDC_MAX_SWEEPS) {
+    if (static_cast<int>(ctx->seen_nblk.size()) <= ctx->k) ctx->seen_nblk.resize(ctx->k + 1, ctx->all.nblk);
+    ctx->seen_nblk[ctx->k] = mb.nblk;
+  }
   // the statistics of this sweep refer to its own set, which the selection replaces
   std::vector<int32_t> cnt = mb.cnt;
   std::vector<int64_t> nnz = mb.nnz;
@@ -456,6 +470,222 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
     st->ms = ms;
   }
   ctx->k = next;
+  return SDC_OK;
+}
+
+// ---------------------------------------------------------------- graph-captured sweeps
+
+// Prediction slot of node m in sweep k (steps whose first sweep takes all rows).
+int pred_slot_of(const sdc_ctx* ctx, int k, int m) { return std::min(k, SDC_MAX_SWEEPS - 1) * ctx->prm.M + m; }
+
+// CG launches captured for node m of sweep k: the predicted count (the last
+// step's, plus one) and an eighth more, at least two (launches after
+// convergence return at once).
+int graph_budget(const sdc_ctx* ctx, int k, int m) {
+  const int need = std::max(1, ctx->pred[pred_slot_of(ctx, k, m)]) + 1;
+  return std::min(need + std::max(2, need / 8), ctx->prm.cg_maxit + 1);
+}
+
+bool graph_adaptive(const sdc_ctx* ctx) { return ctx->prm.theta > 0.0; }
+
+// Grid of sweep k >= 1 in a graph: the map entries that sweep had in the
+// last step, a quarter more and 16, at most the all-rows map's.  A set that
+// outgrows it makes the step be redone (its selection covers only the grid's
+// entries, so the maps built from it stay within their capacity).
+int graph_cap(const sdc_ctx* ctx, int k) {
+  const int seen = k < static_cast<int>(ctx->seen_nblk.size()) ? ctx->seen_nblk[k] : ctx->all.nblk;
+  return std::min(ctx->all.nblk, seen + seen / 4 + 16);
+}
+
+// The map sweep k of a graph step runs on: all rows in the first sweep (and
+// in every sweep without a drop tolerance), else the set the previous sweep
+// selected into slot (k - 1) & 1, read through its live entry count with a
+// grid of the all-rows capacity.
+Map graph_map(const sdc_ctx* ctx, int k) {
+  if (k == 0 || !graph_adaptive(ctx)) return ctx->all.dev();
+  const int slot = (k - 1) & 1;
+  const MapBuf& mb = ctx->dyn[slot];
+  return Map{mb.rec, mb.inst_blk0, mb.inst_nblk, ctx->list[slot], ctx->gcap[k], ctx->n_inst, mb.totals};
+}
+
+// Enqueue sweep k of a graph step on s: the launch sequence of do_sweep with
+// fixed CG budgets, each solve's outcome written to the device history of
+// (k, m), and copies of that history (after the last sweep) and of the
+// sweep's map sizes to pinned host memory.  Always one launch per CG
+// iteration (the one-workgroup solves of small sets need the set sizes on
+// the host).
+int enqueue_graph_sweep(sdc_ctx* ctx, int k, hipStream_t s) {
+  const int M = ctx->prm.M, K = ctx->prm.K, ni = ctx->n_inst;
+  const int64_t N = ctx->N;
+  const Map map = graph_map(ctx, k);
+  const EmiArgs emi = ctx->emi_args();
+  const CgStop stop = ctx->cg_stop();
+  double* const tot = ctx->all.tot_if_large(ctx->cg_tot);
+  launch_sweep_start(s, M, map, N, ctx->A(), ctx->ml, ctx->v0, ctx->w0, ctx->v, ctx->w, ctx->I, ctx->R, ctx->Phi,
+                     ctx->Gam, ctx->amax, ctx->cargs, emi);
+  for (int m = 0; m < M; ++m) {
+    double* x = ctx->dv + m * N;
+    launch_rhs(s, M, m, map, N, ctx->A(), ctx->ml, ctx->Phi + m * N, ctx->dI, ctx->dv, ctx->r[0], x, ctx->cargs, emi);
+    const Mat H = ctx->H(m);
+    const double* dinv = ctx->dinv + static_cast<int64_t>(m) * N;
+    const size_t h = (static_cast<size_t>(k) * M + m) * ni;
+    const CgState cg{ctx->ghist + h, ctx->ghist + static_cast<size_t>(K) * M * ni + h, ctx->cg_blk_done};
+    launch_cg_start(s, map, ni, N, H, dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0], cg);
+    const int B = ctx->gbudget[k * M + m];
+    for (int it = 0; it < B; ++it) {
+      const int a = it & 1, o = a ^ 1;
+      launch_cg_iter(s, map, N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a], ctx->wv[a],
+                     ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o], stop, cg, tot,
+                     ctx->pair_all);
+    }
+    launch_post(s, M, m, map, N, ctx->ionic_d, x, ctx->v + m * N, ctx->w + m * N, ctx->I + m * N, ctx->R + m * N,
+                ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N, ctx->dR, ctx->amax, ctx->cargs, emi, false);
+  }
+  if (k + 1 < K && graph_adaptive(ctx)) {
+    const int slot = k & 1;
+    launch_select(s, map, ni, ctx->rowptr, ctx->amax, ctx->prm.theta, nullptr, ctx->sel_cnt, ctx->sel_nnz,
+                  ctx->list[slot], nullptr, ctx->next(ctx->dyn[slot]), ctx->zv(), nullptr);
+  }
+  const size_t W = map_sizes_words(ni);
+  if (k > 0 && graph_adaptive(ctx))
+    HIPC(hipMemcpyAsync(ctx->gh_sizes + k * W, ctx->dyn[(k - 1) & 1].inst_nnz, W * sizeof(int64_t),
+                        hipMemcpyDeviceToHost, s));
+  if (k + 1 == K)
+    HIPC(hipMemcpyAsync(ctx->gh_hist, ctx->ghist, 2 * static_cast<size_t>(K) * M * ni * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, s));
+  HIPC(hipGetLastError());
+  return SDC_OK;
+}
+
+void graph_release(sdc_ctx* ctx) {
+  for (auto& g : ctx->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  ctx->gexec.clear();
+  ctx->graph_ready = false;
+}
+
+// Capture every sweep of a step as one graph each, with the current budgets.
+int graph_capture(sdc_ctx* ctx) {
+  const int K = ctx->prm.K, M = ctx->prm.M;
+  graph_release(ctx);
+  ctx->gexec.assign(K, nullptr);
+  ctx->gbudget.assign(static_cast<size_t>(K) * M, 0);
+  ctx->gcap.assign(K, ctx->all.nblk);
+  for (int k = 0; k < K; ++k) {
+    for (int m = 0; m < M; ++m) ctx->gbudget[k * M + m] = graph_budget(ctx, k, m);
+    if (k > 0) ctx->gcap[k] = graph_cap(ctx, k);
+  }
+  for (int k = 0; k < K; ++k) {
+    HIPC(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_graph_sweep(ctx, k, ctx->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (rc != SDC_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      graph_release(ctx);
+      return rc != SDC_OK ? rc : fail(ctx, SDC_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    const hipError_t ei = hipGraphInstantiate(&ctx->gexec[k], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      graph_release(ctx);
+      return fail(ctx, SDC_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    }
+  }
+  ctx->graph_ready = true;
+  ++ctx->graph_captures;
+  return SDC_OK;
+}
+
+// The sweeps of a started step as K graph launches and one synchronisation.
+// Re-captures first when a predicted CG count or the last step's set sizes
+// no longer fit (or a grid is twice what the last step needed); sets
+// *short_budget (and changes nothing the caller keeps) when a solve did not
+// finish within its budget or a set outgrew its grid, so that the caller
+// redoes the step.
+int graph_step(sdc_ctx* ctx, sdc_step_stats* st, bool* short_budget) {
+  const int K = ctx->prm.K, M = ctx->prm.M, ni = ctx->n_inst;
+  bool fits = ctx->graph_ready;
+  for (int k = 0; fits && k < K; ++k) {
+    for (int m = 0; m < M; ++m)
+      if (std::max(1, ctx->pred[pred_slot_of(ctx, k, m)]) + 1 > ctx->gbudget[k * M + m]) fits = false;
+    if (k > 0 && graph_adaptive(ctx)) {
+      const int seen = k < static_cast<int>(ctx->seen_nblk.size()) ? ctx->seen_nblk[k] : ctx->all.nblk;
+      if (seen > ctx->gcap[k] || ctx->gcap[k] > 2 * graph_cap(ctx, k)) fits = false;
+    }
+  }
+  if (!fits) TRY(graph_capture(ctx));
+  HIPC(hipEventRecord(ctx->gev[0], ctx->stream));
+  for (int k = 0; k < K; ++k) {
+    HIPC(hipGraphLaunch(ctx->gexec[k], ctx->stream));
+    HIPC(hipEventRecord(ctx->gev[k + 1], ctx->stream));
+  }
+  HIPC(hipStreamSynchronize(ctx->stream));
+  ++ctx->graph_steps;
+  // a set that outgrew its sweep's grid: that sweep and the ones after it
+  // worked on part of their sets, so their outcome means nothing; redo
+  const size_t W = map_sizes_words(ni);
+  ctx->seen_nblk.resize(K, ctx->all.nblk);
+  for (int k = 1; k < K && graph_adaptive(ctx); ++k) {
+    const int32_t* tot = reinterpret_cast<const int32_t*>(ctx->gh_sizes + k * W + ni + 1);
+    ctx->seen_nblk[k] = tot[0];
+    if (tot[0] > ctx->gcap[k] || tot[2] != 0) *short_budget = true;
+  }
+  if (*short_budget) return SDC_OK;
+  const int32_t* done = ctx->gh_hist;
+  const int32_t* iters = ctx->gh_hist + static_cast<size_t>(K) * M * ni;
+  for (int k = 0; k < K; ++k)
+    for (int m = 0; m < M; ++m)
+      for (int i = 0; i < ni; ++i) {
+        const int d = done[(k * M + m) * ni + i];
+        if (d == 2)
+          return fail(ctx, SDC_ERR_CG_MAXIT, "CG: instance %d, node %d, sweep %d: no convergence in %d iterations",
+                      i, m, k, ctx->prm.cg_maxit);
+        if (d == 3)
+          return fail(ctx, SDC_ERR_NONFINITE, "CG: instance %d, node %d, sweep %d: non-finite or non-positive "
+                      "curvature", i, m, k);
+        if (d == 0) *short_budget = true;
+      }
+  if (*short_budget) return SDC_OK;
+  // the outcome: predictions, the last sweep's counts, the host mirror of the maps
+  if (st) std::memset(st, 0, sizeof *st);
+  for (int k = 0; k < K; ++k) {
+    const MapBuf* mb = &ctx->all;
+    if (k > 0 && graph_adaptive(ctx)) {
+      const int slot = (k - 1) & 1;
+      mb = &ctx->dyn[slot];
+      TRY(parse_map_sizes(ctx, &ctx->dyn[slot], ctx->gh_sizes + k * W));
+      ctx->dyn[slot].idx = ctx->list[slot];
+    }
+    for (int m = 0; m < M; ++m) {
+      int mx = 0;
+      for (int i = 0; i < ni; ++i) mx = std::max(mx, iters[(k * M + m) * ni + i]);
+      ctx->pred[pred_slot_of(ctx, k, m)] = mx + 1;
+    }
+    if (st) {
+      sdc_sweep_stats& q = st->sweep[k];
+      q.n_active = mb->rows;
+      for (int i = 0; i < ni; ++i) q.nnz_active += mb->nnz[i];
+      for (int m = 0; m < M; ++m)
+        for (int i = 0; i < ni; ++i) {
+          const int it = iters[(k * M + m) * ni + i];
+          q.cg_iters_max[m] = std::max(q.cg_iters_max[m], it);
+          q.cg_row_iters[m] += static_cast<int64_t>(it) * mb->cnt[i];
+          q.cg_nnz_iters[m] += static_cast<int64_t>(it) * mb->nnz[i];
+        }
+      float ms = 0.f;
+      HIPC(hipEventElapsedTime(&ms, ctx->gev[k], ctx->gev[k + 1]));
+      q.ms = ms;
+      if (k > 0) st->sweep[k - 1].n_next = q.n_active;
+    }
+  }
+  if (st) {
+    st->n_sweeps = K;
+    st->sweep[K - 1].n_next = st->sweep[K - 1].n_active;
+  }
+  ctx->last_iters.assign(iters + static_cast<size_t>(K - 1) * M * ni, iters + static_cast<size_t>(K) * M * ni);
+  ctx->cur = K >= 2 && graph_adaptive(ctx) ? (K - 2) & 1 : -1;
+  ctx->k = K;
   return SDC_OK;
 }
 
@@ -790,6 +1020,11 @@ void sdc_destroy(sdc_ctx* ctx) {
   for (auto* p : ctx->pin) if (p) (void)hipFree(p);
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
   for (auto e : ctx->sweep_ev) if (e) (void)hipEventDestroy(e);
+  graph_release(ctx);
+  for (auto e : ctx->gev) if (e) (void)hipEventDestroy(e);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->gh_hist) (void)hipHostFree(ctx->gh_hist);
+  if (ctx->gh_sizes) (void)hipHostFree(ctx->gh_sizes);
   if (ctx->h_i32) (void)hipHostFree(ctx->h_i32);
   if (ctx->h_i64) (void)hipHostFree(ctx->h_i64);
   if (ctx->h_term) (void)hipHostFree(ctx->h_term);
@@ -1103,10 +1338,24 @@ int sdc_end_step(sdc_ctx* ctx, double* v, double* w) {
 
 int sdc_step(sdc_ctx* ctx, double* v, double* w, double t, sdc_step_stats* stats) {
   TRY(sdc_begin_step(ctx, v, w, t));
+  int first = 0;
+  if (ctx->graph_usable()) {
+    // graph-captured sweeps: one synchronisation per step; a short budget
+    // redoes the step with the synchronous CG loop below
+    bool short_budget = false;
+    const int rc = graph_step(ctx, stats, &short_budget);
+    if (rc != SDC_OK) {
+      ctx->in_step = false;
+      return rc;
+    }
+    if (!short_budget) return sdc_end_step(ctx, v, w);
+    ++ctx->graph_redone;
+    first = 1;
+  }
   // fast path: predicted CG budgets, one synchronisation per sweep; if a
   // budget was short, redo the step from its saved start state with the
   // synchronous CG loop (identical results, exact iteration counts)
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  for (int attempt = first; attempt < 2; ++attempt) {
     const bool async = attempt == 0;
     if (!async) {
       ++ctx->redone_steps;
@@ -1265,6 +1514,35 @@ int sdc_get_info(sdc_ctx* ctx, sdc_info* out) {
   out->rows_per_thread = ctx->use_dia && ctx->pair_all && compiled_diagonals(ctx->nd) ? 2 : 1;
   out->t_rows1_us = ctx->t_rows_us[0];
   out->t_rows2_us = ctx->t_rows_us[1];
+  out->graph_steps = ctx->graph_steps;
+  out->graph_captures = ctx->graph_captures;
+  out->graph_redone = ctx->graph_redone;
+  return SDC_OK;
+}
+
+int sdc_set_graph(sdc_ctx* ctx, int32_t enable) {
+  TRY(check_ready(ctx));
+  if (!enable) {
+    ctx->graph_mode = false;
+    graph_release(ctx);
+    return SDC_OK;
+  }
+  if (ctx->emi || ctx->linearized() || ctx->terminate() || ctx->apriori_drop() || ctx->first_subset() ||
+      ctx->prm.cg_energy_tol > 0.0)
+    return fail(ctx, SDC_ERR_ARG, "graph-captured sweeps support the default options of the monodomain model "
+                "(scheme 0, fixed sweep count and drop tolerance, every first sweep on all rows, residual CG stop)");
+  const int K = ctx->prm.K, M = ctx->prm.M, ni = ctx->n_inst;
+  if (!ctx->cap_stream) HIPC(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  if (!ctx->ghist) {
+    TRY(dalloc(ctx, &ctx->ghist, 2 * static_cast<size_t>(K) * M * ni));
+    HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->gh_hist), 2 * static_cast<size_t>(K) * M * ni * sizeof(int32_t)));
+    HIPC(hipHostMalloc(reinterpret_cast<void**>(&ctx->gh_sizes), K * map_sizes_words(ni) * sizeof(int64_t)));
+    ctx->gev.assign(K + 1, nullptr);
+    for (auto& e : ctx->gev) HIPC(hipEventCreate(&e));
+    HIPC(hipStreamSynchronize(ctx->stream));
+  }
+  ctx->graph_mode = true;
+  ctx->graph_ready = false;
   return SDC_OK;
 }
 

@@ -29,6 +29,7 @@ struct MapBuf {
   // host mirror, valid after the map is built
   int32_t nblk = 0;
   int32_t n_inst = 0;
+  int32_t cap = 0;                    // entries the record array holds
   int32_t max_nb = 0;                 // most blocks of one instance
   int64_t rows = 0;
   std::vector<int32_t> cnt;
@@ -43,7 +44,7 @@ struct MapBuf {
     return max_nb > kTotBlocks || (nblk > kTotMapBlocks && max_nb > kTotMinBlocks) ? tot : nullptr;
   }
   NextMap next(const int64_t* node_off, const int32_t* dia_off, int nd) const {
-    return NextMap{rec, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals, node_off, dia_off, nd};
+    return NextMap{rec, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals, node_off, dia_off, nd, cap};
   }
 };
 
@@ -213,6 +214,30 @@ struct sdc_ctx {
     const bool e = prm.cg_energy_tol > 0.0;
     return CgStop{prm.cg_rtol * prm.cg_rtol, e ? prm.cg_energy_tol * prm.cg_energy_tol : 0.0, prm.cg_maxit,
                   e ? prm.cg_delay : 0};
+  }
+
+  // graph-captured sweeps (sdc_set_graph): sweep k of a step is one graph
+  // with a fixed launch sequence: its CG solves take gbudget[k][m] launches
+  // (launches after convergence return at once), the maps of sweeps k >= 1
+  // are read through their live entry counts with grids of the all-rows
+  // capacity, and the outcome goes to device history that the host reads
+  // once per step
+  bool graph_mode = false;
+  bool graph_ready = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipGraphExec_t> gexec;   // [K]
+  std::vector<int> gbudget;            // [K][M]
+  std::vector<int> gcap;               // [K] grid of sweep k (k >= 1): map entries the graph covers
+  std::vector<int> seen_nblk;          // [K] map entries of sweep k in the last step (eager or graph)
+  int32_t* ghist = nullptr;            // device [K][M][n_inst] done, then [K][M][n_inst] iters
+  int32_t* gh_hist = nullptr;          // pinned copy of ghist
+  int64_t* gh_sizes = nullptr;         // pinned [K][map_sizes_words]: the sizes of each sweep's map
+  std::vector<hipEvent_t> gev;         // K + 1 events around the sweeps of a graph step
+  int64_t graph_steps = 0, graph_captures = 0, graph_redone = 0;
+  bool graph_usable() const {
+    bool pinned = false;
+    for (auto* q : pin) pinned = pinned || q;
+    return graph_mode && !pinned && !prof;
   }
 
   // kernel timing (bench only)

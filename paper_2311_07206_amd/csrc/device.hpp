@@ -27,6 +27,9 @@ __device__ inline int logical_block(int nblk) {
 // one vector load (lane q holds word q) and takes the fields from the lanes:
 // vector loads complete in order, so the entry and the list entry of the row
 // (at a position known from the block index alone) arrive in one round trip.
+// With a live count in device memory (graph-captured sweeps) the block index
+// is the entry (no XCD remapping: the count is not known before the loads),
+// the count arrives in the same round trip, and `dead` marks blocks past it.
 struct Row {
   int word;   // word (lane mod kRecWords) of the block record
   int inst, beg, end, bi, nb, lo, hi;
@@ -34,20 +37,25 @@ struct Row {
   int row;
   int blk;    // logical block: position of the entry in the map
   bool valid;
+  bool dead;  // a block past the live entries: returns without writing
   // diagonal offset d of the instance (uniform d)
   __device__ int off(int d) const { return __builtin_amdgcn_readlane(word, offsetof(BlkRec, off) / 4 + d); }
 };
 
+// The number of entries of a map (a device load when it is live).
+__device__ inline int map_entries(const Map& map) { return map.live ? *map.live : map.nblk; }
+
 // LIST: 1 the map has a list, 0 all rows, -1 decided at run time.
 template <int LIST = -1>
 __device__ inline Row map_row(const Map& map) {
-  const int L = logical_block(map.nblk);
+  const int L = map.live ? static_cast<int>(blockIdx.x) : logical_block(map.nblk);
   const int t = static_cast<int>(threadIdx.x);
   const int32_t* words = reinterpret_cast<const int32_t*>(map.rec + L);
   Row r;
   r.word = words[min(t & 63, kRecWords - 1)];
   r.listed = 0;
   if (LIST == 1 || (LIST < 0 && map.idx)) r.listed = map.idx[L * kBlock + t];
+  const int n_live = map.live ? *map.live : map.nblk;
   r.inst = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, inst) / 4);
   r.beg = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, beg) / 4);
   r.end = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, end) / 4);
@@ -56,7 +64,8 @@ __device__ inline Row map_row(const Map& map) {
   r.lo = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, lo) / 4);
   r.hi = __builtin_amdgcn_readlane(r.word, offsetof(BlkRec, hi) / 4);
   r.blk = L;
-  r.valid = t < r.end - r.beg;
+  r.dead = L >= n_live;
+  r.valid = !r.dead && t < r.end - r.beg;
   const bool listed_map = LIST == 1 || (LIST < 0 && map.idx);
   r.row = r.valid ? (listed_map ? r.listed : r.beg + t) : 0;
   return r;

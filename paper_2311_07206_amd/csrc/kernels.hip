@@ -339,6 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Map map, int n_inst, int64_
   }
   if (static_cast<int>(blockIdx.x) >= map.nblk) return;
   const Row rw = map_row(map);
+  if (rw.dead) return;
   if (threadIdx.x == 0) cg.blk_done[rw.blk] = 0;
   double s[3] = {0.0, 0.0, 0.0};
   if (rw.valid) {
@@ -442,7 +443,8 @@ __device__ inline void energy_record(const double* sc, double* so, bool first, i
 
 template <int S, bool FIRST, int LIST, bool TOT>
 __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_done, const BlkRec* __restrict__ rec,
-                                                    const int32_t* __restrict__ idx, int nblk, int it,
+                                                    const int32_t* __restrict__ idx, int nblk,
+                                                    const int32_t* __restrict__ live, int it,
                                                     const double* __restrict__ part_in,
                                                     const double* __restrict__ scal_in, int64_t N, Mat H,
                                                     const double* __restrict__ dinv,
@@ -458,14 +460,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
                                                     int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   __shared__ double sh_in[16], sh_out[16];
   // first round trip: the block's map entry and stop flag, the list entry of the thread's row
-  const Map map{rec, nullptr, nullptr, idx, nblk, 0};
+  const Map map{rec, nullptr, nullptr, idx, nblk, 0, live};
   const Row rw = map_row<LIST>(map);
   const int L = rw.blk;
-  // Early exit of a stopped block.  The test includes invariants of the
-  // arguments (it >= 0, nd >= 0, output buffers given) and of the list
-  // (entries >= 0), so that every cache line of the kernel arguments and the
-  // list entry are read before the branch rather than after it.
-  if (blk_done[L] | (it < 0) | (H.nd < 0) | (rw.listed < 0) | (s_out == nullptr) | (iters == nullptr)) return;
+  // Early exit of a stopped block (or one past a live map's entries).  The
+  // test includes invariants of the arguments (it >= 0, nd >= 0, output
+  // buffers given) and of the list (entries >= 0), so that every cache line
+  // of the kernel arguments and the list entry are read before the branch
+  // rather than after it.
+  if (rw.dead | blk_done[L] | (it < 0) | (H.nd < 0) | (rw.listed < 0) | (s_out == nullptr) | (iters == nullptr))
+    return;
   const int inst = rw.inst, nb = rw.nb, b0 = L - rw.bi;
   const bool valid = rw.valid;
   const int i = rw.row;
@@ -600,7 +604,8 @@ __device__ inline void pair_block_total(double (&v)[NV], double* sh /* [4 * NV] 
 template <int S, bool FIRST, bool TOT>
 __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__ blk_done,
                                                            const BlkRec* __restrict__ rec,
-                                                           const int32_t* __restrict__ idx, int nblk, int it,
+                                                           const int32_t* __restrict__ idx, int nblk,
+                                                           const int32_t* __restrict__ live, int it,
                                                            const double* __restrict__ part_in,
                                                            const double* __restrict__ scal_in, int64_t N, Mat H,
                                                            const double* __restrict__ dinv,
@@ -968,6 +973,7 @@ __global__ __launch_bounds__(kBlock) void k_select_count(Map map, const int32_t*
                                                          const int32_t* __restrict__ stop) {
   __shared__ int sc[4], sn[4];
   const Row rw = map_row(map);
+  if (rw.dead) return;
   const double th = inst_theta ? inst_theta[rw.inst] : theta;
   const bool keep = rw.valid && !(stop && stop[rw.inst]) && keep_row(amax[rw.row], th);
   const unsigned long long mask = __ballot(keep);
@@ -1025,18 +1031,24 @@ __device__ int64_t scan_inplace(T* a, int n, int64_t* sh) {
 }
 
 // Fill a work map from per-instance counts and list offsets (one block).
-__device__ void build_map(const int32_t* cnt, const int32_t* aoff, int n_inst, const NextMap& nm,
+// Returns false, with an empty map, when the counts need more entries than
+// the record array holds (inconsistent counts: nothing is written past it).
+__device__ bool build_map(const int32_t* cnt, const int32_t* aoff, int n_inst, const NextMap& nm,
                           int32_t total_rows) {
+  __shared__ int fits;
   if (threadIdx.x == 0) {
-    int32_t b = 0;
+    int64_t b = 0;
+    for (int i = 0; i < n_inst; ++i) b += (static_cast<int64_t>(cnt[i]) + kBlock - 1) / kBlock;
+    fits = b <= nm.cap;
+    b = 0;
     for (int i = 0; i < n_inst; ++i) {
-      const int32_t nb = (cnt[i] + kBlock - 1) / kBlock;
-      nm.inst_blk0[i] = b;
+      const int32_t nb = fits ? (cnt[i] + kBlock - 1) / kBlock : 0;
+      nm.inst_blk0[i] = static_cast<int32_t>(b);
       nm.inst_nblk[i] = nb;
       b += nb;
     }
-    nm.totals[0] = b;
-    nm.totals[1] = total_rows;
+    nm.totals[0] = static_cast<int32_t>(b);
+    nm.totals[1] = fits ? total_rows : 0;
   }
   __syncthreads();
   const int32_t nblk = nm.totals[0];
@@ -1058,6 +1070,7 @@ __device__ void build_map(const int32_t* cnt, const int32_t* aoff, int n_inst, c
     r.pad = 0;
     for (int d = 0; d < nm.nd; ++d) r.off[d] = nm.dia_off[lo * nm.nd + d];
   }
+  return fits;
 }
 
 // Pass 2 (one block): block offsets, per-instance totals, next work map.
@@ -1065,7 +1078,9 @@ __global__ __launch_bounds__(kScanThreads) void k_select_scan(Map map, int n_ins
                                                               int32_t* sel_nnz, NextMap nm) {
   __shared__ int64_t sh[kScanThreads];
   int32_t* aoff_scratch = nm.aoff;
-  const int nb = map.nblk;
+  // the entries the count pass covered: all of them, or those of the grid
+  // when a live map outgrew it (entries past it hold an earlier scan's values)
+  const int nb = min(map_entries(map), map.nblk);
   const int64_t total = scan_inplace<int32_t>(sel_cnt, nb, sh);
   const int64_t total_nnz = scan_inplace<int32_t>(sel_nnz, nb, sh);
   // an instance's blocks are consecutive: its totals are differences of the prefixes
@@ -1079,8 +1094,8 @@ __global__ __launch_bounds__(kScanThreads) void k_select_scan(Map map, int n_ins
   }
   if (threadIdx.x == 0) aoff_scratch[n_inst] = static_cast<int32_t>(total);
   __syncthreads();
-  build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, static_cast<int32_t>(total));
-  if (threadIdx.x == 0) nm.totals[2] = 0;
+  const bool fits = build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, static_cast<int32_t>(total));
+  if (threadIdx.x == 0) nm.totals[2] = fits ? 0 : 2;
 }
 
 // Pass 3: stable write of the kept rows; zero the work vectors on dropped rows.
@@ -1094,6 +1109,7 @@ __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* 
                                                          const int32_t* __restrict__ stop) {
   __shared__ int wc[4];
   const Row rw = map_row(map);
+  if (rw.dead) return;
   const double th = inst_theta ? inst_theta[rw.inst] : theta;
   const bool keep = rw.valid && !(stop && stop[rw.inst]) && keep_row(amax[rw.row], th);
   const unsigned long long mask = __ballot(keep);
@@ -1105,8 +1121,11 @@ __global__ __launch_bounds__(kBlock) void k_select_write(Map map, const double* 
   const int rank = __popcll(mask & ((1ull << lane) - 1ull));
   if (keep) {
     const int q = base + rank;
-    idx_pad[nm.inst_blk0[rw.inst] * kBlock + (q - nm.aoff[rw.inst])] = rw.row;
-    if (idx_compact) idx_compact[q] = rw.row;
+    const int64_t pos = static_cast<int64_t>(nm.inst_blk0[rw.inst]) * kBlock + (q - nm.aoff[rw.inst]);
+    if (pos < static_cast<int64_t>(nm.inst_blk0[rw.inst] + nm.inst_nblk[rw.inst]) * kBlock) {
+      idx_pad[pos] = rw.row;
+      if (idx_compact) idx_compact[q] = rw.row;
+    }
   }
   if (rw.valid && !keep && zv.dv) {
     const int i = rw.row;
@@ -1178,8 +1197,8 @@ __global__ __launch_bounds__(kScanThreads) void k_map_from_list(const int32_t* _
                      static_cast<unsigned long long>(z));
   }
   __syncthreads();
-  build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, n);
-  if (threadIdx.x == 0) nm.totals[2] = bad;
+  const bool fits = build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, n);
+  if (threadIdx.x == 0) nm.totals[2] = bad ? 1 : fits ? 0 : 2;
 }
 
 // Energy of node m's correction on the map's rows: partial sums of x_i (H x)_i.
@@ -1188,6 +1207,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Map map, int64_t N, Mat H, co
                                                    double* __restrict__ e_part) {
   __shared__ double sh[16];
   const Row rw = map_row(map);
+  if (rw.dead) return;
   double e[1] = {0.0};
   if (rw.valid) {
     const int i = rw.row;
@@ -1231,6 +1251,7 @@ __global__ __launch_bounds__(kBlock) void k_drop_part(Map map, int64_t N, const 
                                                       double* __restrict__ part) {
   __shared__ double sh[8];
   const Row rw = map_row(map);
+  if (rw.dead) return;
   double c = 0.0, d = INFINITY;
   if (rw.valid) {
     const int i = rw.row;
@@ -1600,10 +1621,12 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
     if (ev_start) {
       // events stamped by the dispatch itself: they time the kernel's execution
       hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(threads), 0, s, ev_start, ev_stop, 0, cg.blk_done, map.rec,
-                            map.idx, map.nblk, it, pin, scal_in, N, H, dinv, x, p, u_in, w_in, s_in, u_out,
+                            map.idx, map.nblk, map.live, it, pin, scal_in, N, H, dinv, x, p, u_in, w_in, s_in,
+                            u_out,
                             w_out, s_out, part_out, scal_out, stop, cg.done, cg.iters);
     } else {
-      kern<<<grid(map.nblk), threads, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, it, pin, scal_in, N, H, dinv,
+      kern<<<grid(map.nblk), threads, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, map.live, it, pin, scal_in, N,
+                                              H, dinv,
                                               x, p, u_in, w_in, s_in, u_out, w_out, s_out, part_out, scal_out, stop,
                                               cg.done, cg.iters);
     }

@@ -39,6 +39,10 @@ struct BlkRec {
 // Work map.  The list is stored padded by block: the rows of entry b are
 // idx[b * kBlock + t] for t < end - beg (the tail of each block is unused).
 // When idx is null the positions are row numbers (all rows active).
+// live (graph-captured sweeps): the number of map entries, in device memory,
+// written by the selection that built the map; the grid then has nblk >=
+// *live blocks (the capacity), block b takes entry b and blocks past *live
+// return at once.  Null: nblk is the number of entries (and the grid size).
 struct Map {
   const BlkRec* rec;
   const int32_t* inst_blk0;   // first entry of each instance
@@ -46,6 +50,7 @@ struct Map {
   const int32_t* idx;
   int32_t nblk;               // grid size
   int32_t n_inst;
+  const int32_t* live = nullptr;
 };
 
 // Cell-by-cell model: membrane node pairs.  part[i] is the other node of
@@ -198,6 +203,7 @@ struct NextMap {
   const int64_t* node_off;
   const int32_t* dia_off;
   int nd;
+  int32_t cap;             // entries rec (and cap * kBlock positions of the padded list) can hold
 };
 // Vectors that must be zero on inactive rows: the double-buffered CG vectors
 // gathered at neighbouring columns (r, w, s) and the M node corrections dv[M][N].
