@@ -177,6 +177,36 @@ def summarize_counters(fetch_csv, write_csv, min_blocks=0):
     return out
 
 
+def summarize_pmc(path):
+    """Mean of every counter of a rocprofv3 --pmc CSV per dispatch, for the
+    CG iteration by launch class (listed set, every row) and for the 256 MiB
+    calibration copies; only dispatches after the last calibration copy
+    count for the CG classes.  Copies are recognised by the largest
+    WRITE-side or request counts of the run (they are its biggest dispatches)."""
+    import collections
+    import csv
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: (int(r["Dispatch_Id"]), r["Counter_Name"]))
+    by = collections.defaultdict(dict)
+    names = {}
+    for r in rows:
+        d = int(r["Dispatch_Id"])
+        by[d][r["Counter_Name"]] = float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"]
+    ids = sorted(by)
+    copies = [d for d in ids if "copyBuffer" in names[d]]
+    big = [d for d in copies if sum(by[d].values()) >= 0.5 * max(sum(by[c].values()) for c in copies)] if copies else []
+    start = max(big) if big else -1
+    out = {}
+    groups = {"copy_256MiB": big}
+    for c in ("listed", "all_rows"):
+        groups[c] = [d for d in ids if d > start and cg_launch_class(names[d]) == c]
+    for g, ds in groups.items():
+        if ds:
+            keys = sorted(by[ds[0]])
+            out[g] = {"dispatches": len(ds), **{k: float(np.mean([by[d].get(k, 0.0) for d in ds])) for k in keys}}
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,7 +224,7 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="grid side of the 2D leg (workload uses 512)")
     ap.add_argument("--steps-2d", type=int, default=20)
     ap.add_argument("--warmup-2d", type=int, default=5)
-    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-2d", action="store_true", help="skip the 512^2 single-instance leg")
@@ -221,6 +251,8 @@ def parse():
                     help="with --summarize-counters: only CG launches with at least this many map entries")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="pair rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, print JSON and exit")
+    ap.add_argument("--summarize-pmc", metavar="COUNTER_CSV",
+                    help="per-dispatch means of every counter of a rocprofv3 --pmc run, by launch class")
     return ap.parse_args()
 
 
@@ -333,6 +365,9 @@ def main():
         return
     if args.summarize_counters:
         print(json.dumps(summarize_counters(*args.summarize_counters, min_blocks=args.min_blocks), indent=1))
+        return
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
