@@ -924,6 +924,25 @@ def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True, cg_energy=Tr
     if cg_energy:
         out["cg_energy_stop"] = cg_energy_variant(P, v0, w0, warm * P.dt, nsteps, out["ms_per_step"], v_std, v_non,
                                                   speedup=speedup)
+    out["storage_variants"] = storage_variants(P, v0, w0, warm * P.dt, nsteps)
+    return out
+
+
+def storage_variants(P, v0, w0, t0, nsteps, formats=(("csr", 1), ("sell", 3))):
+    """The same steps with the matrix storage forced (CSR, sliced ELL):
+    ms per step and the setup's SpMV-shaped timing of each."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    out = {}
+    for name, fmt in formats:
+        s = Solver.from_problem(P, fmt=fmt)
+        v, w = torch.tensor(v0, device=dev), torch.tensor(w0, device=dev)
+        s.step(v.clone(), w.clone(), t0)   # iteration history for the budgets
+        el, _ = _timed_steps(s, v, w, t0, P.dt, nsteps, torch.cuda.synchronize)
+        out[name] = {"ms_per_step": 1e3 * el / nsteps}
+        s.close()
     return out
 
 

@@ -70,7 +70,14 @@ typedef struct {
   int32_t cg_maxit;   /* CG iteration limit per solve (SDC_ERR_CG_MAXIT)       */
   int32_t format;     /* matrix storage: 0 = timed choice at setup, 1 = CSR,   */
                       /* 2 = diagonal (every instance's rows use <= 32        */
-                      /* distinct column offsets; else SDC_ERR_ARG)           */
+                      /* distinct column offsets; else SDC_ERR_ARG),          */
+                      /* 3 = sliced ELL (slices of 64 rows, one wavefront,    */
+                      /* entries column by column, padded to the slice's      */
+                      /* longest row; not with scheme 1).  The timed choice   */
+                      /* keeps the diagonal copy when it reads at most 0.6 of */
+                      /* CSR's matrix bytes, else times one SpMV-shaped CG    */
+                      /* start per storage built; every storage gives         */
+                      /* bitwise the same results.                            */
   /* Energy-norm termination (paper Sec. 3.2), off when tol_sdc <= 0: after  */
   /* at least K_min sweeps an instance stops once                            */
   /*   sum_m dv_m^T H_m dv_m <= ((1 - rho) / rho * tol_sdc)^2                 */
@@ -379,7 +386,7 @@ typedef struct {
   double cg_all_rows, cg_all_nnz;
 } sdc_profile_stats;
 
-/* Setup outcome: storage in use (1 CSR, 2 diagonal), diagonals per row in the
+/* Setup outcome: storage in use (1 CSR, 2 diagonal, 3 sliced ELL), diagonals per row in the
  * diagonal storage (0 if not available), the setup timings of one SpMV-shaped
  * CG start launch over all rows in each storage (0 if not timed), the
  * number of steps redone because a predicted CG budget was too small, the
@@ -400,6 +407,7 @@ typedef struct {
   int64_t graph_steps;
   int64_t graph_captures;
   int64_t graph_redone;
+  double t_sell_us;   /* setup timing of the sliced ELL storage (0 if not timed) */
 } sdc_info;
 
 int sdc_get_info(sdc_ctx* ctx, sdc_info* out);

@@ -753,6 +753,61 @@ int build_dia(sdc_ctx* ctx) {
   return SDC_OK;
 }
 
+// The sliced ELL values of A and every H_m from their CSR values.
+int fill_sell(sdc_ctx* ctx) {
+  if (!ctx->sell_ptr) return SDC_OK;
+  launch_build_sell(ctx->stream, ctx->N, ctx->nslice, ctx->rowptr, ctx->sell_ptr, ctx->Aval, ctx->sell_A);
+  for (int m = 0; m < ctx->prm.M; ++m)
+    launch_build_sell(ctx->stream, ctx->N, ctx->nslice, ctx->rowptr, ctx->sell_ptr, ctx->Hval + m * ctx->nnz,
+                      ctx->sell_H + m * ctx->sell_len);
+  HIPC(hipGetLastError());
+  return SDC_OK;
+}
+
+// Sliced ELL copy (format 3, and a candidate of the timed choice): slices of
+// kSlice consecutive rows, each padded to its longest row, entries column by
+// column; columns built on the host, values copied on the device from the
+// CSR values of A and every H_m (bitwise the same entries).
+int build_sell(sdc_ctx* ctx) {
+  const int64_t N = ctx->N;
+  const HostSystem& hs = ctx->host;
+  const int ns = static_cast<int>((N + kSlice - 1) / kSlice);
+  std::vector<int32_t> ptr(ns + 1, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int len = 0;
+    for (int64_t r = static_cast<int64_t>(sl) * kSlice; r < std::min<int64_t>(N, (sl + 1) * int64_t(kSlice)); ++r)
+      len = std::max(len, hs.rowptr[r + 1] - hs.rowptr[r]);
+    const int64_t next = static_cast<int64_t>(ptr[sl]) + static_cast<int64_t>(len) * kSlice;
+    if (next >= (int64_t(1) << 31)) return SDC_OK;   // too large for int32 offsets: no copy
+    ptr[sl + 1] = static_cast<int32_t>(next);
+  }
+  const int64_t len_all = ptr[ns];
+  std::vector<int32_t> col(static_cast<size_t>(len_all), 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    const int len = (ptr[sl + 1] - ptr[sl]) / kSlice;
+    for (int lane = 0; lane < kSlice; ++lane) {
+      const int64_t r = static_cast<int64_t>(sl) * kSlice + lane;
+      for (int d = 0; d < len; ++d) {
+        int32_t c = 0;
+        if (r < N) c = d < hs.rowptr[r + 1] - hs.rowptr[r] ? hs.col[hs.rowptr[r] + d] : static_cast<int32_t>(r);
+        col[static_cast<size_t>(ptr[sl]) + static_cast<size_t>(d) * kSlice + lane] = c;
+      }
+    }
+  }
+  const int M = ctx->prm.M;
+  TRY(dalloc(ctx, &ctx->sell_ptr, ns + 1));
+  TRY(dalloc(ctx, &ctx->sell_col, len_all));
+  TRY(dalloc(ctx, &ctx->sell_A, len_all));
+  TRY(dalloc(ctx, &ctx->sell_H, static_cast<size_t>(M) * len_all));
+  HIPC(hipMemcpyAsync(ctx->sell_ptr, ptr.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  HIPC(hipMemcpyAsync(ctx->sell_col, col.data(), len_all * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  ctx->nslice = ns;
+  ctx->sell_len = len_all;
+  TRY(fill_sell(ctx));
+  HIPC(hipStreamSynchronize(ctx->stream));   // the host staging vectors go out of scope
+  return SDC_OK;
+}
+
 // Storage choice (unless the caller forced one): the diagonal copy when it
 // reads at most 0.6 of CSR's matrix bytes (8 B per stored diagonal and row
 // against 12 B per entry with its column index: 2D triangles 0.38, 3D
@@ -763,21 +818,29 @@ int build_dia(sdc_ctx* ctx) {
 // the timings are taken and reported either way.
 int autotune(sdc_ctx* ctx) {
   ctx->use_dia = false;
-  if (ctx->nd == 0 || ctx->prm.format == 1) return SDC_OK;
+  ctx->use_sell = false;
+  if (ctx->prm.format == 1) return SDC_OK;
   if (ctx->prm.format == 2) {
     ctx->use_dia = true;
+    return SDC_OK;
+  }
+  if (ctx->prm.format == 3) {
+    ctx->use_sell = true;
     return SDC_OK;
   }
   hipEvent_t e0, e1;
   HIPC(hipEventCreate(&e0));
   HIPC(hipEventCreate(&e1));
   const Map map = ctx->all.dev();
-  // interleaved rounds, keep each storage's fastest round (robust to noise)
-  double t[2] = {1e30, 1e30};
+  // interleaved rounds, keep each storage's fastest round (robust to noise);
+  // candidates: CSR, the diagonal copy, the sliced ELL copy (those built)
+  double t[3] = {1e30, 1e30, 1e30};
+  const bool cand[3] = {true, ctx->nd > 0, ctx->sell_ptr != nullptr};
   const int reps = 10;
   for (int round = 0; round < 4; ++round)
-    for (int f = 0; f < 2; ++f) {
-      const Mat H = ctx->matH(0, f == 1);
+    for (int f = 0; f < 3; ++f) {
+      if (!cand[f]) continue;
+      const Mat H = ctx->matH(0, f + 1);
       launch_cg_start(ctx->stream, map, ctx->n_inst, ctx->N, H, ctx->dinv, ctx->r[0], ctx->r[1], ctx->wv[1],
                       ctx->part[0], ctx->cg());
       HIPC(hipEventRecord(e0, ctx->stream));
@@ -793,10 +856,15 @@ int autotune(sdc_ctx* ctx) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   ctx->t_csr_us = t[0];
-  ctx->t_dia_us = t[1];
-  const double dia_bytes = 8.0 * (ctx->nd / 2 + 1) * static_cast<double>(ctx->N);
-  const double csr_bytes = 12.0 * static_cast<double>(ctx->nnz);
-  ctx->use_dia = dia_bytes <= 0.6 * csr_bytes || t[1] < 1.05 * t[0];
+  ctx->t_dia_us = cand[1] ? t[1] : 0.0;
+  ctx->t_sell_us = cand[2] ? t[2] : 0.0;
+  if (cand[1]) {
+    const double dia_bytes = 8.0 * (ctx->nd / 2 + 1) * static_cast<double>(ctx->N);
+    const double csr_bytes = 12.0 * static_cast<double>(ctx->nnz);
+    ctx->use_dia = dia_bytes <= 0.6 * csr_bytes || t[1] < 1.05 * std::min(t[0], t[2]);
+  }
+  // the sliced ELL copy when it beats CSR by 3 % (and the diagonal copy is not kept)
+  ctx->use_sell = !ctx->use_dia && cand[2] && t[2] < 0.97 * t[0];
   return SDC_OK;
 }
 
@@ -1063,8 +1131,8 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     return fail(ctx, SDC_ERR_ARG, "null argument");
   if (prm->M < 1 || prm->M > SDC_MAX_NODES) return fail(ctx, SDC_ERR_ARG, "M must be in 1..%d", SDC_MAX_NODES);
   if (prm->K < 1 || prm->K > SDC_MAX_SWEEPS) return fail(ctx, SDC_ERR_ARG, "K must be in 1..%d", SDC_MAX_SWEEPS);
-  if (!(prm->dt > 0.0) || !(prm->cg_rtol > 0.0) || prm->cg_maxit < 1 || prm->format < 0 || prm->format > 2)
-    return fail(ctx, SDC_ERR_ARG, "dt, cg_rtol must be > 0, cg_maxit >= 1, format in 0..2");
+  if (!(prm->dt > 0.0) || !(prm->cg_rtol > 0.0) || prm->cg_maxit < 1 || prm->format < 0 || prm->format > 3)
+    return fail(ctx, SDC_ERR_ARG, "dt, cg_rtol must be > 0, cg_maxit >= 1, format in 0..3");
   if (prm->tol_sdc > 0.0 && !(prm->rho > 0.0 && prm->rho < 1.0))
     return fail(ctx, SDC_ERR_ARG, "energy-norm termination needs 0 < rho < 1");
   if (prm->drop_mode < 0 || prm->drop_mode > 1) return fail(ctx, SDC_ERR_ARG, "drop_mode must be 0 or 1");
@@ -1166,6 +1234,10 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
   TRY(build_dia(ctx));
   if (prm->format == 2 && ctx->nd == 0)
     return fail(ctx, SDC_ERR_ARG, "diagonal storage requested but a row pattern has more than %d offsets", kMaxDiag);
+  if (prm->format == 3 && prm->scheme == 1)
+    return fail(ctx, SDC_ERR_ARG, "the sliced ELL storage is not available with the linearized scheme");
+  if ((prm->format == 0 || prm->format == 3) && prm->scheme == 0) TRY(build_sell(ctx));
+  if (prm->format == 3 && !ctx->sell_ptr) return fail(ctx, SDC_ERR_ARG, "sliced ELL storage too large");
 
   const size_t MN = static_cast<size_t>(M) * N;
   TRY(dalloc(ctx, &ctx->v0, N));
@@ -1498,6 +1570,7 @@ int sdc_set_coefficients(sdc_ctx* ctx, const double* node_sigma, const double* i
                      ctx->prm.dt * ctx->col.QI[m][m], ctx->Hval + m * nnz, ctx->dinv + m * N, nullptr, nullptr);
     HIPC(hipGetLastError());
     if (ctx->nd > 0) TRY(build_dia(ctx));
+    TRY(fill_sell(ctx));
   }
   HIPC(hipStreamSynchronize(ctx->stream));
   return SDC_OK;
@@ -1506,7 +1579,7 @@ int sdc_set_coefficients(sdc_ctx* ctx, const double* node_sigma, const double* i
 int sdc_get_info(sdc_ctx* ctx, sdc_info* out) {
   TRY(check_ready(ctx));
   if (!out) return fail(ctx, SDC_ERR_ARG, "null output");
-  out->format = ctx->use_dia ? 2 : 1;
+  out->format = ctx->fmt();
   out->n_diagonals = ctx->nd;
   out->t_csr_us = ctx->t_csr_us;
   out->t_dia_us = ctx->t_dia_us;
@@ -1517,6 +1590,7 @@ int sdc_get_info(sdc_ctx* ctx, sdc_info* out) {
   out->graph_steps = ctx->graph_steps;
   out->graph_captures = ctx->graph_captures;
   out->graph_redone = ctx->graph_redone;
+  out->t_sell_us = ctx->t_sell_us;
   return SDC_OK;
 }
 

@@ -107,6 +107,16 @@ struct sdc_ctx {
   double *dia_A = nullptr, *dia_H = nullptr;   // [nd/2+1][N], [M][nd/2+1][N] (offsets >= 0)
   bool use_dia = false;
   double t_csr_us = 0.0, t_dia_us = 0.0;
+  // sliced ELL copy of A and every H_m (not with the linearized scheme, whose
+  // sweeps rewrite the diagonals of the CSR and diagonal copies)
+  int32_t* sell_ptr = nullptr;   // [nslice + 1] slice offsets (entries)
+  int32_t* sell_col = nullptr;   // [sell_len] columns, padding = the row
+  double* sell_A = nullptr;      // [sell_len]
+  double* sell_H = nullptr;      // [M][sell_len]
+  int64_t sell_len = 0;
+  int nslice = 0;
+  bool use_sell = false;
+  double t_sell_us = 0.0;
   // all-rows CG launches with diagonal storage: two rows per thread (else
   // one), and the setup timings of one and two rows per thread (0: not timed)
   bool pair_all = true;
@@ -258,15 +268,21 @@ struct sdc_ctx {
   // output description for building a map into mb (records carry the diagonal offsets)
   NextMap next(const MapBuf& mb) const { return mb.next(node_off_d, nd > 0 ? dia_off : nullptr, nd); }
   CgState cg() const { return CgState{cg_done, cg_iters, cg_blk_done}; }
-  Mat matA(bool dia) const {
-    return Mat{rowptr, colidx, Aval, dia_off, dia_A, node_off_d, dia ? nd : 0};
+  // storage: 1 CSR, 2 diagonal, 3 sliced ELL
+  Mat matA(int fmt) const {
+    Mat a{rowptr, colidx, Aval, dia_off, dia_A, node_off_d, fmt == 2 ? nd : 0};
+    if (fmt == 3) a.sptr = sell_ptr, a.scol = sell_col, a.sval = sell_A;
+    return a;
   }
-  Mat matH(int m, bool dia) const {
-    return Mat{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz, dia_off,
-               dia_H ? dia_H + static_cast<int64_t>(m) * (nd / 2 + 1) * N : nullptr, node_off_d, dia ? nd : 0};
+  Mat matH(int m, int fmt) const {
+    Mat h{rowptr, colidx, Hval + static_cast<int64_t>(m) * nnz, dia_off,
+          dia_H ? dia_H + static_cast<int64_t>(m) * (nd / 2 + 1) * N : nullptr, node_off_d, fmt == 2 ? nd : 0};
+    if (fmt == 3) h.sptr = sell_ptr, h.scol = sell_col, h.sval = sell_H + static_cast<int64_t>(m) * sell_len;
+    return h;
   }
-  Mat A() const { return matA(use_dia); }
-  Mat H(int m) const { return matH(m, use_dia); }
+  int fmt() const { return use_dia ? 2 : use_sell ? 3 : 1; }
+  Mat A() const { return matA(fmt()); }
+  Mat H(int m) const { return matH(m, fmt()); }
   ZeroVecs zv() const {
     return ZeroVecs{{r[0], r[1], wv[0], wv[1], s[0], s[1]}, dv, prm.M, N, emi ? dI : nullptr, emi ? dR : nullptr};
   }

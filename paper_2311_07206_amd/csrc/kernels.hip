@@ -75,6 +75,32 @@ __device__ __forceinline__ void for_entries(const Mat& A, int64_t N, const Row& 
         f(in ? a[q] : 0.0, cq[q], in && cq[q] == i);
       }
     }
+  } else if constexpr (S == -2) {
+    // Sliced ELL: the rows of a wavefront-sized slice hold their entries
+    // column by column, so the 64 lanes of a wave on consecutive rows read
+    // each entry position with one coalesced load.  Entries go in the row's
+    // CSR order; past the row's length the slice's padding (value 0, the
+    // row's own column) adds exact zeros, so the sums equal the CSR loop's.
+    const int n_row = A.rowptr[i + 1] - A.rowptr[i];
+    const int sl = i / kSlice, lane = i % kSlice;
+    const int e0 = A.sptr[sl], len = (A.sptr[sl + 1] - e0) / kSlice;
+    const double* vp = A.sval + e0 + lane;
+    const int32_t* cp = A.scol + e0 + lane;
+    for (int db = 0; db < len; db += kCsrChunk) {
+      double a[kCsrChunk];
+      int cq[kCsrChunk];
+#pragma unroll
+      for (int q = 0; q < kCsrChunk; ++q) {
+        const int d = min(db + q, len - 1);
+        a[q] = vp[d * kSlice];
+        cq[q] = cp[d * kSlice];
+      }
+#pragma unroll
+      for (int q = 0; q < kCsrChunk; ++q) {
+        const bool in = db + q < len;
+        f(in ? a[q] : 0.0, cq[q], in && db + q < n_row && cq[q] == i);
+      }
+    }
   } else {
     constexpr int kUnroll = S > 0 ? S : 1;
     const int nd = S > 0 ? S : A.nd;
@@ -93,10 +119,11 @@ __device__ __forceinline__ void for_entries(const Mat& A, int64_t N, const Row& 
   }
 }
 
-// Storage tags compiled: CSR, diagonal storage with 3 (1D), 7 (2D triangles)
-// or 19 (3D five-tet) diagonals, and diagonal storage with a runtime count.
+// Storage tags compiled: CSR (0), sliced ELL (-2), diagonal storage with 3
+// (1D), 7 (2D triangles) or 19 (3D five-tet) diagonals, and diagonal storage
+// with a runtime count (-1).
 template <class F>
-void dispatch_storage(int nd, F&& f) {
+void dispatch_nd(int nd, F&& f) {
   switch (nd) {
     case 0: f(std::integral_constant<int, 0>{}); break;
     case 3: f(std::integral_constant<int, 3>{}); break;
@@ -104,6 +131,14 @@ void dispatch_storage(int nd, F&& f) {
     case 19: f(std::integral_constant<int, 19>{}); break;
     default: f(std::integral_constant<int, -1>{}); break;
   }
+}
+
+template <class F>
+void dispatch_storage(const Mat& A, F&& f) {
+  if (A.nd == 0 && A.sptr)
+    f(std::integral_constant<int, -2>{});
+  else
+    dispatch_nd(A.nd, f);
 }
 
 // Aliev-Panfilov current and gating rate (paper Sec. 5.1).
@@ -1534,7 +1569,7 @@ void launch_sweep_start(hipStream_t s, int M, const Map& map, int64_t N, const M
                         double* Gam, double* amax, const CollArgs& c, const EmiArgs& e) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    dispatch_storage(A.nd, [&](auto st) {
+    dispatch_storage(A, [&](auto st) {
       constexpr int MM = decltype(mm)::value, S = decltype(st)::value;
       if (e.part)
         k_sweep_start<MM, S, true><<<grid(map.nblk), kBlock, 0, s>>>(map, N, A, ml, v0, w0, v, w, I, R, Phi, Gam,
@@ -1551,7 +1586,7 @@ void launch_rhs(hipStream_t s, int M, int m, const Map& map, int64_t N, const Ma
                 double* x, const CollArgs& c, const EmiArgs& e, const double* G) {
   if (map.nblk <= 0) return;
   dispatch_m(M, [&](auto mm) {
-    dispatch_storage(A.nd, [&](auto st) {
+    dispatch_storage(A, [&](auto st) {
       constexpr int MM = decltype(mm)::value, S = decltype(st)::value;
       if (e.part)
         k_rhs<MM, S, true, false><<<grid(map.nblk), kBlock, 0, s>>>(map, m, N, A, ml, Phi_m, dI, dv, r, x, c, e,
@@ -1592,7 +1627,7 @@ void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const
                      const double* dinv, const double* r0, double* u0, double* w0, double* part_out,
                      const CgState& cg) {
   const size_t lds = cap_lds(map);
-  dispatch_storage(H.nd, [&](auto st) {
+  dispatch_storage(H, [&](auto st) {
     k_cg_start<decltype(st)::value><<<grid(map.nblk), kBlock, lds, s>>>(map, n_inst, N, H, dinv, r0, u0, w0,
                                                                         part_out, cg);
   });
@@ -1600,7 +1635,7 @@ void launch_cg_start(hipStream_t s, const Map& map, int n_inst, int64_t N, const
 
 bool compiled_diagonals(int nd) {
   bool fixed = false;
-  dispatch_storage(nd, [&](auto st) { fixed = decltype(st)::value > 0; });
+  dispatch_nd(nd, [&](auto st) { fixed = decltype(st)::value > 0; });
   return fixed;
 }
 
@@ -1631,7 +1666,7 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                                               cg.done, cg.iters);
     }
   };
-  dispatch_storage(H.nd, [&](auto st) {
+  dispatch_storage(H, [&](auto st) {
     constexpr int S = decltype(st)::value;
     auto pick = [&](auto tt) {
       constexpr bool T = decltype(tt)::value;
@@ -1710,7 +1745,7 @@ void launch_cg_wg(hipStream_t s, const Map& map, int64_t N, const Mat& H, const 
                   double* x, double* pbuf, const CgStop& stop, const CgState& cg, int rows_per_thread) {
   if (map.n_inst <= 0) return;
   const dim3 g(static_cast<unsigned>(map.n_inst));
-  dispatch_storage(H.nd, [&](auto st) {
+  dispatch_storage(H, [&](auto st) {
     constexpr int S = decltype(st)::value;
     if (rows_per_thread == 2)
       k_cg_wg<S, 2><<<g, kWgThreads, 0, s>>>(map, N, H, dinv, b, x, pbuf, stop, cg.done, cg.iters);
@@ -1721,7 +1756,7 @@ void launch_cg_wg(hipStream_t s, const Map& map, int64_t N, const Mat& H, const 
 
 void launch_energy(hipStream_t s, const Map& map, int64_t N, const Mat& H, const double* x, double* e_part) {
   if (map.nblk <= 0) return;
-  dispatch_storage(H.nd, [&](auto st) {
+  dispatch_storage(H, [&](auto st) {
     k_energy<decltype(st)::value><<<grid(map.nblk), kBlock, cap_lds(map), s>>>(map, N, H, x, e_part);
   });
 }
@@ -1810,6 +1845,25 @@ void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int ns, const 
   if (hi <= lo) return;
   k_build_h_dia<<<dim3(static_cast<unsigned>((hi - lo + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
       N, lo, hi, ns, A, ml, c, H);
+}
+
+__global__ __launch_bounds__(kBlock) void k_build_sell(int64_t N, int nslice, const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ sptr,
+                                                       const double* __restrict__ val, double* __restrict__ sval) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= static_cast<int64_t>(nslice) * kSlice) return;
+  const int sl = static_cast<int>(i / kSlice), lane = static_cast<int>(i % kSlice);
+  const int e0 = sptr[sl], len = (sptr[sl + 1] - e0) / kSlice;
+  const int n_row = i < N ? rowptr[i + 1] - rowptr[i] : 0;
+  const int r0 = i < N ? rowptr[i] : 0;
+  for (int d = 0; d < len; ++d) sval[e0 + d * kSlice + lane] = d < n_row ? val[r0 + d] : 0.0;
+}
+
+void launch_build_sell(hipStream_t s, int64_t N, int nslice, const int32_t* rowptr, const int32_t* sptr,
+                       const double* val, double* sval) {
+  const int64_t n = static_cast<int64_t>(nslice) * kSlice;
+  k_build_sell<<<grid(static_cast<int>((n + kBlock - 1) / kBlock)), kBlock, 0, s>>>(N, nslice, rowptr, sptr, val,
+                                                                                    sval);
 }
 
 void launch_iota(hipStream_t s, int32_t* out, int64_t n) {

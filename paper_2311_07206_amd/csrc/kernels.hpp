@@ -78,6 +78,12 @@ struct Csr {
 // entry with offset -o is read as the entry (r - o, r).  Entries absent from
 // the pattern hold 0, and a column outside the instance is replaced by r
 // itself (with value 0).
+// With nd == 0 and sptr not null the entries are read from a sliced ELL copy
+// instead of the CSR arrays: rows in slices of kSlice (one wavefront), slice
+// s holding its entries column by column from sptr[s], entry d of row r at
+// sptr[r / kSlice] + d * kSlice + r % kSlice, in the CSR order of the row and
+// padded to the slice's longest row with value 0 in the row's own column
+// (rowptr still gives each row's length).
 struct Mat {
   const int32_t* rowptr;
   const int32_t* col;
@@ -86,7 +92,11 @@ struct Mat {
   const double* dval;
   const int64_t* node_off;
   int nd;
+  const int32_t* sptr = nullptr;
+  const int32_t* scol = nullptr;
+  const double* sval = nullptr;
 };
+constexpr int kSlice = 64;
 
 // Per-instance CG scalars, layout [n_inst][kScal] (one 128-byte line each).
 // kRZ holds gamma = r.z; kE the running sum of the step terms alpha_j gamma_j
@@ -263,6 +273,11 @@ void launch_build_h(hipStream_t s, int64_t N, const int32_t* rowptr, const int32
                     const double* A, const double* ml, double c, double* H, double* dinv,
                     const int32_t* ppos, const double* pmass);
 void launch_iota(hipStream_t s, int32_t* out, int64_t n);
+// Sliced ELL values from CSR values on the same pattern: sval[sptr[r / kSlice]
+// + d * kSlice + r % kSlice] = val[rowptr[r] + d] for d below row r's length,
+// 0 for the padding (nslice slices, N rows).
+void launch_build_sell(hipStream_t s, int64_t N, int nslice, const int32_t* rowptr, const int32_t* sptr,
+                       const double* val, double* sval);
 // Diagonal storage of H_m = ML + c A for the rows [lo, hi): ns stored
 // diagonals, the first of which is offset 0.
 void launch_build_h_dia(hipStream_t s, int64_t N, int lo, int hi, int ns, const double* A,

@@ -286,10 +286,11 @@ class Solver:
         steps, rows per thread of the all-rows CG launches and their timings."""
         st = _lib.Info()
         self._check(self.lib.sdc_get_info(self.ctx, ctypes.byref(st)))
-        return {"format": {1: "csr", 2: "dia"}[st.format], "n_diagonals": st.n_diagonals,
+        return {"format": {1: "csr", 2: "dia", 3: "sell"}[st.format], "n_diagonals": st.n_diagonals,
                 "t_csr_us": st.t_csr_us, "t_dia_us": st.t_dia_us, "redone_steps": st.redone_steps,
                 "rows_per_thread": st.rows_per_thread, "t_rows1_us": st.t_rows1_us, "t_rows2_us": st.t_rows2_us,
-                "graph_steps": st.graph_steps, "graph_captures": st.graph_captures, "graph_redone": st.graph_redone}
+                "graph_steps": st.graph_steps, "graph_captures": st.graph_captures, "graph_redone": st.graph_redone,
+                "t_sell_us": st.t_sell_us}
 
     def set_graph(self, enable=True):
         """Graph-captured sweeps for step() (see sdc_set_graph)."""
