@@ -102,22 +102,83 @@ __device__ __forceinline__ void for_entries(const Mat& A, int64_t N, const Row& 
       }
     }
   } else {
+    // Every load is unconditional (a column outside the instance reads row
+    // i's own entry and is weighted 0), so that the compiler issues all of
+    // them before the first wait.  Offset 0 sits at index h of the symmetric
+    // offset list; its column is i itself.
     constexpr int kUnroll = S > 0 ? S : 1;
     const int nd = S > 0 ? S : A.nd;
     const int h = nd / 2;
 #pragma unroll kUnroll
     for (int d = 0; d < nd; ++d) {
-      const int c = i + rw.off(d);
+      const int c = d == h ? i : i + rw.off(d);
       const bool in = c >= rw.lo && c < rw.hi;
+      const int k = in ? c : i;
       double a;
-      if (d < h)   // offset -o: the stored entry (c, c + o) of row c
-        a = in ? A.dval[(nd - 1 - d - h) * N + c] : 0.0;
-      else
+      if (d < h) {   // offset -o: the stored entry (c, c + o) of row c
+        const double e = A.dval[(nd - 1 - d - h) * N + k];
+        a = in ? e : 0.0;
+      } else {
         a = A.dval[(d - h) * N + i];
-      f(a, in ? c : i, d == h);   // offset 0 sits at index h of the symmetric offset list
+      }
+      f(a, k, d == h);
     }
   }
 }
+
+// Row i's stored entries under diagonal storage with S diagonals and its
+// neighbours' values in the vectors u, w and (NS) s, read in a phase of its
+// own: no arithmetic touches a loaded value before sums(), so a kernel that
+// places a scheduling barrier between the two has every load in flight
+// before its first wait.  sums() accumulates in for_entries<S>' order with
+// its values (an entry whose column lies outside the instance counts 0), so
+// the results agree bitwise.
+template <int S, bool NS>
+struct DiaLoads {
+  static constexpr int h = S / 2;
+  double a[S], gu[S], gw[S], gs[NS ? S : 1];
+  bool in[S];
+  __device__ __forceinline__ void load(const Mat& A, int64_t N, const Row& rw, int i, const double* __restrict__ u,
+                                       const double* __restrict__ w, const double* __restrict__ s) {
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+      const int c = d == h ? i : i + rw.off(d);
+      in[d] = c >= rw.lo && c < rw.hi;
+      const int k = in[d] ? c : i;
+      a[d] = d < h ? A.dval[(S - 1 - d - h) * N + k] : A.dval[(d - h) * N + i];
+      gu[d] = u[k];
+      gw[d] = w[k];
+      if constexpr (NS) gs[d] = s[k];
+    }
+  }
+  __device__ __forceinline__ void sums(double& ar, double& aw, double& as, double& hii) const {
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+      const double hv = d < h && !in[d] ? 0.0 : a[d];
+      ar += hv * gu[d];
+      aw += hv * gw[d];
+      if constexpr (NS) as += hv * gs[d];
+      if (d == h) hii = hv;
+    }
+  }
+};
+
+// Whether a CG kernel reading `rows` rows per thread under diagonal storage
+// with S diagonals keeps its loads in one phase.  The kernels do so only with
+// the instance totals formed beforehand (three loads instead of a thread's
+// share of the partial sums, which would otherwise stay live across the phase)
+// and while the loaded values fit the registers of a few waves per SIMD;
+// beyond that the compiler's own interleaving of loads and arithmetic is the
+// better schedule (measured on the 2D and 3D workloads).
+template <int S, int rows>
+constexpr bool phased_loads() { return S > 0 && 4 * S * rows <= 80; }
+
+// Waves per SIMD the two-rows-per-thread kernel is compiled for: with more
+// diagonals than a phase holds, a budget of two waves (256 registers) lets
+// the compiler keep most of a row pair's loads in flight together instead of
+// trading them for occupancy (the 19-diagonal 3D stencil runs faster so).
+template <int S>
+constexpr int pair_max_waves() { return phased_loads<S, 2>() ? 8 : 2; }
 
 // Storage tags compiled: CSR (0), sliced ELL (-2), diagonal storage with 3
 // (1D), 7 (2D triangles) or 19 (3D five-tet) diagonals, and diagonal storage
@@ -510,18 +571,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   const int i = rw.row;
   // second round trip, issued together: the row's values and neighbour sums,
   // the instance's scalars and partial sums from the previous launch
+  constexpr bool kPhased = TOT && phased_loads<S, 1>();
   double a_r = 0.0, a_w = 0.0, a_s = 0.0, hii = 0.0;
-  for_entries<S>(H, N, rw, i, [&](double h, int k, bool diag) {
-    a_r += h * u_in[k];
-    a_w += h * w_in[k];
-    if (!FIRST) a_s += h * s_in[k];
-    if (diag) hii = h;
-  });
+  DiaLoads<kPhased ? S : 1, !FIRST> dl;
+  if constexpr (kPhased) {
+    dl.load(H, N, rw, i, u_in, w_in, s_in);
+  } else {
+    for_entries<S>(H, N, rw, i, [&](double h, int k, bool diag) {
+      a_r += h * u_in[k];
+      a_w += h * w_in[k];
+      if (!FIRST) a_s += h * s_in[k];
+      if (diag) hii = h;
+    });
+  }
   const double si = FIRST ? 0.0 : s_in[i];
   const double p_old = FIRST ? 0.0 : p[i];
   const double ui = u_in[i], wi = w_in[i], x_old = x[i];
-  // the Jacobi factor from the row's diagonal, as the stored dinv was formed
-  const double di = 1.0 / hii;
   double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
   const double* sc = scal_in + inst * kScal;
   if (!FIRST) {
@@ -530,22 +595,39 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     sc_bb = sc[kBB];
   }
   double acc[3] = {0.0, 0.0, 0.0};
+  constexpr int kq = TOT ? 1 : kTotBlocks / kBlock;
+  double pv[kq][3];
   if constexpr (TOT) {
     // totals formed by k_cg_totals (part_in holds them, [n_inst][4])
-    acc[0] = part_in[4 * inst];
-    acc[1] = part_in[4 * inst + 1];
-    acc[2] = part_in[4 * inst + 2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pv[0][k] = part_in[4 * inst + k];
   } else {
     // the instance's partials (at most kTotBlocks of them) by unconditional
-    // loads: a clamped index and a 0/1 weight
+    // loads at a clamped index; the weights follow in the arithmetic
 #pragma unroll
-    for (int q = 0; q < kTotBlocks / kBlock; ++q) {
+    for (int q = 0; q < kq; ++q) {
       const int b = static_cast<int>(threadIdx.x) + q * kBlock;
       const double* pp = part_in + 4 * (b0 + min(b, nb - 1));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pv[q][k] = pp[k];
+    }
+  }
+  if constexpr (kPhased) {
+    __builtin_amdgcn_sched_barrier(0);   // every load above is issued before the arithmetic below
+    dl.sums(a_r, a_w, a_s, hii);
+  }
+  // the Jacobi factor from the row's diagonal, as the stored dinv was formed
+  const double di = 1.0 / hii;
+  if constexpr (TOT) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] = pv[0][k];
+  } else {
+#pragma unroll
+    for (int q = 0; q < kq; ++q) {
+      const int b = static_cast<int>(threadIdx.x) + q * kBlock;
       const double wgt = b < nb ? 1.0 : 0.0;
-      acc[0] += wgt * pp[0];
-      acc[1] += wgt * pp[1];
-      acc[2] += wgt * pp[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[k] += wgt * pv[q][k];
     }
     block_total<3>(acc, sh_in);
   }
@@ -637,23 +719,24 @@ __device__ inline void pair_block_total(double (&v)[NV], double* sh /* [4 * NV] 
 // arithmetic per row and the order of every sum are those of k_cg_iter, so
 // the two kernels agree bitwise.
 template <int S, bool FIRST, bool TOT>
-__global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__ blk_done,
-                                                           const BlkRec* __restrict__ rec,
-                                                           const int32_t* __restrict__ idx, int nblk,
-                                                           const int32_t* __restrict__ live, int it,
-                                                           const double* __restrict__ part_in,
-                                                           const double* __restrict__ scal_in, int64_t N, Mat H,
-                                                           const double* __restrict__ dinv,
-                                                           double* __restrict__ x, double* __restrict__ p,
-                                                           const double* __restrict__ u_in,
-                                                           const double* __restrict__ w_in,
-                                                           const double* __restrict__ s_in,
-                                                           double* __restrict__ u_out,
-                                                           double* __restrict__ w_out,
-                                                           double* __restrict__ s_out,
-                                                           double* __restrict__ part_out,
-                                                           double* __restrict__ scal_out, CgStop stop,
-                                                           int32_t* __restrict__ done, int32_t* __restrict__ iters) {
+__global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(1, pair_max_waves<S>())))
+void k_cg_iter2(int32_t* __restrict__ blk_done,
+                const BlkRec* __restrict__ rec,
+                const int32_t* __restrict__ idx, int nblk,
+                const int32_t* __restrict__ live, int it,
+                const double* __restrict__ part_in,
+                const double* __restrict__ scal_in, int64_t N, Mat H,
+                const double* __restrict__ dinv,
+                double* __restrict__ x, double* __restrict__ p,
+                const double* __restrict__ u_in,
+                const double* __restrict__ w_in,
+                const double* __restrict__ s_in,
+                double* __restrict__ u_out,
+                double* __restrict__ w_out,
+                double* __restrict__ s_out,
+                double* __restrict__ part_out,
+                double* __restrict__ scal_out, CgStop stop,
+                int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   static_assert(S > 0, "diagonal storage with a compile-time count");
   __shared__ double sh_in[16], sh_out[16];
   const int L = logical_block(nblk);
@@ -678,83 +761,153 @@ __global__ __launch_bounds__(kPairThreads) void k_cg_iter2(int32_t* __restrict__
   const bool interior = n_rows == kBlock && rw.beg + rw.off(0) >= rw.lo && rw.end - 1 + rw.off(S - 1) < rw.hi;
   double ar[2] = {0.0, 0.0}, aw[2] = {0.0, 0.0}, as[2] = {0.0, 0.0}, hii[2] = {0.0, 0.0};
   double si[2], pold[2], di[2], ui[2], wi[2], xold[2];
-  if (interior) {
-    // both rows valid, ib = ia + 1, every column inside the instance
-#pragma unroll
-    for (int d = 0; d < S; ++d) {
-      const int c = ia + rw.off(d);
-      const double* hp = d < h ? H.dval + static_cast<int64_t>(S - 1 - d - h) * N + c
-                               : H.dval + static_cast<int64_t>(d - h) * N + ia;
-      const double h0 = hp[0], h1 = hp[1];
-      ar[0] += h0 * u_in[c];
-      ar[1] += h1 * u_in[c + 1];
-      aw[0] += h0 * w_in[c];
-      aw[1] += h1 * w_in[c + 1];
-      if (!FIRST) {
-        as[0] += h0 * s_in[c];
-        as[1] += h1 * s_in[c + 1];
-      }
-      if (d == h) {
-        hii[0] = h0;
-        hii[1] = h1;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      si[q] = FIRST ? 0.0 : s_in[ia + q];
-      pold[q] = FIRST ? 0.0 : p[ia + q];
-      ui[q] = u_in[ia + q];
-      wi[q] = w_in[ia + q];
-      xold[q] = x[ia + q];
-    }
-  } else {
+  double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
+  const double* sc = scal_in + inst * kScal;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if constexpr (TOT && phased_loads<S, 2>()) {
+    // Everything the iteration reads is requested before the first wait: the
+    // two rows' own values, the instance's scalars and totals (ahead of the
+    // interior/edge branch, so that no load waits behind it), then the
+    // stencil's values and neighbour sums.
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int i = q ? ib : ia;
-      for_entries<S>(H, N, rw, i, [&](double hv, int k, bool diag) {
-        ar[q] += hv * u_in[k];
-        aw[q] += hv * w_in[k];
-        if (!FIRST) as[q] += hv * s_in[k];
-        if (diag) hii[q] = hv;
-      });
       si[q] = FIRST ? 0.0 : s_in[i];
       pold[q] = FIRST ? 0.0 : p[i];
       ui[q] = u_in[i];
       wi[q] = w_in[i];
       xold[q] = x[i];
     }
-  }
-  double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
-  const double* sc = scal_in + inst * kScal;
-  if (!FIRST) {
-    sc_rz = sc[kRZ];
-    sc_alpha = sc[kAlpha];
-    sc_bb = sc[kBB];
-  }
-  double acc[3] = {0.0, 0.0, 0.0};
-  if constexpr (TOT) {
-    acc[0] = part_in[4 * inst];
-    acc[1] = part_in[4 * inst + 1];
-    acc[2] = part_in[4 * inst + 2];
-  } else {
-    // the partials of the one-row kernel's threads 2t and 2t+1, each summed
-    // in that kernel's order, then their pair sum
-    double pa[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-#pragma unroll
-    for (int q = 0; q < kTotBlocks / kBlock; ++q) {
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int b = 2 * t + v + q * kBlock;
-        const double* pp = part_in + 4 * (b0 + min(b, nb - 1));
-        const double wgt = b < nb ? 1.0 : 0.0;
-        pa[v][0] += wgt * pp[0];
-        pa[v][1] += wgt * pp[1];
-        pa[v][2] += wgt * pp[2];
-      }
+    if (!FIRST) {
+      sc_rz = sc[kRZ];
+      sc_alpha = sc[kAlpha];
+      sc_bb = sc[kBB];
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) acc[k] = pa[0][k] + pa[1][k];
-    pair_block_total<3>(acc, sh_in);
+    for (int k = 0; k < 3; ++k) acc[k] = part_in[4 * inst + k];
+    if (interior) {
+      // both rows valid, ib = ia + 1, every column inside the instance: each
+      // pair of values is one 16-byte load; the offset-0 term takes the rows'
+      // own values read above
+      double hv[S][2], gu[S][2], gw[S][2], gs[FIRST ? 1 : S][2];
+#pragma unroll
+      for (int d = 0; d < S; ++d) {
+        const double* hp = d < h ? H.dval + static_cast<int64_t>(S - 1 - d - h) * N + ia + rw.off(d)
+                                 : H.dval + static_cast<int64_t>(d - h) * N + ia;
+        hv[d][0] = hp[0];
+        hv[d][1] = hp[1];
+        if (d != h) {
+          const int c = ia + rw.off(d);
+          gu[d][0] = u_in[c];
+          gu[d][1] = u_in[c + 1];
+          gw[d][0] = w_in[c];
+          gw[d][1] = w_in[c + 1];
+          if constexpr (!FIRST) {
+            gs[d][0] = s_in[c];
+            gs[d][1] = s_in[c + 1];
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);   // every load above is issued before the arithmetic below
+#pragma unroll
+      for (int d = 0; d < S; ++d) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const double hq = hv[d][q];
+          ar[q] += hq * (d == h ? ui[q] : gu[d][q]);
+          aw[q] += hq * (d == h ? wi[q] : gw[d][q]);
+          if constexpr (!FIRST) as[q] += hq * (d == h ? si[q] : gs[d][q]);
+          if (d == h) hii[q] = hq;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int i = q ? ib : ia;
+        for_entries<S>(H, N, rw, i, [&](double hv, int k, bool diag) {
+          ar[q] += hv * u_in[k];
+          aw[q] += hv * w_in[k];
+          if (!FIRST) as[q] += hv * s_in[k];
+          if (diag) hii[q] = hv;
+        });
+      }
+    }
+  } else {
+    if (interior) {
+      // both rows valid, ib = ia + 1, every column inside the instance
+#pragma unroll
+      for (int d = 0; d < S; ++d) {
+        const int c = ia + rw.off(d);
+        const double* hp = d < h ? H.dval + static_cast<int64_t>(S - 1 - d - h) * N + c
+                                 : H.dval + static_cast<int64_t>(d - h) * N + ia;
+        const double h0 = hp[0], h1 = hp[1];
+        ar[0] += h0 * u_in[c];
+        ar[1] += h1 * u_in[c + 1];
+        aw[0] += h0 * w_in[c];
+        aw[1] += h1 * w_in[c + 1];
+        if (!FIRST) {
+          as[0] += h0 * s_in[c];
+          as[1] += h1 * s_in[c + 1];
+        }
+        if (d == h) {
+          hii[0] = h0;
+          hii[1] = h1;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        si[q] = FIRST ? 0.0 : s_in[ia + q];
+        pold[q] = FIRST ? 0.0 : p[ia + q];
+        ui[q] = u_in[ia + q];
+        wi[q] = w_in[ia + q];
+        xold[q] = x[ia + q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int i = q ? ib : ia;
+        for_entries<S>(H, N, rw, i, [&](double hv, int k, bool diag) {
+          ar[q] += hv * u_in[k];
+          aw[q] += hv * w_in[k];
+          if (!FIRST) as[q] += hv * s_in[k];
+          if (diag) hii[q] = hv;
+        });
+        si[q] = FIRST ? 0.0 : s_in[i];
+        pold[q] = FIRST ? 0.0 : p[i];
+        ui[q] = u_in[i];
+        wi[q] = w_in[i];
+        xold[q] = x[i];
+      }
+    }
+    if (!FIRST) {
+      sc_rz = sc[kRZ];
+      sc_alpha = sc[kAlpha];
+      sc_bb = sc[kBB];
+    }
+    if constexpr (TOT) {
+      acc[0] = part_in[4 * inst];
+      acc[1] = part_in[4 * inst + 1];
+      acc[2] = part_in[4 * inst + 2];
+    } else {
+      // the partials of the one-row kernel's threads 2t and 2t+1, each summed
+      // in that kernel's order, then their pair sum
+      double pa[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+      for (int q = 0; q < kTotBlocks / kBlock; ++q) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int b = 2 * t + v + q * kBlock;
+          const double* pp = part_in + 4 * (b0 + min(b, nb - 1));
+          const double wgt = b < nb ? 1.0 : 0.0;
+          pa[v][0] += wgt * pp[0];
+          pa[v][1] += wgt * pp[1];
+          pa[v][2] += wgt * pp[2];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[k] = pa[0][k] + pa[1][k];
+      pair_block_total<3>(acc, sh_in);
+    }
   }
   const double gamma = acc[0], delta = acc[1], rr = acc[2];
   double alpha, beta, bb;
