@@ -408,6 +408,10 @@ typedef struct {
   int64_t graph_captures;
   int64_t graph_redone;
   double t_sell_us;   /* setup timing of the sliced ELL storage (0 if not timed) */
+  /* order of the work maps' 256-row blocks over the 8 XCDs: each XCD takes */
+  /* runs of xcd_chunk consecutive blocks in turn (about 8 stencil reaches, */
+  /* the matrix bandwidth); 0 = each XCD a contiguous eighth of the map     */
+  int32_t xcd_chunk;
 } sdc_info;
 
 int sdc_get_info(sdc_ctx* ctx, sdc_info* out);

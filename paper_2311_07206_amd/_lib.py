@@ -61,7 +61,8 @@ class Info(ctypes.Structure):
     _fields_ = [("format", c_int32), ("n_diagonals", c_int32), ("t_csr_us", c_double),
                 ("t_dia_us", c_double), ("redone_steps", c_int64), ("rows_per_thread", c_int32),
                 ("t_rows1_us", c_double), ("t_rows2_us", c_double), ("graph_steps", c_int64),
-                ("graph_captures", c_int64), ("graph_redone", c_int64), ("t_sell_us", c_double)]
+                ("graph_captures", c_int64), ("graph_redone", c_int64), ("t_sell_us", c_double),
+                ("xcd_chunk", c_int32)]
 
 
 class Emi(ctypes.Structure):

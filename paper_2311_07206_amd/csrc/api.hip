@@ -57,6 +57,7 @@ int alloc_map(sdc_ctx* ctx, MapBuf* mb, int32_t nblk_cap) {
   mb->nnz.assign(ni, 0);
   mb->n_inst = ni;
   mb->cap = nblk_cap;
+  mb->xcd_shift = ctx->xcd_shift;
   return SDC_OK;
 }
 
@@ -505,7 +506,8 @@ Map graph_map(const sdc_ctx* ctx, int k) {
   if (k == 0 || !graph_adaptive(ctx)) return ctx->all.dev();
   const int slot = (k - 1) & 1;
   const MapBuf& mb = ctx->dyn[slot];
-  return Map{mb.rec, mb.inst_blk0, mb.inst_nblk, ctx->list[slot], ctx->gcap[k], ctx->n_inst, mb.totals};
+  return Map{mb.rec, mb.inst_blk0, mb.inst_nblk, ctx->list[slot], ctx->gcap[k], ctx->n_inst, mb.totals,
+             mb.xcd_shift};
 }
 
 // Enqueue sweep k of a graph step on s: the launch sequence of do_sweep with
@@ -1252,6 +1254,19 @@ int sdc_setup_mesh(sdc_ctx* ctx, const sdc_params* prm, int32_t dim, int32_t n_i
     TRY(dalloc(ctx, &ctx->s[q], N));
   }
 
+  // The XCD order of the work maps: chunks of about 8 stencil reaches (the
+  // matrix bandwidth, in 256-row blocks), at least 4 blocks; a 3D grid's
+  // reach of a plane makes the chunks an eighth of the map.
+  {
+    int64_t reach = 1;
+    for (int64_t r = 0; r < N; ++r)
+      for (int32_t e = ctx->host.rowptr[r]; e < ctx->host.rowptr[r + 1]; ++e)
+        reach = std::max(reach, std::abs(static_cast<int64_t>(ctx->host.col[e]) - r));
+    const int64_t chunk = std::max<int64_t>(4, (8 * reach + kBlock - 1) / kBlock);
+    int sh = 0;
+    while ((int64_t{1} << sh) < chunk && sh < kXcdContig) ++sh;
+    ctx->xcd_shift = sh;
+  }
   // all-rows work map (host-built)
   std::vector<BlkRec> rec;
   std::vector<int32_t> blk0(n_inst + 1), nblk(n_inst + 1), cnt(n_inst + 1), aoff(n_inst + 1);
@@ -1591,6 +1606,7 @@ int sdc_get_info(sdc_ctx* ctx, sdc_info* out) {
   out->graph_captures = ctx->graph_captures;
   out->graph_redone = ctx->graph_redone;
   out->t_sell_us = ctx->t_sell_us;
+  out->xcd_chunk = ctx->xcd_shift >= sdc::kXcdContig ? 0 : 1 << ctx->xcd_shift;
   return SDC_OK;
 }
 

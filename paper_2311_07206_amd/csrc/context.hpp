@@ -30,12 +30,13 @@ struct MapBuf {
   int32_t nblk = 0;
   int32_t n_inst = 0;
   int32_t cap = 0;                    // entries the record array holds
+  int32_t xcd_shift = kXcdContig;     // order of the entries over the XCDs (see Map)
   int32_t max_nb = 0;                 // most blocks of one instance
   int64_t rows = 0;
   std::vector<int32_t> cnt;
   std::vector<int64_t> nnz;
 
-  Map dev() const { return Map{rec, inst_blk0, inst_nblk, idx, nblk, n_inst}; }
+  Map dev() const { return Map{rec, inst_blk0, inst_nblk, idx, nblk, n_inst, nullptr, xcd_shift}; }
   // the per-instance totals pass: for instances over kTotBlocks blocks, and
   // on maps long enough (over kTotMapBlocks blocks, i.e. launches that
   // stream from HBM) that one more launch costs less than every block
@@ -102,6 +103,7 @@ struct sdc_ctx {
   double *Aval = nullptr, *Hval = nullptr, *ml = nullptr, *dinv = nullptr;
   // diagonal storage (nd > 0 when every instance has at most kMaxDiag offsets)
   int nd = 0;
+  int32_t xcd_shift = sdc::kXcdContig;   // order of map entries over the XCDs, from the matrix bandwidth
   int32_t* dia_off = nullptr;      // [n_inst][nd]
   std::vector<int32_t> dia_off_h;
   double *dia_A = nullptr, *dia_H = nullptr;   // [nd/2+1][N], [M][nd/2+1][N] (offsets >= 0)

@@ -14,13 +14,22 @@ __device__ inline bool keep_row(double a, double theta) { return theta <= 0.0 ||
 constexpr int kRecWords = static_cast<int>(sizeof(BlkRec) / sizeof(int32_t));
 
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
-// b mod 8).  Give each XCD a contiguous range of map entries instead, so that
+// b mod 8).  Give each XCD runs of consecutive map entries instead, so that
 // neighbouring row blocks, which read each other's rows through the stencil,
-// share one L2.  A bijection of [0, nblk) when the grid has nblk workgroups.
-__device__ inline int logical_block(int nblk) {
+// share one L2: XCD x takes chunks x, x + 8, x + 16, ... of 2^sh entries (in
+// order), and the entries past the last full round of 8 chunks in contiguous
+// eighths.  Chunks a few times the stencil's reach keep the reads inside one
+// L2 and still deal every XCD an even share of a batch's instances, also when
+// some of them have stopped iterating (contiguous eighths would leave the
+// XCDs whose eighth holds stopped instances idle).  A bijection of [0, nblk)
+// when the grid has nblk workgroups.
+__device__ inline int logical_block(int nblk, int sh) {
   const int b = static_cast<int>(blockIdx.x);
-  const int x = b & 7, q = nblk >> 3, rem = nblk & 7;
-  return x * q + min(x, rem) + (b >> 3);
+  const int x = b & 7, k = b >> 3;
+  const int full = (nblk >> (sh + 3)) << (sh + 3);   // entries in full rounds of 8 chunks
+  if (b < full) return ((((k >> sh) << 3) + x) << sh) + (k & ((1 << sh) - 1));
+  const int n = nblk - full, q = n >> 3, rem = n & 7;
+  return full + x * q + min(x, rem) + ((b - full) >> 3);
 }
 
 // The thread's row and its block's map entry.  Each wave reads the entry with
@@ -48,7 +57,7 @@ __device__ inline int map_entries(const Map& map) { return map.live ? *map.live 
 // LIST: 1 the map has a list, 0 all rows, -1 decided at run time.
 template <int LIST = -1>
 __device__ inline Row map_row(const Map& map) {
-  const int L = map.live ? static_cast<int>(blockIdx.x) : logical_block(map.nblk);
+  const int L = map.live ? static_cast<int>(blockIdx.x) : logical_block(map.nblk, map.xcd_shift);
   const int t = static_cast<int>(threadIdx.x);
   const int32_t* words = reinterpret_cast<const int32_t*>(map.rec + L);
   Row r;

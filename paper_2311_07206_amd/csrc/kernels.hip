@@ -539,7 +539,7 @@ __device__ inline void energy_record(const double* sc, double* so, bool first, i
 
 template <int S, bool FIRST, int LIST, bool TOT>
 __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_done, const BlkRec* __restrict__ rec,
-                                                    const int32_t* __restrict__ idx, int nblk,
+                                                    const int32_t* __restrict__ idx, int nblk, int xcd_shift,
                                                     const int32_t* __restrict__ live, int it,
                                                     const double* __restrict__ part_in,
                                                     const double* __restrict__ scal_in, int64_t N, Mat H,
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
                                                     int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   __shared__ double sh_in[16], sh_out[16];
   // first round trip: the block's map entry and stop flag, the list entry of the thread's row
-  const Map map{rec, nullptr, nullptr, idx, nblk, 0, live};
+  const Map map{rec, nullptr, nullptr, idx, nblk, 0, live, xcd_shift};
   const Row rw = map_row<LIST>(map);
   const int L = rw.blk;
   // Early exit of a stopped block (or one past a live map's entries).  The
@@ -722,7 +722,7 @@ template <int S, bool FIRST, bool TOT>
 __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(1, pair_max_waves<S>())))
 void k_cg_iter2(int32_t* __restrict__ blk_done,
                 const BlkRec* __restrict__ rec,
-                const int32_t* __restrict__ idx, int nblk,
+                const int32_t* __restrict__ idx, int nblk, int xcd_shift,
                 const int32_t* __restrict__ live, int it,
                 const double* __restrict__ part_in,
                 const double* __restrict__ scal_in, int64_t N, Mat H,
@@ -739,7 +739,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
                 int32_t* __restrict__ done, int32_t* __restrict__ iters) {
   static_assert(S > 0, "diagonal storage with a compile-time count");
   __shared__ double sh_in[16], sh_out[16];
-  const int L = logical_block(nblk);
+  const int L = logical_block(nblk, xcd_shift);
   const int t = static_cast<int>(threadIdx.x);
   Row rw;
   rw.word = reinterpret_cast<const int32_t*>(rec + L)[min(t & 63, kRecWords - 1)];
@@ -1809,14 +1809,12 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
     if (ev_start) {
       // events stamped by the dispatch itself: they time the kernel's execution
       hipExtLaunchKernelGGL(kern, grid(map.nblk), dim3(threads), 0, s, ev_start, ev_stop, 0, cg.blk_done, map.rec,
-                            map.idx, map.nblk, map.live, it, pin, scal_in, N, H, dinv, x, p, u_in, w_in, s_in,
-                            u_out,
-                            w_out, s_out, part_out, scal_out, stop, cg.done, cg.iters);
+                            map.idx, map.nblk, map.xcd_shift, map.live, it, pin, scal_in, N, H, dinv, x, p, u_in,
+                            w_in, s_in, u_out, w_out, s_out, part_out, scal_out, stop, cg.done, cg.iters);
     } else {
-      kern<<<grid(map.nblk), threads, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, map.live, it, pin, scal_in, N,
-                                              H, dinv,
-                                              x, p, u_in, w_in, s_in, u_out, w_out, s_out, part_out, scal_out, stop,
-                                              cg.done, cg.iters);
+      kern<<<grid(map.nblk), threads, 0, s>>>(cg.blk_done, map.rec, map.idx, map.nblk, map.xcd_shift, map.live, it,
+                                              pin, scal_in, N, H, dinv, x, p, u_in, w_in, s_in, u_out, w_out, s_out,
+                                              part_out, scal_out, stop, cg.done, cg.iters);
     }
   };
   dispatch_storage(H, [&](auto st) {

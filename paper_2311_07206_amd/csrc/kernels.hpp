@@ -43,6 +43,12 @@ struct BlkRec {
 // written by the selection that built the map; the grid then has nblk >=
 // *live blocks (the capacity), block b takes entry b and blocks past *live
 // return at once.  Null: nblk is the number of entries (and the grid size).
+// Order of a map's entries over the 8 XCDs: XCD x takes chunks of
+// 2^xcd_shift consecutive entries, chunk c going to XCD c mod 8, and a tail
+// shorter than 8 chunks in eighths.  kXcdContig makes every map one tail,
+// i.e. each XCD a contiguous eighth.
+constexpr int kXcdContig = 24;
+
 struct Map {
   const BlkRec* rec;
   const int32_t* inst_blk0;   // first entry of each instance
@@ -51,6 +57,7 @@ struct Map {
   int32_t nblk;               // grid size
   int32_t n_inst;
   const int32_t* live = nullptr;
+  int32_t xcd_shift = kXcdContig;
 };
 
 // Cell-by-cell model: membrane node pairs.  part[i] is the other node of

@@ -282,15 +282,17 @@ class Solver:
             self.node_sigma = s_a.copy()
 
     def info(self):
-        """Storage in use ('csr' or 'dia'), diagonals, setup timings, redone
-        steps, rows per thread of the all-rows CG launches and their timings."""
+        """Storage in use ('csr', 'dia' or 'sell'), diagonals, setup timings,
+        redone steps, rows per thread of the all-rows CG launches and their
+        timings, graph-mode counts, and the XCD chunk of the work maps (blocks
+        of 256 rows; 0 = contiguous eighths)."""
         st = _lib.Info()
         self._check(self.lib.sdc_get_info(self.ctx, ctypes.byref(st)))
         return {"format": {1: "csr", 2: "dia", 3: "sell"}[st.format], "n_diagonals": st.n_diagonals,
                 "t_csr_us": st.t_csr_us, "t_dia_us": st.t_dia_us, "redone_steps": st.redone_steps,
                 "rows_per_thread": st.rows_per_thread, "t_rows1_us": st.t_rows1_us, "t_rows2_us": st.t_rows2_us,
                 "graph_steps": st.graph_steps, "graph_captures": st.graph_captures, "graph_redone": st.graph_redone,
-                "t_sell_us": st.t_sell_us}
+                "t_sell_us": st.t_sell_us, "xcd_chunk": st.xcd_chunk}
 
     def set_graph(self, enable=True):
         """Graph-captured sweeps for step() (see sdc_set_graph)."""

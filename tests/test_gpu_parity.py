@@ -364,6 +364,25 @@ def test_batched_instances_match_oracle_per_instance():
     assert orc.model.N == P.N
 
 
+def test_batched_chunked_xcd_order_matches_oracle():
+    """A batch whose work map spans full rounds of XCD chunks and a shorter
+    tail in eighths: every row is processed once, the result matches the
+    oracle (the order changes no arithmetic)."""
+    P = config4(n_inst=8, sizes=(40, 56), n_steps=3)
+    s = _solver(P)
+    chunk = s.info()["xcd_chunk"]
+    nblk = int(sum((np.diff(P.node_off) + 255) // 256))
+    reach = max(int(n) + 2 for n in np.sqrt(np.diff(P.node_off)).round())   # 2D grid: (side + 1) + 1
+    print(f"[xcd order] {nblk} blocks, chunk {chunk}, reach {reach}", flush=True)
+    assert chunk == max(4, 1 << int(np.ceil(np.log2((8 * reach + 255) // 256))))
+    assert 8 * chunk <= nblk and nblk % (8 * chunk) != 0
+    gv, gw, sets, stats, _ = gpu_run(P, P.n_steps, s=s)
+    ov, ow, log = run(build(P), P.v_init, P.w_init, P.n_steps, P.K, P.stimuli, idx_replay=sets)
+    assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+    assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
+    assert_counts(stats, log)
+
+
 def _instance(P, i):
     from workloads.configs import Problem
     lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
