@@ -73,18 +73,22 @@ def measured_traffic(path=None):
 def summarize_trace(path):
     """Markdown summary of a rocprofv3 --kernel-trace CSV: per-kernel totals and
     the CG iteration kernel's duration by grid size and by launch class.
-    When the run made calibration copies (the longest copies of the run),
-    only the dispatches after the last of them count (the timed window)."""
+    When the run made calibration copies (three back-to-back device copies of
+    at least 50 us and within 30 % of each other's duration: the first of
+    them touches its memory first), only the dispatches after the last such
+    triple count (the timed window); a setup's own large copies come
+    earlier."""
     import collections
     import csv
     import re
-    rows = list(csv.DictReader(open(path)))
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))   # the CSV is not in time order
     dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
-    copies = [q for q, r in enumerate(rows) if "copyBuffer" in r["Kernel_Name"]]
+    is_copy = ["copyBuffer" in r["Kernel_Name"] for r in rows]
     start = 0
-    if copies:
-        longest = max(dur[q] for q in copies)
-        start = max(q for q in copies if dur[q] >= 0.5 * longest) + 1 if longest > 50000 else 0
+    for q in range(len(rows) - 2):
+        trio = dur[q:q + 3]
+        if all(is_copy[q:q + 3]) and min(trio) >= 50000 and max(trio) <= 1.3 * min(trio):
+            start = q + 3
     durs, grid, by_cls = collections.defaultdict(list), collections.defaultdict(list), collections.defaultdict(list)
     for r, d in list(zip(rows, dur))[start:]:
         m = re.search(r"(k_\w+)", r["Kernel_Name"])
@@ -244,7 +248,12 @@ def parse():
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the time-per-sweep curve over front-shell active sets")
     ap.add_argument("--calib", action="store_true",
-                    help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
+                    help="device copies of 256 MiB at the start of each timed window (counter calibration and the "
+                         "window's start in rocprofv3 runs)")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="skip the batched workload (profiling runs of the 2D or 3D leg alone)")
+    ap.add_argument("--no-storage-variants", action="store_true",
+                    help="skip the 3D leg's runs with CSR and sliced ELL storage forced")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
                     help="print a summary of a rocprofv3 kernel trace and exit")
     ap.add_argument("--min-blocks", type=int, default=0,
@@ -372,7 +381,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    out, window = headline(args)
+    out, window = ({}, None) if args.no_headline else headline(args)
     if not args.headline_only:
         out["copy_GBps"] = copy_bandwidth()
         if "roofline" in out:
@@ -381,11 +390,12 @@ def main():
             out["workload_2d"] = workload_2d(args)
         if not args.no_3d:
             out["workload_3d"] = workload_3d(speedup=not args.no_speedup, first_sweep=not args.no_first_sweep,
-                                             cg_energy=not args.no_cg_energy)
+                                             cg_energy=not args.no_cg_energy,
+                                             variants=not args.no_storage_variants, calib=args.calib)
         if not args.no_emi:
             out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
             out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
-    if not args.no_cpu and not args.headline_only:
+    if not args.no_cpu and not args.headline_only and window is not None:
         out["cpu_baseline"] = cpu_baseline(*window, args.cpu_sample_steps, args.steps)
     print(json.dumps(out), flush=True)
 
@@ -609,6 +619,8 @@ def workload_2d(args):
     v_start, w_start, t_start = v.cpu().numpy().copy(), w.cpu().numpy().copy(), args.warmup_2d * P.dt
     nsteps = args.steps_2d
     vv, ww = torch.tensor(v_start, device=dev), torch.tensor(w_start, device=dev)
+    if args.calib:
+        calibration_copies(dev)
     elapsed, logs = _timed_steps(s, vv, ww, t_start, P.dt, nsteps, sync)
     v_std = vv.cpu().numpy()
     out = {"workload": f"2D monodomain {args.n}x{args.n} P1 ({P.N} dofs), M={P.M} K={P.K} dt={P.dt} ms, "
@@ -872,7 +884,7 @@ def workload_linearized(P, v0, w0, t0, nsteps, speedup=True):
     return out
 
 
-def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True, cg_energy=True):
+def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True, cg_energy=True, variants=True, calib=False):
     """The 128^3 3D workload (2.1M dofs, 27M stored entries): HBM-resident."""
     import torch
 
@@ -887,6 +899,8 @@ def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True, cg_energy=Tr
     for k in range(warm):
         s.step(v, w, k * P.dt)
     v0, w0 = v.cpu().numpy().copy(), w.cpu().numpy().copy()
+    if calib:
+        calibration_copies(dev)
     el, logs = _timed_steps(s, v, w, warm * P.dt, P.dt, nsteps, torch.cuda.synchronize)
     # the kernel timings from a second pass over the same steps
     s.profile(True)
@@ -924,7 +938,8 @@ def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True, cg_energy=Tr
     if cg_energy:
         out["cg_energy_stop"] = cg_energy_variant(P, v0, w0, warm * P.dt, nsteps, out["ms_per_step"], v_std, v_non,
                                                   speedup=speedup)
-    out["storage_variants"] = storage_variants(P, v0, w0, warm * P.dt, nsteps)
+    if variants:
+        out["storage_variants"] = storage_variants(P, v0, w0, warm * P.dt, nsteps)
     return out
 
 

@@ -92,6 +92,27 @@ def test_summarize_trace_bins_cg_launches_by_grid(tmp_path):
     assert "| 1024..1024 | 1 | 11.00 | 11.00 |" in text
 
 
+def test_summarize_trace_window_starts_after_the_calibration_copies(tmp_path):
+    # a setup copy longer than the calibration copies, then three calibration
+    # copies back to back, then the window
+    path = tmp_path / "kt.csv"
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Workgroup_Size_X"]
+    # (rows listed out of time order, as rocprofv3 may write them)
+    cp = "__amd_rocclr_copyBuffer"
+    rows = [("void sdc::k_cg_iter<7, false, 1, false>(...)", 10 ** 7, 10 ** 7 + 5000, 200 * 256, 256),
+            (cp, 0, 400000, 1, 1), ("void sdc::k_rhs<4, 7, false>(...)", 10 ** 6, 10 ** 6 + 9000, 256, 256),
+            (cp, 2 * 10 ** 6, 2 * 10 ** 6 + 118000, 1, 1), (cp, 3 * 10 ** 6, 3 * 10 ** 6 + 101000, 1, 1),
+            (cp, 4 * 10 ** 6, 4 * 10 ** 6 + 99500, 1, 1), (cp, 2 * 10 ** 7, 2 * 10 ** 7 + 3000, 1, 1)]
+    with open(path, "w", newline="") as f:
+        wr = csv.DictWriter(f, fieldnames=fields)
+        wr.writeheader()
+        for r in rows:
+            wr.writerow(dict(zip(fields, r)))
+    text = bench.summarize_trace(str(path))
+    assert text.startswith("dispatches counted: 2 of 7 (after the calibration copies)")
+    assert "k_rhs" not in text and "| k_cg_iter | 1 |" in text
+
+
 def test_measured_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     src = tmp_path / "k.hip"
     src.write_bytes(b"kernel source")
