@@ -595,15 +595,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     sc_bb = sc[kBB];
   }
   double acc[3] = {0.0, 0.0, 0.0};
-  constexpr int kq = TOT ? 1 : kTotBlocks / kBlock;
+  // The instance's totals (k_cg_totals) or, without them, its partial sums
+  // (at most kTotBlocks): the first kq kBlock by unconditional loads at a
+  // clamped index issued with the rest (weights in the arithmetic), further
+  // ones in a loop of uniform trip count for instances of more blocks.
+  // Terms of weight 0 add nothing, so skipping them leaves the sums bitwise
+  // those of the full unrolled read.  Two rounds cover the listed sets of a
+  // 2D batch (fewer registers); the 19-diagonal 3D sets span up to four and
+  // keep them unrolled (measured faster).
+  constexpr int kq = TOT ? 1 : S > 7 ? kTotBlocks / kBlock : 2;
   double pv[kq][3];
   if constexpr (TOT) {
-    // totals formed by k_cg_totals (part_in holds them, [n_inst][4])
 #pragma unroll
     for (int k = 0; k < 3; ++k) pv[0][k] = part_in[4 * inst + k];
   } else {
-    // the instance's partials (at most kTotBlocks of them) by unconditional
-    // loads at a clamped index; the weights follow in the arithmetic
 #pragma unroll
     for (int q = 0; q < kq; ++q) {
       const int b = static_cast<int>(threadIdx.x) + q * kBlock;
@@ -628,6 +633,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
       const double wgt = b < nb ? 1.0 : 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) acc[k] += wgt * pv[q][k];
+    }
+    for (int q = kq; q * kBlock < nb; ++q) {   // nb <= kTotBlocks without totals
+      const int b = static_cast<int>(threadIdx.x) + q * kBlock;
+      const double* pp = part_in + 4 * (b0 + min(b, nb - 1));
+      const double wgt = b < nb ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[k] += wgt * pp[k];
     }
     block_total<3>(acc, sh_in);
   }
