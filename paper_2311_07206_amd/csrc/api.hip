@@ -484,7 +484,7 @@ int pred_slot_of(const sdc_ctx* ctx, int k, int m) { return std::min(k, SDC_MAX_
 // convergence return at once).
 int graph_budget(const sdc_ctx* ctx, int k, int m) {
   const int need = std::max(1, ctx->pred[pred_slot_of(ctx, k, m)]) + 1;
-  return std::min(need + std::max(2, need / 8), ctx->prm.cg_maxit + 1);
+  return std::min(need + std::max(3, need / 16), ctx->prm.cg_maxit + 1);
 }
 
 bool graph_adaptive(const sdc_ctx* ctx) { return ctx->prm.theta > 0.0; }

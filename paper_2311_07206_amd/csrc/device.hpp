@@ -36,9 +36,10 @@ __device__ inline int logical_block(int nblk, int sh) {
 // one vector load (lane q holds word q) and takes the fields from the lanes:
 // vector loads complete in order, so the entry and the list entry of the row
 // (at a position known from the block index alone) arrive in one round trip.
-// With a live count in device memory (graph-captured sweeps) the block index
-// is the entry (no XCD remapping: the count is not known before the loads),
-// the count arrives in the same round trip, and `dead` marks blocks past it.
+// With a live count in device memory (graph-captured sweeps) the grid is
+// the map's capacity: the XCD order is taken over the grid (a bijection of
+// it, so every live entry gets a block), the count arrives in the same round
+// trip, and `dead` marks blocks whose entry lies past it.
 struct Row {
   int word;   // word (lane mod kRecWords) of the block record
   int inst, beg, end, bi, nb, lo, hi;
@@ -57,7 +58,7 @@ __device__ inline int map_entries(const Map& map) { return map.live ? *map.live 
 // LIST: 1 the map has a list, 0 all rows, -1 decided at run time.
 template <int LIST = -1>
 __device__ inline Row map_row(const Map& map) {
-  const int L = map.live ? static_cast<int>(blockIdx.x) : logical_block(map.nblk, map.xcd_shift);
+  const int L = logical_block(map.nblk, map.xcd_shift);
   const int t = static_cast<int>(threadIdx.x);
   const int32_t* words = reinterpret_cast<const int32_t*>(map.rec + L);
   Row r;
