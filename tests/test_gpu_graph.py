@@ -44,7 +44,7 @@ def _steps(P, s, n_steps):
     return states, stats
 
 
-@pytest.mark.parametrize("case", ["1d", "2d", "3d", "batched", "nonadaptive"])
+@pytest.mark.parametrize("case", ["1d", "2d", "3d", "batched", "batched_chunks", "nonadaptive"])
 def test_graph_steps_equal_host_launched_steps_bitwise(case):
     if case == "1d":
         P, n = config0(n=160, theta=1e-6), 14
@@ -54,6 +54,10 @@ def test_graph_steps_equal_host_launched_steps_bitwise(case):
         P, n = config2(n=14, theta=1e-7), 5
     elif case == "batched":
         P, n = config4(n_inst=4, sizes=(12, 30)), 8
+    elif case == "batched_chunks":
+        # maps long enough for full rounds of XCD chunks (90 blocks, chunk 4):
+        # the graph sweeps take that order over their grids
+        P, n = config4(n_inst=8, sizes=(40, 56)), 6
     else:
         P, n = config1(n=40, theta=0.0), 6
     print(f"[graph {case}] N={P.N}, {n} steps", flush=True)
@@ -71,6 +75,15 @@ def test_graph_steps_equal_host_launched_steps_bitwise(case):
     assert info["graph_steps"] >= n - 2 and info["graph_steps"] - info["graph_redone"] >= n // 2
     assert info["graph_captures"] >= 1
     assert ref.info()["graph_steps"] == 0
+    if case == "batched_chunks":
+        # a listed sweep's grid (the entries its set had, a quarter more and
+        # 16) spans at least one full round of 8 XCD chunks
+        chunk = info["xcd_chunk"]
+        rows = g.active().cpu().numpy()
+        cnt = np.diff(np.searchsorted(rows, P.node_off))
+        entries = int(np.sum((cnt + 255) // 256))
+        print(f"   chunk {chunk}, last set {rows.size} rows in {entries} entries", flush=True)
+        assert chunk == 4 and entries + entries // 4 + 16 >= 8 * chunk
     # the set the last sweep used is the host mirror's: the same rows either way
     assert np.array_equal(ref.active().cpu().numpy(), g.active().cpu().numpy())
     ref.close()
