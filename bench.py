@@ -379,7 +379,7 @@ def main():
         print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (the library is single-device); --gpus must be 1"}))
         sys.exit(2)
     out, window = ({}, None) if args.no_headline else headline(args)
     if not args.headline_only:
