@@ -1007,7 +1007,6 @@ def workload_emi(nsteps=3, warm=1, speedup=True, three_d=False):
                        f"{len(P.mem_intra)} membrane sites, M={P.M} "
                        f"K={P.K} dt={P.dt}, theta={P.theta}; steps {warm}..{warm + nsteps - 1} after the stimulus",
            "value": dofs / el, "unit": "active dof-sweeps/s", "ms_per_step": 1e3 * el / nsteps,
-           "repeats_ms_per_step": [1e3 * t / nsteps for t in times],
            "algorithmic_GBps": nbytes / el / 1e9, "storage": s.info(),
            "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)],
            "cg_iters_sweep0": [int(np.max([lg[0]["cg_iters_max"][m] for lg in logs])) for m in range(P.M)]}
