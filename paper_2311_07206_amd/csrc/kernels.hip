@@ -469,6 +469,11 @@ __device__ inline void block_total(double (&v)[NV], double* sh /* [4 * NV] */) {
 }
 
 // One launch per iteration; FIRST is launch 0 (beta = 0, no previous p, s).
+// XW: launches of odd index read and write the iterate x, applying their own
+// update and the one the launch before deferred (x_k = x_{k-1} + alpha_k p_k
+// from the previous launch's alpha and p, then this launch's update, in that
+// order, so x is bitwise that of one update per launch); launches of even
+// index leave x, and a launch that finds the stop writes the deferred update.
 // Memory round trips before the arithmetic: (1) the block record, the list
 // entry of the thread's row and the block's stop flag; (2) everything else
 // the iteration reads: the instance's partial sums and scalars from the
@@ -537,7 +542,7 @@ __device__ inline void energy_record(const double* sc, double* so, bool first, i
   so[kRing + (it - 1) % d] = e_last;
 }
 
-template <int S, bool FIRST, int LIST, bool TOT>
+template <int S, bool FIRST, int LIST, bool TOT, bool XW>
 __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_done, const BlkRec* __restrict__ rec,
                                                     const int32_t* __restrict__ idx, int nblk, int xcd_shift,
                                                     const int32_t* __restrict__ live, int it,
@@ -586,7 +591,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   }
   const double si = FIRST ? 0.0 : s_in[i];
   const double p_old = FIRST ? 0.0 : p[i];
-  const double ui = u_in[i], wi = w_in[i], x_old = x[i];
+  const double ui = u_in[i], wi = w_in[i];
+  const double x_old = XW ? x[i] : 0.0;
   double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
   const double* sc = scal_in + inst * kScal;
   if (!FIRST) {
@@ -673,6 +679,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     if (stop.delay > 0) energy_record(sc, so, FIRST, it, stop.delay, e_sum, e_last);
   }
   if (status != 0) {
+    // the stop leaves x final: a launch of odd index applies the update the
+    // launch before it deferred
+    if (XW && valid) x[i] = fma(sc_alpha, p_old, x_old);
     if (threadIdx.x == 0) blk_done[L] = status;
     return;
   }
@@ -681,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     const double w_new = a_r - alpha * (a_w + beta * a_s);   // H u of the new residual
     const double pi = ui + beta * p_old;
     const double sv = wi + beta * si;                         // dinv (w + beta s)
-    x[i] = x_old + alpha * pi;
+    if (XW) x[i] = fma(alpha, pi, fma(sc_alpha, p_old, x_old));   // this update and the deferred one
     p[i] = pi;
     s_out[i] = sv;
     const double un = ui - alpha * sv;                        // dinv (r - alpha s)
@@ -730,7 +739,7 @@ __device__ inline void pair_block_total(double (&v)[NV], double* sh /* [4 * NV] 
 // per row halves.  Other blocks take the rows one after the other.  The
 // arithmetic per row and the order of every sum are those of k_cg_iter, so
 // the two kernels agree bitwise.
-template <int S, bool FIRST, bool TOT>
+template <int S, bool FIRST, bool TOT, bool XW>
 __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(1, pair_max_waves<S>())))
 void k_cg_iter2(int32_t* __restrict__ blk_done,
                 const BlkRec* __restrict__ rec,
@@ -788,7 +797,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
       pold[q] = FIRST ? 0.0 : p[i];
       ui[q] = u_in[i];
       wi[q] = w_in[i];
-      xold[q] = x[i];
+      xold[q] = XW ? x[i] : 0.0;
     }
     if (!FIRST) {
       sc_rz = sc[kRZ];
@@ -872,7 +881,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
         pold[q] = FIRST ? 0.0 : p[ia + q];
         ui[q] = u_in[ia + q];
         wi[q] = w_in[ia + q];
-        xold[q] = x[ia + q];
+        xold[q] = XW ? x[ia + q] : 0.0;
       }
     } else {
 #pragma unroll
@@ -888,7 +897,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
         pold[q] = FIRST ? 0.0 : p[i];
         ui[q] = u_in[i];
         wi[q] = w_in[i];
-        xold[q] = x[i];
+        xold[q] = XW ? x[i] : 0.0;
       }
     }
     if (!FIRST) {
@@ -950,6 +959,12 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
     if (stop.delay > 0) energy_record(sc, so, FIRST, it, stop.delay, e_sum, e_last);
   }
   if (status != 0) {
+    // the stop leaves x final (see k_cg_iter)
+    if constexpr (XW) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (q ? vb : va) x[q ? ib : ia] = fma(sc_alpha, pold[q], xold[q]);
+    }
     if (t == 0) blk_done[L] = status;
     return;
   }
@@ -962,7 +977,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
     const double w_new = ar[q] - alpha * (aw[q] + beta * as[q]);
     pn[q] = ui[q] + beta * pold[q];
     sn[q] = wi[q] + beta * si[q];
-    xn[q] = xold[q] + alpha * pn[q];
+    xn[q] = fma(alpha, pn[q], fma(sc_alpha, pold[q], xold[q]));
     un[q] = ui[q] - alpha * sn[q];
     wn[q] = di[q] * w_new;
     const double rn = hii[q] * un[q];
@@ -973,7 +988,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
   if (interior) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      x[ia + q] = xn[q];
+      if (XW) x[ia + q] = xn[q];
       p[ia + q] = pn[q];
       s_out[ia + q] = sn[q];
       u_out[ia + q] = un[q];
@@ -987,7 +1002,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
         continue;
       }
       const int i = q ? ib : ia;
-      x[i] = xn[q];
+      if (XW) x[i] = xn[q];
       p[i] = pn[q];
       s_out[i] = sn[q];
       u_out[i] = un[q];
@@ -1829,24 +1844,28 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                                               part_out, scal_out, stop, cg.done, cg.iters);
     }
   };
+  // Launches of odd index write x (their own update and the one the launch
+  // before deferred), launches of even index leave it: x is read and written
+  // every other launch.
   dispatch_storage(H, [&](auto st) {
     constexpr int S = decltype(st)::value;
-    auto pick = [&](auto tt) {
-      constexpr bool T = decltype(tt)::value;
+    auto pick = [&](auto tt, auto xw) {
+      constexpr bool T = decltype(tt)::value, XW = decltype(xw)::value;
       if (map.idx) {
-        it == 0 ? go(k_cg_iter<S, true, 1, T>, kBlock) : go(k_cg_iter<S, false, 1, T>, kBlock);
+        it == 0 ? go(k_cg_iter<S, true, 1, T, false>, kBlock) : go(k_cg_iter<S, false, 1, T, XW>, kBlock);
       } else if (S > 0 && pair_all) {
         // every row of the instances: two rows per thread
         if constexpr (S > 0)
-          it == 0 ? go(k_cg_iter2<S, true, T>, kPairThreads) : go(k_cg_iter2<S, false, T>, kPairThreads);
+          it == 0 ? go(k_cg_iter2<S, true, T, false>, kPairThreads) : go(k_cg_iter2<S, false, T, XW>, kPairThreads);
       } else {
-        it == 0 ? go(k_cg_iter<S, true, 0, T>, kBlock) : go(k_cg_iter<S, false, 0, T>, kBlock);
+        it == 0 ? go(k_cg_iter<S, true, 0, T, false>, kBlock) : go(k_cg_iter<S, false, 0, T, XW>, kBlock);
       }
     };
+    const bool odd = (it & 1) != 0;
     if (tot)
-      pick(std::true_type{});
+      odd ? pick(std::true_type{}, std::true_type{}) : pick(std::true_type{}, std::false_type{});
     else
-      pick(std::false_type{});
+      odd ? pick(std::false_type{}, std::true_type{}) : pick(std::false_type{}, std::false_type{});
   });
 }
 
