@@ -274,10 +274,12 @@ def cg_roofline(prof, storage, n_diag, peak=None):
       touches) -- the per-iteration count of the scope table;
     storage_min: what the chosen storage must move at least: the symmetric
       diagonal storage reads its nd/2 + 1 stored diagonals per row (8 B each),
-      CSR 12 B per entry and a 4 B row pointer; per row 4 vectors read once
-      (u, w, s scaled by the preconditioner, p) and the same 4 written, and
-      the iterate x read and written every other launch (72 B; dinv is
-      formed from the diagonal), plus the list entry;
+      CSR 12 B per entry and a 4 B row pointer; per row 3 vectors read once
+      (u, w, s scaled by the preconditioner) and the same 3 written, the
+      iterate x read and written every other launch (8 B a launch) and the
+      direction p read and written every other launch, with u read a second
+      time there to rebuild it (12 B a launch): 68 B (dinv is formed from the
+      diagonal), plus the list entry;
     achieved: scope_table bytes / mean launch duration (the reported frac).
     """
     peak = peak or HBM_PEAK_GBS
@@ -286,9 +288,9 @@ def cg_roofline(prof, storage, n_diag, peak=None):
     listed_rows = rows - prof["cg_all_rows"]
     b_scope = 12.0 * nnz + 116.0 * rows + 4.0 * listed_rows
     if storage == "dia":
-        b_min = (8.0 * (n_diag // 2 + 1) + 72.0) * rows + 4.0 * listed_rows
+        b_min = (8.0 * (n_diag // 2 + 1) + 68.0) * rows + 4.0 * listed_rows
     else:
-        b_min = 12.0 * nnz + 76.0 * rows + 4.0 * listed_rows
+        b_min = 12.0 * nnz + 72.0 * rows + 4.0 * listed_rows
     sec = ms * 1e-3
     out = {"kernel": "k_cg_iter (all CG-iteration launches: listed sets k_cg_iter, every row k_cg_iter2)",
            "bound": "hbm", "achieved": b_scope / sec / 1e9, "peak": peak, "unit": "GB/s",
@@ -304,7 +306,7 @@ def cg_roofline(prof, storage, n_diag, peak=None):
         if launches <= 0 or lms <= 0:
             continue
         bs = 12.0 * lnnz + (116.0 + 4.0 * listed) * lrows
-        bm = ((8.0 * (n_diag // 2 + 1) + 72.0) * lrows if storage == "dia" else 12.0 * lnnz + 76.0 * lrows) \
+        bm = ((8.0 * (n_diag // 2 + 1) + 68.0) * lrows if storage == "dia" else 12.0 * lnnz + 72.0 * lrows) \
             + 4.0 * listed * lrows
         out[cls] = {"launches": launches, "avg_launch_us": 1e3 * lms / launches, "rows_per_launch": lrows / launches,
                     "scope_table_GBps": bs / (lms * 1e-3) / 1e9, "frac": bs / (lms * 1e-3) / 1e9 / peak,

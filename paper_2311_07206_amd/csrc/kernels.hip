@@ -474,6 +474,9 @@ __device__ inline void block_total(double (&v)[NV], double* sh /* [4 * NV] */) {
 // from the previous launch's alpha and p, then this launch's update, in that
 // order, so x is bitwise that of one update per launch); launches of even
 // index leave x, and a launch that finds the stop writes the deferred update.
+// The direction p is deferred likewise: launches of even index neither read
+// nor write it, and the next launch forms their p again, bitwise, from the
+// same operands.
 // Memory round trips before the arithmetic: (1) the block record, the list
 // entry of the thread's row and the block's stop flag; (2) everything else
 // the iteration reads: the instance's partial sums and scalars from the
@@ -590,15 +593,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     });
   }
   const double si = FIRST ? 0.0 : s_in[i];
-  const double p_old = FIRST ? 0.0 : p[i];
   const double ui = u_in[i], wi = w_in[i];
+  // The direction p is kept, like x, by the launches of odd index only (a
+  // row's p then costs 24 bytes per two launches instead of 32): such a
+  // launch rebuilds the previous launch's p_{L-1} = u_{L-1} + beta_{L-1}
+  // p_{L-2} from p_{L-2} (zero before the first launch), u_{L-1} (still in
+  // this launch's output buffer) and beta_{L-1}, as that launch formed it.
+  const double p_prev2 = XW && it > 1 ? p[i] : 0.0;
+  const double u_prev = XW ? u_out[i] : 0.0;
   const double x_old = XW ? x[i] : 0.0;
-  double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
+  double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0, sc_beta = 0.0;
   const double* sc = scal_in + inst * kScal;
   if (!FIRST) {
     sc_rz = sc[kRZ];
     sc_alpha = sc[kAlpha];
     sc_bb = sc[kBB];
+    sc_beta = sc[kBeta];
   }
   double acc[3] = {0.0, 0.0, 0.0};
   // The instance's totals (k_cg_totals) or, without them, its partial sums
@@ -629,6 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   }
   // the Jacobi factor from the row's diagonal, as the stored dinv was formed
   const double di = 1.0 / hii;
+  const double p_old = XW ? fma(sc_beta, p_prev2, u_prev) : 0.0;   // p_{L-1}
   if constexpr (TOT) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) acc[k] = pv[0][k];
@@ -676,6 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     so[kRZ] = gamma;
     so[kAlpha] = alpha;
     so[kBB] = bb;
+    so[kBeta] = beta;
     if (stop.delay > 0) energy_record(sc, so, FIRST, it, stop.delay, e_sum, e_last);
   }
   if (status != 0) {
@@ -688,10 +700,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   double s[3] = {0.0, 0.0, 0.0};
   if (valid) {
     const double w_new = a_r - alpha * (a_w + beta * a_s);   // H u of the new residual
-    const double pi = ui + beta * p_old;
     const double sv = wi + beta * si;                         // dinv (w + beta s)
-    if (XW) x[i] = fma(alpha, pi, fma(sc_alpha, p_old, x_old));   // this update and the deferred one
-    p[i] = pi;
+    if constexpr (XW) {
+      const double pi = fma(beta, p_old, ui);
+      x[i] = fma(alpha, pi, fma(sc_alpha, p_old, x_old));   // the deferred update, then this one
+      p[i] = pi;
+    }
     s_out[i] = sv;
     const double un = ui - alpha * sv;                        // dinv (r - alpha s)
     u_out[i] = un;
@@ -781,8 +795,12 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
   constexpr int h = S / 2;
   const bool interior = n_rows == kBlock && rw.beg + rw.off(0) >= rw.lo && rw.end - 1 + rw.off(S - 1) < rw.hi;
   double ar[2] = {0.0, 0.0}, aw[2] = {0.0, 0.0}, as[2] = {0.0, 0.0}, hii[2] = {0.0, 0.0};
-  double si[2], pold[2], di[2], ui[2], wi[2], xold[2];
-  double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0;
+  // x and p are kept by the launches of odd index only (see k_cg_iter); with
+  // 19 diagonals this variant needs more registers than two waves per SIMD
+  // allow and runs at one, measured faster than keeping p in every launch
+  const bool p_read = XW && it > 1;
+  double si[2], pld[2], uprev[2], pold[2], di[2], ui[2], wi[2], xold[2];
+  double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0, sc_beta = 0.0;
   const double* sc = scal_in + inst * kScal;
   double acc[3] = {0.0, 0.0, 0.0};
   if constexpr (TOT && phased_loads<S, 2>()) {
@@ -794,7 +812,8 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
     for (int q = 0; q < 2; ++q) {
       const int i = q ? ib : ia;
       si[q] = FIRST ? 0.0 : s_in[i];
-      pold[q] = FIRST ? 0.0 : p[i];
+      pld[q] = p_read ? p[i] : 0.0;
+      uprev[q] = XW ? u_out[i] : 0.0;
       ui[q] = u_in[i];
       wi[q] = w_in[i];
       xold[q] = XW ? x[i] : 0.0;
@@ -803,6 +822,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
       sc_rz = sc[kRZ];
       sc_alpha = sc[kAlpha];
       sc_bb = sc[kBB];
+      sc_beta = sc[kBeta];
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) acc[k] = part_in[4 * inst + k];
@@ -878,7 +898,8 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         si[q] = FIRST ? 0.0 : s_in[ia + q];
-        pold[q] = FIRST ? 0.0 : p[ia + q];
+        pld[q] = p_read ? p[ia + q] : 0.0;
+        uprev[q] = XW ? u_out[ia + q] : 0.0;
         ui[q] = u_in[ia + q];
         wi[q] = w_in[ia + q];
         xold[q] = XW ? x[ia + q] : 0.0;
@@ -894,7 +915,8 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
           if (diag) hii[q] = hv;
         });
         si[q] = FIRST ? 0.0 : s_in[i];
-        pold[q] = FIRST ? 0.0 : p[i];
+        pld[q] = p_read ? p[i] : 0.0;
+        uprev[q] = XW ? u_out[i] : 0.0;
         ui[q] = u_in[i];
         wi[q] = w_in[i];
         xold[q] = XW ? x[i] : 0.0;
@@ -904,6 +926,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
       sc_rz = sc[kRZ];
       sc_alpha = sc[kAlpha];
       sc_bb = sc[kBB];
+      sc_beta = sc[kBeta];
     }
     if constexpr (TOT) {
       acc[0] = part_in[4 * inst];
@@ -956,8 +979,11 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
     so[kRZ] = gamma;
     so[kAlpha] = alpha;
     so[kBB] = bb;
+    so[kBeta] = beta;
     if (stop.delay > 0) energy_record(sc, so, FIRST, it, stop.delay, e_sum, e_last);
   }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) pold[q] = XW ? fma(sc_beta, pld[q], uprev[q]) : 0.0;   // p_{L-1}
   if (status != 0) {
     // the stop leaves x final (see k_cg_iter)
     if constexpr (XW) {
@@ -975,7 +1001,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const double w_new = ar[q] - alpha * (aw[q] + beta * as[q]);
-    pn[q] = ui[q] + beta * pold[q];
+    pn[q] = fma(beta, pold[q], ui[q]);
     sn[q] = wi[q] + beta * si[q];
     xn[q] = fma(alpha, pn[q], fma(sc_alpha, pold[q], xold[q]));
     un[q] = ui[q] - alpha * sn[q];
@@ -988,8 +1014,10 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
   if (interior) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      if (XW) x[ia + q] = xn[q];
-      p[ia + q] = pn[q];
+      if (XW) {
+        x[ia + q] = xn[q];
+        p[ia + q] = pn[q];
+      }
       s_out[ia + q] = sn[q];
       u_out[ia + q] = un[q];
       w_out[ia + q] = wn[q];
@@ -1002,8 +1030,10 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
         continue;
       }
       const int i = q ? ib : ia;
-      if (XW) x[i] = xn[q];
-      p[i] = pn[q];
+      if (XW) {
+        x[i] = xn[q];
+        p[i] = pn[q];
+      }
       s_out[i] = sn[q];
       u_out[i] = un[q];
       w_out[i] = wn[q];

@@ -143,11 +143,11 @@ def test_cg_launch_classes_and_roofline_byte_models():
             "cg_all_ms": 1.0, "cg_all_rows": 1000.0, "cg_all_nnz": 7000.0}
     r = bench.cg_roofline(prof, "dia", 7)
     assert r["bytes_per_launch_scope_table"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2)
-    assert r["bytes_per_launch_storage_min"] == pytest.approx(((8 * 4 + 72) * 1200 + 4 * 200) / 2)
+    assert r["bytes_per_launch_storage_min"] == pytest.approx(((8 * 4 + 68) * 1200 + 4 * 200) / 2)
     assert r["achieved"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2e-3 / 1e9)
     assert r["listed"]["launches"] == 1 and r["all_rows"]["rows_per_launch"] == 1000.0
     c = bench.cg_roofline(prof, "csr", 0)
-    assert c["bytes_per_launch_storage_min"] == pytest.approx((12 * 8400 + 76 * 1200 + 4 * 200) / 2)
+    assert c["bytes_per_launch_storage_min"] == pytest.approx((12 * 8400 + 72 * 1200 + 4 * 200) / 2)
     t = bench.add_traffic(dict(r), {"all": 50.0, "listed": 20.0, "all_rows": 100.0}, prof)
     assert t["traffic"] == pytest.approx(60.0) and t["listed"]["traffic"] == 20.0
     assert t["frac_measured"] == pytest.approx(120.0 / 2e-3 / 1e9 / 8000.0)
