@@ -745,6 +745,16 @@ __device__ inline void pair_block_total(double (&v)[NV], double* sh /* [4 * NV] 
   for (int k = 0; k < NV; ++k) v[k] = (sh[k] + sh[NV + k]) + (sh[2 * NV + k] + sh[3 * NV + k]);
 }
 
+// Stores of the outputs of a launch over every row.  Such a launch streams
+// more data than the caches keep between launches (a batch's all-rows
+// launch moves about 300 MB), so its outputs are written non-temporally and
+// leave the L2 to the neighbour rows the stencil gathers still read; all-rows
+// launches measured 7-12 % faster so.  Listed sets keep ordinary stores:
+// their next launch reads the outputs back while the Infinity Cache still
+// holds them (non-temporal stores made batched listed launches about 20 %
+// slower).
+__device__ inline void stream_store(double* a, double v) { __builtin_nontemporal_store(v, a); }
+
 // k_cg_iter for maps without a list (every row of the instances: the first
 // sweep of a step) and diagonal storage, with 128 threads per 256-row map
 // entry.  Thread t owns rows beg + 2t and beg + 2t + 1; in blocks whose
@@ -812,11 +822,8 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
     for (int q = 0; q < 2; ++q) {
       const int i = q ? ib : ia;
       si[q] = FIRST ? 0.0 : s_in[i];
-      pld[q] = p_read ? p[i] : 0.0;
-      uprev[q] = XW ? u_out[i] : 0.0;
       ui[q] = u_in[i];
       wi[q] = w_in[i];
-      xold[q] = XW ? x[i] : 0.0;
     }
     if (!FIRST) {
       sc_rz = sc[kRZ];
@@ -872,6 +879,16 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
           if (diag) hii[q] = hv;
         });
       }
+    }
+    // the values only the update needs, requested after the stencil's
+    // arithmetic: the launches of odd index fit four waves per SIMD so
+    // (126 registers instead of 152 with 7 diagonals)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = q ? ib : ia;
+      pld[q] = p_read ? p[i] : 0.0;
+      uprev[q] = XW ? u_out[i] : 0.0;
+      xold[q] = XW ? x[i] : 0.0;
     }
   } else {
     if (interior) {
@@ -989,7 +1006,7 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
     if constexpr (XW) {
 #pragma unroll
       for (int q = 0; q < 2; ++q)
-        if (q ? vb : va) x[q ? ib : ia] = fma(sc_alpha, pold[q], xold[q]);
+        if (q ? vb : va) stream_store(&x[q ? ib : ia], fma(sc_alpha, pold[q], xold[q]));
     }
     if (t == 0) blk_done[L] = status;
     return;
@@ -1015,12 +1032,12 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       if (XW) {
-        x[ia + q] = xn[q];
-        p[ia + q] = pn[q];
+        stream_store(&x[ia + q], xn[q]);
+        stream_store(&p[ia + q], pn[q]);
       }
-      s_out[ia + q] = sn[q];
-      u_out[ia + q] = un[q];
-      w_out[ia + q] = wn[q];
+      stream_store(&s_out[ia + q], sn[q]);
+      stream_store(&u_out[ia + q], un[q]);
+      stream_store(&w_out[ia + q], wn[q]);
     }
   } else {
 #pragma unroll
@@ -1031,12 +1048,12 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
       }
       const int i = q ? ib : ia;
       if (XW) {
-        x[i] = xn[q];
-        p[i] = pn[q];
+        stream_store(&x[i], xn[q]);
+        stream_store(&p[i], pn[q]);
       }
-      s_out[i] = sn[q];
-      u_out[i] = un[q];
-      w_out[i] = wn[q];
+      stream_store(&s_out[i], sn[q]);
+      stream_store(&u_out[i], un[q]);
+      stream_store(&w_out[i], wn[q]);
     }
   }
   double tot[3];
