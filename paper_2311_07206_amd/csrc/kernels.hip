@@ -880,16 +880,6 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
         });
       }
     }
-    // the values only the update needs, requested after the stencil's
-    // arithmetic: the launches of odd index fit four waves per SIMD so
-    // (126 registers instead of 152 with 7 diagonals)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int i = q ? ib : ia;
-      pld[q] = p_read ? p[i] : 0.0;
-      uprev[q] = XW ? u_out[i] : 0.0;
-      xold[q] = XW ? x[i] : 0.0;
-    }
   } else {
     if (interior) {
       // both rows valid, ib = ia + 1, every column inside the instance
@@ -915,11 +905,8 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         si[q] = FIRST ? 0.0 : s_in[ia + q];
-        pld[q] = p_read ? p[ia + q] : 0.0;
-        uprev[q] = XW ? u_out[ia + q] : 0.0;
         ui[q] = u_in[ia + q];
         wi[q] = w_in[ia + q];
-        xold[q] = XW ? x[ia + q] : 0.0;
       }
     } else {
 #pragma unroll
@@ -932,11 +919,8 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
           if (diag) hii[q] = hv;
         });
         si[q] = FIRST ? 0.0 : s_in[i];
-        pld[q] = p_read ? p[i] : 0.0;
-        uprev[q] = XW ? u_out[i] : 0.0;
         ui[q] = u_in[i];
         wi[q] = w_in[i];
-        xold[q] = XW ? x[i] : 0.0;
       }
     }
     if (!FIRST) {
@@ -969,6 +953,24 @@ void k_cg_iter2(int32_t* __restrict__ blk_done,
       for (int k = 0; k < 3; ++k) acc[k] = pa[0][k] + pa[1][k];
       pair_block_total<3>(acc, sh_in);
     }
+  }
+  // The values only the update needs (x, p and the previous residual, read
+  // by launches of odd index) are requested after the stencil's arithmetic;
+  // the barrier keeps the compiler from hoisting them.  Those launches then
+  // fit four waves per SIMD with 7 diagonals (106 or 126 registers instead
+  // of 152) and two with 19 (249 instead of 341).
+  if constexpr (XW) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = q ? ib : ia;
+      pld[q] = p_read ? p[i] : 0.0;
+      uprev[q] = u_out[i];
+      xold[q] = x[i];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) pld[q] = uprev[q] = xold[q] = 0.0;
   }
   const double gamma = acc[0], delta = acc[1], rr = acc[2];
   double alpha, beta, bb;
