@@ -248,7 +248,13 @@ int sdc_get_system(sdc_ctx* ctx, int32_t* rowptr, int32_t* col, double* val, dou
 /* ---- time stepping (paper Sec. 3, eq. final-sdc; Sec. 4.2) ------------- */
 
 /* One SDC step: (v, w) at time t -> (v, w) at t + dt, in place.  v, w are
- * device double[N].  stats (host, may be NULL) receives per-sweep counts. */
+ * device double[N].  stats (host, may be NULL) receives per-sweep counts.
+ * The CG solves run with iteration budgets predicted from the last step's
+ * counts, one host synchronisation per sweep; a budget that falls short
+ * redoes the step with the synchronous loop (the same results).  A step
+ * whose t does not continue the last step begun (t != t_last + dt: the
+ * first step, a restart from a checkpoint, a window run again) takes the
+ * synchronous loop at once. */
 int sdc_step(sdc_ctx* ctx, double* v, double* w, double t, sdc_step_stats* stats);
 
 /* The same step in parts: begin (stimulus, spread, all rows active), then

@@ -91,9 +91,12 @@ int record_step(sdc_ctx* ctx, int slot, const double* v, const double* w, double
   const int64_t N = ctx->N;
   const size_t MN = static_cast<size_t>(M) * N;
   TRY(sdc_begin_step(ctx, v, w, t));
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  // predicted budgets when t continues the last step begun, else (the first
+  // step of a segment recomputed from its checkpoint) the synchronous loop
+  const int first = ctx->t_jump ? 1 : 0;
+  for (int attempt = first; attempt < 2; ++attempt) {
     const bool async = attempt == 0;
-    if (!async) TRY(restart_step(ctx));
+    if (attempt > first) TRY(restart_step(ctx));
     bool short_budget = false;
     for (int k = 0; k < K && !short_budget; ++k) {
       const MapBuf& mb = ctx->curmap();

@@ -1395,6 +1395,9 @@ int sdc_begin_step(sdc_ctx* ctx, const double* v, const double* w, double t) {
   TRY(check_ready(ctx));
   if (!v || !w) return fail(ctx, SDC_ERR_ARG, "null state");
   const int64_t N = ctx->N;
+  ctx->t_jump = !(ctx->t_known && std::fabs(t - ctx->t_next) <= 1e-6 * ctx->prm.dt);
+  ctx->t_next = t + ctx->prm.dt;
+  ctx->t_known = true;
   HIPC(hipMemcpyAsync(ctx->v0, v, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
   HIPC(hipMemcpyAsync(ctx->w0, w, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
   for (const auto& s : ctx->stims)
@@ -1425,8 +1428,11 @@ int sdc_end_step(sdc_ctx* ctx, double* v, double* w) {
 
 int sdc_step(sdc_ctx* ctx, double* v, double* w, double t, sdc_step_stats* stats) {
   TRY(sdc_begin_step(ctx, v, w, t));
-  int first = 0;
-  if (ctx->graph_usable()) {
+  // a step that does not continue the last one takes the synchronous loop
+  // at once (its budget history belongs to another time)
+  int first = ctx->t_jump ? 1 : 0;
+  bool fresh = true;   // the step state is still as sdc_begin_step left it
+  if (!ctx->t_jump && ctx->graph_usable()) {
     // graph-captured sweeps: one synchronisation per step; a short budget
     // redoes the step with the synchronous CG loop below
     bool short_budget = false;
@@ -1438,16 +1444,18 @@ int sdc_step(sdc_ctx* ctx, double* v, double* w, double t, sdc_step_stats* stats
     if (!short_budget) return sdc_end_step(ctx, v, w);
     ++ctx->graph_redone;
     first = 1;
+    fresh = false;
   }
   // fast path: predicted CG budgets, one synchronisation per sweep; if a
   // budget was short, redo the step from its saved start state with the
   // synchronous CG loop (identical results, exact iteration counts)
   for (int attempt = first; attempt < 2; ++attempt) {
     const bool async = attempt == 0;
-    if (!async) {
+    if (!fresh) {
       ++ctx->redone_steps;
       TRY(restart_step(ctx));
     }
+    fresh = false;
     if (stats) std::memset(stats, 0, sizeof *stats);
     bool short_budget = false;
     for (int k = 0; k < ctx->prm.K; ++k) {

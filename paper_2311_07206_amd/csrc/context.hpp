@@ -197,6 +197,14 @@ struct sdc_ctx {
   int32_t* hist_done = nullptr;    // [M][n_inst]
   int32_t* hist_iters = nullptr;   // [M][n_inst]
   int64_t redone_steps = 0;
+  // Time of the step that would continue the last one begun (t + dt), and
+  // whether the current step's t differs from it (the first step, a restart
+  // from a checkpoint, a window run again): the CG budgets predicted from
+  // the last step's iteration counts then belong to another time, and the
+  // step takes the synchronous CG loop instead of risking a redo.
+  double t_next = 0.0;
+  bool t_known = false;
+  bool t_jump = true;
   // energy-norm termination (prm.tol_sdc > 0)
   double* e_part = nullptr;        // [M][nblk of all] per-block energies of the sweep
   double* inst_energy = nullptr;   // [n_inst]

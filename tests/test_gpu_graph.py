@@ -7,8 +7,8 @@ Checked against host-launched steps with the same CG launches
 states bitwise equal after every step and the same per-sweep statistics, on
 1D, 2D, 3D, batched and non-adaptive runs.  Every step after the first
 capture replays the graphs, with the host's own work and synchronisations
-between replays; the first steps take the fallback (budgets from the
-default prediction are short) and later ones the graphs.
+between replays; the first step takes the synchronous loop (no budget
+history yet), and later ones the graphs.
 """
 import numpy as np
 import pytest
