@@ -1418,24 +1418,65 @@ __global__ __launch_bounds__(kBlock) void k_zero_rows(Map map, ZeroVecs zv) {
     }
 }
 
-// Work map of an ascending list: instance i's entries are those in
-// [node_off[i], node_off[i+1]); found by binary search.  One block.
-__global__ __launch_bounds__(kScanThreads) void k_map_from_list(const int32_t* __restrict__ idx,
-                                                                int32_t n, int64_t N, int n_inst,
-                                                                const int32_t* __restrict__ rowptr,
-                                                                NextMap nm) {
-  int32_t* aoff_scratch = nm.aoff;
-  const int64_t* node_off = nm.node_off;
-  // validate: entries in [0, N) and strictly ascending; a bad list gives an
-  // empty map and totals[2] = 1, so no later kernel indexes with it
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
+// Work map of an ascending list, in three launches: k_list_prep clears the
+// counters, k_list_scan validates the list and counts each instance's stored
+// entries (one thread per entry), k_map_from_list (one block) finds the
+// instances' ranges and builds the map.
+__global__ __launch_bounds__(kBlock) void k_list_prep(int n_inst, NextMap nm) {
+  for (int i = threadIdx.x; i < n_inst; i += kBlock) nm.inst_nnz[i] = 0;
+  if (threadIdx.x == 0) nm.totals[2] = 0;
+}
+
+// Entry q is valid when it lies in [0, N) and above entry q - 1; any other
+// entry marks the list invalid (totals[2] = 1, the same value from every
+// writer).  A valid entry's row adds its stored entries of A to the count of
+// its instance (the last i with node_off[i] <= row).  In a valid list the
+// instances of a block's entries are consecutive: they are summed in LDS
+// bins from the block's first instance and added with one atomic each
+// (integer sums, so the order of the additions does not matter).
+__global__ __launch_bounds__(kBlock) void k_list_scan(const int32_t* __restrict__ idx, int32_t n, int64_t N,
+                                                      int n_inst, const int32_t* __restrict__ rowptr,
+                                                      NextMap nm) {
+  __shared__ unsigned long long bins[kBlock];
+  __shared__ int first;
+  const int q = static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+  bins[threadIdx.x] = 0;
+  const bool live = q < n;
+  const int32_t v = live ? idx[q] : 0;
+  const bool ok = live && v >= 0 && v < N && (q == 0 || idx[q - 1] < v);
+  if (live && !ok) nm.totals[2] = 1;
+  int inst = -1;
+  if (ok) {
+    int lo = 0, hi = n_inst;   // node_off[lo] <= v < node_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (nm.node_off[mid] <= v) lo = mid; else hi = mid;
+    }
+    inst = lo;
+  }
+  if (threadIdx.x == 0) first = inst;
   __syncthreads();
-  for (int q = threadIdx.x; q < n; q += kScanThreads) {
-    const int32_t v = idx[q];
-    if (v < 0 || v >= N || (q > 0 && idx[q - 1] >= v)) bad = 1;
+  const int k = inst - first;
+  if (inst >= 0) {
+    const auto z = static_cast<unsigned long long>(rowptr[v + 1] - rowptr[v]);
+    if (first >= 0 && k >= 0 && k < kBlock) atomicAdd(&bins[k], z);
+    else atomicAdd(reinterpret_cast<unsigned long long*>(&nm.inst_nnz[inst]), z);
   }
   __syncthreads();
+  const int i = first + static_cast<int>(threadIdx.x);
+  if (first >= 0 && i < n_inst && bins[threadIdx.x])
+    atomicAdd(reinterpret_cast<unsigned long long*>(&nm.inst_nnz[i]), bins[threadIdx.x]);
+}
+
+// Instance i's entries of the list are those in [node_off[i],
+// node_off[i+1]), found by binary search; then the map.  One block.  An
+// invalid list (totals[2] from k_list_scan) gives an empty map and keeps
+// totals[2] = 1, so no later kernel indexes with it.
+__global__ __launch_bounds__(kScanThreads) void k_map_from_list(const int32_t* __restrict__ idx,
+                                                                int32_t n, int n_inst, NextMap nm) {
+  int32_t* aoff_scratch = nm.aoff;
+  const int64_t* node_off = nm.node_off;
+  const bool bad = nm.totals[2] != 0;
   if (bad) n = 0;
   for (int i = threadIdx.x; i <= n_inst; i += kScanThreads) {
     const int64_t key = node_off[i];
@@ -1449,16 +1490,7 @@ __global__ __launch_bounds__(kScanThreads) void k_map_from_list(const int32_t* _
   __syncthreads();
   for (int i = threadIdx.x; i < n_inst; i += kScanThreads) {
     nm.inst_cnt[i] = aoff_scratch[i + 1] - aoff_scratch[i];
-    nm.inst_nnz[i] = 0;
-  }
-  __syncthreads();
-  // stored entries per instance (integer sums, order-independent)
-  for (int i = 0; i < n_inst; ++i) {
-    int64_t z = 0;
-    for (int q = aoff_scratch[i] + threadIdx.x; q < aoff_scratch[i + 1]; q += kScanThreads)
-      z += rowptr[idx[q] + 1] - rowptr[idx[q]];
-    if (z) atomicAdd(reinterpret_cast<unsigned long long*>(&nm.inst_nnz[i]),
-                     static_cast<unsigned long long>(z));
+    if (bad) nm.inst_nnz[i] = 0;
   }
   __syncthreads();
   const bool fits = build_map(nm.inst_cnt, aoff_scratch, n_inst, nm, n);
@@ -2005,7 +2037,11 @@ void launch_zero_rows(hipStream_t s, const Map& map, const ZeroVecs& zv) {
 
 void launch_map_from_list(hipStream_t s, const int32_t* idx, int64_t n, int64_t N, int n_inst,
                           const int32_t* rowptr, const NextMap& nm, int32_t* idx_pad) {
-  k_map_from_list<<<1, kScanThreads, 0, s>>>(idx, static_cast<int32_t>(n), N, n_inst, rowptr, nm);
+  k_list_prep<<<1, kBlock, 0, s>>>(n_inst, nm);
+  if (n > 0)
+    k_list_scan<<<dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
+        idx, static_cast<int32_t>(n), N, n_inst, rowptr, nm);
+  k_map_from_list<<<1, kScanThreads, 0, s>>>(idx, static_cast<int32_t>(n), n_inst, nm);
   if (n > 0)
     k_pad_list<<<dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
         idx, static_cast<int32_t>(n), n_inst, nm, idx_pad);

@@ -492,3 +492,36 @@ def test_invalid_index_lists_are_rejected():
     # a good call still works afterwards
     x, it = s.solve(0, torch.arange(P.N, dtype=torch.int32, device=DEV), b)
     assert it[0] > 0 and torch.isfinite(x).all()
+
+
+def test_list_maps_count_stored_entries_and_reject_bad_lists():
+    """Work maps built from a device list (pinned sets, restricted solves):
+    the stored entries of a pinned sweep are those of the listed rows of A,
+    with lists whose 256-entry blocks span several instances and instances
+    without entries; a list out of order, with a repeated entry, or with an
+    entry outside [0, N) is rejected."""
+    from paper_2311_07206_amd import SDCError
+    P = config4(n_inst=7, sizes=(12, 30))
+    s = _solver(P)
+    rp = s.system()[0]
+    rng = np.random.default_rng(3)
+    parts = []
+    for i in (0, 2, 3, 6):
+        lo, hi = int(P.node_off[i]), int(P.node_off[i + 1])
+        parts.append(np.sort(rng.choice(np.arange(lo, hi), size=min(90, hi - lo), replace=False)))
+    idx = np.concatenate(parts).astype(np.int32)
+    print(f"[list maps] {idx.size} rows over instances 0, 2, 3, 6", flush=True)
+    s.set_active(1, torch.tensor(idx, device=DEV))
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    st = s.step(v, w, 0.0, stats=True)
+    s.set_active(0, None)
+    assert st[1]["n_active"] == idx.size
+    assert st[1]["nnz_active"] == int(np.sum(rp[idx + 1] - rp[idx]))
+    b = torch.ones(P.N, dtype=torch.float64, device=DEV)
+    x, _ = s.solve(0, torch.tensor(idx, device=DEV), b)
+    assert torch.all(x[torch.tensor(idx, device=DEV).long()] != 0)
+    for bad in (idx[::-1], np.r_[idx[:5], idx[4], idx[5:]], np.r_[idx, P.N], np.r_[-1, idx]):
+        with pytest.raises(SDCError, match="ascending"):
+            s.solve(0, torch.tensor(bad.astype(np.int32), device=DEV), b)
+    s.close()
