@@ -562,8 +562,9 @@ def adjoint_ratio(P, s, nsteps=100, ckpt=10):
     0.5 ||v(T) - v_target||^2 with respect to the nodal conductivity and each
     instance's Aliev-Panfilov a, v_target from a forward run of the same
     steps with the seeded perturbed conductivity (the workload's target).
-    Ratio = backward wall time (checkpoint recomputation included) / forward
-    wall time."""
+    Ratio = backward wall time (checkpoint recomputation and the first
+    allocation of the recording slots included) / forward wall time; the
+    loss expression's torch kernels run once untimed before the backward."""
     import torch
 
     from paper_2311_07206_amd import Solver
@@ -589,6 +590,11 @@ def adjoint_ratio(P, s, nsteps=100, ckpt=10):
     sync()
     tf = time.perf_counter() - t
     loss = 0.5 * ((vT - vt) ** 2).sum()
+    # the loss's own backward kernels, once untimed: their first launch loads
+    # code that is no part of the reverse pass (about 0.2 s on the 48-instance
+    # workload); the library's first-call costs stay in the timing
+    zv = torch.zeros_like(vT, requires_grad=True)
+    (0.5 * ((zv - vt) ** 2).sum()).backward()
     sync()
     t = time.perf_counter()
     loss.backward()
