@@ -172,7 +172,7 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     const CgState& cg, double* tot, bool pair_all = true,
                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 constexpr int kTotBlocks = 4 * kBlock;
-constexpr int kTotMapBlocks = 4096;
+constexpr int kTotMapBlocks = 2048;
 constexpr int kTotMinBlocks = 64;
 // The whole restricted PCG of each instance in one workgroup of kWgThreads
 // threads, rows_per_thread (1 or 2) rows each, for maps whose instances hold
