@@ -9,8 +9,10 @@ Jacobi-PCG to rtol 1e-12 (synthetic seeded inputs).  A "step" is one SDC
 time step of every instance: K sweeps, each with M restricted solves per
 instance, the reaction and the active-set selection.  `--warmup` steps run
 first from t = 0 (the stimulus), then exactly `--steps` steps are timed with
-the device synchronised on both sides; the timed window is repeated
-`--repeats` times from the same state and the median repeat is reported.
+the device synchronised on both sides (by default 5 and 95: the timed steps
+are the rest of the workload's 100-step run, t = 1..20 ms); the timed
+window is repeated `--repeats` times from the same state and the median
+repeat is reported.
 
 Reported value: active dof-sweeps per second = sum over the window's steps
 and sweeps of the active rows, divided by its wall time.  The roofline
@@ -23,7 +25,9 @@ storage must move, and HBM traffic from committed rocprofv3 counters.  The
 adjoint/forward ratio is the reverse pass of 100 steps (checkpoint every
 10) over the forward pass of the same steps.  The CPU baseline is the FP64
 oracle on one host core over the first step(s) of the same window.  Further
-legs: the 2D 512^2 and 3D 128^3 single-instance workloads and the
+legs: the 2D 512^2 and 3D 128^3 single-instance workloads (a window of
+their early steps with its variants, and their whole runs, T = 200 and 400
+ms, with windows at fixed times and the oracle on the same steps) and the
 cell-by-cell workloads.
 """
 import argparse
@@ -41,8 +45,26 @@ HBM_PEAK_GBS = 8000.0
 # wall-clock speedups of adaptive over non-adaptive SDC that the paper
 # reports on CPUs (Kaskade 7; 2D: Core i7-9700T, 3D: Xeon E5), for context
 PAPER_SPEEDUP = {"2d_monodomain": 2.13, "2d_emi": 3.336, "3d_monodomain": 3.29, "3d_emi": 4.344}
+# snapshot times (ms) of the whole runs: the first steps, and the front at
+# 10, 50 and 150 ms; in 3D also the second stimulus at 120 ms (colliding fronts)
+FULL_RUN_SNAPSHOTS_2D = (0.0, 10.0, 50.0, 150.0)
+FULL_RUN_SNAPSHOTS_3D = (0.0, 10.0, 50.0, 120.0, 150.0)
 COUNTERS = os.path.join(ROOT, "profiles", "k_cg_iter_batched48_counters.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2311_07206_amd", "csrc", "kernels.hip")
+COUNTERS_3D = os.path.join(ROOT, "profiles", "k_cg_iter2_3d128.md")
+# the device kernels and their launch constants: counter summaries name the
+# hash of these files, and their bytes are used only while it still matches
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2311_07206_amd", "csrc", f)
+               for f in ("kernels.hip", "kernels.hpp", "device.hpp")]
+
+
+def kernel_sources_sha():
+    """sha256 over the kernel source files, in the order of KERNEL_SRCS."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(path=None):
@@ -50,15 +72,13 @@ def measured_traffic(path=None):
     WRITE_SIZE runs, as a dict with "all" and, when the summary has them,
     "listed" and "all_rows" launches; None when the kernel source changed
     since the counters were taken."""
-    import hashlib
     try:
         text = open(path or COUNTERS).read()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
     fields = {k[2:].strip(): v.strip() for k, v in fields.items()}
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if fields.get("kernels.hip sha256") != src:
+    if fields.get("kernel sources sha256") != kernel_sources_sha():
         return None
     out = {"all": float(fields["measured bytes per launch"])}
     for key, name in (("listed", "measured bytes per listed launch"),
@@ -172,7 +192,8 @@ def summarize_counters(fetch_csv, write_csv, min_blocks=0):
     out = {"copy_fetch_kib": [c[0] for c in copy], "copy_write_kib": [c[1] for c in copy],
            "fetch_factor": ff, "write_factor": fw, "dispatches": int(len(cg_f)), "updating": int(work.sum()),
            "fetch_kib_per_launch": fetch_kib, "write_kib_per_launch": write_kib,
-           "measured_bytes_per_launch": (ff * fetch_kib + fw * write_kib) * 1024.0}
+           "measured_bytes_per_launch": (ff * fetch_kib + fw * write_kib) * 1024.0,
+           "kernel_sources_sha256": kernel_sources_sha()}
     for c in ("listed", "all_rows"):
         sel = work & (cls == c)
         if sel.any():
@@ -214,7 +235,8 @@ def summarize_pmc(path):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20, help="timed steps of the batched workload")
+    ap.add_argument("--steps", type=int, default=95,
+                    help="timed steps of the batched workload (default: the rest of its 100-step run)")
     ap.add_argument("--warmup", type=int, default=5, help="untimed steps from t = 0 before the window")
     ap.add_argument("--repeats", type=int, default=5, help="repeats of the timed window (median reported)")
     ap.add_argument("--headline-only", action="store_true",
@@ -245,6 +267,11 @@ def parse():
                     help="skip the runs with the energy-error CG stop (the paper's 1e-3)")
     ap.add_argument("--small-set-rows", type=int, default=0,
                     help="the latency curve's solver option (0: default one-launch solves of small sets, -1: off)")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip the whole runs of the 2D and 3D workloads (T = 200 and 400 ms) and their windows")
+    ap.add_argument("--full-window", type=int, default=5, help="steps of each window of the whole runs")
+    ap.add_argument("--full-oracle-steps", type=int, default=1,
+                    help="oracle steps at the start of each window of the whole runs (0: none)")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the time-per-sweep curve over front-shell active sets")
     ap.add_argument("--calib", action="store_true",
@@ -280,7 +307,11 @@ def cg_roofline(prof, storage, n_diag, peak=None):
       direction p read and written every other launch, with u read a second
       time there to rebuild it (12 B a launch): 68 B (dinv is formed from the
       diagonal), plus the list entry;
-    achieved: scope_table bytes / mean launch duration (the reported frac).
+    achieved: storage_min bytes / mean launch duration (the reported frac):
+      the scope table's count is written for CSR storage (a column index
+      and the full row per entry) and exceeds what the symmetric diagonal
+      storage moves, so its rate can pass the HBM peak; it is reported
+      beside (scope_table_GBps, frac_scope_table).
     """
     peak = peak or HBM_PEAK_GBS
     L, ms = prof["cg_launches"], prof["cg_ms"]
@@ -293,11 +324,11 @@ def cg_roofline(prof, storage, n_diag, peak=None):
         b_min = 12.0 * nnz + 72.0 * rows + 4.0 * listed_rows
     sec = ms * 1e-3
     out = {"kernel": "k_cg_iter (all CG-iteration launches: listed sets k_cg_iter, every row k_cg_iter2)",
-           "bound": "hbm", "achieved": b_scope / sec / 1e9, "peak": peak, "unit": "GB/s",
-           "frac": b_scope / sec / 1e9 / peak, "traffic": None,
+           "bound": "hbm", "achieved": b_min / sec / 1e9, "peak": peak, "unit": "GB/s",
+           "frac": b_min / sec / 1e9 / peak, "traffic": None,
            "avg_launch_us": 1e3 * ms / L, "launches": L,
-           "bytes_per_launch_scope_table": b_scope / L, "bytes_per_launch_storage_min": b_min / L,
-           "storage_min_GBps": b_min / sec / 1e9, "frac_storage_min": b_min / sec / 1e9 / peak,
+           "bytes_per_launch_storage_min": b_min / L, "bytes_per_launch_scope_table": b_scope / L,
+           "scope_table_GBps": b_scope / sec / 1e9, "frac_scope_table": b_scope / sec / 1e9 / peak,
            "rows_per_launch": rows / L}
     for cls, launches, lms, lrows, lnnz, listed in (
             ("all_rows", prof["cg_all_launches"], prof["cg_all_ms"], prof["cg_all_rows"], prof["cg_all_nnz"], 0.0),
@@ -309,8 +340,8 @@ def cg_roofline(prof, storage, n_diag, peak=None):
         bm = ((8.0 * (n_diag // 2 + 1) + 68.0) * lrows if storage == "dia" else 12.0 * lnnz + 72.0 * lrows) \
             + 4.0 * listed * lrows
         out[cls] = {"launches": launches, "avg_launch_us": 1e3 * lms / launches, "rows_per_launch": lrows / launches,
-                    "scope_table_GBps": bs / (lms * 1e-3) / 1e9, "frac": bs / (lms * 1e-3) / 1e9 / peak,
-                    "storage_min_GBps": bm / (lms * 1e-3) / 1e9, "frac_storage_min": bm / (lms * 1e-3) / 1e9 / peak}
+                    "storage_min_GBps": bm / (lms * 1e-3) / 1e9, "frac": bm / (lms * 1e-3) / 1e9 / peak,
+                    "scope_table_GBps": bs / (lms * 1e-3) / 1e9, "frac_scope_table": bs / (lms * 1e-3) / 1e9 / peak}
     return out
 
 
@@ -384,23 +415,42 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU (the library is single-device); --gpus must be 1"}))
         sys.exit(2)
+    t_run = time.perf_counter()
+
+    def done(leg):
+        # one line per finished leg on stderr (the JSON line stays alone on stdout)
+        print(f"[bench] {leg} done at {time.perf_counter() - t_run:.0f} s", file=sys.stderr, flush=True)
+
     out, window = ({}, None) if args.no_headline else headline(args)
+    done("batched workload")
     if not args.headline_only:
         out["copy_GBps"] = copy_bandwidth()
         if "roofline" in out:
             out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / out["copy_GBps"]
         if not args.no_2d:
             out["workload_2d"] = workload_2d(args)
+            done("2D workload")
         if not args.no_3d:
             out["workload_3d"] = workload_3d(speedup=not args.no_speedup, first_sweep=not args.no_first_sweep,
                                              cg_energy=not args.no_cg_energy,
                                              variants=not args.no_storage_variants, calib=args.calib,
                                              repeats=args.repeats)
+            done("3D workload window")
+            if not args.no_full_run:
+                from workloads import config2
+                # the 3D oracle takes about 50 s to build and 18 s per step on
+                # one core: it runs the window of the second stimulus only
+                out["workload_3d"]["full_run"] = full_run(config2(), FULL_RUN_SNAPSHOTS_3D, args.full_window,
+                                                          args.repeats, args.full_oracle_steps,
+                                                          cpu=args.full_oracle_steps > 0, oracle_at=(120.0,))
+                done("3D whole run")
         if not args.no_emi:
             out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
             out["workload_emi_3d"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, three_d=True)
+            done("cell-by-cell workloads")
     if not args.no_cpu and not args.headline_only and window is not None:
         out["cpu_baseline"] = cpu_baseline(*window, args.cpu_sample_steps, args.steps)
+        done("CPU baseline")
     print(json.dumps(out), flush=True)
 
 
@@ -672,6 +722,10 @@ def workload_2d(args):
         out["linearized"] = workload_linearized(P, v_start, w_start, t_start, nsteps, speedup=not args.no_speedup)
     if not args.no_latency:
         out["latency_curve"] = latency_curve(P, small_set_rows=args.small_set_rows)
+    if not args.no_full_run:
+        out["full_run"] = full_run(config1(n=args.n, theta=1e-7), FULL_RUN_SNAPSHOTS_2D, args.full_window,
+                                   args.repeats, args.full_oracle_steps, cpu=args.full_oracle_steps > 0,
+                                   nonadaptive=not args.no_speedup)
     return out
 
 
@@ -749,15 +803,17 @@ def latency_curve(P, snapshots=(10.0, 50.0, 150.0), densities=(1.0, 0.5, 0.1, 0.
             s.profile(False)
             s.set_active(0, None)
             nl = pr["cg_launches"] - pr["cg_all_launches"]
-            cg_ms, cg_b = pr["cg_ms"] - pr["cg_all_ms"], pr["cg_bytes"] - pr["cg_all_bytes"]
+            cg_ms = pr["cg_ms"] - pr["cg_all_ms"]
             row = {"density": d, "n_active": int(idx.size), "ms_per_sweep": float(np.median(ms)),
                    "cg_iterations_per_sweep": float(np.mean(iters)),
                    "sweep_us_per_cg_iteration": 1e3 * float(np.mean(ms)) / max(float(np.mean(iters)), 1.0),
                    "algorithmic_GBps": float(np.mean(nbytes)) / float(np.mean(ms)) / 1e6,
                    "first_sweep_ms": float(np.median(first))}
-            if nl > 0:
-                row["cg_launch_us"] = 1e3 * cg_ms / nl
-                row["cg_launch_GBps"] = cg_b / (cg_ms * 1e-3) / 1e9
+            if nl > 0 and cg_ms > 0:
+                info = s.info()
+                lr = cg_roofline(pr, info["format"], info["n_diagonals"])["listed"]
+                row["cg_launch_us"] = lr["avg_launch_us"]
+                row["cg_launch_GBps"] = lr["storage_min_GBps"]
             rows.append(row)
         out.append({"t_ms": t_snap, "selected_n_active": [st["n_active"] for st in sel], "masks": rows})
     redone = s.info()["redone_steps"] - redone0
@@ -866,6 +922,95 @@ def cg_energy_variant(P, v0, w0, t0, nsteps, ms_std, v_std, v_non=None, tol=1e-3
     return out
 
 
+def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_at=None, nonadaptive=False):
+    """The workload's whole run from t = 0 (every step of its schedule, all
+    stimuli), timed as one pass with the device synchronised at its ends.
+    Windows of `window` steps starting at the snapshot times are then timed
+    `repeats` times each (median reported), each repeat from the state the
+    whole run had one step earlier and that step run untimed first, so that
+    the timed steps continue their predecessor as in the whole run.  With
+    `cpu`, the oracle runs the first `oracle_steps` steps of each window (of
+    those starting at the times `oracle_at`, default all) from the same state
+    on one core, beside the GPU's median time for the same steps: both rates
+    over identical steps.  With `nonadaptive`, the whole run is timed again
+    with theta = 0: the speedup over the whole run, as the paper reports
+    its speedups, and the distance of the two final potentials."""
+    import torch
+
+    from paper_2311_07206_amd import Solver
+    dev = torch.device("cuda", 0)
+    sync = torch.cuda.synchronize
+    s = Solver.from_problem(P)
+    v = torch.tensor(P.v_init, device=dev)
+    w = torch.tensor(P.w_init, device=dev)
+    starts = sorted({min(P.n_steps - window, int(round(t / P.dt))) for t in snap_ms})
+    saved = {max(0, n0 - 1) for n0 in starts}
+    snaps, dofs = {}, 0
+    sync()
+    t = time.perf_counter()
+    for n in range(P.n_steps):
+        if n in saved:
+            snaps[n] = (v.clone(), w.clone())
+        dofs += sum(st["n_active"] for st in s.step(v, w, n * P.dt, stats=True))
+    sync()
+    el = time.perf_counter() - t
+    print(f"[bench] {P.name}: whole run of {P.n_steps} steps in {el:.1f} s", file=sys.stderr, flush=True)
+    out = {"steps": P.n_steps, "t_end_ms": P.n_steps * P.dt, "seconds": el, "ms_per_step": 1e3 * el / P.n_steps,
+           "value": dofs / el, "unit": "active dof-sweeps/s",
+           "stimuli_ms": [float(st[0]) for st in P.stimuli], "redone_steps": s.info()["redone_steps"],
+           "windows": []}
+    if nonadaptive:
+        el0, v_non = nonadaptive_run(P, P.v_init, P.w_init, 0.0, P.n_steps, warm_budget=False, return_state=True)
+        v_end = v.cpu().numpy()
+        out["adaptive_vs_nonadaptive"] = {
+            "nonadaptive_seconds": el0, "speedup": el0 / el,
+            "rel_l2_final_v": float(np.linalg.norm(v_end - v_non) / np.linalg.norm(v_non)),
+            "max_abs_final_v": float(np.abs(v_end - v_non).max())}
+        print(f"[bench] {P.name}: non-adaptive whole run in {el0:.1f} s", file=sys.stderr, flush=True)
+    orc = None
+    for n0 in starts:
+        lead = 1 if n0 > 0 else 0
+        times, t_first, logs, state0 = [], [], None, None
+        for _ in range(max(1, repeats)):
+            vv, ww = (x.clone() for x in snaps[n0 - lead])
+            for k in range(lead):   # untimed: the step before the window
+                s.step(vv, ww, (n0 - lead + k) * P.dt)
+            if state0 is None:
+                state0 = (vv.cpu().numpy(), ww.cpu().numpy())
+            sync()
+            t = time.perf_counter()
+            lg = []
+            for k in range(window):
+                lg.append(s.step(vv, ww, (n0 + k) * P.dt, stats=True))
+                if k + 1 == oracle_steps:
+                    sync()
+                    t_first.append(time.perf_counter() - t)
+            sync()
+            times.append(time.perf_counter() - t)
+            logs = logs or lg
+        el_w = float(np.median(times))
+        wd = {"t0_ms": n0 * P.dt, "steps": window, "ms_per_step": 1e3 * el_w / window,
+              "value": sum(st["n_active"] for x in logs for st in x) / el_w,
+              "mean_active_per_sweep": [float(np.mean([x[k]["n_active"] for x in logs])) for k in range(P.K)]}
+        if cpu and (oracle_at is None or any(abs(n0 * P.dt - ta) < 0.5 * P.dt for ta in oracle_at)):
+            from threadpoolctl import threadpool_limits
+
+            from oracle.sdc import build, run
+            orc = orc or build(P)
+            with threadpool_limits(limits=1):
+                t = time.perf_counter()
+                _, _, olog = run(orc, state0[0], state0[1], oracle_steps, P.K, P.stimuli, t0=n0 * P.dt)
+                el_o = time.perf_counter() - t
+            od = sum(info["n_active"] for step in olog for info in step)
+            gd = sum(st["n_active"] for x in logs[:oracle_steps] for st in x)
+            el_g = float(np.median(t_first))
+            wd["oracle"] = {"steps": oracle_steps, "seconds": el_o, "value": od / el_o, "cores": 1,
+                            "gpu_value_same_steps": gd / el_g, "gpu_over_oracle": (gd / el_g) / (od / el_o)}
+        out["windows"].append(wd)
+    s.close()
+    return out
+
+
 def _timed_steps(solver, v, w, t0, dt, n, sync):
     sync()
     t = time.perf_counter()
@@ -942,17 +1087,11 @@ def workload_3d(nsteps=10, warm=10, speedup=True, first_sweep=True, cg_energy=Tr
            "algorithmic_GBps": nbytes / el / 1e9, "storage": s.info(),
            "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)]}
     if prof["cg_launches"]:
-        out["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
-        out["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]
-    if prof["cg_all_launches"]:
-        # the first sweep's launches on all 2.1 M rows (0.4 GB each): beyond the
-        # Infinity Cache, so these time HBM
-        ach = prof["cg_all_bytes"] / (prof["cg_all_ms"] * 1e-3) / 1e9
-        out["roofline_all_rows"] = {
-            "kernel": "k_cg_iter2", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "avg_launch_us": 1e3 * prof["cg_all_ms"] / prof["cg_all_launches"],
-            "bytes_per_launch": prof["cg_all_bytes"] / prof["cg_all_launches"],
-            "launches": prof["cg_all_launches"]}
+        # the first sweep's launches on all 2.1 M rows (0.3 GB each) reach
+        # beyond the Infinity Cache: its all_rows class times HBM
+        info = out["storage"]
+        out["roofline"] = cg_roofline(prof, info["format"], info["n_diagonals"])
+        out["roofline"] = add_traffic(out["roofline"], measured_traffic(COUNTERS_3D), prof)
     s.close()
     v_std, v_non = v.cpu().numpy(), None
     if speedup:
@@ -1020,8 +1159,8 @@ def workload_emi(nsteps=3, warm=1, speedup=True, three_d=False):
            "mean_active_per_sweep": [float(np.mean([lg[k]["n_active"] for lg in logs])) for k in range(P.K)],
            "cg_iters_sweep0": [int(np.max([lg[0]["cg_iters_max"][m] for lg in logs])) for m in range(P.M)]}
     if prof["cg_launches"]:
-        out["k_cg_iter_GBps"] = prof["cg_bytes"] / (prof["cg_ms"] * 1e-3) / 1e9
-        out["k_cg_iter_avg_us"] = 1e3 * prof["cg_ms"] / prof["cg_launches"]
+        info = out["storage"]
+        out["roofline"] = cg_roofline(prof, info["format"], info["n_diagonals"])
     s.close()
     if speedup:
         # solves above the asynchronous budget limit run synchronously, so

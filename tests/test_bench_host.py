@@ -114,23 +114,27 @@ def test_summarize_trace_window_starts_after_the_calibration_copies(tmp_path):
 
 
 def test_measured_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
-    src = tmp_path / "k.hip"
+    src, hdr = tmp_path / "k.hip", tmp_path / "k.hpp"
     src.write_bytes(b"kernel source")
-    sha = hashlib.sha256(b"kernel source").hexdigest()
+    hdr.write_bytes(b"launch constants")
+    sha = hashlib.sha256(b"kernel source" + b"launch constants").hexdigest()
     md = tmp_path / "c.md"
-    md.write_text(f"# x\n\n- kernels.hip sha256: {sha}\n- measured bytes per launch: 90.5\n"
+    md.write_text(f"# x\n\n- kernel sources sha256: {sha}\n- measured bytes per launch: 90.5\n"
                   f"- measured bytes per listed launch: 40.0\n- measured bytes per all-rows launch: 120.0\n")
-    monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
+    monkeypatch.setattr(bench, "KERNEL_SRCS", [str(src), str(hdr)])
     assert bench.measured_traffic(str(md)) == {"all": 90.5, "listed": 40.0, "all_rows": 120.0}
+    hdr.write_bytes(b"launch constants, edited")   # a header edit counts as a kernel change
+    assert bench.measured_traffic(str(md)) is None
+    hdr.write_bytes(b"launch constants")
     src.write_bytes(b"kernel source, edited")
     assert bench.measured_traffic(str(md)) is None
 
 
 def test_committed_counters_name_the_current_kernel_source():
-    """The profile summary bench.py reads carries the hash of kernels.hip as
-    committed; a kernel edit without new counters makes `traffic` null."""
+    """The profile summary bench.py reads carries the hash of the kernel
+    sources; a kernel edit without new counters makes `traffic` null."""
     text = open(bench.COUNTERS).read()
-    assert "kernels.hip sha256:" in text and "measured bytes per launch:" in text
+    assert "kernel sources sha256:" in text and "measured bytes per launch:" in text
 
 
 def test_cg_launch_classes_and_roofline_byte_models():
@@ -144,7 +148,9 @@ def test_cg_launch_classes_and_roofline_byte_models():
     r = bench.cg_roofline(prof, "dia", 7)
     assert r["bytes_per_launch_scope_table"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2)
     assert r["bytes_per_launch_storage_min"] == pytest.approx(((8 * 4 + 68) * 1200 + 4 * 200) / 2)
-    assert r["achieved"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2e-3 / 1e9)
+    assert r["achieved"] == pytest.approx(((8 * 4 + 68) * 1200 + 4 * 200) / 2e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    assert r["scope_table_GBps"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2e-3 / 1e9)
     assert r["listed"]["launches"] == 1 and r["all_rows"]["rows_per_launch"] == 1000.0
     c = bench.cg_roofline(prof, "csr", 0)
     assert c["bytes_per_launch_storage_min"] == pytest.approx((12 * 8400 + 72 * 1200 + 4 * 200) / 2)
