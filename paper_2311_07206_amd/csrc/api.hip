@@ -176,7 +176,10 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
       (*iters)[i] = ctx->h_i32[ni + i];
       mx = std::max(mx, (*iters)[i]);
     }
-    if (pred_slot >= 0) ctx->pred[pred_slot] = mx + 1;
+    if (pred_slot >= 0) {
+      ctx->note_count(pred_slot, mx);
+      ctx->pred[pred_slot] = mx + 1;
+    }
     return SDC_OK;
   }
   launch_cg_start(ctx->stream, map, ni, ctx->N, H, dinv, ctx->r[0], ctx->r[1], ctx->wv[1], ctx->part[0], ctx->cg());
@@ -231,6 +234,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
   if (pred_slot >= 0) {
     int mx = 0;
     for (int v : *iters) mx = std::max(mx, v);
+    ctx->note_count(pred_slot, mx);
     ctx->pred[pred_slot] = mx + 1;
   }
   return SDC_OK;
@@ -264,7 +268,8 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
   const Mat H = ctx->H(m);
   const double* dinv = ctx->dinv + static_cast<int64_t>(m) * ctx->N;
   const CgStop stop = ctx->cg_stop();
-  const int budget = std::min(std::max(1, ctx->pred[pred_slot]) + 1, ctx->prm.cg_maxit + 1);
+  const int p = std::max(1, ctx->pred[pred_slot]);
+  const int budget = std::min(p + ctx->budget_margin(p), ctx->prm.cg_maxit + 1);
   // the kernels record the outcome straight into the node's history slot
   const CgState cg{ctx->hist_done + m * ni, ctx->hist_iters + m * ni, ctx->cg_blk_done};
   if (wg_solve(ctx, mb)) {
@@ -411,10 +416,14 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
         if (d == 3)
           return fail(ctx, SDC_ERR_NONFINITE, "CG: instance %d, node %d, sweep %d: non-finite or non-positive curvature",
                       i, m, ctx->k);
-        if (d == 0 && short_budget) *short_budget = true;
+        if (d == 0) {   // overran its budget: a rise beyond the margin
+          if (short_budget) *short_budget = true;
+          ctx->rise_now = true;
+        }
         mx = std::max(mx, iters[m][i]);
       }
       const int slot = ctx->pred_slot(m);
+      ctx->note_count(slot, mx);
       ctx->pred[slot] = mx + 1;
       if (ev_budget[m] > 0) {
         MapBuf view;
@@ -662,6 +671,7 @@ int graph_step(sdc_ctx* ctx, sdc_step_stats* st, bool* short_budget) {
     for (int m = 0; m < M; ++m) {
       int mx = 0;
       for (int i = 0; i < ni; ++i) mx = std::max(mx, iters[(k * M + m) * ni + i]);
+      ctx->note_count(pred_slot_of(ctx, k, m), mx);
       ctx->pred[pred_slot_of(ctx, k, m)] = mx + 1;
     }
     if (st) {
@@ -1395,6 +1405,9 @@ int sdc_begin_step(sdc_ctx* ctx, const double* v, const double* w, double t) {
   TRY(check_ready(ctx));
   if (!v || !w) return fail(ctx, SDC_ERR_ARG, "null state");
   const int64_t N = ctx->N;
+  // the rise record of the step before (if it continued its predecessor)
+  ctx->rise_steps = (ctx->rise_steps << 1) | (ctx->rise_now ? 1u : 0u);
+  ctx->rise_now = false;
   ctx->t_jump = !(ctx->t_known && std::fabs(t - ctx->t_next) <= 1e-6 * ctx->prm.dt);
   ctx->t_next = t + ctx->prm.dt;
   ctx->t_known = true;

@@ -266,6 +266,22 @@ struct sdc_ctx {
   hipEvent_t sweep_ev[2] = {nullptr, nullptr};   // around a sweep whose statistics are asked for
   sdc_profile_stats pst{};
   std::vector<int> pred;   // predicted CG iterations [3][SDC_MAX_SWEEPS][M]
+  // Margin of an asynchronous CG budget over its prediction.  A solve whose
+  // count rose by two or more from the last step's (for the same sweep and
+  // node) overruns a budget of the prediction plus one, and its step is
+  // redone.  Such rises are recorded per step (steps that continue the last
+  // one only): while at least two of the last 64 steps had one, budgets get
+  // max(2, pred / 16) launches of margin, else one.  The record does not
+  // depend on the margin, and launches after convergence return at once,
+  // so the margin changes no result, only how often a step is redone.
+  uint64_t rise_steps = 0;   // bit j: the step j + 1 steps back had a rise
+  bool rise_now = false;     // the current step has one
+  bool wide_margin() const { return __builtin_popcountll(rise_steps) >= 2; }
+  int budget_margin(int p) const { return wide_margin() ? std::max(2, p / 16) : 1; }
+  // a solve's new count (mx updates) against the slot's prediction
+  void note_count(int slot, int mx) {
+    if (!t_jump && mx > pred[slot]) rise_now = true;
+  }
   // prediction slot of node m in the current sweep: steps whose first sweep
   // takes all rows while heuristic first-sweep sets are on keep their own
   // history (their solves differ from the other steps')
