@@ -489,7 +489,7 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
 int pred_slot_of(const sdc_ctx* ctx, int k, int m) { return std::min(k, SDC_MAX_SWEEPS - 1) * ctx->prm.M + m; }
 
 // CG launches captured for node m of sweep k: the predicted count (the last
-// step's, plus one) and an eighth more, at least two (launches after
+// step's, plus one) and a sixteenth more, at least three (launches after
 // convergence return at once).
 int graph_budget(const sdc_ctx* ctx, int k, int m) {
   const int need = std::max(1, ctx->pred[pred_slot_of(ctx, k, m)]) + 1;
@@ -609,8 +609,10 @@ int graph_capture(sdc_ctx* ctx) {
 }
 
 // The sweeps of a started step as K graph launches and one synchronisation.
-// Re-captures first when a predicted CG count or the last step's set sizes
-// no longer fit (or a grid is twice what the last step needed); sets
+// Re-captures first when a predicted CG count no longer fits its budget, a
+// set of the last step came within an eighth of its grid (growing fronts:
+// captured again before the set outgrows it, which would redo the step) or
+// a grid is twice what the last step needed; sets
 // *short_budget (and changes nothing the caller keeps) when a solve did not
 // finish within its budget or a set outgrew its grid, so that the caller
 // redoes the step.
@@ -622,7 +624,7 @@ int graph_step(sdc_ctx* ctx, sdc_step_stats* st, bool* short_budget) {
       if (std::max(1, ctx->pred[pred_slot_of(ctx, k, m)]) + 1 > ctx->gbudget[k * M + m]) fits = false;
     if (k > 0 && graph_adaptive(ctx)) {
       const int seen = k < static_cast<int>(ctx->seen_nblk.size()) ? ctx->seen_nblk[k] : ctx->all.nblk;
-      if (seen > ctx->gcap[k] || ctx->gcap[k] > 2 * graph_cap(ctx, k)) fits = false;
+      if (seen + seen / 8 > ctx->gcap[k] || ctx->gcap[k] > 2 * graph_cap(ctx, k)) fits = false;
     }
   }
   if (!fits) TRY(graph_capture(ctx));
