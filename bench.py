@@ -442,7 +442,8 @@ def main():
                 # one core: it runs the window of the second stimulus only
                 out["workload_3d"]["full_run"] = full_run(config2(), FULL_RUN_SNAPSHOTS_3D, args.full_window,
                                                           args.repeats, args.full_oracle_steps,
-                                                          cpu=args.full_oracle_steps > 0, oracle_at=(120.0,))
+                                                          cpu=args.full_oracle_steps > 0, oracle_at=(120.0,),
+                                                          nonadaptive=not args.no_speedup, paper_key="3d_monodomain")
                 done("3D whole run")
         if not args.no_emi:
             out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup)
@@ -725,7 +726,7 @@ def workload_2d(args):
     if not args.no_full_run:
         out["full_run"] = full_run(config1(n=args.n, theta=1e-7), FULL_RUN_SNAPSHOTS_2D, args.full_window,
                                    args.repeats, args.full_oracle_steps, cpu=args.full_oracle_steps > 0,
-                                   nonadaptive=not args.no_speedup)
+                                   nonadaptive=not args.no_speedup, paper_key="2d_monodomain")
     return out
 
 
@@ -922,7 +923,8 @@ def cg_energy_variant(P, v0, w0, t0, nsteps, ms_std, v_std, v_non=None, tol=1e-3
     return out
 
 
-def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_at=None, nonadaptive=False):
+def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_at=None, nonadaptive=False,
+             paper_key=None):
     """The workload's whole run from t = 0 (every step of its schedule, all
     stimuli), timed as one pass with the device synchronised at its ends.
     Windows of `window` steps starting at the snapshot times are then timed
@@ -966,6 +968,8 @@ def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_a
             "nonadaptive_seconds": el0, "speedup": el0 / el,
             "rel_l2_final_v": float(np.linalg.norm(v_end - v_non) / np.linalg.norm(v_non)),
             "max_abs_final_v": float(np.abs(v_end - v_non).max())}
+        if paper_key:
+            out["adaptive_vs_nonadaptive"][f"paper_cpu_speedup_{paper_key}"] = PAPER_SPEEDUP[paper_key]
         print(f"[bench] {P.name}: non-adaptive whole run in {el0:.1f} s", file=sys.stderr, flush=True)
     orc = None
     for n0 in starts:
