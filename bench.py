@@ -962,12 +962,27 @@ def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_a
            "stimuli_ms": [float(st[0]) for st in P.stimuli], "redone_steps": s.info()["redone_steps"],
            "windows": []}
     if nonadaptive:
-        el0, v_non = nonadaptive_run(P, P.v_init, P.w_init, 0.0, P.n_steps, warm_budget=False, return_state=True)
-        v_end = v.cpu().numpy()
-        out["adaptive_vs_nonadaptive"] = {
-            "nonadaptive_seconds": el0, "speedup": el0 / el,
-            "rel_l2_final_v": float(np.linalg.norm(v_end - v_non) / np.linalg.norm(v_non)),
-            "max_abs_final_v": float(np.abs(v_end - v_non).max())}
+        # the same run with theta = 0, its states kept at the same steps (the
+        # final state is back at rest, so the distance is taken there)
+        s0 = Solver.from_problem(P, theta=0.0)
+        vn, wn = torch.tensor(P.v_init, device=dev), torch.tensor(P.w_init, device=dev)
+        kept = {}
+        sync()
+        t = time.perf_counter()
+        for n in range(P.n_steps):
+            if n in saved:
+                kept[n] = vn.clone()
+            s0.step(vn, wn, n * P.dt)
+        sync()
+        el0 = time.perf_counter() - t
+        s0.close()
+        dist = {}
+        for n in sorted(saved):
+            a, b = snaps[n][0].cpu().numpy(), kept[n].cpu().numpy()
+            dist[f"{n * P.dt:g}"] = {"max_abs_v": float(np.abs(a - b).max()),
+                                     "rel_l2_v": float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))}
+        out["adaptive_vs_nonadaptive"] = {"nonadaptive_seconds": el0, "speedup": el0 / el,
+                                          "theta": P.theta, "v_distance_at_ms": dist}
         if paper_key:
             out["adaptive_vs_nonadaptive"][f"paper_cpu_speedup_{paper_key}"] = PAPER_SPEEDUP[paper_key]
         print(f"[bench] {P.name}: non-adaptive whole run in {el0:.1f} s", file=sys.stderr, flush=True)
