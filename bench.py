@@ -19,9 +19,9 @@ and sweeps of the active rows, divided by its wall time.  The roofline
 entry is for the dominant kernel (the CG iteration, one launch per CG
 iteration over all instances still iterating), timed with HIP events on the
 library's stream in a second pass over the same window; its bytes per
-launch are given three ways: the per-iteration count of the scope table
-(12 B per stored entry, 120 B per row), the minimum the chosen matrix
-storage must move, and HBM traffic from committed rocprofv3 counters.  The
+launch are given three ways: the minimum the chosen matrix storage must
+move, a textbook count for CSR storage (12 B per stored entry, 120 B per
+row), and HBM traffic from committed rocprofv3 counters.  The
 adjoint/forward ratio is the reverse pass of 100 steps (checkpoint every
 10) over the forward pass of the same steps.  The CPU baseline is the FP64
 oracle on one host core over the first step(s) of the same window.  Further
@@ -296,9 +296,9 @@ def cg_roofline(prof, storage, n_diag, peak=None):
     """The CG iteration's roofline over the profiled launches: bytes per
     launch three ways and the event-timed mean launch duration.
 
-    scope_table: 12 B per stored entry (8 value + 4 column) and, per row,
-      4 (row pointer) + 4 (list entry, listed sets only) + 112 (14 vector
-      touches) -- the per-iteration count of the scope table;
+    csr_count: a textbook Jacobi-PCG iteration on CSR storage: 12 B per
+      stored entry (8 value + 4 column) and, per row, 4 (row pointer) + 4
+      (list entry, listed sets only) + 112 (14 vector touches);
     storage_min: what the chosen storage must move at least: the symmetric
       diagonal storage reads its nd/2 + 1 stored diagonals per row (8 B each),
       CSR 12 B per entry and a 4 B row pointer; per row 3 vectors read once
@@ -308,10 +308,9 @@ def cg_roofline(prof, storage, n_diag, peak=None):
       time there to rebuild it (12 B a launch): 68 B (dinv is formed from the
       diagonal), plus the list entry;
     achieved: storage_min bytes / mean launch duration (the reported frac):
-      the scope table's count is written for CSR storage (a column index
-      and the full row per entry) and exceeds what the symmetric diagonal
-      storage moves, so its rate can pass the HBM peak; it is reported
-      beside (scope_table_GBps, frac_scope_table).
+      csr_count (a column index and the full row per entry) exceeds what
+      the symmetric diagonal storage moves, so its rate can pass the HBM
+      peak; it is reported beside (csr_count_GBps, frac_csr_count).
     """
     peak = peak or HBM_PEAK_GBS
     L, ms = prof["cg_launches"], prof["cg_ms"]
@@ -327,8 +326,8 @@ def cg_roofline(prof, storage, n_diag, peak=None):
            "bound": "hbm", "achieved": b_min / sec / 1e9, "peak": peak, "unit": "GB/s",
            "frac": b_min / sec / 1e9 / peak, "traffic": None,
            "avg_launch_us": 1e3 * ms / L, "launches": L,
-           "bytes_per_launch_storage_min": b_min / L, "bytes_per_launch_scope_table": b_scope / L,
-           "scope_table_GBps": b_scope / sec / 1e9, "frac_scope_table": b_scope / sec / 1e9 / peak,
+           "bytes_per_launch_storage_min": b_min / L, "bytes_per_launch_csr_count": b_scope / L,
+           "csr_count_GBps": b_scope / sec / 1e9, "frac_csr_count": b_scope / sec / 1e9 / peak,
            "rows_per_launch": rows / L}
     for cls, launches, lms, lrows, lnnz, listed in (
             ("all_rows", prof["cg_all_launches"], prof["cg_all_ms"], prof["cg_all_rows"], prof["cg_all_nnz"], 0.0),
@@ -341,7 +340,7 @@ def cg_roofline(prof, storage, n_diag, peak=None):
             + 4.0 * listed * lrows
         out[cls] = {"launches": launches, "avg_launch_us": 1e3 * lms / launches, "rows_per_launch": lrows / launches,
                     "storage_min_GBps": bm / (lms * 1e-3) / 1e9, "frac": bm / (lms * 1e-3) / 1e9 / peak,
-                    "scope_table_GBps": bs / (lms * 1e-3) / 1e9, "frac_scope_table": bs / (lms * 1e-3) / 1e9 / peak}
+                    "csr_count_GBps": bs / (lms * 1e-3) / 1e9, "frac_csr_count": bs / (lms * 1e-3) / 1e9 / peak}
     return out
 
 

@@ -146,11 +146,11 @@ def test_cg_launch_classes_and_roofline_byte_models():
     prof = {"cg_launches": 2, "cg_ms": 2.0, "cg_rows": 1200.0, "cg_nnz": 8400.0, "cg_all_launches": 1,
             "cg_all_ms": 1.0, "cg_all_rows": 1000.0, "cg_all_nnz": 7000.0}
     r = bench.cg_roofline(prof, "dia", 7)
-    assert r["bytes_per_launch_scope_table"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2)
+    assert r["bytes_per_launch_csr_count"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2)
     assert r["bytes_per_launch_storage_min"] == pytest.approx(((8 * 4 + 68) * 1200 + 4 * 200) / 2)
     assert r["achieved"] == pytest.approx(((8 * 4 + 68) * 1200 + 4 * 200) / 2e-3 / 1e9)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
-    assert r["scope_table_GBps"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2e-3 / 1e9)
+    assert r["csr_count_GBps"] == pytest.approx((12 * 8400 + 116 * 1200 + 4 * 200) / 2e-3 / 1e9)
     assert r["listed"]["launches"] == 1 and r["all_rows"]["rows_per_launch"] == 1000.0
     c = bench.cg_roofline(prof, "csr", 0)
     assert c["bytes_per_launch_storage_min"] == pytest.approx((12 * 8400 + 72 * 1200 + 4 * 200) / 2)
