@@ -272,6 +272,8 @@ def parse():
     ap.add_argument("--full-window", type=int, default=5, help="steps of each window of the whole runs")
     ap.add_argument("--full-oracle-steps", type=int, default=1,
                     help="oracle steps at the start of each window of the whole runs (0: none)")
+    ap.add_argument("--full-oracle-3d", action="store_true",
+                    help="also time the oracle on the 3D window of the second stimulus (about 60 s of CPU)")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the time-per-sweep curve over front-shell active sets")
     ap.add_argument("--calib", action="store_true",
@@ -437,11 +439,12 @@ def main():
             done("3D workload window")
             if not args.no_full_run:
                 from workloads import config2
-                # the 3D oracle takes about 50 s to build and 18 s per step on
-                # one core: it runs the window of the second stimulus only
+                # the 3D oracle takes about 50 s to build and 11-18 s per step on
+                # one core: on request it runs the window of the second stimulus
                 out["workload_3d"]["full_run"] = full_run(config2(), FULL_RUN_SNAPSHOTS_3D, args.full_window,
                                                           args.repeats, args.full_oracle_steps,
-                                                          cpu=args.full_oracle_steps > 0, oracle_at=(120.0,),
+                                                          cpu=args.full_oracle_3d and args.full_oracle_steps > 0,
+                                                          oracle_at=(120.0,),
                                                           nonadaptive=not args.no_speedup, paper_key="3d_monodomain")
                 done("3D whole run")
         if not args.no_emi:
