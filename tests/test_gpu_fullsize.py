@@ -86,6 +86,84 @@ def test_batched_full_size_sampled_instances():
         assert rel(gv[lo:hi], ov) < 1e-10 and rel(gw[lo:hi], ow) < 1e-10
 
 
+def _sets_of_one_step(s, P, v, w, t):
+    """One step sweep by sweep from (v, w) (copies), returning its sets."""
+    vv, ww = v.clone(), w.clone()
+    s.begin_step(vv, ww, t)
+    sets = [None]
+    for k in range(P.K):
+        s.sweep()
+        if k + 1 < P.K:
+            sets.append(s.active().cpu().numpy().astype(np.int64))
+    s.end_step(vv, ww)
+    return sets, vv, ww
+
+
+def test_batched_full_size_late_step_sampled_instances():
+    """The batched workload run by `step` (predicted CG budgets, the
+    benchmark's launch path) to the end of its headline window (step 99,
+    t = 19.8 ms, fronts well inside the instances); its last step from the
+    GPU's own state, replayed by the oracle on the smallest and the largest
+    instance with the GPU's sets.  The step and the sweep-by-sweep path give
+    the same bits."""
+    P = config4()
+    s = _solver(P)
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    n0 = 99
+    for n in range(n0):
+        s.step(v, w, n * P.dt)
+    print(f"[batched full late] GPU at step {n0}", flush=True)
+    v0, w0 = v.cpu().numpy(), w.cpu().numpy()
+    vc, wc = v.clone(), w.clone()
+    s.step(v, w, n0 * P.dt)   # continues the run: predicted budgets
+    gv, gw = v.cpu().numpy(), w.cpu().numpy()
+    sets, sv, sw = _sets_of_one_step(s, P, vc, wc, n0 * P.dt)
+    assert np.array_equal(gv, sv.cpu().numpy()) and np.array_equal(gw, sw.cpu().numpy())
+    assert 0 < sets[1].size < P.N
+    sizes = np.diff(P.node_off)
+    for i in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        lo, hi = P.node_off[i], P.node_off[i + 1]
+        sub = _instance(P, i)
+        rep = [[None] + [s_[(s_ >= lo) & (s_ < hi)] - lo for s_ in sets[1:]]]
+        print(f"[batched full late] oracle instance {i} ({hi - lo} dofs), set sizes "
+              f"{[r.size for r in rep[0][1:]]}", flush=True)
+        ov, ow, _ = run(build(sub), v0[lo:hi], w0[lo:hi], 1, P.K, sub.stimuli, idx_replay=rep, t0=n0 * P.dt)
+        assert rel(gv[lo:hi], ov) < 1e-10 and rel(gw[lo:hi], ow) < 1e-10
+        assert np.abs(gv[lo:hi] - ov).max() <= 1e-10 * np.abs(ov).max()
+
+
+def test_2d_full_size_late_steps_match_oracle():
+    """The 512^2 workload run by `step` to t = 50 ms (the front across the
+    domain: the second sweep keeps every row) and on to t = 150 ms; at each
+    time one step from the GPU's own state is replayed by the oracle with the
+    GPU's sets."""
+    from oracle.sdc import apply_stimuli
+    P = config1()
+    s = _solver(P)
+    orc = build(P)
+    v = torch.tensor(P.v_init, device=DEV)
+    w = torch.tensor(P.w_init, device=DEV)
+    n = 0
+    for n0 in (250, 750):
+        while n < n0:
+            s.step(v, w, n * P.dt)
+            n += 1
+        print(f"[2d full late] GPU at step {n0} (t = {n0 * P.dt:g} ms)", flush=True)
+        ov, ow = v.cpu().numpy(), w.cpu().numpy()
+        vc, wc = v.clone(), w.clone()
+        s.step(v, w, n0 * P.dt)   # continues the run: predicted budgets
+        n += 1
+        gv, gw = v.cpu().numpy(), w.cpu().numpy()
+        sets, sv, sw = _sets_of_one_step(s, P, vc, wc, n0 * P.dt)
+        assert np.array_equal(gv, sv.cpu().numpy()) and np.array_equal(gw, sw.cpu().numpy())
+        apply_stimuli(ov, n0 * P.dt, P.dt, P.stimuli)
+        ov, ow, infos = orc.step(ov, ow, P.K, idx_replay=sets)
+        print(f"   set sizes {[len(x) for x in sets[1:]]}, rel v {rel(gv, ov):.2e} w {rel(gw, ow):.2e}", flush=True)
+        assert rel(gv, ov) < 1e-10 and rel(gw, ow) < 1e-10
+        assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
+
+
 def test_3d_full_size_assembly_and_restricted_pcg():
     P = config2()
     s = _solver(P)
