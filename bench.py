@@ -531,7 +531,7 @@ def headline(args):
     if not args.headline_only:
         if not args.no_graph:
             out["graph"] = graph_window(P, v_start.cpu().numpy(), w_start.cpu().numpy(), t_start, args.steps,
-                                        args.repeats, out["ms_per_step"])
+                                        args.repeats, out["ms_per_step"], v_host=v_end)
         if not args.no_speedup:
             el0 = nonadaptive_run(P, v_start.cpu().numpy(), w_start.cpu().numpy(), t_start, args.steps)
             out["adaptive_vs_nonadaptive"] = {"nonadaptive_ms_per_step": 1e3 * el0 / args.steps,
@@ -560,10 +560,12 @@ def calibration_copies(dev, n=3):
     del src, dst
 
 
-def graph_window(P, v0, w0, t0, nsteps, repeats, ms_host):
+def graph_window(P, v0, w0, t0, nsteps, repeats, ms_host, v_host=None):
     """The same window with graph-captured sweeps (sdc_set_graph): one
     untimed pass (captures, budgets), then `repeats` timed passes from the
-    same state, median reported beside the host-launched steps' time."""
+    same state, median reported beside the host-launched steps' time; with
+    v_host (the host-launched window's final potential), whether every
+    repeat ended on the same bits."""
     import torch
 
     from paper_2311_07206_amd import Solver
@@ -573,18 +575,22 @@ def graph_window(P, v0, w0, t0, nsteps, repeats, ms_host):
     s.set_graph(True)
     _timed_steps(s, torch.tensor(v0, device=dev), torch.tensor(w0, device=dev), t0, P.dt, nsteps, sync)
     i0 = s.info()
-    times, dofs = [], None
+    times, dofs, same = [], None, v_host is not None
     for _ in range(max(1, repeats)):
-        el, logs = _timed_steps(s, torch.tensor(v0, device=dev), torch.tensor(w0, device=dev), t0, P.dt, nsteps, sync)
+        vg = torch.tensor(v0, device=dev)
+        el, logs = _timed_steps(s, vg, torch.tensor(w0, device=dev), t0, P.dt, nsteps, sync)
         times.append(el)
         dofs = sum(st["n_active"] for lg in logs for st in lg)
+        if v_host is not None:
+            same = same and np.array_equal(vg.cpu().numpy(), v_host)
     i1 = s.info()
     s.close()
     el = float(np.median(times))
     return {"ms_per_step": 1e3 * el / nsteps, "value": dofs / el, "unit": "active dof-sweeps/s",
             "host_launched_ms_per_step": ms_host, "speedup_vs_host_launched": ms_host / (1e3 * el / nsteps),
             "graph_steps": i1["graph_steps"] - i0["graph_steps"], "redone": i1["graph_redone"] - i0["graph_redone"],
-            "captures": i1["graph_captures"] - i0["graph_captures"], "repeats": len(times)}
+            "captures": i1["graph_captures"] - i0["graph_captures"], "repeats": len(times),
+            "bitwise_equal_to_host_launched": same if v_host is not None else None}
 
 
 def sequential_instances(P, v0, w0, t0, nsteps):
@@ -709,7 +715,7 @@ def workload_2d(args):
             out["roofline"] = cg_roofline(prof, info["format"], info["n_diagonals"])
     s.close()
     if not args.no_graph:
-        out["graph"] = graph_window(P, v_start, w_start, t_start, nsteps, 3, out["ms_per_step"])
+        out["graph"] = graph_window(P, v_start, w_start, t_start, nsteps, 3, out["ms_per_step"], v_host=v_std)
     v_non = None
     if not args.no_speedup:
         el0, v_non = nonadaptive_run(P, v_start, w_start, t_start, nsteps, return_state=True)
