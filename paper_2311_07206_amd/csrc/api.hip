@@ -304,8 +304,7 @@ int do_sweep(sdc_ctx* ctx, sdc_sweep_stats* st, bool select_next, bool async,
   const MapBuf& mb = ctx->curmap();
   const Map map = mb.dev();
   if (ctx->k < SDC_MAX_SWEEPS) {
-    if (static_cast<int>(ctx->seen_nblk.size()) <= ctx->k) ctx->seen_nblk.resize(ctx->k + 1, ctx->all.nblk);
-    ctx->seen_nblk[ctx->k] = mb.nblk;
+    ctx->note_seen(ctx->k, mb.nblk);
   }
   // the statistics of this sweep refer to its own set, which the selection replaces
   std::vector<int32_t> cnt = mb.cnt;
@@ -610,9 +609,10 @@ int graph_capture(sdc_ctx* ctx) {
 
 // The sweeps of a started step as K graph launches and one synchronisation.
 // Re-captures first when a predicted CG count no longer fits its budget, a
-// set of the last step came within an eighth of its grid (growing fronts:
-// captured again before the set outgrows it, which would redo the step) or
-// a grid is twice what the last step needed; sets
+// set of the last step, grown once more by twice its last growth, would
+// exceed its grid (growing fronts: captured again before the set outgrows
+// it, which would redo the step) or a grid is twice what the last step
+// needed; sets
 // *short_budget (and changes nothing the caller keeps) when a solve did not
 // finish within its budget or a set outgrew its grid, so that the caller
 // redoes the step.
@@ -624,7 +624,9 @@ int graph_step(sdc_ctx* ctx, sdc_step_stats* st, bool* short_budget) {
       if (std::max(1, ctx->pred[pred_slot_of(ctx, k, m)]) + 1 > ctx->gbudget[k * M + m]) fits = false;
     if (k > 0 && graph_adaptive(ctx)) {
       const int seen = k < static_cast<int>(ctx->seen_nblk.size()) ? ctx->seen_nblk[k] : ctx->all.nblk;
-      if (seen + seen / 8 > ctx->gcap[k] || ctx->gcap[k] > 2 * graph_cap(ctx, k)) fits = false;
+      const int prev = k < static_cast<int>(ctx->seen_prev.size()) ? ctx->seen_prev[k] : seen;
+      // the set may grow within this step as much as twice its last growth
+      if (seen + 2 * std::max(0, seen - prev) > ctx->gcap[k] || ctx->gcap[k] > 2 * graph_cap(ctx, k)) fits = false;
     }
   }
   if (!fits) TRY(graph_capture(ctx));
@@ -641,7 +643,7 @@ int graph_step(sdc_ctx* ctx, sdc_step_stats* st, bool* short_budget) {
   ctx->seen_nblk.resize(K, ctx->all.nblk);
   for (int k = 1; k < K && graph_adaptive(ctx); ++k) {
     const int32_t* tot = reinterpret_cast<const int32_t*>(ctx->gh_sizes + k * W + ni + 1);
-    ctx->seen_nblk[k] = tot[0];
+    ctx->note_seen(k, tot[0]);
     if (tot[0] > ctx->gcap[k] || tot[2] != 0) *short_budget = true;
   }
   if (*short_budget) return SDC_OK;

@@ -249,6 +249,13 @@ struct sdc_ctx {
   std::vector<int> gbudget;            // [K][M]
   std::vector<int> gcap;               // [K] grid of sweep k (k >= 1): map entries the graph covers
   std::vector<int> seen_nblk;          // [K] map entries of sweep k in the last step (eager or graph)
+  std::vector<int> seen_prev;          // [K] the same one step earlier
+  void note_seen(int k, int nblk) {
+    if (static_cast<int>(seen_nblk.size()) <= k) seen_nblk.resize(k + 1, all.nblk);
+    if (static_cast<int>(seen_prev.size()) <= k) seen_prev.resize(k + 1, all.nblk);
+    seen_prev[k] = seen_nblk[k];
+    seen_nblk[k] = nblk;
+  }
   int32_t* ghist = nullptr;            // device [K][M][n_inst] done, then [K][M][n_inst] iters
   int32_t* gh_hist = nullptr;          // pinned copy of ghist
   int64_t* gh_sizes = nullptr;         // pinned [K][map_sizes_words]: the sizes of each sweep's map
