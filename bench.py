@@ -446,7 +446,8 @@ def main():
                                                           args.repeats, args.full_oracle_steps,
                                                           cpu=args.full_oracle_3d and args.full_oracle_steps > 0,
                                                           oracle_at=(120.0,),
-                                                          nonadaptive=not args.no_speedup, paper_key="3d_monodomain")
+                                                          nonadaptive=not args.no_speedup, paper_key="3d_monodomain",
+                                                          first=None if args.no_first_sweep else (3, 10))
                 done("3D whole run")
         if not args.no_emi:
             out["workload_emi"] = workload_emi(args.emi_steps, speedup=not args.no_speedup, calib=args.calib)
@@ -737,7 +738,8 @@ def workload_2d(args):
     if not args.no_full_run:
         out["full_run"] = full_run(config1(n=args.n, theta=1e-7), FULL_RUN_SNAPSHOTS_2D, args.full_window,
                                    args.repeats, args.full_oracle_steps, cpu=args.full_oracle_steps > 0,
-                                   nonadaptive=not args.no_speedup, paper_key="2d_monodomain")
+                                   nonadaptive=not args.no_speedup, paper_key="2d_monodomain",
+                                   first=None if args.no_first_sweep else (4, 10))
     return out
 
 
@@ -935,7 +937,7 @@ def cg_energy_variant(P, v0, w0, t0, nsteps, ms_std, v_std, v_non=None, tol=1e-3
 
 
 def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_at=None, nonadaptive=False,
-             paper_key=None):
+             paper_key=None, first=None):
     """The workload's whole run from t = 0 (every step of its schedule, all
     stimuli), timed as one pass with the device synchronised at its ends.
     Windows of `window` steps starting at the snapshot times are then timed
@@ -947,7 +949,10 @@ def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_a
     on one core, beside the GPU's median time for the same steps: both rates
     over identical steps.  With `nonadaptive`, the whole run is timed again
     with theta = 0: the speedup over the whole run, as the paper reports
-    its speedups, and the distance of the two final potentials."""
+    its speedups, and the distance of the two potentials at the window
+    times.  With `first` = (rings, every), the whole run once more with the
+    heuristic first-sweep set: its time and its distance to the
+    non-adaptive run at the same times."""
     import torch
 
     from paper_2311_07206_amd import Solver
@@ -972,12 +977,12 @@ def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_a
            "value": dofs / el, "unit": "active dof-sweeps/s",
            "stimuli_ms": [float(st[0]) for st in P.stimuli], "redone_steps": s.info()["redone_steps"],
            "windows": []}
+    kept = {}
     if nonadaptive:
         # the same run with theta = 0, its states kept at the same steps (the
         # final state is back at rest, so the distance is taken there)
         s0 = Solver.from_problem(P, theta=0.0)
         vn, wn = torch.tensor(P.v_init, device=dev), torch.tensor(P.w_init, device=dev)
-        kept = {}
         sync()
         t = time.perf_counter()
         for n in range(P.n_steps):
@@ -997,6 +1002,29 @@ def full_run(P, snap_ms, window=5, repeats=5, oracle_steps=1, cpu=True, oracle_a
         if paper_key:
             out["adaptive_vs_nonadaptive"][f"paper_cpu_speedup_{paper_key}"] = PAPER_SPEEDUP[paper_key]
         print(f"[bench] {P.name}: non-adaptive whole run in {el0:.1f} s", file=sys.stderr, flush=True)
+    if first is not None:
+        rings, every = first
+        s1 = Solver.from_problem(P, first_rings=rings, first_full_every=every)
+        vf, wf = torch.tensor(P.v_init, device=dev), torch.tensor(P.w_init, device=dev)
+        kept1 = {}
+        sync()
+        t = time.perf_counter()
+        for n in range(P.n_steps):
+            if n in saved:
+                kept1[n] = vf.clone()
+            s1.step(vf, wf, n * P.dt)
+        sync()
+        el1 = time.perf_counter() - t
+        s1.close()
+        fd = {"first_rings": rings, "first_full_every": every, "seconds": el1, "ms_per_step": 1e3 * el1 / P.n_steps,
+              "speedup_vs_standard": el / el1}
+        if kept:
+            fd["speedup_vs_nonadaptive"] = out["adaptive_vs_nonadaptive"]["nonadaptive_seconds"] / el1
+            fd["max_abs_v_to_nonadaptive_at_ms"] = {
+                f"{n * P.dt:g}": float(np.abs(kept1[n].cpu().numpy() - kept[n].cpu().numpy()).max()) for n in sorted(saved)}
+        out["first_sweep_subset"] = fd
+        print(f"[bench] {P.name}: whole run with the heuristic first-sweep set in {el1:.1f} s", file=sys.stderr,
+              flush=True)
     orc = None
     for n0 in starts:
         lead = 1 if n0 > 0 else 0
