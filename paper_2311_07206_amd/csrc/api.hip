@@ -195,7 +195,7 @@ int run_cg(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot, std:
         launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
                        ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a],
                        ctx->cg_scal[o], stop, ctx->cg(), mb.tot_if_large(ctx->cg_tot),
-                       ctx->pair_all, timed ? ctx->ev[2 * b] : nullptr,
+                       ctx->pair_all, mb.late_partials(), timed ? ctx->ev[2 * b] : nullptr,
                        timed ? ctx->ev[2 * b + 1] : nullptr);
       }
       HIPC(hipGetLastError());
@@ -284,7 +284,7 @@ int run_cg_async(sdc_ctx* ctx, int m, const MapBuf& mb, double* x, int pred_slot
     const int a = it & 1, o = a ^ 1;
     launch_cg_iter(ctx->stream, map, ctx->N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a],
                    ctx->wv[a], ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o],
-                   stop, cg, mb.tot_if_large(ctx->cg_tot), ctx->pair_all,
+                   stop, cg, mb.tot_if_large(ctx->cg_tot), ctx->pair_all, mb.late_partials(),
                    timed ? ctx->ev[2 * (*ev_off + it)] : nullptr,
                    timed ? ctx->ev[2 * (*ev_off + it) + 1] : nullptr);
   }

@@ -44,6 +44,10 @@ struct MapBuf {
   double* tot_if_large(double* tot) const {
     return max_nb > kTotBlocks || (nblk > kTotMapBlocks && max_nb > kTotMinBlocks) ? tot : nullptr;
   }
+  // listed sets whose instances have at most kTotBlocks blocks: the CG
+  // launches sum their partials themselves after the stencil sums instead of
+  // a totals pass before them
+  bool late_partials() const { return idx && max_nb <= kTotBlocks; }
   NextMap next(const int64_t* node_off, const int32_t* dia_off, int nd) const {
     return NextMap{rec, inst_blk0, inst_nblk, inst_cnt, inst_nnz, aoff, totals, node_off, dia_off, nd, cap};
   }

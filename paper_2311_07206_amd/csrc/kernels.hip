@@ -545,7 +545,12 @@ __device__ inline void energy_record(const double* sc, double* so, bool first, i
   so[kRing + (it - 1) % d] = e_last;
 }
 
-template <int S, bool FIRST, int LIST, bool TOT, bool XW>
+// TOT: 0 the kernel sums its instance's partial sums (loads issued with the
+// row's values); 1 it reads the instance's totals (k_cg_totals ran first);
+// 2 it sums the partial sums itself once its stencil sums are formed, in
+// the order of k_cg_totals (bitwise the same totals, without that launch),
+// and reads the values only the update needs after that.
+template <int S, bool FIRST, int LIST, int TOT, bool XW>
 __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_done, const BlkRec* __restrict__ rec,
                                                     const int32_t* __restrict__ idx, int nblk, int xcd_shift,
                                                     const int32_t* __restrict__ live, int it,
@@ -579,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   const int i = rw.row;
   // second round trip, issued together: the row's values and neighbour sums,
   // the instance's scalars and partial sums from the previous launch
-  constexpr bool kPhased = TOT && phased_loads<S, 1>();
+  constexpr bool kPhased = TOT != 0 && phased_loads<S, 1>();
   double a_r = 0.0, a_w = 0.0, a_s = 0.0, hii = 0.0;
   DiaLoads<kPhased ? S : 1, !FIRST> dl;
   if constexpr (kPhased) {
@@ -599,9 +604,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   // launch rebuilds the previous launch's p_{L-1} = u_{L-1} + beta_{L-1}
   // p_{L-2} from p_{L-2} (zero before the first launch), u_{L-1} (still in
   // this launch's output buffer) and beta_{L-1}, as that launch formed it.
-  const double p_prev2 = XW && it > 1 ? p[i] : 0.0;
-  const double u_prev = XW ? u_out[i] : 0.0;
-  const double x_old = XW ? x[i] : 0.0;
+  double p_prev2 = 0.0, u_prev = 0.0, x_old = 0.0;
+  if constexpr (XW && TOT != 2) {
+    p_prev2 = it > 1 ? p[i] : 0.0;
+    u_prev = u_out[i];
+    x_old = x[i];
+  }
   double sc_rz = 0.0, sc_alpha = 0.0, sc_bb = 0.0, sc_beta = 0.0;
   const double* sc = scal_in + inst * kScal;
   if (!FIRST) {
@@ -619,12 +627,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   // those of the full unrolled read.  Two rounds cover the listed sets of a
   // 2D batch (fewer registers); the 19-diagonal 3D sets span up to four and
   // keep them unrolled (measured faster).
-  constexpr int kq = TOT ? 1 : S > 7 ? kTotBlocks / kBlock : 2;
+  constexpr int kq = TOT != 0 ? 1 : S > 7 ? kTotBlocks / kBlock : 2;
   double pv[kq][3];
-  if constexpr (TOT) {
+  if constexpr (TOT == 1) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) pv[0][k] = part_in[4 * inst + k];
-  } else {
+  } else if constexpr (TOT == 0) {
 #pragma unroll
     for (int q = 0; q < kq; ++q) {
       const int b = static_cast<int>(threadIdx.x) + q * kBlock;
@@ -636,13 +644,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
   if constexpr (kPhased) {
     __builtin_amdgcn_sched_barrier(0);   // every load above is issued before the arithmetic below
     dl.sums(a_r, a_w, a_s, hii);
+    // the stencil sums formed here, before the partial sums are read (so
+    // the row's loaded values are not kept alive across that read)
+    if constexpr (TOT == 2) asm volatile("" : "+v"(a_r), "+v"(a_w), "+v"(a_s), "+v"(hii));
   }
   // the Jacobi factor from the row's diagonal, as the stored dinv was formed
   const double di = 1.0 / hii;
-  const double p_old = XW ? fma(sc_beta, p_prev2, u_prev) : 0.0;   // p_{L-1}
-  if constexpr (TOT) {
+  if constexpr (TOT == 1) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) acc[k] = pv[0][k];
+  } else if constexpr (TOT == 2) {
+    // the instance's partial sums (at most kTotBlocks), then the update's values
+    __builtin_amdgcn_sched_barrier(0);
+    for (int b = static_cast<int>(threadIdx.x); b < nb; b += kBlock)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[k] += part_in[4 * (b0 + b) + k];
+    block_total<3>(acc, sh_in);
+    if constexpr (XW) {
+      p_prev2 = it > 1 ? p[i] : 0.0;
+      u_prev = u_out[i];
+      x_old = x[i];
+    }
   } else {
 #pragma unroll
     for (int q = 0; q < kq; ++q) {
@@ -660,6 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int32_t* __restrict__ blk_do
     }
     block_total<3>(acc, sh_in);
   }
+  const double p_old = XW ? fma(sc_beta, p_prev2, u_prev) : 0.0;   // p_{L-1}
   const double gamma = acc[0], delta = acc[1], rr = acc[2];
   double alpha, beta, bb;
   if (FIRST) {
@@ -1904,11 +1927,12 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     double* x, double* p, const double* u_in, const double* w_in, const double* s_in,
                     double* u_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, const CgStop& stop,
-                    const CgState& cg, double* tot, bool pair_all, hipEvent_t ev_start,
+                    const CgState& cg, double* tot, bool pair_all, bool late, hipEvent_t ev_start,
                     hipEvent_t ev_stop) {
   if (map.nblk <= 0) return;
   const double* pin = part_in;
-  if (tot) {
+  late = late && tot && map.idx;   // listed sets: partial sums read late instead of the totals pass
+  if (tot && !late) {
     k_cg_totals<<<dim3(static_cast<unsigned>(map.n_inst)), kBlock, 0, s>>>(map.inst_blk0, map.inst_nblk,
                                                                                  part_in, tot);
     pin = tot;
@@ -1932,14 +1956,18 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
     constexpr int S = decltype(st)::value;
     auto pick = [&](auto tt, auto xw) {
       constexpr bool T = decltype(tt)::value, XW = decltype(xw)::value;
-      if (map.idx) {
-        it == 0 ? go(k_cg_iter<S, true, 1, T, false>, kBlock) : go(k_cg_iter<S, false, 1, T, XW>, kBlock);
+      if (map.idx && late) {
+        it == 0 ? go(k_cg_iter<S, true, 1, 2, false>, kBlock) : go(k_cg_iter<S, false, 1, 2, XW>, kBlock);
+      } else if (map.idx) {
+        constexpr int TL = T ? 1 : 0;
+        it == 0 ? go(k_cg_iter<S, true, 1, TL, false>, kBlock) : go(k_cg_iter<S, false, 1, TL, XW>, kBlock);
       } else if (S > 0 && pair_all) {
         // every row of the instances: two rows per thread
         if constexpr (S > 0)
           it == 0 ? go(k_cg_iter2<S, true, T, false>, kPairThreads) : go(k_cg_iter2<S, false, T, XW>, kPairThreads);
       } else {
-        it == 0 ? go(k_cg_iter<S, true, 0, T, false>, kBlock) : go(k_cg_iter<S, false, 0, T, XW>, kBlock);
+        constexpr int TA = T ? 1 : 0;
+        it == 0 ? go(k_cg_iter<S, true, 0, TA, false>, kBlock) : go(k_cg_iter<S, false, 0, TA, XW>, kBlock);
       }
     };
     const bool odd = (it & 1) != 0;

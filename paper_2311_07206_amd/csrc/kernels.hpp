@@ -169,7 +169,7 @@ void launch_cg_iter(hipStream_t s, const Map& map, int64_t N, const Mat& H, cons
                     double* x, double* p, const double* u_in, const double* w_in, const double* s_in,
                     double* u_out, double* w_out, double* s_out, int it, const double* part_in,
                     double* part_out, const double* scal_in, double* scal_out, const CgStop& stop,
-                    const CgState& cg, double* tot, bool pair_all = true,
+                    const CgState& cg, double* tot, bool pair_all = true, bool late = false,
                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 constexpr int kTotBlocks = 4 * kBlock;
 constexpr int kTotMapBlocks = 2048;
