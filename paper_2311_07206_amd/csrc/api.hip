@@ -531,6 +531,10 @@ int enqueue_graph_sweep(sdc_ctx* ctx, int k, hipStream_t s) {
   const EmiArgs emi = ctx->emi_args();
   const CgStop stop = ctx->cg_stop();
   double* const tot = ctx->all.tot_if_large(ctx->cg_tot);
+  // a listed set's instances have at most the blocks of the all-rows map's
+  // instances: when those are few enough, the listed launches read their
+  // partial sums themselves (as host-launched steps do, bitwise alike)
+  const bool late = ctx->all.max_nb <= kTotBlocks;
   launch_sweep_start(s, M, map, N, ctx->A(), ctx->ml, ctx->v0, ctx->w0, ctx->v, ctx->w, ctx->I, ctx->R, ctx->Phi,
                      ctx->Gam, ctx->amax, ctx->cargs, emi);
   for (int m = 0; m < M; ++m) {
@@ -546,7 +550,7 @@ int enqueue_graph_sweep(sdc_ctx* ctx, int k, hipStream_t s) {
       const int a = it & 1, o = a ^ 1;
       launch_cg_iter(s, map, N, H, dinv, x, ctx->p, ctx->r[o], ctx->wv[o], ctx->s[o], ctx->r[a], ctx->wv[a],
                      ctx->s[a], it, ctx->part[a], ctx->part[o], ctx->cg_scal[a], ctx->cg_scal[o], stop, cg, tot,
-                     ctx->pair_all);
+                     ctx->pair_all, late);
     }
     launch_post(s, M, m, map, N, ctx->ionic_d, x, ctx->v + m * N, ctx->w + m * N, ctx->I + m * N, ctx->R + m * N,
                 ctx->dI + m * N, ctx->dR + m * N, ctx->Gam + m * N, ctx->dR, ctx->amax, ctx->cargs, emi, false);
